@@ -1,0 +1,688 @@
+/*
+ * oif_oracle.c -- plain FP64 CPU oracle of one coupled lattice-Boltzmann /
+ * immersed-membrane time step, written from the paper (Cimrak, Gusenbauer,
+ * Jancigova, "An ESPResSo implementation of elastic objects immersed in a
+ * fluid", Sections "Method" and "Elastic interactions").
+ *
+ * TEST INFRASTRUCTURE ONLY: the product library never includes, links or
+ * calls this file.  It is deliberately slow and serial so that every formula
+ * can be checked against the paper by eye.  No blocking, fusion or
+ * reordering beyond what the step definition states.
+ *
+ * Where the paper is silent or garbled, the readings used here are:
+ *   - collision: single-relaxation-time BGK with relaxation time tau and the
+ *     standard second-order equilibrium (the paper only requires mass and
+ *     momentum conservation and defers the operator to its references);
+ *   - external force term f_i: Guo forcing, with the fluid velocity taken as
+ *     u = (sum_i n_i e_i + F/2) / rho (equal to the paper's moment definition
+ *     when F = 0);
+ *   - drag: force on the mesh point -xi (v - u); the opposite force
+ *     +xi (v - u) is spread to the fluid (eq. dragforce read so that the point
+ *     relaxes towards the fluid velocity, momentum conserving);
+ *   - interpolation and spreading: trilinear over the 8 surrounding nodes, each
+ *     node weighted by the volume of the cuboid between the point and the
+ *     diagonally opposite node (so spreading is the adjoint of interpolation);
+ *   - the velocity interpolated is that of the populations at the start of the
+ *     step, with half the body force only;
+ *   - mesh integrator: symplectic Euler, V += F/m then X += V, time step 1;
+ *   - bending: theta = inner dihedral angle, n = inward unit normal of each
+ *     triangle, the force on each wing vertex along its own triangle's normal,
+ *     minus half the sum on each vertex of the shared edge;
+ *   - volume force: along the outward normal (the stored normals point
+ *     inward), one third of it on each vertex; the volume is the
+ *     divergence-theorem sum over signed tetrahedra;
+ *   - global area: per triangle, along the same centroid-to-vertex unit vector
+ *     as the local area force, scaled by the object-global ratio.
+ */
+#include "oif_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* D3Q19 velocity set, weights and opposites                                 */
+/* ------------------------------------------------------------------------- */
+static const int EV[19][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+static double weight(int i) {
+    if (i == 0) return 1.0 / 3.0;
+    if (i <= 6) return 1.0 / 18.0;
+    return 1.0 / 36.0;
+}
+
+static int opposite(int i) {
+    if (i == 0) return 0;
+    return (i % 2 == 1) ? i + 1 : i - 1;
+}
+
+/* ------------------------------------------------------------------------- */
+/* small vector helpers                                                      */
+/* ------------------------------------------------------------------------- */
+static void sub3(const double* a, const double* b, double* r) {
+    r[0] = a[0] - b[0];
+    r[1] = a[1] - b[1];
+    r[2] = a[2] - b[2];
+}
+static double dot3(const double* a, const double* b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static void cross3(const double* a, const double* b, double* r) {
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double norm3(const double* a) { return sqrt(dot3(a, a)); }
+
+/* ------------------------------------------------------------------------- */
+/* Stretching force: F_s = ks kappa(lambda) (dL / L0) n, with the            */
+/* neo-Hookean kappa(lambda) = (lambda^0.5 + lambda^-2.5)/(lambda+lambda^-3) */
+/* ------------------------------------------------------------------------- */
+double orc_kappa(double lambda) {
+    return (pow(lambda, 0.5) + pow(lambda, -2.5)) / (lambda + pow(lambda, -3.0));
+}
+
+/* ------------------------------------------------------------------------- */
+/* Mesh topology                                                             */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int lo, hi;   /* undirected key */
+    int from, to; /* directed edge as it appears in the triangle */
+    int wing;     /* third vertex of the triangle */
+    int t;        /* triangle id */
+} dedge;
+
+static int dedge_cmp(const void* pa, const void* pb) {
+    const dedge* a = (const dedge*)pa;
+    const dedge* b = (const dedge*)pb;
+    if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;
+    if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;
+    /* put the lo -> hi direction first */
+    int da = (a->from == a->lo) ? 0 : 1;
+    int db = (b->from == b->lo) ? 0 : 1;
+    return da - db;
+}
+
+int orc_topology(int nv, int nt, const int* tri, int* edge, int* hinge, int* hinge_tri) {
+    int nd = 3 * nt;
+    dedge* d = (dedge*)malloc(sizeof(dedge) * (size_t)nd);
+    if (!d) return -1;
+    for (int t = 0; t < nt; ++t) {
+        for (int s = 0; s < 3; ++s) {
+            int p = tri[3 * t + s];
+            int q = tri[3 * t + (s + 1) % 3];
+            int r = tri[3 * t + (s + 2) % 3];
+            if (p < 0 || p >= nv || q < 0 || q >= nv || r < 0 || r >= nv || p == q) {
+                free(d);
+                return -1;
+            }
+            dedge* e = &d[3 * t + s];
+            e->lo = p < q ? p : q;
+            e->hi = p < q ? q : p;
+            e->from = p;
+            e->to = q;
+            e->wing = r;
+            e->t = t;
+        }
+    }
+    qsort(d, (size_t)nd, sizeof(dedge), dedge_cmp);
+    if (nd % 2) {
+        free(d);
+        return -1;
+    }
+    int ne = 0;
+    for (int k = 0; k < nd; k += 2) {
+        dedge* a = &d[k];
+        dedge* b = &d[k + 1];
+        /* each undirected edge exactly twice, once in each direction */
+        if (a->lo != b->lo || a->hi != b->hi || a->from != a->lo || b->from != b->hi) {
+            free(d);
+            return -1;
+        }
+        if (k + 2 < nd && d[k + 2].lo == a->lo && d[k + 2].hi == a->hi) {
+            free(d);
+            return -1;
+        }
+        edge[2 * ne + 0] = a->lo;
+        edge[2 * ne + 1] = a->hi;
+        /* T1 runs B -> C (B = lo, C = hi), wing A; T2 has wing D */
+        hinge[4 * ne + 0] = a->wing;
+        hinge[4 * ne + 1] = a->from;
+        hinge[4 * ne + 2] = a->to;
+        hinge[4 * ne + 3] = b->wing;
+        hinge_tri[2 * ne + 0] = a->t;
+        hinge_tri[2 * ne + 1] = b->t;
+        ++ne;
+    }
+    free(d);
+    return ne;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Geometry: triangle areas, total surface, enclosed volume                  */
+/* ------------------------------------------------------------------------- */
+void orc_geometry(int nv, const double* x, int nt, const int* tri, double* S,
+                  double* area_total, double* volume) {
+    (void)nv;
+    double A = 0.0, V = 0.0;
+    const double* r0 = &x[0]; /* volume reference point: node 0 */
+    for (int t = 0; t < nt; ++t) {
+        const double* a = &x[3 * tri[3 * t + 0]];
+        const double* b = &x[3 * tri[3 * t + 1]];
+        const double* c = &x[3 * tri[3 * t + 2]];
+        double ab[3], ac[3], N[3];
+        sub3(b, a, ab);
+        sub3(c, a, ac);
+        cross3(ab, ac, N);
+        double s = 0.5 * norm3(N);
+        if (S) S[t] = s;
+        A += s;
+        /* signed tetrahedron (r0, a, b, c); with inward-oriented triangles
+         * the sum of a~ . (b~ x c~) is -6 V */
+        double at[3], bt[3], ct[3], bc[3];
+        sub3(a, r0, at);
+        sub3(b, r0, bt);
+        sub3(c, r0, ct);
+        cross3(bt, ct, bc);
+        V += -dot3(at, bc) / 6.0;
+    }
+    if (area_total) *area_total = A;
+    if (volume) *volume = V;
+}
+
+/* unit normal of triangle (a, b, c): AB x AC normalised (points inward for a
+ * correctly stored triangle) */
+static void unit_normal(const double* a, const double* b, const double* c, double* n) {
+    double ab[3], ac[3];
+    sub3(b, a, ab);
+    sub3(c, a, ac);
+    cross3(ab, ac, n);
+    double l = norm3(n);
+    n[0] /= l;
+    n[1] /= l;
+    n[2] /= l;
+}
+
+/* Inner dihedral angle of hinge (A, B, C, D): T1 = (A, B, C), T2 = (D, C, B)
+ * in their stored cyclic orders.  theta = pi + atan2((n1 x n2) . e, n1 . n2)
+ * with e the unit vector B -> C; a flat hinge gives pi, a convex one less. */
+double orc_dihedral(const double* xa, const double* xb, const double* xc, const double* xd) {
+    double n1[3], n2[3], e[3], m[3];
+    unit_normal(xa, xb, xc, n1);
+    unit_normal(xd, xc, xb, n2);
+    sub3(xc, xb, e);
+    double le = norm3(e);
+    e[0] /= le;
+    e[1] /= le;
+    e[2] /= le;
+    cross3(n1, n2, m);
+    return M_PI + atan2(dot3(m, e), dot3(n1, n2));
+}
+
+void orc_relaxed(int nv, const double* x, int nt, const int* tri, int ne, const int* edge,
+                 const int* hinge, double* L0, double* theta0, double* S0,
+                 double* Sg0, double* V0) {
+    for (int e = 0; e < ne; ++e) {
+        double d[3];
+        sub3(&x[3 * edge[2 * e + 1]], &x[3 * edge[2 * e + 0]], d);
+        L0[e] = norm3(d);
+        const int* h = &hinge[4 * e];
+        theta0[e] = orc_dihedral(&x[3 * h[0]], &x[3 * h[1]], &x[3 * h[2]], &x[3 * h[3]]);
+    }
+    orc_geometry(nv, x, nt, tri, S0, Sg0, V0);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Elastic forces ("Elastic interactions")                                   */
+/* ------------------------------------------------------------------------- */
+
+/* Stretching: each edge endpoint is pulled towards (L > L0) or pushed away
+ * from (L < L0) the other with magnitude ks kappa(lambda) (L - L0)/L0. */
+void orc_force_stretch(int nv, const double* x, int ne, const int* edge, const double* L0,
+                       double ks, int linear, double* F) {
+    (void)nv;
+    if (ks == 0.0) return;
+    for (int e = 0; e < ne; ++e) {
+        int a = edge[2 * e], b = edge[2 * e + 1];
+        double d[3];
+        sub3(&x[3 * b], &x[3 * a], d);
+        double L = norm3(d);
+        double lam = L / L0[e];
+        double kap = linear ? 1.0 : orc_kappa(lam);
+        double f = ks * kap * (L - L0[e]) / L0[e];
+        for (int c = 0; c < 3; ++c) {
+            F[3 * a + c] += f * d[c] / L;
+            F[3 * b + c] -= f * d[c] / L;
+        }
+    }
+}
+
+/* Bending: F_b = kb (theta - theta0)/theta0 n on each wing vertex along the
+ * unit (inward) normal of its own triangle; each vertex of the shared edge
+ * receives minus half the sum of the two wing forces. */
+void orc_force_bend(int nv, const double* x, int ne, const int* hinge, const double* theta0,
+                    double kb, double* F) {
+    (void)nv;
+    if (kb == 0.0) return;
+    for (int e = 0; e < ne; ++e) {
+        int A = hinge[4 * e], B = hinge[4 * e + 1], C = hinge[4 * e + 2], D = hinge[4 * e + 3];
+        double n1[3], n2[3];
+        unit_normal(&x[3 * A], &x[3 * B], &x[3 * C], n1);
+        unit_normal(&x[3 * D], &x[3 * C], &x[3 * B], n2);
+        double theta = orc_dihedral(&x[3 * A], &x[3 * B], &x[3 * C], &x[3 * D]);
+        double f = kb * (theta - theta0[e]) / theta0[e];
+        for (int c = 0; c < 3; ++c) {
+            F[3 * A + c] += f * n1[c];
+            F[3 * D + c] += f * n2[c];
+            F[3 * B + c] -= 0.5 * f * (n1[c] + n2[c]);
+            F[3 * C + c] -= 0.5 * f * (n1[c] + n2[c]);
+        }
+    }
+}
+
+/* centroid-to-vertex unit vectors of triangle t */
+static void tri_w(const double* x, const int* tv, double w[3][3]) {
+    double cen[3];
+    for (int c = 0; c < 3; ++c)
+        cen[c] = (x[3 * tv[0] + c] + x[3 * tv[1] + c] + x[3 * tv[2] + c]) / 3.0;
+    for (int s = 0; s < 3; ++s) {
+        sub3(&x[3 * tv[s]], cen, w[s]);
+        double l = norm3(w[s]);
+        for (int c = 0; c < 3; ++c) w[s][c] /= l;
+    }
+}
+
+static double tri_area(const double* x, const int* tv) {
+    double ab[3], ac[3], N[3];
+    sub3(&x[3 * tv[1]], &x[3 * tv[0]], ab);
+    sub3(&x[3 * tv[2]], &x[3 * tv[0]], ac);
+    cross3(ab, ac, N);
+    return 0.5 * norm3(N);
+}
+
+/* Local area: F_al = -kal (S - S0)/S w at each vertex. */
+void orc_force_local_area(int nv, const double* x, int nt, const int* tri, const double* S0,
+                          double kal, double* F) {
+    (void)nv;
+    if (kal == 0.0) return;
+    for (int t = 0; t < nt; ++t) {
+        const int* tv = &tri[3 * t];
+        double S = tri_area(x, tv);
+        double w[3][3];
+        tri_w(x, tv, w);
+        double coef = -kal * (S - S0[t]) / S;
+        for (int s = 0; s < 3; ++s)
+            for (int c = 0; c < 3; ++c) F[3 * tv[s] + c] += coef * w[s][c];
+    }
+}
+
+/* Global area: F_ag = -kag (Sg - Sg0)/Sg w, applied per triangle to its
+ * vertices with the local centroid-to-vertex direction. */
+void orc_force_global_area(int nv, const double* x, int nt, const int* tri, double Sg0,
+                           double kag, double* F) {
+    if (kag == 0.0) return;
+    double Sg;
+    orc_geometry(nv, x, nt, tri, NULL, &Sg, NULL);
+    double coef = -kag * (Sg - Sg0) / Sg;
+    for (int t = 0; t < nt; ++t) {
+        const int* tv = &tri[3 * t];
+        double w[3][3];
+        tri_w(x, tv, w);
+        for (int s = 0; s < 3; ++s)
+            for (int c = 0; c < 3; ++c) F[3 * tv[s] + c] += coef * w[s][c];
+    }
+}
+
+/* Volume: per triangle F_v = -kv (V - V0)/V0 S n_out, one third to each vertex. */
+void orc_force_volume(int nv, const double* x, int nt, const int* tri, double V0,
+                      double kv, double* F) {
+    if (kv == 0.0) return;
+    double V;
+    orc_geometry(nv, x, nt, tri, NULL, NULL, &V);
+    double coef = -kv * (V - V0) / V0;
+    for (int t = 0; t < nt; ++t) {
+        const int* tv = &tri[3 * t];
+        double n_in[3];
+        unit_normal(&x[3 * tv[0]], &x[3 * tv[1]], &x[3 * tv[2]], n_in);
+        double S = tri_area(x, tv);
+        for (int s = 0; s < 3; ++s)
+            for (int c = 0; c < 3; ++c) F[3 * tv[s] + c] += coef * S * (-n_in[c]) / 3.0;
+    }
+}
+
+void orc_membrane_forces(int nv, const double* x, int nt, const int* tri, int ne,
+                         const int* edge, const int* hinge, const double* L0,
+                         const double* theta0, const double* S0, double Sg0, double V0,
+                         const double* k, int linear, double* F) {
+    orc_force_stretch(nv, x, ne, edge, L0, k[0], linear, F);
+    orc_force_bend(nv, x, ne, hinge, theta0, k[1], F);
+    orc_force_local_area(nv, x, nt, tri, S0, k[2], F);
+    orc_force_global_area(nv, x, nt, tri, Sg0, k[3], F);
+    orc_force_volume(nv, x, nt, tri, V0, k[4], F);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Lattice Boltzmann ("Method", eq. lbequation and the moment definitions)   */
+/* ------------------------------------------------------------------------- */
+static long node_index(const orc_lattice* L, int x, int y, int z) {
+    return ((long)z * L->ny + y) * L->nx + x;
+}
+
+static int wrap(int i, int n) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+void orc_moments(const orc_lattice* L, const double* n, const double* Fx, double* rho,
+                 double* u) {
+    long N = (long)L->nx * L->ny * L->nz;
+    for (long p = 0; p < N; ++p) {
+        double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < 19; ++i) {
+            double ni = n[i * N + p];
+            r += ni;
+            for (int c = 0; c < 3; ++c) j[c] += ni * EV[i][c];
+        }
+        double F[3];
+        for (int c = 0; c < 3; ++c) F[c] = L->g[c] + (Fx ? Fx[c * N + p] : 0.0);
+        if (rho) rho[p] = r;
+        if (u)
+            for (int c = 0; c < 3; ++c) u[c * N + p] = (j[c] + 0.5 * F[c]) / r;
+    }
+}
+
+void orc_lb_step(const orc_lattice* L, const double* n, const double* G, double* nout) {
+    long N = (long)L->nx * L->ny * L->nz;
+    double tau = L->tau;
+    for (int z = 0; z < L->nz; ++z)
+        for (int y = 0; y < L->ny; ++y)
+            for (int x = 0; x < L->nx; ++x) {
+                long p = node_index(L, x, y, z);
+                double F[3];
+                for (int c = 0; c < 3; ++c) F[c] = L->g[c] + (G ? G[c * N + p] : 0.0);
+                /* moments */
+                double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+                for (int i = 0; i < 19; ++i) {
+                    double ni = n[i * N + p];
+                    rho += ni;
+                    for (int c = 0; c < 3; ++c) j[c] += ni * EV[i][c];
+                }
+                double u[3];
+                for (int c = 0; c < 3; ++c) u[c] = (j[c] + 0.5 * F[c]) / rho;
+                double usq = dot3(u, u);
+                for (int i = 0; i < 19; ++i) {
+                    double e[3] = {EV[i][0], EV[i][1], EV[i][2]};
+                    double eu = dot3(e, u);
+                    double w = weight(i);
+                    /* second-order equilibrium */
+                    double neq = w * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+                    /* Guo source term */
+                    double src = 0.0;
+                    for (int c = 0; c < 3; ++c) src += (3.0 * (e[c] - u[c]) + 9.0 * eu * e[c]) * F[c];
+                    src *= (1.0 - 0.5 / tau) * w;
+                    double ns = n[i * N + p] - (n[i * N + p] - neq) / tau + src;
+                    /* propagation to x + e_i */
+                    int xd = wrap(x + EV[i][0], L->nx);
+                    int yd = wrap(y + EV[i][1], L->ny);
+                    int zd = z + EV[i][2];
+                    if (L->walls_z && (zd < 0 || zd >= L->nz)) {
+                        /* halfway bounce-back: the population returns to its
+                         * own node in the opposite direction */
+                        nout[opposite(i) * N + p] = ns;
+                    } else {
+                        zd = wrap(zd, L->nz);
+                        nout[i * N + node_index(L, xd, yd, zd)] = ns;
+                    }
+                }
+            }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Coupling ("Immersed Boundary method", eq. dragforce and what follows)     */
+/* ------------------------------------------------------------------------- */
+int orc_stencil(const orc_lattice* L, const double* X, long* idx, double* w) {
+    int dims[3] = {L->nx, L->ny, L->nz};
+    int i0[3];
+    double phi[3];
+    for (int c = 0; c < 3; ++c) {
+        double s = X[c] - 0.5; /* nodes sit at cell centres */
+        double f = floor(s);
+        i0[c] = (int)f;
+        phi[c] = s - f;
+    }
+    int clamped = 0;
+    int k = 0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                int d[3] = {dx, dy, dz};
+                int ii[3];
+                double ww = 1.0;
+                for (int c = 0; c < 3; ++c) {
+                    ii[c] = i0[c] + d[c];
+                    ww *= d[c] ? phi[c] : 1.0 - phi[c];
+                }
+                ii[0] = wrap(ii[0], dims[0]);
+                ii[1] = wrap(ii[1], dims[1]);
+                if (L->walls_z) {
+                    if (ii[2] < 0) {
+                        ii[2] = 0;
+                        ++clamped;
+                    } else if (ii[2] >= dims[2]) {
+                        ii[2] = dims[2] - 1;
+                        ++clamped;
+                    }
+                } else {
+                    ii[2] = wrap(ii[2], dims[2]);
+                }
+                idx[k] = node_index(L, ii[0], ii[1], ii[2]);
+                w[k] = ww;
+                ++k;
+            }
+    return clamped;
+}
+
+int orc_couple_point(const orc_lattice* L, const double* u, const double* X, const double* V,
+                     double* G, double* drag) {
+    long N = (long)L->nx * L->ny * L->nz;
+    long idx[8];
+    double w[8];
+    int clamped = orc_stencil(L, X, idx, w);
+    /* fluid velocity at the point: linear interpolation from the 8 nodes */
+    double uj[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 8; ++k)
+        for (int c = 0; c < 3; ++c) uj[c] += w[k] * u[c * N + idx[k]];
+    /* xi (v - u): the force handed to the fluid; the point feels its opposite */
+    for (int c = 0; c < 3; ++c) drag[c] = L->xi * (V[c] - uj[c]);
+    /* distributed to the same 8 nodes with the same weights */
+    for (int k = 0; k < 8; ++k)
+        for (int c = 0; c < 3; ++c) G[c * N + idx[k]] += w[k] * drag[c];
+    return clamped;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Coupled system                                                            */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int nv, nt, ne;
+    int* tri;
+    int* edge;
+    int* hinge;
+    int* hinge_tri;
+    double *L0, *theta0, *S0;
+    double Sg0, V0;
+    double k[5];
+    int linear;
+} orc_tmpl;
+
+struct orc_system {
+    orc_lattice L;
+    int n_tmpl, n_obj;
+    orc_tmpl* t;
+    int* o_tmpl;
+    int* o_off;
+    double* o_mass;
+    double* o_fext;
+    long M;
+    double* Fel; /* [M][3] */
+    double* G;   /* [3][N] */
+    double* u;   /* [3][N] */
+    double* rho; /* [N] */
+    double* ntmp;
+};
+
+void orc_system_destroy(orc_system* s) {
+    if (!s) return;
+    for (int t = 0; t < s->n_tmpl; ++t) {
+        free(s->t[t].tri);
+        free(s->t[t].edge);
+        free(s->t[t].hinge);
+        free(s->t[t].hinge_tri);
+        free(s->t[t].L0);
+        free(s->t[t].theta0);
+        free(s->t[t].S0);
+    }
+    free(s->t);
+    free(s->o_tmpl);
+    free(s->o_off);
+    free(s->o_mass);
+    free(s->o_fext);
+    free(s->Fel);
+    free(s->G);
+    free(s->u);
+    free(s->rho);
+    free(s->ntmp);
+    free(s);
+}
+
+orc_system* orc_system_create(const orc_lattice* L, const orc_mesh* m, const int* t_node_off,
+                              const double* t_x) {
+    orc_system* s = (orc_system*)calloc(1, sizeof(orc_system));
+    s->L = *L;
+    s->n_tmpl = m->n_tmpl;
+    s->n_obj = m->n_obj;
+    s->t = (orc_tmpl*)calloc((size_t)(m->n_tmpl > 0 ? m->n_tmpl : 1), sizeof(orc_tmpl));
+    for (int t = 0; t < m->n_tmpl; ++t) {
+        orc_tmpl* T = &s->t[t];
+        T->nv = m->t_nv[t];
+        T->nt = m->t_nt[t];
+        int ne_max = 3 * T->nt / 2 + 1;
+        T->tri = (int*)malloc(sizeof(int) * 3 * (size_t)T->nt);
+        memcpy(T->tri, &m->tri[3 * (size_t)m->t_tri_off[t]], sizeof(int) * 3 * (size_t)T->nt);
+        T->edge = (int*)malloc(sizeof(int) * 2 * (size_t)ne_max);
+        T->hinge = (int*)malloc(sizeof(int) * 4 * (size_t)ne_max);
+        T->hinge_tri = (int*)malloc(sizeof(int) * 2 * (size_t)ne_max);
+        T->ne = orc_topology(T->nv, T->nt, T->tri, T->edge, T->hinge, T->hinge_tri);
+        if (T->ne < 0) {
+            orc_system_destroy(s);
+            return NULL;
+        }
+        T->L0 = (double*)malloc(sizeof(double) * (size_t)T->ne);
+        T->theta0 = (double*)malloc(sizeof(double) * (size_t)T->ne);
+        T->S0 = (double*)malloc(sizeof(double) * (size_t)T->nt);
+        orc_relaxed(T->nv, &t_x[3 * (size_t)t_node_off[t]], T->nt, T->tri, T->ne, T->edge,
+                    T->hinge, T->L0, T->theta0, T->S0, &T->Sg0, &T->V0);
+        for (int c = 0; c < 5; ++c) T->k[c] = m->t_k[5 * t + c];
+        T->linear = m->t_linear[t];
+    }
+    s->o_tmpl = (int*)malloc(sizeof(int) * (size_t)(m->n_obj + 1));
+    s->o_off = (int*)malloc(sizeof(int) * (size_t)(m->n_obj + 1));
+    s->o_mass = (double*)malloc(sizeof(double) * (size_t)(m->n_obj + 1));
+    s->o_fext = (double*)malloc(sizeof(double) * 3 * (size_t)(m->n_obj + 1));
+    s->M = 0;
+    for (int o = 0; o < m->n_obj; ++o) {
+        s->o_tmpl[o] = m->o_tmpl[o];
+        s->o_off[o] = m->o_node_off[o];
+        s->o_mass[o] = m->o_mass[o];
+        for (int c = 0; c < 3; ++c) s->o_fext[3 * o + c] = m->o_fext[3 * o + c];
+        long end = (long)m->o_node_off[o] + s->t[m->o_tmpl[o]].nv;
+        if (end > s->M) s->M = end;
+    }
+    long N = (long)L->nx * L->ny * L->nz;
+    s->Fel = (double*)calloc((size_t)(3 * s->M + 1), sizeof(double));
+    s->G = (double*)calloc((size_t)(3 * N), sizeof(double));
+    s->u = (double*)calloc((size_t)(3 * N), sizeof(double));
+    s->rho = (double*)calloc((size_t)N, sizeof(double));
+    s->ntmp = (double*)calloc((size_t)(19 * N), sizeof(double));
+    return s;
+}
+
+void orc_system_geometry(orc_system* s, const double* X, double* Sg, double* Vol) {
+    for (int o = 0; o < s->n_obj; ++o) {
+        orc_tmpl* T = &s->t[s->o_tmpl[o]];
+        orc_geometry(T->nv, &X[3 * (size_t)s->o_off[o]], T->nt, T->tri, NULL, &Sg[o], &Vol[o]);
+    }
+}
+
+void orc_system_forces(orc_system* s, const double* X, double* F) {
+    memset(F, 0, sizeof(double) * 3 * (size_t)s->M);
+    for (int o = 0; o < s->n_obj; ++o) {
+        orc_tmpl* T = &s->t[s->o_tmpl[o]];
+        size_t off = 3 * (size_t)s->o_off[o];
+        orc_membrane_forces(T->nv, &X[off], T->nt, T->tri, T->ne, T->edge, T->hinge, T->L0,
+                            T->theta0, T->S0, T->Sg0, T->V0, T->k, T->linear, &F[off]);
+    }
+}
+
+long orc_system_touched(orc_system* s, const double* X) {
+    long N = (long)s->L.nx * s->L.ny * s->L.nz;
+    unsigned char* mark = (unsigned char*)calloc((size_t)N, 1);
+    long cnt = 0;
+    for (long j = 0; j < s->M; ++j) {
+        long idx[8];
+        double w[8];
+        orc_stencil(&s->L, &X[3 * j], idx, w);
+        for (int k = 0; k < 8; ++k)
+            if (!mark[idx[k]]) {
+                mark[idx[k]] = 1;
+                ++cnt;
+            }
+    }
+    free(mark);
+    return cnt;
+}
+
+int orc_system_run(orc_system* s, double* n, double* X, double* V, int n_steps, double* diag) {
+    const orc_lattice* L = &s->L;
+    long N = (long)L->nx * L->ny * L->nz;
+    for (int step = 0; step < n_steps; ++step) {
+        double d[10] = {0};
+        /* a non-finite mesh state has no stencil: stop instead of indexing */
+        for (long j = 0; j < 3 * s->M; ++j)
+            if (!isfinite(X[j]) || !isfinite(V[j]) || fabs(X[j]) > 1e9) return -1 - step;
+        /* 1-2: geometry and membrane forces from the positions at step start */
+        orc_system_forces(s, X, s->Fel);
+        /* 3: coupling.  Node velocity from the populations at step start,
+         * with half the body force only. */
+        orc_moments(L, n, NULL, s->rho, s->u);
+        memset(s->G, 0, sizeof(double) * 3 * (size_t)N);
+        for (int o = 0; o < s->n_obj; ++o) {
+            int nv = s->t[s->o_tmpl[o]].nv;
+            double m = s->o_mass[o];
+            for (int v = 0; v < nv; ++v) {
+                long j = (long)s->o_off[o] + v;
+                double drag[3]; /* xi (v - u): the force handed to the fluid */
+                d[0] += orc_couple_point(L, s->u, &X[3 * j], &V[3 * j], s->G, drag);
+                /* 4: mesh update, kick then drift */
+                for (int c = 0; c < 3; ++c) {
+                    double Ft = s->Fel[3 * j + c] - drag[c] + s->o_fext[3 * o + c];
+                    V[3 * j + c] += Ft / m;
+                    X[3 * j + c] += V[3 * j + c];
+                    d[1 + c] += s->Fel[3 * j + c];
+                    d[4 + c] += -drag[c];
+                    d[7 + c] += s->o_fext[3 * o + c];
+                }
+            }
+        }
+        /* 5: lattice Boltzmann update with force density g + G */
+        orc_lb_step(L, n, s->G, s->ntmp);
+        memcpy(n, s->ntmp, sizeof(double) * 19 * (size_t)N);
+        if (diag && step == n_steps - 1) memcpy(diag, d, sizeof(d));
+    }
+    return 0;
+}

@@ -1,0 +1,145 @@
+/*
+ * oif_oracle.h -- plain FP64 CPU oracle for one coupled lattice-Boltzmann /
+ * immersed-membrane time step (Cimrak, Gusenbauer, Jancigova: "An ESPResSo
+ * implementation of elastic objects immersed in a fluid").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include,
+ * link or call this code; only the tests, the smoke check and the bench's
+ * CPU-baseline leg use it.  It shares no code, header, table or helper with
+ * the HIP path.
+ *
+ * Conventions (the paper fixes none of them):
+ *   D3Q19 ordering: 0 rest; 1/2 = +-x; 3/4 = +-y; 5/6 = +-z;
+ *   7/8 = (1,1,0)/(-1,-1,0); 9/10 = (1,-1,0)/(-1,1,0);
+ *   11/12 = (1,0,1)/(-1,0,-1); 13/14 = (1,0,-1)/(-1,0,1);
+ *   15/16 = (0,1,1)/(0,-1,-1); 17/18 = (0,1,-1)/(0,-1,1).
+ *   Populations are stored as full n_i (not deviations), layout
+ *   [19][nz][ny][nx], x fastest.  Lattice node (i,j,k) sits at (i+1/2, j+1/2, k+1/2).
+ *   Lattice units: grid spacing 1, time step 1.
+ *   Triangles are stored with the normal AB x AC pointing into the object
+ *   (template section of the paper).
+ */
+#ifndef OIF_ORACLE_H
+#define OIF_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* kappa(lambda) of the neo-Hookean stretching law ("Stretching force"). */
+double orc_kappa(double lambda);
+
+/* Undirected edges and hinges from a closed, consistently oriented triangle
+ * list.  For every edge {u < v}: edge = (u, v); hinge = (A, B, C, D) where the
+ * triangle T1 = hinge_tri[0] runs B -> C in its stored cyclic order and has the
+ * third vertex A, and T2 = hinge_tri[1] is the other triangle on the edge with
+ * third vertex D.  Arrays must hold 3*nt/2 entries.  Returns the edge count,
+ * or -1 if an edge is not shared by exactly two oppositely oriented triangles. */
+int orc_topology(int nv, int nt, const int* tri, int* edge, int* hinge, int* hinge_tri);
+
+/* Triangle areas S[nt], total area, enclosed volume (inward orientation). */
+void orc_geometry(int nv, const double* x, int nt, const int* tri, double* S,
+                  double* area_total, double* volume);
+
+/* Inner dihedral angle of a hinge (A, B, C, D) as defined for orc_topology. */
+double orc_dihedral(const double* xa, const double* xb, const double* xc, const double* xd);
+
+/* Relaxed values of a template from its node positions (after any stretch). */
+void orc_relaxed(int nv, const double* x, int nt, const int* tri, int ne, const int* edge,
+                 const int* hinge, double* L0, double* theta0, double* S0,
+                 double* Sg0, double* V0);
+
+/* Membrane forces of one object; ADDS into F[nv][3].
+ * k = {ks, kb, kal, kag, kv}; linear != 0 selects kappa = 1. */
+void orc_membrane_forces(int nv, const double* x, int nt, const int* tri, int ne,
+                         const int* edge, const int* hinge, const double* L0,
+                         const double* theta0, const double* S0, double Sg0, double V0,
+                         const double* k, int linear, double* F);
+
+/* Individual force families (same conventions), each ADDS into F. */
+void orc_force_stretch(int nv, const double* x, int ne, const int* edge, const double* L0,
+                       double ks, int linear, double* F);
+void orc_force_bend(int nv, const double* x, int ne, const int* hinge, const double* theta0,
+                    double kb, double* F);
+void orc_force_local_area(int nv, const double* x, int nt, const int* tri, const double* S0,
+                          double kal, double* F);
+void orc_force_global_area(int nv, const double* x, int nt, const int* tri, double Sg0,
+                           double kag, double* F);
+void orc_force_volume(int nv, const double* x, int nt, const int* tri, double V0,
+                      double kv, double* F);
+
+/* Lattice description. */
+typedef struct {
+    int nx, ny, nz;
+    int walls_z;     /* halfway bounce-back walls at z = 0 and z = nz */
+    double tau;      /* BGK relaxation time */
+    double rho0;
+    double g[3];     /* uniform body-force density */
+    double xi;       /* friction coefficient of the drag coupling */
+} orc_lattice;
+
+/* Density and velocity of every node, u = (sum n_i e_i + F/2) / rho with the
+ * given force density field Fx (3*N, may be NULL for body force only). */
+void orc_moments(const orc_lattice* L, const double* n, const double* Fx,
+                 double* rho, double* u);
+
+/* One collide + stream update of the whole lattice, n -> nout, with force
+ * density g + G (G may be NULL).  n and nout must not alias. */
+void orc_lb_step(const orc_lattice* L, const double* n, const double* G, double* nout);
+
+/* Trilinear stencil of a point: 8 node indices and weights.  Returns the number
+ * of clamped corner indices (only with walls_z). */
+int orc_stencil(const orc_lattice* L, const double* X, long* idx, double* w);
+
+/* Drag coupling of one mesh point at X with velocity V: interpolates the node
+ * velocity field u (3*N) at X, writes the force handed to the fluid,
+ * drag = xi (V - u(X)), and ADDS its trilinear share to G (3*N).  The point
+ * itself feels -drag.  Returns the number of clamped corners. */
+int orc_couple_point(const orc_lattice* L, const double* u, const double* X, const double* V,
+                     double* G, double* drag);
+
+/* Coupled system.  Mesh data of all objects is concatenated. */
+typedef struct {
+    int n_tmpl;
+    const int* t_nv;        /* per template */
+    const int* t_nt;
+    const int* t_tri_off;   /* offset into tri (in triangles) */
+    const int* tri;         /* concatenated [nt][3], template-local ids */
+    const double* t_k;      /* [n_tmpl][5] ks kb kal kag kv */
+    const int* t_linear;
+    /* relaxed values, computed by orc_system_prepare */
+    int n_obj;
+    const int* o_tmpl;
+    const int* o_node_off;  /* offset into X/V (in nodes) */
+    const double* o_mass;
+    const double* o_fext;   /* [n_obj][3] */
+} orc_mesh;
+
+typedef struct orc_system orc_system;
+
+/* Build a coupled system from template node coordinates (already stretched,
+ * concatenated per template, t_x) and the object placements (X0 = absolute
+ * initial positions of all mesh nodes).  Returns NULL on a mesh error. */
+orc_system* orc_system_create(const orc_lattice* L, const orc_mesh* mesh,
+                              const int* t_node_off, const double* t_x);
+void orc_system_destroy(orc_system* s);
+
+/* Advance n_steps coupled steps.  n: populations (19*N) in/out; X, V: mesh
+ * positions/velocities (3*M) in/out.  diag (may be NULL) receives, for the LAST
+ * step: [0] clamped stencil corners, [1..3] sum of elastic forces,
+ * [4..6] sum of coupling forces on the mesh, [7..9] sum of external forces. */
+int orc_system_run(orc_system* s, double* n, double* X, double* V, int n_steps, double* diag);
+
+/* Per-object geometry of the current positions: S_g[o], V[o]. */
+void orc_system_geometry(orc_system* s, const double* X, double* Sg, double* Vol);
+
+/* Elastic forces of all objects at positions X (overwrites F[3*M]). */
+void orc_system_forces(orc_system* s, const double* X, double* F);
+
+/* Number of distinct lattice nodes inside any mesh node's 2x2x2 stencil. */
+long orc_system_touched(orc_system* s, const double* X);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,73 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a copy of ``oracle/oif_oracle.c`` (on the CPU,
+never in the product code), builds it, and runs the oracle pin suite against
+that library in a subprocess; the suite must fail.  A mutation that survives
+means some part of the oracle is not pinned.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oif_oracle.c")
+PIN_FILES = ["tests/test_oracle_mesh.py", "tests/test_oracle_lb.py", "tests/test_oracle_coupling.py"]
+
+MUTATIONS = {
+    "kappa_exponent": ("(lambda + pow(lambda, -3.0))", "(lambda + pow(lambda, -2.0))"),
+    "stretch_sign": ("double f = ks * kap * (L - L0[e]) / L0[e];",
+                     "double f = ks * kap * (L0[e] - L) / L0[e];"),
+    "stretch_denominator": ("double f = ks * kap * (L - L0[e]) / L0[e];",
+                            "double f = ks * kap * (L - L0[e]) / L;"),
+    "bend_wing_normal": ("F[3 * D + c] += f * n2[c];", "F[3 * D + c] += f * n1[c];"),
+    "bend_split": ("F[3 * B + c] -= 0.5 * f * (n1[c] + n2[c]);",
+                   "F[3 * B + c] -= f * (n1[c] + n2[c]);"),
+    "dihedral_sign": ("return M_PI + atan2(dot3(m, e), dot3(n1, n2));",
+                      "return M_PI - atan2(dot3(m, e), dot3(n1, n2));"),
+    "local_area_denominator": ("double coef = -kal * (S - S0[t]) / S;",
+                               "double coef = -kal * (S - S0[t]) / S0[t];"),
+    "global_area_denominator": ("double coef = -kag * (Sg - Sg0) / Sg;",
+                                "double coef = -kag * (Sg - Sg0) / Sg0;"),
+    "volume_force_inward": ("coef * S * (-n_in[c]) / 3.0", "coef * S * (n_in[c]) / 3.0"),
+    "volume_force_split": ("coef * S * (-n_in[c]) / 3.0", "coef * S * (-n_in[c]) / 2.0"),
+    "volume_sign": ("V += -dot3(at, bc) / 6.0;", "V += dot3(at, bc) / 6.0;"),
+    "equilibrium_coefficient": ("4.5 * eu * eu", "4.0 * eu * eu"),
+    "guo_prefactor": ("src *= (1.0 - 0.5 / tau) * w;", "src *= w;"),
+    "guo_second_order_term": ("(3.0 * (e[c] - u[c]) + 9.0 * eu * e[c])",
+                              "(3.0 * (e[c] - u[c]))"),
+    "lb_velocity_half_force": ("u[c] = (j[c] + 0.5 * F[c]) / rho;", "u[c] = j[c] / rho;"),
+    "bounce_back_direction": ("nout[opposite(i) * N + p] = ns;", "nout[i * N + p] = ns;"),
+    "stream_direction": ("int xd = wrap(x + EV[i][0], L->nx);", "int xd = wrap(x - EV[i][0], L->nx);"),
+    "weight_table": ("return 1.0 / 36.0;", "return 1.0 / 32.0;"),
+    "drag_sign": ("drag[c] = L->xi * (V[c] - uj[c]);", "drag[c] = L->xi * (uj[c] - V[c]);"),
+    "interp_uniform": ("uj[c] += w[k] * u[c * N + idx[k]];", "uj[c] += 0.125 * u[c * N + idx[k]];"),
+    "spread_uniform": ("G[c * N + idx[k]] += w[k] * drag[c];",
+                       "G[c * N + idx[k]] += 0.125 * drag[c];"),
+    "node_offset": ("double s = X[c] - 0.5;", "double s = X[c];"),
+    "interp_full_force": ("for (int c = 0; c < 3; ++c) u[c * N + p] = (j[c] + 0.5 * F[c]) / r;",
+                          "for (int c = 0; c < 3; ++c) u[c * N + p] = (j[c] + F[c]) / r;"),
+    "mass_ignored": ("V[3 * j + c] += Ft / m;", "V[3 * j + c] += Ft;"),
+    "drift_before_kick": ("V[3 * j + c] += Ft / m;\n                    X[3 * j + c] += V[3 * j + c];",
+                          "X[3 * j + c] += V[3 * j + c];\n                    V[3 * j + c] += Ft / m;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {old!r}"
+    mutated = src.replace(old, new)
+    cfile = tmp_path / "oif_oracle.c"
+    cfile.write_text(mutated)
+    (tmp_path / "oif_oracle.h").write_text(open(SRC[:-2] + ".h").read())
+    so = tmp_path / "liboif_oracle_mut.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
+                    "-ffp-contract=off", "-o", str(so), str(cfile), "-lm"], check=True)
+    env = dict(os.environ, OIF_ORACLE_LIB=str(so), PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        *PIN_FILES], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode != 0, f"mutation {name} survived the pins:\n{r.stdout[-2000:]}"
