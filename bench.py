@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled lattice-Boltzmann / immersed-membrane step on one
+MI355X, on the precision-form workload: 256x128x128 periodic box, 500
+level-3 icospheres (642 nodes, radius 4) at seeded random centres.
+
+One step = membrane forces + coupling + mesh update + LB collide/stream over
+the whole box.  Inputs are resident in HBM before the timed region.  Prints one
+JSON line:
+  value          MLUPS of the coupled step with FP32 storage (whole job)
+  roofline       the lattice kernel (dominant) against 8 TB/s: algorithmic
+                 bytes 2 x 19 x 4 per node per launch / its average duration
+                 from HIP events on its own stream during the timed region
+  cpu_baseline   the FP64 oracle, single-threaded on the host, on a bounded
+                 sample (a few steps of the same workload)
+  storage        FP16/BF16 deviation storage: throughput and velocity error
+                 against the FP64 form after the same number of steps on the
+                 64^3 sub-run (31 cells, same number density)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+BYTES_POP = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def measure(oif, box, prec, steps, warmup, graph_steps=0, tune=None):
+    ctx = oif.Context.from_box(box, precision=prec)
+    if tune:
+        ctx.autotune(tune)
+    if warmup:
+        ctx.step(warmup)
+    t = ctx.step_timed(steps)
+    info = ctx.info()
+    out = dict(total_ms=t.total_ms, lb_ms=t.lb_ms, mesh_ms=t.mesh_ms, lb_block=info.lb_block,
+               mesh_block=info.mesh_block, xcd_remap=info.xcd_remap)
+    if graph_steps:
+        ctx.set_graph(graph_steps)
+        ctx.step(2 * graph_steps)  # capture + warm
+        t0 = time.perf_counter()
+        ctx.step(steps)
+        out["graph_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / steps
+    d = ctx.diagnostics()
+    out["mass_rel_drift"] = abs(d.mass - box.n_nodes * box.rho0) / (box.n_nodes * box.rho0)
+    out["touched"] = ctx.touched_nodes()
+    ctx.close()
+    return out
+
+
+def storage_error(oif, steps):
+    """Velocity error of FP16/BF16/FP32 storage against the FP64 form after
+    `steps` steps of the 64^3 sub-run."""
+    from paper_1312_3426_amd import synth
+
+    box = synth.config_precision_subbox(steps)
+    ref = oif.Context.from_box(box, precision="fp64")
+    ref.step(steps)
+    u_ref = ref.read_velocity()
+    ref.close()
+    umax = float(np.abs(u_ref).max())
+    out = {}
+    for prec in ("fp32", "fp16", "bf16"):
+        c = oif.Context.from_box(box, precision=prec)
+        c.step(steps)
+        du = c.read_velocity() - u_ref
+        c.close()
+        out[prec] = dict(u_err_max=float(np.abs(du).max() / umax),
+                         u_err_rms=float(np.sqrt(np.mean(du * du)) / umax))
+    return out, umax
+
+
+def cpu_baseline(box, steps):
+    import oracle
+
+    oracle.build()
+    t0 = time.perf_counter()
+    s = oracle.System(box)
+    t1 = time.perf_counter()
+    s.run(steps)
+    t2 = time.perf_counter()
+    return dict(value=box.n_nodes * steps / (t2 - t1) / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{steps} coupled steps of the full workload ({box.nx}x{box.ny}x{box.nz}, "
+                       f"{len(box.objects)} cells), single-threaded FP64, {t2 - t1:.1f} s "
+                       f"(+{t1 - t0:.1f} s setup)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-storage", action="store_true")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1312_3426_amd", "autotune.json"))
+    ap.add_argument("--workload", default="precision", choices=["precision", "scale"])
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is documented, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1312_3426_amd import oif, synth
+
+    if a.workload == "precision":
+        box = synth.config_precision(a.steps)
+    else:
+        box = synth.config_scale(a.steps)
+    N, M = box.n_nodes, box.n_mesh_nodes
+    log(f"[bench] workload {box.name}: N={N} M={M} steps={a.steps} warmup={a.warmup}")
+
+    res = {}
+    for prec in ("fp32", "fp16", "bf16"):
+        log(f"[bench] measuring {prec} storage")
+        res[prec] = measure(oif, box, prec, a.steps, a.warmup, graph_steps=50, tune=a.tune_cache)
+        log(f"[bench]   {prec}: {json.dumps(res[prec])}")
+
+    r32 = res["fp32"]
+    ms_step = r32["total_ms"] / a.steps
+    mlups = N / (ms_step * 1e-3) / 1e6
+    lb_bytes = 2 * 19 * BYTES_POP["fp32"] * N
+    achieved = lb_bytes / (r32["lb_ms"] * 1e-3) / 1e9
+    T = r32["touched"]
+    full_bytes = 2 * 19 * 4 * N + 48 * M + 100 * T
+    full_gbs = full_bytes / (ms_step * 1e-3) / 1e9
+
+    line = {
+        "metric": "MLUPS + mesh-node updates/s per coupled step; FP16-store vs FP32 at fixed error",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": box.name, "nx": box.nx, "ny": box.ny, "nz": box.nz, "cells": len(box.objects),
+                   "mesh_nodes": M, "storage": "fp32", "launch": {k: r32[k] for k in ("lb_block", "mesh_block", "xcd_remap")}},
+        "mesh_node_updates_per_s": round(M / (ms_step * 1e-3), 1),
+        "kernel_ms": {"lb": round(r32["lb_ms"], 5), "mesh": round(r32["mesh_ms"], 5)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "lb_kernel<FP32>", "bytes_per_launch": lb_bytes},
+        "full_step": {"bytes": full_bytes, "touched_nodes": T, "GB/s": round(full_gbs, 1),
+                      "frac": round(full_gbs / HBM_PEAK_GBS, 4)},
+        "graph": {p: (round(N / (res[p]["graph_ms_per_step"] * 1e-3) / 1e6, 2) if "graph_ms_per_step" in res[p] else None)
+                  for p in res},
+        "storage": {},
+    }
+    for p in ("fp16", "bf16"):
+        ms_p = res[p]["total_ms"] / a.steps
+        lbb = 2 * 19 * BYTES_POP[p] * N
+        line["storage"][p] = {"mlups": round(N / (ms_p * 1e-3) / 1e6, 2),
+                              "speedup_vs_fp32": round(ms_step / ms_p, 3),
+                              "lb_ms": round(res[p]["lb_ms"], 5),
+                              "lb_GB/s": round(lbb / (res[p]["lb_ms"] * 1e-3) / 1e9, 1),
+                              "mass_rel_drift": res[p]["mass_rel_drift"]}
+    if not a.no_storage:
+        log("[bench] storage-form velocity error on the 64^3 sub-run")
+        err, umax = storage_error(oif, 500)
+        for p in err:
+            line["storage"].setdefault(p, {}).update(err[p])
+        line["storage"]["error_reference"] = f"FP64 form, 64^3 sub-run, 500 steps, max|u| = {umax:.3e}"
+    if not a.no_cpu:
+        log(f"[bench] cpu baseline: oracle, {a.cpu_steps} steps")
+        line["cpu_baseline"] = cpu_baseline(box, a.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

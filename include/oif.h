@@ -1,0 +1,293 @@
+/*
+ * oif.h -- C ABI of the MI355X (gfx950) coupled lattice-Boltzmann /
+ * immersed-elastic-object step.
+ *
+ * Method: Cimrak, Gusenbauer, Jancigova, "An ESPResSo implementation of
+ * elastic objects immersed in a fluid" -- Section "Method" (D3Q19 LB update,
+ * eq. lbequation; IB point dynamics, eq. newton; drag coupling,
+ * eq. dragforce, with linear interpolation of the fluid velocity and
+ * distribution of the opposite force), Section "Elastic interactions"
+ * (stretching, bending, local area, global area, volume forces) and
+ * Section "Implementation details and OIF command description" (templates,
+ * objects, analysis, customisation).
+ *
+ * Conventions shared by every call
+ *   - Lattice units: grid spacing 1, time step 1.  Lattice node (i, j, k)
+ *     sits at (i + 1/2, j + 1/2, k + 1/2); the box spans [0,nx)x[0,ny)x[0,nz).
+ *   - D3Q19 ordering: 0 rest; 1/2 = +-x; 3/4 = +-y; 5/6 = +-z;
+ *     7/8 = (1,1,0)/(-1,-1,0); 9/10 = (1,-1,0)/(-1,1,0);
+ *     11/12 = (1,0,1)/(-1,0,-1); 13/14 = (1,0,-1)/(-1,0,1);
+ *     15/16 = (0,1,1)/(0,-1,-1); 17/18 = (0,1,-1)/(0,-1,1).
+ *   - Field layouts on the host: populations [19][nz][ny][nx] (x fastest),
+ *     vector fields [3][nz][ny][nx], mesh arrays [node][3].
+ *   - Collision: BGK with relaxation time tau, second-order equilibrium, Guo
+ *     forcing with force density g + G (G = coupling force); fluid velocity
+ *     u = (sum_i n_i e_i + F/2) / rho.  Drag: the mesh point feels
+ *     -xi (v - u), the fluid receives +xi (v - u) with trilinear weights.
+ *     Mesh update: symplectic Euler (v += F/m, then x += v).
+ *   - Every call returns OIF_OK (0) or a negative error code; the message of
+ *     the last error of a context is returned by oif_last_error.
+ *   - Ownership: input arrays are copied during the call and stay the
+ *     caller's; output arrays are caller-allocated host memory of the stated
+ *     size.  Device memory is owned by the context.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef OIF_H
+#define OIF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define OIF_OK 0
+#define OIF_E_ARG (-1)         /* bad pointer, size, id range or non-finite parameter */
+#define OIF_E_ID (-2)          /* ids must start at 0 and be consecutive */
+#define OIF_E_MESH (-3)        /* mesh not closed/manifold or not inward-oriented */
+#define OIF_E_STATE (-4)       /* call not valid in the current state */
+#define OIF_E_NOMEM (-5)       /* device or host allocation failed */
+#define OIF_E_HIP (-6)         /* a HIP runtime call failed */
+#define OIF_E_NONFINITE (-7)   /* watchdog: NaN/Inf in populations or mesh state */
+#define OIF_E_OVERFLOW (-8)    /* watchdog: fixed-point force accumulator out of range */
+#define OIF_E_UNSUPPORTED (-9) /* configuration not supported by this build */
+
+/* precision forms of the lattice populations */
+#define OIF_PREC_FP64 0          /* FP64 arithmetic and storage */
+#define OIF_PREC_FP32 1          /* FP32 arithmetic, FP32 storage of deviations */
+#define OIF_PREC_FP32_ST_FP16 2  /* FP32 arithmetic, FP16 storage of deviations x 2^s */
+#define OIF_PREC_FP32_ST_BF16 3  /* FP32 arithmetic, BF16 storage of deviations */
+
+/* stretching law ("Stretching force": neo-Hookean kappa(lambda), or kappa = 1) */
+#define OIF_STRETCH_NEOHOOKE 0
+#define OIF_STRETCH_LINEAR 1
+
+typedef struct oif_ctx oif_ctx;
+typedef struct oif_batch oif_batch;
+
+/* Fluid box ("Method"; the lbfluid parameters of the paper's example script).
+ *   nx, ny, nz      lattice size, each in [1, 4096], nx*ny*nz <= 2^31 / 19
+ *   walls_z         1: halfway bounce-back walls at z = 0 and z = nz (needs nz >= 2)
+ *   tau             BGK relaxation time, > 1/2 (kinematic viscosity (tau - 1/2)/3)
+ *   rho0            rest density, > 0; the fluid starts at rest at rho0
+ *   body_force      uniform force density g
+ *   friction        drag coefficient xi of eq. dragforce, >= 0
+ *   precision       OIF_PREC_*
+ *   fp16_scale_exp  FP16 storage: deviations n_i - w_i rho0 are stored times
+ *                   2^fp16_scale_exp, in [0, 24]
+ *   fixed_point_exp FP32 modes: the coupling force density is accumulated in
+ *                   int64 with resolution 2^-fixed_point_exp, in [16, 56]
+ *   device          HIP device ordinal
+ * Fill with oif_lattice_desc_init first; it sets tau 1, rho0 1, friction 0,
+ * FP32, fp16_scale_exp 12, fixed_point_exp 40, device 0, sizes 0. */
+typedef struct {
+    int nx, ny, nz;
+    int walls_z;
+    double tau;
+    double rho0;
+    double body_force[3];
+    double friction;
+    int precision;
+    int fp16_scale_exp;
+    int fixed_point_exp;
+    int device;
+} oif_lattice_desc;
+
+/* Elastic moduli of a template ("Elastic interactions"); 0 switches a force off. */
+typedef struct {
+    double ks, kb, kal, kag, kv;
+    int stretch_law; /* OIF_STRETCH_* */
+} oif_moduli;
+
+/* Object analysis (oif_object_analyze of the paper): origin = mean of the
+ * mesh nodes, bounds = {xmin, xmax, ymin, ymax, zmin, zmax}, enclosed volume,
+ * surface area, velocity = mean of the node velocities. */
+typedef struct {
+    double origin[3];
+    double bounds[6];
+    double volume;
+    double area;
+    double velocity[3];
+} oif_analysis;
+
+/* Counts and sizes (oif_info of the paper). */
+typedef struct {
+    int n_templates;
+    int n_objects;
+    int precision;
+    int walls_z;
+    long long n_nodes;
+    long long n_mesh_nodes;
+    long long steps_done;
+    long long device_bytes;
+    int lb_block;       /* tuned launch shapes in use */
+    int mesh_block;
+    int xcd_remap;
+    int graph_steps;    /* steps per captured hipGraph, 0 = eager launches */
+    long long max_lds;  /* LDS bytes per workgroup available to the membrane kernel */
+    int lds_objects;    /* objects whose mesh is staged in LDS (the rest use global scratch) */
+} oif_info_t;
+
+/* FP64 conservation diagnostics and watchdog state. */
+typedef struct {
+    double mass;              /* sum of rho over the lattice */
+    double momentum_fluid[3]; /* sum over nodes of sum_i n_i e_i */
+    double momentum_mesh[3];  /* sum over mesh nodes of m v */
+    int nonfinite;            /* non-zero if any population or mesh value is NaN/Inf */
+    int clamped;              /* non-zero if a stencil reached past a z-wall and was clamped */
+    int overflow;             /* non-zero if a coupling force was out of fixed-point range */
+} oif_diag;
+
+/* Timing of one oif_step_timed call (HIP events on the context's stream). */
+typedef struct {
+    double total_ms;     /* first launch to last launch of the call */
+    double lb_ms;        /* average duration of one lattice kernel launch */
+    double mesh_ms;      /* average duration of one membrane/coupling kernel launch */
+    int lb_launches;
+    int mesh_launches;
+} oif_timing;
+
+/* ---- lattice -------------------------------------------------------------- */
+
+/* Fill d with defaults (see oif_lattice_desc).  Errors: OIF_E_ARG if d is NULL. */
+int oif_lattice_desc_init(oif_lattice_desc* d);
+
+/* Create a context: allocates the lattice on the device and sets the fluid
+ * to rest at rho0 (oif_init + lbfluid of the paper).  *out receives the
+ * context.  Errors: OIF_E_ARG (invalid desc), OIF_E_UNSUPPORTED (no gfx950
+ * device), OIF_E_NOMEM, OIF_E_HIP. */
+int oif_create(const oif_lattice_desc* desc, oif_ctx** out);
+
+/* Release all device and host memory of the context.  NULL is accepted. */
+int oif_destroy(oif_ctx* ctx);
+
+/* Message of the context's last error ("" if none); owned by the context. */
+const char* oif_last_error(const oif_ctx* ctx);
+
+/* Run the context's work on the given hipStream_t (e.g. a PyTorch stream)
+ * instead of its own stream; NULL restores the own stream.  The caller keeps
+ * the stream alive while it is bound. */
+int oif_bind_stream(oif_ctx* ctx, void* hip_stream);
+
+/* ---- templates and objects ------------------------------------------------ */
+
+/* Register template tid (template creation of the paper).  nodes: nv x 3
+ * coordinates, approximately centred at the origin; tris: nt x 3 node ids
+ * whose normal AB x AC points INTO the object.  stretch (NULL = 1,1,1) scales
+ * the coordinates per axis before the relaxed lengths, angles, triangle
+ * areas, total area and volume are computed (in FP64, on the host).
+ * Ids start at 0 and are consecutive; a template cannot change once objects
+ * exist.  Errors: OIF_E_ARG, OIF_E_ID, OIF_E_MESH (not closed, not manifold,
+ * inconsistent orientation, or enclosed volume <= 0, i.e. outward normals),
+ * OIF_E_STATE. */
+int oif_template_create(oif_ctx* ctx, int tid, const double* nodes, int nv, const int32_t* tris,
+                        int nt, const double stretch[3], const oif_moduli* k);
+
+/* Add object oid made from template tid (adding objects of the paper):
+ * node positions = origin + R x_template, R = rot (row-major 3x3, NULL =
+ * identity).  mass <= 0 means the default 1.  part_type is stored and
+ * reported only.  Objects start at rest.  Errors: OIF_E_ARG, OIF_E_ID. */
+int oif_object_add(oif_ctx* ctx, int oid, int tid, const double origin[3], const double rot[9],
+                   double mass, int part_type);
+
+/* R = Rz(rz) Ry(ry) Rx(rx): rotation by rx about x, then ry about y, then rz
+ * about z (fixed axes), row-major. */
+int oif_euler_to_rot(double rx, double ry, double rz, double R[9]);
+
+/* The same external force on every node of object oid (object
+ * customisation: force). */
+int oif_object_set_force(oif_ctx* ctx, int oid, const double f[3]);
+
+/* Translate object oid so that the mean of its nodes is at o (object
+ * customisation: origin). */
+int oif_object_set_origin(oif_ctx* ctx, int oid, const double o[3]);
+
+/* Replace the node positions of object oid (object customisation:
+ * mesh-nodes); x holds nv x 3 absolute coordinates. */
+int oif_object_set_nodes(oif_ctx* ctx, int oid, const double* x);
+
+/* ---- stepping ------------------------------------------------------------- */
+
+/* Advance n_steps coupled steps (membrane forces, coupling, mesh update, LB
+ * update), then run the FP64 watchdog.  Returns OIF_E_NONFINITE or
+ * OIF_E_OVERFLOW if the watchdog trips (the state is kept for inspection).
+ * Steps are replayed from captured hipGraphs when graph mode is on. */
+int oif_step(oif_ctx* ctx, int n_steps);
+
+/* Same as oif_step with eager launches bracketed by HIP events; fills t. */
+int oif_step_timed(oif_ctx* ctx, int n_steps, oif_timing* t);
+
+/* Graph mode: steps_per_graph > 0 captures that many steps (rounded up to an
+ * even number) in one hipGraph and replays it; 0 launches eagerly. */
+int oif_set_graph(oif_ctx* ctx, int steps_per_graph);
+
+/* Launch shapes: lb_block in {64,128,256,512,1024}, mesh_block in
+ * {64,128,256,512,1024}; xcd_remap 0/1 maps consecutive lattice blocks to the
+ * same XCD.  Values < 0 keep the current setting. */
+int oif_set_launch(oif_ctx* ctx, int lb_block, int mesh_block, int xcd_remap);
+
+/* Measured search of the launch shapes on this context's workload; the
+ * choice is applied and, if cache_path is not NULL, stored there as JSON
+ * keyed by device, precision and box shape (and read from it when present). */
+int oif_autotune(oif_ctx* ctx, const char* cache_path);
+
+/* ---- read-back / write ---------------------------------------------------- */
+
+/* Full populations n_i in FP64, 19 * nx*ny*nz values, layout [19][nz][ny][nx]. */
+int oif_read_populations(oif_ctx* ctx, double* out);
+
+/* Overwrite the populations (same layout); the values are rounded to the
+ * storage form of the context. */
+int oif_write_populations(oif_ctx* ctx, const double* in);
+
+/* Density rho [nz][ny][nx]. */
+int oif_read_density(oif_ctx* ctx, double* out);
+
+/* Velocity u = (sum_i n_i e_i + g/2) / rho, layout [3][nz][ny][nx]. */
+int oif_read_velocity(oif_ctx* ctx, double* out);
+
+/* Mesh positions (absolute, unwrapped) and velocities of object oid, or of
+ * all objects concatenated in id order when oid = -1; X and V (either may be
+ * NULL) hold n x 3 values. */
+int oif_read_mesh(oif_ctx* ctx, int oid, double* X, double* V);
+
+/* Overwrite positions and/or velocities (NULL keeps) of object oid or of all
+ * objects (oid = -1); checkpoint restore. */
+int oif_write_mesh(oif_ctx* ctx, int oid, const double* X, const double* V);
+
+/* Object analysis (origin, bounds, volume, area, velocity). */
+int oif_object_analyze(oif_ctx* ctx, int oid, oif_analysis* a);
+
+int oif_info(oif_ctx* ctx, oif_info_t* info);
+
+/* FP64 sums of mass and momentum and the watchdog flags of the current state. */
+int oif_diagnostics(oif_ctx* ctx, oif_diag* d);
+
+/* Number of distinct lattice nodes inside the 2x2x2 stencil of any mesh node
+ * at the current positions (used for the byte model of the coupling). */
+int oif_touched_nodes(oif_ctx* ctx, long long* count);
+
+/* ---- batching form: many independent boxes advanced together --------------- */
+
+/* Bind n existing contexts (same precision and device) into a batch: every
+ * step launches one membrane/coupling kernel over all objects of all boxes
+ * (largest meshes first) and one lattice kernel over all boxes' nodes.  The
+ * contexts stay owned by the caller and must outlive the batch; stepping a
+ * member context alone while the batch exists is allowed. */
+int oif_batch_create(oif_ctx* const* boxes, int n, oif_batch** out);
+int oif_batch_destroy(oif_batch* b);
+
+/* Advance all boxes n_steps steps (graph-captured if oif_batch_set_graph was
+ * given a positive count), then run each box's watchdog. */
+int oif_batch_step(oif_batch* b, int n_steps);
+int oif_batch_set_graph(oif_batch* b, int steps_per_graph);
+int oif_batch_set_launch(oif_batch* b, int lb_block, int mesh_block, int xcd_remap);
+int oif_batch_autotune(oif_batch* b, const char* cache_path);
+int oif_batch_step_timed(oif_batch* b, int n_steps, oif_timing* t);
+const char* oif_batch_last_error(const oif_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OIF_H */

@@ -1,0 +1,94 @@
+// device_common.h -- D3Q19 tables, storage forms of the populations and a
+// deterministic block reduction, shared by the lattice and membrane kernels.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "oif_device.h"
+
+namespace oif {
+namespace dev {
+
+// D3Q19 velocity set (ordering documented in include/oif.h) and weights,
+// written as constexpr functions so fully unrolled loops fold them away.
+__host__ __device__ constexpr int cx(int i) {
+    return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
+           : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
+}
+__host__ __device__ constexpr int cy(int i) {
+    return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
+           : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int cz(int i) {
+    return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
+           : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+template <typename R>
+__host__ __device__ constexpr R wt(int i) {
+    return i == 0 ? R(1) / R(3) : (i <= 6 ? R(1) / R(18) : R(1) / R(36));
+}
+
+// storage forms: S = stored type, R = arithmetic type
+template <int P> struct Prec;
+template <> struct Prec<PREC_FP64> { typedef double S; typedef double R; };
+template <> struct Prec<PREC_FP32> { typedef float S; typedef float R; };
+template <> struct Prec<PREC_FP16> { typedef uint16_t S; typedef float R; };
+template <> struct Prec<PREC_BF16> { typedef uint16_t S; typedef float R; };
+
+template <int P>
+__device__ __forceinline__ typename Prec<P>::R dec(typename Prec<P>::S s, float inv);
+template <>
+__device__ __forceinline__ double dec<PREC_FP64>(double s, float) { return s; }
+template <>
+__device__ __forceinline__ float dec<PREC_FP32>(float s, float) { return s; }
+template <>
+__device__ __forceinline__ float dec<PREC_FP16>(uint16_t s, float inv) {
+    return __half2float(__ushort_as_half(s)) * inv;
+}
+template <>
+__device__ __forceinline__ float dec<PREC_BF16>(uint16_t s, float) {
+    return __uint_as_float(((unsigned)s) << 16);
+}
+
+template <int P>
+__device__ __forceinline__ typename Prec<P>::S enc(typename Prec<P>::R r, float scale);
+template <>
+__device__ __forceinline__ double enc<PREC_FP64>(double r, float) { return r; }
+template <>
+__device__ __forceinline__ float enc<PREC_FP32>(float r, float) { return r; }
+template <>
+__device__ __forceinline__ uint16_t enc<PREC_FP16>(float r, float scale) {
+    return __half_as_ushort(__float2half_rn(r * scale));
+}
+template <>
+__device__ __forceinline__ uint16_t enc<PREC_BF16>(float r, float) {
+    // round to nearest even on the upper 16 bits; NaN stays NaN
+    unsigned u = __float_as_uint(r);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Block-wide FP64 sum with a fixed combination order: a butterfly inside each
+// 64-lane wave (every lane ends with the same value), then the per-wave sums
+// added in wave order.  Deterministic for a given block size.  `red` must hold
+// one double per wave; all threads of the block must call it.
+__device__ inline double block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double tot = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int k = 0; k < nw; ++k) tot += red[k];
+    __syncthreads();
+    return tot;
+}
+
+}  // namespace dev
+}  // namespace oif

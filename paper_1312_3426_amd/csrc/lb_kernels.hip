@@ -1,0 +1,285 @@
+// lb_kernels.hip -- lattice kernels of the coupled step (paper, Section
+// "Method": the D3Q19 propagation/collision update with an external force
+// term, eq. lbequation, and the moment definitions of density and velocity).
+//
+//   lb_kernel   one lattice node per thread: decode the 19 stored deviations,
+//               BGK collision with Guo forcing (force density g + G, G read
+//               only where the node's mask bit is set, then cleared), push the
+//               19 post-collision values to the neighbours (halfway
+//               bounce-back at z walls), encode.  HBM bound: every node reads
+//               and writes 19 stored values once, 2 x 19 x sizeof(storage)
+//               bytes per node; the force read adds 24 bytes only at nodes
+//               touched by the spreading.
+//   diag_*      FP64 sums of mass and momentum and a non-finite watchdog,
+//               two passes with a fixed summation order (deterministic).
+//   *_to_*      conversions between the storage form and canonical FP64 fields.
+#include "device_common.h"
+
+namespace oif {
+namespace {
+
+using namespace dev;
+
+template <int P>
+__global__ void __launch_bounds__(1024)
+lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int nblocks, int parity,
+          int remap) {
+    typedef typename Prec<P>::S S;
+    typedef typename Prec<P>::R R;
+    int bid = blockIdx.x;
+    if (remap) {
+        // workgroups are dispatched round-robin over the 8 XCDs; give each XCD
+        // a contiguous range of lattice blocks so neighbouring planes share an L2
+        const int full = nblocks & ~7;
+        if (bid < full) bid = (bid & 7) * (full >> 3) + (bid >> 3);
+    }
+    int box = 0, blk = bid;
+    if (work) {
+        const int2 w = work[bid];
+        box = w.x;
+        blk = w.y;
+    }
+    const BoxDev* __restrict__ B = boxes + box;
+    const int N = B->N;
+    const int p = blk * (int)blockDim.x + (int)threadIdx.x;
+    if (p >= N) return;
+    const S* __restrict__ src = (const S*)B->f[parity];
+    S* __restrict__ dst = (S*)B->f[parity ^ 1];
+    const float inv = B->st_inv, scale = B->st_scale;
+
+    // force density: body force plus the coupling force where the mask says so
+    R fx = (R)B->g[0], fy = (R)B->g[1], fz = (R)B->g[2];
+    unsigned long long* mk = B->mask + (p >> 6);
+    const unsigned long long m = *mk;
+    if (m) {
+        if ((m >> (p & 63)) & 1ull) {
+            if (P == PREC_FP64) {
+                double* G = (double*)B->G;
+                fx += (R)G[p];
+                fy += (R)G[N + p];
+                fz += (R)G[2 * N + p];
+                G[p] = 0.0;
+                G[N + p] = 0.0;
+                G[2 * N + p] = 0.0;
+            } else {
+                long long* G = (long long*)B->G;
+                const double s = B->fp_inv;
+                fx += (R)((double)G[p] * s);
+                fy += (R)((double)G[N + p] * s);
+                fz += (R)((double)G[2 * N + p] * s);
+                G[p] = 0;
+                G[N + p] = 0;
+                G[2 * N + p] = 0;
+            }
+        }
+        // the word covers exactly this wave's 64 nodes, and every lane has
+        // already loaded it: its first lane clears it
+        if ((p & 63) == 0) *mk = 0ull;
+    }
+
+    R d[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) d[i] = dec<P>(src[(size_t)i * N + p], inv);
+
+    R drho = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) drho += d[i];
+    const R jx = d[1] - d[2] + d[7] - d[8] + d[9] - d[10] + d[11] - d[12] + d[13] - d[14];
+    const R jy = d[3] - d[4] + d[7] - d[8] - d[9] + d[10] + d[15] - d[16] + d[17] - d[18];
+    const R jz = d[5] - d[6] + d[11] - d[12] - d[13] + d[14] + d[15] - d[16] - d[17] + d[18];
+    const R rho = (R)B->rho0 + drho;
+    const R ir = R(1) / rho;
+    const R ux = (jx + R(0.5) * fx) * ir;
+    const R uy = (jy + R(0.5) * fy) * ir;
+    const R uz = (jz + R(0.5) * fz) * ir;
+    const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+    const R uF = ux * fx + uy * fy + uz * fz;
+    const R om = (R)B->omega, gu = (R)B->guo;
+
+    // neighbour offsets with periodic wrap
+    const int nx = B->nx, ny = B->ny, nz = B->nz;
+    const int x = p % nx;
+    const int t = p / nx;
+    const int y = t % ny;
+    const int z = t / ny;
+    const int plane = nx * ny;
+    const int oxm = x ? -1 : nx - 1, oxp = (x < nx - 1) ? 1 : -(nx - 1);
+    const int oym = y ? -nx : (ny - 1) * nx, oyp = (y < ny - 1) ? nx : -(ny - 1) * nx;
+    const int ozm = z ? -plane : (nz - 1) * plane, ozp = (z < nz - 1) ? plane : -(nz - 1) * plane;
+    const bool wlo = B->walls_z && z == 0;
+    const bool whi = B->walls_z && z == nz - 1;
+
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        // deviations: n_i^eq - w_i rho0 = w_i [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u^2)]
+        const R eu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
+        const R eF = R(cx(i)) * fx + R(cy(i)) * fy + R(cz(i)) * fz;
+        const R w = wt<R>(i);
+        const R deq = w * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - usq));
+        // Guo source (1 - 1/(2 tau)) w_i [3 (e_i - u) + 9 (e_i . u) e_i] . F
+        const R srcf = gu * w * (R(3) * (eF - uF) + R(9) * eu * eF);
+        const R ds = d[i] - om * (d[i] - deq) + srcf;
+        const S out = enc<P>(ds, scale);
+        const bool bounce = (cz(i) > 0 && whi) || (cz(i) < 0 && wlo);
+        if (bounce) {
+            dst[(size_t)opp(i) * N + p] = out;
+        } else {
+            const int off = (cx(i) > 0 ? oxp : (cx(i) < 0 ? oxm : 0)) +
+                            (cy(i) > 0 ? oyp : (cy(i) < 0 ? oym : 0)) +
+                            (cz(i) > 0 ? ozp : (cz(i) < 0 ? ozm : 0));
+            dst[(size_t)i * N + p + off] = out;
+        }
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256)
+diag_lattice_kernel(const BoxDev* __restrict__ B, int parity, double* __restrict__ part) {
+    typedef typename Prec<P>::S S;
+    __shared__ double red[16];
+    const S* __restrict__ src = (const S*)B->f[parity];
+    const int N = B->N;
+    const float inv = B->st_inv;
+    double dm = 0, jx = 0, jy = 0, jz = 0, bad = 0;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
+        double d[19];
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            d[i] = (double)dec<P>(src[(size_t)i * N + p], inv);
+            if (!isfinite(d[i])) bad = 1.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            dm += d[i];
+            jx += cx(i) * d[i];
+            jy += cy(i) * d[i];
+            jz += cz(i) * d[i];
+        }
+    }
+    const double s0 = block_sum(dm, red), s1 = block_sum(jx, red), s2 = block_sum(jy, red),
+                 s3 = block_sum(jz, red), s4 = block_sum(bad, red);
+    if (threadIdx.x == 0) {
+        double* o = part + 5 * blockIdx.x;
+        o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3; o[4] = s4;
+    }
+}
+
+__global__ void diag_final_kernel(const double* __restrict__ part, int nlat, int nmesh,
+                                  double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a[5] = {0, 0, 0, 0, 0}, b[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < nlat; ++k)
+        for (int c = 0; c < 5; ++c) a[c] += part[5 * k + c];
+    for (int k = 0; k < nmesh; ++k)
+        for (int c = 0; c < 5; ++c) b[c] += part[5 * (nlat + k) + c];
+    for (int c = 0; c < 5; ++c) {
+        out[c] = a[c];
+        out[5 + c] = b[c];
+    }
+}
+
+__device__ inline double weight_of(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+template <int P>
+__global__ void pops_to_f64_kernel(const BoxDev* __restrict__ B, int parity, double* __restrict__ out) {
+    typedef typename Prec<P>::S S;
+    const int N = B->N;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)19 * N) return;
+    const int i = (int)(k / N);
+    const S* src = (const S*)B->f[parity];
+    out[k] = weight_of(i) * B->rho0 + (double)dec<P>(src[k], B->st_inv);
+}
+
+template <int P>
+__global__ void f64_to_pops_kernel(const BoxDev* __restrict__ B, int parity, const double* __restrict__ in) {
+    typedef typename Prec<P>::S S;
+    typedef typename Prec<P>::R R;
+    const int N = B->N;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)19 * N) return;
+    const int i = (int)(k / N);
+    S* dst = (S*)B->f[parity];
+    dst[k] = enc<P>((R)(in[k] - weight_of(i) * B->rho0), B->st_scale);
+}
+
+template <int P>
+__global__ void moments_kernel(const BoxDev* __restrict__ B, int parity, double* __restrict__ rho,
+                               double* __restrict__ u) {
+    typedef typename Prec<P>::S S;
+    const int N = B->N;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const S* src = (const S*)B->f[parity];
+    double d[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) d[i] = (double)dec<P>(src[(size_t)i * N + p], B->st_inv);
+    double dr = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        dr += d[i];
+        jx += cx(i) * d[i];
+        jy += cy(i) * d[i];
+        jz += cz(i) * d[i];
+    }
+    const double r = B->rho0 + dr;
+    if (rho) rho[p] = r;
+    if (u) {
+        u[p] = (jx + 0.5 * B->g[0]) / r;
+        u[N + p] = (jy + 0.5 * B->g[1]) / r;
+        u[2 * N + p] = (jz + 0.5 * B->g[2]) / r;
+    }
+}
+
+}  // namespace
+
+#define OIF_DISPATCH_P(prec, KER, grid, blk, s, ...)                                                 \
+    switch (prec) {                                                                              \
+        case PREC_FP64: hipLaunchKernelGGL(KER<PREC_FP64>, grid, blk, 0, s, __VA_ARGS__); break; \
+        case PREC_FP32: hipLaunchKernelGGL(KER<PREC_FP32>, grid, blk, 0, s, __VA_ARGS__); break; \
+        case PREC_FP16: hipLaunchKernelGGL(KER<PREC_FP16>, grid, blk, 0, s, __VA_ARGS__); break; \
+        case PREC_BF16: hipLaunchKernelGGL(KER<PREC_BF16>, grid, blk, 0, s, __VA_ARGS__); break; \
+        default: return hipErrorInvalidValue;                                                    \
+    }
+
+hipError_t launch_lb(const LbLaunch& L) {
+    OIF_DISPATCH_P(L.precision, lb_kernel, dim3(L.nblocks), dim3(L.block), L.stream, L.boxes, L.work,
+                   L.nblocks, L.parity, L.remap);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_lattice(const BoxDev* box_dev, int precision, int parity, double* partials,
+                               int nblocks, hipStream_t s) {
+    OIF_DISPATCH_P(precision, diag_lattice_kernel, dim3(nblocks), dim3(256), s, box_dev, parity, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_final(const double* partials, int nlat, int nmesh, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partials, nlat, nmesh, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pops_to_f64(const BoxDev* box_dev, int N, int precision, int parity, double* out,
+                              hipStream_t s) {
+    const size_t n = (size_t)19 * N;
+    OIF_DISPATCH_P(precision, pops_to_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), s, box_dev,
+                   parity, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_f64_to_pops(const BoxDev* box_dev, int N, int precision, int parity,
+                              const double* in, hipStream_t s) {
+    const size_t n = (size_t)19 * N;
+    OIF_DISPATCH_P(precision, f64_to_pops_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), s, box_dev,
+                   parity, in);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const BoxDev* box_dev, int N, int precision, int parity, double* rho,
+                          double* u, hipStream_t s) {
+    OIF_DISPATCH_P(precision, moments_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), s, box_dev,
+                   parity, rho, u);
+    return hipGetLastError();
+}
+
+}  // namespace oif

@@ -1,0 +1,357 @@
+// mesh_kernels.hip -- membrane forces, fluid coupling and mesh integration
+// (paper: Section "Elastic interactions" for the stretching, bending, local
+// area, global area and volume forces; Section "Method" for the IB point
+// dynamics, eq. newton, and the drag coupling, eq. dragforce, with linear
+// interpolation of the fluid velocity and distribution of the reaction).
+//
+// One workgroup per object.  Its node positions are staged in LDS (FP64), then
+//   1. per triangle: unit inward normal, area, (S - S0)/S; FP64 block sums of
+//      the object's area and volume (divergence theorem, signed tetrahedra);
+//   2. per edge: the stretching coefficient from the strain (L - L0)/L0 and
+//      the bending magnitude from theta - theta0, both formed in FP64 so the
+//      cancellation near the relaxed shape keeps its digits;
+//   3. per node: gather of its edge, hinge and triangle contributions in a
+//      fixed order (deterministic, no atomics), trilinear interpolation of the
+//      fluid velocity from the 8 surrounding nodes, drag, symplectic Euler
+//      update, and spreading of the reaction to the 8 nodes (int64 fixed-point
+//      atomics in the FP32 forms, FP64 atomics in the FP64 form) with the
+//      nodes' mask bits set.
+// Meshes whose arrays do not fit in LDS use a per-object global scratch area
+// with the same layout.
+#include "device_common.h"
+
+namespace oif {
+namespace {
+
+using namespace dev;
+
+template <int P, bool USE_LDS>
+__global__ void __launch_bounds__(1024)
+mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
+    typedef typename Prec<P>::S S;
+    typedef typename Prec<P>::R R;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[16];
+
+    const ObjDev<R>& O = objs[blockIdx.x];
+    const TmplDev<R>* __restrict__ T = O.t;
+    const BoxDev* __restrict__ B = O.box;
+    const int nv = T->nv, nt = T->nt, ne = T->ne;
+    const MeshLayout lay = mesh_layout(sizeof(R), nv, nt, ne);
+    unsigned char* base = USE_LDS ? smem : O.scratch;
+    double* xs = (double*)base;       // [nv][3]
+    R* tn = (R*)(base + lay.tn);      // [nt][4]: unit inward normal, area
+    R* tr = (R*)(base + lay.tr);      // [nt]: (S - S0)/S
+    R* se = (R*)(base + lay.se);      // [ne]: ks kappa strain / L
+    R* fh = (R*)(base + lay.fh);      // [ne]: kb (theta - theta0)/theta0
+
+    for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x) xs[k] = O.X[k];
+    __syncthreads();
+
+    // 1. triangles
+    double sarea = 0.0, svol = 0.0;
+    {
+        const double r0x = xs[0], r0y = xs[1], r0z = xs[2];
+        for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+            const int a = T->tri[3 * t], b = T->tri[3 * t + 1], c = T->tri[3 * t + 2];
+            const double ax = xs[3 * a] - r0x, ay = xs[3 * a + 1] - r0y, az = xs[3 * a + 2] - r0z;
+            const double bx = xs[3 * b] - r0x, by = xs[3 * b + 1] - r0y, bz = xs[3 * b + 2] - r0z;
+            const double qx = xs[3 * c] - r0x, qy = xs[3 * c + 1] - r0y, qz = xs[3 * c + 2] - r0z;
+            const double abx = bx - ax, aby = by - ay, abz = bz - az;
+            const double acx = qx - ax, acy = qy - ay, acz = qz - az;
+            const double nx_ = aby * acz - abz * acy;
+            const double ny_ = abz * acx - abx * acz;
+            const double nz_ = abx * acy - aby * acx;
+            const double len = sqrt(nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
+            const double S = 0.5 * len;
+            tn[4 * t + 0] = (R)(nx_ / len);
+            tn[4 * t + 1] = (R)(ny_ / len);
+            tn[4 * t + 2] = (R)(nz_ / len);
+            tn[4 * t + 3] = (R)S;
+            tr[t] = (R)((S - T->S0[t]) / S);
+            sarea += S;
+            // signed tetrahedron (node 0, a, b, c): inward orientation gives -6 V
+            const double cxx = by * qz - bz * qy, cyy = bz * qx - bx * qz, czz = bx * qy - by * qx;
+            svol -= (ax * cxx + ay * cyy + az * czz) / 6.0;
+        }
+    }
+    const double Sg = block_sum(sarea, red);
+    const double Vol = block_sum(svol, red);
+    if (threadIdx.x == 0 && O.geo) {
+        O.geo[0] = Sg;
+        O.geo[1] = Vol;
+    }
+
+    // 2. edges: stretching coefficient and bending magnitude of each hinge
+    const bool do_s = T->ks != 0.0, do_b = T->kb != 0.0;
+    if (do_s || do_b) {
+        for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+            const int4 h = T->hinge[e];  // (A, B, C, D): the edge is B -> C
+            const double dx = xs[3 * h.z] - xs[3 * h.y], dy = xs[3 * h.z + 1] - xs[3 * h.y + 1],
+                         dz = xs[3 * h.z + 2] - xs[3 * h.y + 2];
+            const double L = sqrt(dx * dx + dy * dy + dz * dz);
+            if (do_s) {
+                const double L0 = T->L0[e];
+                const double strain = (L - L0) / L0;
+                double kap = 1.0;
+                if (!T->linear) {
+                    const double lam = L / L0, sl = sqrt(lam), l2 = lam * lam;
+                    kap = (sl + 1.0 / (l2 * sl)) / (lam + 1.0 / (l2 * lam));
+                }
+                se[e] = (R)(T->ks * kap * strain / L);
+            }
+            if (do_b) {
+                // inward unit normals of T1 = (A, B, C) and T2 = (D, C, B)
+                const double* pa = &xs[3 * h.x];
+                const double* pb = &xs[3 * h.y];
+                const double* pc = &xs[3 * h.z];
+                const double* pd = &xs[3 * h.w];
+                const double u1x = pb[0] - pa[0], u1y = pb[1] - pa[1], u1z = pb[2] - pa[2];
+                const double v1x = pc[0] - pa[0], v1y = pc[1] - pa[1], v1z = pc[2] - pa[2];
+                double n1x = u1y * v1z - u1z * v1y, n1y = u1z * v1x - u1x * v1z, n1z = u1x * v1y - u1y * v1x;
+                const double u2x = pc[0] - pd[0], u2y = pc[1] - pd[1], u2z = pc[2] - pd[2];
+                const double v2x = pb[0] - pd[0], v2y = pb[1] - pd[1], v2z = pb[2] - pd[2];
+                double n2x = u2y * v2z - u2z * v2y, n2y = u2z * v2x - u2x * v2z, n2z = u2x * v2y - u2y * v2x;
+                const double i1 = 1.0 / sqrt(n1x * n1x + n1y * n1y + n1z * n1z);
+                const double i2 = 1.0 / sqrt(n2x * n2x + n2y * n2y + n2z * n2z);
+                n1x *= i1; n1y *= i1; n1z *= i1;
+                n2x *= i2; n2y *= i2; n2z *= i2;
+                const double mx = n1y * n2z - n1z * n2y, my = n1z * n2x - n1x * n2z, mz = n1x * n2y - n1y * n2x;
+                // inner dihedral angle: pi when flat, below pi on a convex ridge
+                const double theta = 3.14159265358979323846 +
+                                     atan2((mx * dx + my * dy + mz * dz) / L, n1x * n2x + n1y * n2y + n1z * n2z);
+                const double th0 = T->theta0[e];
+                fh[e] = (R)(T->kb * (theta - th0) / th0);
+            }
+        }
+    }
+    __syncthreads();
+
+    const R cg = (R)(-T->kag * (Sg - T->Sg0) / Sg);   // global area coefficient
+    const R cv = (R)(-T->kv * (Vol - T->V0) / T->V0); // volume coefficient
+    const R kal = (R)T->kal;
+    const R third = R(1) / R(3);
+    const int nxb = B->nx, nyb = B->ny, nzb = B->nz, Nb = B->N;
+    const S* __restrict__ pop = (const S*)B->f[parity];
+    const float inv = B->st_inv;
+    const R gx = (R)B->g[0], gy = (R)B->g[1], gz = (R)B->g[2];
+    const R rho0 = (R)B->rho0, xi = (R)B->xi;
+    unsigned flags = 0;
+
+    // 3. nodes
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        const double px = xs[3 * v], py = xs[3 * v + 1], pz = xs[3 * v + 2];
+        R Fx = 0, Fy = 0, Fz = 0;
+        if (do_s) {
+            // F_v += ks kappa (L - L0)/L0 (x_u - x_v)/L  ("Stretching force")
+            for (int k = T->e_off[v]; k < T->e_off[v + 1]; ++k) {
+                const int2 ie = T->e_inc[k];
+                const R s = se[ie.y];
+                Fx += s * (R)(xs[3 * ie.x] - px);
+                Fy += s * (R)(xs[3 * ie.x + 1] - py);
+                Fz += s * (R)(xs[3 * ie.x + 2] - pz);
+            }
+        }
+        if (do_b) {
+            // wings along their triangle's normal, edge ends minus half the sum ("Bending force")
+            for (int k = T->h_off[v]; k < T->h_off[v + 1]; ++k) {
+                const int code = T->h_inc[k];
+                const int e = code >> 2, role = code & 3;
+                const int2 ht = T->hinge_tri[e];
+                const R f = fh[e];
+                const R n1x = tn[4 * ht.x], n1y = tn[4 * ht.x + 1], n1z = tn[4 * ht.x + 2];
+                const R n2x = tn[4 * ht.y], n2y = tn[4 * ht.y + 1], n2z = tn[4 * ht.y + 2];
+                if (role == 0) {
+                    Fx += f * n1x; Fy += f * n1y; Fz += f * n1z;
+                } else if (role == 3) {
+                    Fx += f * n2x; Fy += f * n2y; Fz += f * n2z;
+                } else {
+                    const R hf = R(0.5) * f;
+                    Fx -= hf * (n1x + n2x); Fy -= hf * (n1y + n2y); Fz -= hf * (n1z + n2z);
+                }
+            }
+        }
+        // local area (-kal dS/S w), global area (-kag dSg/Sg w), volume
+        // (-kv dV/V0 S n_out / 3); w = unit centroid -> vertex
+        for (int k = T->t_off[v]; k < T->t_off[v + 1]; ++k) {
+            const int t = T->t_inc[k] >> 2;
+            const int a = T->tri[3 * t], b = T->tri[3 * t + 1], c = T->tri[3 * t + 2];
+            const R wx = (R)(px - (xs[3 * a] + xs[3 * b] + xs[3 * c]) * (1.0 / 3.0));
+            const R wy = (R)(py - (xs[3 * a + 1] + xs[3 * b + 1] + xs[3 * c + 1]) * (1.0 / 3.0));
+            const R wz = (R)(pz - (xs[3 * a + 2] + xs[3 * b + 2] + xs[3 * c + 2]) * (1.0 / 3.0));
+            const R ct = (-kal * tr[t] + cg) / sqrt(wx * wx + wy * wy + wz * wz);
+            const R vf = cv * tn[4 * t + 3] * third;
+            Fx += ct * wx - vf * tn[4 * t];
+            Fy += ct * wy - vf * tn[4 * t + 1];
+            Fz += ct * wz - vf * tn[4 * t + 2];
+        }
+
+        // coupling: trilinear interpolation of the fluid velocity at the node
+        R vx = O.V[3 * v], vy = O.V[3 * v + 1], vz = O.V[3 * v + 2];
+        R dgx = 0, dgy = 0, dgz = 0;
+        const double sx = px - 0.5, sy = py - 0.5, sz = pz - 0.5;
+        const bool ok = fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7;
+        if (!ok) {
+            flags |= ST_NONFINITE;  // no stencil for a non-finite or runaway node
+        } else {
+            const double flx = floor(sx), fly = floor(sy), flz = floor(sz);
+            const R phx = (R)(sx - flx), phy = (R)(sy - fly), phz = (R)(sz - flz);
+            int ix = (O.anchor[0] + (int)flx) % nxb;
+            ix += ix < 0 ? nxb : 0;
+            int iy = (O.anchor[1] + (int)fly) % nyb;
+            iy += iy < 0 ? nyb : 0;
+            const int ix1 = ix + 1 == nxb ? 0 : ix + 1;
+            const int iy1 = iy + 1 == nyb ? 0 : iy + 1;
+            int iz0, iz1;
+            const int izr = O.anchor[2] + (int)flz;
+            if (B->walls_z) {
+                iz0 = izr < 0 ? 0 : (izr >= nzb ? nzb - 1 : izr);
+                iz1 = izr + 1 < 0 ? 0 : (izr + 1 >= nzb ? nzb - 1 : izr + 1);
+                if (izr < 0 || izr + 1 >= nzb) flags |= ST_CLAMPED;
+            } else {
+                iz0 = izr % nzb;
+                iz0 += iz0 < 0 ? nzb : 0;
+                iz1 = iz0 + 1 == nzb ? 0 : iz0 + 1;
+            }
+            int q[8];
+            R w[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+                q[k] = ((dz ? iz1 : iz0) * nyb + (dy ? iy1 : iy)) * nxb + (dx ? ix1 : ix);
+                w[k] = (dx ? phx : R(1) - phx) * (dy ? phy : R(1) - phy) * (dz ? phz : R(1) - phz);
+            }
+            R ujx = 0, ujy = 0, ujz = 0;
+#pragma unroll 1
+            for (int k = 0; k < 8; ++k) {
+                R dd[19];
+#pragma unroll
+                for (int i = 0; i < 19; ++i) dd[i] = dec<P>(pop[(size_t)i * Nb + q[k]], inv);
+                R dr = 0;
+#pragma unroll
+                for (int i = 0; i < 19; ++i) dr += dd[i];
+                const R jx = dd[1] - dd[2] + dd[7] - dd[8] + dd[9] - dd[10] + dd[11] - dd[12] + dd[13] - dd[14];
+                const R jy = dd[3] - dd[4] + dd[7] - dd[8] - dd[9] + dd[10] + dd[15] - dd[16] + dd[17] - dd[18];
+                const R jz = dd[5] - dd[6] + dd[11] - dd[12] - dd[13] + dd[14] + dd[15] - dd[16] - dd[17] + dd[18];
+                const R ir = R(1) / (rho0 + dr);
+                ujx += w[k] * ((jx + R(0.5) * gx) * ir);
+                ujy += w[k] * ((jy + R(0.5) * gy) * ir);
+                ujz += w[k] * ((jz + R(0.5) * gz) * ir);
+            }
+            // eq. dragforce: the fluid receives xi (v - u), the point its opposite
+            dgx = xi * (vx - ujx);
+            dgy = xi * (vy - ujy);
+            dgz = xi * (vz - ujz);
+#pragma unroll 1
+            for (int k = 0; k < 8; ++k) {
+                if (w[k] == R(0)) continue;
+                const R cxv = w[k] * dgx, cyv = w[k] * dgy, czv = w[k] * dgz;
+                if (P == PREC_FP64) {
+                    double* G = (double*)B->G;
+                    atomicAdd(G + q[k], (double)cxv);
+                    atomicAdd(G + Nb + q[k], (double)cyv);
+                    atomicAdd(G + 2 * Nb + q[k], (double)czv);
+                } else {
+                    const double s = B->fp_scale;
+                    const double ax = (double)cxv * s, ay = (double)cyv * s, az = (double)czv * s;
+                    const double lim = 4.0e18;
+                    if (!(fabs(ax) < lim && fabs(ay) < lim && fabs(az) < lim)) {
+                        flags |= ST_OVERFLOW;
+                        continue;
+                    }
+                    unsigned long long* G = (unsigned long long*)B->G;
+                    atomicAdd(G + q[k], (unsigned long long)__double2ll_rn(ax));
+                    atomicAdd(G + Nb + q[k], (unsigned long long)__double2ll_rn(ay));
+                    atomicAdd(G + 2 * Nb + q[k], (unsigned long long)__double2ll_rn(az));
+                }
+                atomicOr(B->mask + (q[k] >> 6), 1ull << (q[k] & 63));
+            }
+        }
+        // eq. newton, symplectic Euler: kick with the total force, then drift
+        vx += (Fx - dgx + O.fext[0]) * O.inv_mass;
+        vy += (Fy - dgy + O.fext[1]) * O.inv_mass;
+        vz += (Fz - dgz + O.fext[2]) * O.inv_mass;
+        O.V[3 * v] = vx;
+        O.V[3 * v + 1] = vy;
+        O.V[3 * v + 2] = vz;
+        O.X[3 * v] = px + (double)vx;
+        O.X[3 * v + 1] = py + (double)vy;
+        O.X[3 * v + 2] = pz + (double)vz;
+    }
+    if (flags) atomicOr(B->status, flags);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+diag_mesh_kernel(const ObjDev<R>* __restrict__ objs, double* __restrict__ part) {
+    __shared__ double red[16];
+    const ObjDev<R>& O = objs[blockIdx.x];
+    const int nv = O.t->nv;
+    double vx = 0, vy = 0, vz = 0, bad = 0;
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        const double a = O.V[3 * v], b = O.V[3 * v + 1], c = O.V[3 * v + 2];
+        vx += a; vy += b; vz += c;
+        if (!isfinite(a + b + c) || !isfinite(O.X[3 * v] + O.X[3 * v + 1] + O.X[3 * v + 2])) bad = 1.0;
+    }
+    const double m = O.mass;
+    const double s0 = block_sum(vx, red), s1 = block_sum(vy, red), s2 = block_sum(vz, red),
+                 s3 = block_sum(bad, red);
+    if (threadIdx.x == 0) {
+        double* o = part + 5 * blockIdx.x;
+        o[0] = 0.0; o[1] = m * s0; o[2] = m * s1; o[3] = m * s2; o[4] = s3;
+    }
+}
+
+template <int P>
+hipError_t launch_mesh_p(const MeshLaunch& L) {
+    typedef typename Prec<P>::R R;
+    const ObjDev<R>* objs = (const ObjDev<R>*)L.objs;
+    if (L.lds_bytes > 0)
+        hipLaunchKernelGGL((mesh_kernel<P, true>), dim3(L.nobj), dim3(L.block), L.lds_bytes, L.stream, objs,
+                           L.parity);
+    else
+        hipLaunchKernelGGL((mesh_kernel<P, false>), dim3(L.nobj), dim3(L.block), 0, L.stream, objs, L.parity);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t mesh_lds_bytes(int precision, int nv, int nt, int ne) {
+    return mesh_layout(precision == PREC_FP64 ? sizeof(double) : sizeof(float), nv, nt, ne).total;
+}
+
+hipError_t launch_mesh(const MeshLaunch& L) {
+    if (L.nobj <= 0) return hipSuccess;
+    switch (L.precision) {
+        case PREC_FP64: return launch_mesh_p<PREC_FP64>(L);
+        case PREC_FP32: return launch_mesh_p<PREC_FP32>(L);
+        case PREC_FP16: return launch_mesh_p<PREC_FP16>(L);
+        case PREC_BF16: return launch_mesh_p<PREC_BF16>(L);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Let the LDS-resident variants use up to `bytes` of dynamic LDS per workgroup.
+hipError_t mesh_set_max_lds(size_t bytes) {
+    hipError_t e = hipSuccess;
+    const void* fns[4] = {(const void*)mesh_kernel<PREC_FP64, true>, (const void*)mesh_kernel<PREC_FP32, true>,
+                          (const void*)mesh_kernel<PREC_FP16, true>, (const void*)mesh_kernel<PREC_BF16, true>};
+    for (const void* f : fns) {
+        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (r != hipSuccess) e = r;
+    }
+    return e;
+}
+
+hipError_t launch_diag_mesh(const void* objs, int nobj, int precision, double* partials, hipStream_t s) {
+    if (nobj <= 0) return hipSuccess;
+    if (precision == PREC_FP64)
+        hipLaunchKernelGGL(diag_mesh_kernel<double>, dim3(nobj), dim3(256), 0, s, (const ObjDev<double>*)objs,
+                           partials);
+    else
+        hipLaunchKernelGGL(diag_mesh_kernel<float>, dim3(nobj), dim3(256), 0, s, (const ObjDev<float>*)objs,
+                           partials);
+    return hipGetLastError();
+}
+
+}  // namespace oif

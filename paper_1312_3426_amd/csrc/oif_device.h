@@ -1,0 +1,142 @@
+// oif_device.h -- device-side data layout of the coupled LB / membrane step
+// and the launchers the host runtime calls.  Internal to liboif.so.
+//
+// HBM layout of one box (context):
+//   f[2]   two population buffers, each [19][N] of the storage type, holding
+//          deviations n_i - w_i rho0 (SoA, x fastest inside a plane); the step
+//          reads f[parity] and writes f[parity ^ 1]
+//   G      coupling force density, [3][N]: double (FP64 form) or int64 fixed
+//          point with resolution 2^-e (FP32 forms, order-independent sums)
+//   mask   one bit per node, set where G is non-zero; the lattice kernel reads
+//          G only where a bit is set and clears both
+//   X, V   mesh node positions (object-local, relative to an integer lattice
+//          anchor of the object; FP64 in every form, so that edge lengths
+//          and areas near their relaxed values do not lose their digits to
+//          position round-off) and velocities ([M][3], compute type)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace oif {
+
+enum : int { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16 = 2, PREC_BF16 = 3 };
+enum : unsigned { ST_NONFINITE = 1u, ST_CLAMPED = 2u, ST_OVERFLOW = 4u };
+
+struct BoxDev {
+    int nx, ny, nz, walls_z;
+    int N;
+    int precision;
+    void* f[2];
+    void* G;
+    unsigned long long* mask;
+    unsigned* status;
+    double g[3];
+    double rho0;
+    double omega;   // 1 / tau
+    double guo;     // 1 - 1/(2 tau)
+    double xi;
+    float st_scale; // storage scale of deviations (2^s for FP16, else 1)
+    float st_inv;
+    double fp_scale; // fixed-point scale 2^e
+    double fp_inv;
+};
+
+template <typename real>
+struct TmplDev {
+    int nv, nt, ne;
+    int linear;
+    const int* tri;        // [nt][3]
+    const int* e_off;      // [nv + 1] incident edges of each node
+    const int2* e_inc;     // (neighbour node, edge id)
+    const double* L0;      // [ne] (FP64: L - L0 cancels near the relaxed shape)
+    const int* h_off;      // [nv + 1] incident hinges of each node
+    const int* h_inc;      // hinge id << 2 | role (0 = A, 1 = B, 2 = C, 3 = D)
+    const int4* hinge;     // (A, B, C, D): T1 = (A, B, C) runs B -> C, T2 has wing D
+    const int2* hinge_tri; // (T1, T2)
+    const double* theta0;  // [ne] (FP64: theta - theta0 cancels near the relaxed shape)
+    const int* t_off;      // [nv + 1] incident triangles of each node
+    const int* t_inc;      // triangle id << 2 | slot
+    const double* S0;      // [nt] (FP64: S - S0 cancels near the relaxed shape)
+    double Sg0, V0;
+    double ks, kb, kal, kag, kv;
+};
+
+// Per-object LDS (or global scratch) layout of the membrane kernel, R = the
+// arithmetic type: positions (FP64), per triangle the unit inward normal and
+// area (R x 4) and (S - S0)/S (R), per edge the stretching coefficient and the
+// bending magnitude (R each).
+struct MeshLayout {
+    size_t tn, tr, se, fh, total;
+};
+__host__ __device__ inline MeshLayout mesh_layout(size_t r, int nv, int nt, int ne) {
+    MeshLayout L;
+    L.tn = ((size_t)nv * 3 * sizeof(double) + 15) & ~(size_t)15;
+    L.tr = L.tn + (size_t)nt * 4 * r;
+    L.se = (L.tr + (size_t)nt * r + 15) & ~(size_t)15;
+    L.fh = L.se + (size_t)ne * r;
+    L.total = L.fh + (size_t)ne * r;
+    return L;
+}
+
+template <typename real>
+struct ObjDev {
+    const TmplDev<real>* t;
+    const BoxDev* box;
+    double* X;        // [nv][3] object-local positions (FP64 in every form)
+    real* V;          // [nv][3]
+    double* geo;      // [2]: total area, volume at the start of the last step
+    int anchor[3];
+    real inv_mass;
+    real fext[3];
+    double mass;
+    unsigned char* scratch; // global stand-in for LDS when the mesh does not fit
+};
+
+// ---- launchers (kernels.hip) ----------------------------------------------
+struct LbLaunch {
+    const BoxDev* boxes;   // device array
+    const int2* work;      // device array (box, block) or nullptr for box 0
+    int nblocks;
+    int block;
+    int parity;
+    int remap;
+    int precision;
+    hipStream_t stream;
+};
+hipError_t launch_lb(const LbLaunch& L);
+
+struct MeshLaunch {
+    const void* objs;      // device array of ObjDev<real>
+    int nobj;
+    int block;
+    int parity;
+    int precision;
+    size_t lds_bytes;      // dynamic LDS per block (0 = each object's global scratch)
+    hipStream_t stream;
+};
+hipError_t launch_mesh(const MeshLaunch& L);
+
+// Per-template LDS bytes of the mesh kernel.
+size_t mesh_lds_bytes(int precision, int nv, int nt, int ne);
+// Allow the LDS-resident mesh kernels to use up to `bytes` of dynamic LDS.
+hipError_t mesh_set_max_lds(size_t bytes);
+
+// FP64 diagnostics.  Lattice partials: per block [sum dev, jx, jy, jz, nonfinite];
+// mesh partials: per object [0, m vx, m vy, m vz, nonfinite], stored after the
+// lattice partials; final: out[0..4] lattice sums, out[5..9] mesh sums.
+hipError_t launch_diag_lattice(const BoxDev* box_dev, int precision, int parity, double* partials,
+                               int nblocks, hipStream_t s);
+hipError_t launch_diag_mesh(const void* objs, int nobj, int precision, double* partials,
+                            hipStream_t s);
+hipError_t launch_diag_final(const double* partials, int nlat, int nmesh, double* out, hipStream_t s);
+
+// conversions between the storage form and canonical FP64 arrays
+hipError_t launch_pops_to_f64(const BoxDev* box_dev, int N, int precision, int parity, double* out,
+                              hipStream_t s);
+hipError_t launch_f64_to_pops(const BoxDev* box_dev, int N, int precision, int parity,
+                              const double* in, hipStream_t s);
+hipError_t launch_moments(const BoxDev* box_dev, int N, int precision, int parity, double* rho,
+                          double* u, hipStream_t s);
+
+}  // namespace oif

@@ -1,0 +1,1512 @@
+// runtime.cpp -- host runtime and C ABI of liboif.so (declared in include/oif.h).
+//
+// Templates are processed on the host in FP64 (topology, relaxed lengths,
+// dihedral angles, triangle areas, total area and volume), objects are placed
+// on the host, and everything the step touches lives on the device.  The
+// device copy of the mesh state is authoritative while stepping; host edits
+// first pull it back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/oif.h"
+#include "oif_device.h"
+
+using namespace oif;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// templates (paper: template creation; relaxed values)
+// ---------------------------------------------------------------------------
+struct Template {
+    int nv = 0, nt = 0, ne = 0;
+    std::vector<double> x;              // stretched coordinates [nv][3]
+    std::vector<int> tri;               // [nt][3]
+    std::vector<std::array<int, 4>> hinge;
+    std::vector<std::array<int, 2>> hinge_tri;
+    std::vector<std::array<int, 2>> edge;
+    std::vector<double> L0, theta0, S0;
+    double Sg0 = 0, V0 = 0;
+    oif_moduli k{};
+    std::vector<int> e_off, h_off, t_off;
+    std::vector<std::array<int, 2>> e_inc;
+    std::vector<int> h_inc, t_inc;
+};
+
+inline void vsub(const double* a, const double* b, double* r) {
+    r[0] = a[0] - b[0]; r[1] = a[1] - b[1]; r[2] = a[2] - b[2];
+}
+inline void vcross(const double* a, const double* b, double* r) {
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+inline double vdot(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// vector area (B - A) x (C - A) / 2 of triangle (a, b, c)
+void vec_area(const double* x, int a, int b, int c, double* n) {
+    double ab[3], ac[3];
+    vsub(&x[3 * b], &x[3 * a], ab);
+    vsub(&x[3 * c], &x[3 * a], ac);
+    vcross(ab, ac, n);
+    n[0] *= 0.5; n[1] *= 0.5; n[2] *= 0.5;
+}
+
+// Inner dihedral angle of hinge (A, B, C, D): T1 = (A, B, C), T2 = (D, C, B);
+// pi + atan2((n1 x n2) . e, n1 . n2) with e = unit(C - B); pi when flat.
+double dihedral(const double* x, int A, int B, int C, int D) {
+    double n1[3], n2[3], e[3], m[3];
+    vec_area(x, A, B, C, n1);
+    vec_area(x, D, C, B, n2);
+    const double l1 = std::sqrt(vdot(n1, n1)), l2 = std::sqrt(vdot(n2, n2));
+    for (int c = 0; c < 3; ++c) { n1[c] /= l1; n2[c] /= l2; }
+    vsub(&x[3 * C], &x[3 * B], e);
+    const double le = std::sqrt(vdot(e, e));
+    for (int c = 0; c < 3; ++c) e[c] /= le;
+    vcross(n1, n2, m);
+    return M_PI + std::atan2(vdot(m, e), vdot(n1, n2));
+}
+
+int build_template(const double* nodes, int nv, const int32_t* tris, int nt, const double* stretch,
+                   const oif_moduli* k, Template& T, std::string& err) {
+    if (nv < 4 || nt < 4 || !nodes || !tris) { err = "template needs >= 4 nodes and >= 4 triangles"; return OIF_E_ARG; }
+    T = Template();
+    T.nv = nv; T.nt = nt;
+    T.x.resize(3 * (size_t)nv);
+    const double s[3] = {stretch ? stretch[0] : 1.0, stretch ? stretch[1] : 1.0, stretch ? stretch[2] : 1.0};
+    for (int v = 0; v < nv; ++v)
+        for (int c = 0; c < 3; ++c) {
+            const double val = nodes[3 * v + c] * s[c];
+            if (!std::isfinite(val)) { err = "non-finite template coordinate"; return OIF_E_ARG; }
+            T.x[3 * v + c] = val;
+        }
+    T.tri.assign(tris, tris + 3 * (size_t)nt);
+    for (int t = 0; t < nt; ++t) {
+        const int a = T.tri[3 * t], b = T.tri[3 * t + 1], c = T.tri[3 * t + 2];
+        if (a < 0 || a >= nv || b < 0 || b >= nv || c < 0 || c >= nv || a == b || b == c || a == c) {
+            err = "triangle " + std::to_string(t) + " has an invalid node id";
+            return OIF_E_MESH;
+        }
+    }
+    // half-edges grouped by undirected key; a closed, consistently oriented
+    // manifold has exactly one half-edge each way per edge
+    struct Half { int from, to, wing, t; };
+    std::map<std::pair<int, int>, std::vector<Half>> groups;
+    for (int t = 0; t < nt; ++t)
+        for (int s3 = 0; s3 < 3; ++s3) {
+            Half h{T.tri[3 * t + s3], T.tri[3 * t + (s3 + 1) % 3], T.tri[3 * t + (s3 + 2) % 3], t};
+            groups[{std::min(h.from, h.to), std::max(h.from, h.to)}].push_back(h);
+        }
+    for (auto& kv : groups) {
+        const auto& g = kv.second;
+        if (g.size() != 2 || g[0].from == g[1].from) {
+            err = "edge (" + std::to_string(kv.first.first) + "," + std::to_string(kv.first.second) +
+                  ") is not shared by two oppositely oriented triangles";
+            return OIF_E_MESH;
+        }
+        const Half& t1 = g[0].from < g[0].to ? g[0] : g[1];
+        const Half& t2 = g[0].from < g[0].to ? g[1] : g[0];
+        T.edge.push_back({kv.first.first, kv.first.second});
+        T.hinge.push_back({t1.wing, t1.from, t1.to, t2.wing});
+        T.hinge_tri.push_back({t1.t, t2.t});
+    }
+    T.ne = (int)T.edge.size();
+    // relaxed values, FP64
+    T.L0.resize(T.ne);
+    T.theta0.resize(T.ne);
+    for (int e = 0; e < T.ne; ++e) {
+        double d[3];
+        vsub(&T.x[3 * T.edge[e][1]], &T.x[3 * T.edge[e][0]], d);
+        T.L0[e] = std::sqrt(vdot(d, d));
+        const auto& h = T.hinge[e];
+        T.theta0[e] = dihedral(T.x.data(), h[0], h[1], h[2], h[3]);
+        if (!(T.L0[e] > 0) || !std::isfinite(T.theta0[e]) || !(T.theta0[e] > 0)) {
+            err = "degenerate edge or hinge in template";
+            return OIF_E_MESH;
+        }
+    }
+    T.S0.resize(nt);
+    double Sg = 0, V = 0;
+    const double* r0 = &T.x[0];
+    for (int t = 0; t < nt; ++t) {
+        const int a = T.tri[3 * t], b = T.tri[3 * t + 1], c = T.tri[3 * t + 2];
+        double n[3];
+        vec_area(T.x.data(), a, b, c, n);
+        T.S0[t] = std::sqrt(vdot(n, n));
+        if (!(T.S0[t] > 0)) { err = "degenerate triangle in template"; return OIF_E_MESH; }
+        Sg += T.S0[t];
+        double pa[3], pb[3], pc[3], bc[3];
+        vsub(&T.x[3 * a], r0, pa);
+        vsub(&T.x[3 * b], r0, pb);
+        vsub(&T.x[3 * c], r0, pc);
+        vcross(pb, pc, bc);
+        V -= vdot(pa, bc) / 6.0;
+    }
+    T.Sg0 = Sg;
+    T.V0 = V;
+    if (!(V > 0)) {
+        err = "enclosed volume is not positive: triangle normals must point into the object";
+        return OIF_E_MESH;
+    }
+    T.k = *k;
+    // per-node incidence lists (CSR)
+    std::vector<std::vector<std::array<int, 2>>> ei(nv);
+    std::vector<std::vector<int>> hi(nv), ti(nv);
+    for (int e = 0; e < T.ne; ++e) {
+        ei[T.edge[e][0]].push_back({T.edge[e][1], e});
+        ei[T.edge[e][1]].push_back({T.edge[e][0], e});
+        for (int r = 0; r < 4; ++r) hi[T.hinge[e][r]].push_back((e << 2) | r);
+    }
+    for (int t = 0; t < nt; ++t)
+        for (int s3 = 0; s3 < 3; ++s3) ti[T.tri[3 * t + s3]].push_back((t << 2) | s3);
+    T.e_off.assign(1, 0); T.h_off.assign(1, 0); T.t_off.assign(1, 0);
+    for (int v = 0; v < nv; ++v) {
+        for (auto& p : ei[v]) T.e_inc.push_back(p);
+        for (int c : hi[v]) T.h_inc.push_back(c);
+        for (int c : ti[v]) T.t_inc.push_back(c);
+        T.e_off.push_back((int)T.e_inc.size());
+        T.h_off.push_back((int)T.h_inc.size());
+        T.t_off.push_back((int)T.t_inc.size());
+    }
+    return OIF_OK;
+}
+
+struct Object {
+    int tid = 0;
+    double mass = 1.0;
+    int ptype = 0;
+    double fext[3] = {0, 0, 0};
+    int anchor[3] = {0, 0, 0};
+    long long off = 0; // first node in the concatenated mesh arrays
+    int nv = 0;
+};
+
+// device buffer helper
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct oif_ctx {
+    oif_lattice_desc d{};
+    std::string err;
+    hipStream_t own = nullptr, stream = nullptr;
+    int N = 0;
+    size_t st_size = 0;
+    void* f[2] = {nullptr, nullptr};
+    void* G = nullptr;
+    unsigned long long* mask = nullptr;
+    unsigned* status = nullptr;
+    BoxDev box{};
+    BoxDev* box_dev = nullptr;
+    int parity = 0;
+    long long steps = 0;
+    size_t max_lds = 65536;
+
+    std::vector<Template> tmpl;
+    std::vector<Object> obj;
+    long long M = 0;
+    std::vector<double> Xh, Vh; // host mesh state (absolute positions), valid when !host_stale
+    bool host_stale = false;
+    bool mesh_dirty = true;     // device mesh arrays must be rebuilt
+
+    // device mesh
+    std::vector<DevBuf> tbufs;  // per-template arrays
+    DevBuf tmpl_dev, obj_dev, X_dev, V_dev, geo_dev, scratch_dev;
+    std::vector<unsigned char> obj_host; // ObjDev<real> array as uploaded (sorted)
+    int n_lds_obj = 0;          // objects [0, n_lds_obj) use LDS, the rest global scratch
+    size_t lds_need = 0;
+
+    // launch configuration
+    int lb_block = 256, mesh_block = 256, remap = 1;
+    int graph_steps = 0;
+    hipGraphExec_t gexec = nullptr;
+    int g_len = 0;
+
+    // diagnostics
+    DevBuf part_dev, diag_out;
+    int diag_blocks = 256;
+};
+
+struct oif_batch {
+    std::vector<oif_ctx*> ctx;
+    std::string err;
+    int precision = 0;
+    DevBuf boxes_dev, work_dev, obj_dev;
+    std::vector<unsigned char> obj_host;
+    int nblocks = 0, nobj = 0, n_lds_obj = 0;
+    size_t lds_need = 0;
+    int lb_block = 256, mesh_block = 256, remap = 1;
+    int graph_steps = 0;
+    hipGraphExec_t gexec = nullptr;
+    int g_len = 0;
+    bool built = false;
+};
+
+namespace {
+
+int fail(oif_ctx* c, int code, const std::string& m) {
+    if (c) c->err = m;
+    return code;
+}
+
+#define HIPCALL(ctx, expr)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? OIF_E_NOMEM : OIF_E_HIP,               \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+bool is_fp64(const oif_ctx* c) { return c->d.precision == OIF_PREC_FP64; }
+size_t real_size(int prec) { return prec == OIF_PREC_FP64 ? 8 : 4; }
+
+int dev_alloc(oif_ctx* c, DevBuf& b, size_t n) {
+    b.release();
+    if (n == 0) n = 16;
+    hipError_t e = hipMalloc(&b.p, n);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail(c, OIF_E_NOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    }
+    b.n = n;
+    return OIF_OK;
+}
+
+void drop_graph(oif_ctx* c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->g_len = 0;
+}
+
+// Pull the device mesh state into Xh/Vh (absolute coordinates).
+int pull_mesh(oif_ctx* c) {
+    if (!c->host_stale || c->M == 0 || !c->X_dev.p) {
+        c->host_stale = false;
+        return OIF_OK;
+    }
+    const size_t n = 3 * (size_t)c->M;
+    std::vector<double> xl(n), vl(n);
+    HIPCALL(c, hipMemcpyAsync(xl.data(), c->X_dev.p, n * 8, hipMemcpyDeviceToHost, c->stream));
+    if (is_fp64(c)) {
+        HIPCALL(c, hipMemcpyAsync(vl.data(), c->V_dev.p, n * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCALL(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> vf(n);
+        HIPCALL(c, hipMemcpyAsync(vf.data(), c->V_dev.p, n * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCALL(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < n; ++i) vl[i] = vf[i];
+    }
+    for (const Object& o : c->obj)
+        for (int v = 0; v < o.nv; ++v)
+            for (int k = 0; k < 3; ++k) {
+                const size_t i = 3 * ((size_t)o.off + v) + k;
+                c->Xh[i] = xl[i] + o.anchor[k];
+                c->Vh[i] = vl[i];
+            }
+    c->host_stale = false;
+    return OIF_OK;
+}
+
+template <typename real>
+int upload_mesh_t(oif_ctx* c) {
+    // per-template arrays
+    for (auto& b : c->tbufs) b.release();
+    c->tbufs.assign(c->tmpl.size(), DevBuf());
+    std::vector<TmplDev<real>> td(c->tmpl.size());
+    for (size_t t = 0; t < c->tmpl.size(); ++t) {
+        const Template& T = c->tmpl[t];
+        // one allocation, sub-arrays 16-byte aligned
+        std::vector<std::pair<const void*, size_t>> parts;
+        const std::vector<double>& L0 = T.L0;
+        const std::vector<double>& S0 = T.S0;
+        const std::vector<double>& th = T.theta0;
+        std::vector<int4> hv(T.ne);
+        std::vector<int2> ht(T.ne), einc(T.e_inc.size());
+        for (int e = 0; e < T.ne; ++e) {
+            hv[e] = make_int4(T.hinge[e][0], T.hinge[e][1], T.hinge[e][2], T.hinge[e][3]);
+            ht[e] = make_int2(T.hinge_tri[e][0], T.hinge_tri[e][1]);
+        }
+        for (size_t k = 0; k < T.e_inc.size(); ++k) einc[k] = make_int2(T.e_inc[k][0], T.e_inc[k][1]);
+        parts = {{T.tri.data(), T.tri.size() * 4},       {T.e_off.data(), T.e_off.size() * 4},
+                 {einc.data(), einc.size() * 8},         {L0.data(), L0.size() * sizeof(double)},
+                 {T.h_off.data(), T.h_off.size() * 4},   {T.h_inc.data(), T.h_inc.size() * 4},
+                 {hv.data(), hv.size() * 16},            {ht.data(), ht.size() * 8},
+                 {th.data(), th.size() * sizeof(double)}, {T.t_off.data(), T.t_off.size() * 4},
+                 {T.t_inc.data(), T.t_inc.size() * 4},   {S0.data(), S0.size() * sizeof(double)}};
+        std::vector<size_t> offs;
+        size_t total = 0;
+        for (auto& p : parts) {
+            offs.push_back(total);
+            total += (p.second + 15) & ~(size_t)15;
+        }
+        std::vector<unsigned char> host(total, 0);
+        for (size_t k = 0; k < parts.size(); ++k) std::memcpy(host.data() + offs[k], parts[k].first, parts[k].second);
+        int rc = dev_alloc(c, c->tbufs[t], total);
+        if (rc) return rc;
+        HIPCALL(c, hipMemcpy(c->tbufs[t].p, host.data(), total, hipMemcpyHostToDevice));
+        unsigned char* b = (unsigned char*)c->tbufs[t].p;
+        TmplDev<real>& D = td[t];
+        D.nv = T.nv; D.nt = T.nt; D.ne = T.ne;
+        D.linear = T.k.stretch_law == OIF_STRETCH_LINEAR;
+        D.tri = (const int*)(b + offs[0]);
+        D.e_off = (const int*)(b + offs[1]);
+        D.e_inc = (const int2*)(b + offs[2]);
+        D.L0 = (const double*)(b + offs[3]);
+        D.h_off = (const int*)(b + offs[4]);
+        D.h_inc = (const int*)(b + offs[5]);
+        D.hinge = (const int4*)(b + offs[6]);
+        D.hinge_tri = (const int2*)(b + offs[7]);
+        D.theta0 = (const double*)(b + offs[8]);
+        D.t_off = (const int*)(b + offs[9]);
+        D.t_inc = (const int*)(b + offs[10]);
+        D.S0 = (const double*)(b + offs[11]);
+        D.Sg0 = T.Sg0; D.V0 = T.V0;
+        D.ks = T.k.ks; D.kb = T.k.kb; D.kal = T.k.kal; D.kag = T.k.kag; D.kv = T.k.kv;
+    }
+    int rc = dev_alloc(c, c->tmpl_dev, td.size() * sizeof(TmplDev<real>));
+    if (rc) return rc;
+    HIPCALL(c, hipMemcpy(c->tmpl_dev.p, td.data(), td.size() * sizeof(TmplDev<real>), hipMemcpyHostToDevice));
+
+    // mesh state (object-local) and per-object descriptors
+    const size_t n = 3 * (size_t)c->M;
+    std::vector<double> xl(n);
+    std::vector<real> vl(n);
+    for (const Object& o : c->obj)
+        for (int v = 0; v < o.nv; ++v)
+            for (int k = 0; k < 3; ++k) {
+                const size_t i = 3 * ((size_t)o.off + v) + k;
+                xl[i] = c->Xh[i] - o.anchor[k];
+                vl[i] = (real)c->Vh[i];
+            }
+    if ((rc = dev_alloc(c, c->X_dev, n * sizeof(double)))) return rc;
+    if ((rc = dev_alloc(c, c->V_dev, n * sizeof(real)))) return rc;
+    if ((rc = dev_alloc(c, c->geo_dev, 2 * sizeof(double) * (c->obj.size() + 1)))) return rc;
+    HIPCALL(c, hipMemcpy(c->X_dev.p, xl.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    HIPCALL(c, hipMemcpy(c->V_dev.p, vl.data(), n * sizeof(real), hipMemcpyHostToDevice));
+
+    // objects sorted: LDS-resident first, each group largest mesh first
+    const size_t budget = c->max_lds > 512 ? c->max_lds - 512 : 0;
+    std::vector<int> order(c->obj.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    auto need = [&](int i) {
+        const Template& T = c->tmpl[c->obj[i].tid];
+        return mesh_lds_bytes(c->d.precision, T.nv, T.nt, T.ne);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const bool la = need(a) <= budget, lb = need(b) <= budget;
+        if (la != lb) return la;
+        return c->obj[a].nv > c->obj[b].nv;
+    });
+    c->n_lds_obj = 0;
+    c->lds_need = 0;
+    size_t scratch_total = 0;
+    for (int i : order) {
+        if (need(i) <= budget) {
+            ++c->n_lds_obj;
+            c->lds_need = std::max(c->lds_need, need(i));
+        } else {
+            scratch_total += (need(i) + 255) & ~(size_t)255;
+        }
+    }
+    if ((rc = dev_alloc(c, c->scratch_dev, scratch_total))) return rc;
+    std::vector<ObjDev<real>> od(c->obj.size());
+    size_t soff = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
+        const Object& o = c->obj[order[k]];
+        ObjDev<real>& D = od[k];
+        D.t = (const TmplDev<real>*)c->tmpl_dev.p + o.tid;
+        D.box = c->box_dev;
+        D.X = (double*)c->X_dev.p + 3 * o.off;
+        D.V = (real*)c->V_dev.p + 3 * o.off;
+        D.geo = (double*)c->geo_dev.p + 2 * order[k];
+        for (int a = 0; a < 3; ++a) {
+            D.anchor[a] = o.anchor[a];
+            D.fext[a] = (real)o.fext[a];
+        }
+        D.inv_mass = (real)(1.0 / o.mass);
+        D.mass = o.mass;
+        D.scratch = nullptr;
+        if ((int)k >= c->n_lds_obj) {
+            D.scratch = (unsigned char*)c->scratch_dev.p + soff;
+            soff += (need(order[k]) + 255) & ~(size_t)255;
+        }
+    }
+    c->obj_host.assign((unsigned char*)od.data(), (unsigned char*)(od.data() + od.size()));
+    if ((rc = dev_alloc(c, c->obj_dev, od.size() * sizeof(ObjDev<real>)))) return rc;
+    HIPCALL(c, hipMemcpy(c->obj_dev.p, od.data(), od.size() * sizeof(ObjDev<real>), hipMemcpyHostToDevice));
+    // diagnostics partials: lattice blocks + objects
+    if ((rc = dev_alloc(c, c->part_dev, 5 * sizeof(double) * (c->diag_blocks + c->obj.size() + 1)))) return rc;
+    return OIF_OK;
+}
+
+int sync_mesh(oif_ctx* c) {
+    if (!c->mesh_dirty) return OIF_OK;
+    int rc = pull_mesh(c);
+    if (rc) return rc;
+    drop_graph(c);
+    rc = is_fp64(c) ? upload_mesh_t<double>(c) : upload_mesh_t<float>(c);
+    if (rc) return rc;
+    c->mesh_dirty = false;
+    return OIF_OK;
+}
+
+size_t objdev_size(int prec) { return prec == OIF_PREC_FP64 ? sizeof(ObjDev<double>) : sizeof(ObjDev<float>); }
+
+int enqueue_steps(oif_ctx* c, int n, int parity0, hipStream_t s) {
+    int par = parity0;
+    const int nblk = (c->N + c->lb_block - 1) / c->lb_block;
+    const size_t osz = objdev_size(c->d.precision);
+    for (int k = 0; k < n; ++k) {
+        if (!c->obj.empty()) {
+            MeshLaunch ml{};
+            ml.block = c->mesh_block;
+            ml.parity = par;
+            ml.precision = c->d.precision;
+            ml.stream = s;
+            if (c->n_lds_obj > 0) {
+                ml.objs = c->obj_dev.p;
+                ml.nobj = c->n_lds_obj;
+                ml.lds_bytes = c->lds_need;
+                HIPCALL(c, launch_mesh(ml));
+            }
+            if ((int)c->obj.size() > c->n_lds_obj) {
+                ml.objs = (const unsigned char*)c->obj_dev.p + osz * c->n_lds_obj;
+                ml.nobj = (int)c->obj.size() - c->n_lds_obj;
+                ml.lds_bytes = 0;
+                HIPCALL(c, launch_mesh(ml));
+            }
+        }
+        LbLaunch ll{};
+        ll.boxes = c->box_dev;
+        ll.work = nullptr;
+        ll.nblocks = nblk;
+        ll.block = c->lb_block;
+        ll.parity = par;
+        ll.remap = c->remap;
+        ll.precision = c->d.precision;
+        ll.stream = s;
+        HIPCALL(c, launch_lb(ll));
+        par ^= 1;
+    }
+    return OIF_OK;
+}
+
+int run_diag(oif_ctx* c, double out[10], unsigned* status) {
+    double* part = (double*)c->part_dev.p;
+    HIPCALL(c, launch_diag_lattice(c->box_dev, c->d.precision, c->parity, part, c->diag_blocks, c->stream));
+    HIPCALL(c, launch_diag_mesh(c->obj_dev.p, (int)c->obj.size(), c->d.precision, part + 5 * c->diag_blocks, c->stream));
+    HIPCALL(c, launch_diag_final(part, c->diag_blocks, (int)c->obj.size(), (double*)c->diag_out.p, c->stream));
+    HIPCALL(c, hipMemcpyAsync(out, c->diag_out.p, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCALL(c, hipMemcpyAsync(status, c->status, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    return OIF_OK;
+}
+
+int watchdog(oif_ctx* c) {
+    double out[10];
+    unsigned st = 0;
+    int rc = run_diag(c, out, &st);
+    if (rc) return rc;
+    if (out[4] != 0 || out[9] != 0 || (st & ST_NONFINITE))
+        return fail(c, OIF_E_NONFINITE, "watchdog: non-finite populations or mesh state");
+    if (st & ST_OVERFLOW) return fail(c, OIF_E_OVERFLOW, "watchdog: coupling force out of fixed-point range");
+    return OIF_OK;
+}
+
+int check_obj(oif_ctx* c, int oid) {
+    if (!c) return OIF_E_ARG;
+    if (oid < 0 || oid >= (int)c->obj.size()) return fail(c, OIF_E_ARG, "object id out of range");
+    return OIF_OK;
+}
+
+int step_impl(oif_ctx* c, int n) {
+    int rc = sync_mesh(c);
+    if (rc) return rc;
+    HIPCALL(c, hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream));
+    int left = n;
+    if (c->graph_steps > 0 && n >= c->graph_steps) {
+        if (c->parity) {  // the captured graph starts at parity 0
+            if ((rc = enqueue_steps(c, 1, c->parity, c->stream))) return rc;
+            c->parity ^= 1;
+            --left;
+        }
+        if (!c->gexec || c->g_len != c->graph_steps) {
+            drop_graph(c);
+            hipGraph_t g = nullptr;
+            HIPCALL(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            rc = enqueue_steps(c, c->graph_steps, 0, c->stream);
+            hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+            if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+            HIPCALL(c, e2);
+            hipError_t e3 = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPCALL(c, e3);
+            c->g_len = c->graph_steps;
+        }
+        while (left >= c->graph_steps) {
+            HIPCALL(c, hipGraphLaunch(c->gexec, c->stream));
+            left -= c->graph_steps;
+        }
+    }
+    if (left > 0) {
+        if ((rc = enqueue_steps(c, left, c->parity, c->stream))) return rc;
+        c->parity ^= (left & 1);
+    }
+    c->steps += n;
+    if (c->M) c->host_stale = true;
+    return watchdog(c);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int oif_lattice_desc_init(oif_lattice_desc* d) {
+    if (!d) return OIF_E_ARG;
+    std::memset(d, 0, sizeof(*d));
+    d->tau = 1.0;
+    d->rho0 = 1.0;
+    d->precision = OIF_PREC_FP32;
+    d->fp16_scale_exp = 12;
+    d->fixed_point_exp = 40;
+    return OIF_OK;
+}
+
+const char* oif_last_error(const oif_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
+    if (!desc || !out) return OIF_E_ARG;
+    *out = nullptr;
+    const oif_lattice_desc& d = *desc;
+    const long long N = (long long)d.nx * d.ny * d.nz;
+    bool ok = d.nx >= 1 && d.ny >= 1 && d.nz >= 1 && d.nx <= 4096 && d.ny <= 4096 && d.nz <= 4096 &&
+              N * 19 < (1LL << 31) && std::isfinite(d.tau) && d.tau > 0.5 && std::isfinite(d.rho0) &&
+              d.rho0 > 0 && std::isfinite(d.friction) && d.friction >= 0 && d.precision >= 0 &&
+              d.precision <= 3 && d.fp16_scale_exp >= 0 && d.fp16_scale_exp <= 24 &&
+              d.fixed_point_exp >= 16 && d.fixed_point_exp <= 56 && (!d.walls_z || d.nz >= 2);
+    for (int c = 0; c < 3; ++c) ok = ok && std::isfinite(d.body_force[c]);
+    if (!ok) return OIF_E_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= d.device || d.device < 0) return OIF_E_UNSUPPORTED;
+    if (hipSetDevice(d.device) != hipSuccess) return OIF_E_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, d.device) != hipSuccess) return OIF_E_HIP;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return OIF_E_UNSUPPORTED;
+
+    std::unique_ptr<oif_ctx> c(new oif_ctx());
+    c->d = d;
+    c->N = (int)N;
+    c->st_size = d.precision == OIF_PREC_FP64 ? 8 : (d.precision == OIF_PREC_FP32 ? 4 : 2);
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, d.device) == hipSuccess && lds > 0)
+        c->max_lds = (size_t)lds;
+    if (mesh_set_max_lds(c->max_lds) != hipSuccess) c->max_lds = std::min<size_t>(c->max_lds, 65536);
+    (void)hipGetLastError();  // the opt-in result must not leak into the next launch check
+    if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) return OIF_E_HIP;
+    c->stream = c->own;
+    oif_ctx* cp = c.get();
+    auto alloc = [&](void** p, size_t n) -> int {
+        if (hipMalloc(p, n) != hipSuccess) { *p = nullptr; return OIF_E_NOMEM; }
+        return OIF_OK;
+    };
+    const size_t popb = 19 * (size_t)N * c->st_size;
+    const size_t nmask = ((size_t)N + 63) / 64;
+    int rc = OIF_OK;
+    if ((rc = alloc(&c->f[0], popb)) || (rc = alloc(&c->f[1], popb)) || (rc = alloc(&c->G, 24 * (size_t)N)) ||
+        (rc = alloc((void**)&c->mask, 8 * nmask)) || (rc = alloc((void**)&c->status, 256)) ||
+        (rc = alloc((void**)&c->box_dev, sizeof(BoxDev)))) {
+        oif_destroy(c.release());
+        return rc;
+    }
+    if (hipMemsetAsync(c->f[0], 0, popb, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->f[1], 0, popb, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->G, 0, 24 * (size_t)N, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->mask, 0, 8 * nmask, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->status, 0, 256, c->stream) != hipSuccess) {
+        oif_destroy(c.release());
+        return OIF_E_HIP;
+    }
+    BoxDev& b = c->box;
+    b.nx = d.nx; b.ny = d.ny; b.nz = d.nz; b.walls_z = d.walls_z ? 1 : 0;
+    b.N = (int)N;
+    b.precision = d.precision;
+    b.f[0] = c->f[0]; b.f[1] = c->f[1];
+    b.G = c->G;
+    b.mask = c->mask;
+    b.status = c->status;
+    for (int k = 0; k < 3; ++k) b.g[k] = d.body_force[k];
+    b.rho0 = d.rho0;
+    b.omega = 1.0 / d.tau;
+    b.guo = 1.0 - 0.5 / d.tau;
+    b.xi = d.friction;
+    b.st_scale = d.precision == OIF_PREC_FP32_ST_FP16 ? std::ldexp(1.0f, d.fp16_scale_exp) : 1.0f;
+    b.st_inv = 1.0f / b.st_scale;
+    b.fp_scale = std::ldexp(1.0, d.fixed_point_exp);
+    b.fp_inv = std::ldexp(1.0, -d.fixed_point_exp);
+    if (hipMemcpyAsync(c->box_dev, &b, sizeof(BoxDev), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        dev_alloc(cp, c->diag_out, 16 * sizeof(double)) != OIF_OK ||
+        dev_alloc(cp, c->part_dev, 5 * sizeof(double) * (c->diag_blocks + 1)) != OIF_OK ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        oif_destroy(c.release());
+        return OIF_E_HIP;
+    }
+    *out = c.release();
+    return OIF_OK;
+}
+
+int oif_destroy(oif_ctx* c) {
+    if (!c) return OIF_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    for (void* p : {c->f[0], c->f[1], c->G, (void*)c->mask, (void*)c->status, (void*)c->box_dev})
+        if (p) (void)hipFree(p);
+    for (auto& b : c->tbufs) b.release();
+    for (DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->geo_dev, &c->scratch_dev,
+                      &c->part_dev, &c->diag_out})
+        b->release();
+    if (c->own) (void)hipStreamDestroy(c->own);
+    delete c;
+    return OIF_OK;
+}
+
+int oif_bind_stream(oif_ctx* c, void* s) {
+    if (!c) return OIF_E_ARG;
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    c->stream = s ? (hipStream_t)s : c->own;
+    return OIF_OK;
+}
+
+int oif_template_create(oif_ctx* c, int tid, const double* nodes, int nv, const int32_t* tris, int nt,
+                        const double stretch[3], const oif_moduli* k) {
+    if (!c || !k) return OIF_E_ARG;
+    if (tid != (int)c->tmpl.size()) return fail(c, OIF_E_ID, "template ids must start at 0 and be consecutive");
+    if (!c->obj.empty()) return fail(c, OIF_E_STATE, "templates must be created before objects");
+    for (double v : {k->ks, k->kb, k->kal, k->kag, k->kv})
+        if (!std::isfinite(v)) return fail(c, OIF_E_ARG, "non-finite modulus");
+    if (stretch)
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(stretch[a]) || stretch[a] <= 0) return fail(c, OIF_E_ARG, "stretch must be > 0");
+    Template T;
+    int rc = build_template(nodes, nv, tris, nt, stretch, k, T, c->err);
+    if (rc) return rc;
+    c->tmpl.push_back(std::move(T));
+    c->mesh_dirty = true;
+    return OIF_OK;
+}
+
+int oif_euler_to_rot(double rx, double ry, double rz, double R[9]) {
+    if (!R) return OIF_E_ARG;
+    const double cx = std::cos(rx), sx = std::sin(rx), cy = std::cos(ry), sy = std::sin(ry),
+                 cz = std::cos(rz), sz = std::sin(rz);
+    // Rz * Ry * Rx
+    R[0] = cz * cy; R[1] = cz * sy * sx - sz * cx; R[2] = cz * sy * cx + sz * sx;
+    R[3] = sz * cy; R[4] = sz * sy * sx + cz * cx; R[5] = sz * sy * cx - cz * sx;
+    R[6] = -sy;     R[7] = cy * sx;                R[8] = cy * cx;
+    return OIF_OK;
+}
+
+int oif_object_add(oif_ctx* c, int oid, int tid, const double origin[3], const double rot[9], double mass,
+                   int part_type) {
+    if (!c || !origin) return OIF_E_ARG;
+    if (oid != (int)c->obj.size()) return fail(c, OIF_E_ID, "object ids must start at 0 and be consecutive");
+    if (tid < 0 || tid >= (int)c->tmpl.size()) return fail(c, OIF_E_ARG, "unknown template id");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(origin[a]) || std::fabs(origin[a]) > 1e6) return fail(c, OIF_E_ARG, "origin must be finite, |o| <= 1e6");
+    if (rot)
+        for (int a = 0; a < 9; ++a)
+            if (!std::isfinite(rot[a])) return fail(c, OIF_E_ARG, "non-finite rotation");
+    if (!std::isfinite(mass)) return fail(c, OIF_E_ARG, "non-finite mass");
+    int rc = pull_mesh(c);
+    if (rc) return rc;
+    const Template& T = c->tmpl[tid];
+    Object o;
+    o.tid = tid;
+    o.mass = mass > 0 ? mass : 1.0;
+    o.ptype = part_type;
+    o.nv = T.nv;
+    o.off = c->M;
+    for (int a = 0; a < 3; ++a) o.anchor[a] = (int)std::floor(origin[a] + 0.5);
+    const double I[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    const double* R = rot ? rot : I;
+    c->Xh.resize(3 * (size_t)(c->M + T.nv));
+    c->Vh.resize(3 * (size_t)(c->M + T.nv), 0.0);
+    for (int v = 0; v < T.nv; ++v) {
+        const double* p = &T.x[3 * v];
+        for (int a = 0; a < 3; ++a)
+            c->Xh[3 * ((size_t)o.off + v) + a] = origin[a] + R[3 * a] * p[0] + R[3 * a + 1] * p[1] + R[3 * a + 2] * p[2];
+    }
+    c->M += T.nv;
+    c->obj.push_back(o);
+    c->mesh_dirty = true;
+    return OIF_OK;
+}
+
+int oif_object_set_force(oif_ctx* c, int oid, const double f[3]) {
+    int rc = check_obj(c, oid);
+    if (rc) return rc;
+    if (!f || !std::isfinite(f[0]) || !std::isfinite(f[1]) || !std::isfinite(f[2])) return fail(c, OIF_E_ARG, "bad force");
+    for (int a = 0; a < 3; ++a) c->obj[oid].fext[a] = f[a];
+    c->mesh_dirty = true;
+    return OIF_OK;
+}
+
+int oif_object_set_origin(oif_ctx* c, int oid, const double o[3]) {
+    int rc = check_obj(c, oid);
+    if (rc) return rc;
+    if (!o) return OIF_E_ARG;
+    if ((rc = pull_mesh(c))) return rc;
+    const Object& ob = c->obj[oid];
+    double mean[3] = {0, 0, 0};
+    for (int v = 0; v < ob.nv; ++v)
+        for (int a = 0; a < 3; ++a) mean[a] += c->Xh[3 * ((size_t)ob.off + v) + a];
+    for (int a = 0; a < 3; ++a) mean[a] /= ob.nv;
+    for (int v = 0; v < ob.nv; ++v)
+        for (int a = 0; a < 3; ++a) c->Xh[3 * ((size_t)ob.off + v) + a] += o[a] - mean[a];
+    c->mesh_dirty = true;
+    return OIF_OK;
+}
+
+int oif_object_set_nodes(oif_ctx* c, int oid, const double* x) {
+    return oif_write_mesh(c, oid, x, nullptr);
+}
+
+int oif_write_mesh(oif_ctx* c, int oid, const double* X, const double* V) {
+    if (!c) return OIF_E_ARG;
+    if (oid != -1) {
+        int rc = check_obj(c, oid);
+        if (rc) return rc;
+    }
+    int rc = pull_mesh(c);
+    if (rc) return rc;
+    const size_t off = oid < 0 ? 0 : 3 * (size_t)c->obj[oid].off;
+    const size_t n = oid < 0 ? 3 * (size_t)c->M : 3 * (size_t)c->obj[oid].nv;
+    for (size_t i = 0; i < n; ++i) {
+        if ((X && !(std::fabs(X[i]) <= 1e6)) || (V && !std::isfinite(V[i])))
+            return fail(c, OIF_E_ARG, "mesh positions must be finite with |x| <= 1e6, velocities finite");
+    }
+    if (X) std::memcpy(&c->Xh[off], X, n * sizeof(double));
+    if (V) std::memcpy(&c->Vh[off], V, n * sizeof(double));
+    c->mesh_dirty = true;
+    return OIF_OK;
+}
+
+int oif_read_mesh(oif_ctx* c, int oid, double* X, double* V) {
+    if (!c) return OIF_E_ARG;
+    if (oid != -1) {
+        int rc = check_obj(c, oid);
+        if (rc) return rc;
+    }
+    int rc = pull_mesh(c);
+    if (rc) return rc;
+    const size_t off = oid < 0 ? 0 : 3 * (size_t)c->obj[oid].off;
+    const size_t n = oid < 0 ? 3 * (size_t)c->M : 3 * (size_t)c->obj[oid].nv;
+    if (X && n) std::memcpy(X, &c->Xh[off], n * sizeof(double));
+    if (V && n) std::memcpy(V, &c->Vh[off], n * sizeof(double));
+    return OIF_OK;
+}
+
+int oif_step(oif_ctx* c, int n) {
+    if (!c || n < 0) return OIF_E_ARG;
+    if (n == 0) return OIF_OK;
+    return step_impl(c, n);
+}
+
+int oif_step_timed(oif_ctx* c, int n, oif_timing* t) {
+    if (!c || n <= 0 || !t) return OIF_E_ARG;
+    int rc = sync_mesh(c);
+    if (rc) return rc;
+    HIPCALL(c, hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream));
+    std::vector<hipEvent_t> ev(3 * (size_t)n);
+    for (auto& e : ev) HIPCALL(c, hipEventCreate(&e));
+    const int nblk = (c->N + c->lb_block - 1) / c->lb_block;
+    const size_t osz = objdev_size(c->d.precision);
+    int err = OIF_OK;
+    for (int k = 0; k < n && !err; ++k) {
+        (void)hipEventRecord(ev[3 * k], c->stream);
+        if (!c->obj.empty()) {
+            MeshLaunch ml{};
+            ml.block = c->mesh_block; ml.parity = c->parity; ml.precision = c->d.precision; ml.stream = c->stream;
+            if (c->n_lds_obj > 0) {
+                ml.objs = c->obj_dev.p; ml.nobj = c->n_lds_obj; ml.lds_bytes = c->lds_need;
+                if (launch_mesh(ml) != hipSuccess) err = OIF_E_HIP;
+            }
+            if ((int)c->obj.size() > c->n_lds_obj) {
+                ml.objs = (const unsigned char*)c->obj_dev.p + osz * c->n_lds_obj;
+                ml.nobj = (int)c->obj.size() - c->n_lds_obj; ml.lds_bytes = 0;
+                if (launch_mesh(ml) != hipSuccess) err = OIF_E_HIP;
+            }
+        }
+        (void)hipEventRecord(ev[3 * k + 1], c->stream);
+        LbLaunch ll{c->box_dev, nullptr, nblk, c->lb_block, c->parity, c->remap, c->d.precision, c->stream};
+        if (launch_lb(ll) != hipSuccess) err = OIF_E_HIP;
+        (void)hipEventRecord(ev[3 * k + 2], c->stream);
+        c->parity ^= 1;
+    }
+    (void)hipStreamSynchronize(c->stream);
+    double lb = 0, ms = 0;
+    float v = 0;
+    for (int k = 0; k < n; ++k) {
+        (void)hipEventElapsedTime(&v, ev[3 * k], ev[3 * k + 1]);
+        ms += v;
+        (void)hipEventElapsedTime(&v, ev[3 * k + 1], ev[3 * k + 2]);
+        lb += v;
+    }
+    (void)hipEventElapsedTime(&v, ev[0], ev[3 * (size_t)n - 1]);
+    t->total_ms = v;
+    t->lb_ms = lb / n;
+    t->mesh_ms = c->obj.empty() ? 0.0 : ms / n;
+    t->lb_launches = n;
+    t->mesh_launches = c->obj.empty() ? 0 : n;
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (err) return fail(c, err, "kernel launch failed");
+    c->steps += n;
+    if (c->M) c->host_stale = true;
+    return watchdog(c);
+}
+
+int oif_set_graph(oif_ctx* c, int steps_per_graph) {
+    if (!c || steps_per_graph < 0) return OIF_E_ARG;
+    c->graph_steps = steps_per_graph > 0 ? steps_per_graph + (steps_per_graph & 1) : 0;
+    drop_graph(c);
+    return OIF_OK;
+}
+
+int oif_set_launch(oif_ctx* c, int lb_block, int mesh_block, int xcd_remap) {
+    if (!c) return OIF_E_ARG;
+    auto okb = [](int b) { return b == 64 || b == 128 || b == 256 || b == 512 || b == 1024; };
+    if (lb_block >= 0 && !okb(lb_block)) return fail(c, OIF_E_ARG, "lb_block must be 64..1024, power of two");
+    if (mesh_block >= 0 && !okb(mesh_block)) return fail(c, OIF_E_ARG, "mesh_block must be 64..1024, power of two");
+    if (lb_block >= 0) c->lb_block = lb_block;
+    if (mesh_block >= 0) c->mesh_block = mesh_block;
+    if (xcd_remap >= 0) c->remap = xcd_remap ? 1 : 0;
+    drop_graph(c);
+    return OIF_OK;
+}
+
+int oif_read_populations(oif_ctx* c, double* out) {
+    if (!c || !out) return OIF_E_ARG;
+    double* tmp = nullptr;
+    const size_t n = 19 * (size_t)c->N;
+    HIPCALL(c, hipMalloc(&tmp, n * 8));
+    hipError_t e = launch_pops_to_f64(c->box_dev, c->N, c->d.precision, c->parity, tmp, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    HIPCALL(c, e);
+    return OIF_OK;
+}
+
+int oif_write_populations(oif_ctx* c, const double* in) {
+    if (!c || !in) return OIF_E_ARG;
+    double* tmp = nullptr;
+    const size_t n = 19 * (size_t)c->N;
+    HIPCALL(c, hipMalloc(&tmp, n * 8));
+    hipError_t e = hipMemcpyAsync(tmp, in, n * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_f64_to_pops(c->box_dev, c->N, c->d.precision, c->parity, tmp, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    HIPCALL(c, e);
+    return OIF_OK;
+}
+
+static int read_moments(oif_ctx* c, double* rho, double* u) {
+    double* tmp = nullptr;
+    const size_t n = (size_t)c->N * (rho ? 1 : 3);
+    HIPCALL(c, hipMalloc(&tmp, n * 8));
+    hipError_t e = launch_moments(c->box_dev, c->N, c->d.precision, c->parity, rho ? tmp : nullptr,
+                                  rho ? nullptr : tmp, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(rho ? rho : u, tmp, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    HIPCALL(c, e);
+    return OIF_OK;
+}
+
+int oif_read_density(oif_ctx* c, double* out) {
+    if (!c || !out) return OIF_E_ARG;
+    return read_moments(c, out, nullptr);
+}
+
+int oif_read_velocity(oif_ctx* c, double* out) {
+    if (!c || !out) return OIF_E_ARG;
+    return read_moments(c, nullptr, out);
+}
+
+int oif_object_analyze(oif_ctx* c, int oid, oif_analysis* a) {
+    int rc = check_obj(c, oid);
+    if (rc) return rc;
+    if (!a) return OIF_E_ARG;
+    if ((rc = pull_mesh(c))) return rc;
+    const Object& o = c->obj[oid];
+    const Template& T = c->tmpl[o.tid];
+    const double* X = &c->Xh[3 * (size_t)o.off];
+    const double* V = &c->Vh[3 * (size_t)o.off];
+    std::memset(a, 0, sizeof(*a));
+    for (int k = 0; k < 3; ++k) { a->bounds[2 * k] = X[k]; a->bounds[2 * k + 1] = X[k]; }
+    for (int v = 0; v < o.nv; ++v)
+        for (int k = 0; k < 3; ++k) {
+            a->origin[k] += X[3 * v + k];
+            a->velocity[k] += V[3 * v + k];
+            a->bounds[2 * k] = std::min(a->bounds[2 * k], X[3 * v + k]);
+            a->bounds[2 * k + 1] = std::max(a->bounds[2 * k + 1], X[3 * v + k]);
+        }
+    for (int k = 0; k < 3; ++k) { a->origin[k] /= o.nv; a->velocity[k] /= o.nv; }
+    double S = 0, Vol = 0;
+    for (int t = 0; t < T.nt; ++t) {
+        const int p = T.tri[3 * t], q = T.tri[3 * t + 1], r = T.tri[3 * t + 2];
+        double n[3];
+        vec_area(X, p, q, r, n);
+        S += std::sqrt(vdot(n, n));
+        double pa[3], pb[3], pc[3], bc[3];
+        vsub(&X[3 * p], X, pa);
+        vsub(&X[3 * q], X, pb);
+        vsub(&X[3 * r], X, pc);
+        vcross(pb, pc, bc);
+        Vol -= vdot(pa, bc) / 6.0;
+    }
+    a->area = S;
+    a->volume = Vol;
+    return OIF_OK;
+}
+
+int oif_info(oif_ctx* c, oif_info_t* info) {
+    if (!c || !info) return OIF_E_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->n_templates = (int)c->tmpl.size();
+    info->n_objects = (int)c->obj.size();
+    info->precision = c->d.precision;
+    info->walls_z = c->d.walls_z;
+    info->n_nodes = c->N;
+    info->n_mesh_nodes = c->M;
+    info->steps_done = c->steps;
+    long long bytes = 2 * 19LL * c->N * (long long)c->st_size + 24LL * c->N + 8LL * ((c->N + 63) / 64);
+    for (auto& b : c->tbufs) bytes += (long long)b.n;
+    for (const DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->geo_dev, &c->scratch_dev})
+        bytes += (long long)b->n;
+    info->device_bytes = bytes;
+    info->lb_block = c->lb_block;
+    info->mesh_block = c->mesh_block;
+    info->xcd_remap = c->remap;
+    info->graph_steps = c->graph_steps;
+    info->max_lds = (long long)c->max_lds;
+    info->lds_objects = c->n_lds_obj;
+    return OIF_OK;
+}
+
+int oif_diagnostics(oif_ctx* c, oif_diag* d) {
+    if (!c || !d) return OIF_E_ARG;
+    int rc = sync_mesh(c);
+    if (rc) return rc;
+    double out[10];
+    unsigned st = 0;
+    if ((rc = run_diag(c, out, &st))) return rc;
+    d->mass = (double)c->N * c->d.rho0 + out[0];
+    for (int k = 0; k < 3; ++k) {
+        d->momentum_fluid[k] = out[1 + k];
+        d->momentum_mesh[k] = out[6 + k];
+    }
+    d->nonfinite = (out[4] != 0 || out[9] != 0 || (st & ST_NONFINITE)) ? 1 : 0;
+    d->clamped = (st & ST_CLAMPED) ? 1 : 0;
+    d->overflow = (st & ST_OVERFLOW) ? 1 : 0;
+    return OIF_OK;
+}
+
+int oif_touched_nodes(oif_ctx* c, long long* count) {
+    if (!c || !count) return OIF_E_ARG;
+    int rc = pull_mesh(c);
+    if (rc) return rc;
+    std::vector<unsigned char> mark((size_t)c->N, 0);
+    long long cnt = 0;
+    const int dims[3] = {c->d.nx, c->d.ny, c->d.nz};
+    for (long long j = 0; j < c->M; ++j) {
+        int i0[3];
+        for (int a = 0; a < 3; ++a) i0[a] = (int)std::floor(c->Xh[3 * j + a] - 0.5);
+        for (int k = 0; k < 8; ++k) {
+            int ii[3];
+            for (int a = 0; a < 3; ++a) {
+                int v = i0[a] + ((k >> a) & 1);
+                if (a == 2 && c->d.walls_z) v = std::min(std::max(v, 0), dims[2] - 1);
+                v %= dims[a];
+                if (v < 0) v += dims[a];
+                ii[a] = v;
+            }
+            const size_t q = ((size_t)ii[2] * dims[1] + ii[1]) * dims[0] + ii[0];
+            if (!mark[q]) { mark[q] = 1; ++cnt; }
+        }
+    }
+    *count = cnt;
+    return OIF_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// autotuner: measured search of the launch shapes, cached as JSON
+// ===========================================================================
+namespace {
+
+std::string tune_key(int prec, const std::vector<std::array<int, 3>>& dims, long long nobj, long long M) {
+    std::ostringstream k;
+    k << "gfx950|p" << prec;
+    for (auto& d : dims) k << "|" << d[0] << "x" << d[1] << "x" << d[2];
+    k << "|o" << nobj << "|m" << M;
+    return k.str();
+}
+
+bool cache_lookup(const char* path, const std::string& key, int out[3]) {
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    const std::string pat = "\"" + key + "\": [";
+    const size_t p = s.find(pat);
+    if (p == std::string::npos) return false;
+    return std::sscanf(s.c_str() + p + pat.size(), "%d, %d, %d", &out[0], &out[1], &out[2]) == 3;
+}
+
+void cache_store(const char* path, const std::string& key, const int v[3]) {
+    if (!path) return;
+    std::map<std::string, std::array<int, 3>> entries;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line)) {
+            const size_t a = line.find('"'), b = line.find("\": [");
+            if (a == std::string::npos || b == std::string::npos || b <= a) continue;
+            std::array<int, 3> e{};
+            if (std::sscanf(line.c_str() + b + 4, "%d, %d, %d", &e[0], &e[1], &e[2]) == 3)
+                entries[line.substr(a + 1, b - a - 1)] = e;
+        }
+    }
+    entries[key] = {v[0], v[1], v[2]};
+    std::ofstream f(path);
+    f << "{\n";
+    size_t i = 0;
+    for (auto& kv : entries) {
+        f << "  \"" << kv.first << "\": [" << kv.second[0] << ", " << kv.second[1] << ", " << kv.second[2] << "]";
+        f << (++i < entries.size() ? ",\n" : "\n");
+    }
+    f << "}\n";
+}
+
+// Time `n` eager steps; returns average lattice and mesh kernel times (ms).
+int time_steps(oif_ctx* c, int n, double* lb_ms, double* mesh_ms) {
+    oif_timing t{};
+    const long long steps0 = c->steps;
+    int rc = oif_step_timed(c, n, &t);
+    c->steps = steps0;
+    if (rc) return rc;
+    *lb_ms = t.lb_ms;
+    *mesh_ms = t.mesh_ms;
+    return OIF_OK;
+}
+
+struct Snapshot {
+    DevBuf f, x, v;
+};
+
+int snapshot(oif_ctx* c, Snapshot& s, bool restore) {
+    const size_t pb = 19 * (size_t)c->N * c->st_size;
+    const size_t mb = 3 * (size_t)c->M * real_size(c->d.precision);
+    const size_t xb = 3 * (size_t)c->M * sizeof(double);
+    if (!restore) {
+        int rc;
+        if ((rc = dev_alloc(c, s.f, pb))) return rc;
+        if (mb && (rc = dev_alloc(c, s.x, xb))) return rc;
+        if (mb && (rc = dev_alloc(c, s.v, mb))) return rc;
+        HIPCALL(c, hipMemcpyAsync(s.f.p, c->f[c->parity], pb, hipMemcpyDeviceToDevice, c->stream));
+        if (mb) {
+            HIPCALL(c, hipMemcpyAsync(s.x.p, c->X_dev.p, xb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCALL(c, hipMemcpyAsync(s.v.p, c->V_dev.p, mb, hipMemcpyDeviceToDevice, c->stream));
+        }
+    } else {
+        HIPCALL(c, hipMemcpyAsync(c->f[c->parity], s.f.p, pb, hipMemcpyDeviceToDevice, c->stream));
+        if (mb) {
+            HIPCALL(c, hipMemcpyAsync(c->X_dev.p, s.x.p, xb, hipMemcpyDeviceToDevice, c->stream));
+            HIPCALL(c, hipMemcpyAsync(c->V_dev.p, s.v.p, mb, hipMemcpyDeviceToDevice, c->stream));
+        }
+        HIPCALL(c, hipStreamSynchronize(c->stream));
+        s.f.release();
+        s.x.release();
+        s.v.release();
+    }
+    return OIF_OK;
+}
+
+}  // namespace
+
+extern "C" int oif_autotune(oif_ctx* c, const char* cache_path) {
+    if (!c) return OIF_E_ARG;
+    int rc = sync_mesh(c);
+    if (rc) return rc;
+    const std::string key = tune_key(c->d.precision, {{c->d.nx, c->d.ny, c->d.nz}}, (long long)c->obj.size(), c->M);
+    int best[3];
+    if (cache_lookup(cache_path, key, best)) return oif_set_launch(c, best[0], best[1], best[2]);
+    Snapshot s;
+    if ((rc = snapshot(c, s, false))) return rc;
+    const int reps = 6;  // even: parity is unchanged after each trial
+    double best_lb = 1e300, best_mesh = 1e300;
+    best[0] = c->lb_block; best[1] = c->mesh_block; best[2] = c->remap;
+    for (int lb : {128, 256, 512, 1024})
+        for (int rm : {0, 1}) {
+            c->lb_block = lb;
+            c->remap = rm;
+            double tl, tm;
+            if ((rc = time_steps(c, reps, &tl, &tm))) return rc;
+            if (tl < best_lb) { best_lb = tl; best[0] = lb; best[2] = rm; }
+        }
+    c->lb_block = best[0];
+    c->remap = best[2];
+    if (!c->obj.empty())
+        for (int mb : {64, 128, 256, 512, 1024}) {
+            c->mesh_block = mb;
+            double tl, tm;
+            if ((rc = time_steps(c, reps, &tl, &tm))) return rc;
+            if (tm < best_mesh) { best_mesh = tm; best[1] = mb; }
+        }
+    c->mesh_block = best[1];
+    if ((rc = snapshot(c, s, true))) return rc;
+    c->host_stale = c->M > 0;
+    drop_graph(c);
+    cache_store(cache_path, key, best);
+    return OIF_OK;
+}
+
+// ===========================================================================
+// batching form: all boxes of a batch advance with one membrane/coupling
+// launch over all objects and one lattice launch over all boxes' nodes
+// ===========================================================================
+namespace {
+
+int bfail(oif_batch* b, int code, const std::string& m) {
+    b->err = m;
+    return code;
+}
+
+#define BHIP(b, expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return bfail(b, OIF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void bdrop_graph(oif_batch* b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->g_len = 0;
+}
+
+int batch_build(oif_batch* b) {
+    for (oif_ctx* c : b->ctx) {
+        int rc = sync_mesh(c);
+        if (rc) return bfail(b, rc, std::string("box: ") + c->err);
+    }
+    bdrop_graph(b);
+    // boxes and lattice work list
+    std::vector<BoxDev> boxes;
+    std::vector<int2> work;
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        boxes.push_back(b->ctx[i]->box);
+        const int nb = (b->ctx[i]->N + b->lb_block - 1) / b->lb_block;
+        for (int k = 0; k < nb; ++k) work.push_back(make_int2((int)i, k));
+    }
+    b->nblocks = (int)work.size();
+    b->boxes_dev.release();
+    b->work_dev.release();
+    BHIP(b, hipMalloc(&b->boxes_dev.p, boxes.size() * sizeof(BoxDev)));
+    BHIP(b, hipMalloc(&b->work_dev.p, work.size() * sizeof(int2)));
+    BHIP(b, hipMemcpy(b->boxes_dev.p, boxes.data(), boxes.size() * sizeof(BoxDev), hipMemcpyHostToDevice));
+    BHIP(b, hipMemcpy(b->work_dev.p, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice));
+    // objects of all boxes: LDS-resident group first, each largest mesh first
+    const size_t osz = objdev_size(b->precision);
+    struct Ent { const unsigned char* p; bool lds; int nv; size_t need; };
+    std::vector<Ent> ents;
+    for (oif_ctx* c : b->ctx) {
+        const size_t n = c->obj.size();
+        for (size_t k = 0; k < n; ++k) {
+            const unsigned char* p = c->obj_host.data() + k * osz;
+            const bool lds = (int)k < c->n_lds_obj;
+            // the template pointer of the sorted entry says which mesh it is
+            const void* tptr = b->precision == OIF_PREC_FP64 ? (const void*)((const ObjDev<double>*)p)->t
+                                                            : (const void*)((const ObjDev<float>*)p)->t;
+            const size_t tsz = b->precision == OIF_PREC_FP64 ? sizeof(TmplDev<double>) : sizeof(TmplDev<float>);
+            const size_t tid = ((const unsigned char*)tptr - (const unsigned char*)c->tmpl_dev.p) / tsz;
+            const Template& T = c->tmpl[tid];
+            ents.push_back({p, lds, T.nv, mesh_lds_bytes(b->precision, T.nv, T.nt, T.ne)});
+        }
+    }
+    std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& c) {
+        if (a.lds != c.lds) return a.lds;
+        return a.nv > c.nv;
+    });
+    std::vector<unsigned char> host(ents.size() * osz);
+    b->n_lds_obj = 0;
+    b->lds_need = 0;
+    for (size_t k = 0; k < ents.size(); ++k) {
+        std::memcpy(host.data() + k * osz, ents[k].p, osz);
+        if (ents[k].lds) {
+            ++b->n_lds_obj;
+            b->lds_need = std::max(b->lds_need, ents[k].need);
+        }
+    }
+    b->nobj = (int)ents.size();
+    b->obj_dev.release();
+    BHIP(b, hipMalloc(&b->obj_dev.p, host.size() + 16));
+    if (!host.empty()) BHIP(b, hipMemcpy(b->obj_dev.p, host.data(), host.size(), hipMemcpyHostToDevice));
+    b->built = true;
+    return OIF_OK;
+}
+
+int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<hipEvent_t>* ev) {
+    int par = parity0;
+    const size_t osz = objdev_size(b->precision);
+    for (int k = 0; k < n; ++k) {
+        if (ev) (void)hipEventRecord((*ev)[3 * k], s);
+        MeshLaunch ml{};
+        ml.block = b->mesh_block;
+        ml.parity = par;
+        ml.precision = b->precision;
+        ml.stream = s;
+        if (b->n_lds_obj > 0) {
+            ml.objs = b->obj_dev.p;
+            ml.nobj = b->n_lds_obj;
+            ml.lds_bytes = b->lds_need;
+            BHIP(b, launch_mesh(ml));
+        }
+        if (b->nobj > b->n_lds_obj) {
+            ml.objs = (const unsigned char*)b->obj_dev.p + osz * b->n_lds_obj;
+            ml.nobj = b->nobj - b->n_lds_obj;
+            ml.lds_bytes = 0;
+            BHIP(b, launch_mesh(ml));
+        }
+        if (ev) (void)hipEventRecord((*ev)[3 * k + 1], s);
+        LbLaunch ll{(const BoxDev*)b->boxes_dev.p, (const int2*)b->work_dev.p, b->nblocks, b->lb_block, par,
+                    b->remap, b->precision, s};
+        BHIP(b, launch_lb(ll));
+        if (ev) (void)hipEventRecord((*ev)[3 * k + 2], s);
+        par ^= 1;
+    }
+    return OIF_OK;
+}
+
+int batch_prepare(oif_batch* b) {
+    bool dirty = !b->built;
+    for (oif_ctx* c : b->ctx) dirty = dirty || c->mesh_dirty;
+    const int par = b->ctx[0]->parity;
+    for (oif_ctx* c : b->ctx)
+        if (c->parity != par) return bfail(b, OIF_E_STATE, "boxes of a batch must be at the same step parity");
+    if (dirty) return batch_build(b);
+    return OIF_OK;
+}
+
+int batch_finish(oif_batch* b, int n) {
+    for (oif_ctx* c : b->ctx) {
+        c->parity ^= (n & 1);
+        c->steps += n;
+        if (c->M) c->host_stale = true;
+    }
+    for (oif_ctx* c : b->ctx) {
+        int rc = watchdog(c);
+        if (rc) return bfail(b, rc, c->err);
+    }
+    return OIF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oif_batch_create(oif_ctx* const* boxes, int n, oif_batch** out) {
+    if (!boxes || n <= 0 || !out) return OIF_E_ARG;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i)
+        if (!boxes[i] || boxes[i]->d.precision != boxes[0]->d.precision || boxes[i]->d.device != boxes[0]->d.device)
+            return OIF_E_ARG;
+    std::unique_ptr<oif_batch> b(new oif_batch());
+    b->ctx.assign(boxes, boxes + n);
+    b->precision = boxes[0]->d.precision;
+    b->lb_block = boxes[0]->lb_block;
+    b->mesh_block = boxes[0]->mesh_block;
+    b->remap = boxes[0]->remap;
+    *out = b.release();
+    return OIF_OK;
+}
+
+int oif_batch_destroy(oif_batch* b) {
+    if (!b) return OIF_OK;
+    if (!b->ctx.empty()) (void)hipStreamSynchronize(b->ctx[0]->stream);
+    bdrop_graph(b);
+    b->boxes_dev.release();
+    b->work_dev.release();
+    b->obj_dev.release();
+    delete b;
+    return OIF_OK;
+}
+
+const char* oif_batch_last_error(const oif_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+int oif_batch_set_graph(oif_batch* b, int steps_per_graph) {
+    if (!b || steps_per_graph < 0) return OIF_E_ARG;
+    b->graph_steps = steps_per_graph > 0 ? steps_per_graph + (steps_per_graph & 1) : 0;
+    bdrop_graph(b);
+    return OIF_OK;
+}
+
+int oif_batch_set_launch(oif_batch* b, int lb_block, int mesh_block, int xcd_remap) {
+    if (!b) return OIF_E_ARG;
+    auto okb = [](int v) { return v == 64 || v == 128 || v == 256 || v == 512 || v == 1024; };
+    if ((lb_block >= 0 && !okb(lb_block)) || (mesh_block >= 0 && !okb(mesh_block))) return OIF_E_ARG;
+    if (lb_block >= 0) b->lb_block = lb_block;
+    if (mesh_block >= 0) b->mesh_block = mesh_block;
+    if (xcd_remap >= 0) b->remap = xcd_remap ? 1 : 0;
+    b->built = false;
+    bdrop_graph(b);
+    return OIF_OK;
+}
+
+int oif_batch_step(oif_batch* b, int n) {
+    if (!b || n < 0) return OIF_E_ARG;
+    if (n == 0) return OIF_OK;
+    int rc = batch_prepare(b);
+    if (rc) return rc;
+    hipStream_t s = b->ctx[0]->stream;
+    for (oif_ctx* c : b->ctx) BHIP(b, hipMemsetAsync(c->status, 0, sizeof(unsigned), s));
+    int par = b->ctx[0]->parity;
+    int left = n;
+    if (b->graph_steps > 0 && n >= b->graph_steps) {
+        if (par) {
+            if ((rc = batch_enqueue(b, 1, par, s, nullptr))) return rc;
+            par ^= 1;
+            --left;
+        }
+        if (!b->gexec || b->g_len != b->graph_steps) {
+            bdrop_graph(b);
+            hipGraph_t g = nullptr;
+            BHIP(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            rc = batch_enqueue(b, b->graph_steps, 0, s, nullptr);
+            hipError_t e2 = hipStreamEndCapture(s, &g);
+            if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+            BHIP(b, e2);
+            hipError_t e3 = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            BHIP(b, e3);
+            b->g_len = b->graph_steps;
+        }
+        while (left >= b->graph_steps) {
+            BHIP(b, hipGraphLaunch(b->gexec, s));
+            left -= b->graph_steps;
+        }
+    }
+    if (left > 0 && (rc = batch_enqueue(b, left, par, s, nullptr))) return rc;
+    return batch_finish(b, n);
+}
+
+int oif_batch_step_timed(oif_batch* b, int n, oif_timing* t) {
+    if (!b || n <= 0 || !t) return OIF_E_ARG;
+    int rc = batch_prepare(b);
+    if (rc) return rc;
+    hipStream_t s = b->ctx[0]->stream;
+    for (oif_ctx* c : b->ctx) BHIP(b, hipMemsetAsync(c->status, 0, sizeof(unsigned), s));
+    std::vector<hipEvent_t> ev(3 * (size_t)n);
+    for (auto& e : ev) BHIP(b, hipEventCreate(&e));
+    rc = batch_enqueue(b, n, b->ctx[0]->parity, s, &ev);
+    (void)hipStreamSynchronize(s);
+    double lb = 0, ms = 0;
+    float v = 0;
+    for (int k = 0; k < n && !rc; ++k) {
+        (void)hipEventElapsedTime(&v, ev[3 * k], ev[3 * k + 1]);
+        ms += v;
+        (void)hipEventElapsedTime(&v, ev[3 * k + 1], ev[3 * k + 2]);
+        lb += v;
+    }
+    (void)hipEventElapsedTime(&v, ev[0], ev[3 * (size_t)n - 1]);
+    t->total_ms = v;
+    t->lb_ms = lb / n;
+    t->mesh_ms = ms / n;
+    t->lb_launches = n;
+    t->mesh_launches = n;
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc) return rc;
+    return batch_finish(b, n);
+}
+
+int oif_batch_autotune(oif_batch* b, const char* cache_path) {
+    if (!b) return OIF_E_ARG;
+    std::vector<std::array<int, 3>> dims;
+    long long nobj = 0, M = 0;
+    for (oif_ctx* c : b->ctx) {
+        dims.push_back({c->d.nx, c->d.ny, c->d.nz});
+        nobj += (long long)c->obj.size();
+        M += c->M;
+    }
+    const std::string key = tune_key(b->precision, dims, nobj, M);
+    int best[3] = {b->lb_block, b->mesh_block, b->remap};
+    if (cache_lookup(cache_path, key, best)) return oif_batch_set_launch(b, best[0], best[1], best[2]);
+    int rc = batch_prepare(b);
+    if (rc) return rc;
+    std::vector<Snapshot> snaps(b->ctx.size());
+    for (size_t i = 0; i < b->ctx.size(); ++i)
+        if ((rc = snapshot(b->ctx[i], snaps[i], false))) return bfail(b, rc, b->ctx[i]->err);
+    const int reps = 6;
+    double best_lb = 1e300, best_mesh = 1e300;
+    auto trial = [&](double* tl, double* tm) -> int {
+        oif_timing t{};
+        std::vector<long long> st;
+        for (oif_ctx* c : b->ctx) st.push_back(c->steps);
+        int r = oif_batch_step_timed(b, reps, &t);
+        for (size_t i = 0; i < b->ctx.size(); ++i) b->ctx[i]->steps = st[i];
+        *tl = t.lb_ms;
+        *tm = t.mesh_ms;
+        return r;
+    };
+    for (int lb : {128, 256, 512, 1024})
+        for (int rm : {0, 1}) {
+            oif_batch_set_launch(b, lb, -1, rm);
+            double tl, tm;
+            if ((rc = trial(&tl, &tm))) return rc;
+            if (tl < best_lb) { best_lb = tl; best[0] = lb; best[2] = rm; }
+        }
+    oif_batch_set_launch(b, best[0], -1, best[2]);
+    for (int mb : {64, 128, 256, 512, 1024}) {
+        oif_batch_set_launch(b, -1, mb, -1);
+        double tl, tm;
+        if ((rc = trial(&tl, &tm))) return rc;
+        if (tm < best_mesh) { best_mesh = tm; best[1] = mb; }
+    }
+    oif_batch_set_launch(b, best[0], best[1], best[2]);
+    for (size_t i = 0; i < b->ctx.size(); ++i)
+        if ((rc = snapshot(b->ctx[i], snaps[i], true))) return bfail(b, rc, b->ctx[i]->err);
+    cache_store(cache_path, key, best);
+    return OIF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,182 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Criterion (see gpu_util): max|gpu - oracle| <=
+RTOL * max|oracle| + ATOL * scale, RTOL = 1e-12 (FP64 form) or 1e-5 (FP32
+form); the FP16/BF16 storage forms against the bounds stated in their tests."""
+import numpy as np
+import pytest
+
+from paper_1312_3426_amd import synth
+
+from gpu_util import W, check, compare, fmt, gpu_fields, oracle_fields, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def oif():
+    from paper_1312_3426_amd import oif as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build()
+    return oracle
+
+
+def assert_ok(res, what):
+    bad = {k: v for k, v in res.items() if not v[3]}
+    assert not bad, f"{what}: {fmt(bad)}"
+
+
+# ---------------------------------------------------------------------------
+# lattice only: random initial populations, body force, ragged sizes
+# ---------------------------------------------------------------------------
+LB_CASES = [
+    # (nx, ny, nz, walls, tau)
+    (20, 20, 20, False, 0.8),   # 8000 nodes: 31.25 blocks of 256
+    (9, 7, 11, True, 1.3),      # 693 nodes, bounce-back walls
+    (1, 1, 16, True, 1.0),      # channel column
+    (67, 3, 5, False, 0.55),    # rows longer than a wave
+    (64, 1, 1, False, 1.7),     # single row, exactly one wave
+    (2, 2, 2, False, 0.9),      # every neighbour wraps onto the box
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", LB_CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{'w' if c[3] else ''}")
+def test_lb_only_vs_oracle(oif, orc, prec, case):
+    nx, ny, nz, walls, tau = case
+    say(f"[lb_only] {prec} {case}")
+    rng = np.random.default_rng(nx * 1000 + ny * 10 + nz)
+    box = synth.Box(nx, ny, nz, tau=tau, g=(1e-5, -2e-5, 3e-5), walls_z=walls)
+    n0 = synth.random_populations(rng, box, amp=1e-3)
+    ctx = oif.Context.from_box(box, precision=prec)
+    ctx.write_populations(n0)
+    n_or = n0.copy()
+    for step in (1, 9):
+        ctx.step(step)
+        for _ in range(step):
+            n_or = orc.lb_step(n_or, tau=tau, g=box.g, walls_z=walls)
+        _, u_or = orc.moments(n_or, g=box.g)
+        g = dict(delta=ctx.read_populations() - W[:, None, None, None], u=ctx.read_velocity())
+        o = dict(delta=n_or - W[:, None, None, None], u=u_or)
+        res = check(g, o, prec, 1.0, max(nx, ny, nz), keys=("delta", "u"))
+        say(f"   after {step}: {fmt(res)}")
+        assert_ok(res, f"step {step}")
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# coupled step
+# ---------------------------------------------------------------------------
+def run_pair(oif, orc, box, prec, checkpoints, **ctx_kw):
+    ctx = oif.Context.from_box(box, precision=prec, **ctx_kw)
+    sysm = orc.System(box)
+    X0 = sysm.X.copy()
+    done = 0
+    results = []
+    for k in checkpoints:
+        say(f"   stepping to {k}")
+        ctx.step(k - done)
+        sysm.run(k - done)
+        done = k
+        g, o = gpu_fields(ctx, box.rho0, X0), oracle_fields(sysm, X0)
+        results.append((k, g, o))
+    ctx.close()
+    return results
+
+
+def test_sphere_fp64_vs_oracle(oif, orc):
+    """Plain FP64 method case: 20^3 periodic box, 642-node sphere, 100 steps."""
+    say("[coupled] sphere642 20^3 fp64")
+    box = synth.config_sphere_fp64(100)
+    for k, g, o in run_pair(oif, orc, box, "fp64", (1, 10, 100)):
+        res = check(g, o, "fp64", box.rho0, 20)
+        say(f"   step {k}: {fmt(res)}")
+        assert_ok(res, f"step {k}")
+
+
+def test_sphere_fp64_deformed_start(oif, orc):
+    """FP64 with a strongly deformed, moving mesh and a moving fluid from the
+    first step, so every field is far above its round-off floor."""
+    say("[coupled] sphere642 deformed start fp64")
+    box = synth.config_sphere_fp64(40)
+    rng = np.random.default_rng(17)
+    sysm = orc.System(box)
+    # deformed by ~2 % of an edge (forces ~1e-3): strong signals in every
+    # field while the dynamics stay gentle enough not to amplify round-off
+    X0 = sysm.X + 0.012 * rng.standard_normal(sysm.X.shape)
+    V0 = 2e-4 * rng.standard_normal(sysm.X.shape)
+    n0 = synth.random_populations(rng, box, amp=2e-3)
+    sysm.X[:] = X0
+    sysm.V[:] = V0
+    sysm.n[:] = n0
+    ctx = oif.Context.from_box(box, precision="fp64")
+    ctx.write_mesh(-1, X0, V0)
+    ctx.write_populations(n0)
+    done = 0
+    for k in (1, 40):
+        ctx.step(k - done)
+        sysm.run(k - done)
+        done = k
+        res = check(gpu_fields(ctx, box.rho0, X0), oracle_fields(sysm, X0), "fp64", box.rho0, 20)
+        say(f"   step {k}: {fmt(res)}")
+        assert_ok(res, f"step {k}")
+        if k == 1:  # every field well above its round-off floor: plain relative 1e-12
+            for key, (e, r, b, ok) in res.items():
+                assert e <= 1e-12 * r, (k, key, e / r)
+    ctx.close()
+
+
+def test_channel_rbc_fp32_vs_oracle(oif, orc):
+    """FP32 channel case: 64x32x32 with z walls, ten 393-node cells, 1000 steps."""
+    say("[coupled] rbc393x10 64x32x32 walls fp32")
+    box = synth.config_channel_rbc(1000)
+    for k, g, o in run_pair(oif, orc, box, "fp32", (1, 100, 1000)):
+        res = check(g, o, "fp32", box.rho0, 64)
+        say(f"   step {k}: {fmt(res)}")
+        assert_ok(res, f"step {k}")
+
+
+@pytest.mark.parametrize("prec,bound", [("fp16", 5e-3), ("bf16", 5e-2)])
+def test_storage_forms_velocity_error(oif, orc, prec, bound):
+    """FP16 / BF16 storage of deviations: velocity error against the FP64
+    oracle on the channel case after 200 steps, relative to max |u|."""
+    say(f"[coupled] rbc393x10 channel {prec} storage")
+    box = synth.config_channel_rbc(200)
+    (k, g, o), = run_pair(oif, orc, box, prec, (200,))
+    e = {key: rel(g[key], o[key]) for key in ("u", "delta", "dX", "V")}
+    say(f"   step {k}: " + ", ".join(f"{a}={b:.2e}" for a, b in e.items()))
+    assert e["u"] <= bound
+
+
+def test_fp32_deterministic(oif):
+    """Fixed-point spreading makes the FP32 form bitwise reproducible."""
+    say("[determinism] rbc393x10 fp32 x2")
+    box = synth.config_channel_rbc(50)
+    outs = []
+    for _ in range(2):
+        ctx = oif.Context.from_box(box, precision="fp32")
+        ctx.step(50)
+        outs.append((ctx.read_populations(), *ctx.read_mesh(-1)))
+        ctx.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_watchdog_trips_on_divergent_friction(oif):
+    """The stated friction 1.5 diverges (explicit coupling); the watchdog
+    reports it instead of returning garbage."""
+    say("[watchdog] sphere642 friction 1.5")
+    box = synth.config_sphere_fp64(60)
+    box.friction = 1.5
+    ctx = oif.Context.from_box(box, precision="fp32")
+    with pytest.raises(oif.OifError) as ei:
+        for _ in range(12):
+            ctx.step(10)
+    assert ei.value.code == oif.E_NONFINITE
+    assert ctx.diagnostics().nonfinite == 1
+    ctx.close()
