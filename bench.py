@@ -47,7 +47,8 @@ def measure(oif, box, prec, steps, warmup, graph_steps=0, tune=None):
     t = ctx.step_timed(steps)
     info = ctx.info()
     out = dict(total_ms=t.total_ms, lb_ms=t.lb_ms, mesh_ms=t.mesh_ms, lb_block=info.lb_block,
-               mesh_block=info.mesh_block, xcd_remap=info.xcd_remap)
+               mesh_block=info.mesh_block, xcd_remap=info.xcd_remap, max_lds=info.max_lds,
+               lds_objects=info.lds_objects)
     if graph_steps:
         ctx.set_graph(graph_steps)
         ctx.step(2 * graph_steps)  # capture + warm

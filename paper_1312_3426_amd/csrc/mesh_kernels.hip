@@ -18,12 +18,68 @@
 //      nodes' mask bits set.
 // Meshes whose arrays do not fit in LDS use a per-object global scratch area
 // with the same layout.
+#include <limits.h>
+
 #include "device_common.h"
 
 namespace oif {
 namespace {
 
 using namespace dev;
+
+// Accumulation of the reaction force handed to the fluid.  FP32 forms: int64
+// fixed point with resolution 2^-e, so sums are exact and independent of the
+// order in which mesh nodes add (bitwise reproducible); FP64 form: FP64.
+template <int P>
+struct Acc {
+    typedef unsigned long long T;
+    __device__ static T convert(float v, double scale, unsigned& fl) {
+        const double a = (double)v * scale;
+        if (!(fabs(a) < 4.0e18)) {  // out of range or not finite
+            fl |= ST_OVERFLOW;
+            return 0ull;
+        }
+        return (T)__double2ll_rn(a);
+    }
+    __device__ static unsigned add(T* acc, float x, float y, float z, double scale) {
+        unsigned fl = 0;
+        const T a = convert(x, scale, fl), b = convert(y, scale, fl), c = convert(z, scale, fl);
+        atomicAdd(acc, a);
+        atomicAdd(acc + 1, b);
+        atomicAdd(acc + 2, c);
+        return fl;
+    }
+    __device__ static unsigned flush(const BoxDev* B, int q, T x, T y, T z) {
+        if ((x | y | z) == 0ull) return 0u;
+        T* G = (T*)B->G;
+        atomicAdd(G + q, x);
+        atomicAdd(G + B->N + q, y);
+        atomicAdd(G + 2 * B->N + q, z);
+        atomicOr(B->mask + (q >> 6), 1ull << (q & 63));
+        return 0u;
+    }
+};
+
+template <>
+struct Acc<PREC_FP64> {
+    typedef double T;
+    __device__ static T convert(double v, double, unsigned&) { return v; }
+    __device__ static unsigned add(T* acc, double x, double y, double z, double) {
+        atomicAdd(acc, x);
+        atomicAdd(acc + 1, y);
+        atomicAdd(acc + 2, z);
+        return 0u;
+    }
+    __device__ static unsigned flush(const BoxDev* B, int q, T x, T y, T z) {
+        if (x == 0.0 && y == 0.0 && z == 0.0) return 0u;
+        T* G = (T*)B->G;
+        atomicAdd(G + q, x);
+        atomicAdd(G + B->N + q, y);
+        atomicAdd(G + 2 * B->N + q, z);
+        atomicOr(B->mask + (q >> 6), 1ull << (q & 63));
+        return 0u;
+    }
+};
 
 template <int P, bool USE_LDS>
 __global__ void __launch_bounds__(1024)
@@ -37,15 +93,25 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
     const TmplDev<R>* __restrict__ T = O.t;
     const BoxDev* __restrict__ B = O.box;
     const int nv = T->nv, nt = T->nt, ne = T->ne;
-    const MeshLayout lay = mesh_layout(sizeof(R), nv, nt, ne);
+    const int ucap = T->ucap, ccap = T->ccap;
+    const MeshLayout lay = mesh_layout(sizeof(R), nv, nt, ne, ucap, ccap);
     unsigned char* base = USE_LDS ? smem : O.scratch;
     double* xs = (double*)base;       // [nv][3]
+    R* fs = (R*)(base + lay.fs);      // [nv][3]: elastic force
+    int* sb = (int*)(base + lay.sb);  // [nv][3]: lower stencil corner
     R* tn = (R*)(base + lay.tn);      // [nt][4]: unit inward normal, area
     R* tr = (R*)(base + lay.tr);      // [nt]: (S - S0)/S
     R* se = (R*)(base + lay.se);      // [ne]: ks kappa strain / L
     R* fh = (R*)(base + lay.fh);      // [ne]: kb (theta - theta0)/theta0
+    unsigned* need = (unsigned*)(base + lay.need);  // coupling phase: stencil-box bits
+    __shared__ int bbox[6];
+    __shared__ int ncomp;
 
     for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x) xs[k] = O.X[k];
+    if (threadIdx.x == 0) {
+        bbox[0] = bbox[1] = bbox[2] = INT_MAX;
+        bbox[3] = bbox[4] = bbox[5] = INT_MIN;
+    }
     __syncthreads();
 
     // 1. triangles
@@ -134,7 +200,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
     const int nxb = B->nx, nyb = B->ny, nzb = B->nz, Nb = B->N;
     const S* __restrict__ pop = (const S*)B->f[parity];
     const float inv = B->st_inv;
-    const R gx = (R)B->g[0], gy = (R)B->g[1], gz = (R)B->g[2];
+    const R gx_ = (R)B->g[0], gy_ = (R)B->g[1], gz_ = (R)B->g[2];
     const R rho0 = (R)B->rho0, xi = (R)B->xi;
     unsigned flags = 0;
 
@@ -186,47 +252,103 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
             Fz += ct * wz - vf * tn[4 * t + 2];
         }
 
-        // coupling: trilinear interpolation of the fluid velocity at the node
-        R vx = O.V[3 * v], vy = O.V[3 * v + 1], vz = O.V[3 * v + 2];
-        R dgx = 0, dgy = 0, dgz = 0;
+        fs[3 * v] = Fx;
+        fs[3 * v + 1] = Fy;
+        fs[3 * v + 2] = Fz;
+        // lower corner of the node's 2x2x2 stencil (unwrapped lattice index);
+        // nodes sit at cell centres, so the stencil starts at floor(x - 1/2)
         const double sx = px - 0.5, sy = py - 0.5, sz = pz - 0.5;
-        const bool ok = fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7;
-        if (!ok) {
-            flags |= ST_NONFINITE;  // no stencil for a non-finite or runaway node
+        if (fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7) {
+            const int bx = O.anchor[0] + (int)floor(sx);
+            const int by = O.anchor[1] + (int)floor(sy);
+            const int bz = O.anchor[2] + (int)floor(sz);
+            sb[3 * v] = bx;
+            sb[3 * v + 1] = by;
+            sb[3 * v + 2] = bz;
+            atomicMin(&bbox[0], bx); atomicMin(&bbox[1], by); atomicMin(&bbox[2], bz);
+            atomicMax(&bbox[3], bx); atomicMax(&bbox[4], by); atomicMax(&bbox[5], bz);
         } else {
-            const double flx = floor(sx), fly = floor(sy), flz = floor(sz);
-            const R phx = (R)(sx - flx), phy = (R)(sy - fly), phz = (R)(sz - flz);
-            int ix = (O.anchor[0] + (int)flx) % nxb;
-            ix += ix < 0 ? nxb : 0;
-            int iy = (O.anchor[1] + (int)fly) % nyb;
-            iy += iy < 0 ? nyb : 0;
-            const int ix1 = ix + 1 == nxb ? 0 : ix + 1;
-            const int iy1 = iy + 1 == nyb ? 0 : iy + 1;
-            int iz0, iz1;
-            const int izr = O.anchor[2] + (int)flz;
-            if (B->walls_z) {
-                iz0 = izr < 0 ? 0 : (izr >= nzb ? nzb - 1 : izr);
-                iz1 = izr + 1 < 0 ? 0 : (izr + 1 >= nzb ? nzb - 1 : izr + 1);
-                if (izr < 0 || izr + 1 >= nzb) flags |= ST_CLAMPED;
-            } else {
-                iz0 = izr % nzb;
-                iz0 += iz0 < 0 ? nzb : 0;
-                iz1 = iz0 + 1 == nzb ? 0 : iz0 + 1;
-            }
-            int q[8];
-            R w[8];
+            sb[3 * v] = INT_MIN;  // no stencil for a non-finite or runaway node
+            flags |= ST_NONFINITE;
+        }
+    }
+    __syncthreads();
+
+    // Coupling phase.  The object's stencil box (unwrapped lattice indices
+    // [o, o + e)) is kept in LDS when it fits: one bit per box node marks the
+    // nodes some stencil touches, those nodes are numbered compactly, the
+    // fluid velocity u = (sum_i n_i e_i + g/2)/rho is computed once per such
+    // node, and the reaction forces of all mesh nodes are summed per lattice
+    // node in LDS before one global atomic per node and component.
+    const int ox = bbox[0], oy = bbox[1], oz = bbox[2];
+    const long long exl = (long long)bbox[3] - ox + 2, eyl = (long long)bbox[4] - oy + 2,
+                    ezl = (long long)bbox[5] - oz + 2;
+    const bool grid = bbox[3] >= bbox[0] && exl * eyl * ezl <= (long long)ucap;
+    const int ex = (int)exl, exy = (int)(exl * eyl);
+    unsigned* pre = need + lay.nwords;             // exclusive popcount prefix per word
+    R* ug = (R*)(base + lay.ug);                   // [ccap][3] velocity at compact nodes
+    int* qn = (int*)(base + lay.qn);               // [ccap] lattice index of compact nodes
+    typedef typename Acc<P>::T A;
+    A* gacc = (A*)(base + lay.gacc);               // [ccap][3] summed reaction force
+    bool compact = false;
+    if (grid) {
+        const int vol = (int)(exl * eyl * ezl);
+        const int nw = (vol + 31) >> 5;
+        for (int k = threadIdx.x; k < nw; k += blockDim.x) need[k] = 0u;
+        __syncthreads();
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+            if (sb[3 * v] == INT_MIN) continue;
+            const int b0 = (sb[3 * v + 2] - oz) * exy + (sb[3 * v + 1] - oy) * ex + (sb[3 * v] - ox);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-                q[k] = ((dz ? iz1 : iz0) * nyb + (dy ? iy1 : iy)) * nxb + (dx ? ix1 : ix);
-                w[k] = (dx ? phx : R(1) - phx) * (dy ? phy : R(1) - phy) * (dz ? phz : R(1) - phz);
+                const int idx = b0 + (k >> 2) * exy + ((k >> 1) & 1) * ex + (k & 1);
+                atomicOr(&need[idx >> 5], 1u << (idx & 31));
             }
-            R ujx = 0, ujy = 0, ujz = 0;
-#pragma unroll 1
-            for (int k = 0; k < 8; ++k) {
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {  // wave 0: exclusive scan of the per-word popcounts
+            const int per = (nw + 63) >> 6;
+            const int w0 = threadIdx.x * per;
+            unsigned s = 0;
+            for (int k = w0; k < w0 + per && k < nw; ++k) s += __popc(need[k]);
+            unsigned incl = s;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const unsigned o = __shfl_up(incl, off, 64);
+                if ((int)threadIdx.x >= off) incl += o;
+            }
+            unsigned run = incl - s;
+            for (int k = w0; k < w0 + per && k < nw; ++k) {
+                pre[k] = run;
+                run += __popc(need[k]);
+            }
+            if (threadIdx.x == 63) ncomp = (int)incl;
+        }
+        __syncthreads();
+        compact = ncomp <= ccap;  // block-uniform
+        if (compact) {
+            for (int k = threadIdx.x; k < 3 * ncomp; k += blockDim.x) gacc[k] = A(0);
+            for (int idx = threadIdx.x; idx < vol; idx += blockDim.x) {
+                const unsigned word = need[idx >> 5];
+                if (!((word >> (idx & 31)) & 1u)) continue;
+                const int c = (int)(pre[idx >> 5] + __popc(word & ((1u << (idx & 31)) - 1u)));
+                int gx = (ox + idx % ex) % nxb;
+                gx += gx < 0 ? nxb : 0;
+                int gy = (oy + (idx / ex) % (int)eyl) % nyb;
+                gy += gy < 0 ? nyb : 0;
+                int gz = oz + idx / exy;
+                if (B->walls_z) {
+                    if (gz < 0 || gz >= nzb) flags |= ST_CLAMPED;
+                    gz = gz < 0 ? 0 : (gz >= nzb ? nzb - 1 : gz);
+                } else {
+                    gz %= nzb;
+                    gz += gz < 0 ? nzb : 0;
+                }
+                const int q = (gz * nyb + gy) * nxb + gx;
+                qn[c] = q;
                 R dd[19];
 #pragma unroll
-                for (int i = 0; i < 19; ++i) dd[i] = dec<P>(pop[(size_t)i * Nb + q[k]], inv);
+                for (int i = 0; i < 19; ++i) dd[i] = dec<P>(pop[(size_t)i * Nb + q], inv);
                 R dr = 0;
 #pragma unroll
                 for (int i = 0; i < 19; ++i) dr += dd[i];
@@ -234,49 +356,121 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
                 const R jy = dd[3] - dd[4] + dd[7] - dd[8] - dd[9] + dd[10] + dd[15] - dd[16] + dd[17] - dd[18];
                 const R jz = dd[5] - dd[6] + dd[11] - dd[12] - dd[13] + dd[14] + dd[15] - dd[16] - dd[17] + dd[18];
                 const R ir = R(1) / (rho0 + dr);
-                ujx += w[k] * ((jx + R(0.5) * gx) * ir);
-                ujy += w[k] * ((jy + R(0.5) * gy) * ir);
-                ujz += w[k] * ((jz + R(0.5) * gz) * ir);
+                ug[3 * c] = (jx + R(0.5) * gx_) * ir;
+                ug[3 * c + 1] = (jy + R(0.5) * gy_) * ir;
+                ug[3 * c + 2] = (jz + R(0.5) * gz_) * ir;
             }
-            // eq. dragforce: the fluid receives xi (v - u), the point its opposite
-            dgx = xi * (vx - ujx);
-            dgy = xi * (vy - ujy);
-            dgz = xi * (vz - ujz);
-#pragma unroll 1
+        }
+        __syncthreads();
+    }
+
+    // per mesh node: interpolate, drag, integrate, spread
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        const double px = xs[3 * v], py = xs[3 * v + 1], pz = xs[3 * v + 2];
+        R vx = O.V[3 * v], vy = O.V[3 * v + 1], vz = O.V[3 * v + 2];
+        R dgx = 0, dgy = 0, dgz = 0;
+        if (sb[3 * v] != INT_MIN) {
+            const double sx = px - 0.5, sy = py - 0.5, sz = pz - 0.5;
+            const R phx = (R)(sx - floor(sx)), phy = (R)(sy - floor(sy)), phz = (R)(sz - floor(sz));
+            R w[8];
+#pragma unroll
             for (int k = 0; k < 8; ++k) {
-                if (w[k] == R(0)) continue;
-                const R cxv = w[k] * dgx, cyv = w[k] * dgy, czv = w[k] * dgz;
-                if (P == PREC_FP64) {
-                    double* G = (double*)B->G;
-                    atomicAdd(G + q[k], (double)cxv);
-                    atomicAdd(G + Nb + q[k], (double)cyv);
-                    atomicAdd(G + 2 * Nb + q[k], (double)czv);
-                } else {
-                    const double s = B->fp_scale;
-                    const double ax = (double)cxv * s, ay = (double)cyv * s, az = (double)czv * s;
-                    const double lim = 4.0e18;
-                    if (!(fabs(ax) < lim && fabs(ay) < lim && fabs(az) < lim)) {
-                        flags |= ST_OVERFLOW;
-                        continue;
-                    }
-                    unsigned long long* G = (unsigned long long*)B->G;
-                    atomicAdd(G + q[k], (unsigned long long)__double2ll_rn(ax));
-                    atomicAdd(G + Nb + q[k], (unsigned long long)__double2ll_rn(ay));
-                    atomicAdd(G + 2 * Nb + q[k], (unsigned long long)__double2ll_rn(az));
+                const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+                w[k] = (dx ? phx : R(1) - phx) * (dy ? phy : R(1) - phy) * (dz ? phz : R(1) - phz);
+            }
+            if (compact) {
+                int cc[8];
+                const int b0 = (sb[3 * v + 2] - oz) * exy + (sb[3 * v + 1] - oy) * ex + (sb[3 * v] - ox);
+                R ujx = 0, ujy = 0, ujz = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int idx = b0 + (k >> 2) * exy + ((k >> 1) & 1) * ex + (k & 1);
+                    const unsigned word = need[idx >> 5];
+                    cc[k] = (int)(pre[idx >> 5] + __popc(word & ((1u << (idx & 31)) - 1u)));
+                    ujx += w[k] * ug[3 * cc[k]];
+                    ujy += w[k] * ug[3 * cc[k] + 1];
+                    ujz += w[k] * ug[3 * cc[k] + 2];
                 }
-                atomicOr(B->mask + (q[k] >> 6), 1ull << (q[k] & 63));
+                // eq. dragforce: the fluid receives xi (v - u), the point its opposite
+                dgx = xi * (vx - ujx);
+                dgy = xi * (vy - ujy);
+                dgz = xi * (vz - ujz);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (w[k] == R(0)) continue;
+                    flags |= Acc<P>::add(&gacc[3 * cc[k]], w[k] * dgx, w[k] * dgy, w[k] * dgz, B->fp_scale);
+                }
+            } else {
+                // stencil box too large for LDS: per-corner loads and atomics
+                int ix = sb[3 * v] % nxb;
+                ix += ix < 0 ? nxb : 0;
+                int iy = sb[3 * v + 1] % nyb;
+                iy += iy < 0 ? nyb : 0;
+                const int ix1 = ix + 1 == nxb ? 0 : ix + 1;
+                const int iy1 = iy + 1 == nyb ? 0 : iy + 1;
+                int iz0, iz1;
+                const int izr = sb[3 * v + 2];
+                if (B->walls_z) {
+                    iz0 = izr < 0 ? 0 : (izr >= nzb ? nzb - 1 : izr);
+                    iz1 = izr + 1 < 0 ? 0 : (izr + 1 >= nzb ? nzb - 1 : izr + 1);
+                    if (izr < 0 || izr + 1 >= nzb) flags |= ST_CLAMPED;
+                } else {
+                    iz0 = izr % nzb;
+                    iz0 += iz0 < 0 ? nzb : 0;
+                    iz1 = iz0 + 1 == nzb ? 0 : iz0 + 1;
+                }
+                int q[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+                    q[k] = ((dz ? iz1 : iz0) * nyb + (dy ? iy1 : iy)) * nxb + (dx ? ix1 : ix);
+                }
+                R ujx = 0, ujy = 0, ujz = 0;
+#pragma unroll 1
+                for (int k = 0; k < 8; ++k) {
+                    R dd[19];
+#pragma unroll
+                    for (int i = 0; i < 19; ++i) dd[i] = dec<P>(pop[(size_t)i * Nb + q[k]], inv);
+                    R dr = 0;
+#pragma unroll
+                    for (int i = 0; i < 19; ++i) dr += dd[i];
+                    const R jx = dd[1] - dd[2] + dd[7] - dd[8] + dd[9] - dd[10] + dd[11] - dd[12] + dd[13] - dd[14];
+                    const R jy = dd[3] - dd[4] + dd[7] - dd[8] - dd[9] + dd[10] + dd[15] - dd[16] + dd[17] - dd[18];
+                    const R jz = dd[5] - dd[6] + dd[11] - dd[12] - dd[13] + dd[14] + dd[15] - dd[16] - dd[17] + dd[18];
+                    const R ir = R(1) / (rho0 + dr);
+                    ujx += w[k] * ((jx + R(0.5) * gx_) * ir);
+                    ujy += w[k] * ((jy + R(0.5) * gy_) * ir);
+                    ujz += w[k] * ((jz + R(0.5) * gz_) * ir);
+                }
+                dgx = xi * (vx - ujx);
+                dgy = xi * (vy - ujy);
+                dgz = xi * (vz - ujz);
+#pragma unroll 1
+                for (int k = 0; k < 8; ++k) {
+                    if (w[k] == R(0)) continue;
+                    const typename Acc<P>::T ax = Acc<P>::convert(w[k] * dgx, B->fp_scale, flags);
+                    const typename Acc<P>::T ay = Acc<P>::convert(w[k] * dgy, B->fp_scale, flags);
+                    const typename Acc<P>::T az = Acc<P>::convert(w[k] * dgz, B->fp_scale, flags);
+                    flags |= Acc<P>::flush(B, q[k], ax, ay, az);
+                }
             }
         }
         // eq. newton, symplectic Euler: kick with the total force, then drift
-        vx += (Fx - dgx + O.fext[0]) * O.inv_mass;
-        vy += (Fy - dgy + O.fext[1]) * O.inv_mass;
-        vz += (Fz - dgz + O.fext[2]) * O.inv_mass;
+        vx += (fs[3 * v] - dgx + O.fext[0]) * O.inv_mass;
+        vy += (fs[3 * v + 1] - dgy + O.fext[1]) * O.inv_mass;
+        vz += (fs[3 * v + 2] - dgz + O.fext[2]) * O.inv_mass;
         O.V[3 * v] = vx;
         O.V[3 * v + 1] = vy;
         O.V[3 * v + 2] = vz;
         O.X[3 * v] = px + (double)vx;
         O.X[3 * v + 1] = py + (double)vy;
         O.X[3 * v + 2] = pz + (double)vz;
+    }
+    if (compact) {
+        // one global atomic per touched lattice node and component
+        __syncthreads();
+        for (int c = threadIdx.x; c < ncomp; c += blockDim.x)
+            flags |= Acc<P>::flush(B, qn[c], gacc[3 * c], gacc[3 * c + 1], gacc[3 * c + 2]);
     }
     if (flags) atomicOr(B->status, flags);
 }
@@ -316,8 +510,8 @@ hipError_t launch_mesh_p(const MeshLaunch& L) {
 
 }  // namespace
 
-size_t mesh_lds_bytes(int precision, int nv, int nt, int ne) {
-    return mesh_layout(precision == PREC_FP64 ? sizeof(double) : sizeof(float), nv, nt, ne).total;
+size_t mesh_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap) {
+    return mesh_layout(precision == PREC_FP64 ? sizeof(double) : sizeof(float), nv, nt, ne, ucap, ccap).total;
 }
 
 hipError_t launch_mesh(const MeshLaunch& L) {

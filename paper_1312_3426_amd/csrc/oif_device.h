@@ -60,22 +60,45 @@ struct TmplDev {
     const double* S0;      // [nt] (FP64: S - S0 cancels near the relaxed shape)
     double Sg0, V0;
     double ks, kb, kal, kag, kv;
+    int ucap;              // lattice nodes of the largest stencil box kept in LDS
+    int ccap;              // touched lattice nodes an object may have in LDS
 };
 
 // Per-object LDS (or global scratch) layout of the membrane kernel, R = the
-// arithmetic type: positions (FP64), per triangle the unit inward normal and
-// area (R x 4) and (S - S0)/S (R), per edge the stretching coefficient and the
-// bending magnitude (R each).
+// arithmetic type:
+//   xs  node positions, FP64 [nv][3]
+//   fs  elastic force per node, R [nv][3]
+//   sb  lower stencil corner per node (unwrapped lattice index), int [nv][3]
+//   then a region used twice:
+//     forces phase:  tn  unit inward normal + area per triangle, R [nt][4]
+//                    tr  (S - S0)/S per triangle, R [nt]
+//                    se  stretching coefficient per edge, R [ne]
+//                    fh  bending magnitude per edge, R [ne]
+//     coupling phase: need  one bit per node of the object's stencil box
+//                     pre   exclusive popcount prefix per bit word
+//                     ug    fluid velocity at the touched nodes, R [ccap][3]
+//                     qn    their lattice indices, int [ccap]
+//                     gacc  summed reaction force, 8-byte accumulators [ccap][3]
 struct MeshLayout {
-    size_t tn, tr, se, fh, total;
+    size_t fs, sb, tn, tr, se, fh, need, nwords, ug, qn, gacc, total;
 };
-__host__ __device__ inline MeshLayout mesh_layout(size_t r, int nv, int nt, int ne) {
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+__host__ __device__ inline MeshLayout mesh_layout(size_t r, int nv, int nt, int ne, int ucap, int ccap) {
     MeshLayout L;
-    L.tn = ((size_t)nv * 3 * sizeof(double) + 15) & ~(size_t)15;
+    L.fs = align16((size_t)nv * 3 * sizeof(double));
+    L.sb = align16(L.fs + (size_t)nv * 3 * r);
+    L.tn = align16(L.sb + (size_t)nv * 3 * sizeof(int));
     L.tr = L.tn + (size_t)nt * 4 * r;
-    L.se = (L.tr + (size_t)nt * r + 15) & ~(size_t)15;
+    L.se = align16(L.tr + (size_t)nt * r);
     L.fh = L.se + (size_t)ne * r;
-    L.total = L.fh + (size_t)ne * r;
+    const size_t end_forces = L.fh + (size_t)ne * r;
+    L.need = L.tn;
+    L.nwords = ((size_t)ucap + 31) / 32;
+    L.ug = align16(L.need + 2 * L.nwords * 4);
+    L.qn = L.ug + (size_t)ccap * 3 * r;
+    L.gacc = align16(L.qn + (size_t)ccap * 4);
+    const size_t end_coupling = L.gacc + (size_t)ccap * 3 * 8;
+    L.total = align16(end_forces > end_coupling ? end_forces : end_coupling);
     return L;
 }
 
@@ -118,7 +141,7 @@ struct MeshLaunch {
 hipError_t launch_mesh(const MeshLaunch& L);
 
 // Per-template LDS bytes of the mesh kernel.
-size_t mesh_lds_bytes(int precision, int nv, int nt, int ne);
+size_t mesh_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap);
 // Allow the LDS-resident mesh kernels to use up to `bytes` of dynamic LDS.
 hipError_t mesh_set_max_lds(size_t bytes);
 

@@ -21,7 +21,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/oif.h"
+#include "oif.h"
 #include "oif_device.h"
 
 using namespace oif;
@@ -41,6 +41,8 @@ struct Template {
     std::vector<double> L0, theta0, S0;
     double Sg0 = 0, V0 = 0;
     oif_moduli k{};
+    int ucap = 0; // lattice nodes of the largest stencil box an object can span
+    int ccap = 0; // touched lattice nodes an object may have (LDS capacity)
     std::vector<int> e_off, h_off, t_off;
     std::vector<std::array<int, 2>> e_inc;
     std::vector<int> h_inc, t_inc;
@@ -162,6 +164,22 @@ int build_template(const double* nodes, int nv, const int32_t* tris, int nt, con
         return OIF_E_MESH;
     }
     T.k = *k;
+    // Stencil box of an object: nodes within radius Rb of the centroid span at
+    // most ceil(2 Rb) + 2 lattice nodes per axis; two more allow for deformation.
+    {
+        double c[3] = {0, 0, 0}, rb = 0;
+        for (int v = 0; v < nv; ++v)
+            for (int a = 0; a < 3; ++a) c[a] += T.x[3 * v + a] / nv;
+        for (int v = 0; v < nv; ++v) {
+            double d[3];
+            vsub(&T.x[3 * v], c, d);
+            rb = std::max(rb, std::sqrt(vdot(d, d)));
+        }
+        const double side = std::ceil(2.0 * rb) + 4.0;
+        T.ucap = side * side * side < 1e6 ? (int)(side * side * side) : 1000000;
+        // touched nodes: a shell about two nodes thick around the surface
+        T.ccap = std::min(T.ucap, (int)std::ceil(4.0 * T.Sg0) + 128);
+    }
     // per-node incidence lists (CSR)
     std::vector<std::vector<std::array<int, 2>>> ei(nv);
     std::vector<std::vector<int>> hi(nv), ti(nv);
@@ -386,6 +404,8 @@ int upload_mesh_t(oif_ctx* c) {
         D.S0 = (const double*)(b + offs[11]);
         D.Sg0 = T.Sg0; D.V0 = T.V0;
         D.ks = T.k.ks; D.kb = T.k.kb; D.kal = T.k.kal; D.kag = T.k.kag; D.kv = T.k.kv;
+        D.ucap = T.ucap;
+        D.ccap = T.ccap;
     }
     int rc = dev_alloc(c, c->tmpl_dev, td.size() * sizeof(TmplDev<real>));
     if (rc) return rc;
@@ -409,12 +429,12 @@ int upload_mesh_t(oif_ctx* c) {
     HIPCALL(c, hipMemcpy(c->V_dev.p, vl.data(), n * sizeof(real), hipMemcpyHostToDevice));
 
     // objects sorted: LDS-resident first, each group largest mesh first
-    const size_t budget = c->max_lds > 512 ? c->max_lds - 512 : 0;
+    const size_t budget = c->max_lds;
     std::vector<int> order(c->obj.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     auto need = [&](int i) {
         const Template& T = c->tmpl[c->obj[i].tid];
-        return mesh_lds_bytes(c->d.precision, T.nv, T.nt, T.ne);
+        return mesh_lds_bytes(c->d.precision, T.nv, T.nt, T.ne, T.ucap, T.ccap);
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         const bool la = need(a) <= budget, lb = need(b) <= budget;
@@ -627,7 +647,10 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, d.device) == hipSuccess && lds > 0)
         c->max_lds = (size_t)lds;
-    if (mesh_set_max_lds(c->max_lds) != hipSuccess) c->max_lds = std::min<size_t>(c->max_lds, 65536);
+    // dynamic LDS budget of the membrane kernel: the device's per-workgroup
+    // limit minus room for the kernel's static LDS (reduction scratch)
+    c->max_lds = c->max_lds > 1024 ? c->max_lds - 1024 : 0;
+    if (mesh_set_max_lds(c->max_lds) != hipSuccess) c->max_lds = std::min<size_t>(c->max_lds, 65536 - 1024);
     (void)hipGetLastError();  // the opt-in result must not leak into the next launch check
     if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) return OIF_E_HIP;
     c->stream = c->own;
@@ -1261,7 +1284,7 @@ int batch_build(oif_batch* b) {
             const size_t tsz = b->precision == OIF_PREC_FP64 ? sizeof(TmplDev<double>) : sizeof(TmplDev<float>);
             const size_t tid = ((const unsigned char*)tptr - (const unsigned char*)c->tmpl_dev.p) / tsz;
             const Template& T = c->tmpl[tid];
-            ents.push_back({p, lds, T.nv, mesh_lds_bytes(b->precision, T.nv, T.nt, T.ne)});
+            ents.push_back({p, lds, T.nv, mesh_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap)});
         }
     }
     std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& c) {
