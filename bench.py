@@ -109,6 +109,11 @@ def main():
     ap.add_argument("--no-storage", action="store_true")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1312_3426_amd", "autotune.json"))
     ap.add_argument("--workload", default="precision", choices=["precision", "scale"])
+    ap.add_argument("--only", default=None, choices=["fp32", "fp16", "bf16"],
+                    help="measure one storage form only (short profiled runs)")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shapes, no autotuning")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run the plain copy kernel on BYTES bytes and print its bandwidth")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -116,6 +121,11 @@ def main():
         sys.exit(2)
 
     from paper_1312_3426_amd import oif, synth
+
+    if a.copy_probe:
+        g = oif.copy_bandwidth(a.copy_probe, reps=20)
+        print(json.dumps({"copy_bytes": a.copy_probe, "reps": 20, "GB/s": round(g, 1)}), flush=True)
+        return
 
     if a.workload == "precision":
         box = synth.config_precision(a.steps)
@@ -125,10 +135,15 @@ def main():
     log(f"[bench] workload {box.name}: N={N} M={M} steps={a.steps} warmup={a.warmup}")
 
     res = {}
-    for prec in ("fp32", "fp16", "bf16"):
+    for prec in ([a.only] if a.only else ["fp32", "fp16", "bf16"]):
         log(f"[bench] measuring {prec} storage")
-        res[prec] = measure(oif, box, prec, a.steps, a.warmup, graph_steps=50, tune=a.tune_cache)
+        res[prec] = measure(oif, box, prec, a.steps, a.warmup, graph_steps=0 if a.only else 50,
+                            tune=None if a.no_tune else a.tune_cache)
         log(f"[bench]   {prec}: {json.dumps(res[prec])}")
+    if "fp32" not in res:
+        return
+    copy_gbs = oif.copy_bandwidth(1 << 30, reps=20)
+    log(f"[bench] plain copy kernel, 1 GiB: {copy_gbs:.1f} GB/s")
 
     r32 = res["fp32"]
     ms_step = r32["total_ms"] / a.steps
@@ -158,7 +173,8 @@ def main():
         "kernel_ms": {"lb": round(r32["lb_ms"], 5), "mesh": round(r32["mesh_ms"], 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "lb_kernel<FP32>", "bytes_per_launch": lb_bytes},
+                     "kernel": "lb_kernel<FP32>", "bytes_per_launch": lb_bytes,
+                     "copy_kernel_GB/s": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "full_step": {"bytes": full_bytes, "touched_nodes": T, "GB/s": round(full_gbs, 1),
                       "frac": round(full_gbs / HBM_PEAK_GBS, 4)},
         "graph": {p: (round(N / (res[p]["graph_ms_per_step"] * 1e-3) / 1e6, 2) if "graph_ms_per_step" in res[p] else None)
@@ -166,6 +182,8 @@ def main():
         "storage": {},
     }
     for p in ("fp16", "bf16"):
+        if p not in res:
+            continue
         ms_p = res[p]["total_ms"] / a.steps
         lbb = 2 * 19 * BYTES_POP[p] * N
         line["storage"][p] = {"mlups": round(N / (ms_p * 1e-3) / 1e6, 2),

@@ -268,6 +268,15 @@ int oif_diagnostics(oif_ctx* ctx, oif_diag* d);
  * at the current positions (used for the byte model of the coupling). */
 int oif_touched_nodes(oif_ctx* ctx, long long* count);
 
+/* Measurement helper (not part of the method): bandwidth of a plain
+ * 16-byte-per-thread device copy of `bytes` bytes (rounded down to a multiple
+ * of 16) on `device`, averaged over `reps` launches, counting read plus write
+ * (2 * bytes per launch).  Allocates and frees two buffers.  This is the
+ * achievable-bandwidth reference for the lattice kernel's roofline and the
+ * known-size kernel for scaling HBM byte counters.
+ * Errors: OIF_E_ARG, OIF_E_UNSUPPORTED, OIF_E_NOMEM, OIF_E_HIP. */
+int oif_copy_bandwidth(int device, long long bytes, int reps, double* gbps);
+
 /* ---- batching form: many independent boxes advanced together --------------- */
 
 /* Bind n existing contexts (same precision and device) into a batch: every

@@ -231,9 +231,23 @@ __global__ void moments_kernel(const BoxDev* __restrict__ B, int parity, double*
     }
 }
 
+// plain streaming copy, 16 bytes per thread (bandwidth reference)
+__global__ void __launch_bounds__(256) copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                   size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 }  // namespace
 
-#define OIF_DISPATCH_P(prec, KER, grid, blk, s, ...)                                                 \
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const float4*)src,
+                       (float4*)dst, n);
+    return hipGetLastError();
+}
+
+#define OIF_DISPATCH_P(prec, KER, grid, blk, s, ...)                                               \
     switch (prec) {                                                                              \
         case PREC_FP64: hipLaunchKernelGGL(KER<PREC_FP64>, grid, blk, 0, s, __VA_ARGS__); break; \
         case PREC_FP32: hipLaunchKernelGGL(KER<PREC_FP32>, grid, blk, 0, s, __VA_ARGS__); break; \

@@ -154,6 +154,9 @@ hipError_t launch_diag_mesh(const void* objs, int nobj, int precision, double* p
                             hipStream_t s);
 hipError_t launch_diag_final(const double* partials, int nlat, int nmesh, double* out, hipStream_t s);
 
+// plain device-to-device copy kernel of `bytes` (a multiple of 16)
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
 // conversions between the storage form and canonical FP64 arrays
 hipError_t launch_pops_to_f64(const BoxDev* box_dev, int N, int precision, int parity, double* out,
                               hipStream_t s);

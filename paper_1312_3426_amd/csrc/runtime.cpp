@@ -1062,6 +1062,43 @@ int oif_diagnostics(oif_ctx* c, oif_diag* d) {
     return OIF_OK;
 }
 
+int oif_copy_bandwidth(int device, long long bytes, int reps, double* gbps) {
+    if (!gbps || bytes < 16 || reps < 1 || device < 0) return OIF_E_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return OIF_E_UNSUPPORTED;
+    if (hipSetDevice(device) != hipSuccess) return OIF_E_HIP;
+    const size_t n = (size_t)bytes & ~(size_t)15;
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, n) != hipSuccess) return OIF_E_NOMEM;
+    if (hipMalloc(&b, n) != hipSuccess) {
+        (void)hipFree(a);
+        return OIF_E_NOMEM;
+    }
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = OIF_OK;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess || hipMemsetAsync(a, 0, n, s) != hipSuccess ||
+        launch_copy(a, b, n, s) != hipSuccess || hipEventRecord(e0, s) != hipSuccess) {
+        rc = OIF_E_HIP;
+    } else {
+        for (int r = 0; r < reps && rc == OIF_OK; ++r)
+            if (launch_copy((r & 1) ? b : a, (r & 1) ? a : b, n, s) != hipSuccess) rc = OIF_E_HIP;
+        float ms = 0;
+        if (rc == OIF_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = OIF_E_HIP;
+        if (rc == OIF_OK) *gbps = 2.0 * (double)n * reps / (ms * 1e-3) / 1e9;
+    }
+    if (s) (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    return rc;
+}
+
 int oif_touched_nodes(oif_ctx* c, long long* count) {
     if (!c || !count) return OIF_E_ARG;
     int rc = pull_mesh(c);

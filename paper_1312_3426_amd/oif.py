@@ -98,6 +98,7 @@ SIGNATURES = {
     "oif_info": (_i, [_vp, _vp]),
     "oif_diagnostics": (_i, [_vp, _vp]),
     "oif_touched_nodes": (_i, [_vp, _vp]),
+    "oif_copy_bandwidth": (_i, [_i, _ll, _i, _vp]),
     "oif_batch_create": (_i, [_vp, _i, _vp]),
     "oif_batch_destroy": (_i, [_vp]),
     "oif_batch_step": (_i, [_vp, _i]),
@@ -131,6 +132,15 @@ def _p(a: Optional[np.ndarray]):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def copy_bandwidth(nbytes: int, reps: int = 20, device: int = 0) -> float:
+    """GB/s (read + write) of a plain device copy kernel: the achievable-bandwidth reference."""
+    v = C.c_double()
+    rc = lib().oif_copy_bandwidth(int(device), int(nbytes), int(reps), C.byref(v))
+    if rc != OIF_OK:
+        raise OifError(rc, "oif_copy_bandwidth failed")
+    return v.value
 
 
 def euler_to_rot(rx: float, ry: float, rz: float) -> np.ndarray:
