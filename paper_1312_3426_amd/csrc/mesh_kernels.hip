@@ -115,7 +115,9 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
     __syncthreads();
 
     // 1. triangles
-    double sarea = 0.0, svol = 0.0;
+    // (S - S0 is formed as (S^2 - S0^2)/(S + S0): the cancelling difference in
+    // FP64 multiply-adds, the square root and division in the arithmetic type)
+    double sdarea = 0.0, svol = 0.0;
     {
         const double r0x = xs[0], r0y = xs[1], r0z = xs[2];
         for (int t = threadIdx.x; t < nt; t += blockDim.x) {
@@ -128,21 +130,25 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
             const double nx_ = aby * acz - abz * acy;
             const double ny_ = abz * acx - abx * acz;
             const double nz_ = abx * acy - aby * acx;
-            const double len = sqrt(nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
-            const double S = 0.5 * len;
-            tn[4 * t + 0] = (R)(nx_ / len);
-            tn[4 * t + 1] = (R)(ny_ / len);
-            tn[4 * t + 2] = (R)(nz_ / len);
-            tn[4 * t + 3] = (R)S;
-            tr[t] = (R)((S - T->S0[t]) / S);
-            sarea += S;
+            const double n2 = nx_ * nx_ + ny_ * ny_ + nz_ * nz_;  // 4 S^2
+            const R len = sqrt((R)n2);
+            const R S = R(0.5) * len;
+            const double S0 = T->S0[t];
+            const R dS = (R)(0.25 * n2 - S0 * S0) / (S + (R)S0);
+            tn[4 * t + 0] = (R)nx_ / len;
+            tn[4 * t + 1] = (R)ny_ / len;
+            tn[4 * t + 2] = (R)nz_ / len;
+            tn[4 * t + 3] = S;
+            tr[t] = dS / S;
+            sdarea += (double)dS;
             // signed tetrahedron (node 0, a, b, c): inward orientation gives -6 V
             const double cxx = by * qz - bz * qy, cyy = bz * qx - bx * qz, czz = bx * qy - by * qx;
             svol -= (ax * cxx + ay * cyy + az * czz) / 6.0;
         }
     }
-    const double Sg = block_sum(sarea, red);
+    const double dSg = block_sum(sdarea, red);  // Sg - Sg0
     const double Vol = block_sum(svol, red);
+    const double Sg = T->Sg0 + dSg;
     if (threadIdx.x == 0 && O.geo) {
         O.geo[0] = Sg;
         O.geo[1] = Vol;
@@ -155,45 +161,46 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
             const int4 h = T->hinge[e];  // (A, B, C, D): the edge is B -> C
             const double dx = xs[3 * h.z] - xs[3 * h.y], dy = xs[3 * h.z + 1] - xs[3 * h.y + 1],
                          dz = xs[3 * h.z + 2] - xs[3 * h.y + 2];
-            const double L = sqrt(dx * dx + dy * dy + dz * dz);
+            const double L2 = dx * dx + dy * dy + dz * dz;
+            const double L = sqrt(L2);
             if (do_s) {
+                // strain (L - L0)/L0 = (L^2 - L0^2) / (L0 (L + L0))
                 const double L0 = T->L0[e];
-                const double strain = (L - L0) / L0;
-                double kap = 1.0;
+                const R strain = (R)(L2 - L0 * L0) / ((R)L0 * (R)(L + L0));
+                R kap = R(1);
                 if (!T->linear) {
-                    const double lam = L / L0, sl = sqrt(lam), l2 = lam * lam;
-                    kap = (sl + 1.0 / (l2 * sl)) / (lam + 1.0 / (l2 * lam));
+                    const R lam = R(1) + strain, sl = sqrt(lam), l2 = lam * lam;
+                    kap = (sl + R(1) / (l2 * sl)) / (lam + R(1) / (l2 * lam));
                 }
-                se[e] = (R)(T->ks * kap * strain / L);
+                se[e] = (R)T->ks * kap * strain / (R)L;
             }
             if (do_b) {
-                // inward unit normals of T1 = (A, B, C) and T2 = (D, C, B)
+                // normals of T1 = (A, B, C) and T2 = (D, C, B) (inward, unnormalised)
                 const double* pa = &xs[3 * h.x];
                 const double* pb = &xs[3 * h.y];
                 const double* pc = &xs[3 * h.z];
                 const double* pd = &xs[3 * h.w];
                 const double u1x = pb[0] - pa[0], u1y = pb[1] - pa[1], u1z = pb[2] - pa[2];
                 const double v1x = pc[0] - pa[0], v1y = pc[1] - pa[1], v1z = pc[2] - pa[2];
-                double n1x = u1y * v1z - u1z * v1y, n1y = u1z * v1x - u1x * v1z, n1z = u1x * v1y - u1y * v1x;
+                const double n1x = u1y * v1z - u1z * v1y, n1y = u1z * v1x - u1x * v1z, n1z = u1x * v1y - u1y * v1x;
                 const double u2x = pc[0] - pd[0], u2y = pc[1] - pd[1], u2z = pc[2] - pd[2];
                 const double v2x = pb[0] - pd[0], v2y = pb[1] - pd[1], v2z = pb[2] - pd[2];
-                double n2x = u2y * v2z - u2z * v2y, n2y = u2z * v2x - u2x * v2z, n2z = u2x * v2y - u2y * v2x;
-                const double i1 = 1.0 / sqrt(n1x * n1x + n1y * n1y + n1z * n1z);
-                const double i2 = 1.0 / sqrt(n2x * n2x + n2y * n2y + n2z * n2z);
-                n1x *= i1; n1y *= i1; n1z *= i1;
-                n2x *= i2; n2y *= i2; n2z *= i2;
+                const double n2x = u2y * v2z - u2z * v2y, n2y = u2z * v2x - u2x * v2z, n2z = u2x * v2y - u2y * v2x;
                 const double mx = n1y * n2z - n1z * n2y, my = n1z * n2x - n1x * n2z, mz = n1x * n2y - n1y * n2x;
-                // inner dihedral angle: pi when flat, below pi on a convex ridge
-                const double theta = 3.14159265358979323846 +
-                                     atan2((mx * dx + my * dy + mz * dz) / L, n1x * n2x + n1y * n2y + n1z * n2z);
-                const double th0 = T->theta0[e];
-                fh[e] = (R)(T->kb * (theta - th0) / th0);
+                // theta - pi = atan2((m . e), n1 . n2) for the unit vectors; the
+                // difference to theta0 - pi is the angle of the relative rotation,
+                // atan2(sin d, cos d), every term scaled by |N1| |N2| L > 0
+                const double md = mx * dx + my * dy + mz * dz;
+                const double dot = n1x * n2x + n1y * n2y + n1z * n2z;
+                const double2 cs = T->cs0[e];  // cos, sin of theta0 - pi
+                const R dth = atan2((R)(md * cs.x - dot * L * cs.y), (R)(dot * L * cs.x + md * cs.y));
+                fh[e] = (R)T->kb * dth / (R)T->theta0[e];
             }
         }
     }
     __syncthreads();
 
-    const R cg = (R)(-T->kag * (Sg - T->Sg0) / Sg);   // global area coefficient
+    const R cg = (R)(-T->kag * dSg / Sg);             // global area coefficient
     const R cv = (R)(-T->kv * (Vol - T->V0) / T->V0); // volume coefficient
     const R kal = (R)T->kal;
     const R third = R(1) / R(3);

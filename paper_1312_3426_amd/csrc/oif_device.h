@@ -54,7 +54,8 @@ struct TmplDev {
     const int* h_inc;      // hinge id << 2 | role (0 = A, 1 = B, 2 = C, 3 = D)
     const int4* hinge;     // (A, B, C, D): T1 = (A, B, C) runs B -> C, T2 has wing D
     const int2* hinge_tri; // (T1, T2)
-    const double* theta0;  // [ne] (FP64: theta - theta0 cancels near the relaxed shape)
+    const double* theta0;  // [ne] relaxed inner dihedral angle
+    const double2* cs0;    // [ne] cos and sin of theta0 - pi (FP64)
     const int* t_off;      // [nv + 1] incident triangles of each node
     const int* t_inc;      // triangle id << 2 | slot
     const double* S0;      // [nt] (FP64: S - S0 cancels near the relaxed shape)

@@ -362,6 +362,11 @@ int upload_mesh_t(oif_ctx* c) {
         const std::vector<double>& L0 = T.L0;
         const std::vector<double>& S0 = T.S0;
         const std::vector<double>& th = T.theta0;
+        std::vector<double> cs0(2 * (size_t)T.ne);  // cos, sin of theta0 - pi
+        for (int e = 0; e < T.ne; ++e) {
+            cs0[2 * e] = std::cos(T.theta0[e] - M_PI);
+            cs0[2 * e + 1] = std::sin(T.theta0[e] - M_PI);
+        }
         std::vector<int4> hv(T.ne);
         std::vector<int2> ht(T.ne), einc(T.e_inc.size());
         for (int e = 0; e < T.ne; ++e) {
@@ -374,7 +379,8 @@ int upload_mesh_t(oif_ctx* c) {
                  {T.h_off.data(), T.h_off.size() * 4},   {T.h_inc.data(), T.h_inc.size() * 4},
                  {hv.data(), hv.size() * 16},            {ht.data(), ht.size() * 8},
                  {th.data(), th.size() * sizeof(double)}, {T.t_off.data(), T.t_off.size() * 4},
-                 {T.t_inc.data(), T.t_inc.size() * 4},   {S0.data(), S0.size() * sizeof(double)}};
+                 {T.t_inc.data(), T.t_inc.size() * 4},   {S0.data(), S0.size() * sizeof(double)},
+                 {cs0.data(), cs0.size() * sizeof(double)}};
         std::vector<size_t> offs;
         size_t total = 0;
         for (auto& p : parts) {
@@ -402,6 +408,7 @@ int upload_mesh_t(oif_ctx* c) {
         D.t_off = (const int*)(b + offs[9]);
         D.t_inc = (const int*)(b + offs[10]);
         D.S0 = (const double*)(b + offs[11]);
+        D.cs0 = (const double2*)(b + offs[12]);
         D.Sg0 = T.Sg0; D.V0 = T.V0;
         D.ks = T.k.ks; D.kb = T.k.kb; D.kal = T.k.kal; D.kag = T.k.kag; D.kv = T.k.kv;
         D.ucap = T.ucap;
