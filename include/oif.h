@@ -127,6 +127,7 @@ typedef struct {
     int graph_steps;    /* steps per captured hipGraph, 0 = eager launches */
     long long max_lds;  /* LDS bytes per workgroup available to the membrane kernel */
     int lds_objects;    /* objects whose mesh is staged in LDS (the rest use global scratch) */
+    int overlap;        /* 1 if untouched nodes are updated concurrently with the membrane kernel */
 } oif_info_t;
 
 /* FP64 conservation diagnostics and watchdog state. */
@@ -139,13 +140,19 @@ typedef struct {
     int overflow;             /* non-zero if a coupling force was out of fixed-point range */
 } oif_diag;
 
-/* Timing of one oif_step_timed call (HIP events on the context's stream). */
+/* Timing of one oif_step_timed call (HIP events on the streams the kernels run
+ * on).  With overlap (see oif_set_overlap) lb_ms is the lattice launch over the
+ * untouched nodes, which runs concurrently with the membrane kernel, and
+ * lb_touched_ms the launch over the touched nodes after it. */
 typedef struct {
-    double total_ms;     /* first launch to last launch of the call */
-    double lb_ms;        /* average duration of one lattice kernel launch */
-    double mesh_ms;      /* average duration of one membrane/coupling kernel launch */
+    double total_ms;      /* first launch to last launch of the call */
+    double lb_ms;         /* average duration of one lattice kernel launch */
+    double mesh_ms;       /* average duration of one membrane/coupling kernel launch */
     int lb_launches;
     int mesh_launches;
+    double lb_touched_ms; /* overlap only: lattice launch over the touched nodes */
+    double mark_ms;       /* overlap only: marking of the touched nodes */
+    int overlap;          /* 1 if the steps ran overlapped */
 } oif_timing;
 
 /* ---- lattice -------------------------------------------------------------- */
@@ -221,6 +228,13 @@ int oif_step_timed(oif_ctx* ctx, int n_steps, oif_timing* t);
 /* Graph mode: steps_per_graph > 0 captures that many steps (rounded up to an
  * even number) in one hipGraph and replays it; 0 launches eagerly. */
 int oif_set_graph(oif_ctx* ctx, int steps_per_graph);
+
+/* Overlap (default on): each step first marks the lattice nodes inside any
+ * mesh node's 2x2x2 stencil; the lattice update of all other nodes (which no
+ * coupling force can reach) then runs on a second stream concurrently with the
+ * membrane/coupling kernel, and the marked nodes are updated after it.  The
+ * result is identical to the sequential order; 0 runs the step sequentially. */
+int oif_set_overlap(oif_ctx* ctx, int on);
 
 /* Launch shapes: lb_block in {64,128,256,512,1024}, mesh_block in
  * {64,128,256,512,1024}; xcd_remap 0/1 maps consecutive lattice blocks to the

@@ -90,5 +90,25 @@ __device__ inline double block_sum(double v, double* red) {
     return tot;
 }
 
+// Merge per-lane integer bounds [lo, hi] (3 axes) into the block's bbox[6]
+// (lo in 0..2, hi in 3..5): reduced inside the wave by shuffles, then one LDS
+// atomic per wave and axis instead of one per lane (same-address atomics
+// serialise).  All lanes of each wave must call it.
+__device__ inline void wave_bbox_to_block(int lo[3], int hi[3], int* bbox) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = min(lo[c], __shfl_xor(lo[c], off, 64));
+            hi[c] = max(hi[c], __shfl_xor(hi[c], off, 64));
+        }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            atomicMin(&bbox[c], lo[c]);
+            atomicMax(&bbox[3 + c], hi[c]);
+        }
+}
+
 }  // namespace dev
 }  // namespace oif

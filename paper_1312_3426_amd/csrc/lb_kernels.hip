@@ -23,7 +23,7 @@ using namespace dev;
 template <int P>
 __global__ void __launch_bounds__(1024)
 lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int nblocks, int parity,
-          int remap) {
+          int remap, int mode) {
     typedef typename Prec<P>::S S;
     typedef typename Prec<P>::R R;
     int bid = blockIdx.x;
@@ -47,34 +47,52 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
     S* __restrict__ dst = (S*)B->f[parity ^ 1];
     const float inv = B->st_inv, scale = B->st_scale;
 
-    // force density: body force plus the coupling force where the mask says so
+    // Force density: body force plus the coupling force G where the node's mask
+    // bit is set.  Mask and touch words cover exactly one wave's 64 nodes; all
+    // lanes load a word before the wave's first lane clears it.
     R fx = (R)B->g[0], fy = (R)B->g[1], fz = (R)B->g[2];
     unsigned long long* mk = B->mask + (p >> 6);
-    const unsigned long long m = *mk;
-    if (m) {
-        if ((m >> (p & 63)) & 1ull) {
-            if (P == PREC_FP64) {
-                double* G = (double*)B->G;
-                fx += (R)G[p];
-                fy += (R)G[N + p];
-                fz += (R)G[2 * N + p];
-                G[p] = 0.0;
-                G[N + p] = 0.0;
-                G[2 * N + p] = 0.0;
-            } else {
-                long long* G = (long long*)B->G;
-                const double s = B->fp_inv;
-                fx += (R)((double)G[p] * s);
-                fy += (R)((double)G[N + p] * s);
-                fz += (R)((double)G[2 * N + p] * s);
-                G[p] = 0;
-                G[N + p] = 0;
-                G[2 * N + p] = 0;
+    unsigned long long m = 0ull;
+    if (mode == LB_ALL) {
+        m = *mk;
+        if (m && (p & 63) == 0) *mk = 0ull;
+    } else {
+        // split update: untouched nodes run while the membrane kernel spreads,
+        // touched nodes (inside some stencil of this step) after it
+        unsigned long long* tw = B->touch + (p >> 6);
+        const unsigned long long tb = *tw;
+        const bool mine = (tb >> (p & 63)) & 1ull;
+        if (mode == LB_FREE) {
+            if (mine) return;  // a coupling force can reach only touched nodes
+        } else {
+            if (tb == 0ull) return;  // the whole wave is untouched
+            m = *mk;
+            if ((p & 63) == 0) {
+                *tw = 0ull;
+                if (m) *mk = 0ull;
             }
+            if (!mine) return;
         }
-        // the word covers exactly this wave's 64 nodes, and every lane has
-        // already loaded it: its first lane clears it
-        if ((p & 63) == 0) *mk = 0ull;
+    }
+    if ((m >> (p & 63)) & 1ull) {
+        if (P == PREC_FP64) {
+            double* G = (double*)B->G;
+            fx += (R)G[p];
+            fy += (R)G[N + p];
+            fz += (R)G[2 * N + p];
+            G[p] = 0.0;
+            G[N + p] = 0.0;
+            G[2 * N + p] = 0.0;
+        } else {
+            long long* G = (long long*)B->G;
+            const double s = B->fp_inv;
+            fx += (R)((double)G[p] * s);
+            fy += (R)((double)G[N + p] * s);
+            fz += (R)((double)G[2 * N + p] * s);
+            G[p] = 0;
+            G[N + p] = 0;
+            G[2 * N + p] = 0;
+        }
     }
 
     R d[19];
@@ -258,7 +276,7 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
 
 hipError_t launch_lb(const LbLaunch& L) {
     OIF_DISPATCH_P(L.precision, lb_kernel, dim3(L.nblocks), dim3(L.block), L.stream, L.boxes, L.work,
-                   L.nblocks, L.parity, L.remap);
+                   L.nblocks, L.parity, L.remap, L.mode);
     return hipGetLastError();
 }
 

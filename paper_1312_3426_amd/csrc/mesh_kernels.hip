@@ -210,6 +210,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
     const R gx_ = (R)B->g[0], gy_ = (R)B->g[1], gz_ = (R)B->g[2];
     const R rho0 = (R)B->rho0, xi = (R)B->xi;
     unsigned flags = 0;
+    int blo[3] = {INT_MAX, INT_MAX, INT_MAX}, bhi[3] = {INT_MIN, INT_MIN, INT_MIN};
 
     // 3. nodes
     for (int v = threadIdx.x; v < nv; v += blockDim.x) {
@@ -272,13 +273,14 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
             sb[3 * v] = bx;
             sb[3 * v + 1] = by;
             sb[3 * v + 2] = bz;
-            atomicMin(&bbox[0], bx); atomicMin(&bbox[1], by); atomicMin(&bbox[2], bz);
-            atomicMax(&bbox[3], bx); atomicMax(&bbox[4], by); atomicMax(&bbox[5], bz);
+            blo[0] = min(blo[0], bx); blo[1] = min(blo[1], by); blo[2] = min(blo[2], bz);
+            bhi[0] = max(bhi[0], bx); bhi[1] = max(bhi[1], by); bhi[2] = max(bhi[2], bz);
         } else {
             sb[3 * v] = INT_MIN;  // no stencil for a non-finite or runaway node
             flags |= ST_NONFINITE;
         }
     }
+    wave_bbox_to_block(blo, bhi, bbox);
     __syncthreads();
 
     // Coupling phase.  The object's stencil box (unwrapped lattice indices
@@ -306,8 +308,11 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
         for (int v = threadIdx.x; v < nv; v += blockDim.x) {
             if (sb[3 * v] == INT_MIN) continue;
             const int b0 = (sb[3 * v + 2] - oz) * exy + (sb[3 * v + 1] - oy) * ex + (sb[3 * v] - ox);
+            // corners in a lane-rotated order: lanes whose nodes share a cell
+            // then hit different words in the same instruction
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int kk = 0; kk < 8; ++kk) {
+                const int k = (kk + (int)threadIdx.x) & 7;
                 const int idx = b0 + (k >> 2) * exy + ((k >> 1) & 1) * ex + (k & 1);
                 atomicOr(&need[idx >> 5], 1u << (idx & 31));
             }
@@ -379,33 +384,37 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
         if (sb[3 * v] != INT_MIN) {
             const double sx = px - 0.5, sy = py - 0.5, sz = pz - 0.5;
             const R phx = (R)(sx - floor(sx)), phy = (R)(sy - floor(sy)), phz = (R)(sz - floor(sz));
-            R w[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-                w[k] = (dx ? phx : R(1) - phx) * (dy ? phy : R(1) - phy) * (dz ? phz : R(1) - phz);
-            }
             if (compact) {
-                int cc[8];
+                // corners in an order rotated by the node index (the same for
+                // any block size): lanes whose nodes share a cell then add to
+                // different LDS accumulators in the same instruction; the
+                // integer sums do not depend on the order
+                const int rot = v & 7;
                 const int b0 = (sb[3 * v + 2] - oz) * exy + (sb[3 * v + 1] - oy) * ex + (sb[3 * v] - ox);
+                int cr[8];
+                R wr[8];
                 R ujx = 0, ujy = 0, ujz = 0;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int idx = b0 + (k >> 2) * exy + ((k >> 1) & 1) * ex + (k & 1);
+                for (int kk = 0; kk < 8; ++kk) {
+                    const int k = (kk + rot) & 7;
+                    const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+                    wr[kk] = (dx ? phx : R(1) - phx) * (dy ? phy : R(1) - phy) * (dz ? phz : R(1) - phz);
+                    const int idx = b0 + dz * exy + dy * ex + dx;
                     const unsigned word = need[idx >> 5];
-                    cc[k] = (int)(pre[idx >> 5] + __popc(word & ((1u << (idx & 31)) - 1u)));
-                    ujx += w[k] * ug[3 * cc[k]];
-                    ujy += w[k] * ug[3 * cc[k] + 1];
-                    ujz += w[k] * ug[3 * cc[k] + 2];
+                    cr[kk] = (int)(pre[idx >> 5] + __popc(word & ((1u << (idx & 31)) - 1u)));
+                    ujx += wr[kk] * ug[3 * cr[kk]];
+                    ujy += wr[kk] * ug[3 * cr[kk] + 1];
+                    ujz += wr[kk] * ug[3 * cr[kk] + 2];
                 }
                 // eq. dragforce: the fluid receives xi (v - u), the point its opposite
                 dgx = xi * (vx - ujx);
                 dgy = xi * (vy - ujy);
                 dgz = xi * (vz - ujz);
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    if (w[k] == R(0)) continue;
-                    flags |= Acc<P>::add(&gacc[3 * cc[k]], w[k] * dgx, w[k] * dgy, w[k] * dgz, B->fp_scale);
+                for (int kk = 0; kk < 8; ++kk) {
+                    if (wr[kk] == R(0)) continue;
+                    flags |= Acc<P>::add(&gacc[3 * cr[kk]], wr[kk] * dgx, wr[kk] * dgy, wr[kk] * dgz,
+                                         B->fp_scale);
                 }
             } else {
                 // stencil box too large for LDS: per-corner loads and atomics
@@ -426,18 +435,14 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
                     iz0 += iz0 < 0 ? nzb : 0;
                     iz1 = iz0 + 1 == nzb ? 0 : iz0 + 1;
                 }
-                int q[8];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
-                    q[k] = ((dz ? iz1 : iz0) * nyb + (dy ? iy1 : iy)) * nxb + (dx ? ix1 : ix);
-                }
                 R ujx = 0, ujy = 0, ujz = 0;
 #pragma unroll 1
                 for (int k = 0; k < 8; ++k) {
                     R dd[19];
+                    const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+                    const int qk = ((dz ? iz1 : iz0) * nyb + (dy ? iy1 : iy)) * nxb + (dx ? ix1 : ix);
 #pragma unroll
-                    for (int i = 0; i < 19; ++i) dd[i] = dec<P>(pop[(size_t)i * Nb + q[k]], inv);
+                    for (int i = 0; i < 19; ++i) dd[i] = dec<P>(pop[(size_t)i * Nb + qk], inv);
                     R dr = 0;
 #pragma unroll
                     for (int i = 0; i < 19; ++i) dr += dd[i];
@@ -445,20 +450,24 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
                     const R jy = dd[3] - dd[4] + dd[7] - dd[8] - dd[9] + dd[10] + dd[15] - dd[16] + dd[17] - dd[18];
                     const R jz = dd[5] - dd[6] + dd[11] - dd[12] - dd[13] + dd[14] + dd[15] - dd[16] - dd[17] + dd[18];
                     const R ir = R(1) / (rho0 + dr);
-                    ujx += w[k] * ((jx + R(0.5) * gx_) * ir);
-                    ujy += w[k] * ((jy + R(0.5) * gy_) * ir);
-                    ujz += w[k] * ((jz + R(0.5) * gz_) * ir);
+                    const R wk = (dx ? phx : R(1) - phx) * (dy ? phy : R(1) - phy) * (dz ? phz : R(1) - phz);
+                    ujx += wk * ((jx + R(0.5) * gx_) * ir);
+                    ujy += wk * ((jy + R(0.5) * gy_) * ir);
+                    ujz += wk * ((jz + R(0.5) * gz_) * ir);
                 }
                 dgx = xi * (vx - ujx);
                 dgy = xi * (vy - ujy);
                 dgz = xi * (vz - ujz);
 #pragma unroll 1
                 for (int k = 0; k < 8; ++k) {
-                    if (w[k] == R(0)) continue;
-                    const typename Acc<P>::T ax = Acc<P>::convert(w[k] * dgx, B->fp_scale, flags);
-                    const typename Acc<P>::T ay = Acc<P>::convert(w[k] * dgy, B->fp_scale, flags);
-                    const typename Acc<P>::T az = Acc<P>::convert(w[k] * dgz, B->fp_scale, flags);
-                    flags |= Acc<P>::flush(B, q[k], ax, ay, az);
+                    const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
+                    const R wk = (dx ? phx : R(1) - phx) * (dy ? phy : R(1) - phy) * (dz ? phz : R(1) - phz);
+                    if (wk == R(0)) continue;
+                    const typename Acc<P>::T ax = Acc<P>::convert(wk * dgx, B->fp_scale, flags);
+                    const typename Acc<P>::T ay = Acc<P>::convert(wk * dgy, B->fp_scale, flags);
+                    const typename Acc<P>::T az = Acc<P>::convert(wk * dgz, B->fp_scale, flags);
+                    const int qk = ((dz ? iz1 : iz0) * nyb + (dy ? iy1 : iy)) * nxb + (dx ? ix1 : ix);
+                    flags |= Acc<P>::flush(B, qk, ax, ay, az);
                 }
             }
         }
@@ -480,6 +489,88 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
             flags |= Acc<P>::flush(B, qn[c], gacc[3 * c], gacc[3 * c + 1], gacc[3 * c + 2]);
     }
     if (flags) atomicOr(B->status, flags);
+}
+
+// Touch bits of this step: every lattice node inside the 2x2x2 stencil of a mesh
+// node (the nodes the membrane kernel will read populations from and spread
+// to).  One workgroup per object; the object's stencil box is marked in an LDS
+// bitmask first, so each touched node costs one global atomic, not one per
+// corner.  Oversize boxes fall back to per-corner atomics.
+template <typename R>
+__global__ void __launch_bounds__(256) mark_kernel(const ObjDev<R>* __restrict__ objs) {
+    extern __shared__ unsigned bits[];
+    __shared__ int bbox[6];
+    const ObjDev<R>& O = objs[blockIdx.x];
+    const TmplDev<R>* __restrict__ T = O.t;
+    const BoxDev* __restrict__ B = O.box;
+    const int nv = T->nv;
+    const int nxb = B->nx, nyb = B->ny, nzb = B->nz;
+    if (threadIdx.x == 0) {
+        bbox[0] = bbox[1] = bbox[2] = INT_MAX;
+        bbox[3] = bbox[4] = bbox[5] = INT_MIN;
+    }
+    __syncthreads();
+    int blo[3] = {INT_MAX, INT_MAX, INT_MAX}, bhi[3] = {INT_MIN, INT_MIN, INT_MIN};
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        const double sx = O.X[3 * v] - 0.5, sy = O.X[3 * v + 1] - 0.5, sz = O.X[3 * v + 2] - 0.5;
+        if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
+        const int bx = O.anchor[0] + (int)floor(sx), by = O.anchor[1] + (int)floor(sy),
+                  bz = O.anchor[2] + (int)floor(sz);
+        blo[0] = min(blo[0], bx); blo[1] = min(blo[1], by); blo[2] = min(blo[2], bz);
+        bhi[0] = max(bhi[0], bx); bhi[1] = max(bhi[1], by); bhi[2] = max(bhi[2], bz);
+    }
+    wave_bbox_to_block(blo, bhi, bbox);
+    __syncthreads();
+    const int ox = bbox[0], oy = bbox[1], oz = bbox[2];
+    const long long exl = (long long)bbox[3] - ox + 2, eyl = (long long)bbox[4] - oy + 2,
+                    ezl = (long long)bbox[5] - oz + 2;
+    if (bbox[3] < bbox[0]) return;  // no finite node (block-uniform)
+    auto lattice_index = [&](int gx, int gy, int gz) {
+        gx %= nxb;
+        gx += gx < 0 ? nxb : 0;
+        gy %= nyb;
+        gy += gy < 0 ? nyb : 0;
+        if (B->walls_z) {
+            gz = gz < 0 ? 0 : (gz >= nzb ? nzb - 1 : gz);
+        } else {
+            gz %= nzb;
+            gz += gz < 0 ? nzb : 0;
+        }
+        return (gz * nyb + gy) * nxb + gx;
+    };
+    if (exl * eyl * ezl <= (long long)T->ucap) {
+        const int ex = (int)exl, exy = (int)(exl * eyl), vol = (int)(exl * eyl * ezl);
+        for (int k = threadIdx.x; k < (vol + 31) / 32; k += blockDim.x) bits[k] = 0u;
+        __syncthreads();
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+            const double sx = O.X[3 * v] - 0.5, sy = O.X[3 * v + 1] - 0.5, sz = O.X[3 * v + 2] - 0.5;
+            if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
+            const int b0 = (O.anchor[2] + (int)floor(sz) - oz) * exy + (O.anchor[1] + (int)floor(sy) - oy) * ex +
+                           (O.anchor[0] + (int)floor(sx) - ox);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int idx = b0 + (k >> 2) * exy + ((k >> 1) & 1) * ex + (k & 1);
+                atomicOr(&bits[idx >> 5], 1u << (idx & 31));
+            }
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < vol; idx += blockDim.x) {
+            if (!((bits[idx >> 5] >> (idx & 31)) & 1u)) continue;
+            const int q = lattice_index(ox + idx % ex, oy + (idx / ex) % (int)eyl, oz + idx / exy);
+            atomicOr(B->touch + (q >> 6), 1ull << (q & 63));
+        }
+    } else {
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+            const double sx = O.X[3 * v] - 0.5, sy = O.X[3 * v + 1] - 0.5, sz = O.X[3 * v + 2] - 0.5;
+            if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
+            const int bx = O.anchor[0] + (int)floor(sx), by = O.anchor[1] + (int)floor(sy),
+                      bz = O.anchor[2] + (int)floor(sz);
+            for (int k = 0; k < 8; ++k) {
+                const int q = lattice_index(bx + (k & 1), by + ((k >> 1) & 1), bz + (k >> 2));
+                atomicOr(B->touch + (q >> 6), 1ull << (q & 63));
+            }
+        }
+    }
 }
 
 template <typename R>
@@ -542,6 +633,15 @@ hipError_t mesh_set_max_lds(size_t bytes) {
         if (r != hipSuccess) e = r;
     }
     return e;
+}
+
+hipError_t launch_mark(const void* objs, int nobj, int precision, size_t lds_bytes, hipStream_t s) {
+    if (nobj <= 0) return hipSuccess;
+    if (precision == PREC_FP64)
+        hipLaunchKernelGGL(mark_kernel<double>, dim3(nobj), dim3(256), lds_bytes, s, (const ObjDev<double>*)objs);
+    else
+        hipLaunchKernelGGL(mark_kernel<float>, dim3(nobj), dim3(256), lds_bytes, s, (const ObjDev<float>*)objs);
+    return hipGetLastError();
 }
 
 hipError_t launch_diag_mesh(const void* objs, int nobj, int precision, double* partials, hipStream_t s) {

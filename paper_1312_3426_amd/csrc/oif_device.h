@@ -9,10 +9,11 @@
 //          point with resolution 2^-e (FP32 forms, order-independent sums)
 //   mask   one bit per node, set where G is non-zero; the lattice kernel reads
 //          G only where a bit is set and clears both
-//   X, V   mesh node positions (object-local, relative to an integer lattice
-//          anchor of the object; FP64 in every form, so that edge lengths
-//          and areas near their relaxed values do not lose their digits to
-//          position round-off) and velocities ([M][3], compute type)
+//   X, V   mesh node positions (absolute, unwrapped, FP64 in every form, so
+//          that edge lengths and areas near their relaxed values do not lose
+//          their digits to position round-off; an integer per-object anchor is
+//          added to the stencil index and is 0 here) and velocities ([M][3],
+//          compute type)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,6 +31,7 @@ struct BoxDev {
     void* f[2];
     void* G;
     unsigned long long* mask;
+    unsigned long long* touch;  // one bit per node inside any stencil of the current step
     unsigned* status;
     double g[3];
     double rho0;
@@ -118,6 +120,13 @@ struct ObjDev {
 };
 
 // ---- launchers (kernels.hip) ----------------------------------------------
+// Which nodes a lattice launch updates.
+enum : int {
+    LB_ALL = 0,      // every node (coupling force read where the mask says so)
+    LB_FREE = 1,     // only nodes whose touch bit is clear (no coupling force there)
+    LB_TOUCHED = 2,  // only nodes whose touch bit is set; clears touch, mask and G
+};
+
 struct LbLaunch {
     const BoxDev* boxes;   // device array
     const int2* work;      // device array (box, block) or nullptr for box 0
@@ -127,8 +136,13 @@ struct LbLaunch {
     int remap;
     int precision;
     hipStream_t stream;
+    int mode;              // LB_ALL, LB_FREE or LB_TOUCHED
 };
 hipError_t launch_lb(const LbLaunch& L);
+
+// Set the touch bits of every lattice node inside the 2x2x2 stencil of any
+// mesh node of the given objects (one workgroup per object).
+hipError_t launch_mark(const void* objs, int nobj, int precision, size_t lds_bytes, hipStream_t s);
 
 struct MeshLaunch {
     const void* objs;      // device array of ObjDev<real>

@@ -237,7 +237,12 @@ struct oif_ctx {
     void* f[2] = {nullptr, nullptr};
     void* G = nullptr;
     unsigned long long* mask = nullptr;
+    unsigned long long* touch = nullptr;
     unsigned* status = nullptr;
+    hipStream_t side = nullptr;          // lattice update of untouched nodes
+    hipEvent_t ev_mark = nullptr, ev_free = nullptr;
+    int overlap = 0;
+    size_t mark_lds = 0;
     BoxDev box{};
     BoxDev* box_dev = nullptr;
     int parity = 0;
@@ -450,6 +455,8 @@ int upload_mesh_t(oif_ctx* c) {
     });
     c->n_lds_obj = 0;
     c->lds_need = 0;
+    c->mark_lds = 16;
+    for (const Template& T : c->tmpl) c->mark_lds = std::max(c->mark_lds, (size_t)((T.ucap + 31) / 32) * 4);
     size_t scratch_total = 0;
     for (int i : order) {
         if (need(i) <= budget) {
@@ -503,40 +510,93 @@ int sync_mesh(oif_ctx* c) {
 
 size_t objdev_size(int prec) { return prec == OIF_PREC_FP64 ? sizeof(ObjDev<double>) : sizeof(ObjDev<float>); }
 
+// Events bracketing one step's launches (timing only; any may be null).
+struct StepEvents {
+    hipEvent_t t0 = nullptr, t_mark = nullptr, t_mesh = nullptr, t_wait = nullptr, t_lb = nullptr;
+    hipEvent_t f0 = nullptr, f1 = nullptr;  // on the side stream
+};
+
+inline void rec(hipEvent_t e, hipStream_t s) {
+    if (e) (void)hipEventRecord(e, s);
+}
+
+int enqueue_mesh(oif_ctx* c, int par, hipStream_t s) {
+    const size_t osz = objdev_size(c->d.precision);
+    MeshLaunch ml{};
+    ml.block = c->mesh_block;
+    ml.parity = par;
+    ml.precision = c->d.precision;
+    ml.stream = s;
+    if (c->n_lds_obj > 0) {
+        ml.objs = c->obj_dev.p;
+        ml.nobj = c->n_lds_obj;
+        ml.lds_bytes = c->lds_need;
+        HIPCALL(c, launch_mesh(ml));
+    }
+    if ((int)c->obj.size() > c->n_lds_obj) {
+        ml.objs = (const unsigned char*)c->obj_dev.p + osz * c->n_lds_obj;
+        ml.nobj = (int)c->obj.size() - c->n_lds_obj;
+        ml.lds_bytes = 0;
+        HIPCALL(c, launch_mesh(ml));
+    }
+    return OIF_OK;
+}
+
+int enqueue_lb(oif_ctx* c, int par, hipStream_t s, int mode) {
+    LbLaunch ll{};
+    ll.boxes = c->box_dev;
+    ll.work = nullptr;
+    ll.nblocks = (c->N + c->lb_block - 1) / c->lb_block;
+    ll.block = c->lb_block;
+    ll.parity = par;
+    ll.remap = c->remap;
+    ll.precision = c->d.precision;
+    ll.stream = s;
+    ll.mode = mode;
+    HIPCALL(c, launch_lb(ll));
+    return OIF_OK;
+}
+
+// One coupled step.  Without objects, or with overlap off: membrane kernel then
+// lattice kernel on `s`.  With overlap: the touch bits of this step's stencils
+// are marked first; the lattice update of the untouched nodes then runs on the
+// side stream while the membrane kernel runs on `s`, and the touched nodes are
+// updated once both are done (they need the spread coupling force).
+int enqueue_one(oif_ctx* c, int par, hipStream_t s, const StepEvents* ev) {
+    StepEvents none;
+    const StepEvents& E = ev ? *ev : none;
+    int rc;
+    if (c->obj.empty() || !c->overlap) {
+        rec(E.t0, s);
+        if (!c->obj.empty() && (rc = enqueue_mesh(c, par, s))) return rc;
+        rec(E.t_mesh, s);
+        if ((rc = enqueue_lb(c, par, s, LB_ALL))) return rc;
+        rec(E.t_lb, s);
+        return OIF_OK;
+    }
+    rec(E.t0, s);
+    HIPCALL(c, launch_mark(c->obj_dev.p, (int)c->obj.size(), c->d.precision, c->mark_lds, s));
+    rec(E.t_mark, s);
+    HIPCALL(c, hipEventRecord(c->ev_mark, s));
+    HIPCALL(c, hipStreamWaitEvent(c->side, c->ev_mark, 0));
+    rec(E.f0, c->side);
+    if ((rc = enqueue_lb(c, par, c->side, LB_FREE))) return rc;
+    rec(E.f1, c->side);
+    HIPCALL(c, hipEventRecord(c->ev_free, c->side));
+    if ((rc = enqueue_mesh(c, par, s))) return rc;
+    rec(E.t_mesh, s);
+    HIPCALL(c, hipStreamWaitEvent(s, c->ev_free, 0));
+    rec(E.t_wait, s);
+    if ((rc = enqueue_lb(c, par, s, LB_TOUCHED))) return rc;
+    rec(E.t_lb, s);
+    return OIF_OK;
+}
+
 int enqueue_steps(oif_ctx* c, int n, int parity0, hipStream_t s) {
     int par = parity0;
-    const int nblk = (c->N + c->lb_block - 1) / c->lb_block;
-    const size_t osz = objdev_size(c->d.precision);
     for (int k = 0; k < n; ++k) {
-        if (!c->obj.empty()) {
-            MeshLaunch ml{};
-            ml.block = c->mesh_block;
-            ml.parity = par;
-            ml.precision = c->d.precision;
-            ml.stream = s;
-            if (c->n_lds_obj > 0) {
-                ml.objs = c->obj_dev.p;
-                ml.nobj = c->n_lds_obj;
-                ml.lds_bytes = c->lds_need;
-                HIPCALL(c, launch_mesh(ml));
-            }
-            if ((int)c->obj.size() > c->n_lds_obj) {
-                ml.objs = (const unsigned char*)c->obj_dev.p + osz * c->n_lds_obj;
-                ml.nobj = (int)c->obj.size() - c->n_lds_obj;
-                ml.lds_bytes = 0;
-                HIPCALL(c, launch_mesh(ml));
-            }
-        }
-        LbLaunch ll{};
-        ll.boxes = c->box_dev;
-        ll.work = nullptr;
-        ll.nblocks = nblk;
-        ll.block = c->lb_block;
-        ll.parity = par;
-        ll.remap = c->remap;
-        ll.precision = c->d.precision;
-        ll.stream = s;
-        HIPCALL(c, launch_lb(ll));
+        int rc = enqueue_one(c, par, s, nullptr);
+        if (rc) return rc;
         par ^= 1;
     }
     return OIF_OK;
@@ -659,7 +719,13 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     c->max_lds = c->max_lds > 1024 ? c->max_lds - 1024 : 0;
     if (mesh_set_max_lds(c->max_lds) != hipSuccess) c->max_lds = std::min<size_t>(c->max_lds, 65536 - 1024);
     (void)hipGetLastError();  // the opt-in result must not leak into the next launch check
-    if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) return OIF_E_HIP;
+    if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_mark, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_free, hipEventDisableTiming) != hipSuccess) {
+        oif_destroy(c.release());
+        return OIF_E_HIP;
+    }
     c->stream = c->own;
     oif_ctx* cp = c.get();
     auto alloc = [&](void** p, size_t n) -> int {
@@ -670,7 +736,8 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     const size_t nmask = ((size_t)N + 63) / 64;
     int rc = OIF_OK;
     if ((rc = alloc(&c->f[0], popb)) || (rc = alloc(&c->f[1], popb)) || (rc = alloc(&c->G, 24 * (size_t)N)) ||
-        (rc = alloc((void**)&c->mask, 8 * nmask)) || (rc = alloc((void**)&c->status, 256)) ||
+        (rc = alloc((void**)&c->mask, 8 * nmask)) || (rc = alloc((void**)&c->touch, 8 * nmask)) ||
+        (rc = alloc((void**)&c->status, 256)) ||
         (rc = alloc((void**)&c->box_dev, sizeof(BoxDev)))) {
         oif_destroy(c.release());
         return rc;
@@ -679,6 +746,7 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
         hipMemsetAsync(c->f[1], 0, popb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->G, 0, 24 * (size_t)N, c->stream) != hipSuccess ||
         hipMemsetAsync(c->mask, 0, 8 * nmask, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->touch, 0, 8 * nmask, c->stream) != hipSuccess ||
         hipMemsetAsync(c->status, 0, 256, c->stream) != hipSuccess) {
         oif_destroy(c.release());
         return OIF_E_HIP;
@@ -690,6 +758,7 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     b.f[0] = c->f[0]; b.f[1] = c->f[1];
     b.G = c->G;
     b.mask = c->mask;
+    b.touch = c->touch;
     b.status = c->status;
     for (int k = 0; k < 3; ++k) b.g[k] = d.body_force[k];
     b.rho0 = d.rho0;
@@ -715,13 +784,17 @@ int oif_destroy(oif_ctx* c) {
     if (!c) return OIF_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
-    for (void* p : {c->f[0], c->f[1], c->G, (void*)c->mask, (void*)c->status, (void*)c->box_dev})
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    for (void* p : {c->f[0], c->f[1], c->G, (void*)c->mask, (void*)c->touch, (void*)c->status, (void*)c->box_dev})
         if (p) (void)hipFree(p);
     for (auto& b : c->tbufs) b.release();
     for (DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->geo_dev, &c->scratch_dev,
                       &c->part_dev, &c->diag_out})
         b->release();
     if (c->own) (void)hipStreamDestroy(c->own);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_mark) (void)hipEventDestroy(c->ev_mark);
+    if (c->ev_free) (void)hipEventDestroy(c->ev_free);
     delete c;
     return OIF_OK;
 }
@@ -783,7 +856,9 @@ int oif_object_add(oif_ctx* c, int oid, int tid, const double origin[3], const d
     o.ptype = part_type;
     o.nv = T.nv;
     o.off = c->M;
-    for (int a = 0; a < 3; ++a) o.anchor[a] = (int)std::floor(origin[a] + 0.5);
+    // positions are kept absolute in FP64 (anchor 0): the representation the
+    // host reads and writes, so checkpoints round-trip bit for bit
+    for (int a = 0; a < 3; ++a) o.anchor[a] = 0;
     const double I[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
     const double* R = rot ? rot : I;
     c->Xh.resize(3 * (size_t)(c->M + T.nv));
@@ -874,49 +949,54 @@ int oif_step_timed(oif_ctx* c, int n, oif_timing* t) {
     int rc = sync_mesh(c);
     if (rc) return rc;
     HIPCALL(c, hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream));
-    std::vector<hipEvent_t> ev(3 * (size_t)n);
-    for (auto& e : ev) HIPCALL(c, hipEventCreate(&e));
-    const int nblk = (c->N + c->lb_block - 1) / c->lb_block;
-    const size_t osz = objdev_size(c->d.precision);
-    int err = OIF_OK;
-    for (int k = 0; k < n && !err; ++k) {
-        (void)hipEventRecord(ev[3 * k], c->stream);
-        if (!c->obj.empty()) {
-            MeshLaunch ml{};
-            ml.block = c->mesh_block; ml.parity = c->parity; ml.precision = c->d.precision; ml.stream = c->stream;
-            if (c->n_lds_obj > 0) {
-                ml.objs = c->obj_dev.p; ml.nobj = c->n_lds_obj; ml.lds_bytes = c->lds_need;
-                if (launch_mesh(ml) != hipSuccess) err = OIF_E_HIP;
-            }
-            if ((int)c->obj.size() > c->n_lds_obj) {
-                ml.objs = (const unsigned char*)c->obj_dev.p + osz * c->n_lds_obj;
-                ml.nobj = (int)c->obj.size() - c->n_lds_obj; ml.lds_bytes = 0;
-                if (launch_mesh(ml) != hipSuccess) err = OIF_E_HIP;
-            }
-        }
-        (void)hipEventRecord(ev[3 * k + 1], c->stream);
-        LbLaunch ll{c->box_dev, nullptr, nblk, c->lb_block, c->parity, c->remap, c->d.precision, c->stream};
-        if (launch_lb(ll) != hipSuccess) err = OIF_E_HIP;
-        (void)hipEventRecord(ev[3 * k + 2], c->stream);
+    const bool split = c->overlap && !c->obj.empty();
+    std::vector<StepEvents> ev((size_t)n);
+    std::vector<hipEvent_t> all;
+    auto mk = [&](hipEvent_t& e) -> int {
+        if (hipEventCreate(&e) != hipSuccess) return OIF_E_HIP;
+        all.push_back(e);
+        return OIF_OK;
+    };
+    for (auto& E : ev) {
+        if (mk(E.t0) || mk(E.t_mesh) || mk(E.t_lb)) rc = OIF_E_HIP;
+        if (split && (mk(E.t_mark) || mk(E.t_wait) || mk(E.f0) || mk(E.f1))) rc = OIF_E_HIP;
+    }
+    for (int k = 0; k < n && !rc; ++k) {
+        rc = enqueue_one(c, c->parity, c->stream, &ev[k]);
         c->parity ^= 1;
     }
     (void)hipStreamSynchronize(c->stream);
-    double lb = 0, ms = 0;
-    float v = 0;
-    for (int k = 0; k < n; ++k) {
-        (void)hipEventElapsedTime(&v, ev[3 * k], ev[3 * k + 1]);
-        ms += v;
-        (void)hipEventElapsedTime(&v, ev[3 * k + 1], ev[3 * k + 2]);
-        lb += v;
+    (void)hipStreamSynchronize(c->side);
+    std::memset(t, 0, sizeof(*t));
+    if (!rc) {
+        auto el = [](hipEvent_t a, hipEvent_t b) {
+            float v = 0;
+            (void)hipEventElapsedTime(&v, a, b);
+            return (double)v;
+        };
+        for (int k = 0; k < n; ++k) {
+            const StepEvents& E = ev[k];
+            if (split) {
+                t->mark_ms += el(E.t0, E.t_mark);
+                t->mesh_ms += el(E.t_mark, E.t_mesh);
+                t->lb_ms += el(E.f0, E.f1);
+                t->lb_touched_ms += el(E.t_wait, E.t_lb);
+            } else {
+                t->mesh_ms += el(E.t0, E.t_mesh);
+                t->lb_ms += el(E.t_mesh, E.t_lb);
+            }
+        }
+        t->total_ms = el(ev[0].t0, ev[(size_t)n - 1].t_lb);
+        t->lb_ms /= n;
+        t->lb_touched_ms /= n;
+        t->mark_ms /= n;
+        t->mesh_ms = c->obj.empty() ? 0.0 : t->mesh_ms / n;
+        t->lb_launches = n;
+        t->mesh_launches = c->obj.empty() ? 0 : n;
+        t->overlap = split ? 1 : 0;
     }
-    (void)hipEventElapsedTime(&v, ev[0], ev[3 * (size_t)n - 1]);
-    t->total_ms = v;
-    t->lb_ms = lb / n;
-    t->mesh_ms = c->obj.empty() ? 0.0 : ms / n;
-    t->lb_launches = n;
-    t->mesh_launches = c->obj.empty() ? 0 : n;
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    if (err) return fail(c, err, "kernel launch failed");
+    for (auto& e : all) (void)hipEventDestroy(e);
+    if (rc) return fail(c, rc, "kernel launch failed");
     c->steps += n;
     if (c->M) c->host_stale = true;
     return watchdog(c);
@@ -925,6 +1005,15 @@ int oif_step_timed(oif_ctx* c, int n, oif_timing* t) {
 int oif_set_graph(oif_ctx* c, int steps_per_graph) {
     if (!c || steps_per_graph < 0) return OIF_E_ARG;
     c->graph_steps = steps_per_graph > 0 ? steps_per_graph + (steps_per_graph & 1) : 0;
+    drop_graph(c);
+    return OIF_OK;
+}
+
+int oif_set_overlap(oif_ctx* c, int on) {
+    if (!c) return OIF_E_ARG;
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    HIPCALL(c, hipStreamSynchronize(c->side));
+    c->overlap = on ? 1 : 0;
     drop_graph(c);
     return OIF_OK;
 }
@@ -1047,6 +1136,7 @@ int oif_info(oif_ctx* c, oif_info_t* info) {
     info->xcd_remap = c->remap;
     info->graph_steps = c->graph_steps;
     info->max_lds = (long long)c->max_lds;
+    info->overlap = c->overlap;
     info->lds_objects = c->n_lds_obj;
     return OIF_OK;
 }
@@ -1241,6 +1331,8 @@ extern "C" int oif_autotune(oif_ctx* c, const char* cache_path) {
     if (cache_lookup(cache_path, key, best)) return oif_set_launch(c, best[0], best[1], best[2]);
     Snapshot s;
     if ((rc = snapshot(c, s, false))) return rc;
+    const int overlap = c->overlap;
+    c->overlap = 0;  // time each kernel alone
     const int reps = 6;  // even: parity is unchanged after each trial
     double best_lb = 1e300, best_mesh = 1e300;
     best[0] = c->lb_block; best[1] = c->mesh_block; best[2] = c->remap;
@@ -1262,6 +1354,7 @@ extern "C" int oif_autotune(oif_ctx* c, const char* cache_path) {
             if (tm < best_mesh) { best_mesh = tm; best[1] = mb; }
         }
     c->mesh_block = best[1];
+    c->overlap = overlap;
     if ((rc = snapshot(c, s, true))) return rc;
     c->host_stale = c->M > 0;
     drop_graph(c);

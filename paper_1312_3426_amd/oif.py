@@ -53,7 +53,7 @@ class Info(C.Structure):
                 ("walls_z", C.c_int), ("n_nodes", C.c_longlong), ("n_mesh_nodes", C.c_longlong),
                 ("steps_done", C.c_longlong), ("device_bytes", C.c_longlong), ("lb_block", C.c_int),
                 ("mesh_block", C.c_int), ("xcd_remap", C.c_int), ("graph_steps", C.c_int),
-                ("max_lds", C.c_longlong), ("lds_objects", C.c_int)]
+                ("max_lds", C.c_longlong), ("lds_objects", C.c_int), ("overlap", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -64,7 +64,8 @@ class Diag(C.Structure):
 
 class Timing(C.Structure):
     _fields_ = [("total_ms", C.c_double), ("lb_ms", C.c_double), ("mesh_ms", C.c_double),
-                ("lb_launches", C.c_int), ("mesh_launches", C.c_int)]
+                ("lb_launches", C.c_int), ("mesh_launches", C.c_int), ("lb_touched_ms", C.c_double),
+                ("mark_ms", C.c_double), ("overlap", C.c_int)]
 
 
 _lib = None
@@ -86,6 +87,7 @@ SIGNATURES = {
     "oif_step": (_i, [_vp, _i]),
     "oif_step_timed": (_i, [_vp, _i, _vp]),
     "oif_set_graph": (_i, [_vp, _i]),
+    "oif_set_overlap": (_i, [_vp, _i]),
     "oif_set_launch": (_i, [_vp, _i, _i, _i]),
     "oif_autotune": (_i, [_vp, C.c_char_p]),
     "oif_read_populations": (_i, [_vp, _vp]),
@@ -241,6 +243,9 @@ class Context:
 
     def set_launch(self, lb_block: int = -1, mesh_block: int = -1, xcd_remap: int = -1):
         self._chk(lib().oif_set_launch(self.h, int(lb_block), int(mesh_block), int(xcd_remap)))
+
+    def set_overlap(self, on: bool):
+        self._chk(lib().oif_set_overlap(self.h, int(bool(on))))
 
     def autotune(self, cache_path: Optional[str] = None):
         self._chk(lib().oif_autotune(self.h, None if cache_path is None else cache_path.encode()))

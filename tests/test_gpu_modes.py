@@ -1,0 +1,274 @@
+"""GPU tests of the execution modes and the auxiliary subsystems, through the
+C ABI: overlapped vs sequential steps, graph replay vs eager launches,
+autotuning, checkpoint/restore, the batching form, object analysis,
+conservation diagnostics, the watchdog and input validation."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1312_3426_amd import synth
+
+from gpu_util import W, check, fmt, gpu_fields, oracle_fields, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def oif():
+    from paper_1312_3426_amd import oif as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build()
+    return oracle
+
+
+def state(ctx):
+    X, V = ctx.read_mesh(-1)
+    return ctx.read_populations(), X, V
+
+
+def same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def channel(steps=40):
+    return synth.config_channel_rbc(steps)
+
+
+def test_overlap_matches_sequential_bitwise(oif):
+    say("[modes] overlap vs sequential, fp32 channel")
+    box = channel()
+    outs = []
+    for ov in (False, True):
+        c = oif.Context.from_box(box, precision="fp32")
+        c.set_overlap(ov)
+        c.step(40)
+        assert c.info().overlap == int(ov)
+        outs.append(state(c))
+        c.close()
+    assert same(*outs)
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_graph_matches_eager_bitwise(oif, overlap):
+    say(f"[modes] graph vs eager, overlap={overlap}")
+    box = channel()
+    outs = []
+    for g in (0, 8):
+        c = oif.Context.from_box(box, precision="fp32")
+        c.set_overlap(overlap)
+        c.set_graph(g)
+        c.step(3)    # odd: the graph path must first realign to parity 0
+        c.step(37)   # 4 replays of 8 steps + 5 eager
+        outs.append(state(c))
+        c.close()
+    assert same(*outs)
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_step_timed_matches_step(oif, overlap):
+    say(f"[modes] timed vs plain stepping, overlap={overlap}")
+    box = channel()
+    outs = []
+    for timed in (False, True):
+        c = oif.Context.from_box(box, precision="fp32")
+        c.set_overlap(overlap)
+        if timed:
+            t = c.step_timed(40)
+            assert t.total_ms > 0 and t.lb_ms > 0 and t.mesh_ms > 0 and t.overlap == int(overlap)
+        else:
+            c.step(40)
+        outs.append(state(c))
+        c.close()
+    assert same(*outs)
+
+
+def test_autotune_leaves_state_unchanged(oif, tmp_path):
+    say("[modes] autotune mid-run")
+    box = channel()
+    outs = []
+    cache = str(tmp_path / "tune.json")
+    for tune in (False, True):
+        c = oif.Context.from_box(box, precision="fp32")
+        c.step(20)
+        if tune:
+            c.autotune(cache)
+            i = c.info()
+            assert i.lb_block in (128, 256, 512, 1024) and i.mesh_block in (64, 128, 256, 512, 1024)
+        c.step(20)
+        outs.append(state(c))
+        c.close()
+    # tuning changes launch shapes: FP32 results are independent of them except
+    # for the FP64 area/volume block sums, which differ only by round-off
+    for a, b in zip(*outs):
+        assert rel(a, b) < 1e-6
+    assert os.path.exists(cache) and "gfx950" in open(cache).read()
+    # a second context finds the shapes in the cache
+    c = oif.Context.from_box(box, precision="fp32")
+    c.autotune(cache)
+    c.close()
+
+
+def test_checkpoint_restore_bitwise(oif):
+    say("[modes] checkpoint / restore")
+    box = channel()
+    a = oif.Context.from_box(box, precision="fp32")
+    a.step(30)
+    n, X, V = state(a)
+    a.step(20)
+    ref = state(a)
+    a.close()
+    b = oif.Context.from_box(box, precision="fp32")
+    b.write_populations(n)
+    b.write_mesh(-1, X, V)
+    b.step(20)
+    assert same(ref, state(b))
+    b.close()
+
+
+def test_batch_matches_single_boxes(oif):
+    say("[modes] batch of 3 boxes vs single contexts")
+    boxes = synth.config_batch(n_boxes=3, steps=20)
+    singles = []
+    for bx in boxes:
+        c = oif.Context.from_box(bx, precision="fp32")
+        c.set_overlap(False)
+        c.step(20)
+        singles.append(state(c))
+        c.close()
+    ctxs = [oif.Context.from_box(bx, precision="fp32") for bx in boxes]
+    B = oif.Batch(ctxs)
+    B.set_graph(4)
+    B.step(1)
+    B.step(19)
+    for c, ref in zip(ctxs, singles):
+        assert same(ref, state(c))
+    t = B.step_timed(4)
+    assert t.total_ms > 0
+    B.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_batch_box_vs_oracle(oif, orc):
+    """A batched box with 162/642/2562-node spheres against the oracle."""
+    say("[modes] batch box 0 vs oracle (fp32)")
+    boxes = synth.config_batch(n_boxes=2, steps=30)
+    ctxs = [oif.Context.from_box(bx, precision="fp32") for bx in boxes]
+    B = oif.Batch(ctxs)
+    B.step(30)
+    for bx, c in zip(boxes, ctxs):
+        s = orc.System(bx)
+        X0 = s.X.copy()
+        s.run(30)
+        res = check(gpu_fields(c, bx.rho0, X0), oracle_fields(s, X0), "fp32", bx.rho0, max(bx.nx, bx.ny, bx.nz))
+        say(f"   {bx.name} ({len(bx.objects)} cells): {fmt(res)}")
+        assert all(v[3] for v in res.values())
+    B.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_object_analysis_vs_oracle(oif, orc):
+    say("[aux] object analysis")
+    box = synth.config_sphere_fp64(30)
+    c = oif.Context.from_box(box, precision="fp64")
+    c.step(30)
+    s = orc.System(box)
+    s.run(30)
+    Sg, Vol = s.geometry()
+    a = c.object_analyze(0)
+    assert a.volume == pytest.approx(Vol[0], rel=1e-12)
+    assert a.area == pytest.approx(Sg[0], rel=1e-12)
+    assert np.allclose(a.origin, s.X.mean(axis=0), rtol=0, atol=1e-12)
+    assert np.allclose(a.velocity, s.V.mean(axis=0), rtol=1e-9, atol=1e-16)
+    assert a.bounds[0] == pytest.approx(s.X[:, 0].min(), abs=1e-12)
+    assert a.bounds[5] == pytest.approx(s.X[:, 2].max(), abs=1e-12)
+    info = c.info()
+    assert (info.n_objects, info.n_templates, info.n_mesh_nodes, info.steps_done) == (1, 1, 642, 30)
+    c.close()
+
+
+def test_fp64_momentum_budget_and_mass(oif):
+    """Stretching and volume forces sum to zero on a closed mesh, so with an
+    external force the total momentum grows by steps x (N g + M f_ext)."""
+    say("[aux] FP64 diagnostics: momentum budget")
+    box = synth.config_sphere_fp64(25)
+    t = box.templates[0]
+    t.kb = t.kal = t.kag = 0.0
+    box.objects[0].fext = (3e-6, -1e-6, 2e-6)
+    c = oif.Context.from_box(box, precision="fp64")
+    d0 = c.diagnostics()
+    c.step(25)
+    d1 = c.diagnostics()
+    P0 = np.array(d0.momentum_fluid) + np.array(d0.momentum_mesh)
+    P1 = np.array(d1.momentum_fluid) + np.array(d1.momentum_mesh)
+    want = 25 * (box.n_nodes * np.array(box.g) + box.n_mesh_nodes * np.array(box.objects[0].fext))
+    assert np.abs((P1 - P0) - want).max() < 1e-12 * np.abs(want).max() + 1e-15
+    assert d1.mass == pytest.approx(box.n_nodes * box.rho0, rel=1e-14)
+    assert d1.nonfinite == 0 and d1.clamped == 0 and d1.overflow == 0
+    c.close()
+
+
+def test_watchdog_nonfinite_population(oif):
+    say("[aux] watchdog: NaN written from the host")
+    box = synth.Box(16, 8, 8)
+    c = oif.Context.from_box(box, precision="fp32")
+    n = c.read_populations()
+    n[3, 2, 1, 5] = np.nan
+    c.write_populations(n)
+    with pytest.raises(oif.OifError) as ei:
+        c.step(1)
+    assert ei.value.code == oif.E_NONFINITE
+    c.close()
+
+
+def test_watchdog_fixed_point_overflow(oif):
+    say("[aux] watchdog: fixed-point range")
+    box = synth.config_sphere_fp64(2)
+    box.objects[0].fext = (1e6, 0.0, 0.0)
+    c = oif.Context.from_box(box, precision="fp32", fixed_point_exp=56)
+    c.step(1)
+    with pytest.raises(oif.OifError) as ei:
+        c.step(1)
+    assert ei.value.code == oif.E_OVERFLOW
+    c.close()
+
+
+def test_input_validation(oif):
+    say("[aux] validation of templates and objects")
+    x, t = synth.icosphere(2, 3.0)
+    c = oif.Context(16, 16, 16, precision="fp32")
+    with pytest.raises(oif.OifError) as ei:
+        c.template_create(0, x, t[:, [0, 2, 1]], ks=0.1)   # outward normals
+    assert ei.value.code == oif.E_MESH
+    with pytest.raises(oif.OifError) as ei:
+        c.template_create(1, x, t, ks=0.1)                 # ids start at 0
+    assert ei.value.code == oif.E_ID
+    with pytest.raises(oif.OifError) as ei:
+        c.template_create(0, x, t[:-1], ks=0.1)           # open mesh
+    assert ei.value.code == oif.E_MESH
+    c.template_create(0, x, t, ks=0.1, stretch=(1.0, 1.0, 1.5))
+    with pytest.raises(oif.OifError) as ei:
+        c.object_add(1, 0, (8, 8, 8))
+    assert ei.value.code == oif.E_ID
+    c.object_add(0, 0, (8, 8, 8), rot=oif.euler_to_rot(0.3, 0.2, 0.1), mass=2.0)
+    with pytest.raises(oif.OifError) as ei:
+        c.template_create(1, x, t, ks=0.1)                 # after objects exist
+    assert ei.value.code == oif.E_STATE
+    # stretched template: relaxed volume scales by 1.5; object placement keeps it
+    a = c.object_analyze(0)
+    import oracle
+    _, _, V0 = oracle.geometry(x, t)
+    assert a.volume == pytest.approx(1.5 * V0, rel=1e-12)
+    assert np.allclose(a.origin, 8.0, atol=1e-12)
+    c.object_set_origin(0, (5.0, 6.0, 7.0))
+    assert np.allclose(c.object_analyze(0).origin, (5, 6, 7), atol=1e-12)
+    c.step(2)
+    c.close()
