@@ -15,10 +15,18 @@ JSON line:
   storage        FP16/BF16 deviation storage: throughput and velocity error
                  against the FP64 form after the same number of steps on the
                  64^3 sub-run (31 cells, same number density)
+  batching       32 uneven boxes (1.05-4.7 M nodes in all, 1-20 cells each of
+                 162/642/2562 nodes): one launch per kernel over all boxes,
+                 eager and as a captured graph, against a loop that steps the
+                 boxes one after another
+  roofline.traffic  HBM bytes per lattice-kernel launch from the rocprofv3
+                 FETCH_SIZE / WRITE_SIZE record in profiles/, reported only while
+                 the lattice kernel's sources hash to the recorded value
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -32,6 +40,35 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 BYTES_POP = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+LB_SOURCES = ("paper_1312_3426_amd/csrc/lb_kernels.hip", "paper_1312_3426_amd/csrc/device_common.h",
+              "paper_1312_3426_amd/csrc/oif_device.h")
+TRAFFIC_RECORD = "profiles/lb_kernel_fp32_sphere642x500_256x128x128.md"
+
+
+def lb_sources_hash():
+    h = hashlib.sha256()
+    for f in LB_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per lattice-kernel launch from the counter record, or None if
+    there is none or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, TRAFFIC_RECORD)
+    if not os.path.exists(path):
+        return None, "no counter record"
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic-record:"):
+                rec = dict(kv.split("=", 1) for kv in line.split(":", 1)[1].split())
+    if not rec:
+        return None, "no counter record"
+    if rec.get("sources") != lb_sources_hash():
+        return None, "lattice kernel changed since the counters were taken"
+    return int(rec["fetch_bytes"]) + int(rec["write_bytes"]), TRAFFIC_RECORD
 
 
 def log(*a):
@@ -84,6 +121,42 @@ def storage_error(oif, steps):
     return out, umax
 
 
+def batching(oif, steps, tune):
+    """Batched stepping of the 32-box case against stepping the boxes one after
+    another (each box's own launches, event-timed, no host synchronisation
+    between its steps)."""
+    from paper_1312_3426_amd import synth
+
+    boxes = synth.config_batch(steps=steps)
+    N = sum(b.n_nodes for b in boxes)
+    ctxs = [oif.Context.from_box(b, precision="fp32") for b in boxes]
+    for c in ctxs:
+        if tune:
+            c.autotune(tune)
+        c.step(2)
+    loop_ms = sum(c.step_timed(steps).total_ms for c in ctxs)
+    b = oif.Batch(ctxs)
+    if tune:
+        b.autotune(tune)
+    b.step(2)
+    eager_ms = b.step_timed(steps).total_ms
+    b.set_graph(50)
+    b.step(100)
+    t0 = time.perf_counter()
+    b.step(steps)
+    graph_ms = (time.perf_counter() - t0) * 1e3
+    b.close()
+    for c in ctxs:
+        c.close()
+    ml = lambda ms: round(N * steps / (ms * 1e-3) / 1e6, 2)  # noqa: E731
+    return {"boxes": len(boxes), "nodes": N, "mesh_nodes": sum(x.n_mesh_nodes for x in boxes),
+            "steps": steps, "loop_mlups": ml(loop_ms), "batched_mlups": ml(eager_ms),
+            "batched_graph_mlups": ml(graph_ms), "speedup_batched": round(loop_ms / eager_ms, 3),
+            "speedup_batched_graph": round(loop_ms / graph_ms, 3),
+            "timing": "loop and batched: HIP events around the launches; graph: wall clock incl. "
+                      "one FP64 watchdog"}
+
+
 def cpu_baseline(box, steps):
     import oracle
 
@@ -107,6 +180,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-storage", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1312_3426_amd", "autotune.json"))
     ap.add_argument("--workload", default="precision", choices=["precision", "scale"])
     ap.add_argument("--only", default=None, choices=["fp32", "fp16", "bf16"],
@@ -150,6 +224,9 @@ def main():
     mlups = N / (ms_step * 1e-3) / 1e6
     lb_bytes = 2 * 19 * BYTES_POP["fp32"] * N
     achieved = lb_bytes / (r32["lb_ms"] * 1e-3) / 1e9
+    traffic, traffic_src = recorded_traffic()
+    if a.workload != "precision":
+        traffic, traffic_src = None, "counter record is for the 256x128x128 workload"
     T = r32["touched"]
     full_bytes = 2 * 19 * 4 * N + 48 * M + 100 * T
     full_gbs = full_bytes / (ms_step * 1e-3) / 1e9
@@ -172,7 +249,8 @@ def main():
         "mesh_node_updates_per_s": round(M / (ms_step * 1e-3), 1),
         "kernel_ms": {"lb": round(r32["lb_ms"], 5), "mesh": round(r32["mesh_ms"], 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "kernel": "lb_kernel<FP32>", "bytes_per_launch": lb_bytes,
                      "copy_kernel_GB/s": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "full_step": {"bytes": full_bytes, "touched_nodes": T, "GB/s": round(full_gbs, 1),
@@ -197,6 +275,9 @@ def main():
         for p in err:
             line["storage"].setdefault(p, {}).update(err[p])
         line["storage"]["error_reference"] = f"FP64 form, 64^3 sub-run, 500 steps, max|u| = {umax:.3e}"
+    if not a.no_batch:
+        log("[bench] batching: 32 boxes, batched vs one after another")
+        line["batching"] = batching(oif, 200, None if a.no_tune else a.tune_cache)
     if not a.no_cpu:
         log(f"[bench] cpu baseline: oracle, {a.cpu_steps} steps")
         line["cpu_baseline"] = cpu_baseline(box, a.cpu_steps)
