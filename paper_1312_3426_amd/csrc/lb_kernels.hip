@@ -20,80 +20,43 @@ namespace {
 
 using namespace dev;
 
+// Coupling force density at node p, read from G and cleared there.
 template <int P>
-__global__ void __launch_bounds__(1024)
-lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int nblocks, int parity,
-          int remap, int mode) {
+__device__ __forceinline__ void take_force(const BoxDev* __restrict__ B, int p, typename Prec<P>::R& fx,
+                                           typename Prec<P>::R& fy, typename Prec<P>::R& fz) {
+    typedef typename Prec<P>::R R;
+    const int N = B->N;
+    if (P == PREC_FP64) {
+        double* G = (double*)B->G;
+        fx += (R)G[p];
+        fy += (R)G[N + p];
+        fz += (R)G[2 * N + p];
+        G[p] = 0.0;
+        G[N + p] = 0.0;
+        G[2 * N + p] = 0.0;
+    } else {
+        long long* G = (long long*)B->G;
+        const double s = B->fp_inv;
+        fx += (R)((double)G[p] * s);
+        fy += (R)((double)G[N + p] * s);
+        fz += (R)((double)G[2 * N + p] * s);
+        G[p] = 0;
+        G[N + p] = 0;
+        G[2 * N + p] = 0;
+    }
+}
+
+// BGK collision with Guo forcing at node p (force density f) and push of the
+// 19 post-collision deviations to the neighbours.
+template <int P>
+__device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p, typename Prec<P>::R fx,
+                                             typename Prec<P>::R fy, typename Prec<P>::R fz, int parity) {
     typedef typename Prec<P>::S S;
     typedef typename Prec<P>::R R;
-    int bid = blockIdx.x;
-    if (remap) {
-        // workgroups are dispatched round-robin over the 8 XCDs; give each XCD
-        // a contiguous range of lattice blocks so neighbouring planes share an L2
-        const int full = nblocks & ~7;
-        if (bid < full) bid = (bid & 7) * (full >> 3) + (bid >> 3);
-    }
-    int box = 0, blk = bid;
-    if (work) {
-        const int2 w = work[bid];
-        box = w.x;
-        blk = w.y;
-    }
-    const BoxDev* __restrict__ B = boxes + box;
     const int N = B->N;
-    const int p = blk * (int)blockDim.x + (int)threadIdx.x;
-    if (p >= N) return;
     const S* __restrict__ src = (const S*)B->f[parity];
     S* __restrict__ dst = (S*)B->f[parity ^ 1];
     const float inv = B->st_inv, scale = B->st_scale;
-
-    // Force density: body force plus the coupling force G where the node's mask
-    // bit is set.  Mask and touch words cover exactly one wave's 64 nodes; all
-    // lanes load a word before the wave's first lane clears it.
-    R fx = (R)B->g[0], fy = (R)B->g[1], fz = (R)B->g[2];
-    unsigned long long* mk = B->mask + (p >> 6);
-    unsigned long long m = 0ull;
-    if (mode == LB_ALL) {
-        m = *mk;
-        if (m && (p & 63) == 0) *mk = 0ull;
-    } else {
-        // split update: untouched nodes run while the membrane kernel spreads,
-        // touched nodes (inside some stencil of this step) after it
-        unsigned long long* tw = B->touch + (p >> 6);
-        const unsigned long long tb = *tw;
-        const bool mine = (tb >> (p & 63)) & 1ull;
-        if (mode == LB_FREE) {
-            if (mine) return;  // a coupling force can reach only touched nodes
-        } else {
-            if (tb == 0ull) return;  // the whole wave is untouched
-            m = *mk;
-            if ((p & 63) == 0) {
-                *tw = 0ull;
-                if (m) *mk = 0ull;
-            }
-            if (!mine) return;
-        }
-    }
-    if ((m >> (p & 63)) & 1ull) {
-        if (P == PREC_FP64) {
-            double* G = (double*)B->G;
-            fx += (R)G[p];
-            fy += (R)G[N + p];
-            fz += (R)G[2 * N + p];
-            G[p] = 0.0;
-            G[N + p] = 0.0;
-            G[2 * N + p] = 0.0;
-        } else {
-            long long* G = (long long*)B->G;
-            const double s = B->fp_inv;
-            fx += (R)((double)G[p] * s);
-            fy += (R)((double)G[N + p] * s);
-            fz += (R)((double)G[2 * N + p] * s);
-            G[p] = 0;
-            G[N + p] = 0;
-            G[2 * N + p] = 0;
-        }
-    }
 
     R d[19];
 #pragma unroll
@@ -148,6 +111,61 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
             dst[(size_t)i * N + p + off] = out;
         }
     }
+}
+
+template <int P>
+__global__ void __launch_bounds__(1024)
+lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int nblocks, int parity,
+          int remap, int mode) {
+    typedef typename Prec<P>::R R;
+    int bid = blockIdx.x;
+    if (remap) {
+        // workgroups are dispatched round-robin over the 8 XCDs; give each XCD
+        // a contiguous range of lattice blocks so neighbouring planes share an L2
+        const int full = nblocks & ~7;
+        if (bid < full) bid = (bid & 7) * (full >> 3) + (bid >> 3);
+    }
+    int box = 0, blk = bid;
+    if (work) {
+        const int2 w = work[bid];
+        box = w.x;
+        blk = w.y;
+    }
+    const BoxDev* __restrict__ B = boxes + box;
+    const int N = B->N;
+    const int p = blk * (int)blockDim.x + (int)threadIdx.x;
+    if (p >= N) return;
+
+    // Force density: body force plus the coupling force G where the node's mask
+    // bit is set.  Mask and touch words cover exactly one wave's 64 nodes; all
+    // lanes load a word before the wave's first lane clears it.
+    R fx = (R)B->g[0], fy = (R)B->g[1], fz = (R)B->g[2];
+    unsigned long long* mk = B->mask + (p >> 6);
+    unsigned long long m = 0ull;
+    if (mode == LB_ALL) {
+        m = *mk;
+        if (m && (p & 63) == 0) *mk = 0ull;
+    } else {
+        // split update: the nodes outside every stencil of this step run while
+        // the membrane kernel spreads (no coupling force can reach them), the
+        // others after it
+        unsigned long long* tw = B->touch[parity] + (p >> 6);
+        const unsigned long long tb = *tw;
+        const bool mine = (tb >> (p & 63)) & 1ull;
+        if (mode == LB_FREE) {
+            if (mine) return;
+        } else {
+            if (tb == 0ull) return;  // the whole wave is untouched
+            m = *mk;
+            if ((p & 63) == 0) {
+                *tw = 0ull;
+                if (m) *mk = 0ull;
+            }
+            if (!mine) return;
+        }
+    }
+    if ((m >> (p & 63)) & 1ull) take_force<P>(B, p, fx, fy, fz);
+    collide_push<P>(B, p, fx, fy, fz, parity);
 }
 
 template <int P>

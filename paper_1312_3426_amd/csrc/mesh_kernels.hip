@@ -81,9 +81,91 @@ struct Acc<PREC_FP64> {
     }
 };
 
+// Lattice index of the (unwrapped) node (gx, gy, gz): periodic in x and y,
+// periodic or clamped to the walls in z.
+__device__ __forceinline__ int lattice_node(const BoxDev* __restrict__ B, int gx, int gy, int gz) {
+    const int nxb = B->nx, nyb = B->ny, nzb = B->nz;
+    gx %= nxb;
+    gx += gx < 0 ? nxb : 0;
+    gy %= nyb;
+    gy += gy < 0 ? nyb : 0;
+    if (B->walls_z) {
+        gz = gz < 0 ? 0 : (gz >= nzb ? nzb - 1 : gz);
+    } else {
+        gz %= nzb;
+        gz += gz < 0 ? nzb : 0;
+    }
+    return (gz * nyb + gy) * nxb + gx;
+}
+
+// Stencil marking of one object for split stepping: every lattice node inside
+// the 2x2x2 stencil of a finite node position gets its bit in `touch`.  The
+// object's stencil box is marked in the bitmask `bits` ((ucap + 31)/32 words)
+// first when it fits, so each touched node costs one global atomic however
+// many stencils contain it; otherwise every corner goes to `touch` directly.
+// Called by the whole workgroup.
+__device__ void mark_object(const double* pos, int nv, const int* anchor, const BoxDev* __restrict__ B,
+                            int ucap, unsigned* bits, int* bbox, unsigned long long* touch) {
+    __syncthreads();  // earlier users of bits and bbox are done
+    if (threadIdx.x == 0) {
+        bbox[0] = bbox[1] = bbox[2] = INT_MAX;
+        bbox[3] = bbox[4] = bbox[5] = INT_MIN;
+    }
+    __syncthreads();
+    int blo[3] = {INT_MAX, INT_MAX, INT_MAX}, bhi[3] = {INT_MIN, INT_MIN, INT_MIN};
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        const double sx = pos[3 * v] - 0.5, sy = pos[3 * v + 1] - 0.5, sz = pos[3 * v + 2] - 0.5;
+        if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
+        const int bx = anchor[0] + (int)floor(sx), by = anchor[1] + (int)floor(sy),
+                  bz = anchor[2] + (int)floor(sz);
+        blo[0] = min(blo[0], bx); blo[1] = min(blo[1], by); blo[2] = min(blo[2], bz);
+        bhi[0] = max(bhi[0], bx); bhi[1] = max(bhi[1], by); bhi[2] = max(bhi[2], bz);
+    }
+    wave_bbox_to_block(blo, bhi, bbox);
+    __syncthreads();
+    const int ox = bbox[0], oy = bbox[1], oz = bbox[2];
+    if (bbox[3] < bbox[0]) return;  // no finite node (block-uniform)
+    const long long exl = (long long)bbox[3] - ox + 2, eyl = (long long)bbox[4] - oy + 2,
+                    ezl = (long long)bbox[5] - oz + 2;
+    if (exl * eyl * ezl <= (long long)ucap) {
+        const int ex = (int)exl, exy = (int)(exl * eyl), vol = (int)(exl * eyl * ezl);
+        for (int k = threadIdx.x; k < (vol + 31) / 32; k += blockDim.x) bits[k] = 0u;
+        __syncthreads();
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+            const double sx = pos[3 * v] - 0.5, sy = pos[3 * v + 1] - 0.5, sz = pos[3 * v + 2] - 0.5;
+            if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
+            const int b0 = (anchor[2] + (int)floor(sz) - oz) * exy + (anchor[1] + (int)floor(sy) - oy) * ex +
+                           (anchor[0] + (int)floor(sx) - ox);
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const int k = (kk + (int)threadIdx.x) & 7;
+                const int idx = b0 + (k >> 2) * exy + ((k >> 1) & 1) * ex + (k & 1);
+                atomicOr(&bits[idx >> 5], 1u << (idx & 31));
+            }
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < vol; idx += blockDim.x) {
+            if (!((bits[idx >> 5] >> (idx & 31)) & 1u)) continue;
+            const int q = lattice_node(B, ox + idx % ex, oy + (idx / ex) % (int)eyl, oz + idx / exy);
+            atomicOr(touch + (q >> 6), 1ull << (q & 63));
+        }
+    } else {
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+            const double sx = pos[3 * v] - 0.5, sy = pos[3 * v + 1] - 0.5, sz = pos[3 * v + 2] - 0.5;
+            if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
+            const int bx = anchor[0] + (int)floor(sx), by = anchor[1] + (int)floor(sy),
+                      bz = anchor[2] + (int)floor(sz);
+            for (int k = 0; k < 8; ++k) {
+                const int q = lattice_node(B, bx + (k & 1), by + ((k >> 1) & 1), bz + (k >> 2));
+                atomicOr(touch + (q >> 6), 1ull << (q & 63));
+            }
+        }
+    }
+}
+
 template <int P, bool USE_LDS>
 __global__ void __launch_bounds__(1024)
-mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
+mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, int mark_next) {
     typedef typename Prec<P>::S S;
     typedef typename Prec<P>::R R;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -216,9 +298,11 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
     for (int v = threadIdx.x; v < nv; v += blockDim.x) {
         const double px = xs[3 * v], py = xs[3 * v + 1], pz = xs[3 * v + 2];
         R Fx = 0, Fy = 0, Fz = 0;
+        const int4 o0 = T->n_off[v], o1 = T->n_off[v + 1];
         if (do_s) {
             // F_v += ks kappa (L - L0)/L0 (x_u - x_v)/L  ("Stretching force")
-            for (int k = T->e_off[v]; k < T->e_off[v + 1]; ++k) {
+#pragma unroll 2
+            for (int k = o0.x; k < o1.x; ++k) {
                 const int2 ie = T->e_inc[k];
                 const R s = se[ie.y];
                 Fx += s * (R)(xs[3 * ie.x] - px);
@@ -227,32 +311,30 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
             }
         }
         if (do_b) {
-            // wings along their triangle's normal, edge ends minus half the sum ("Bending force")
-            for (int k = T->h_off[v]; k < T->h_off[v + 1]; ++k) {
-                const int code = T->h_inc[k];
-                const int e = code >> 2, role = code & 3;
-                const int2 ht = T->hinge_tri[e];
-                const R f = fh[e];
-                const R n1x = tn[4 * ht.x], n1y = tn[4 * ht.x + 1], n1z = tn[4 * ht.x + 2];
-                const R n2x = tn[4 * ht.y], n2y = tn[4 * ht.y + 1], n2z = tn[4 * ht.y + 2];
-                if (role == 0) {
-                    Fx += f * n1x; Fy += f * n1y; Fz += f * n1z;
-                } else if (role == 3) {
-                    Fx += f * n2x; Fy += f * n2y; Fz += f * n2z;
-                } else {
-                    const R hf = R(0.5) * f;
-                    Fx -= hf * (n1x + n2x); Fy -= hf * (n1y + n2y); Fz -= hf * (n1z + n2z);
-                }
+            // wings along their triangle's normal, edge ends minus half the sum
+            // ("Bending force"); the role picks the two coefficients
+#pragma unroll 4
+            for (int k = o0.y; k < o1.y; ++k) {
+                const int4 r = T->h_inc[k];
+                const int role = r.x & 3;
+                const R f = fh[r.x >> 2];
+                const R hf = R(-0.5) * f;
+                const R a1 = role == 0 ? f : (role == 3 ? R(0) : hf);
+                const R a2 = role == 3 ? f : (role == 0 ? R(0) : hf);
+                Fx += a1 * tn[4 * r.y] + a2 * tn[4 * r.z];
+                Fy += a1 * tn[4 * r.y + 1] + a2 * tn[4 * r.z + 1];
+                Fz += a1 * tn[4 * r.y + 2] + a2 * tn[4 * r.z + 2];
             }
         }
         // local area (-kal dS/S w), global area (-kag dSg/Sg w), volume
         // (-kv dV/V0 S n_out / 3); w = unit centroid -> vertex
-        for (int k = T->t_off[v]; k < T->t_off[v + 1]; ++k) {
-            const int t = T->t_inc[k] >> 2;
-            const int a = T->tri[3 * t], b = T->tri[3 * t + 1], c = T->tri[3 * t + 2];
-            const R wx = (R)(px - (xs[3 * a] + xs[3 * b] + xs[3 * c]) * (1.0 / 3.0));
-            const R wy = (R)(py - (xs[3 * a + 1] + xs[3 * b + 1] + xs[3 * c + 1]) * (1.0 / 3.0));
-            const R wz = (R)(pz - (xs[3 * a + 2] + xs[3 * b + 2] + xs[3 * c + 2]) * (1.0 / 3.0));
+#pragma unroll 2
+        for (int k = o0.z; k < o1.z; ++k) {
+            const int4 r = T->t_inc[k];
+            const int t = r.x;
+            const R wx = (R)(px - (px + xs[3 * r.y] + xs[3 * r.z]) * (1.0 / 3.0));
+            const R wy = (R)(py - (py + xs[3 * r.y + 1] + xs[3 * r.z + 1]) * (1.0 / 3.0));
+            const R wz = (R)(pz - (pz + xs[3 * r.y + 2] + xs[3 * r.z + 2]) * (1.0 / 3.0));
             const R ct = (-kal * tr[t] + cg) / sqrt(wx * wx + wy * wy + wz * wz);
             const R vf = cv * tn[4 * t + 3] * third;
             Fx += ct * wx - vf * tn[4 * t];
@@ -340,6 +422,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
         compact = ncomp <= ccap;  // block-uniform
         if (compact) {
             for (int k = threadIdx.x; k < 3 * ncomp; k += blockDim.x) gacc[k] = A(0);
+            // lattice index of every touched node, in compact numbering
             for (int idx = threadIdx.x; idx < vol; idx += blockDim.x) {
                 const unsigned word = need[idx >> 5];
                 if (!((word >> (idx & 31)) & 1u)) continue;
@@ -356,8 +439,12 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
                     gz %= nzb;
                     gz += gz < 0 ? nzb : 0;
                 }
-                const int q = (gz * nyb + gy) * nxb + gx;
-                qn[c] = q;
+                qn[c] = (gz * nyb + gy) * nxb + gx;
+            }
+            __syncthreads();
+            // fluid velocity there: one dense pass, all population loads in flight
+            for (int c = threadIdx.x; c < ncomp; c += blockDim.x) {
+                const int q = qn[c];
                 R dd[19];
 #pragma unroll
                 for (int i = 0; i < 19; ++i) dd[i] = dec<P>(pop[(size_t)i * Nb + q], inv);
@@ -478,9 +565,13 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
         O.V[3 * v] = vx;
         O.V[3 * v + 1] = vy;
         O.V[3 * v + 2] = vz;
-        O.X[3 * v] = px + (double)vx;
-        O.X[3 * v + 1] = py + (double)vy;
-        O.X[3 * v + 2] = pz + (double)vz;
+        const double qx = px + (double)vx, qy = py + (double)vy, qz = pz + (double)vz;
+        O.X[3 * v] = qx;
+        O.X[3 * v + 1] = qy;
+        O.X[3 * v + 2] = qz;
+        xs[3 * v] = qx;  // only this node's own entry is read in this loop
+        xs[3 * v + 1] = qy;
+        xs[3 * v + 2] = qz;
     }
     if (compact) {
         // one global atomic per touched lattice node and component
@@ -488,89 +579,22 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity) {
         for (int c = threadIdx.x; c < ncomp; c += blockDim.x)
             flags |= Acc<P>::flush(B, qn[c], gacc[3 * c], gacc[3 * c + 1], gacc[3 * c + 2]);
     }
+    // split stepping: the stencils of the new positions, for the next step
+    if (mark_next)
+        mark_object(xs, nv, O.anchor, B, ucap, need, bbox, B->touch[parity ^ 1]);
     if (flags) atomicOr(B->status, flags);
 }
 
-// Touch bits of this step: every lattice node inside the 2x2x2 stencil of a mesh
-// node (the nodes the membrane kernel will read populations from and spread
-// to).  One workgroup per object; the object's stencil box is marked in an LDS
-// bitmask first, so each touched node costs one global atomic, not one per
-// corner.  Oversize boxes fall back to per-corner atomics.
+// Touch bits of a step of parity `parity` from the current positions (split
+// stepping, when the membrane kernel of the previous step did not mark them).
+// One workgroup per object.
 template <typename R>
-__global__ void __launch_bounds__(256) mark_kernel(const ObjDev<R>* __restrict__ objs) {
-    extern __shared__ unsigned bits[];
+__global__ void __launch_bounds__(256) mark_kernel(const ObjDev<R>* __restrict__ objs, int parity, int cap) {
+    extern __shared__ unsigned bits[];  // cap bits
     __shared__ int bbox[6];
     const ObjDev<R>& O = objs[blockIdx.x];
-    const TmplDev<R>* __restrict__ T = O.t;
     const BoxDev* __restrict__ B = O.box;
-    const int nv = T->nv;
-    const int nxb = B->nx, nyb = B->ny, nzb = B->nz;
-    if (threadIdx.x == 0) {
-        bbox[0] = bbox[1] = bbox[2] = INT_MAX;
-        bbox[3] = bbox[4] = bbox[5] = INT_MIN;
-    }
-    __syncthreads();
-    int blo[3] = {INT_MAX, INT_MAX, INT_MAX}, bhi[3] = {INT_MIN, INT_MIN, INT_MIN};
-    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-        const double sx = O.X[3 * v] - 0.5, sy = O.X[3 * v + 1] - 0.5, sz = O.X[3 * v + 2] - 0.5;
-        if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
-        const int bx = O.anchor[0] + (int)floor(sx), by = O.anchor[1] + (int)floor(sy),
-                  bz = O.anchor[2] + (int)floor(sz);
-        blo[0] = min(blo[0], bx); blo[1] = min(blo[1], by); blo[2] = min(blo[2], bz);
-        bhi[0] = max(bhi[0], bx); bhi[1] = max(bhi[1], by); bhi[2] = max(bhi[2], bz);
-    }
-    wave_bbox_to_block(blo, bhi, bbox);
-    __syncthreads();
-    const int ox = bbox[0], oy = bbox[1], oz = bbox[2];
-    const long long exl = (long long)bbox[3] - ox + 2, eyl = (long long)bbox[4] - oy + 2,
-                    ezl = (long long)bbox[5] - oz + 2;
-    if (bbox[3] < bbox[0]) return;  // no finite node (block-uniform)
-    auto lattice_index = [&](int gx, int gy, int gz) {
-        gx %= nxb;
-        gx += gx < 0 ? nxb : 0;
-        gy %= nyb;
-        gy += gy < 0 ? nyb : 0;
-        if (B->walls_z) {
-            gz = gz < 0 ? 0 : (gz >= nzb ? nzb - 1 : gz);
-        } else {
-            gz %= nzb;
-            gz += gz < 0 ? nzb : 0;
-        }
-        return (gz * nyb + gy) * nxb + gx;
-    };
-    if (exl * eyl * ezl <= (long long)T->ucap) {
-        const int ex = (int)exl, exy = (int)(exl * eyl), vol = (int)(exl * eyl * ezl);
-        for (int k = threadIdx.x; k < (vol + 31) / 32; k += blockDim.x) bits[k] = 0u;
-        __syncthreads();
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-            const double sx = O.X[3 * v] - 0.5, sy = O.X[3 * v + 1] - 0.5, sz = O.X[3 * v + 2] - 0.5;
-            if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
-            const int b0 = (O.anchor[2] + (int)floor(sz) - oz) * exy + (O.anchor[1] + (int)floor(sy) - oy) * ex +
-                           (O.anchor[0] + (int)floor(sx) - ox);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int idx = b0 + (k >> 2) * exy + ((k >> 1) & 1) * ex + (k & 1);
-                atomicOr(&bits[idx >> 5], 1u << (idx & 31));
-            }
-        }
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < vol; idx += blockDim.x) {
-            if (!((bits[idx >> 5] >> (idx & 31)) & 1u)) continue;
-            const int q = lattice_index(ox + idx % ex, oy + (idx / ex) % (int)eyl, oz + idx / exy);
-            atomicOr(B->touch + (q >> 6), 1ull << (q & 63));
-        }
-    } else {
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-            const double sx = O.X[3 * v] - 0.5, sy = O.X[3 * v + 1] - 0.5, sz = O.X[3 * v + 2] - 0.5;
-            if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
-            const int bx = O.anchor[0] + (int)floor(sx), by = O.anchor[1] + (int)floor(sy),
-                      bz = O.anchor[2] + (int)floor(sz);
-            for (int k = 0; k < 8; ++k) {
-                const int q = lattice_index(bx + (k & 1), by + ((k >> 1) & 1), bz + (k >> 2));
-                atomicOr(B->touch + (q >> 6), 1ull << (q & 63));
-            }
-        }
-    }
+    mark_object(O.X, O.t->nv, O.anchor, B, min(O.t->ucap, cap), bits, bbox, B->touch[parity]);
 }
 
 template <typename R>
@@ -600,9 +624,10 @@ hipError_t launch_mesh_p(const MeshLaunch& L) {
     const ObjDev<R>* objs = (const ObjDev<R>*)L.objs;
     if (L.lds_bytes > 0)
         hipLaunchKernelGGL((mesh_kernel<P, true>), dim3(L.nobj), dim3(L.block), L.lds_bytes, L.stream, objs,
-                           L.parity);
+                           L.parity, L.mark_next);
     else
-        hipLaunchKernelGGL((mesh_kernel<P, false>), dim3(L.nobj), dim3(L.block), 0, L.stream, objs, L.parity);
+        hipLaunchKernelGGL((mesh_kernel<P, false>), dim3(L.nobj), dim3(L.block), 0, L.stream, objs, L.parity,
+                           L.mark_next);
     return hipGetLastError();
 }
 
@@ -635,12 +660,16 @@ hipError_t mesh_set_max_lds(size_t bytes) {
     return e;
 }
 
-hipError_t launch_mark(const void* objs, int nobj, int precision, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_mark(const void* objs, int nobj, int precision, size_t lds_bytes, int parity,
+                       hipStream_t s) {
     if (nobj <= 0) return hipSuccess;
+    const int cap = (int)(lds_bytes / 4) * 32;
     if (precision == PREC_FP64)
-        hipLaunchKernelGGL(mark_kernel<double>, dim3(nobj), dim3(256), lds_bytes, s, (const ObjDev<double>*)objs);
+        hipLaunchKernelGGL(mark_kernel<double>, dim3(nobj), dim3(256), lds_bytes, s, (const ObjDev<double>*)objs,
+                           parity, cap);
     else
-        hipLaunchKernelGGL(mark_kernel<float>, dim3(nobj), dim3(256), lds_bytes, s, (const ObjDev<float>*)objs);
+        hipLaunchKernelGGL(mark_kernel<float>, dim3(nobj), dim3(256), lds_bytes, s, (const ObjDev<float>*)objs,
+                           parity, cap);
     return hipGetLastError();
 }
 

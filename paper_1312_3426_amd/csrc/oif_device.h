@@ -31,7 +31,10 @@ struct BoxDev {
     void* f[2];
     void* G;
     unsigned long long* mask;
-    unsigned long long* touch;  // one bit per node inside any stencil of the current step
+    // Split (overlapped) stepping, double-buffered by population parity:
+    // touch[k] has one bit per node inside some mesh node's 2x2x2 stencil at
+    // the start of a step of parity k.
+    unsigned long long* touch[2];
     unsigned* status;
     double g[3];
     double rho0;
@@ -49,17 +52,17 @@ struct TmplDev {
     int nv, nt, ne;
     int linear;
     const int* tri;        // [nt][3]
-    const int* e_off;      // [nv + 1] incident edges of each node
+    // Per-node incidence lists (CSR).  Each entry holds everything the node's
+    // gather needs besides LDS data, so the entries of a node are independent
+    // loads with no second indirection.
+    const int4* n_off;     // [nv + 1] (edge, hinge, triangle) list offsets
     const int2* e_inc;     // (neighbour node, edge id)
+    const int4* h_inc;     // (hinge id << 2 | role, T1, T2, 0); role 0 = A, 1 = B, 2 = C, 3 = D
+    const int4* t_inc;     // (triangle, next vertex, vertex after that, 0) in the triangle's order
     const double* L0;      // [ne] (FP64: L - L0 cancels near the relaxed shape)
-    const int* h_off;      // [nv + 1] incident hinges of each node
-    const int* h_inc;      // hinge id << 2 | role (0 = A, 1 = B, 2 = C, 3 = D)
     const int4* hinge;     // (A, B, C, D): T1 = (A, B, C) runs B -> C, T2 has wing D
-    const int2* hinge_tri; // (T1, T2)
     const double* theta0;  // [ne] relaxed inner dihedral angle
     const double2* cs0;    // [ne] cos and sin of theta0 - pi (FP64)
-    const int* t_off;      // [nv + 1] incident triangles of each node
-    const int* t_inc;      // triangle id << 2 | slot
     const double* S0;      // [nt] (FP64: S - S0 cancels near the relaxed shape)
     double Sg0, V0;
     double ks, kb, kal, kag, kv;
@@ -123,8 +126,8 @@ struct ObjDev {
 // Which nodes a lattice launch updates.
 enum : int {
     LB_ALL = 0,      // every node (coupling force read where the mask says so)
-    LB_FREE = 1,     // only nodes whose touch bit is clear (no coupling force there)
-    LB_TOUCHED = 2,  // only nodes whose touch bit is set; clears touch, mask and G
+    LB_FREE = 1,     // only nodes whose touch bit (touch[parity]) is clear
+    LB_TOUCHED = 2,  // only nodes whose touch bit is set; clears touch[parity], mask and G
 };
 
 struct LbLaunch {
@@ -140,9 +143,10 @@ struct LbLaunch {
 };
 hipError_t launch_lb(const LbLaunch& L);
 
-// Set the touch bits of every lattice node inside the 2x2x2 stencil of any
+// Set touch[parity] bits of every lattice node inside the 2x2x2 stencil of any
 // mesh node of the given objects (one workgroup per object).
-hipError_t launch_mark(const void* objs, int nobj, int precision, size_t lds_bytes, hipStream_t s);
+hipError_t launch_mark(const void* objs, int nobj, int precision, size_t lds_bytes, int parity,
+                       hipStream_t s);
 
 struct MeshLaunch {
     const void* objs;      // device array of ObjDev<real>
@@ -151,6 +155,8 @@ struct MeshLaunch {
     int parity;
     int precision;
     size_t lds_bytes;      // dynamic LDS per block (0 = each object's global scratch)
+    int mark_next;         // also mark the stencils of the new positions in
+                           // touch[parity ^ 1] (split stepping)
     hipStream_t stream;
 };
 hipError_t launch_mesh(const MeshLaunch& L);

@@ -237,11 +237,12 @@ struct oif_ctx {
     void* f[2] = {nullptr, nullptr};
     void* G = nullptr;
     unsigned long long* mask = nullptr;
-    unsigned long long* touch = nullptr;
+    unsigned long long* touch[2] = {nullptr, nullptr};
     unsigned* status = nullptr;
     hipStream_t side = nullptr;          // lattice update of untouched nodes
     hipEvent_t ev_mark = nullptr, ev_free = nullptr;
     int overlap = 0;
+    bool touch_valid = false;            // touch[parity] matches the current positions
     size_t mark_lds = 0;
     BoxDev box{};
     BoxDev* box_dev = nullptr;
@@ -372,20 +373,25 @@ int upload_mesh_t(oif_ctx* c) {
             cs0[2 * e] = std::cos(T.theta0[e] - M_PI);
             cs0[2 * e + 1] = std::sin(T.theta0[e] - M_PI);
         }
-        std::vector<int4> hv(T.ne);
-        std::vector<int2> ht(T.ne), einc(T.e_inc.size());
-        for (int e = 0; e < T.ne; ++e) {
+        std::vector<int4> hv(T.ne), noff((size_t)T.nv + 1), hinc(T.h_inc.size()), tinc(T.t_inc.size());
+        std::vector<int2> einc(T.e_inc.size());
+        for (int e = 0; e < T.ne; ++e)
             hv[e] = make_int4(T.hinge[e][0], T.hinge[e][1], T.hinge[e][2], T.hinge[e][3]);
-            ht[e] = make_int2(T.hinge_tri[e][0], T.hinge_tri[e][1]);
-        }
+        for (int v = 0; v <= T.nv; ++v) noff[v] = make_int4(T.e_off[v], T.h_off[v], T.t_off[v], 0);
         for (size_t k = 0; k < T.e_inc.size(); ++k) einc[k] = make_int2(T.e_inc[k][0], T.e_inc[k][1]);
-        parts = {{T.tri.data(), T.tri.size() * 4},       {T.e_off.data(), T.e_off.size() * 4},
-                 {einc.data(), einc.size() * 8},         {L0.data(), L0.size() * sizeof(double)},
-                 {T.h_off.data(), T.h_off.size() * 4},   {T.h_inc.data(), T.h_inc.size() * 4},
-                 {hv.data(), hv.size() * 16},            {ht.data(), ht.size() * 8},
-                 {th.data(), th.size() * sizeof(double)}, {T.t_off.data(), T.t_off.size() * 4},
-                 {T.t_inc.data(), T.t_inc.size() * 4},   {S0.data(), S0.size() * sizeof(double)},
-                 {cs0.data(), cs0.size() * sizeof(double)}};
+        for (size_t k = 0; k < T.h_inc.size(); ++k) {
+            const int e = T.h_inc[k] >> 2;
+            hinc[k] = make_int4(T.h_inc[k], T.hinge_tri[e][0], T.hinge_tri[e][1], 0);
+        }
+        for (size_t k = 0; k < T.t_inc.size(); ++k) {
+            const int t = T.t_inc[k] >> 2, s3 = T.t_inc[k] & 3;
+            tinc[k] = make_int4(t, T.tri[3 * t + (s3 + 1) % 3], T.tri[3 * t + (s3 + 2) % 3], 0);
+        }
+        parts = {{T.tri.data(), T.tri.size() * 4},        {noff.data(), noff.size() * 16},
+                 {einc.data(), einc.size() * 8},          {hinc.data(), hinc.size() * 16},
+                 {tinc.data(), tinc.size() * 16},         {L0.data(), L0.size() * sizeof(double)},
+                 {hv.data(), hv.size() * 16},             {th.data(), th.size() * sizeof(double)},
+                 {cs0.data(), cs0.size() * sizeof(double)}, {S0.data(), S0.size() * sizeof(double)}};
         std::vector<size_t> offs;
         size_t total = 0;
         for (auto& p : parts) {
@@ -402,18 +408,15 @@ int upload_mesh_t(oif_ctx* c) {
         D.nv = T.nv; D.nt = T.nt; D.ne = T.ne;
         D.linear = T.k.stretch_law == OIF_STRETCH_LINEAR;
         D.tri = (const int*)(b + offs[0]);
-        D.e_off = (const int*)(b + offs[1]);
+        D.n_off = (const int4*)(b + offs[1]);
         D.e_inc = (const int2*)(b + offs[2]);
-        D.L0 = (const double*)(b + offs[3]);
-        D.h_off = (const int*)(b + offs[4]);
-        D.h_inc = (const int*)(b + offs[5]);
+        D.h_inc = (const int4*)(b + offs[3]);
+        D.t_inc = (const int4*)(b + offs[4]);
+        D.L0 = (const double*)(b + offs[5]);
         D.hinge = (const int4*)(b + offs[6]);
-        D.hinge_tri = (const int2*)(b + offs[7]);
-        D.theta0 = (const double*)(b + offs[8]);
-        D.t_off = (const int*)(b + offs[9]);
-        D.t_inc = (const int*)(b + offs[10]);
-        D.S0 = (const double*)(b + offs[11]);
-        D.cs0 = (const double2*)(b + offs[12]);
+        D.theta0 = (const double*)(b + offs[7]);
+        D.cs0 = (const double2*)(b + offs[8]);
+        D.S0 = (const double*)(b + offs[9]);
         D.Sg0 = T.Sg0; D.V0 = T.V0;
         D.ks = T.k.ks; D.kb = T.k.kb; D.kal = T.k.kal; D.kag = T.k.kag; D.kv = T.k.kv;
         D.ucap = T.ucap;
@@ -457,6 +460,7 @@ int upload_mesh_t(oif_ctx* c) {
     c->lds_need = 0;
     c->mark_lds = 16;
     for (const Template& T : c->tmpl) c->mark_lds = std::max(c->mark_lds, (size_t)((T.ucap + 31) / 32) * 4);
+    c->mark_lds = std::min<size_t>(c->mark_lds, 49152);  // larger stencil boxes mark corner by corner
     size_t scratch_total = 0;
     for (int i : order) {
         if (need(i) <= budget) {
@@ -505,6 +509,7 @@ int sync_mesh(oif_ctx* c) {
     rc = is_fp64(c) ? upload_mesh_t<double>(c) : upload_mesh_t<float>(c);
     if (rc) return rc;
     c->mesh_dirty = false;
+    c->touch_valid = false;
     return OIF_OK;
 }
 
@@ -520,11 +525,12 @@ inline void rec(hipEvent_t e, hipStream_t s) {
     if (e) (void)hipEventRecord(e, s);
 }
 
-int enqueue_mesh(oif_ctx* c, int par, hipStream_t s) {
+int enqueue_mesh(oif_ctx* c, int par, hipStream_t s, int mark_next) {
     const size_t osz = objdev_size(c->d.precision);
     MeshLaunch ml{};
     ml.block = c->mesh_block;
     ml.parity = par;
+    ml.mark_next = mark_next;
     ml.precision = c->d.precision;
     ml.stream = s;
     if (c->n_lds_obj > 0) {
@@ -557,25 +563,40 @@ int enqueue_lb(oif_ctx* c, int par, hipStream_t s, int mode) {
     return OIF_OK;
 }
 
+// Touch bits of the step of parity c->parity from the current positions, when
+// the membrane kernel of the previous step did not leave them (first split
+// step, mesh written by the host, a step without split).  Never inside a
+// captured graph.
+int ensure_touch(oif_ctx* c) {
+    if (c->touch_valid || !c->overlap || c->obj.empty()) return OIF_OK;
+    const size_t nmask = ((size_t)c->N + 63) / 64;
+    HIPCALL(c, hipMemsetAsync(c->touch[0], 0, 8 * nmask, c->stream));
+    HIPCALL(c, hipMemsetAsync(c->touch[1], 0, 8 * nmask, c->stream));
+    HIPCALL(c, launch_mark(c->obj_dev.p, (int)c->obj.size(), c->d.precision, c->mark_lds, c->parity, c->stream));
+    c->touch_valid = true;
+    return OIF_OK;
+}
+
 // One coupled step.  Without objects, or with overlap off: membrane kernel then
-// lattice kernel on `s`.  With overlap: the touch bits of this step's stencils
-// are marked first; the lattice update of the untouched nodes then runs on the
-// side stream while the membrane kernel runs on `s`, and the touched nodes are
-// updated once both are done (they need the spread coupling force).
+// lattice kernel on `s`.  With overlap (split stepping): the lattice update of
+// the nodes outside every stencil of this step runs on the side stream while
+// the membrane kernel runs on `s` (it also marks the stencils of the new
+// positions for the next step); the stencil nodes are updated once both are
+// done, since they need the spread coupling force.
 int enqueue_one(oif_ctx* c, int par, hipStream_t s, const StepEvents* ev) {
     StepEvents none;
     const StepEvents& E = ev ? *ev : none;
     int rc;
     if (c->obj.empty() || !c->overlap) {
         rec(E.t0, s);
-        if (!c->obj.empty() && (rc = enqueue_mesh(c, par, s))) return rc;
+        if (!c->obj.empty() && (rc = enqueue_mesh(c, par, s, 0))) return rc;
         rec(E.t_mesh, s);
         if ((rc = enqueue_lb(c, par, s, LB_ALL))) return rc;
         rec(E.t_lb, s);
+        c->touch_valid = false;
         return OIF_OK;
     }
     rec(E.t0, s);
-    HIPCALL(c, launch_mark(c->obj_dev.p, (int)c->obj.size(), c->d.precision, c->mark_lds, s));
     rec(E.t_mark, s);
     HIPCALL(c, hipEventRecord(c->ev_mark, s));
     HIPCALL(c, hipStreamWaitEvent(c->side, c->ev_mark, 0));
@@ -583,7 +604,7 @@ int enqueue_one(oif_ctx* c, int par, hipStream_t s, const StepEvents* ev) {
     if ((rc = enqueue_lb(c, par, c->side, LB_FREE))) return rc;
     rec(E.f1, c->side);
     HIPCALL(c, hipEventRecord(c->ev_free, c->side));
-    if ((rc = enqueue_mesh(c, par, s))) return rc;
+    if ((rc = enqueue_mesh(c, par, s, 1))) return rc;
     rec(E.t_mesh, s);
     HIPCALL(c, hipStreamWaitEvent(s, c->ev_free, 0));
     rec(E.t_wait, s);
@@ -634,6 +655,7 @@ int step_impl(oif_ctx* c, int n) {
     int rc = sync_mesh(c);
     if (rc) return rc;
     HIPCALL(c, hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream));
+    if ((rc = ensure_touch(c))) return rc;
     int left = n;
     if (c->graph_steps > 0 && n >= c->graph_steps) {
         if (c->parity) {  // the captured graph starts at parity 0
@@ -736,7 +758,8 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     const size_t nmask = ((size_t)N + 63) / 64;
     int rc = OIF_OK;
     if ((rc = alloc(&c->f[0], popb)) || (rc = alloc(&c->f[1], popb)) || (rc = alloc(&c->G, 24 * (size_t)N)) ||
-        (rc = alloc((void**)&c->mask, 8 * nmask)) || (rc = alloc((void**)&c->touch, 8 * nmask)) ||
+        (rc = alloc((void**)&c->mask, 8 * nmask)) || (rc = alloc((void**)&c->touch[0], 8 * nmask)) ||
+        (rc = alloc((void**)&c->touch[1], 8 * nmask)) ||
         (rc = alloc((void**)&c->status, 256)) ||
         (rc = alloc((void**)&c->box_dev, sizeof(BoxDev)))) {
         oif_destroy(c.release());
@@ -746,7 +769,8 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
         hipMemsetAsync(c->f[1], 0, popb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->G, 0, 24 * (size_t)N, c->stream) != hipSuccess ||
         hipMemsetAsync(c->mask, 0, 8 * nmask, c->stream) != hipSuccess ||
-        hipMemsetAsync(c->touch, 0, 8 * nmask, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->touch[0], 0, 8 * nmask, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->touch[1], 0, 8 * nmask, c->stream) != hipSuccess ||
         hipMemsetAsync(c->status, 0, 256, c->stream) != hipSuccess) {
         oif_destroy(c.release());
         return OIF_E_HIP;
@@ -758,7 +782,8 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     b.f[0] = c->f[0]; b.f[1] = c->f[1];
     b.G = c->G;
     b.mask = c->mask;
-    b.touch = c->touch;
+    b.touch[0] = c->touch[0];
+    b.touch[1] = c->touch[1];
     b.status = c->status;
     for (int k = 0; k < 3; ++k) b.g[k] = d.body_force[k];
     b.rho0 = d.rho0;
@@ -785,7 +810,8 @@ int oif_destroy(oif_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
     if (c->side) (void)hipStreamSynchronize(c->side);
-    for (void* p : {c->f[0], c->f[1], c->G, (void*)c->mask, (void*)c->touch, (void*)c->status, (void*)c->box_dev})
+    for (void* p : {c->f[0], c->f[1], c->G, (void*)c->mask, (void*)c->touch[0], (void*)c->touch[1],
+                    (void*)c->status, (void*)c->box_dev})
         if (p) (void)hipFree(p);
     for (auto& b : c->tbufs) b.release();
     for (DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->geo_dev, &c->scratch_dev,
@@ -949,6 +975,7 @@ int oif_step_timed(oif_ctx* c, int n, oif_timing* t) {
     int rc = sync_mesh(c);
     if (rc) return rc;
     HIPCALL(c, hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream));
+    if ((rc = ensure_touch(c))) return rc;
     const bool split = c->overlap && !c->obj.empty();
     std::vector<StepEvents> ev((size_t)n);
     std::vector<hipEvent_t> all;
@@ -1014,6 +1041,7 @@ int oif_set_overlap(oif_ctx* c, int on) {
     HIPCALL(c, hipStreamSynchronize(c->stream));
     HIPCALL(c, hipStreamSynchronize(c->side));
     c->overlap = on ? 1 : 0;
+    c->touch_valid = false;
     drop_graph(c);
     return OIF_OK;
 }
@@ -1313,6 +1341,7 @@ int snapshot(oif_ctx* c, Snapshot& s, bool restore) {
             HIPCALL(c, hipMemcpyAsync(c->V_dev.p, s.v.p, mb, hipMemcpyDeviceToDevice, c->stream));
         }
         HIPCALL(c, hipStreamSynchronize(c->stream));
+        c->touch_valid = false;
         s.f.release();
         s.x.release();
         s.v.release();
@@ -1492,6 +1521,7 @@ int batch_finish(oif_batch* b, int n) {
     for (oif_ctx* c : b->ctx) {
         c->parity ^= (n & 1);
         c->steps += n;
+        c->touch_valid = false;  // batched steps do not mark stencils
         if (c->M) c->host_stale = true;
     }
     for (oif_ctx* c : b->ctx) {
