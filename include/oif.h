@@ -236,9 +236,11 @@ int oif_set_graph(oif_ctx* ctx, int steps_per_graph);
  * result is identical to the sequential order; 0 runs the step sequentially. */
 int oif_set_overlap(oif_ctx* ctx, int on);
 
-/* Launch shapes: lb_block in {64,128,256,512,1024}, mesh_block in
- * {64,128,256,512,1024}; xcd_remap 0/1 maps consecutive lattice blocks to the
- * same XCD.  Values < 0 keep the current setting. */
+/* Launch shapes: lb_block in {64,128,256,512,1024}, mesh_block a multiple of
+ * 64 in [64, 1024] (one workgroup per object: block sizes that let two objects
+ * share a compute unit matter more than powers of two); xcd_remap 0/1 maps
+ * consecutive lattice blocks to the same XCD.  Values < 0 keep the current
+ * setting. */
 int oif_set_launch(oif_ctx* ctx, int lb_block, int mesh_block, int xcd_remap);
 
 /* Measured search of the launch shapes on this context's workload; the

@@ -73,6 +73,58 @@ __device__ __forceinline__ uint16_t enc<PREC_BF16>(float r, float) {
     return (uint16_t)(u >> 16);
 }
 
+// Device-memory access through descriptor pointers.  Pointers read from the
+// box, template and object descriptors are generic to the compiler, which then
+// emits flat instructions (a 64-bit VGPR address per access, waits on both the
+// LDS and the vector-memory counters).  These helpers place the access in the
+// global address space as a base plus a 32-bit byte offset, so a uniform base
+// stays in SGPRs and one VGPR offset serves all 19 populations of a node.
+// Every array addressed this way is below 4 GiB (the context limits 19 N to
+// 2^31 elements).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ T gload(const T* base, unsigned byte_off) {
+    return *(gptr<const T>)((gptr<const char>)base + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T* base, unsigned byte_off, T v) {
+    *(gptr<T>)((gptr<char>)base + byte_off) = v;
+}
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+    return *(gptr<const T>)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+    *(gptr<T>)p = v;
+}
+// HIP's vector types are classes: load their native vector and repack
+__device__ __forceinline__ int2 gld(const int2* p) {
+    typedef int v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *(gptr<const v2>)p;
+    return make_int2(v.x, v.y);
+}
+__device__ __forceinline__ int4 gld(const int4* p) {
+    typedef int v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *(gptr<const v4>)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 gld(const double2* p) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *(gptr<const v2>)p;
+    return make_double2(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ T gatomic_add(T* p, T v) {
+    return __hip_atomic_fetch_add((gptr<T>)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T gatomic_or(T* p, T v) {
+    return __hip_atomic_fetch_or((gptr<T>)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Block-wide FP64 sum with a fixed combination order: a butterfly inside each
 // 64-lane wave (every lane ends with the same value), then the per-wave sums
 // added in wave order.  Deterministic for a given block size.  `red` must hold

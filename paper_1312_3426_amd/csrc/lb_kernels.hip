@@ -26,23 +26,24 @@ __device__ __forceinline__ void take_force(const BoxDev* __restrict__ B, int p, 
                                            typename Prec<P>::R& fy, typename Prec<P>::R& fz) {
     typedef typename Prec<P>::R R;
     const int N = B->N;
+    const unsigned o = (unsigned)p * 8u;
     if (P == PREC_FP64) {
         double* G = (double*)B->G;
-        fx += (R)G[p];
-        fy += (R)G[N + p];
-        fz += (R)G[2 * N + p];
-        G[p] = 0.0;
-        G[N + p] = 0.0;
-        G[2 * N + p] = 0.0;
+        fx += (R)gload(G, o);
+        fy += (R)gload(G + N, o);
+        fz += (R)gload(G + 2 * (size_t)N, o);
+        gstore(G, o, 0.0);
+        gstore(G + N, o, 0.0);
+        gstore(G + 2 * (size_t)N, o, 0.0);
     } else {
         long long* G = (long long*)B->G;
         const double s = B->fp_inv;
-        fx += (R)((double)G[p] * s);
-        fy += (R)((double)G[N + p] * s);
-        fz += (R)((double)G[2 * N + p] * s);
-        G[p] = 0;
-        G[N + p] = 0;
-        G[2 * N + p] = 0;
+        fx += (R)((double)gload(G, o) * s);
+        fy += (R)((double)gload(G + N, o) * s);
+        fz += (R)((double)gload(G + 2 * (size_t)N, o) * s);
+        gstore(G, o, 0ll);
+        gstore(G + N, o, 0ll);
+        gstore(G + 2 * (size_t)N, o, 0ll);
     }
 }
 
@@ -60,7 +61,7 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
 
     R d[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = dec<P>(src[(size_t)i * N + p], inv);
+    for (int i = 0; i < 19; ++i) d[i] = dec<P>(gload(src + (size_t)i * N, (unsigned)p * (unsigned)sizeof(S)), inv);
 
     R drho = 0;
 #pragma unroll
@@ -103,12 +104,12 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
         const S out = enc<P>(ds, scale);
         const bool bounce = (cz(i) > 0 && whi) || (cz(i) < 0 && wlo);
         if (bounce) {
-            dst[(size_t)opp(i) * N + p] = out;
+            gstore(dst + (size_t)opp(i) * N, (unsigned)p * (unsigned)sizeof(S), out);
         } else {
             const int off = (cx(i) > 0 ? oxp : (cx(i) < 0 ? oxm : 0)) +
                             (cy(i) > 0 ? oyp : (cy(i) < 0 ? oym : 0)) +
                             (cz(i) > 0 ? ozp : (cz(i) < 0 ? ozm : 0));
-            dst[(size_t)i * N + p + off] = out;
+            gstore(dst + (size_t)i * N, (unsigned)(p + off) * (unsigned)sizeof(S), out);
         }
     }
 }
@@ -143,23 +144,23 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
     unsigned long long* mk = B->mask + (p >> 6);
     unsigned long long m = 0ull;
     if (mode == LB_ALL) {
-        m = *mk;
-        if (m && (p & 63) == 0) *mk = 0ull;
+        m = gld(mk);
+        if (m && (p & 63) == 0) gst(mk, 0ull);
     } else {
         // split update: the nodes outside every stencil of this step run while
         // the membrane kernel spreads (no coupling force can reach them), the
         // others after it
         unsigned long long* tw = B->touch[parity] + (p >> 6);
-        const unsigned long long tb = *tw;
+        const unsigned long long tb = gld(tw);
         const bool mine = (tb >> (p & 63)) & 1ull;
         if (mode == LB_FREE) {
             if (mine) return;
         } else {
             if (tb == 0ull) return;  // the whole wave is untouched
-            m = *mk;
+            m = gld(mk);
             if ((p & 63) == 0) {
-                *tw = 0ull;
-                if (m) *mk = 0ull;
+                gst(tw, 0ull);
+                if (m) gst(mk, 0ull);
             }
             if (!mine) return;
         }

@@ -49,13 +49,13 @@ struct Acc {
         atomicAdd(acc + 2, c);
         return fl;
     }
-    __device__ static unsigned flush(const BoxDev* B, int q, T x, T y, T z) {
+    __device__ static unsigned flush(gptr<const BoxDev> B, int q, T x, T y, T z) {
         if ((x | y | z) == 0ull) return 0u;
         T* G = (T*)B->G;
-        atomicAdd(G + q, x);
-        atomicAdd(G + B->N + q, y);
-        atomicAdd(G + 2 * B->N + q, z);
-        atomicOr(B->mask + (q >> 6), 1ull << (q & 63));
+        gatomic_add(G + q, x);
+        gatomic_add(G + B->N + q, y);
+        gatomic_add(G + 2 * (size_t)B->N + q, z);
+        gatomic_or(B->mask + (q >> 6), 1ull << (q & 63));
         return 0u;
     }
 };
@@ -70,20 +70,20 @@ struct Acc<PREC_FP64> {
         atomicAdd(acc + 2, z);
         return 0u;
     }
-    __device__ static unsigned flush(const BoxDev* B, int q, T x, T y, T z) {
+    __device__ static unsigned flush(gptr<const BoxDev> B, int q, T x, T y, T z) {
         if (x == 0.0 && y == 0.0 && z == 0.0) return 0u;
         T* G = (T*)B->G;
-        atomicAdd(G + q, x);
-        atomicAdd(G + B->N + q, y);
-        atomicAdd(G + 2 * B->N + q, z);
-        atomicOr(B->mask + (q >> 6), 1ull << (q & 63));
+        gatomic_add(G + q, x);
+        gatomic_add(G + B->N + q, y);
+        gatomic_add(G + 2 * (size_t)B->N + q, z);
+        gatomic_or(B->mask + (q >> 6), 1ull << (q & 63));
         return 0u;
     }
 };
 
 // Lattice index of the (unwrapped) node (gx, gy, gz): periodic in x and y,
 // periodic or clamped to the walls in z.
-__device__ __forceinline__ int lattice_node(const BoxDev* __restrict__ B, int gx, int gy, int gz) {
+__device__ __forceinline__ int lattice_node(gptr<const BoxDev> B, int gx, int gy, int gz) {
     const int nxb = B->nx, nyb = B->ny, nzb = B->nz;
     gx %= nxb;
     gx += gx < 0 ? nxb : 0;
@@ -98,13 +98,33 @@ __device__ __forceinline__ int lattice_node(const BoxDev* __restrict__ B, int gx
     return (gz * nyb + gy) * nxb + gx;
 }
 
+// q = a / d, r = a % d for 0 <= a < 2^20 and 0 < d, without an integer
+// division: the float estimate a * (1/d) is within one of the quotient.
+__device__ __forceinline__ void divmod_small(int a, int d, float rd, int& q, int& r) {
+    q = (int)((float)a * rd);
+    r = a - q * d;
+    if (r < 0) {
+        --q;
+        r += d;
+    } else if (r >= d) {
+        ++q;
+        r -= d;
+    }
+}
+
+// a mod n in [0, n)
+__device__ __forceinline__ int wrap_mod(int a, int n) {
+    const int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
 // Stencil marking of one object for split stepping: every lattice node inside
 // the 2x2x2 stencil of a finite node position gets its bit in `touch`.  The
 // object's stencil box is marked in the bitmask `bits` ((ucap + 31)/32 words)
 // first when it fits, so each touched node costs one global atomic however
 // many stencils contain it; otherwise every corner goes to `touch` directly.
 // Called by the whole workgroup.
-__device__ void mark_object(const double* pos, int nv, const int* anchor, const BoxDev* __restrict__ B,
+__device__ void mark_object(const double* pos, int nv, const int* anchor, gptr<const BoxDev> B,
                             int ucap, unsigned* bits, int* bbox, unsigned long long* touch) {
     __syncthreads();  // earlier users of bits and bbox are done
     if (threadIdx.x == 0) {
@@ -147,7 +167,7 @@ __device__ void mark_object(const double* pos, int nv, const int* anchor, const 
         for (int idx = threadIdx.x; idx < vol; idx += blockDim.x) {
             if (!((bits[idx >> 5] >> (idx & 31)) & 1u)) continue;
             const int q = lattice_node(B, ox + idx % ex, oy + (idx / ex) % (int)eyl, oz + idx / exy);
-            atomicOr(touch + (q >> 6), 1ull << (q & 63));
+            gatomic_or(touch + (q >> 6), 1ull << (q & 63));
         }
     } else {
         for (int v = threadIdx.x; v < nv; v += blockDim.x) {
@@ -157,7 +177,7 @@ __device__ void mark_object(const double* pos, int nv, const int* anchor, const 
                       bz = anchor[2] + (int)floor(sz);
             for (int k = 0; k < 8; ++k) {
                 const int q = lattice_node(B, bx + (k & 1), by + ((k >> 1) & 1), bz + (k >> 2));
-                atomicOr(touch + (q >> 6), 1ull << (q & 63));
+                gatomic_or(touch + (q >> 6), 1ull << (q & 63));
             }
         }
     }
@@ -172,8 +192,8 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     __shared__ double red[16];
 
     const ObjDev<R>& O = objs[blockIdx.x];
-    const TmplDev<R>* __restrict__ T = O.t;
-    const BoxDev* __restrict__ B = O.box;
+    const gptr<const TmplDev<R>> T = (gptr<const TmplDev<R>>)O.t;
+    const gptr<const BoxDev> B = (gptr<const BoxDev>)O.box;
     const int nv = T->nv, nt = T->nt, ne = T->ne;
     const int ucap = T->ucap, ccap = T->ccap;
     const MeshLayout lay = mesh_layout(sizeof(R), nv, nt, ne, ucap, ccap);
@@ -189,7 +209,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     __shared__ int bbox[6];
     __shared__ int ncomp;
 
-    for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x) xs[k] = O.X[k];
+    for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x) xs[k] = gld(O.X + k);
     if (threadIdx.x == 0) {
         bbox[0] = bbox[1] = bbox[2] = INT_MAX;
         bbox[3] = bbox[4] = bbox[5] = INT_MIN;
@@ -203,7 +223,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     {
         const double r0x = xs[0], r0y = xs[1], r0z = xs[2];
         for (int t = threadIdx.x; t < nt; t += blockDim.x) {
-            const int a = T->tri[3 * t], b = T->tri[3 * t + 1], c = T->tri[3 * t + 2];
+            const int a = gld(T->tri + 3 * t), b = gld(T->tri + 3 * t + 1), c = gld(T->tri + 3 * t + 2);
             const double ax = xs[3 * a] - r0x, ay = xs[3 * a + 1] - r0y, az = xs[3 * a + 2] - r0z;
             const double bx = xs[3 * b] - r0x, by = xs[3 * b + 1] - r0y, bz = xs[3 * b + 2] - r0z;
             const double qx = xs[3 * c] - r0x, qy = xs[3 * c + 1] - r0y, qz = xs[3 * c + 2] - r0z;
@@ -215,7 +235,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
             const double n2 = nx_ * nx_ + ny_ * ny_ + nz_ * nz_;  // 4 S^2
             const R len = sqrt((R)n2);
             const R S = R(0.5) * len;
-            const double S0 = T->S0[t];
+            const double S0 = gld(T->S0 + t);
             const R dS = (R)(0.25 * n2 - S0 * S0) / (S + (R)S0);
             tn[4 * t + 0] = (R)nx_ / len;
             tn[4 * t + 1] = (R)ny_ / len;
@@ -232,22 +252,22 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     const double Vol = block_sum(svol, red);
     const double Sg = T->Sg0 + dSg;
     if (threadIdx.x == 0 && O.geo) {
-        O.geo[0] = Sg;
-        O.geo[1] = Vol;
+        gst(O.geo, Sg);
+        gst(O.geo + 1, Vol);
     }
 
     // 2. edges: stretching coefficient and bending magnitude of each hinge
     const bool do_s = T->ks != 0.0, do_b = T->kb != 0.0;
     if (do_s || do_b) {
         for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-            const int4 h = T->hinge[e];  // (A, B, C, D): the edge is B -> C
+            const int4 h = gld(T->hinge + e);  // (A, B, C, D): the edge is B -> C
             const double dx = xs[3 * h.z] - xs[3 * h.y], dy = xs[3 * h.z + 1] - xs[3 * h.y + 1],
                          dz = xs[3 * h.z + 2] - xs[3 * h.y + 2];
             const double L2 = dx * dx + dy * dy + dz * dz;
             const double L = sqrt(L2);
             if (do_s) {
                 // strain (L - L0)/L0 = (L^2 - L0^2) / (L0 (L + L0))
-                const double L0 = T->L0[e];
+                const double L0 = gld(T->L0 + e);
                 const R strain = (R)(L2 - L0 * L0) / ((R)L0 * (R)(L + L0));
                 R kap = R(1);
                 if (!T->linear) {
@@ -274,9 +294,9 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                 // atan2(sin d, cos d), every term scaled by |N1| |N2| L > 0
                 const double md = mx * dx + my * dy + mz * dz;
                 const double dot = n1x * n2x + n1y * n2y + n1z * n2z;
-                const double2 cs = T->cs0[e];  // cos, sin of theta0 - pi
+                const double2 cs = gld(T->cs0 + e);  // cos, sin of theta0 - pi
                 const R dth = atan2((R)(md * cs.x - dot * L * cs.y), (R)(dot * L * cs.x + md * cs.y));
-                fh[e] = (R)T->kb * dth / (R)T->theta0[e];
+                fh[e] = (R)T->kb * dth / (R)gld(T->theta0 + e);
             }
         }
     }
@@ -298,12 +318,12 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     for (int v = threadIdx.x; v < nv; v += blockDim.x) {
         const double px = xs[3 * v], py = xs[3 * v + 1], pz = xs[3 * v + 2];
         R Fx = 0, Fy = 0, Fz = 0;
-        const int4 o0 = T->n_off[v], o1 = T->n_off[v + 1];
+        const int4 o0 = gld(T->n_off + v), o1 = gld(T->n_off + v + 1);
         if (do_s) {
             // F_v += ks kappa (L - L0)/L0 (x_u - x_v)/L  ("Stretching force")
 #pragma unroll 2
             for (int k = o0.x; k < o1.x; ++k) {
-                const int2 ie = T->e_inc[k];
+                const int2 ie = gld(T->e_inc + k);
                 const R s = se[ie.y];
                 Fx += s * (R)(xs[3 * ie.x] - px);
                 Fy += s * (R)(xs[3 * ie.x + 1] - py);
@@ -315,7 +335,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
             // ("Bending force"); the role picks the two coefficients
 #pragma unroll 4
             for (int k = o0.y; k < o1.y; ++k) {
-                const int4 r = T->h_inc[k];
+                const int4 r = gld(T->h_inc + k);
                 const int role = r.x & 3;
                 const R f = fh[r.x >> 2];
                 const R hf = R(-0.5) * f;
@@ -330,7 +350,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
         // (-kv dV/V0 S n_out / 3); w = unit centroid -> vertex
 #pragma unroll 2
         for (int k = o0.z; k < o1.z; ++k) {
-            const int4 r = T->t_inc[k];
+            const int4 r = gld(T->t_inc + k);
             const int t = r.x;
             const R wx = (R)(px - (px + xs[3 * r.y] + xs[3 * r.z]) * (1.0 / 3.0));
             const R wy = (R)(py - (py + xs[3 * r.y + 1] + xs[3 * r.z + 1]) * (1.0 / 3.0));
@@ -422,22 +442,27 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
         compact = ncomp <= ccap;  // block-uniform
         if (compact) {
             for (int k = threadIdx.x; k < 3 * ncomp; k += blockDim.x) gacc[k] = A(0);
-            // lattice index of every touched node, in compact numbering
+            // lattice index of every touched node, in compact numbering (the
+            // box origin wrapped once, box offsets without integer division)
+            const int oxw = wrap_mod(ox, nxb), oyw = wrap_mod(oy, nyb);
+            const int ozw = B->walls_z ? oz : wrap_mod(oz, nzb);
+            const int ey = (int)eyl;
+            const float rex = 1.0f / (float)ex, rey = 1.0f / (float)ey;
             for (int idx = threadIdx.x; idx < vol; idx += blockDim.x) {
                 const unsigned word = need[idx >> 5];
                 if (!((word >> (idx & 31)) & 1u)) continue;
                 const int c = (int)(pre[idx >> 5] + __popc(word & ((1u << (idx & 31)) - 1u)));
-                int gx = (ox + idx % ex) % nxb;
-                gx += gx < 0 ? nxb : 0;
-                int gy = (oy + (idx / ex) % (int)eyl) % nyb;
-                gy += gy < 0 ? nyb : 0;
-                int gz = oz + idx / exy;
+                int t, dx, dy, dz;
+                divmod_small(idx, ex, rex, t, dx);
+                divmod_small(t, ey, rey, dz, dy);
+                int gx = oxw + dx, gy = oyw + dy, gz = ozw + dz;
+                while (gx >= nxb) gx -= nxb;
+                while (gy >= nyb) gy -= nyb;
                 if (B->walls_z) {
                     if (gz < 0 || gz >= nzb) flags |= ST_CLAMPED;
                     gz = gz < 0 ? 0 : (gz >= nzb ? nzb - 1 : gz);
                 } else {
-                    gz %= nzb;
-                    gz += gz < 0 ? nzb : 0;
+                    while (gz >= nzb) gz -= nzb;
                 }
                 qn[c] = (gz * nyb + gy) * nxb + gx;
             }
@@ -447,7 +472,8 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                 const int q = qn[c];
                 R dd[19];
 #pragma unroll
-                for (int i = 0; i < 19; ++i) dd[i] = dec<P>(pop[(size_t)i * Nb + q], inv);
+                for (int i = 0; i < 19; ++i)
+                    dd[i] = dec<P>(gload(pop + (size_t)i * Nb, (unsigned)q * (unsigned)sizeof(S)), inv);
                 R dr = 0;
 #pragma unroll
                 for (int i = 0; i < 19; ++i) dr += dd[i];
@@ -466,7 +492,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     // per mesh node: interpolate, drag, integrate, spread
     for (int v = threadIdx.x; v < nv; v += blockDim.x) {
         const double px = xs[3 * v], py = xs[3 * v + 1], pz = xs[3 * v + 2];
-        R vx = O.V[3 * v], vy = O.V[3 * v + 1], vz = O.V[3 * v + 2];
+        R vx = gld(O.V + 3 * v), vy = gld(O.V + 3 * v + 1), vz = gld(O.V + 3 * v + 2);
         R dgx = 0, dgy = 0, dgz = 0;
         if (sb[3 * v] != INT_MIN) {
             const double sx = px - 0.5, sy = py - 0.5, sz = pz - 0.5;
@@ -529,7 +555,8 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                     const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
                     const int qk = ((dz ? iz1 : iz0) * nyb + (dy ? iy1 : iy)) * nxb + (dx ? ix1 : ix);
 #pragma unroll
-                    for (int i = 0; i < 19; ++i) dd[i] = dec<P>(pop[(size_t)i * Nb + qk], inv);
+                    for (int i = 0; i < 19; ++i)
+                        dd[i] = dec<P>(gload(pop + (size_t)i * Nb, (unsigned)qk * (unsigned)sizeof(S)), inv);
                     R dr = 0;
 #pragma unroll
                     for (int i = 0; i < 19; ++i) dr += dd[i];
@@ -562,13 +589,13 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
         vx += (fs[3 * v] - dgx + O.fext[0]) * O.inv_mass;
         vy += (fs[3 * v + 1] - dgy + O.fext[1]) * O.inv_mass;
         vz += (fs[3 * v + 2] - dgz + O.fext[2]) * O.inv_mass;
-        O.V[3 * v] = vx;
-        O.V[3 * v + 1] = vy;
-        O.V[3 * v + 2] = vz;
+        gst(O.V + 3 * v, vx);
+        gst(O.V + 3 * v + 1, vy);
+        gst(O.V + 3 * v + 2, vz);
         const double qx = px + (double)vx, qy = py + (double)vy, qz = pz + (double)vz;
-        O.X[3 * v] = qx;
-        O.X[3 * v + 1] = qy;
-        O.X[3 * v + 2] = qz;
+        gst(O.X + 3 * v, qx);
+        gst(O.X + 3 * v + 1, qy);
+        gst(O.X + 3 * v + 2, qz);
         xs[3 * v] = qx;  // only this node's own entry is read in this loop
         xs[3 * v + 1] = qy;
         xs[3 * v + 2] = qz;
@@ -582,7 +609,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     // split stepping: the stencils of the new positions, for the next step
     if (mark_next)
         mark_object(xs, nv, O.anchor, B, ucap, need, bbox, B->touch[parity ^ 1]);
-    if (flags) atomicOr(B->status, flags);
+    if (flags) gatomic_or(B->status, flags);
 }
 
 // Touch bits of a step of parity `parity` from the current positions (split
@@ -593,7 +620,7 @@ __global__ void __launch_bounds__(256) mark_kernel(const ObjDev<R>* __restrict__
     extern __shared__ unsigned bits[];  // cap bits
     __shared__ int bbox[6];
     const ObjDev<R>& O = objs[blockIdx.x];
-    const BoxDev* __restrict__ B = O.box;
+    const gptr<const BoxDev> B = (gptr<const BoxDev>)O.box;
     mark_object(O.X, O.t->nv, O.anchor, B, min(O.t->ucap, cap), bits, bbox, B->touch[parity]);
 }
 

@@ -1049,8 +1049,9 @@ int oif_set_overlap(oif_ctx* c, int on) {
 int oif_set_launch(oif_ctx* c, int lb_block, int mesh_block, int xcd_remap) {
     if (!c) return OIF_E_ARG;
     auto okb = [](int b) { return b == 64 || b == 128 || b == 256 || b == 512 || b == 1024; };
+    auto okm = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
     if (lb_block >= 0 && !okb(lb_block)) return fail(c, OIF_E_ARG, "lb_block must be 64..1024, power of two");
-    if (mesh_block >= 0 && !okb(mesh_block)) return fail(c, OIF_E_ARG, "mesh_block must be 64..1024, power of two");
+    if (mesh_block >= 0 && !okm(mesh_block)) return fail(c, OIF_E_ARG, "mesh_block must be a multiple of 64 in 64..1024");
     if (lb_block >= 0) c->lb_block = lb_block;
     if (mesh_block >= 0) c->mesh_block = mesh_block;
     if (xcd_remap >= 0) c->remap = xcd_remap ? 1 : 0;
@@ -1376,7 +1377,7 @@ extern "C" int oif_autotune(oif_ctx* c, const char* cache_path) {
     c->lb_block = best[0];
     c->remap = best[2];
     if (!c->obj.empty())
-        for (int mb : {64, 128, 256, 512, 1024}) {
+        for (int mb : {128, 256, 384, 512, 640, 768, 1024}) {
             c->mesh_block = mb;
             double tl, tm;
             if ((rc = time_steps(c, reps, &tl, &tm))) return rc;
@@ -1574,7 +1575,8 @@ int oif_batch_set_graph(oif_batch* b, int steps_per_graph) {
 int oif_batch_set_launch(oif_batch* b, int lb_block, int mesh_block, int xcd_remap) {
     if (!b) return OIF_E_ARG;
     auto okb = [](int v) { return v == 64 || v == 128 || v == 256 || v == 512 || v == 1024; };
-    if ((lb_block >= 0 && !okb(lb_block)) || (mesh_block >= 0 && !okb(mesh_block))) return OIF_E_ARG;
+    auto okm = [](int v) { return v >= 64 && v <= 1024 && v % 64 == 0; };
+    if ((lb_block >= 0 && !okb(lb_block)) || (mesh_block >= 0 && !okm(mesh_block))) return OIF_E_ARG;
     if (lb_block >= 0) b->lb_block = lb_block;
     if (mesh_block >= 0) b->mesh_block = mesh_block;
     if (xcd_remap >= 0) b->remap = xcd_remap ? 1 : 0;
@@ -1686,7 +1688,7 @@ int oif_batch_autotune(oif_batch* b, const char* cache_path) {
             if (tl < best_lb) { best_lb = tl; best[0] = lb; best[2] = rm; }
         }
     oif_batch_set_launch(b, best[0], -1, best[2]);
-    for (int mb : {64, 128, 256, 512, 1024}) {
+    for (int mb : {128, 256, 384, 512, 640, 768, 1024}) {
         oif_batch_set_launch(b, -1, mb, -1);
         double tl, tm;
         if ((rc = trial(&tl, &tm))) return rc;

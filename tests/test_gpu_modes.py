@@ -100,7 +100,7 @@ def test_autotune_leaves_state_unchanged(oif, tmp_path):
         if tune:
             c.autotune(cache)
             i = c.info()
-            assert i.lb_block in (128, 256, 512, 1024) and i.mesh_block in (64, 128, 256, 512, 1024)
+            assert i.lb_block in (128, 256, 512, 1024) and i.mesh_block % 64 == 0 and 64 <= i.mesh_block <= 1024
         c.step(20)
         outs.append(state(c))
         c.close()
@@ -270,5 +270,30 @@ def test_input_validation(oif):
     assert np.allclose(a.origin, 8.0, atol=1e-12)
     c.object_set_origin(0, (5.0, 6.0, 7.0))
     assert np.allclose(c.object_analyze(0).origin, (5, 6, 7), atol=1e-12)
+    # launch shapes: lattice blocks are powers of two, membrane blocks multiples of 64
+    for lb, mb in ((100, -1), (2048, -1), (-1, 100), (-1, 1088), (-1, 32)):
+        with pytest.raises(oif.OifError) as ei:
+            c.set_launch(lb, mb, -1)
+        assert ei.value.code == oif.E_ARG
+    c.set_launch(-1, 640, -1)
+    assert c.info().mesh_block == 640
     c.step(2)
     c.close()
+
+
+@pytest.mark.parametrize("mb", [192, 640, 768])
+def test_membrane_block_sizes_match_oracle(oif, orc, mb):
+    """Membrane workgroups of any multiple of 64 (not only powers of two) give
+    the oracle's result: FP32 channel, 20 steps."""
+    say(f"[modes] membrane block {mb} vs oracle")
+    box = channel(20)
+    s = orc.System(box)
+    X0 = s.X.copy()
+    c = oif.Context.from_box(box, precision="fp32")
+    c.set_launch(-1, mb, -1)
+    c.step(20)
+    s.run(20)
+    res = check(gpu_fields(c, box.rho0, X0), oracle_fields(s, X0), "fp32", box.rho0, box.nx)
+    c.close()
+    say(f"   {fmt(res)}")
+    assert all(v[3] for v in res.values()), fmt(res)
