@@ -56,7 +56,19 @@ class _Mesh(C.Structure):
     _fields_ = [("n_tmpl", C.c_int), ("t_nv", C.c_void_p), ("t_nt", C.c_void_p),
                 ("t_tri_off", C.c_void_p), ("tri", C.c_void_p), ("t_k", C.c_void_p),
                 ("t_linear", C.c_void_p), ("n_obj", C.c_int), ("o_tmpl", C.c_void_p),
-                ("o_node_off", C.c_void_p), ("o_mass", C.c_void_p), ("o_fext", C.c_void_p)]
+                ("o_node_off", C.c_void_p), ("o_mass", C.c_void_p), ("o_fext", C.c_void_p),
+                ("t_model", C.c_void_p)]
+
+# force models (orc_membrane_forces)
+MODEL_PAPER = 0
+MODEL_CONSERVATIVE = 1
+
+
+def model_code(model) -> int:
+    """'paper' / 'conservative' (or the integer code) -> integer code."""
+    if isinstance(model, str):
+        return {"paper": MODEL_PAPER, "conservative": MODEL_CONSERVATIVE}[model]
+    return int(model)
 
 
 def lib():
@@ -77,8 +89,16 @@ def lib():
         L.orc_relaxed.restype = None
         L.orc_relaxed.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, ip, dp, dp, dp, dp, dp]
         L.orc_membrane_forces.restype = None
+        L.orc_wing_height.restype = None
+        L.orc_wing_height.argtypes = [C.c_int, dp, C.c_int, ip, dp]
+        L.orc_force_bend_gradient.restype = None
+        L.orc_force_bend_gradient.argtypes = [C.c_int, dp, C.c_int, ip, dp, dp, C.c_double, dp]
+        L.orc_force_local_area_balanced.restype = None
+        L.orc_force_local_area_balanced.argtypes = [C.c_int, dp, C.c_int, ip, dp, C.c_double, dp]
+        L.orc_force_global_area_balanced.restype = None
+        L.orc_force_global_area_balanced.argtypes = [C.c_int, dp, C.c_int, ip, C.c_double, C.c_double, dp]
         L.orc_membrane_forces.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, ip, dp, dp, dp,
-                                          C.c_double, C.c_double, dp, C.c_int, dp]
+                                          C.c_double, C.c_double, dp, C.c_int, C.c_int, dp, dp]
         L.orc_force_stretch.argtypes = [C.c_int, dp, C.c_int, ip, dp, C.c_double, C.c_int, dp]
         L.orc_force_bend.argtypes = [C.c_int, dp, C.c_int, ip, dp, C.c_double, dp]
         L.orc_force_local_area.argtypes = [C.c_int, dp, C.c_int, ip, dp, C.c_double, dp]
@@ -181,14 +201,17 @@ class Relaxed:
                           C.byref(Sg0), C.byref(V0))
         self.Sg0 = Sg0.value
         self.V0 = V0.value
+        self.hbar = wing_height(x, self.hinges)
 
-    def forces(self, x, ks=0.0, kb=0.0, kal=0.0, kag=0.0, kv=0.0, linear=False) -> np.ndarray:
+    def forces(self, x, ks=0.0, kb=0.0, kal=0.0, kag=0.0, kv=0.0, linear=False,
+               model="paper") -> np.ndarray:
         x = _f64(x)
         F = np.zeros((self.nv, 3))
         k = _f64([ks, kb, kal, kag, kv])
         lib().orc_membrane_forces(self.nv, _p(x), len(self.tris), _p(self.tris), len(self.edges),
                                   _p(self.edges), _p(self.hinges), _p(self.L0), _p(self.theta0),
-                                  _p(self.S0), self.Sg0, self.V0, _p(k), int(linear), _p(F))
+                                  _p(self.S0), self.Sg0, self.V0, _p(k), int(linear),
+                                  model_code(model), _p(self.hbar), _p(F))
         return F
 
     def force_family(self, which: str, x, k: float, linear: bool = False) -> np.ndarray:
@@ -206,9 +229,32 @@ class Relaxed:
             L.orc_force_global_area(self.nv, _p(x), nt, _p(self.tris), self.Sg0, k, _p(F))
         elif which == "volume":
             L.orc_force_volume(self.nv, _p(x), nt, _p(self.tris), self.V0, k, _p(F))
+        elif which == "bend_gradient":
+            L.orc_force_bend_gradient(self.nv, _p(x), ne, _p(self.hinges), _p(self.theta0),
+                                      _p(self.hbar), k, _p(F))
+        elif which == "local_area_balanced":
+            L.orc_force_local_area_balanced(self.nv, _p(x), nt, _p(self.tris), _p(self.S0), k, _p(F))
+        elif which == "global_area_balanced":
+            L.orc_force_global_area_balanced(self.nv, _p(x), nt, _p(self.tris), self.Sg0, k, _p(F))
         else:
             raise ValueError(which)
         return F
+
+
+def wing_height(x, hinges) -> np.ndarray:
+    """Mean relaxed wing height (S(A,B,C) + S(D,C,B)) / |C - B| of each hinge."""
+    x, h = _f64(x), _i32(hinges)
+    hbar = np.zeros(len(h))
+    lib().orc_wing_height(len(x), _p(x), len(h), _p(h), _p(hbar))
+    return hbar
+
+
+def force_bend_gradient_hinges(x, hinges, theta0, hbar, kb) -> np.ndarray:
+    """Gradient-form bending forces of an explicit hinge list (A, B, C, D)."""
+    x, h, th, hb = _f64(x), _i32(hinges), _f64(theta0), _f64(hbar)
+    F = np.zeros((len(x), 3))
+    lib().orc_force_bend_gradient(len(x), _p(x), len(h), _p(h), _p(th), _p(hb), float(kb), _p(F))
+    return F
 
 
 def force_stretch_edges(x, edges, L0, ks, linear=False) -> np.ndarray:
@@ -239,6 +285,11 @@ def force_triangles(which: str, x, tris, k, S0=None, Sg0=None, V0=None) -> np.nd
         L.orc_force_global_area(len(x), _p(x), len(t), _p(t), float(Sg0), float(k), _p(F))
     elif which == "volume":
         L.orc_force_volume(len(x), _p(x), len(t), _p(t), float(V0), float(k), _p(F))
+    elif which == "local_area_balanced":
+        S0 = _f64(S0)
+        L.orc_force_local_area_balanced(len(x), _p(x), len(t), _p(t), _p(S0), float(k), _p(F))
+    elif which == "global_area_balanced":
+        L.orc_force_global_area_balanced(len(x), _p(x), len(t), _p(t), float(Sg0), float(k), _p(F))
     else:
         raise ValueError(which)
     return F
@@ -331,7 +382,7 @@ class System:
         L = self._L = _lattice(box.nx, box.ny, box.nz, tau=box.tau, rho0=box.rho0, g=box.g,
                                xi=box.friction, walls_z=box.walls_z)
         # templates: apply the per-axis stretch to the node coordinates
-        t_x, t_nv, t_nt, t_off, t_tri_off, tri, t_k, t_lin = [], [], [], [], [], [], [], []
+        t_x, t_nv, t_nt, t_off, t_tri_off, tri, t_k, t_lin, t_mod = [], [], [], [], [], [], [], [], []
         noff = toff = 0
         self.t_nodes = []
         for t in box.templates:
@@ -345,6 +396,7 @@ class System:
             tri.append(_i32(t.tris))
             t_k.append([t.ks, t.kb, t.kal, t.kag, t.kv])
             t_lin.append(int(t.linear))
+            t_mod.append(model_code(getattr(t, "model", "paper")))
             noff += len(x)
             toff += len(t.tris)
         self._keep = dict(
@@ -352,7 +404,7 @@ class System:
             t_nv=_i32(t_nv or [0]), t_nt=_i32(t_nt or [0]), t_off=_i32(t_off or [0]),
             t_tri_off=_i32(t_tri_off or [0]),
             tri=_i32(np.concatenate(tri) if tri else np.zeros((1, 3))),
-            t_k=_f64(t_k or [[0] * 5]), t_lin=_i32(t_lin or [0]))
+            t_k=_f64(t_k or [[0] * 5]), t_lin=_i32(t_lin or [0]), t_mod=_i32(t_mod or [0]))
         # objects: X = origin + R x_template
         o_t, o_off, o_m, o_f, X0 = [], [], [], [], []
         off = 0
@@ -373,7 +425,7 @@ class System:
         m = _Mesh()
         m.n_tmpl = len(box.templates)
         m.t_nv, m.t_nt, m.t_tri_off, m.tri = _p(k["t_nv"]), _p(k["t_nt"]), _p(k["t_tri_off"]), _p(k["tri"])
-        m.t_k, m.t_linear = _p(k["t_k"]), _p(k["t_lin"])
+        m.t_k, m.t_linear, m.t_model = _p(k["t_k"]), _p(k["t_lin"]), _p(k["t_mod"])
         m.n_obj = len(box.objects)
         m.o_tmpl, m.o_node_off, m.o_mass, m.o_fext = _p(k["o_t"]), _p(k["o_off"]), _p(k["o_m"]), _p(k["o_f"])
         self._mesh = m

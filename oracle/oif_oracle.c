@@ -237,6 +237,20 @@ void orc_relaxed(int nv, const double* x, int nt, const int* tri, int ne, const 
     orc_geometry(nv, x, nt, tri, S0, Sg0, V0);
 }
 
+static double tri_area(const double* x, const int* tv);
+
+void orc_wing_height(int nv, const double* x, int ne, const int* hinge, double* hbar) {
+    (void)nv;
+    for (int e = 0; e < ne; ++e) {
+        const int* h = &hinge[4 * e];
+        const int t1[3] = {h[0], h[1], h[2]}, t2[3] = {h[3], h[2], h[1]};
+        double bc[3];
+        sub3(&x[3 * h[2]], &x[3 * h[1]], bc);
+        /* mean of the two wing heights 2 S / |BC| */
+        hbar[e] = (tri_area(x, t1) + tri_area(x, t2)) / norm3(bc);
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Elastic forces ("Elastic interactions")                                   */
 /* ------------------------------------------------------------------------- */
@@ -285,17 +299,71 @@ void orc_force_bend(int nv, const double* x, int ne, const int* hinge, const dou
     }
 }
 
-/* centroid-to-vertex unit vectors of triangle t */
-static void tri_w(const double* x, const int* tv, double w[3][3]) {
+/* Bending in gradient form: F = -grad E per hinge with
+ * E = kb hbar (theta - theta0)^2 / (2 theta0), hbar the hinge's mean relaxed
+ * wing height (orc_wing_height).  Gradient of the inner dihedral angle: moving
+ * a wing vertex by d along its own triangle's inward normal turns that
+ * triangle about the shared edge by d / h (h = the vertex's distance from the
+ * edge line) and makes the hinge more convex, so grad_A theta = -n1 / h_A and
+ * grad_D theta = -n2 / h_D; in-plane moves of a wing do not change theta.
+ * With the feet of A and D on the edge at B + a (C - B), the edge vertices
+ * take grad_B = -(1 - a_A) grad_A - (1 - a_D) grad_D and
+ * grad_C = -a_A grad_A - a_D grad_D, which makes the gradient sum to zero
+ * and carry no torque (theta is invariant under rigid motions).  On a
+ * symmetric hinge (a = 1/2, h_A = h_D = hbar) this is the paper's rule with
+ * its magnitude kb (theta - theta0)/theta0. */
+void orc_force_bend_gradient(int nv, const double* x, int ne, const int* hinge,
+                             const double* theta0, const double* hbar, double kb, double* F) {
+    (void)nv;
+    if (kb == 0.0) return;
+    for (int e = 0; e < ne; ++e) {
+        int A = hinge[4 * e], B = hinge[4 * e + 1], C = hinge[4 * e + 2], D = hinge[4 * e + 3];
+        double n1[3], n2[3], bc[3], ba[3], bd[3], ca[3], cd[3];
+        unit_normal(&x[3 * A], &x[3 * B], &x[3 * C], n1);
+        unit_normal(&x[3 * D], &x[3 * C], &x[3 * B], n2);
+        sub3(&x[3 * C], &x[3 * B], bc);
+        sub3(&x[3 * A], &x[3 * B], ba);
+        sub3(&x[3 * D], &x[3 * B], bd);
+        double L2 = dot3(bc, bc);
+        double aA = dot3(ba, bc) / L2, aD = dot3(bd, bc) / L2;
+        cross3(ba, bc, ca);
+        cross3(bd, bc, cd);
+        double hA = norm3(ca) / sqrt(L2), hD = norm3(cd) / sqrt(L2);
+        double theta = orc_dihedral(&x[3 * A], &x[3 * B], &x[3 * C], &x[3 * D]);
+        double dEdt = kb * hbar[e] * (theta - theta0[e]) / theta0[e];
+        for (int c = 0; c < 3; ++c) {
+            double gA = -n1[c] / hA, gD = -n2[c] / hD;
+            double gB = -(1.0 - aA) * gA - (1.0 - aD) * gD;
+            double gC = -aA * gA - aD * gD;
+            F[3 * A + c] -= dEdt * gA;
+            F[3 * B + c] -= dEdt * gB;
+            F[3 * C + c] -= dEdt * gC;
+            F[3 * D + c] -= dEdt * gD;
+        }
+    }
+}
+
+/* Centroid-to-vertex directions of triangle t.  balanced = 0: unit vectors,
+ * the paper's w.  balanced = 1: t_v / t_rms with t_rms^2 = (|t_a|^2 + |t_b|^2
+ * + |t_c|^2) / 3; these sum to zero and are parallel to t_v, so forces along
+ * them carry no net force and no torque about the centroid, and on an
+ * equilateral triangle they are the unit vectors. */
+static void tri_dirs(const double* x, const int* tv, int balanced, double w[3][3]) {
     double cen[3];
     for (int c = 0; c < 3; ++c)
         cen[c] = (x[3 * tv[0] + c] + x[3 * tv[1] + c] + x[3 * tv[2] + c]) / 3.0;
+    double ms = 0.0;
     for (int s = 0; s < 3; ++s) {
         sub3(&x[3 * tv[s]], cen, w[s]);
-        double l = norm3(w[s]);
+        ms += dot3(w[s], w[s]) / 3.0;
+    }
+    for (int s = 0; s < 3; ++s) {
+        double l = balanced ? sqrt(ms) : norm3(w[s]);
         for (int c = 0; c < 3; ++c) w[s][c] /= l;
     }
 }
+
+static void tri_w(const double* x, const int* tv, double w[3][3]) { tri_dirs(x, tv, 0, w); }
 
 static double tri_area(const double* x, const int* tv) {
     double ab[3], ac[3], N[3];
@@ -338,6 +406,39 @@ void orc_force_global_area(int nv, const double* x, int nt, const int* tri, doub
     }
 }
 
+/* Local and global area along the balanced directions t_v / t_rms (see
+ * tri_dirs): the same magnitudes as the paper's rules, no net force or torque
+ * on any triangle. */
+void orc_force_local_area_balanced(int nv, const double* x, int nt, const int* tri,
+                                   const double* S0, double kal, double* F) {
+    (void)nv;
+    if (kal == 0.0) return;
+    for (int t = 0; t < nt; ++t) {
+        const int* tv = &tri[3 * t];
+        double S = tri_area(x, tv);
+        double w[3][3];
+        tri_dirs(x, tv, 1, w);
+        double coef = -kal * (S - S0[t]) / S;
+        for (int s = 0; s < 3; ++s)
+            for (int c = 0; c < 3; ++c) F[3 * tv[s] + c] += coef * w[s][c];
+    }
+}
+
+void orc_force_global_area_balanced(int nv, const double* x, int nt, const int* tri, double Sg0,
+                                    double kag, double* F) {
+    if (kag == 0.0) return;
+    double Sg;
+    orc_geometry(nv, x, nt, tri, NULL, &Sg, NULL);
+    double coef = -kag * (Sg - Sg0) / Sg;
+    for (int t = 0; t < nt; ++t) {
+        const int* tv = &tri[3 * t];
+        double w[3][3];
+        tri_dirs(x, tv, 1, w);
+        for (int s = 0; s < 3; ++s)
+            for (int c = 0; c < 3; ++c) F[3 * tv[s] + c] += coef * w[s][c];
+    }
+}
+
 /* Volume: per triangle F_v = -kv (V - V0)/V0 S n_out, one third to each vertex. */
 void orc_force_volume(int nv, const double* x, int nt, const int* tri, double V0,
                       double kv, double* F) {
@@ -358,11 +459,17 @@ void orc_force_volume(int nv, const double* x, int nt, const int* tri, double V0
 void orc_membrane_forces(int nv, const double* x, int nt, const int* tri, int ne,
                          const int* edge, const int* hinge, const double* L0,
                          const double* theta0, const double* S0, double Sg0, double V0,
-                         const double* k, int linear, double* F) {
+                         const double* k, int linear, int model, const double* hbar, double* F) {
     orc_force_stretch(nv, x, ne, edge, L0, k[0], linear, F);
-    orc_force_bend(nv, x, ne, hinge, theta0, k[1], F);
-    orc_force_local_area(nv, x, nt, tri, S0, k[2], F);
-    orc_force_global_area(nv, x, nt, tri, Sg0, k[3], F);
+    if (model == ORC_MODEL_CONSERVATIVE) {
+        orc_force_bend_gradient(nv, x, ne, hinge, theta0, hbar, k[1], F);
+        orc_force_local_area_balanced(nv, x, nt, tri, S0, k[2], F);
+        orc_force_global_area_balanced(nv, x, nt, tri, Sg0, k[3], F);
+    } else {
+        orc_force_bend(nv, x, ne, hinge, theta0, k[1], F);
+        orc_force_local_area(nv, x, nt, tri, S0, k[2], F);
+        orc_force_global_area(nv, x, nt, tri, Sg0, k[3], F);
+    }
     orc_force_volume(nv, x, nt, tri, V0, k[4], F);
 }
 
@@ -514,10 +621,11 @@ typedef struct {
     int* edge;
     int* hinge;
     int* hinge_tri;
-    double *L0, *theta0, *S0;
+    double *L0, *theta0, *S0, *hbar;
     double Sg0, V0;
     double k[5];
     int linear;
+    int model;
 } orc_tmpl;
 
 struct orc_system {
@@ -546,6 +654,7 @@ void orc_system_destroy(orc_system* s) {
         free(s->t[t].L0);
         free(s->t[t].theta0);
         free(s->t[t].S0);
+        free(s->t[t].hbar);
     }
     free(s->t);
     free(s->o_tmpl);
@@ -587,8 +696,11 @@ orc_system* orc_system_create(const orc_lattice* L, const orc_mesh* m, const int
         T->S0 = (double*)malloc(sizeof(double) * (size_t)T->nt);
         orc_relaxed(T->nv, &t_x[3 * (size_t)t_node_off[t]], T->nt, T->tri, T->ne, T->edge,
                     T->hinge, T->L0, T->theta0, T->S0, &T->Sg0, &T->V0);
+        T->hbar = (double*)malloc(sizeof(double) * (size_t)T->ne);
+        orc_wing_height(T->nv, &t_x[3 * (size_t)t_node_off[t]], T->ne, T->hinge, T->hbar);
         for (int c = 0; c < 5; ++c) T->k[c] = m->t_k[5 * t + c];
         T->linear = m->t_linear[t];
+        T->model = m->t_model ? m->t_model[t] : ORC_MODEL_PAPER;
     }
     s->o_tmpl = (int*)malloc(sizeof(int) * (size_t)(m->n_obj + 1));
     s->o_off = (int*)malloc(sizeof(int) * (size_t)(m->n_obj + 1));
@@ -625,7 +737,8 @@ void orc_system_forces(orc_system* s, const double* X, double* F) {
         orc_tmpl* T = &s->t[s->o_tmpl[o]];
         size_t off = 3 * (size_t)s->o_off[o];
         orc_membrane_forces(T->nv, &X[off], T->nt, T->tri, T->ne, T->edge, T->hinge, T->L0,
-                            T->theta0, T->S0, T->Sg0, T->V0, T->k, T->linear, &F[off]);
+                            T->theta0, T->S0, T->Sg0, T->V0, T->k, T->linear, T->model, T->hbar,
+                            &F[off]);
     }
 }
 

@@ -49,12 +49,23 @@ void orc_relaxed(int nv, const double* x, int nt, const int* tri, int ne, const 
                  const int* hinge, double* L0, double* theta0, double* S0,
                  double* Sg0, double* V0);
 
+/* Mean relaxed wing height of each hinge, (S(A,B,C) + S(D,C,B)) / |C - B|. */
+void orc_wing_height(int nv, const double* x, int ne, const int* hinge, double* hbar);
+
+/* Force models.  PAPER: the rules of "Elastic interactions" as printed.
+ * CONSERVATIVE: bending as the gradient of kb hbar (theta - theta0)^2/(2 theta0)
+ * and local/global area along t_v / t_rms, so that every hinge and triangle
+ * exerts no net force and no torque; stretching and volume are unchanged. */
+#define ORC_MODEL_PAPER 0
+#define ORC_MODEL_CONSERVATIVE 1
+
 /* Membrane forces of one object; ADDS into F[nv][3].
- * k = {ks, kb, kal, kag, kv}; linear != 0 selects kappa = 1. */
+ * k = {ks, kb, kal, kag, kv}; linear != 0 selects kappa = 1; hbar (per edge,
+ * from orc_wing_height) is read only by the conservative model. */
 void orc_membrane_forces(int nv, const double* x, int nt, const int* tri, int ne,
                          const int* edge, const int* hinge, const double* L0,
                          const double* theta0, const double* S0, double Sg0, double V0,
-                         const double* k, int linear, double* F);
+                         const double* k, int linear, int model, const double* hbar, double* F);
 
 /* Individual force families (same conventions), each ADDS into F. */
 void orc_force_stretch(int nv, const double* x, int ne, const int* edge, const double* L0,
@@ -67,6 +78,13 @@ void orc_force_global_area(int nv, const double* x, int nt, const int* tri, doub
                            double kag, double* F);
 void orc_force_volume(int nv, const double* x, int nt, const int* tri, double V0,
                       double kv, double* F);
+/* conservative-model families */
+void orc_force_bend_gradient(int nv, const double* x, int ne, const int* hinge,
+                             const double* theta0, const double* hbar, double kb, double* F);
+void orc_force_local_area_balanced(int nv, const double* x, int nt, const int* tri,
+                                   const double* S0, double kal, double* F);
+void orc_force_global_area_balanced(int nv, const double* x, int nt, const int* tri, double Sg0,
+                                    double kag, double* F);
 
 /* Lattice description. */
 typedef struct {
@@ -113,6 +131,7 @@ typedef struct {
     const int* o_node_off;  /* offset into X/V (in nodes) */
     const double* o_mass;
     const double* o_fext;   /* [n_obj][3] */
+    const int* t_model;     /* per template ORC_MODEL_*, or NULL for all PAPER */
 } orc_mesh;
 
 typedef struct orc_system orc_system;

@@ -249,6 +249,7 @@ class Template:
     kv: float = 0.0
     linear: bool = False
     stretch: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    model: str = "paper"   # force model: "paper" or "conservative"
 
 
 @dataclasses.dataclass

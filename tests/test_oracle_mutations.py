@@ -13,7 +13,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oif_oracle.c")
-PIN_FILES = ["tests/test_oracle_mesh.py", "tests/test_oracle_lb.py", "tests/test_oracle_coupling.py"]
+PIN_FILES = ["tests/test_oracle_mesh.py", "tests/test_oracle_lb.py", "tests/test_oracle_coupling.py",
+             "tests/test_oracle_conservative.py"]
 
 MUTATIONS = {
     "kappa_exponent": ("(lambda + pow(lambda, -3.0))", "(lambda + pow(lambda, -2.0))"),
@@ -49,6 +50,16 @@ MUTATIONS = {
     "interp_full_force": ("for (int c = 0; c < 3; ++c) u[c * N + p] = (j[c] + 0.5 * F[c]) / r;",
                           "for (int c = 0; c < 3; ++c) u[c * N + p] = (j[c] + F[c]) / r;"),
     "mass_ignored": ("V[3 * j + c] += Ft / m;", "V[3 * j + c] += Ft;"),
+    "bend_gradient_feet_swapped": ("double gB = -(1.0 - aA) * gA - (1.0 - aD) * gD;",
+                                   "double gB = -aA * gA - aD * gD;"),
+    "bend_gradient_wing_height": ("double gA = -n1[c] / hA, gD = -n2[c] / hD;",
+                                  "double gA = -n1[c] / hA, gD = -n2[c] / hA;"),
+    "bend_gradient_no_hbar": ("double dEdt = kb * hbar[e] * (theta - theta0[e]) / theta0[e];",
+                              "double dEdt = kb * (theta - theta0[e]) / theta0[e];"),
+    "wing_height_sum": ("hbar[e] = (tri_area(x, t1) + tri_area(x, t2)) / norm3(bc);",
+                        "hbar[e] = (tri_area(x, t1) + tri_area(x, t2)) / (2.0 * norm3(bc));"),
+    "balanced_rms_divisor": ("ms += dot3(w[s], w[s]) / 3.0;", "ms += dot3(w[s], w[s]) / 2.0;"),
+    "balanced_unit_vectors": ("double l = balanced ? sqrt(ms) : norm3(w[s]);", "double l = norm3(w[s]);"),
     "drift_before_kick": ("V[3 * j + c] += Ft / m;\n                    X[3 * j + c] += V[3 * j + c];",
                           "X[3 * j + c] += V[3 * j + c];\n                    V[3 * j + c] += Ft / m;"),
 }
