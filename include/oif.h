@@ -63,6 +63,19 @@ extern "C" {
 #define OIF_STRETCH_NEOHOOKE 0
 #define OIF_STRETCH_LINEAR 1
 
+/* Force models of a template.  PAPER: the bending, local-area and global-area
+ * rules as printed ("Elastic interactions").  CONSERVATIVE: the same energies'
+ * scales with directions that exert no net force and no torque on any hinge or
+ * triangle: bending as -grad[kb hbar (theta - theta0)^2 / (2 theta0)] (hbar =
+ * mean relaxed wing height of the hinge; the wings move along their normals by
+ * 1/h, the edge vertices take the rest split by where the wings' feet lie on
+ * the edge), local and global area along t_v / t_rms (centroid-to-vertex
+ * vectors over their RMS length) instead of unit vectors.  Both coincide on
+ * symmetric hinges and equilateral triangles; stretching and volume forces are
+ * the same in both. */
+#define OIF_FORCES_PAPER 0
+#define OIF_FORCES_CONSERVATIVE 1
+
 typedef struct oif_ctx oif_ctx;
 typedef struct oif_batch oif_batch;
 
@@ -98,6 +111,7 @@ typedef struct {
 typedef struct {
     double ks, kb, kal, kag, kv;
     int stretch_law; /* OIF_STRETCH_* */
+    int force_model; /* OIF_FORCES_* (0 = the paper's rules) */
 } oif_moduli;
 
 /* Object analysis (oif_object_analyze of the paper): origin = mean of the
@@ -182,12 +196,12 @@ int oif_bind_stream(oif_ctx* ctx, void* hip_stream);
 /* Register template tid (template creation of the paper).  nodes: nv x 3
  * coordinates, approximately centred at the origin; tris: nt x 3 node ids
  * whose normal AB x AC points INTO the object.  stretch (NULL = 1,1,1) scales
- * the coordinates per axis before the relaxed lengths, angles, triangle
- * areas, total area and volume are computed (in FP64, on the host).
+ * the coordinates per axis before the relaxed lengths, angles, wing heights,
+ * triangle areas, total area and volume are computed (in FP64, on the host).
  * Ids start at 0 and are consecutive; a template cannot change once objects
- * exist.  Errors: OIF_E_ARG, OIF_E_ID, OIF_E_MESH (not closed, not manifold,
- * inconsistent orientation, or enclosed volume <= 0, i.e. outward normals),
- * OIF_E_STATE. */
+ * exist.  Errors: OIF_E_ARG (also an unknown stretch law or force model),
+ * OIF_E_ID, OIF_E_MESH (not closed, not manifold, inconsistent orientation,
+ * or enclosed volume <= 0, i.e. outward normals), OIF_E_STATE. */
 int oif_template_create(oif_ctx* ctx, int tid, const double* nodes, int nv, const int32_t* tris,
                         int nt, const double stretch[3], const oif_moduli* k);
 

@@ -183,7 +183,9 @@ __device__ void mark_object(const double* pos, int nv, const int* anchor, gptr<c
     }
 }
 
-template <int P, bool USE_LDS>
+// CONS: some object of the launch may use the conservative force model (each
+// object's template says whether it does); without it that code is left out.
+template <int P, bool USE_LDS, bool CONS>
 __global__ void __launch_bounds__(1024)
 mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, int mark_next) {
     typedef typename Prec<P>::S S;
@@ -196,7 +198,8 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     const gptr<const BoxDev> B = (gptr<const BoxDev>)O.box;
     const int nv = T->nv, nt = T->nt, ne = T->ne;
     const int ucap = T->ucap, ccap = T->ccap;
-    const MeshLayout lay = mesh_layout(sizeof(R), nv, nt, ne, ucap, ccap);
+    const int cons = CONS ? T->conservative : 0;
+    const MeshLayout lay = mesh_layout(sizeof(R), nv, nt, ne, ucap, ccap, cons);
     unsigned char* base = USE_LDS ? smem : O.scratch;
     double* xs = (double*)base;       // [nv][3]
     R* fs = (R*)(base + lay.fs);      // [nv][3]: elastic force
@@ -296,7 +299,24 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                 const double dot = n1x * n2x + n1y * n2y + n1z * n2z;
                 const double2 cs = gld(T->cs0 + e);  // cos, sin of theta0 - pi
                 const R dth = atan2((R)(md * cs.x - dot * L * cs.y), (R)(dot * L * cs.x + md * cs.y));
-                fh[e] = (R)T->kb * dth / (R)gld(T->theta0 + e);
+                const R f = (R)T->kb * dth / (R)gld(T->theta0 + e);
+                if (!cons) {
+                    fh[e] = f;
+                } else {
+                    // gradient form: the wing factors c / h (c = hbar f, h = |N| / L
+                    // the wing's distance from the edge line) and the positions a of
+                    // the wings' feet on the edge, B + a (C - B)
+                    const R c = (R)gld(T->hbar + e) * f;
+                    const R nA = (R)sqrt(n1x * n1x + n1y * n1y + n1z * n1z);
+                    const R nD = (R)sqrt(n2x * n2x + n2y * n2y + n2z * n2z);
+                    const double abx = pa[0] - pb[0], aby = pa[1] - pb[1], abz = pa[2] - pb[2];
+                    const double dbx = pd[0] - pb[0], dby = pd[1] - pb[1], dbz = pd[2] - pb[2];
+                    R* q = fh + 4 * e;
+                    q[0] = c * (R)L / nA;
+                    q[1] = c * (R)L / nD;
+                    q[2] = (R)((abx * dx + aby * dy + abz * dz) / L2);
+                    q[3] = (R)((dbx * dx + dby * dy + dbz * dz) / L2);
+                }
             }
         }
     }
@@ -332,30 +352,48 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
         }
         if (do_b) {
             // wings along their triangle's normal, edge ends minus half the sum
-            // ("Bending force"); the role picks the two coefficients
+            // ("Bending force"; conservative model: minus the wing forces split
+            // by the positions of the wings' feet); the role picks the two
+            // coefficients of the normals n1, n2
 #pragma unroll 4
             for (int k = o0.y; k < o1.y; ++k) {
                 const int4 r = gld(T->h_inc + k);
                 const int role = r.x & 3;
-                const R f = fh[r.x >> 2];
-                const R hf = R(-0.5) * f;
-                const R a1 = role == 0 ? f : (role == 3 ? R(0) : hf);
-                const R a2 = role == 3 ? f : (role == 0 ? R(0) : hf);
+                R a1, a2;
+                if (!cons) {
+                    const R f = fh[r.x >> 2];
+                    const R hf = R(-0.5) * f;
+                    a1 = role == 0 ? f : (role == 3 ? R(0) : hf);
+                    a2 = role == 3 ? f : (role == 0 ? R(0) : hf);
+                } else {
+                    const R* q = fh + 4 * (r.x >> 2);
+                    const R wA = q[0], wD = q[1], aA = q[2], aD = q[3];
+                    a1 = role == 0 ? wA : (role == 3 ? R(0) : -(role == 1 ? R(1) - aA : aA) * wA);
+                    a2 = role == 3 ? wD : (role == 0 ? R(0) : -(role == 1 ? R(1) - aD : aD) * wD);
+                }
                 Fx += a1 * tn[4 * r.y] + a2 * tn[4 * r.z];
                 Fy += a1 * tn[4 * r.y + 1] + a2 * tn[4 * r.z + 1];
                 Fz += a1 * tn[4 * r.y + 2] + a2 * tn[4 * r.z + 2];
             }
         }
         // local area (-kal dS/S w), global area (-kag dSg/Sg w), volume
-        // (-kv dV/V0 S n_out / 3); w = unit centroid -> vertex
+        // (-kv dV/V0 S n_out / 3); w = centroid -> vertex over its length, or
+        // (conservative model) over the RMS length of the triangle's three
 #pragma unroll 2
         for (int k = o0.z; k < o1.z; ++k) {
             const int4 r = gld(T->t_inc + k);
             const int t = r.x;
-            const R wx = (R)(px - (px + xs[3 * r.y] + xs[3 * r.z]) * (1.0 / 3.0));
-            const R wy = (R)(py - (py + xs[3 * r.y + 1] + xs[3 * r.z + 1]) * (1.0 / 3.0));
-            const R wz = (R)(pz - (pz + xs[3 * r.y + 2] + xs[3 * r.z + 2]) * (1.0 / 3.0));
-            const R ct = (-kal * tr[t] + cg) / sqrt(wx * wx + wy * wy + wz * wz);
+            const double gx = (px + xs[3 * r.y] + xs[3 * r.z]) * (1.0 / 3.0);
+            const double gy = (py + xs[3 * r.y + 1] + xs[3 * r.z + 1]) * (1.0 / 3.0);
+            const double gz = (pz + xs[3 * r.y + 2] + xs[3 * r.z + 2]) * (1.0 / 3.0);
+            const R wx = (R)(px - gx), wy = (R)(py - gy), wz = (R)(pz - gz);
+            R n2 = wx * wx + wy * wy + wz * wz;
+            if (cons) {
+                const R bx = (R)(xs[3 * r.y] - gx), by = (R)(xs[3 * r.y + 1] - gy), bz = (R)(xs[3 * r.y + 2] - gz);
+                const R qx = (R)(xs[3 * r.z] - gx), qy = (R)(xs[3 * r.z + 1] - gy), qz = (R)(xs[3 * r.z + 2] - gz);
+                n2 = (n2 + bx * bx + by * by + bz * bz + qx * qx + qy * qy + qz * qz) * third;
+            }
+            const R ct = (-kal * tr[t] + cg) / sqrt(n2);
             const R vf = cv * tn[4 * t + 3] * third;
             Fx += ct * wx - vf * tn[4 * t];
             Fy += ct * wy - vf * tn[4 * t + 1];
@@ -649,19 +687,28 @@ template <int P>
 hipError_t launch_mesh_p(const MeshLaunch& L) {
     typedef typename Prec<P>::R R;
     const ObjDev<R>* objs = (const ObjDev<R>*)L.objs;
-    if (L.lds_bytes > 0)
-        hipLaunchKernelGGL((mesh_kernel<P, true>), dim3(L.nobj), dim3(L.block), L.lds_bytes, L.stream, objs,
-                           L.parity, L.mark_next);
-    else
-        hipLaunchKernelGGL((mesh_kernel<P, false>), dim3(L.nobj), dim3(L.block), 0, L.stream, objs, L.parity,
-                           L.mark_next);
+    const dim3 g(L.nobj), b(L.block);
+    if (L.lds_bytes > 0) {
+        if (L.conservative)
+            hipLaunchKernelGGL((mesh_kernel<P, true, true>), g, b, L.lds_bytes, L.stream, objs, L.parity,
+                               L.mark_next);
+        else
+            hipLaunchKernelGGL((mesh_kernel<P, true, false>), g, b, L.lds_bytes, L.stream, objs, L.parity,
+                               L.mark_next);
+    } else {
+        if (L.conservative)
+            hipLaunchKernelGGL((mesh_kernel<P, false, true>), g, b, 0, L.stream, objs, L.parity, L.mark_next);
+        else
+            hipLaunchKernelGGL((mesh_kernel<P, false, false>), g, b, 0, L.stream, objs, L.parity, L.mark_next);
+    }
     return hipGetLastError();
 }
 
 }  // namespace
 
-size_t mesh_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap) {
-    return mesh_layout(precision == PREC_FP64 ? sizeof(double) : sizeof(float), nv, nt, ne, ucap, ccap).total;
+size_t mesh_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap, int cons) {
+    return mesh_layout(precision == PREC_FP64 ? sizeof(double) : sizeof(float), nv, nt, ne, ucap, ccap, cons)
+        .total;
 }
 
 hipError_t launch_mesh(const MeshLaunch& L) {
@@ -678,8 +725,14 @@ hipError_t launch_mesh(const MeshLaunch& L) {
 // Let the LDS-resident variants use up to `bytes` of dynamic LDS per workgroup.
 hipError_t mesh_set_max_lds(size_t bytes) {
     hipError_t e = hipSuccess;
-    const void* fns[4] = {(const void*)mesh_kernel<PREC_FP64, true>, (const void*)mesh_kernel<PREC_FP32, true>,
-                          (const void*)mesh_kernel<PREC_FP16, true>, (const void*)mesh_kernel<PREC_BF16, true>};
+    const void* fns[8] = {(const void*)mesh_kernel<PREC_FP64, true, false>,
+                          (const void*)mesh_kernel<PREC_FP32, true, false>,
+                          (const void*)mesh_kernel<PREC_FP16, true, false>,
+                          (const void*)mesh_kernel<PREC_BF16, true, false>,
+                          (const void*)mesh_kernel<PREC_FP64, true, true>,
+                          (const void*)mesh_kernel<PREC_FP32, true, true>,
+                          (const void*)mesh_kernel<PREC_FP16, true, true>,
+                          (const void*)mesh_kernel<PREC_BF16, true, true>};
     for (const void* f : fns) {
         hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (r != hipSuccess) e = r;

@@ -64,6 +64,8 @@ struct TmplDev {
     const double* theta0;  // [ne] relaxed inner dihedral angle
     const double2* cs0;    // [ne] cos and sin of theta0 - pi (FP64)
     const double* S0;      // [nt] (FP64: S - S0 cancels near the relaxed shape)
+    const double* hbar;    // [ne] mean relaxed wing height (conservative model)
+    int conservative;      // force model: 0 = the paper's rules, 1 = conservative
     double Sg0, V0;
     double ks, kb, kal, kag, kv;
     int ucap;              // lattice nodes of the largest stencil box kept in LDS
@@ -79,7 +81,9 @@ struct TmplDev {
 //     forces phase:  tn  unit inward normal + area per triangle, R [nt][4]
 //                    tr  (S - S0)/S per triangle, R [nt]
 //                    se  stretching coefficient per edge, R [ne]
-//                    fh  bending magnitude per edge, R [ne]
+//                    fh  bending coefficients per edge: R [ne] (the paper's
+//                        magnitude) or R [ne][4] (conservative model: wing
+//                        factors c/h_A, c/h_D and foot positions a_A, a_D)
 //     coupling phase: need  one bit per node of the object's stencil box
 //                     pre   exclusive popcount prefix per bit word
 //                     ug    fluid velocity at the touched nodes, R [ccap][3]
@@ -89,15 +93,16 @@ struct MeshLayout {
     size_t fs, sb, tn, tr, se, fh, need, nwords, ug, qn, gacc, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
-__host__ __device__ inline MeshLayout mesh_layout(size_t r, int nv, int nt, int ne, int ucap, int ccap) {
+__host__ __device__ inline MeshLayout mesh_layout(size_t r, int nv, int nt, int ne, int ucap, int ccap,
+                                                   int cons) {
     MeshLayout L;
     L.fs = align16((size_t)nv * 3 * sizeof(double));
     L.sb = align16(L.fs + (size_t)nv * 3 * r);
     L.tn = align16(L.sb + (size_t)nv * 3 * sizeof(int));
     L.tr = L.tn + (size_t)nt * 4 * r;
     L.se = align16(L.tr + (size_t)nt * r);
-    L.fh = L.se + (size_t)ne * r;
-    const size_t end_forces = L.fh + (size_t)ne * r;
+    L.fh = align16(L.se + (size_t)ne * r);
+    const size_t end_forces = L.fh + (size_t)ne * r * (cons ? 4 : 1);
     L.need = L.tn;
     L.nwords = ((size_t)ucap + 31) / 32;
     L.ug = align16(L.need + 2 * L.nwords * 4);
@@ -157,12 +162,13 @@ struct MeshLaunch {
     size_t lds_bytes;      // dynamic LDS per block (0 = each object's global scratch)
     int mark_next;         // also mark the stencils of the new positions in
                            // touch[parity ^ 1] (split stepping)
+    int conservative;      // some object of the launch uses the conservative force model
     hipStream_t stream;
 };
 hipError_t launch_mesh(const MeshLaunch& L);
 
 // Per-template LDS bytes of the mesh kernel.
-size_t mesh_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap);
+size_t mesh_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap, int cons);
 // Allow the LDS-resident mesh kernels to use up to `bytes` of dynamic LDS.
 hipError_t mesh_set_max_lds(size_t bytes);
 

@@ -39,6 +39,7 @@ struct Template {
     std::vector<std::array<int, 2>> hinge_tri;
     std::vector<std::array<int, 2>> edge;
     std::vector<double> L0, theta0, S0;
+    std::vector<double> hbar;           // mean relaxed wing height per hinge
     double Sg0 = 0, V0 = 0;
     oif_moduli k{};
     int ucap = 0; // lattice nodes of the largest stencil box an object can span
@@ -47,6 +48,8 @@ struct Template {
     std::vector<std::array<int, 2>> e_inc;
     std::vector<int> h_inc, t_inc;
 };
+
+inline int tmpl_conservative(const Template& T) { return T.k.force_model == OIF_FORCES_CONSERVATIVE ? 1 : 0; }
 
 inline void vsub(const double* a, const double* b, double* r) {
     r[0] = a[0] - b[0]; r[1] = a[1] - b[1]; r[2] = a[2] - b[2];
@@ -164,6 +167,10 @@ int build_template(const double* nodes, int nv, const int32_t* tris, int nt, con
         return OIF_E_MESH;
     }
     T.k = *k;
+    // mean relaxed wing height of each hinge, (S(T1) + S(T2)) / L0: the length
+    // scale of the gradient form of the bending energy
+    T.hbar.resize(T.ne);
+    for (int e = 0; e < T.ne; ++e) T.hbar[e] = (T.S0[T.hinge_tri[e][0]] + T.S0[T.hinge_tri[e][1]]) / T.L0[e];
     // Stencil box of an object: nodes within radius Rb of the centroid span at
     // most ceil(2 Rb) + 2 lattice nodes per axis; two more allow for deformation.
     {
@@ -263,6 +270,7 @@ struct oif_ctx {
     std::vector<unsigned char> obj_host; // ObjDev<real> array as uploaded (sorted)
     int n_lds_obj = 0;          // objects [0, n_lds_obj) use LDS, the rest global scratch
     size_t lds_need = 0;
+    int any_conservative = 0;   // some template uses the conservative force model
 
     // launch configuration
     int lb_block = 256, mesh_block = 256, remap = 1;
@@ -283,6 +291,7 @@ struct oif_batch {
     std::vector<unsigned char> obj_host;
     int nblocks = 0, nobj = 0, n_lds_obj = 0;
     size_t lds_need = 0;
+    int any_conservative = 0;
     int lb_block = 256, mesh_block = 256, remap = 1;
     int graph_steps = 0;
     hipGraphExec_t gexec = nullptr;
@@ -391,7 +400,8 @@ int upload_mesh_t(oif_ctx* c) {
                  {einc.data(), einc.size() * 8},          {hinc.data(), hinc.size() * 16},
                  {tinc.data(), tinc.size() * 16},         {L0.data(), L0.size() * sizeof(double)},
                  {hv.data(), hv.size() * 16},             {th.data(), th.size() * sizeof(double)},
-                 {cs0.data(), cs0.size() * sizeof(double)}, {S0.data(), S0.size() * sizeof(double)}};
+                 {cs0.data(), cs0.size() * sizeof(double)}, {S0.data(), S0.size() * sizeof(double)},
+                 {T.hbar.data(), T.hbar.size() * sizeof(double)}};
         std::vector<size_t> offs;
         size_t total = 0;
         for (auto& p : parts) {
@@ -417,6 +427,8 @@ int upload_mesh_t(oif_ctx* c) {
         D.theta0 = (const double*)(b + offs[7]);
         D.cs0 = (const double2*)(b + offs[8]);
         D.S0 = (const double*)(b + offs[9]);
+        D.hbar = (const double*)(b + offs[10]);
+        D.conservative = tmpl_conservative(T);
         D.Sg0 = T.Sg0; D.V0 = T.V0;
         D.ks = T.k.ks; D.kb = T.k.kb; D.kal = T.k.kal; D.kag = T.k.kag; D.kv = T.k.kv;
         D.ucap = T.ucap;
@@ -449,7 +461,7 @@ int upload_mesh_t(oif_ctx* c) {
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     auto need = [&](int i) {
         const Template& T = c->tmpl[c->obj[i].tid];
-        return mesh_lds_bytes(c->d.precision, T.nv, T.nt, T.ne, T.ucap, T.ccap);
+        return mesh_lds_bytes(c->d.precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T));
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         const bool la = need(a) <= budget, lb = need(b) <= budget;
@@ -458,6 +470,8 @@ int upload_mesh_t(oif_ctx* c) {
     });
     c->n_lds_obj = 0;
     c->lds_need = 0;
+    c->any_conservative = 0;
+    for (const Template& T : c->tmpl) c->any_conservative |= tmpl_conservative(T);
     c->mark_lds = 16;
     for (const Template& T : c->tmpl) c->mark_lds = std::max(c->mark_lds, (size_t)((T.ucap + 31) / 32) * 4);
     c->mark_lds = std::min<size_t>(c->mark_lds, 49152);  // larger stencil boxes mark corner by corner
@@ -531,6 +545,7 @@ int enqueue_mesh(oif_ctx* c, int par, hipStream_t s, int mark_next) {
     ml.block = c->mesh_block;
     ml.parity = par;
     ml.mark_next = mark_next;
+    ml.conservative = c->any_conservative;
     ml.precision = c->d.precision;
     ml.stream = s;
     if (c->n_lds_obj > 0) {
@@ -840,6 +855,10 @@ int oif_template_create(oif_ctx* c, int tid, const double* nodes, int nv, const 
     if (!c->obj.empty()) return fail(c, OIF_E_STATE, "templates must be created before objects");
     for (double v : {k->ks, k->kb, k->kal, k->kag, k->kv})
         if (!std::isfinite(v)) return fail(c, OIF_E_ARG, "non-finite modulus");
+    if (k->stretch_law != OIF_STRETCH_NEOHOOKE && k->stretch_law != OIF_STRETCH_LINEAR)
+        return fail(c, OIF_E_ARG, "unknown stretch law");
+    if (k->force_model != OIF_FORCES_PAPER && k->force_model != OIF_FORCES_CONSERVATIVE)
+        return fail(c, OIF_E_ARG, "unknown force model");
     if (stretch)
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(stretch[a]) || stretch[a] <= 0) return fail(c, OIF_E_ARG, "stretch must be > 0");
@@ -1451,7 +1470,8 @@ int batch_build(oif_batch* b) {
             const size_t tsz = b->precision == OIF_PREC_FP64 ? sizeof(TmplDev<double>) : sizeof(TmplDev<float>);
             const size_t tid = ((const unsigned char*)tptr - (const unsigned char*)c->tmpl_dev.p) / tsz;
             const Template& T = c->tmpl[tid];
-            ents.push_back({p, lds, T.nv, mesh_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap)});
+            ents.push_back({p, lds, T.nv,
+                            mesh_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T))});
         }
     }
     std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& c) {
@@ -1461,6 +1481,9 @@ int batch_build(oif_batch* b) {
     std::vector<unsigned char> host(ents.size() * osz);
     b->n_lds_obj = 0;
     b->lds_need = 0;
+    b->any_conservative = 0;
+    for (oif_ctx* c : b->ctx)
+        for (const Template& T : c->tmpl) b->any_conservative |= tmpl_conservative(T);
     for (size_t k = 0; k < ents.size(); ++k) {
         std::memcpy(host.data() + k * osz, ents[k].p, osz);
         if (ents[k].lds) {
@@ -1485,6 +1508,7 @@ int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<h
         ml.block = b->mesh_block;
         ml.parity = par;
         ml.precision = b->precision;
+        ml.conservative = b->any_conservative;
         ml.stream = s;
         if (b->n_lds_obj > 0) {
             ml.objs = b->obj_dev.p;

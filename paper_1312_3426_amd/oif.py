@@ -23,6 +23,8 @@ E_ARG, E_ID, E_MESH, E_STATE, E_NOMEM, E_HIP, E_NONFINITE, E_OVERFLOW, E_UNSUPPO
 PREC_FP64, PREC_FP32, PREC_FP32_ST_FP16, PREC_FP32_ST_BF16 = 0, 1, 2, 3
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp16": PREC_FP32_ST_FP16, "bf16": PREC_FP32_ST_BF16}
 STRETCH_NEOHOOKE, STRETCH_LINEAR = 0, 1
+FORCES_PAPER, FORCES_CONSERVATIVE = 0, 1
+_MODELS = {"paper": FORCES_PAPER, "conservative": FORCES_CONSERVATIVE}
 
 
 class OifError(RuntimeError):
@@ -40,7 +42,7 @@ class LatticeDesc(C.Structure):
 
 class Moduli(C.Structure):
     _fields_ = [("ks", C.c_double), ("kb", C.c_double), ("kal", C.c_double), ("kag", C.c_double),
-                ("kv", C.c_double), ("stretch_law", C.c_int)]
+                ("kv", C.c_double), ("stretch_law", C.c_int), ("force_model", C.c_int)]
 
 
 class Analysis(C.Structure):
@@ -205,10 +207,11 @@ class Context:
 
     # -- templates and objects --
     def template_create(self, tid: int, nodes, tris, stretch=None, ks=0.0, kb=0.0, kal=0.0, kag=0.0,
-                        kv=0.0, linear: bool = False):
+                        kv=0.0, linear: bool = False, model="paper"):
         nodes = _f64(nodes)
         tris = np.ascontiguousarray(tris, dtype=np.int32)
-        k = Moduli(ks, kb, kal, kag, kv, STRETCH_LINEAR if linear else STRETCH_NEOHOOKE)
+        m = _MODELS[model] if isinstance(model, str) else int(model)
+        k = Moduli(ks, kb, kal, kag, kv, STRETCH_LINEAR if linear else STRETCH_NEOHOOKE, m)
         st = None if stretch is None else _f64(stretch)
         self._chk(lib().oif_template_create(self.h, tid, _p(nodes), len(nodes), _p(tris), len(tris),
                                             _p(st), C.byref(k)))
@@ -314,7 +317,7 @@ class Context:
                 friction=box.friction, walls_z=box.walls_z, precision=precision, **kw)
         for tid, t in enumerate(box.templates):
             c.template_create(tid, t.nodes, t.tris, stretch=t.stretch, ks=t.ks, kb=t.kb, kal=t.kal,
-                              kag=t.kag, kv=t.kv, linear=t.linear)
+                              kag=t.kag, kv=t.kv, linear=t.linear, model=getattr(t, "model", "paper"))
         for oid, o in enumerate(box.objects):
             c.object_add(oid, o.tid, o.origin, o.rot, o.mass, 0)
             if any(o.fext):

@@ -254,6 +254,9 @@ def test_input_validation(oif):
     with pytest.raises(oif.OifError) as ei:
         c.template_create(0, x, t[:-1], ks=0.1)           # open mesh
     assert ei.value.code == oif.E_MESH
+    with pytest.raises(oif.OifError) as ei:
+        c.template_create(0, x, t, ks=0.1, model=5)       # unknown force model
+    assert ei.value.code == oif.E_ARG
     c.template_create(0, x, t, ks=0.1, stretch=(1.0, 1.0, 1.5))
     with pytest.raises(oif.OifError) as ei:
         c.object_add(1, 0, (8, 8, 8))

@@ -180,3 +180,101 @@ def test_watchdog_trips_on_divergent_friction(oif):
     assert ei.value.code == oif.E_NONFINITE
     assert ctx.diagnostics().nonfinite == 1
     ctx.close()
+
+
+# ---- conservative force model (per template) -------------------------------
+
+def _conservative(box, which=None):
+    for i, t in enumerate(box.templates):
+        if which is None or i in which:
+            t.model = "conservative"
+    return box
+
+
+def test_conservative_sphere_fp64_deformed_start(oif, orc):
+    """Conservative model (gradient bending, balanced area forces), FP64, the
+    deformed moving start: plain relative 1e-12 after one step."""
+    say("[conservative] sphere642 deformed start fp64")
+    box = _conservative(synth.config_sphere_fp64(40))
+    rng = np.random.default_rng(29)
+    sysm = orc.System(box)
+    X0 = sysm.X + 0.012 * rng.standard_normal(sysm.X.shape)
+    V0 = 2e-4 * rng.standard_normal(sysm.X.shape)
+    n0 = synth.random_populations(rng, box, amp=2e-3)
+    sysm.X[:] = X0
+    sysm.V[:] = V0
+    sysm.n[:] = n0
+    ctx = oif.Context.from_box(box, precision="fp64")
+    ctx.write_mesh(-1, X0, V0)
+    ctx.write_populations(n0)
+    done = 0
+    for k in (1, 40):
+        ctx.step(k - done)
+        sysm.run(k - done)
+        done = k
+        res = check(gpu_fields(ctx, box.rho0, X0), oracle_fields(sysm, X0), "fp64", box.rho0, 20)
+        say(f"   step {k}: {fmt(res)}")
+        assert_ok(res, f"step {k}")
+        if k == 1:
+            for key, (e, r, b, ok) in res.items():
+                assert e <= 1e-12 * r, (k, key, e / r)
+    ctx.close()
+
+
+def test_conservative_channel_fp32(oif, orc):
+    """Conservative model, FP32 channel case with walls, 100 steps."""
+    say("[conservative] rbc393x10 64x32x32 walls fp32")
+    box = _conservative(synth.config_channel_rbc(100))
+    for k, g, o in run_pair(oif, orc, box, "fp32", (1, 100)):
+        res = check(g, o, "fp32", box.rho0, 64)
+        say(f"   step {k}: {fmt(res)}")
+        assert_ok(res, f"step {k}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mixed_force_models_in_one_box(oif, orc, prec):
+    """Templates with different models in one launch: each object follows its
+    own template.  Batching-case box (32^3, spheres of 162/642/2562 nodes) with
+    the 642-node template conservative, from a deformed moving start so the two
+    models differ strongly; the same start under the paper's model for every
+    template must be far from the GPU result (the check can tell them apart)."""
+    say(f"[conservative] mixed models, batch box, {prec}")
+    boxes = synth.config_batch(steps=3)
+    box = next(b for b in boxes if 1 in {o.tid for o in b.objects} and len({o.tid for o in b.objects}) >= 2)
+    box = _conservative(box, which={1})
+    rng = np.random.default_rng(41)
+    sysm = orc.System(box)
+    X0 = sysm.X + 0.01 * rng.standard_normal(sysm.X.shape)
+    V0 = 1e-4 * rng.standard_normal(sysm.X.shape)
+    n0 = synth.random_populations(rng, box, amp=1e-3)
+    ctx = oif.Context.from_box(box, precision=prec)
+    ctx.write_mesh(-1, X0, V0)
+    ctx.write_populations(n0)
+    for s_ in (sysm,):
+        s_.X[:] = X0
+        s_.V[:] = V0
+        s_.n[:] = n0
+    for t in box.templates:
+        t.model = "paper"
+    other = orc.System(box)
+    other.X[:] = X0
+    other.V[:] = V0
+    other.n[:] = n0
+    done = 0
+    for k in (1, 3):
+        ctx.step(k - done)
+        sysm.run(k - done)
+        other.run(k - done)
+        done = k
+        g, o = gpu_fields(ctx, box.rho0, X0), oracle_fields(sysm, X0)
+        res = check(g, o, prec, box.rho0, box.nx)
+        say(f"   step {k}: {fmt(res)}")
+        assert_ok(res, f"step {k}")
+        if k == 1:
+            dV = rel(g["V"], oracle_fields(other, X0)["V"])
+            say(f"   paper-model oracle differs in V by {dV:.2e} (rel)")
+            assert dV > 100 * (1e-12 if prec == "fp64" else 1e-5)
+            if prec == "fp64":
+                for key, (e, r, b, ok) in res.items():
+                    assert e <= 1e-12 * r, (k, key, e / r)
+    ctx.close()
