@@ -49,7 +49,7 @@ def build(force: bool = False) -> str:
 class _Lattice(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("walls_z", C.c_int),
                 ("tau", C.c_double), ("rho0", C.c_double), ("g", C.c_double * 3),
-                ("xi", C.c_double)]
+                ("xi", C.c_double), ("solid", C.c_void_p), ("wall_u", C.c_void_p)]
 
 
 class _Mesh(C.Structure):
@@ -109,6 +109,10 @@ def lib():
             f.restype = None
         L.orc_moments.restype = None
         L.orc_moments.argtypes = [vp, dp, dp, dp, dp]
+        L.orc_mark_rhomboid.restype = None
+        L.orc_mark_rhomboid.argtypes = [vp, vp, C.c_int, dp, dp, dp, dp]
+        L.orc_mark_wall.restype = None
+        L.orc_mark_wall.argtypes = [vp, vp, C.c_int, dp, C.c_double]
         L.orc_lb_step.restype = None
         L.orc_lb_step.argtypes = [vp, dp, dp, dp]
         L.orc_stencil.restype = C.c_int
@@ -299,13 +303,40 @@ def force_triangles(which: str, x, tris, k, S0=None, Sg0=None, V0=None) -> np.nd
 # lattice-level functions
 # ---------------------------------------------------------------------------
 
-def _lattice(nx, ny, nz, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0), xi=0.0, walls_z=False) -> _Lattice:
+def _lattice(nx, ny, nz, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0), xi=0.0, walls_z=False,
+             obstacles=None) -> _Lattice:
+    """Lattice descriptor; obstacles = (solid uint8 [N], wall_u float64 [nb+1][3])
+    from ``boundary_field`` (the caller keeps the arrays alive)."""
     L = _Lattice()
     L.nx, L.ny, L.nz, L.walls_z = int(nx), int(ny), int(nz), int(bool(walls_z))
     L.tau, L.rho0, L.xi = float(tau), float(rho0), float(xi)
     for c in range(3):
         L.g[c] = float(g[c])
+    if obstacles is not None:
+        L.solid, L.wall_u = obstacles[0].ctypes.data, obstacles[1].ctypes.data
     return L
+
+
+def boundary_field(nx, ny, nz, boundaries) -> Tuple[np.ndarray, np.ndarray]:
+    """Solid-node field and wall velocities of a list of boundary descriptions
+    (``synth.Boundary``-like: kind 'rhomboid' with corner, a, b, c or kind
+    'wall' with normal, dist; velocity).  Boundary k (1-based, in list order)
+    overwrites earlier ones where they overlap."""
+    if len(boundaries) > 255:
+        raise ValueError("at most 255 boundaries")
+    solid = np.zeros((nz, ny, nx), dtype=np.uint8)
+    wall_u = np.zeros((len(boundaries) + 1, 3))
+    L = _lattice(nx, ny, nz)
+    for k, b in enumerate(boundaries, start=1):
+        wall_u[k] = b.velocity
+        if b.kind == "rhomboid":
+            lib().orc_mark_rhomboid(C.byref(L), solid.ctypes.data, k, _p(_f64(b.corner)), _p(_f64(b.a)),
+                                    _p(_f64(b.b)), _p(_f64(b.c)))
+        elif b.kind == "wall":
+            lib().orc_mark_wall(C.byref(L), solid.ctypes.data, k, _p(_f64(b.normal)), float(b.dist))
+        else:
+            raise ValueError(b.kind)
+    return solid, wall_u
 
 
 def equilibrium_populations(nx, ny, nz, rho0=1.0) -> np.ndarray:
@@ -314,22 +345,23 @@ def equilibrium_populations(nx, ny, nz, rho0=1.0) -> np.ndarray:
 
 
 def lb_step(n: np.ndarray, tau=1.0, g=(0.0, 0.0, 0.0), G: Optional[np.ndarray] = None,
-            walls_z=False) -> np.ndarray:
+            walls_z=False, obstacles=None, rho0=1.0) -> np.ndarray:
     n = _f64(n)
     _, nz, ny, nx = n.shape
-    L = _lattice(nx, ny, nz, tau=tau, g=g, walls_z=walls_z)
+    L = _lattice(nx, ny, nz, tau=tau, g=g, walls_z=walls_z, obstacles=obstacles, rho0=rho0)
     out = np.empty_like(n)
     Gp = None if G is None else _f64(G)
     lib().orc_lb_step(C.byref(L), _p(n), None if Gp is None else _p(Gp), _p(out))
     return out
 
 
-def moments(n: np.ndarray, g=(0.0, 0.0, 0.0), G: Optional[np.ndarray] = None
-            ) -> Tuple[np.ndarray, np.ndarray]:
-    """(rho (nz,ny,nx), u (3,nz,ny,nx)) with u = (sum n e + F/2)/rho, F = g + G."""
+def moments(n: np.ndarray, g=(0.0, 0.0, 0.0), G: Optional[np.ndarray] = None, obstacles=None,
+            rho0=1.0) -> Tuple[np.ndarray, np.ndarray]:
+    """(rho (nz,ny,nx), u (3,nz,ny,nx)) with u = (sum n e + F/2)/rho, F = g + G
+    (rho0 and the wall velocity at solid nodes)."""
     n = _f64(n)
     _, nz, ny, nx = n.shape
-    L = _lattice(nx, ny, nz, g=g)
+    L = _lattice(nx, ny, nz, g=g, obstacles=obstacles, rho0=rho0)
     rho = np.empty((nz, ny, nx))
     u = np.empty((3, nz, ny, nx))
     Gp = None if G is None else _f64(G)
@@ -347,11 +379,12 @@ def stencil(X, dims, walls_z=False) -> Tuple[np.ndarray, np.ndarray, int]:
     return idx, w, cl
 
 
-def couple_point(u: np.ndarray, X, V, xi: float, walls_z=False) -> Tuple[np.ndarray, np.ndarray]:
+def couple_point(u: np.ndarray, X, V, xi: float, walls_z=False, obstacles=None
+                 ) -> Tuple[np.ndarray, np.ndarray]:
     """(G (3, nz, ny, nx) spread by one point, drag xi (V - u(X)))."""
     u = _f64(u)
     _, nz, ny, nx = u.shape
-    L = _lattice(nx, ny, nz, xi=xi, walls_z=walls_z)
+    L = _lattice(nx, ny, nz, xi=xi, walls_z=walls_z, obstacles=obstacles)
     G = np.zeros_like(u)
     drag = np.zeros(3)
     X, V = _f64(X), _f64(V)
@@ -379,8 +412,10 @@ class System:
 
     def __init__(self, box):
         self.box = box
+        bnd = list(getattr(box, "boundaries", []) or [])
+        self.obstacles = boundary_field(box.nx, box.ny, box.nz, bnd) if bnd else None
         L = self._L = _lattice(box.nx, box.ny, box.nz, tau=box.tau, rho0=box.rho0, g=box.g,
-                               xi=box.friction, walls_z=box.walls_z)
+                               xi=box.friction, walls_z=box.walls_z, obstacles=self.obstacles)
         # templates: apply the per-axis stretch to the node coordinates
         t_x, t_nv, t_nt, t_off, t_tri_off, tri, t_k, t_lin, t_mod = [], [], [], [], [], [], [], [], []
         noff = toff = 0

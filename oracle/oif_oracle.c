@@ -489,6 +489,12 @@ void orc_moments(const orc_lattice* L, const double* n, const double* Fx, double
                  double* u) {
     long N = (long)L->nx * L->ny * L->nz;
     for (long p = 0; p < N; ++p) {
+        if (L->solid && L->solid[p]) {
+            if (rho) rho[p] = L->rho0;
+            if (u)
+                for (int c = 0; c < 3; ++c) u[c * N + p] = L->wall_u[3 * L->solid[p] + c];
+            continue;
+        }
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < 19; ++i) {
             double ni = n[i * N + p];
@@ -510,6 +516,10 @@ void orc_lb_step(const orc_lattice* L, const double* n, const double* G, double*
         for (int y = 0; y < L->ny; ++y)
             for (int x = 0; x < L->nx; ++x) {
                 long p = node_index(L, x, y, z);
+                if (L->solid && L->solid[p]) {  /* obstacle node: not updated */
+                    for (int i = 0; i < 19; ++i) nout[i * N + p] = n[i * N + p];
+                    continue;
+                }
                 double F[3];
                 for (int c = 0; c < 3; ++c) F[c] = L->g[c] + (G ? G[c * N + p] : 0.0);
                 /* moments */
@@ -543,7 +553,16 @@ void orc_lb_step(const orc_lattice* L, const double* n, const double* G, double*
                         nout[opposite(i) * N + p] = ns;
                     } else {
                         zd = wrap(zd, L->nz);
-                        nout[i * N + node_index(L, xd, yd, zd)] = ns;
+                        long q = node_index(L, xd, yd, zd);
+                        int b = L->solid ? L->solid[q] : 0;
+                        if (b) {
+                            /* bounce-back from an obstacle moving with u_w:
+                             * n_opp(i)(x) = n_i*(x) - 2 w_i rho0 (e_i . u_w) / c_s^2 */
+                            double euw = dot3(e, &L->wall_u[3 * b]);
+                            nout[opposite(i) * N + p] = ns - 6.0 * w * L->rho0 * euw;
+                        } else {
+                            nout[i * N + q] = ns;
+                        }
                     }
                 }
             }
@@ -606,10 +625,48 @@ int orc_couple_point(const orc_lattice* L, const double* u, const double* X, con
         for (int c = 0; c < 3; ++c) uj[c] += w[k] * u[c * N + idx[k]];
     /* xi (v - u): the force handed to the fluid; the point feels its opposite */
     for (int c = 0; c < 3; ++c) drag[c] = L->xi * (V[c] - uj[c]);
-    /* distributed to the same 8 nodes with the same weights */
-    for (int k = 0; k < 8; ++k)
+    /* distributed to the same 8 nodes with the same weights (fluid nodes only) */
+    for (int k = 0; k < 8; ++k) {
+        if (L->solid && L->solid[idx[k]]) continue;
         for (int c = 0; c < 3; ++c) G[c * N + idx[k]] += w[k] * drag[c];
+    }
     return clamped;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Obstacle shapes (the lbboundary shapes of the paper's scripts)            */
+/* ------------------------------------------------------------------------- */
+
+/* Rhomboid: solve (x - corner) = s a + t b + u c by Cramer's rule; the node
+ * is inside when s, t, u all lie in [0, 1]. */
+void orc_mark_rhomboid(const orc_lattice* L, unsigned char* solid, int id, const double* corner,
+                       const double* a, const double* b, const double* c) {
+    double bc[3], ca[3], ab[3];
+    cross3(b, c, bc);
+    cross3(c, a, ca);
+    cross3(a, b, ab);
+    double det = dot3(a, bc);
+    for (int z = 0; z < L->nz; ++z)
+        for (int y = 0; y < L->ny; ++y)
+            for (int x = 0; x < L->nx; ++x) {
+                double r[3] = {x + 0.5 - corner[0], y + 0.5 - corner[1], z + 0.5 - corner[2]};
+                double s = dot3(r, bc) / det, t = dot3(r, ca) / det, u = dot3(r, ab) / det;
+                if (s >= 0.0 && s <= 1.0 && t >= 0.0 && t <= 1.0 && u >= 0.0 && u <= 1.0)
+                    solid[node_index(L, x, y, z)] = (unsigned char)id;
+            }
+}
+
+/* Wall: the half-space whose signed distance n.x - dist (n normalised) is
+ * negative. */
+void orc_mark_wall(const orc_lattice* L, unsigned char* solid, int id, const double* normal,
+                   double dist) {
+    double len = norm3(normal);
+    for (int z = 0; z < L->nz; ++z)
+        for (int y = 0; y < L->ny; ++y)
+            for (int x = 0; x < L->nx; ++x) {
+                double r[3] = {x + 0.5, y + 0.5, z + 0.5};
+                if (dot3(r, normal) / len - dist < 0.0) solid[node_index(L, x, y, z)] = (unsigned char)id;
+            }
 }
 
 /* ------------------------------------------------------------------------- */

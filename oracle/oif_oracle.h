@@ -94,15 +94,32 @@ typedef struct {
     double rho0;
     double g[3];     /* uniform body-force density */
     double xi;       /* friction coefficient of the drag coupling */
+    /* obstacles (lbboundary of the paper's scripts), may be NULL: solid[N] =
+     * 0 for fluid, k > 0 for a node of boundary k moving with velocity
+     * wall_u[3 k .. 3 k + 2] */
+    const unsigned char* solid;
+    const double* wall_u;
 } orc_lattice;
 
+/* Boundary shapes: set solid[p] = id for every node whose centre lies inside.
+ * Rhomboid: {corner + s a + t b + u c : s, t, u in [0, 1]}.  Wall: the
+ * half-space n.x < dist (n normalised). */
+void orc_mark_rhomboid(const orc_lattice* L, unsigned char* solid, int id, const double* corner,
+                       const double* a, const double* b, const double* c);
+void orc_mark_wall(const orc_lattice* L, unsigned char* solid, int id, const double* normal,
+                   double dist);
+
 /* Density and velocity of every node, u = (sum n_i e_i + F/2) / rho with the
- * given force density field Fx (3*N, may be NULL for body force only). */
+ * given force density field Fx (3*N, may be NULL for body force only); at a
+ * solid node rho0 and the wall velocity. */
 void orc_moments(const orc_lattice* L, const double* n, const double* Fx,
                  double* rho, double* u);
 
 /* One collide + stream update of the whole lattice, n -> nout, with force
- * density g + G (G may be NULL).  n and nout must not alias. */
+ * density g + G (G may be NULL).  A population streaming into a solid node
+ * returns to its own node in the opposite direction, less
+ * 6 w_i rho0 (e_i . u_wall) (bounce-back from a moving wall); solid nodes keep
+ * their populations.  n and nout must not alias. */
 void orc_lb_step(const orc_lattice* L, const double* n, const double* G, double* nout);
 
 /* Trilinear stencil of a point: 8 node indices and weights.  Returns the number
@@ -111,8 +128,9 @@ int orc_stencil(const orc_lattice* L, const double* X, long* idx, double* w);
 
 /* Drag coupling of one mesh point at X with velocity V: interpolates the node
  * velocity field u (3*N) at X, writes the force handed to the fluid,
- * drag = xi (V - u(X)), and ADDS its trilinear share to G (3*N).  The point
- * itself feels -drag.  Returns the number of clamped corners. */
+ * drag = xi (V - u(X)), and ADDS its trilinear share to G (3*N) at fluid
+ * nodes (a solid node takes none).  The point itself feels -drag.  Returns
+ * the number of clamped corners. */
 int orc_couple_point(const orc_lattice* L, const double* u, const double* X, const double* V,
                      double* G, double* drag);
 

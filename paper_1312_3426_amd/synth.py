@@ -262,6 +262,22 @@ class ObjectSpec:
 
 
 @dataclasses.dataclass
+class Boundary:
+    """Obstacle (the lbboundary shapes of the paper's scripts): kind "rhomboid"
+    (corner, edge vectors a, b, c) or "wall" (half-space normal . x < dist),
+    moving with `velocity` (0 = at rest; a moving boundary drives the fluid,
+    e.g. as a velocity inlet)."""
+    kind: str
+    corner: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    a: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    b: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    c: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    normal: Tuple[float, float, float] = (0.0, 0.0, 1.0)
+    dist: float = 0.0
+    velocity: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+
+
+@dataclasses.dataclass
 class Box:
     nx: int
     ny: int
@@ -275,6 +291,7 @@ class Box:
     objects: List[ObjectSpec] = dataclasses.field(default_factory=list)
     steps: int = 1
     name: str = ""
+    boundaries: List[Boundary] = dataclasses.field(default_factory=list)
 
     @property
     def n_nodes(self) -> int:

@@ -14,7 +14,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oif_oracle.c")
 PIN_FILES = ["tests/test_oracle_mesh.py", "tests/test_oracle_lb.py", "tests/test_oracle_coupling.py",
-             "tests/test_oracle_conservative.py"]
+             "tests/test_oracle_conservative.py", "tests/test_oracle_boundaries.py"]
 
 MUTATIONS = {
     "kappa_exponent": ("(lambda + pow(lambda, -3.0))", "(lambda + pow(lambda, -2.0))"),
@@ -60,6 +60,19 @@ MUTATIONS = {
                         "hbar[e] = (tri_area(x, t1) + tri_area(x, t2)) / (2.0 * norm3(bc));"),
     "balanced_rms_divisor": ("ms += dot3(w[s], w[s]) / 3.0;", "ms += dot3(w[s], w[s]) / 2.0;"),
     "balanced_unit_vectors": ("double l = balanced ? sqrt(ms) : norm3(w[s]);", "double l = norm3(w[s]);"),
+    "moving_wall_sign": ("nout[opposite(i) * N + p] = ns - 6.0 * w * L->rho0 * euw;",
+                         "nout[opposite(i) * N + p] = ns + 6.0 * w * L->rho0 * euw;"),
+    "moving_wall_factor": ("nout[opposite(i) * N + p] = ns - 6.0 * w * L->rho0 * euw;",
+                           "nout[opposite(i) * N + p] = ns - 3.0 * w * L->rho0 * euw;"),
+    "obstacle_bounce_direction": ("nout[opposite(i) * N + p] = ns - 6.0 * w * L->rho0 * euw;",
+                                  "nout[i * N + p] = ns - 6.0 * w * L->rho0 * euw;"),
+    "rhomboid_open_faces": ("s >= 0.0 && s <= 1.0 && t >= 0.0 && t <= 1.0 && u >= 0.0 && u <= 1.0",
+                            "s > 0.0 && s < 1.0 && t > 0.0 && t < 1.0 && u > 0.0 && u < 1.0"),
+    "wall_closed_half_space": ("dot3(r, normal) / len - dist < 0.0)", "dot3(r, normal) / len - dist <= 0.0)"),
+    "solid_velocity_ignored": ("for (int c = 0; c < 3; ++c) u[c * N + p] = L->wall_u[3 * L->solid[p] + c];",
+                               "for (int c = 0; c < 3; ++c) u[c * N + p] = 0.0;"),
+    "spread_into_solid": ("if (L->solid && L->solid[idx[k]]) continue;", "if (0) continue;"),
+    "solid_nodes_updated": ("if (L->solid && L->solid[p]) {  /* obstacle node: not updated */", "if (0) {"),
     "drift_before_kick": ("V[3 * j + c] += Ft / m;\n                    X[3 * j + c] += V[3 * j + c];",
                           "X[3 * j + c] += V[3 * j + c];\n                    V[3 * j + c] += Ft / m;"),
 }
