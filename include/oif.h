@@ -191,6 +191,35 @@ const char* oif_last_error(const oif_ctx* ctx);
  * the stream alive while it is bound. */
 int oif_bind_stream(oif_ctx* ctx, void* hip_stream);
 
+/* ---- obstacles ---------------------------------------------------------------- */
+
+/* Obstacles (the lbboundary shapes of the paper's simulation scripts,
+ * "Implementation details"): every lattice node whose centre lies inside the
+ * shape (faces included) becomes a solid node of a new boundary moving with
+ * `velocity` (NULL = at rest); *id (may be NULL) receives its id, 1-based.  A
+ * population that would stream into a solid node returns to its own node in
+ * the opposite direction, less 6 w_i rho0 (e_i . u_wall): bounce-back from a
+ * moving wall, so a moving boundary drives the fluid (a velocity inlet or a
+ * sliding wall).  Solid nodes are not updated, report rho0 and the wall
+ * velocity to the coupling and to oif_read_density/velocity, and take no share
+ * of the spread coupling force.  A later boundary overwrites earlier ones
+ * where they overlap; at most 255 per context.  The built-in z walls
+ * (walls_z) are separate and act first.
+ * Rhomboid: {corner + s a + t b + u c : s, t, u in [0, 1]}, the edge vectors
+ * linearly independent.  Wall: the half-space n . x < dist with n = normal /
+ * |normal|.  Errors: OIF_E_ARG (non-finite or degenerate shape, 255 boundaries
+ * already), OIF_E_NOMEM, OIF_E_HIP. */
+int oif_boundary_rhomboid(oif_ctx* ctx, const double corner[3], const double a[3], const double b[3],
+                          const double c[3], const double velocity[3], int* id);
+int oif_boundary_wall(oif_ctx* ctx, const double normal[3], double dist, const double velocity[3], int* id);
+
+/* Remove all obstacles. */
+int oif_boundary_clear(oif_ctx* ctx);
+
+/* Boundary id of every node (0 = fluid): caller-allocated uint8 [N], layout
+ * [z][y][x]. */
+int oif_read_boundary(oif_ctx* ctx, uint8_t* out);
+
 /* ---- templates and objects ------------------------------------------------ */
 
 /* Register template tid (template creation of the paper).  nodes: nv x 3

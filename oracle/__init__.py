@@ -508,6 +508,6 @@ class System:
     def fields(self) -> Dict[str, np.ndarray]:
         """Canonical output fields: populations, deviations from rest, density,
         velocity (with half the body force), mesh positions and velocities."""
-        rho, u = moments(self.n, g=self.box.g)
+        rho, u = moments(self.n, g=self.box.g, obstacles=self.obstacles, rho0=self.box.rho0)
         delta = self.n - (D3Q19_W * self.box.rho0)[:, None, None, None]
         return dict(n=self.n.copy(), delta=delta, rho=rho, u=u, X=self.X.copy(), V=self.V.copy())

@@ -48,10 +48,13 @@ __device__ __forceinline__ void take_force(const BoxDev* __restrict__ B, int p, 
 }
 
 // BGK collision with Guo forcing at node p (force density f) and push of the
-// 19 post-collision deviations to the neighbours.
+// 19 post-collision deviations to the neighbours; a push into a solid node
+// (bit i of `links`) returns to p in the opposite direction, less
+// 6 w_i rho0 (e_i . u_wall) (bounce-back from a moving obstacle).
 template <int P>
 __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p, typename Prec<P>::R fx,
-                                             typename Prec<P>::R fy, typename Prec<P>::R fz, int parity) {
+                                             typename Prec<P>::R fy, typename Prec<P>::R fz, int parity,
+                                             unsigned links) {
     typedef typename Prec<P>::S S;
     typedef typename Prec<P>::R R;
     const int N = B->N;
@@ -109,7 +112,14 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
             const int off = (cx(i) > 0 ? oxp : (cx(i) < 0 ? oxm : 0)) +
                             (cy(i) > 0 ? oyp : (cy(i) < 0 ? oym : 0)) +
                             (cz(i) > 0 ? ozp : (cz(i) < 0 ? ozm : 0));
-            gstore(dst + (size_t)i * N, (unsigned)(p + off) * (unsigned)sizeof(S), out);
+            if ((links >> i) & 1u) {
+                const double* uw = B->wall_u + 3 * gld(B->btype + p + off);
+                const R euw = R(cx(i)) * (R)gld(uw) + R(cy(i)) * (R)gld(uw + 1) + R(cz(i)) * (R)gld(uw + 2);
+                gstore(dst + (size_t)opp(i) * N, (unsigned)p * (unsigned)sizeof(S),
+                       enc<P>(ds - R(6) * w * (R)B->rho0 * euw, scale));
+            } else {
+                gstore(dst + (size_t)i * N, (unsigned)(p + off) * (unsigned)sizeof(S), out);
+            }
         }
     }
 }
@@ -165,8 +175,15 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
             if (!mine) return;
         }
     }
+    // obstacles: a solid node is not updated (after its lanes' mask word is
+    // handled); a fluid node reads which of its pushes end in a solid node
+    unsigned links = 0u;
+    if (B->btype) {
+        if (gld(B->btype + p)) return;
+        links = gld(B->links + p);
+    }
     if ((m >> (p & 63)) & 1ull) take_force<P>(B, p, fx, fy, fz);
-    collide_push<P>(B, p, fx, fy, fz, parity);
+    collide_push<P>(B, p, fx, fy, fz, parity, links);
 }
 
 template <int P>
@@ -247,6 +264,16 @@ __global__ void moments_kernel(const BoxDev* __restrict__ B, int parity, double*
     const int N = B->N;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
+    if (B->btype && B->btype[p]) {  // obstacle node: rho0 and the wall velocity
+        const double* uw = B->wall_u + 3 * B->btype[p];
+        if (rho) rho[p] = B->rho0;
+        if (u) {
+            u[p] = uw[0];
+            u[N + p] = uw[1];
+            u[2 * N + p] = uw[2];
+        }
+        return;
+    }
     const S* src = (const S*)B->f[parity];
     double d[19];
 #pragma unroll

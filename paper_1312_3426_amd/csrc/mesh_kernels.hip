@@ -331,6 +331,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     const float inv = B->st_inv;
     const R gx_ = (R)B->g[0], gy_ = (R)B->g[1], gz_ = (R)B->g[2];
     const R rho0 = (R)B->rho0, xi = (R)B->xi;
+    const unsigned char* bt = B->btype;  // obstacles (null: none)
     unsigned flags = 0;
     int blo[3] = {INT_MAX, INT_MAX, INT_MAX}, bhi[3] = {INT_MIN, INT_MIN, INT_MIN};
 
@@ -508,6 +509,13 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
             // fluid velocity there: one dense pass, all population loads in flight
             for (int c = threadIdx.x; c < ncomp; c += blockDim.x) {
                 const int q = qn[c];
+                if (bt && gld(bt + q)) {  // obstacle node: the wall velocity
+                    const double* uw = B->wall_u + 3 * gld(bt + q);
+                    ug[3 * c] = (R)gld(uw);
+                    ug[3 * c + 1] = (R)gld(uw + 1);
+                    ug[3 * c + 2] = (R)gld(uw + 2);
+                    continue;
+                }
                 R dd[19];
 #pragma unroll
                 for (int i = 0; i < 19; ++i)
@@ -592,6 +600,14 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                     R dd[19];
                     const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
                     const int qk = ((dz ? iz1 : iz0) * nyb + (dy ? iy1 : iy)) * nxb + (dx ? ix1 : ix);
+                    const R wk = (dx ? phx : R(1) - phx) * (dy ? phy : R(1) - phy) * (dz ? phz : R(1) - phz);
+                    if (bt && gld(bt + qk)) {  // obstacle node: the wall velocity
+                        const double* uw = B->wall_u + 3 * gld(bt + qk);
+                        ujx += wk * (R)gld(uw);
+                        ujy += wk * (R)gld(uw + 1);
+                        ujz += wk * (R)gld(uw + 2);
+                        continue;
+                    }
 #pragma unroll
                     for (int i = 0; i < 19; ++i)
                         dd[i] = dec<P>(gload(pop + (size_t)i * Nb, (unsigned)qk * (unsigned)sizeof(S)), inv);
@@ -602,7 +618,6 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                     const R jy = dd[3] - dd[4] + dd[7] - dd[8] - dd[9] + dd[10] + dd[15] - dd[16] + dd[17] - dd[18];
                     const R jz = dd[5] - dd[6] + dd[11] - dd[12] - dd[13] + dd[14] + dd[15] - dd[16] - dd[17] + dd[18];
                     const R ir = R(1) / (rho0 + dr);
-                    const R wk = (dx ? phx : R(1) - phx) * (dy ? phy : R(1) - phy) * (dz ? phz : R(1) - phz);
                     ujx += wk * ((jx + R(0.5) * gx_) * ir);
                     ujy += wk * ((jy + R(0.5) * gy_) * ir);
                     ujz += wk * ((jz + R(0.5) * gz_) * ir);
@@ -619,6 +634,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                     const typename Acc<P>::T ay = Acc<P>::convert(wk * dgy, B->fp_scale, flags);
                     const typename Acc<P>::T az = Acc<P>::convert(wk * dgz, B->fp_scale, flags);
                     const int qk = ((dz ? iz1 : iz0) * nyb + (dy ? iy1 : iy)) * nxb + (dx ? ix1 : ix);
+                    if (bt && gld(bt + qk)) continue;  // an obstacle takes no share
                     flags |= Acc<P>::flush(B, qk, ax, ay, az);
                 }
             }
@@ -641,8 +657,10 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     if (compact) {
         // one global atomic per touched lattice node and component
         __syncthreads();
-        for (int c = threadIdx.x; c < ncomp; c += blockDim.x)
+        for (int c = threadIdx.x; c < ncomp; c += blockDim.x) {
+            if (bt && gld(bt + qn[c])) continue;  // an obstacle takes no share
             flags |= Acc<P>::flush(B, qn[c], gacc[3 * c], gacc[3 * c + 1], gacc[3 * c + 2]);
+        }
     }
     // split stepping: the stencils of the new positions, for the next step
     if (mark_next)

@@ -35,6 +35,12 @@ struct BoxDev {
     // touch[k] has one bit per node inside some mesh node's 2x2x2 stencil at
     // the start of a step of parity k.
     unsigned long long* touch[2];
+    // Obstacles (null when the box has none): boundary id per node (0 = fluid),
+    // per fluid node the bit set of push directions whose target is solid, and
+    // the wall velocity of each boundary id ([256][3]).
+    const unsigned char* btype;
+    const unsigned* links;
+    const double* wall_u;
     unsigned* status;
     double g[3];
     double rho0;

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <memory>
 #include <sstream>
@@ -246,6 +247,13 @@ struct oif_ctx {
     unsigned long long* mask = nullptr;
     unsigned long long* touch[2] = {nullptr, nullptr};
     unsigned* status = nullptr;
+    // obstacles: host copy of the boundary ids, wall velocities, device arrays
+    std::vector<unsigned char> bt_host;
+    std::vector<double> wall_host;
+    int n_bnd = 0;
+    void* bt_dev = nullptr;
+    void* link_dev = nullptr;
+    void* wall_dev = nullptr;
     hipStream_t side = nullptr;          // lattice update of untouched nodes
     hipEvent_t ev_mark = nullptr, ev_free = nullptr;
     int overlap = 0;
@@ -826,7 +834,7 @@ int oif_destroy(oif_ctx* c) {
     drop_graph(c);
     if (c->side) (void)hipStreamSynchronize(c->side);
     for (void* p : {c->f[0], c->f[1], c->G, (void*)c->mask, (void*)c->touch[0], (void*)c->touch[1],
-                    (void*)c->status, (void*)c->box_dev})
+                    (void*)c->status, (void*)c->box_dev, c->bt_dev, c->link_dev, c->wall_dev})
         if (p) (void)hipFree(p);
     for (auto& b : c->tbufs) b.release();
     for (DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->geo_dev, &c->scratch_dev,
@@ -867,6 +875,135 @@ int oif_template_create(oif_ctx* c, int tid, const double* nodes, int nv, const 
     if (rc) return rc;
     c->tmpl.push_back(std::move(T));
     c->mesh_dirty = true;
+    return OIF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Upload the boundary ids, the per-node bit set of push directions that end
+// in a solid node (the built-in z walls act first), and the wall velocities;
+// then make both population buffers agree at every node, since nothing streams
+// into a solid node and it keeps its values.
+int upload_boundaries(oif_ctx* c) {
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    for (void** p : {&c->bt_dev, &c->link_dev, &c->wall_dev})
+        if (*p) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+    c->box.btype = nullptr;
+    c->box.links = nullptr;
+    c->box.wall_u = nullptr;
+    if (c->n_bnd > 0) {
+        const int nx = c->d.nx, ny = c->d.ny, nz = c->d.nz;
+        const std::vector<unsigned char>& bt = c->bt_host;
+        std::vector<unsigned> links((size_t)c->N, 0u);
+        static const int ex[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+        static const int ey[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+        static const int ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const size_t p = ((size_t)z * ny + y) * nx + x;
+                    if (bt[p]) continue;
+                    unsigned m = 0;
+                    for (int i = 1; i < 19; ++i) {
+                        int zd = z + ez[i];
+                        if (c->d.walls_z && (zd < 0 || zd >= nz)) continue;
+                        zd = (zd + nz) % nz;
+                        const int xd = (x + ex[i] + nx) % nx, yd = (y + ey[i] + ny) % ny;
+                        if (bt[((size_t)zd * ny + yd) * nx + xd]) m |= 1u << i;
+                    }
+                    links[p] = m;
+                }
+        HIPCALL(c, hipMalloc(&c->bt_dev, (size_t)c->N));
+        HIPCALL(c, hipMalloc(&c->link_dev, 4 * (size_t)c->N));
+        HIPCALL(c, hipMalloc(&c->wall_dev, 256 * 3 * sizeof(double)));
+        HIPCALL(c, hipMemcpy(c->bt_dev, bt.data(), (size_t)c->N, hipMemcpyHostToDevice));
+        HIPCALL(c, hipMemcpy(c->link_dev, links.data(), 4 * (size_t)c->N, hipMemcpyHostToDevice));
+        HIPCALL(c, hipMemcpy(c->wall_dev, c->wall_host.data(), 256 * 3 * sizeof(double), hipMemcpyHostToDevice));
+        c->box.btype = (const unsigned char*)c->bt_dev;
+        c->box.links = (const unsigned*)c->link_dev;
+        c->box.wall_u = (const double*)c->wall_dev;
+    }
+    HIPCALL(c, hipMemcpy(c->box_dev, &c->box, sizeof(BoxDev), hipMemcpyHostToDevice));
+    HIPCALL(c, hipMemcpy(c->f[c->parity ^ 1], c->f[c->parity], 19 * (size_t)c->N * c->st_size,
+                         hipMemcpyDeviceToDevice));
+    // launches and batches hold copies of the box descriptor: rebuild them
+    c->mesh_dirty = true;
+    drop_graph(c);
+    return OIF_OK;
+}
+
+int add_boundary(oif_ctx* c, const double* velocity, int* id, const std::function<bool(double, double, double)>& inside) {
+    if (c->n_bnd >= 255) return fail(c, OIF_E_ARG, "at most 255 boundaries");
+    if (velocity)
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(velocity[k])) return fail(c, OIF_E_ARG, "non-finite boundary velocity");
+    if (c->bt_host.empty()) c->bt_host.assign((size_t)c->N, 0);
+    if (c->wall_host.empty()) c->wall_host.assign(256 * 3, 0.0);
+    const int k = ++c->n_bnd;
+    for (int a = 0; a < 3; ++a) c->wall_host[3 * k + a] = velocity ? velocity[a] : 0.0;
+    const int nx = c->d.nx, ny = c->d.ny, nz = c->d.nz;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                if (inside(x + 0.5, y + 0.5, z + 0.5)) c->bt_host[((size_t)z * ny + y) * nx + x] = (unsigned char)k;
+    if (id) *id = k;
+    return upload_boundaries(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+int oif_boundary_rhomboid(oif_ctx* c, const double corner[3], const double a[3], const double b[3],
+                          const double cv[3], const double velocity[3], int* id) {
+    if (!c || !corner || !a || !b || !cv) return OIF_E_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(corner[k]) || !std::isfinite(a[k]) || !std::isfinite(b[k]) || !std::isfinite(cv[k]))
+            return fail(c, OIF_E_ARG, "non-finite rhomboid");
+    double bc[3], ca[3], ab[3];
+    vcross(b, cv, bc);
+    vcross(cv, a, ca);
+    vcross(a, b, ab);
+    const double det = vdot(a, bc);
+    if (!(std::fabs(det) > 0)) return fail(c, OIF_E_ARG, "degenerate rhomboid");
+    const double o[3] = {corner[0], corner[1], corner[2]};
+    const double BC[3] = {bc[0], bc[1], bc[2]}, CA[3] = {ca[0], ca[1], ca[2]}, AB[3] = {ab[0], ab[1], ab[2]};
+    // the node's coordinates (s, t, u) along a, b, c by Cramer's rule
+    return add_boundary(c, velocity, id, [&](double x, double y, double z) {
+        const double r[3] = {x - o[0], y - o[1], z - o[2]};
+        const double s = vdot(r, BC) / det, t = vdot(r, CA) / det, u = vdot(r, AB) / det;
+        return s >= 0.0 && s <= 1.0 && t >= 0.0 && t <= 1.0 && u >= 0.0 && u <= 1.0;
+    });
+}
+
+int oif_boundary_wall(oif_ctx* c, const double normal[3], double dist, const double velocity[3], int* id) {
+    if (!c || !normal) return OIF_E_ARG;
+    const double len = std::sqrt(vdot(normal, normal));
+    if (!std::isfinite(dist) || !std::isfinite(len) || !(len > 0)) return fail(c, OIF_E_ARG, "bad wall");
+    const double n[3] = {normal[0], normal[1], normal[2]};
+    return add_boundary(c, velocity, id, [&](double x, double y, double z) {
+        const double r[3] = {x, y, z};
+        return vdot(r, n) / len - dist < 0.0;
+    });
+}
+
+int oif_boundary_clear(oif_ctx* c) {
+    if (!c) return OIF_E_ARG;
+    c->n_bnd = 0;
+    c->bt_host.clear();
+    c->wall_host.clear();
+    return upload_boundaries(c);
+}
+
+int oif_read_boundary(oif_ctx* c, uint8_t* out) {
+    if (!c || !out) return OIF_E_ARG;
+    if (c->bt_host.empty()) std::memset(out, 0, (size_t)c->N);
+    else std::memcpy(out, c->bt_host.data(), (size_t)c->N);
     return OIF_OK;
 }
 
@@ -1098,6 +1235,8 @@ int oif_write_populations(oif_ctx* c, const double* in) {
     HIPCALL(c, hipMalloc(&tmp, n * 8));
     hipError_t e = hipMemcpyAsync(tmp, in, n * 8, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_f64_to_pops(c->box_dev, c->N, c->d.precision, c->parity, tmp, c->stream);
+    // both buffers: nothing streams into a solid node, which keeps its values
+    if (e == hipSuccess) e = launch_f64_to_pops(c->box_dev, c->N, c->d.precision, c->parity ^ 1, tmp, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(tmp);
     HIPCALL(c, e);

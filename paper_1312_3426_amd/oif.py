@@ -102,6 +102,10 @@ SIGNATURES = {
     "oif_info": (_i, [_vp, _vp]),
     "oif_diagnostics": (_i, [_vp, _vp]),
     "oif_touched_nodes": (_i, [_vp, _vp]),
+    "oif_boundary_rhomboid": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "oif_boundary_wall": (_i, [_vp, _vp, C.c_double, _vp, _vp]),
+    "oif_boundary_clear": (_i, [_vp]),
+    "oif_read_boundary": (_i, [_vp, _vp]),
     "oif_copy_bandwidth": (_i, [_i, _ll, _i, _vp]),
     "oif_batch_create": (_i, [_vp, _i, _vp]),
     "oif_batch_destroy": (_i, [_vp]),
@@ -309,12 +313,39 @@ class Context:
         self._chk(lib().oif_touched_nodes(self.h, C.byref(v)))
         return v.value
 
+    # -- obstacles --
+    def boundary_rhomboid(self, corner, a, b, c, velocity=None) -> int:
+        bid = C.c_int()
+        v = None if velocity is None else _p(_f64(velocity))
+        self._chk(lib().oif_boundary_rhomboid(self.h, _p(_f64(corner)), _p(_f64(a)), _p(_f64(b)),
+                                              _p(_f64(c)), v, C.byref(bid)))
+        return bid.value
+
+    def boundary_wall(self, normal, dist, velocity=None) -> int:
+        bid = C.c_int()
+        v = None if velocity is None else _p(_f64(velocity))
+        self._chk(lib().oif_boundary_wall(self.h, _p(_f64(normal)), float(dist), v, C.byref(bid)))
+        return bid.value
+
+    def boundary_clear(self):
+        self._chk(lib().oif_boundary_clear(self.h))
+
+    def read_boundary(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.uint8)
+        self._chk(lib().oif_read_boundary(self.h, out.ctypes.data))
+        return out
+
     # -- convenience: build from a workload description --
     @classmethod
     def from_box(cls, box, precision="fp32", **kw) -> "Context":
         """Create a context from a ``synth.Box``-like description (duck-typed)."""
         c = cls(box.nx, box.ny, box.nz, tau=box.tau, rho0=box.rho0, body_force=box.g,
                 friction=box.friction, walls_z=box.walls_z, precision=precision, **kw)
+        for bnd in getattr(box, "boundaries", []) or []:
+            if bnd.kind == "rhomboid":
+                c.boundary_rhomboid(bnd.corner, bnd.a, bnd.b, bnd.c, bnd.velocity)
+            else:
+                c.boundary_wall(bnd.normal, bnd.dist, bnd.velocity)
         for tid, t in enumerate(box.templates):
             c.template_create(tid, t.nodes, t.tris, stretch=t.stretch, ks=t.ks, kb=t.kb, kal=t.kal,
                               kag=t.kag, kv=t.kv, linear=t.linear, model=getattr(t, "model", "paper"))

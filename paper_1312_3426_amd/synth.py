@@ -326,6 +326,67 @@ def config_channel_rbc(steps: int = 1000, seed: int = 2, n_cells: int = 10) -> B
                name="rbc393x10_64x32x32_walls")
 
 
+def obstacle_channel_boundaries(nx: int = 96, ny: int = 48, inlet: float = 0.01) -> List[Boundary]:
+    """S-shaped channel from obstacles: side walls at y < 2 and y > ny - 2, a
+    baffle from the low side (x in [0.31, 0.375] nx, y < 2/3 ny) and one from the
+    high side (x in [0.625, 0.69] nx, y > ny/3), and a velocity inlet: a slab
+    at x < 2 moving along +x with `inlet` (periodic in x, so the slab's far
+    face is the outlet)."""
+    fx = lambda f: round(f * nx)  # noqa: E731
+    return [
+        Boundary("wall", normal=(0, 1, 0), dist=2.0),
+        Boundary("wall", normal=(0, -1, 0), dist=-(ny - 2.0)),
+        Boundary("rhomboid", corner=(fx(0.3125), 0, 0), a=(fx(0.0625), 0, 0), b=(0, round(2 * ny / 3), 0),
+                 c=(0, 0, 1e4)),
+        Boundary("rhomboid", corner=(fx(0.625), round(ny / 3), 0), a=(fx(0.0625), 0, 0),
+                 b=(0, ny - round(ny / 3), 0), c=(0, 0, 1e4)),
+        Boundary("rhomboid", corner=(0, 0, 0), a=(2, 0, 0), b=(0, ny, 0), c=(0, 0, 1e4),
+                 velocity=(inlet, 0.0, 0.0)),
+    ]
+
+
+def config_obstacle_channel(steps: int = 200, seed: int = 6, n_cells: int = 10, nx: int = 96, ny: int = 48,
+                            nz: int = 16) -> Box:
+    """Obstacle case (stand-in for the paper's S-channel script): the channel
+    of ``obstacle_channel_boundaries`` with bounce-back walls at z = 0 and
+    z = nz, no body force (the inlet drives the flow), ten 393-node cells
+    (diameter 8) at random rotations, centres at least 5.5 from every solid
+    node and 5 from the z walls, pairwise distance >= 9."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    bnd = obstacle_channel_boundaries(nx, ny)
+    # solid nodes of the shapes (a plain membership test, independent of both
+    # the oracle and the library, used only to keep the cells clear)
+    cx, cy = np.meshgrid(np.arange(nx) + 0.5, np.arange(ny) + 0.5, indexing="xy")
+    solid2d = (cy < 2.0) | (cy > ny - 2.0) | (cx < 2.0)
+    for b in bnd[2:4]:
+        x0, y0 = b.corner[0], b.corner[1]
+        solid2d |= (cx >= x0) & (cx <= x0 + b.a[0]) & (cy >= y0) & (cy <= y0 + b.b[1])
+    sy, sx = np.nonzero(solid2d)
+    pts = np.stack([sx + 0.5, sy + 0.5], axis=1)
+    n, t = rbc_393(4.0)
+    tm = Template(n, t, **MODULI_DEFAULT)
+    cs = np.empty((0, 3))
+    tries = 0
+    while len(cs) < n_cells:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("could not place the cells")
+        c = np.array([nx, ny, nz - 10.0]) * rng.random(3) + [0.0, 0.0, 5.0]
+        dxy = pts - c[:2]
+        dxy[:, 0] -= nx * np.round(dxy[:, 0] / nx)
+        if np.min(np.einsum("ij,ij->i", dxy, dxy)) < 5.5 ** 2:
+            continue
+        if len(cs):
+            d = cs - c
+            d[:, 0] -= nx * np.round(d[:, 0] / nx)
+            if np.min(np.einsum("ij,ij->i", d, d)) < 81.0:
+                continue
+        cs = np.vstack([cs, c])
+    objs = [ObjectSpec(0, c, random_rotation(rng)) for c in cs]
+    return Box(nx, ny, nz, g=(0.0, 0.0, 0.0), walls_z=True, templates=[tm], objects=objs, steps=steps,
+               name=f"rbc393x{n_cells}_schannel_{nx}x{ny}x{nz}", boundaries=bnd)
+
+
 def config_precision(steps: int = 500, seed: int = 3, nx: int = 256, ny: int = 128, nz: int = 128,
                      n_cells: int = 500) -> Box:
     """Precision-form case: 256x128x128 periodic, 500 level-3 icospheres of
