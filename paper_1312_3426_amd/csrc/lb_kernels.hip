@@ -65,6 +65,9 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
     R d[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) d[i] = dec<P>(gload(src + (size_t)i * N, (unsigned)p * (unsigned)sizeof(S)), inv);
+    // an obstacle node is not updated (its link word was loaded beside the
+    // populations, so the test costs no extra round trip)
+    if (links & 1u) return;
 
     R drho = 0;
 #pragma unroll
@@ -88,6 +91,14 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
     const int y = t % ny;
     const int z = t / ny;
     const int plane = nx * ny;
+    // wall velocity of the one moving boundary next to this node (if any)
+    R wx = R(0), wy = R(0), wz = R(0);
+    const unsigned mid = (links >> 23) & 255u;
+    if (mid) {
+        wx = (R)gld(B->wall_u + 3 * mid);
+        wy = (R)gld(B->wall_u + 3 * mid + 1);
+        wz = (R)gld(B->wall_u + 3 * mid + 2);
+    }
     const int oxm = x ? -1 : nx - 1, oxp = (x < nx - 1) ? 1 : -(nx - 1);
     const int oym = y ? -nx : (ny - 1) * nx, oyp = (y < ny - 1) ? nx : -(ny - 1) * nx;
     const int ozm = z ? -plane : (nz - 1) * plane, ozp = (z < nz - 1) ? plane : -(nz - 1) * plane;
@@ -112,14 +123,21 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
             const int off = (cx(i) > 0 ? oxp : (cx(i) < 0 ? oxm : 0)) +
                             (cy(i) > 0 ? oyp : (cy(i) < 0 ? oym : 0)) +
                             (cz(i) > 0 ? ozp : (cz(i) < 0 ? ozm : 0));
-            if ((links >> i) & 1u) {
-                const double* uw = B->wall_u + 3 * gld(B->btype + p + off);
-                const R euw = R(cx(i)) * (R)gld(uw) + R(cy(i)) * (R)gld(uw + 1) + R(cz(i)) * (R)gld(uw + 2);
-                gstore(dst + (size_t)opp(i) * N, (unsigned)p * (unsigned)sizeof(S),
-                       enc<P>(ds - R(6) * w * (R)B->rho0 * euw, scale));
-            } else {
-                gstore(dst + (size_t)i * N, (unsigned)(p + off) * (unsigned)sizeof(S), out);
+            // one store per direction for the whole wave: a push that ends in a
+            // solid node goes back to p in the opposite direction instead
+            const bool bb = (links >> i) & 1u;
+            S val = out;
+            if (bb && (links >> 23)) {  // a moving neighbour: its wall term
+                R euw;
+                if (links >> 31) {  // neighbours of several boundaries: this one's
+                    const double* uw = B->wall_u + 3 * gld(B->btype + p + off);
+                    euw = R(cx(i)) * (R)gld(uw) + R(cy(i)) * (R)gld(uw + 1) + R(cz(i)) * (R)gld(uw + 2);
+                } else {
+                    euw = R(cx(i)) * wx + R(cy(i)) * wy + R(cz(i)) * wz;
+                }
+                val = enc<P>(ds - R(6) * w * (R)B->rho0 * euw, scale);
             }
+            gst(dst + (bb ? (size_t)opp(i) * N + p : (size_t)i * N + (p + off)), val);
         }
     }
 }
@@ -175,13 +193,9 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
             if (!mine) return;
         }
     }
-    // obstacles: a solid node is not updated (after its lanes' mask word is
-    // handled); a fluid node reads which of its pushes end in a solid node
-    unsigned links = 0u;
-    if (B->btype) {
-        if (gld(B->btype + p)) return;
-        links = gld(B->links + p);
-    }
+    // obstacles: which of the node's pushes end in a solid node (and whether
+    // the node itself is solid, tested once its populations are loaded)
+    const unsigned links = B->links ? gld(B->links + p) : 0u;
     if ((m >> (p & 63)) & 1ull) take_force<P>(B, p, fx, fy, fz);
     collide_push<P>(B, p, fx, fy, fz, parity, links);
 }

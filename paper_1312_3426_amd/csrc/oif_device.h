@@ -35,9 +35,12 @@ struct BoxDev {
     // touch[k] has one bit per node inside some mesh node's 2x2x2 stencil at
     // the start of a step of parity k.
     unsigned long long* touch[2];
-    // Obstacles (null when the box has none): boundary id per node (0 = fluid),
-    // per fluid node the bit set of push directions whose target is solid, and
-    // the wall velocity of each boundary id ([256][3]).
+    // Obstacles (null when the box has none): boundary id per node (0 = fluid);
+    // per node a link word: bit 0 = the node is solid, bit i (1..18) = the push
+    // in direction i ends in a solid node, bits 23..30 = the id of the moving
+    // boundary when all of the node's solid neighbours belong to it, bit 31 =
+    // solid neighbours of several boundaries, one of them moving (look each
+    // up); the wall velocity of each boundary id ([256][3]).
     const unsigned char* btype;
     const unsigned* links;
     const double* wall_u;

@@ -907,15 +907,27 @@ int upload_boundaries(oif_ctx* c) {
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
                     const size_t p = ((size_t)z * ny + y) * nx + x;
-                    if (bt[p]) continue;
+                    if (bt[p]) {
+                        links[p] = 1u;  // solid
+                        continue;
+                    }
                     unsigned m = 0;
+                    int first = 0;
+                    bool several = false, moving = false;
                     for (int i = 1; i < 19; ++i) {
                         int zd = z + ez[i];
                         if (c->d.walls_z && (zd < 0 || zd >= nz)) continue;
                         zd = (zd + nz) % nz;
                         const int xd = (x + ex[i] + nx) % nx, yd = (y + ey[i] + ny) % ny;
-                        if (bt[((size_t)zd * ny + yd) * nx + xd]) m |= 1u << i;
+                        const unsigned char b = bt[((size_t)zd * ny + yd) * nx + xd];
+                        if (!b) continue;
+                        m |= 1u << i;
+                        if (!first) first = b;
+                        several = several || b != first;
+                        const double* u = &c->wall_host[3 * b];
+                        moving = moving || u[0] != 0.0 || u[1] != 0.0 || u[2] != 0.0;
                     }
+                    if (moving) m |= several ? 1u << 31 : (unsigned)first << 23;
                     links[p] = m;
                 }
         HIPCALL(c, hipMalloc(&c->bt_dev, (size_t)c->N));
