@@ -48,10 +48,10 @@ __device__ __forceinline__ void take_force(const BoxDev* __restrict__ B, int p, 
 }
 
 // BGK collision with Guo forcing at node p (force density f) and push of the
-// 19 post-collision deviations to the neighbours; a push into a solid node
-// (bit i of `links`) returns to p in the opposite direction, less
-// 6 w_i rho0 (e_i . u_wall) (bounce-back from a moving obstacle).
-template <int P>
+// 19 post-collision deviations to the neighbours; with obstacles (OBST), a push
+// into a solid node (bit i of `links`) returns to p in the opposite direction,
+// less 6 w_i rho0 (e_i . u_wall) (bounce-back from a moving obstacle).
+template <int P, bool OBST>
 __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p, typename Prec<P>::R fx,
                                              typename Prec<P>::R fy, typename Prec<P>::R fz, int parity,
                                              unsigned links) {
@@ -67,7 +67,7 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
     for (int i = 0; i < 19; ++i) d[i] = dec<P>(gload(src + (size_t)i * N, (unsigned)p * (unsigned)sizeof(S)), inv);
     // an obstacle node is not updated (its link word was loaded beside the
     // populations, so the test costs no extra round trip)
-    if (links & 1u) return;
+    if (OBST && (links & 1u)) return;
 
     R drho = 0;
 #pragma unroll
@@ -93,7 +93,7 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
     const int plane = nx * ny;
     // wall velocity of the one moving boundary next to this node (if any)
     R wx = R(0), wy = R(0), wz = R(0);
-    const unsigned mid = (links >> 23) & 255u;
+    const unsigned mid = OBST ? (links >> 23) & 255u : 0u;
     if (mid) {
         wx = (R)gld(B->wall_u + 3 * mid);
         wy = (R)gld(B->wall_u + 3 * mid + 1);
@@ -123,26 +123,30 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
             const int off = (cx(i) > 0 ? oxp : (cx(i) < 0 ? oxm : 0)) +
                             (cy(i) > 0 ? oyp : (cy(i) < 0 ? oym : 0)) +
                             (cz(i) > 0 ? ozp : (cz(i) < 0 ? ozm : 0));
-            // one store per direction for the whole wave: a push that ends in a
-            // solid node goes back to p in the opposite direction instead
-            const bool bb = (links >> i) & 1u;
-            S val = out;
-            if (bb && (links >> 23)) {  // a moving neighbour: its wall term
-                R euw;
-                if (links >> 31) {  // neighbours of several boundaries: this one's
-                    const double* uw = B->wall_u + 3 * gld(B->btype + p + off);
-                    euw = R(cx(i)) * (R)gld(uw) + R(cy(i)) * (R)gld(uw + 1) + R(cz(i)) * (R)gld(uw + 2);
-                } else {
-                    euw = R(cx(i)) * wx + R(cy(i)) * wy + R(cz(i)) * wz;
+            if (OBST && ((links >> i) & 1u)) {
+                // the push ends in a solid node: back to p in the opposite
+                // direction, with the wall term of a moving neighbour
+                S val = out;
+                if (links >> 23) {
+                    R euw;
+                    if (links >> 31) {  // neighbours of several boundaries: this one's
+                        const double* uw = B->wall_u + 3 * gld(B->btype + p + off);
+                        euw = R(cx(i)) * (R)gld(uw) + R(cy(i)) * (R)gld(uw + 1) + R(cz(i)) * (R)gld(uw + 2);
+                    } else {
+                        euw = R(cx(i)) * wx + R(cy(i)) * wy + R(cz(i)) * wz;
+                    }
+                    val = enc<P>(ds - R(6) * w * (R)B->rho0 * euw, scale);
                 }
-                val = enc<P>(ds - R(6) * w * (R)B->rho0 * euw, scale);
+                gstore(dst + (size_t)opp(i) * N, (unsigned)p * (unsigned)sizeof(S), val);
+            } else {
+                gstore(dst + (size_t)i * N, (unsigned)(p + off) * (unsigned)sizeof(S), out);
             }
-            gst(dst + (bb ? (size_t)opp(i) * N + p : (size_t)i * N + (p + off)), val);
         }
     }
 }
 
-template <int P>
+// OBST: some box of the launch has obstacles; without it that code is left out.
+template <int P, bool OBST>
 __global__ void __launch_bounds__(1024)
 lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int nblocks, int parity,
           int remap, int mode) {
@@ -195,9 +199,9 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
     }
     // obstacles: which of the node's pushes end in a solid node (and whether
     // the node itself is solid, tested once its populations are loaded)
-    const unsigned links = B->links ? gld(B->links + p) : 0u;
+    const unsigned links = (OBST && B->links) ? gld(B->links + p) : 0u;
     if ((m >> (p & 63)) & 1ull) take_force<P>(B, p, fx, fy, fz);
-    collide_push<P>(B, p, fx, fy, fz, parity, links);
+    collide_push<P, OBST>(B, p, fx, fy, fz, parity, links);
 }
 
 template <int P>
@@ -334,9 +338,24 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
         default: return hipErrorInvalidValue;                                                    \
     }
 
+template <int P>
+void launch_lb_p(const LbLaunch& L) {
+    if (L.obstacles)
+        hipLaunchKernelGGL((lb_kernel<P, true>), dim3(L.nblocks), dim3(L.block), 0, L.stream, L.boxes, L.work,
+                           L.nblocks, L.parity, L.remap, L.mode);
+    else
+        hipLaunchKernelGGL((lb_kernel<P, false>), dim3(L.nblocks), dim3(L.block), 0, L.stream, L.boxes, L.work,
+                           L.nblocks, L.parity, L.remap, L.mode);
+}
+
 hipError_t launch_lb(const LbLaunch& L) {
-    OIF_DISPATCH_P(L.precision, lb_kernel, dim3(L.nblocks), dim3(L.block), L.stream, L.boxes, L.work,
-                   L.nblocks, L.parity, L.remap, L.mode);
+    switch (L.precision) {
+        case PREC_FP64: launch_lb_p<PREC_FP64>(L); break;
+        case PREC_FP32: launch_lb_p<PREC_FP32>(L); break;
+        case PREC_FP16: launch_lb_p<PREC_FP16>(L); break;
+        case PREC_BF16: launch_lb_p<PREC_BF16>(L); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -154,6 +154,7 @@ struct LbLaunch {
     int precision;
     hipStream_t stream;
     int mode;              // LB_ALL, LB_FREE or LB_TOUCHED
+    int obstacles;         // some box of the launch has obstacles
 };
 hipError_t launch_lb(const LbLaunch& L);
 

@@ -298,6 +298,7 @@ struct oif_batch {
     DevBuf boxes_dev, work_dev, obj_dev;
     std::vector<unsigned char> obj_host;
     int nblocks = 0, nobj = 0, n_lds_obj = 0;
+    int nblocks_plain = 0;  // the work list holds boxes without obstacles first
     size_t lds_need = 0;
     int any_conservative = 0;
     int lb_block = 256, mesh_block = 256, remap = 1;
@@ -582,6 +583,7 @@ int enqueue_lb(oif_ctx* c, int par, hipStream_t s, int mode) {
     ll.precision = c->d.precision;
     ll.stream = s;
     ll.mode = mode;
+    ll.obstacles = c->n_bnd > 0;
     HIPCALL(c, launch_lb(ll));
     return OIF_OK;
 }
@@ -1592,12 +1594,19 @@ int batch_build(oif_batch* b) {
     }
     bdrop_graph(b);
     // boxes and lattice work list
+    // boxes without obstacles take one lattice launch and boxes with them
+    // another, so that every box runs the kernel it runs on its own (and the
+    // batched result equals the box-by-box one bit for bit)
     std::vector<BoxDev> boxes;
     std::vector<int2> work;
-    for (size_t i = 0; i < b->ctx.size(); ++i) {
-        boxes.push_back(b->ctx[i]->box);
-        const int nb = (b->ctx[i]->N + b->lb_block - 1) / b->lb_block;
-        for (int k = 0; k < nb; ++k) work.push_back(make_int2((int)i, k));
+    for (size_t i = 0; i < b->ctx.size(); ++i) boxes.push_back(b->ctx[i]->box);
+    for (int obst = 0; obst < 2; ++obst) {
+        for (size_t i = 0; i < b->ctx.size(); ++i) {
+            if ((b->ctx[i]->n_bnd > 0) != (obst == 1)) continue;
+            const int nb = (b->ctx[i]->N + b->lb_block - 1) / b->lb_block;
+            for (int k = 0; k < nb; ++k) work.push_back(make_int2((int)i, k));
+        }
+        if (obst == 0) b->nblocks_plain = (int)work.size();
     }
     b->nblocks = (int)work.size();
     b->boxes_dev.release();
@@ -1674,9 +1683,13 @@ int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<h
             BHIP(b, launch_mesh(ml));
         }
         if (ev) (void)hipEventRecord((*ev)[3 * k + 1], s);
-        LbLaunch ll{(const BoxDev*)b->boxes_dev.p, (const int2*)b->work_dev.p, b->nblocks, b->lb_block, par,
-                    b->remap, b->precision, s};
-        BHIP(b, launch_lb(ll));
+        LbLaunch ll{(const BoxDev*)b->boxes_dev.p, (const int2*)b->work_dev.p, b->nblocks_plain, b->lb_block, par,
+                    b->remap, b->precision, s, LB_ALL, 0};
+        if (ll.nblocks > 0) BHIP(b, launch_lb(ll));
+        ll.work += b->nblocks_plain;
+        ll.nblocks = b->nblocks - b->nblocks_plain;
+        ll.obstacles = 1;
+        if (ll.nblocks > 0) BHIP(b, launch_lb(ll));
         if (ev) (void)hipEventRecord((*ev)[3 * k + 2], s);
         par ^= 1;
     }
