@@ -272,11 +272,12 @@ int oif_step_timed(oif_ctx* ctx, int n_steps, oif_timing* t);
  * even number) in one hipGraph and replays it; 0 launches eagerly. */
 int oif_set_graph(oif_ctx* ctx, int steps_per_graph);
 
-/* Overlap (default on): each step first marks the lattice nodes inside any
- * mesh node's 2x2x2 stencil; the lattice update of all other nodes (which no
- * coupling force can reach) then runs on a second stream concurrently with the
- * membrane/coupling kernel, and the marked nodes are updated after it.  The
- * result is identical to the sequential order; 0 runs the step sequentially. */
+/* Overlap (default off): the lattice nodes inside any mesh node's 2x2x2
+ * stencil are marked (by the membrane kernel of the previous step); the lattice
+ * update of all other nodes (which no coupling force can reach) then runs on a
+ * second stream concurrently with the membrane/coupling kernel, and the marked
+ * nodes are updated after it.  The result is identical to the sequential
+ * order; 0 runs the step sequentially. */
 int oif_set_overlap(oif_ctx* ctx, int on);
 
 /* Launch shapes: lb_block in {64,128,256,512,1024}, mesh_block a multiple of
@@ -285,6 +286,7 @@ int oif_set_overlap(oif_ctx* ctx, int on);
  * consecutive lattice blocks to the same XCD.  Values < 0 keep the current
  * setting. */
 int oif_set_launch(oif_ctx* ctx, int lb_block, int mesh_block, int xcd_remap);
+
 
 /* Measured search of the launch shapes on this context's workload; the
  * choice is applied and, if cache_path is not NULL, stored there as JSON

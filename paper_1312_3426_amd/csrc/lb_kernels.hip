@@ -47,28 +47,41 @@ __device__ __forceinline__ void take_force(const BoxDev* __restrict__ B, int p, 
     }
 }
 
-// BGK collision with Guo forcing at node p (force density f) and push of the
-// 19 post-collision deviations to the neighbours; with obstacles (OBST), a push
-// into a solid node (bit i of `links`) returns to p in the opposite direction,
-// less 6 w_i rho0 (e_i . u_wall) (bounce-back from a moving obstacle).
-template <int P, bool OBST>
-__device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p, typename Prec<P>::R fx,
-                                             typename Prec<P>::R fy, typename Prec<P>::R fz, int parity,
-                                             unsigned links) {
-    typedef typename Prec<P>::S S;
-    typedef typename Prec<P>::R R;
-    const int N = B->N;
-    const S* __restrict__ src = (const S*)B->f[parity];
-    S* __restrict__ dst = (S*)B->f[parity ^ 1];
-    const float inv = B->st_inv, scale = B->st_scale;
+// a * b + c with one rounding
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-    R d[19];
-#pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = dec<P>(gload(src + (size_t)i * N, (unsigned)p * (unsigned)sizeof(S)), inv);
-    // an obstacle node is not updated (its link word was loaded beside the
-    // populations, so the test costs no extra round trip)
-    if (OBST && (links & 1u)) return;
+// e_i . a over the non-zero components of e_i only (i is a compile-time
+// constant once the loops are unrolled)
+template <typename R>
+__device__ __forceinline__ R edot(int i, R ax, R ay, R az) {
+    R s = R(0);
+    bool any = false;
+    if (cx(i)) {
+        s = cx(i) > 0 ? ax : -ax;
+        any = true;
+    }
+    if (cy(i)) {
+        s = any ? (cy(i) > 0 ? s + ay : s - ay) : (cy(i) > 0 ? ay : -ay);
+        any = true;
+    }
+    if (cz(i)) s = any ? (cz(i) > 0 ? s + az : s - az) : (cz(i) > 0 ? az : -az);
+    return s;
+}
 
+// BGK collision with Guo forcing of one node's 19 deviations, in place:
+// d_i <- (1 - omega) d_i + omega deq_i + S_i with the force density f
+// (eq. lbequation with the external force term; density and velocity are the
+// moments of the node's populations, the velocity shifted by half the force).
+//   deq_i = w_i [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u^2)]
+//   S_i   = (1 - 1/(2 tau)) w_i [3 (e_i - u) + 9 (e_i . u) e_i] . F
+// Opposite directions share the parts even in e_i and negate the odd ones, so
+// they are formed once per pair.  Every operation is rounded as written (no
+// contraction into fused multiply-adds beyond the explicit ones), so that all
+// lattice kernels that inline this function give the same bits node by node.
+template <typename R>
+__device__ __forceinline__ void collide(const BoxDev* __restrict__ B, R (&d)[19], R fx, R fy, R fz) {
+#pragma clang fp contract(off)
     R drho = 0;
 #pragma unroll
     for (int i = 0; i < 19; ++i) drho += d[i];
@@ -81,8 +94,61 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
     const R uy = (jy + R(0.5) * fy) * ir;
     const R uz = (jz + R(0.5) * fz) * ir;
     const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
-    const R uF = ux * fx + uy * fy + uz * fz;
+    const R uF3 = R(3) * (ux * fx + uy * fy + uz * fz);
     const R om = (R)B->omega, gu = (R)B->guo;
+    const R keep = R(1) - om;
+    {  // rest population: e = 0
+        const R w = wt<R>(0);
+        const R deq = w * fmadd(-rho, usq, drho);
+        const R src = -(gu * w) * uF3;
+        d[0] = fmadd(keep, d[0], fmadd(om, deq, src));
+    }
+#pragma unroll
+    for (int i = 1; i < 19; i += 2) {  // i and its opposite i + 1, e_{i+1} = -e_i
+        const R w = wt<R>(i);
+        const R eu = edot<R>(i, ux, uy, uz), eF = edot<R>(i, fx, fy, fz);
+        const R even = w * fmadd(rho, fmadd(R(4.5) * eu, eu, -usq), drho);
+        const R odd = (R(3) * w) * (rho * eu);
+        const R gw = gu * w;
+        const R seven = gw * fmadd(R(9) * eu, eF, -uF3);
+        const R sodd = (R(3) * gw) * eF;
+        d[i] = fmadd(keep, d[i], fmadd(om, even + odd, seven + sodd));
+        d[i + 1] = fmadd(keep, d[i + 1], fmadd(om, even - odd, seven - sodd));
+    }
+}
+
+// Collision at node p (force density f) and push of the 19 post-collision
+// deviations to the neighbours (halfway bounce-back at z walls); with
+// obstacles (OBST), a push into a solid node (bit i of `links`) returns to p in
+// the opposite direction, less 6 w_i rho0 (e_i . u_wall) (bounce-back from a
+// moving obstacle).
+template <int P>
+__device__ __forceinline__ void load_pops(const BoxDev* __restrict__ B, int p, int parity,
+                                          typename Prec<P>::S (&raw)[19]) {
+    typedef typename Prec<P>::S S;
+    const S* __restrict__ src = (const S*)B->f[parity];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) raw[i] = gload(src + (size_t)i * B->N, (unsigned)p * (unsigned)sizeof(S));
+}
+
+template <int P, bool OBST>
+__device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p,
+                                             const typename Prec<P>::S (&raw)[19], typename Prec<P>::R fx,
+                                             typename Prec<P>::R fy, typename Prec<P>::R fz, int parity,
+                                             unsigned links) {
+    typedef typename Prec<P>::S S;
+    typedef typename Prec<P>::R R;
+    const int N = B->N;
+    S* __restrict__ dst = (S*)B->f[parity ^ 1];
+    const float inv = B->st_inv, scale = B->st_scale;
+
+    // an obstacle node is not updated (its link word was loaded beside the
+    // populations, so the test costs no extra round trip)
+    if (OBST && (links & 1u)) return;
+    R d[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) d[i] = dec<P>(raw[i], inv);
+    collide<R>(B, d, fx, fy, fz);
 
     // neighbour offsets with periodic wrap
     const int nx = B->nx, ny = B->ny, nz = B->nz;
@@ -107,14 +173,7 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
 
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-        // deviations: n_i^eq - w_i rho0 = w_i [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u^2)]
-        const R eu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
-        const R eF = R(cx(i)) * fx + R(cy(i)) * fy + R(cz(i)) * fz;
-        const R w = wt<R>(i);
-        const R deq = w * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - usq));
-        // Guo source (1 - 1/(2 tau)) w_i [3 (e_i - u) + 9 (e_i . u) e_i] . F
-        const R srcf = gu * w * (R(3) * (eF - uF) + R(9) * eu * eF);
-        const R ds = d[i] - om * (d[i] - deq) + srcf;
+        const R ds = d[i];
         const S out = enc<P>(ds, scale);
         const bool bounce = (cz(i) > 0 && whi) || (cz(i) < 0 && wlo);
         if (bounce) {
@@ -135,7 +194,7 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
                     } else {
                         euw = R(cx(i)) * wx + R(cy(i)) * wy + R(cz(i)) * wz;
                     }
-                    val = enc<P>(ds - R(6) * w * (R)B->rho0 * euw, scale);
+                    val = enc<P>(ds - R(6) * wt<R>(i) * (R)B->rho0 * euw, scale);
                 }
                 gstore(dst + (size_t)opp(i) * N, (unsigned)p * (unsigned)sizeof(S), val);
             } else {
@@ -146,10 +205,14 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
 }
 
 // OBST: some box of the launch has obstacles; without it that code is left out.
-template <int P, bool OBST>
+// ALL: mode is LB_ALL (every node is updated, so the population loads go out
+// first and are in flight while the mask word and any coupling force are
+// fetched).
+template <int P, bool OBST, bool ALL>
 __global__ void __launch_bounds__(1024)
 lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int nblocks, int parity,
           int remap, int mode) {
+    typedef typename Prec<P>::S S;
     typedef typename Prec<P>::R R;
     int bid = blockIdx.x;
     if (remap) {
@@ -168,6 +231,8 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
     const int N = B->N;
     const int p = blk * (int)blockDim.x + (int)threadIdx.x;
     if (p >= N) return;
+    S raw[19];
+    if (ALL) load_pops<P>(B, p, parity, raw);
 
     // Force density: body force plus the coupling force G where the node's mask
     // bit is set.  Mask and touch words cover exactly one wave's 64 nodes; all
@@ -175,7 +240,7 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
     R fx = (R)B->g[0], fy = (R)B->g[1], fz = (R)B->g[2];
     unsigned long long* mk = B->mask + (p >> 6);
     unsigned long long m = 0ull;
-    if (mode == LB_ALL) {
+    if (ALL) {
         m = gld(mk);
         if (m && (p & 63) == 0) gst(mk, 0ull);
     } else {
@@ -200,8 +265,9 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
     // obstacles: which of the node's pushes end in a solid node (and whether
     // the node itself is solid, tested once its populations are loaded)
     const unsigned links = (OBST && B->links) ? gld(B->links + p) : 0u;
+    if (!ALL) load_pops<P>(B, p, parity, raw);
     if ((m >> (p & 63)) & 1ull) take_force<P>(B, p, fx, fy, fz);
-    collide_push<P, OBST>(B, p, fx, fy, fz, parity, links);
+    collide_push<P, OBST>(B, p, raw, fx, fy, fz, parity, links);
 }
 
 template <int P>
@@ -340,12 +406,18 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
 
 template <int P>
 void launch_lb_p(const LbLaunch& L) {
-    if (L.obstacles)
-        hipLaunchKernelGGL((lb_kernel<P, true>), dim3(L.nblocks), dim3(L.block), 0, L.stream, L.boxes, L.work,
-                           L.nblocks, L.parity, L.remap, L.mode);
-    else
-        hipLaunchKernelGGL((lb_kernel<P, false>), dim3(L.nblocks), dim3(L.block), 0, L.stream, L.boxes, L.work,
-                           L.nblocks, L.parity, L.remap, L.mode);
+#define OIF_LB(O, A)                                                                                     \
+    hipLaunchKernelGGL((lb_kernel<P, O, A>), dim3(L.nblocks), dim3(L.block), 0, L.stream, L.boxes, L.work, \
+                       L.nblocks, L.parity, L.remap, L.mode)
+    const bool all = L.mode == LB_ALL;
+    if (L.obstacles) {
+        if (all) OIF_LB(true, true);
+        else OIF_LB(true, false);
+    } else {
+        if (all) OIF_LB(false, true);
+        else OIF_LB(false, false);
+    }
+#undef OIF_LB
 }
 
 hipError_t launch_lb(const LbLaunch& L) {

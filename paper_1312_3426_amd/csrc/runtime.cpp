@@ -1595,8 +1595,8 @@ int batch_build(oif_batch* b) {
     bdrop_graph(b);
     // boxes and lattice work list
     // boxes without obstacles take one lattice launch and boxes with them
-    // another, so that every box runs the kernel it runs on its own (and the
-    // batched result equals the box-by-box one bit for bit)
+    // another (the kernel without the obstacle code), so that every box runs
+    // the kernel it runs on its own
     std::vector<BoxDev> boxes;
     std::vector<int2> work;
     for (size_t i = 0; i < b->ctx.size(); ++i) boxes.push_back(b->ctx[i]->box);
@@ -1683,13 +1683,13 @@ int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<h
             BHIP(b, launch_mesh(ml));
         }
         if (ev) (void)hipEventRecord((*ev)[3 * k + 1], s);
-        LbLaunch ll{(const BoxDev*)b->boxes_dev.p, (const int2*)b->work_dev.p, b->nblocks_plain, b->lb_block, par,
-                    b->remap, b->precision, s, LB_ALL, 0};
-        if (ll.nblocks > 0) BHIP(b, launch_lb(ll));
-        ll.work += b->nblocks_plain;
-        ll.nblocks = b->nblocks - b->nblocks_plain;
-        ll.obstacles = 1;
-        if (ll.nblocks > 0) BHIP(b, launch_lb(ll));
+        for (int obst = 0; obst < 2; ++obst) {
+            const int off = obst ? b->nblocks_plain : 0;
+            LbLaunch ll{(const BoxDev*)b->boxes_dev.p, (const int2*)b->work_dev.p + off,
+                        obst ? b->nblocks - b->nblocks_plain : b->nblocks_plain, b->lb_block, par, b->remap,
+                        b->precision, s, LB_ALL, obst};
+            if (ll.nblocks > 0) BHIP(b, launch_lb(ll));
+        }
         if (ev) (void)hipEventRecord((*ev)[3 * k + 2], s);
         par ^= 1;
     }

@@ -111,6 +111,26 @@ def test_obstacle_batch_matches_single_boxes(oif):
         c.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_obstacle_kernel_without_solid_nodes_is_bitwise_plain(oif, prec):
+    """A boundary that contains no node centre switches the box to the lattice
+    kernel with the obstacle code; with nothing solid the update must be the
+    plain one bit for bit (same collision arithmetic in both kernels)."""
+    say(f"[obstacles] empty boundary vs none, {prec}")
+    box = synth.config_channel_rbc(10)
+    outs = []
+    for empty in (False, True):
+        c = oif.Context.from_box(box, precision=prec)
+        if empty:
+            # half-space z < 0.25: below the first node centre (z = 0.5)
+            c.boundary_wall((0.0, 0.0, 1.0), 0.25)
+            assert not c.read_boundary().any()
+        c.step(10)
+        outs.append((c.read_populations(), c.read_mesh(-1)[0]))
+        c.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_boundary_clear_restores_plain_step(oif):
     box = synth.config_channel_rbc(10)
     outs = []

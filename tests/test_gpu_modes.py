@@ -41,12 +41,16 @@ def channel(steps=40):
     return synth.config_channel_rbc(steps)
 
 
-def test_overlap_matches_sequential_bitwise(oif):
-    say("[modes] overlap vs sequential, fp32 channel")
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_overlap_matches_sequential_bitwise(oif, prec):
+    """Split stepping runs other instantiations of the lattice kernel (touch
+    masks, populations loaded after the mask) than the sequential step; the
+    collision is rounded as written in all of them, so the bits agree."""
+    say(f"[modes] overlap vs sequential, {prec} channel")
     box = channel()
     outs = []
     for ov in (False, True):
-        c = oif.Context.from_box(box, precision="fp32")
+        c = oif.Context.from_box(box, precision=prec)
         c.set_overlap(ov)
         c.step(40)
         assert c.info().overlap == int(ov)
