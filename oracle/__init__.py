@@ -49,7 +49,12 @@ def build(force: bool = False) -> str:
 class _Lattice(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("walls_z", C.c_int),
                 ("tau", C.c_double), ("rho0", C.c_double), ("g", C.c_double * 3),
-                ("xi", C.c_double), ("solid", C.c_void_p), ("wall_u", C.c_void_p)]
+                ("xi", C.c_double), ("solid", C.c_void_p), ("wall_u", C.c_void_p),
+                ("collision", C.c_int), ("gamma_shear", C.c_double), ("gamma_bulk", C.c_double),
+                ("gamma_odd", C.c_double), ("gamma_even", C.c_double)]
+
+BGK, MRT = 0, 1
+EULER, VERLET = 0, 1
 
 
 class _Mesh(C.Structure):
@@ -57,7 +62,7 @@ class _Mesh(C.Structure):
                 ("t_tri_off", C.c_void_p), ("tri", C.c_void_p), ("t_k", C.c_void_p),
                 ("t_linear", C.c_void_p), ("n_obj", C.c_int), ("o_tmpl", C.c_void_p),
                 ("o_node_off", C.c_void_p), ("o_mass", C.c_void_p), ("o_fext", C.c_void_p),
-                ("t_model", C.c_void_p)]
+                ("t_model", C.c_void_p), ("integrator", C.c_int)]
 
 # force models (orc_membrane_forces)
 MODEL_PAPER = 0
@@ -131,6 +136,10 @@ def lib():
         L.orc_system_forces.argtypes = [vp, dp, dp]
         L.orc_system_touched.restype = C.c_long
         L.orc_system_touched.argtypes = [vp, dp]
+        L.orc_system_get_force.restype = None
+        L.orc_system_get_force.argtypes = [vp, dp]
+        L.orc_system_set_force.restype = None
+        L.orc_system_set_force.argtypes = [vp, dp]
         _lib = L
     return _lib
 
@@ -304,12 +313,17 @@ def force_triangles(which: str, x, tris, k, S0=None, Sg0=None, V0=None) -> np.nd
 # ---------------------------------------------------------------------------
 
 def _lattice(nx, ny, nz, tau=1.0, rho0=1.0, g=(0.0, 0.0, 0.0), xi=0.0, walls_z=False,
-             obstacles=None) -> _Lattice:
+             obstacles=None, mrt=None) -> _Lattice:
     """Lattice descriptor; obstacles = (solid uint8 [N], wall_u float64 [nb+1][3])
-    from ``boundary_field`` (the caller keeps the arrays alive)."""
+    from ``boundary_field`` (the caller keeps the arrays alive); mrt = None (BGK
+    with tau) or the rates (gamma_shear, gamma_bulk, gamma_odd, gamma_even) of
+    the multiple-relaxation-time operator."""
     L = _Lattice()
     L.nx, L.ny, L.nz, L.walls_z = int(nx), int(ny), int(nz), int(bool(walls_z))
     L.tau, L.rho0, L.xi = float(tau), float(rho0), float(xi)
+    if mrt is not None:
+        L.collision = MRT
+        L.gamma_shear, L.gamma_bulk, L.gamma_odd, L.gamma_even = (float(v) for v in mrt)
     for c in range(3):
         L.g[c] = float(g[c])
     if obstacles is not None:
@@ -345,10 +359,10 @@ def equilibrium_populations(nx, ny, nz, rho0=1.0) -> np.ndarray:
 
 
 def lb_step(n: np.ndarray, tau=1.0, g=(0.0, 0.0, 0.0), G: Optional[np.ndarray] = None,
-            walls_z=False, obstacles=None, rho0=1.0) -> np.ndarray:
+            walls_z=False, obstacles=None, rho0=1.0, mrt=None) -> np.ndarray:
     n = _f64(n)
     _, nz, ny, nx = n.shape
-    L = _lattice(nx, ny, nz, tau=tau, g=g, walls_z=walls_z, obstacles=obstacles, rho0=rho0)
+    L = _lattice(nx, ny, nz, tau=tau, g=g, walls_z=walls_z, obstacles=obstacles, rho0=rho0, mrt=mrt)
     out = np.empty_like(n)
     Gp = None if G is None else _f64(G)
     lib().orc_lb_step(C.byref(L), _p(n), None if Gp is None else _p(Gp), _p(out))
@@ -415,7 +429,8 @@ class System:
         bnd = list(getattr(box, "boundaries", []) or [])
         self.obstacles = boundary_field(box.nx, box.ny, box.nz, bnd) if bnd else None
         L = self._L = _lattice(box.nx, box.ny, box.nz, tau=box.tau, rho0=box.rho0, g=box.g,
-                               xi=box.friction, walls_z=box.walls_z, obstacles=self.obstacles)
+                               xi=box.friction, walls_z=box.walls_z, obstacles=self.obstacles,
+                               mrt=getattr(box, "mrt", None))
         # templates: apply the per-axis stretch to the node coordinates
         t_x, t_nv, t_nt, t_off, t_tri_off, tri, t_k, t_lin, t_mod = [], [], [], [], [], [], [], [], []
         noff = toff = 0
@@ -462,6 +477,7 @@ class System:
         m.t_nv, m.t_nt, m.t_tri_off, m.tri = _p(k["t_nv"]), _p(k["t_nt"]), _p(k["t_tri_off"]), _p(k["tri"])
         m.t_k, m.t_linear, m.t_model = _p(k["t_k"]), _p(k["t_lin"]), _p(k["t_mod"])
         m.n_obj = len(box.objects)
+        m.integrator = VERLET if getattr(box, "integrator", "euler") == "verlet" else EULER
         m.o_tmpl, m.o_node_off, m.o_mass, m.o_fext = _p(k["o_t"]), _p(k["o_off"]), _p(k["o_m"]), _p(k["o_f"])
         self._mesh = m
         h = lib().orc_system_create(C.byref(L), C.byref(m), _p(k["t_off"]), _p(k["t_x"]))
@@ -487,6 +503,19 @@ class System:
         self.last_diag = d
         if rc != 0:
             raise FloatingPointError(f"oracle: non-finite mesh state at step {-rc - 1}")
+
+    @property
+    def F(self) -> np.ndarray:
+        """Total force of the last step per mesh node (carried by velocity Verlet)."""
+        F = np.zeros((max(self.M, 1), 3))
+        lib().orc_system_get_force(self._h, _p(F))
+        return F[:self.M]
+
+    @F.setter
+    def F(self, value) -> None:
+        F = np.ascontiguousarray(np.broadcast_to(_f64(value), (self.M, 3)))
+        if self.M:
+            lib().orc_system_set_force(self._h, _p(F))
 
     def geometry(self) -> Tuple[np.ndarray, np.ndarray]:
         no = len(self.box.objects)

@@ -12,7 +12,10 @@
  * Where the paper is silent or garbled, the readings used here are:
  *   - collision: single-relaxation-time BGK with relaxation time tau and the
  *     standard second-order equilibrium (the paper only requires mass and
- *     momentum conservation and defers the operator to its references);
+ *     momentum conservation and defers the operator to its references); or,
+ *     as an option, the multiple-relaxation-time operator of those references
+ *     (relaxation in the orthogonal D3Q19 mode space, forcing as in the BGK
+ *     case mode by mode), which equals BGK when every rate is 1 - 1/tau;
  *   - external force term f_i: Guo forcing, with the fluid velocity taken as
  *     u = (sum_i n_i e_i + F/2) / rho (equal to the paper's moment definition
  *     when F = 0);
@@ -25,6 +28,8 @@
  *   - the velocity interpolated is that of the populations at the start of the
  *     step, with half the body force only;
  *   - mesh integrator: symplectic Euler, V += F/m then X += V, time step 1;
+ *     or, as an option, velocity Verlet (the integrator of the paper's
+ *     engine) with the drag taken at the half-step velocity;
  *   - bending: theta = inner dihedral angle, n = inward unit normal of each
  *     triangle, the force on each wing vertex along its own triangle's normal,
  *     minus half the sum on each vertex of the shared edge;
@@ -509,9 +514,127 @@ void orc_moments(const orc_lattice* L, const double* n, const double* Fx, double
     }
 }
 
+/* BGK collision with Guo forcing of one node's populations nn[19] under the
+ * force density F: post[i] = n_i - (n_i - n_i^eq)/tau + S_i. */
+static void collide_bgk(const orc_lattice* L, const double* nn, const double* F, double* post) {
+    double tau = L->tau;
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 19; ++i) {
+        rho += nn[i];
+        for (int c = 0; c < 3; ++c) j[c] += nn[i] * EV[i][c];
+    }
+    double u[3];
+    for (int c = 0; c < 3; ++c) u[c] = (j[c] + 0.5 * F[c]) / rho;
+    double usq = dot3(u, u);
+    for (int i = 0; i < 19; ++i) {
+        double e[3] = {EV[i][0], EV[i][1], EV[i][2]};
+        double eu = dot3(e, u);
+        double w = weight(i);
+        /* second-order equilibrium */
+        double neq = w * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+        /* Guo source term */
+        double src = 0.0;
+        for (int c = 0; c < 3; ++c) src += (3.0 * (e[c] - u[c]) + 9.0 * eu * e[c]) * F[c];
+        src *= (1.0 - 0.5 / tau) * w;
+        post[i] = nn[i] - (nn[i] - neq) / tau + src;
+    }
+}
+
+/* The orthogonal D3Q19 mode basis of the multiple-relaxation-time operator:
+ * basis vector k evaluated at velocity e_i.  k = 0 density; 1-3 momentum;
+ * 4 bulk stress (trace); 5-9 shear stress (traceless); 10-15 odd and 16-18
+ * even non-hydrodynamic ("ghost") modes.  sum_i w_i b_k(e_i) b_l(e_i) = 0 for
+ * k != l. */
+static double mode_basis(int k, int i) {
+    double x = EV[i][0], y = EV[i][1], z = EV[i][2];
+    double c2 = x * x + y * y + z * z;
+    switch (k) {
+        case 0: return 1.0;
+        case 1: return x;
+        case 2: return y;
+        case 3: return z;
+        case 4: return c2 - 1.0;
+        case 5: return 3.0 * x * x - c2;
+        case 6: return y * y - z * z;
+        case 7: return x * y;
+        case 8: return x * z;
+        case 9: return y * z;
+        case 10: return (3.0 * c2 - 5.0) * x;
+        case 11: return (3.0 * c2 - 5.0) * y;
+        case 12: return (3.0 * c2 - 5.0) * z;
+        case 13: return (y * y - z * z) * x;
+        case 14: return (z * z - x * x) * y;
+        case 15: return (x * x - y * y) * z;
+        case 16: return 3.0 * c2 * c2 - 6.0 * c2 + 1.0;
+        case 17: return (2.0 * c2 - 3.0) * (3.0 * x * x - c2);
+        default: return (2.0 * c2 - 3.0) * (y * y - z * z);
+    }
+}
+
+/* Multiple-relaxation-time collision of one node under the force density F.
+ * Modes m_k = sum_i b_k(e_i) n_i.  Density is kept and the momentum gains F.
+ * The stress modes relax towards their equilibrium values (those of the
+ * second-order equilibrium, rho u u + rho c_s^2 I with u = (j + F/2)/rho) and
+ * receive the force term of the same form as in the BGK case:
+ *   m_k* = m_k^eq + gamma_k (m_k - m_k^eq) + (1 + gamma_k)/2 phi_k,
+ * phi_k the mode k of the tensor u F + F u, gamma_k = gamma_bulk (k = 4) or
+ * gamma_shear (5-9).  Ghost modes (equilibrium zero) become gamma m_k.  Back
+ * to populations: n_i* = w_i sum_k b_k(e_i) m_k* / (sum_l w_l b_k(e_l)^2). */
+static void collide_mrt(const orc_lattice* L, const double* nn, const double* F, double* post) {
+    double m[19];
+    for (int k = 0; k < 19; ++k) {
+        m[k] = 0.0;
+        for (int i = 0; i < 19; ++i) m[k] += mode_basis(k, i) * nn[i];
+    }
+    double rho = m[0];
+    double u[3];
+    for (int c = 0; c < 3; ++c) u[c] = (m[1 + c] + 0.5 * F[c]) / rho;
+    /* equilibrium stress Pi_ab = rho/3 delta_ab + rho u_a u_b and force
+     * tensor Phi_ab = u_a F_b + F_a u_b, mapped to modes 4-9 the way the
+     * populations' second moments are: m4 = tr - rho, m5 = 3 xx - tr,
+     * m6 = yy - zz, m7 = xy, m8 = xz, m9 = yz */
+    double Pi[3][3], Phi[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            Pi[a][b] = rho * u[a] * u[b] + (a == b ? rho / 3.0 : 0.0);
+            Phi[a][b] = u[a] * F[b] + F[a] * u[b];
+        }
+    double trPi = Pi[0][0] + Pi[1][1] + Pi[2][2], trPhi = Phi[0][0] + Phi[1][1] + Phi[2][2];
+    double meq[10], phi[10];
+    meq[4] = trPi - rho;
+    meq[5] = 3.0 * Pi[0][0] - trPi;
+    meq[6] = Pi[1][1] - Pi[2][2];
+    meq[7] = Pi[0][1];
+    meq[8] = Pi[0][2];
+    meq[9] = Pi[1][2];
+    phi[4] = trPhi;
+    phi[5] = 3.0 * Phi[0][0] - trPhi;
+    phi[6] = Phi[1][1] - Phi[2][2];
+    phi[7] = Phi[0][1];
+    phi[8] = Phi[0][2];
+    phi[9] = Phi[1][2];
+    double ms[19];
+    ms[0] = m[0];
+    for (int c = 0; c < 3; ++c) ms[1 + c] = m[1 + c] + F[c];
+    for (int k = 4; k <= 9; ++k) {
+        double g = (k == 4) ? L->gamma_bulk : L->gamma_shear;
+        ms[k] = meq[k] + g * (m[k] - meq[k]) + 0.5 * (1.0 + g) * phi[k];
+    }
+    for (int k = 10; k <= 15; ++k) ms[k] = L->gamma_odd * m[k];
+    for (int k = 16; k <= 18; ++k) ms[k] = L->gamma_even * m[k];
+    for (int i = 0; i < 19; ++i) {
+        double v = 0.0;
+        for (int k = 0; k < 19; ++k) {
+            double norm = 0.0;
+            for (int l = 0; l < 19; ++l) norm += weight(l) * mode_basis(k, l) * mode_basis(k, l);
+            v += mode_basis(k, i) * ms[k] / norm;
+        }
+        post[i] = weight(i) * v;
+    }
+}
+
 void orc_lb_step(const orc_lattice* L, const double* n, const double* G, double* nout) {
     long N = (long)L->nx * L->ny * L->nz;
-    double tau = L->tau;
     for (int z = 0; z < L->nz; ++z)
         for (int y = 0; y < L->ny; ++y)
             for (int x = 0; x < L->nx; ++x) {
@@ -522,27 +645,14 @@ void orc_lb_step(const orc_lattice* L, const double* n, const double* G, double*
                 }
                 double F[3];
                 for (int c = 0; c < 3; ++c) F[c] = L->g[c] + (G ? G[c * N + p] : 0.0);
-                /* moments */
-                double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
-                for (int i = 0; i < 19; ++i) {
-                    double ni = n[i * N + p];
-                    rho += ni;
-                    for (int c = 0; c < 3; ++c) j[c] += ni * EV[i][c];
-                }
-                double u[3];
-                for (int c = 0; c < 3; ++c) u[c] = (j[c] + 0.5 * F[c]) / rho;
-                double usq = dot3(u, u);
+                double nn[19], post[19];
+                for (int i = 0; i < 19; ++i) nn[i] = n[i * N + p];
+                if (L->collision == ORC_MRT) collide_mrt(L, nn, F, post);
+                else collide_bgk(L, nn, F, post);
                 for (int i = 0; i < 19; ++i) {
                     double e[3] = {EV[i][0], EV[i][1], EV[i][2]};
-                    double eu = dot3(e, u);
                     double w = weight(i);
-                    /* second-order equilibrium */
-                    double neq = w * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
-                    /* Guo source term */
-                    double src = 0.0;
-                    for (int c = 0; c < 3; ++c) src += (3.0 * (e[c] - u[c]) + 9.0 * eu * e[c]) * F[c];
-                    src *= (1.0 - 0.5 / tau) * w;
-                    double ns = n[i * N + p] - (n[i * N + p] - neq) / tau + src;
+                    double ns = post[i];
                     /* propagation to x + e_i */
                     int xd = wrap(x + EV[i][0], L->nx);
                     int yd = wrap(y + EV[i][1], L->ny);
@@ -695,6 +805,8 @@ struct orc_system {
     double* o_fext;
     long M;
     double* Fel; /* [M][3] */
+    double* Fprev; /* [M][3] total force of the last step (velocity Verlet) */
+    int integrator;
     double* G;   /* [3][N] */
     double* u;   /* [3][N] */
     double* rho; /* [N] */
@@ -719,6 +831,7 @@ void orc_system_destroy(orc_system* s) {
     free(s->o_mass);
     free(s->o_fext);
     free(s->Fel);
+    free(s->Fprev);
     free(s->G);
     free(s->u);
     free(s->rho);
@@ -774,6 +887,8 @@ orc_system* orc_system_create(const orc_lattice* L, const orc_mesh* m, const int
     }
     long N = (long)L->nx * L->ny * L->nz;
     s->Fel = (double*)calloc((size_t)(3 * s->M + 1), sizeof(double));
+    s->Fprev = (double*)calloc((size_t)(3 * s->M + 1), sizeof(double));
+    s->integrator = m->integrator;
     s->G = (double*)calloc((size_t)(3 * N), sizeof(double));
     s->u = (double*)calloc((size_t)(3 * N), sizeof(double));
     s->rho = (double*)calloc((size_t)N, sizeof(double));
@@ -817,15 +932,40 @@ long orc_system_touched(orc_system* s, const double* X) {
     return cnt;
 }
 
+void orc_system_get_force(const orc_system* s, double* F) {
+    memcpy(F, s->Fprev, sizeof(double) * 3 * (size_t)s->M);
+}
+
+void orc_system_set_force(orc_system* s, const double* F) {
+    memcpy(s->Fprev, F, sizeof(double) * 3 * (size_t)s->M);
+}
+
 int orc_system_run(orc_system* s, double* n, double* X, double* V, int n_steps, double* diag) {
     const orc_lattice* L = &s->L;
     long N = (long)L->nx * L->ny * L->nz;
+    int verlet = s->integrator == ORC_VERLET;
     for (int step = 0; step < n_steps; ++step) {
         double d[10] = {0};
         /* a non-finite mesh state has no stencil: stop instead of indexing */
         for (long j = 0; j < 3 * s->M; ++j)
             if (!isfinite(X[j]) || !isfinite(V[j]) || fabs(X[j]) > 1e9) return -1 - step;
-        /* 1-2: geometry and membrane forces from the positions at step start */
+        if (verlet) {
+            /* velocity Verlet, first half: half kick with the force of the
+             * previous step, then drift; V holds the half-step velocity */
+            for (int o = 0; o < s->n_obj; ++o) {
+                int nv = s->t[s->o_tmpl[o]].nv;
+                double m = s->o_mass[o];
+                for (int v = 0; v < nv; ++v) {
+                    long j = (long)s->o_off[o] + v;
+                    for (int c = 0; c < 3; ++c) {
+                        V[3 * j + c] += 0.5 * s->Fprev[3 * j + c] / m;
+                        X[3 * j + c] += V[3 * j + c];
+                    }
+                }
+            }
+        }
+        /* 1-2: geometry and membrane forces from the current positions (step
+         * start; after the drift with velocity Verlet) */
         orc_system_forces(s, X, s->Fel);
         /* 3: coupling.  Node velocity from the populations at step start,
          * with half the body force only. */
@@ -838,11 +978,17 @@ int orc_system_run(orc_system* s, double* n, double* X, double* V, int n_steps, 
                 long j = (long)s->o_off[o] + v;
                 double drag[3]; /* xi (v - u): the force handed to the fluid */
                 d[0] += orc_couple_point(L, s->u, &X[3 * j], &V[3 * j], s->G, drag);
-                /* 4: mesh update, kick then drift */
+                /* 4: mesh update: kick then drift (Euler) or the second half
+                 * kick (velocity Verlet) */
                 for (int c = 0; c < 3; ++c) {
                     double Ft = s->Fel[3 * j + c] - drag[c] + s->o_fext[3 * o + c];
-                    V[3 * j + c] += Ft / m;
-                    X[3 * j + c] += V[3 * j + c];
+                    if (verlet) {
+                        V[3 * j + c] += 0.5 * Ft / m;
+                        s->Fprev[3 * j + c] = Ft;
+                    } else {
+                        V[3 * j + c] += Ft / m;
+                        X[3 * j + c] += V[3 * j + c];
+                    }
                     d[1 + c] += s->Fel[3 * j + c];
                     d[4 + c] += -drag[c];
                     d[7 + c] += s->o_fext[3 * o + c];

@@ -99,7 +99,18 @@ typedef struct {
      * wall_u[3 k .. 3 k + 2] */
     const unsigned char* solid;
     const double* wall_u;
+    /* collision operator: ORC_BGK (relaxation time tau) or ORC_MRT, the
+     * multiple-relaxation-time operator in the orthogonal mode space of the
+     * D3Q19 set used by the paper's references: mass and momentum conserved,
+     * the bulk (trace) and shear (traceless) parts of the stress relaxed by
+     * gamma_bulk and gamma_shear, the odd and even non-hydrodynamic (ghost)
+     * modes by gamma_odd and gamma_even */
+    int collision;
+    double gamma_shear, gamma_bulk, gamma_odd, gamma_even;
 } orc_lattice;
+
+#define ORC_BGK 0
+#define ORC_MRT 1
 
 /* Boundary shapes: set solid[p] = id for every node whose centre lies inside.
  * Rhomboid: {corner + s a + t b + u c : s, t, u in [0, 1]}.  Wall: the
@@ -150,7 +161,16 @@ typedef struct {
     const double* o_mass;
     const double* o_fext;   /* [n_obj][3] */
     const int* t_model;     /* per template ORC_MODEL_*, or NULL for all PAPER */
+    int integrator;         /* ORC_EULER or ORC_VERLET (all objects) */
 } orc_mesh;
+
+/* Mesh integrators (dt = 1).  EULER: forces from X_t, V_t; V += F/m, then
+ * X += V.  VERLET (velocity Verlet, as in the paper's engine): V_h = V_t +
+ * F_t/(2m), X_{t+1} = X_t + V_h, forces at X_{t+1} with the drag taken at
+ * V_h, V_{t+1} = V_h + F_{t+1}/(2m); F_t is the total force of the previous
+ * step (zero before the first step). */
+#define ORC_EULER 0
+#define ORC_VERLET 1
 
 typedef struct orc_system orc_system;
 
@@ -166,6 +186,12 @@ void orc_system_destroy(orc_system* s);
  * step: [0] clamped stencil corners, [1..3] sum of elastic forces,
  * [4..6] sum of coupling forces on the mesh, [7..9] sum of external forces. */
 int orc_system_run(orc_system* s, double* n, double* X, double* V, int n_steps, double* diag);
+
+/* The total force of the last step on every mesh node (3*M): the force the
+ * velocity Verlet integrator carries into the next step.  Read or replace it
+ * (with X and V it is the integrator's whole state). */
+void orc_system_get_force(const orc_system* s, double* F);
+void orc_system_set_force(orc_system* s, const double* F);
 
 /* Per-object geometry of the current positions: S_g[o], V[o]. */
 void orc_system_geometry(orc_system* s, const double* X, double* Sg, double* Vol);

@@ -292,6 +292,10 @@ class Box:
     steps: int = 1
     name: str = ""
     boundaries: List[Boundary] = dataclasses.field(default_factory=list)
+    # collision: None = BGK with tau; else the multiple-relaxation-time rates
+    # (gamma_shear, gamma_bulk, gamma_odd, gamma_even)
+    mrt: Optional[Tuple[float, float, float, float]] = None
+    integrator: str = "euler"  # mesh integrator: "euler" or "verlet"
 
     @property
     def n_nodes(self) -> int:

@@ -14,7 +14,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oif_oracle.c")
 PIN_FILES = ["tests/test_oracle_mesh.py", "tests/test_oracle_lb.py", "tests/test_oracle_coupling.py",
-             "tests/test_oracle_conservative.py", "tests/test_oracle_boundaries.py"]
+             "tests/test_oracle_conservative.py", "tests/test_oracle_boundaries.py",
+             "tests/test_oracle_mrt_verlet.py"]
 
 MUTATIONS = {
     "kappa_exponent": ("(lambda + pow(lambda, -3.0))", "(lambda + pow(lambda, -2.0))"),
@@ -73,8 +74,22 @@ MUTATIONS = {
                                "for (int c = 0; c < 3; ++c) u[c * N + p] = 0.0;"),
     "spread_into_solid": ("if (L->solid && L->solid[idx[k]]) continue;", "if (0) continue;"),
     "solid_nodes_updated": ("if (L->solid && L->solid[p]) {  /* obstacle node: not updated */", "if (0) {"),
-    "drift_before_kick": ("V[3 * j + c] += Ft / m;\n                    X[3 * j + c] += V[3 * j + c];",
-                          "X[3 * j + c] += V[3 * j + c];\n                    V[3 * j + c] += Ft / m;"),
+    "drift_before_kick": ("V[3 * j + c] += Ft / m;\n                        X[3 * j + c] += V[3 * j + c];",
+                          "X[3 * j + c] += V[3 * j + c];\n                        V[3 * j + c] += Ft / m;"),
+    "mrt_bulk_shear_swapped": ("double g = (k == 4) ? L->gamma_bulk : L->gamma_shear;",
+                               "double g = (k == 4) ? L->gamma_shear : L->gamma_bulk;"),
+    "mrt_force_factor": ("0.5 * (1.0 + g) * phi[k]", "0.5 * phi[k]"),
+    "mrt_ghost_parity": ("for (int k = 10; k <= 15; ++k) ms[k] = L->gamma_odd * m[k];",
+                         "for (int k = 10; k <= 15; ++k) ms[k] = L->gamma_even * m[k];"),
+    "mrt_momentum_no_force": ("ms[1 + c] = m[1 + c] + F[c];", "ms[1 + c] = m[1 + c];"),
+    "mrt_basis_not_orthogonal": ("case 16: return 3.0 * c2 * c2 - 6.0 * c2 + 1.0;",
+                                 "case 16: return 3.0 * c2 * c2 - 5.0 * c2 + 1.0;"),
+    "mrt_equilibrium_without_uu": ("Pi[a][b] = rho * u[a] * u[b] + (a == b ? rho / 3.0 : 0.0);",
+                                   "Pi[a][b] = (a == b ? rho / 3.0 : 0.0);"),
+    "verlet_full_first_kick": ("V[3 * j + c] += 0.5 * s->Fprev[3 * j + c] / m;",
+                               "V[3 * j + c] += s->Fprev[3 * j + c] / m;"),
+    "verlet_force_not_carried": ("s->Fprev[3 * j + c] = Ft;", "s->Fprev[3 * j + c] = 0.0;"),
+    "verlet_full_second_kick": ("V[3 * j + c] += 0.5 * Ft / m;", "V[3 * j + c] += Ft / m;"),
 }
 
 
