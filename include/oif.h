@@ -272,6 +272,20 @@ int oif_step_timed(oif_ctx* ctx, int n_steps, oif_timing* t);
  * even number) in one hipGraph and replays it; 0 launches eagerly. */
 int oif_set_graph(oif_ctx* ctx, int steps_per_graph);
 
+/* Collision operator.  Default: BGK with the relaxation time tau of the
+ * lattice description (the paper requires only mass and momentum
+ * conservation of the collision and defers its form to its LB references).
+ * gamma = {shear, bulk, odd, even} selects the multiple-relaxation-time
+ * operator of those references instead, in the orthogonal D3Q19 mode space:
+ * mass kept, momentum + F, the traceless and trace parts of the stress
+ * relaxed about rho/3 I + rho u u by gamma[0] and gamma[1] (force term
+ * (1 + gamma)/2 (u F + F u), u = (j + F/2)/rho), the non-hydrodynamic
+ * remainder scaled by gamma[2] / gamma[3] in its parts odd / even under
+ * e -> -e.  Each factor must lie in (-1, 1) (OIF_E_ARG otherwise); the
+ * kinematic viscosity is (1 + gamma[0]) / (6 (1 - gamma[0])), and all four
+ * equal to 1 - 1/tau give the BGK operator.  gamma = NULL returns to BGK. */
+int oif_set_mrt(oif_ctx* ctx, const double* gamma);
+
 /* Overlap (default off): the lattice nodes inside any mesh node's 2x2x2
  * stencil are marked (by the membrane kernel of the previous step); the lattice
  * update of all other nodes (which no coupling force can reach) then runs on a

@@ -117,6 +117,85 @@ __device__ __forceinline__ void collide(const BoxDev* __restrict__ B, R (&d)[19]
     }
 }
 
+// Multiple-relaxation-time collision of one node's 19 deviations, in place
+// (the operator of the paper's LB references, in the orthogonal D3Q19 mode
+// space).  Mass is kept and the momentum gains F.  The second moment relaxes
+// about its equilibrium rho/3 I + rho u u (u = (j + F/2)/rho): with the
+// non-equilibrium part N, the post-collision part is
+//   N* = gs dev(N) + gb iso(N) + (1+gs)/2 dev(Phi) + (1+gb)/2 iso(Phi),
+// Phi = u F + F u, dev/iso the traceless and trace parts.  The populations are
+// rebuilt from density, momentum and second moment as w_i [drho + 3 e.j +
+// 4.5 (A : e e - tr A / 3)], A the second moment of the deviations less
+// drho/3 I; what that leaves of the incoming populations (the
+// non-hydrodynamic part) is kept scaled by g_odd and g_even in its parts odd
+// and even under e -> -e.  Rounded as written, like collide().
+template <typename R>
+__device__ __forceinline__ void collide_mrt(const BoxDev* __restrict__ B, R (&d)[19], R fx, R fy, R fz) {
+#pragma clang fp contract(off)
+    R drho = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) drho += d[i];
+    const R jx = d[1] - d[2] + d[7] - d[8] + d[9] - d[10] + d[11] - d[12] + d[13] - d[14];
+    const R jy = d[3] - d[4] + d[7] - d[8] - d[9] + d[10] + d[15] - d[16] + d[17] - d[18];
+    const R jz = d[5] - d[6] + d[11] - d[12] - d[13] + d[14] + d[15] - d[16] - d[17] + d[18];
+    // second moment of the deviations
+    const R sxy = d[7] + d[8] + d[9] + d[10], sxz = d[11] + d[12] + d[13] + d[14];
+    const R syz = d[15] + d[16] + d[17] + d[18];
+    const R pxx = d[1] + d[2] + sxy + sxz, pyy = d[3] + d[4] + sxy + syz, pzz = d[5] + d[6] + sxz + syz;
+    const R pxy = d[7] + d[8] - d[9] - d[10], pxz = d[11] + d[12] - d[13] - d[14];
+    const R pyz = d[15] + d[16] - d[17] - d[18];
+    const R rho = (R)B->rho0 + drho;
+    const R ir = R(1) / rho;
+    const R ux = (jx + R(0.5) * fx) * ir;
+    const R uy = (jy + R(0.5) * fy) * ir;
+    const R uz = (jz + R(0.5) * fz) * ir;
+    const R t3 = drho / R(3);
+    // A (incoming) and the non-equilibrium stress N = A - rho u u
+    const R axx = pxx - t3, ayy = pyy - t3, azz = pzz - t3;
+    const R rux = rho * ux, ruy = rho * uy, ruz = rho * uz;
+    const R exx = rux * ux, eyy = ruy * uy, ezz = ruz * uz, exy = rux * uy, exz = rux * uz, eyz = ruy * uz;
+    const R nxx = axx - exx, nyy = ayy - eyy, nzz = azz - ezz;
+    const R nxy = pxy - exy, nxz = pxz - exz, nyz = pyz - eyz;
+    const R fxx = R(2) * ux * fx, fyy = R(2) * uy * fy, fzz = R(2) * uz * fz;
+    const R fxy = ux * fy + fx * uy, fxz = ux * fz + fx * uz, fyz = uy * fz + fy * uz;
+    const R gs = (R)B->gamma_shear, gb = (R)B->gamma_bulk;
+    const R hs = R(0.5) * (R(1) + gs), hb = R(0.5) * (R(1) + gb);
+    const R trn3 = (nxx + nyy + nzz) / R(3), trf3 = (fxx + fyy + fzz) / R(3);
+    const R iso = gb * trn3 + hb * trf3;  // trace part of N*, per diagonal entry
+    // post-collision A* = rho u u + N*
+    const R bxx = exx + gs * (nxx - trn3) + hs * (fxx - trf3) + iso;
+    const R byy = eyy + gs * (nyy - trn3) + hs * (fyy - trf3) + iso;
+    const R bzz = ezz + gs * (nzz - trn3) + hs * (fzz - trf3) + iso;
+    const R bxy = exy + gs * nxy + hs * fxy, bxz = exz + gs * nxz + hs * fxz, byz = eyz + gs * nyz + hs * fyz;
+    const R tra3 = (axx + ayy + azz) / R(3), trb3 = (bxx + byy + bzz) / R(3);
+    const R go = (R)B->gamma_odd, ge = (R)B->gamma_even;
+    const R kx = jx + fx, ky = jy + fy, kz = jz + fz;  // post-collision momentum
+    {  // rest population: even, e = 0
+        const R w = wt<R>(0);
+        const R hin = w * (drho - R(4.5) * tra3), hout = w * (drho - R(4.5) * trb3);
+        d[0] = hout + ge * (d[0] - hin);
+    }
+#pragma unroll
+    for (int i = 1; i < 19; i += 2) {  // i and its opposite i + 1
+        const R w = wt<R>(i);
+        // A : e e over the non-zero components of e_i
+        R qa = R(0), qb = R(0);
+        if (cx(i)) { qa = qa + axx; qb = qb + bxx; }
+        if (cy(i)) { qa = qa + ayy; qb = qb + byy; }
+        if (cz(i)) { qa = qa + azz; qb = qb + bzz; }
+        if (cx(i) && cy(i)) { qa = qa + R(2 * cx(i) * cy(i)) * pxy; qb = qb + R(2 * cx(i) * cy(i)) * bxy; }
+        if (cx(i) && cz(i)) { qa = qa + R(2 * cx(i) * cz(i)) * pxz; qb = qb + R(2 * cx(i) * cz(i)) * bxz; }
+        if (cy(i) && cz(i)) { qa = qa + R(2 * cy(i) * cz(i)) * pyz; qb = qb + R(2 * cy(i) * cz(i)) * byz; }
+        const R ein = w * (drho + R(4.5) * (qa - tra3)), eout = w * (drho + R(4.5) * (qb - trb3));
+        const R oin = (R(3) * w) * edot<R>(i, jx, jy, jz), oout = (R(3) * w) * edot<R>(i, kx, ky, kz);
+        const R geven = R(0.5) * (d[i] + d[i + 1]) - ein;
+        const R godd = R(0.5) * (d[i] - d[i + 1]) - oin;
+        const R even = eout + ge * geven, odd = oout + go * godd;
+        d[i] = even + odd;
+        d[i + 1] = even - odd;
+    }
+}
+
 // Collision at node p (force density f) and push of the 19 post-collision
 // deviations to the neighbours (halfway bounce-back at z walls); with
 // obstacles (OBST), a push into a solid node (bit i of `links`) returns to p in
@@ -131,7 +210,7 @@ __device__ __forceinline__ void load_pops(const BoxDev* __restrict__ B, int p, i
     for (int i = 0; i < 19; ++i) raw[i] = gload(src + (size_t)i * B->N, (unsigned)p * (unsigned)sizeof(S));
 }
 
-template <int P, bool OBST>
+template <int P, bool OBST, bool MRT>
 __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p,
                                              const typename Prec<P>::S (&raw)[19], typename Prec<P>::R fx,
                                              typename Prec<P>::R fy, typename Prec<P>::R fz, int parity,
@@ -148,7 +227,8 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
     R d[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) d[i] = dec<P>(raw[i], inv);
-    collide<R>(B, d, fx, fy, fz);
+    if (MRT) collide_mrt<R>(B, d, fx, fy, fz);
+    else collide<R>(B, d, fx, fy, fz);
 
     // neighbour offsets with periodic wrap
     const int nx = B->nx, ny = B->ny, nz = B->nz;
@@ -207,8 +287,8 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
 // OBST: some box of the launch has obstacles; without it that code is left out.
 // ALL: mode is LB_ALL (every node is updated, so the population loads go out
 // first and are in flight while the mask word and any coupling force are
-// fetched).
-template <int P, bool OBST, bool ALL>
+// fetched).  MRT: the boxes use the multiple-relaxation-time collision.
+template <int P, bool OBST, bool ALL, bool MRT>
 __global__ void __launch_bounds__(1024)
 lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int nblocks, int parity,
           int remap, int mode) {
@@ -267,7 +347,7 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
     const unsigned links = (OBST && B->links) ? gld(B->links + p) : 0u;
     if (!ALL) load_pops<P>(B, p, parity, raw);
     if ((m >> (p & 63)) & 1ull) take_force<P>(B, p, fx, fy, fz);
-    collide_push<P, OBST>(B, p, raw, fx, fy, fz, parity, links);
+    collide_push<P, OBST, MRT>(B, p, raw, fx, fy, fz, parity, links);
 }
 
 template <int P>
@@ -406,17 +486,21 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
 
 template <int P>
 void launch_lb_p(const LbLaunch& L) {
-#define OIF_LB(O, A)                                                                                     \
-    hipLaunchKernelGGL((lb_kernel<P, O, A>), dim3(L.nblocks), dim3(L.block), 0, L.stream, L.boxes, L.work, \
+#define OIF_LB(O, A, M)                                                                                     \
+    hipLaunchKernelGGL((lb_kernel<P, O, A, M>), dim3(L.nblocks), dim3(L.block), 0, L.stream, L.boxes, L.work, \
                        L.nblocks, L.parity, L.remap, L.mode)
+#define OIF_LB_M(O, A)         \
+    if (L.mrt) OIF_LB(O, A, true); \
+    else OIF_LB(O, A, false)
     const bool all = L.mode == LB_ALL;
     if (L.obstacles) {
-        if (all) OIF_LB(true, true);
-        else OIF_LB(true, false);
+        if (all) OIF_LB_M(true, true);
+        else OIF_LB_M(true, false);
     } else {
-        if (all) OIF_LB(false, true);
-        else OIF_LB(false, false);
+        if (all) OIF_LB_M(false, true);
+        else OIF_LB_M(false, false);
     }
+#undef OIF_LB_M
 #undef OIF_LB
 }
 

@@ -54,6 +54,11 @@ struct BoxDev {
     float st_inv;
     double fp_scale; // fixed-point scale 2^e
     double fp_inv;
+    // collision: 0 = BGK (omega, guo); 1 = multiple relaxation times with the
+    // factors of the shear and bulk stress and of the odd and even
+    // non-hydrodynamic parts
+    int mrt;
+    double gamma_shear, gamma_bulk, gamma_odd, gamma_even;
 };
 
 template <typename real>
@@ -154,7 +159,8 @@ struct LbLaunch {
     int precision;
     hipStream_t stream;
     int mode;              // LB_ALL, LB_FREE or LB_TOUCHED
-    int obstacles;         // some box of the launch has obstacles
+    int obstacles;         // the boxes of the launch have obstacles
+    int mrt;               // the boxes of the launch use the MRT collision
 };
 hipError_t launch_lb(const LbLaunch& L);
 

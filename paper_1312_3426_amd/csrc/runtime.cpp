@@ -298,7 +298,9 @@ struct oif_batch {
     DevBuf boxes_dev, work_dev, obj_dev;
     std::vector<unsigned char> obj_host;
     int nblocks = 0, nobj = 0, n_lds_obj = 0;
-    int nblocks_plain = 0;  // the work list holds boxes without obstacles first
+    // the work list holds the boxes grouped by lattice-kernel variant
+    // (obstacles, MRT collision): one launch per group
+    int var_off[5] = {0, 0, 0, 0, 0};
     size_t lds_need = 0;
     int any_conservative = 0;
     int lb_block = 256, mesh_block = 256, remap = 1;
@@ -584,6 +586,7 @@ int enqueue_lb(oif_ctx* c, int par, hipStream_t s, int mode) {
     ll.stream = s;
     ll.mode = mode;
     ll.obstacles = c->n_bnd > 0;
+    ll.mrt = c->box.mrt;
     HIPCALL(c, launch_lb(ll));
     return OIF_OK;
 }
@@ -1206,6 +1209,24 @@ int oif_set_graph(oif_ctx* c, int steps_per_graph) {
     return OIF_OK;
 }
 
+int oif_set_mrt(oif_ctx* c, const double* gamma) {
+    if (!c) return OIF_E_ARG;
+    if (gamma)
+        for (int k = 0; k < 4; ++k)
+            if (!(gamma[k] > -1.0 && gamma[k] < 1.0))
+                return fail(c, OIF_E_ARG, "MRT relaxation factors must lie in (-1, 1)");
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    c->box.mrt = gamma ? 1 : 0;
+    c->box.gamma_shear = gamma ? gamma[0] : 0.0;
+    c->box.gamma_bulk = gamma ? gamma[1] : 0.0;
+    c->box.gamma_odd = gamma ? gamma[2] : 0.0;
+    c->box.gamma_even = gamma ? gamma[3] : 0.0;
+    HIPCALL(c, hipMemcpy(c->box_dev, &c->box, sizeof(BoxDev), hipMemcpyHostToDevice));
+    c->mesh_dirty = true;  // batches hold copies of the box descriptor
+    drop_graph(c);
+    return OIF_OK;
+}
+
 int oif_set_overlap(oif_ctx* c, int on) {
     if (!c) return OIF_E_ARG;
     HIPCALL(c, hipStreamSynchronize(c->stream));
@@ -1594,20 +1615,21 @@ int batch_build(oif_batch* b) {
     }
     bdrop_graph(b);
     // boxes and lattice work list
-    // boxes without obstacles take one lattice launch and boxes with them
-    // another (the kernel without the obstacle code), so that every box runs
-    // the kernel it runs on its own
+    // one lattice launch per kernel variant (obstacles or not, MRT or BGK),
+    // so that every box runs the kernel it runs on its own
     std::vector<BoxDev> boxes;
     std::vector<int2> work;
     for (size_t i = 0; i < b->ctx.size(); ++i) boxes.push_back(b->ctx[i]->box);
-    for (int obst = 0; obst < 2; ++obst) {
+    for (int v = 0; v < 4; ++v) {
+        b->var_off[v] = (int)work.size();
         for (size_t i = 0; i < b->ctx.size(); ++i) {
-            if ((b->ctx[i]->n_bnd > 0) != (obst == 1)) continue;
-            const int nb = (b->ctx[i]->N + b->lb_block - 1) / b->lb_block;
+            const oif_ctx* c = b->ctx[i];
+            if ((c->n_bnd > 0 ? 1 : 0) + 2 * c->box.mrt != v) continue;
+            const int nb = (c->N + b->lb_block - 1) / b->lb_block;
             for (int k = 0; k < nb; ++k) work.push_back(make_int2((int)i, k));
         }
-        if (obst == 0) b->nblocks_plain = (int)work.size();
     }
+    b->var_off[4] = (int)work.size();
     b->nblocks = (int)work.size();
     b->boxes_dev.release();
     b->work_dev.release();
@@ -1683,11 +1705,10 @@ int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<h
             BHIP(b, launch_mesh(ml));
         }
         if (ev) (void)hipEventRecord((*ev)[3 * k + 1], s);
-        for (int obst = 0; obst < 2; ++obst) {
-            const int off = obst ? b->nblocks_plain : 0;
-            LbLaunch ll{(const BoxDev*)b->boxes_dev.p, (const int2*)b->work_dev.p + off,
-                        obst ? b->nblocks - b->nblocks_plain : b->nblocks_plain, b->lb_block, par, b->remap,
-                        b->precision, s, LB_ALL, obst};
+        for (int v = 0; v < 4; ++v) {
+            LbLaunch ll{(const BoxDev*)b->boxes_dev.p, (const int2*)b->work_dev.p + b->var_off[v],
+                        b->var_off[v + 1] - b->var_off[v], b->lb_block, par, b->remap, b->precision, s,
+                        LB_ALL, v & 1, v >> 1};
             if (ll.nblocks > 0) BHIP(b, launch_lb(ll));
         }
         if (ev) (void)hipEventRecord((*ev)[3 * k + 2], s);

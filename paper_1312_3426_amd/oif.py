@@ -91,6 +91,7 @@ SIGNATURES = {
     "oif_set_graph": (_i, [_vp, _i]),
     "oif_set_overlap": (_i, [_vp, _i]),
     "oif_set_launch": (_i, [_vp, _i, _i, _i]),
+    "oif_set_mrt": (_i, [_vp, _vp]),
     "oif_autotune": (_i, [_vp, C.c_char_p]),
     "oif_read_populations": (_i, [_vp, _vp]),
     "oif_write_populations": (_i, [_vp, _vp]),
@@ -251,6 +252,15 @@ class Context:
     def set_launch(self, lb_block: int = -1, mesh_block: int = -1, xcd_remap: int = -1):
         self._chk(lib().oif_set_launch(self.h, int(lb_block), int(mesh_block), int(xcd_remap)))
 
+    def set_mrt(self, gamma=None):
+        """Multiple-relaxation-time collision with the factors (shear, bulk,
+        odd, even); None returns to BGK."""
+        if gamma is None:
+            self._chk(lib().oif_set_mrt(self.h, None))
+        else:
+            g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(4))
+            self._chk(lib().oif_set_mrt(self.h, g.ctypes.data))
+
     def set_overlap(self, on: bool):
         self._chk(lib().oif_set_overlap(self.h, int(bool(on))))
 
@@ -341,6 +351,8 @@ class Context:
         """Create a context from a ``synth.Box``-like description (duck-typed)."""
         c = cls(box.nx, box.ny, box.nz, tau=box.tau, rho0=box.rho0, body_force=box.g,
                 friction=box.friction, walls_z=box.walls_z, precision=precision, **kw)
+        if getattr(box, "mrt", None) is not None:
+            c.set_mrt(box.mrt)
         for bnd in getattr(box, "boundaries", []) or []:
             if bnd.kind == "rhomboid":
                 c.boundary_rhomboid(bnd.corner, bnd.a, bnd.b, bnd.c, bnd.velocity)

@@ -1,0 +1,174 @@
+"""GPU parity of the optional engine variants through the C ABI: the
+multiple-relaxation-time collision (the LB operator of the paper's
+references) and the velocity Verlet mesh integrator (the paper's engine),
+against the FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from paper_1312_3426_amd import synth
+
+from gpu_util import W, check, fmt, gpu_fields, oracle_fields, say
+
+pytestmark = pytest.mark.gpu
+
+RATES = {
+    "shear_bulk": (0.25, -0.4, 0.0, 0.0),
+    "ghosts": (-0.3, 0.5, 0.6, -0.7),
+}
+
+
+@pytest.fixture(scope="module")
+def oif():
+    from paper_1312_3426_amd import oif as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build()
+    return oracle
+
+
+def assert_ok(res, what):
+    bad = {k: v for k, v in res.items() if not v[3]}
+    assert not bad, f"{what}: {fmt(bad)}"
+
+
+LB_CASES = [
+    # (nx, ny, nz, walls)
+    (20, 20, 20, False),   # 8000 nodes: 31.25 blocks of 256
+    (9, 7, 11, True),      # ragged, bounce-back walls
+    (2, 2, 2, False),      # every neighbour wraps onto the box
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("rates", sorted(RATES))
+@pytest.mark.parametrize("case", LB_CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{'w' if c[3] else ''}")
+def test_mrt_lattice_vs_oracle(oif, orc, prec, rates, case):
+    nx, ny, nz, walls = case
+    gam = RATES[rates]
+    say(f"[mrt] lattice {prec} {rates} {case}")
+    rng = np.random.default_rng(nx * 100 + ny * 10 + nz)
+    box = synth.Box(nx, ny, nz, g=(1e-5, -2e-5, 3e-5), walls_z=walls, mrt=gam)
+    n0 = synth.random_populations(rng, box, amp=1e-3)
+    ctx = oif.Context.from_box(box, precision=prec)
+    ctx.write_populations(n0)
+    n_or = n0.copy()
+    for step in (1, 9):
+        ctx.step(step)
+        for _ in range(step):
+            n_or = orc.lb_step(n_or, g=box.g, walls_z=walls, mrt=gam)
+        _, u_or = orc.moments(n_or, g=box.g)
+        g = dict(delta=ctx.read_populations() - W[:, None, None, None], u=ctx.read_velocity())
+        o = dict(delta=n_or - W[:, None, None, None], u=u_or)
+        res = check(g, o, prec, 1.0, max(nx, ny, nz), keys=("delta", "u"))
+        say(f"   after {step}: {fmt(res)}")
+        assert_ok(res, f"step {step}")
+    ctx.close()
+
+
+def test_mrt_equal_rates_matches_bgk(oif):
+    """All factors 1 - 1/tau: the MRT kernel reproduces the BGK kernel (FP64,
+    up to the different rounding order of the two operators)."""
+    say("[mrt] equal rates vs BGK, fp64")
+    tau = 0.8
+    gam = 1 - 1 / tau
+    box = synth.config_sphere_fp64(10)
+    box.tau = tau
+    out = []
+    for mrt in (None, (gam,) * 4):
+        c = oif.Context.from_box(box, precision="fp64")
+        c.set_mrt(mrt)
+        c.step(10)
+        out.append((c.read_populations(), c.read_mesh(-1)[0]))
+        c.close()
+    dn = np.abs(out[0][0] - out[1][0]).max()
+    dx = np.abs(out[0][1] - out[1][1]).max()
+    say(f"   max |n_mrt - n_bgk| = {dn:.2e}, |X| {dx:.2e}")
+    assert dn < 1e-14 and dx < 1e-12
+
+
+def _deformed_sphere(orc, box, seed=21):
+    rng = np.random.default_rng(seed)
+    sysm = orc.System(box)
+    X0 = sysm.X + 0.012 * rng.standard_normal(sysm.X.shape)
+    V0 = 2e-4 * rng.standard_normal(sysm.X.shape)
+    n0 = synth.random_populations(rng, box, amp=2e-3)
+    sysm.X[:] = X0
+    sysm.V[:] = V0
+    sysm.n[:] = n0
+    return sysm, X0, V0, n0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mrt_coupled_sphere_vs_oracle(oif, orc, prec):
+    """Coupled step with the MRT collision: 20^3 box, 642-node sphere,
+    deformed moving start, random populations."""
+    say(f"[mrt] coupled sphere642 {prec}")
+    box = synth.config_sphere_fp64(20)
+    box.mrt = RATES["ghosts"]
+    sysm, X0, V0, n0 = _deformed_sphere(orc, box)
+    ctx = oif.Context.from_box(box, precision=prec)
+    ctx.write_mesh(-1, X0, V0)
+    ctx.write_populations(n0)
+    done = 0
+    for k in (1, 20):
+        ctx.step(k - done)
+        sysm.run(k - done)
+        done = k
+        res = check(gpu_fields(ctx, box.rho0, X0), oracle_fields(sysm, X0), prec, box.rho0, 20)
+        say(f"   step {k}: {fmt(res)}")
+        assert_ok(res, f"step {k}")
+    ctx.close()
+
+
+def test_mrt_obstacle_channel_vs_oracle(oif, orc):
+    """MRT collision with obstacles and a moving inlet (the obstacle kernel's
+    MRT variant), ten cells, FP64."""
+    say("[mrt] obstacle channel fp64")
+    box = synth.config_obstacle_channel(10, seed=6)
+    box.mrt = RATES["shear_bulk"]
+    sysm = orc.System(box)
+    X0 = sysm.X.copy()
+    ctx = oif.Context.from_box(box, precision="fp64")
+    ctx.step(10)
+    sysm.run(10)
+    res = check(gpu_fields(ctx, box.rho0, X0), oracle_fields(sysm, X0), "fp64", box.rho0, box.nx)
+    say(f"   step 10: {fmt(res)}")
+    assert_ok(res, "step 10")
+    ctx.close()
+
+
+def test_mrt_batch_matches_single_boxes(oif):
+    """A batch mixing BGK and MRT boxes (one lattice launch per variant)
+    equals the boxes stepped one by one, bit for bit."""
+    say("[mrt] batch of BGK and MRT boxes vs single")
+    boxes = synth.config_batch(n_boxes=3, steps=10)
+    boxes[1].mrt = RATES["ghosts"]
+    singles = []
+    for bx in boxes:
+        c = oif.Context.from_box(bx, precision="fp32")
+        c.step(10)
+        singles.append((c.read_populations(), c.read_mesh(-1)[0]))
+        c.close()
+    ctxs = [oif.Context.from_box(bx, precision="fp32") for bx in boxes]
+    B = oif.Batch(ctxs)
+    B.step(10)
+    for c, (n, X) in zip(ctxs, singles):
+        assert np.array_equal(c.read_populations(), n) and np.array_equal(c.read_mesh(-1)[0], X)
+    B.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_mrt_rejects_unstable_factors(oif):
+    c = oif.Context(8, 8, 8, precision="fp32")
+    for bad in ((1.0, 0, 0, 0), (0, -1.0, 0, 0), (0, 0, float("nan"), 0), (0, 0, 0, 1.5)):
+        with pytest.raises(oif.OifError):
+            c.set_mrt(bad)
+    c.set_mrt((0.1, 0.2, 0.3, 0.4))
+    c.set_mrt(None)
+    c.close()
