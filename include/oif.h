@@ -142,6 +142,7 @@ typedef struct {
     long long max_lds;  /* LDS bytes per workgroup available to the membrane kernel */
     int lds_objects;    /* objects whose mesh is staged in LDS (the rest use global scratch) */
     int overlap;        /* 1 if untouched nodes are updated concurrently with the membrane kernel */
+    int integrator;     /* OIF_INTEGRATOR_EULER or OIF_INTEGRATOR_VERLET */
 } oif_info_t;
 
 /* FP64 conservation diagnostics and watchdog state. */
@@ -285,6 +286,24 @@ int oif_set_graph(oif_ctx* ctx, int steps_per_graph);
  * kinematic viscosity is (1 + gamma[0]) / (6 (1 - gamma[0])), and all four
  * equal to 1 - 1/tau give the BGK operator.  gamma = NULL returns to BGK. */
 int oif_set_mrt(oif_ctx* ctx, const double* gamma);
+
+/* Mesh integrator (eq. newton, time step 1).  EULER (default): forces and
+ * drag from the positions and velocities at the start of the step, V += F/m,
+ * then X += V.  VERLET, the velocity Verlet scheme of the paper's engine:
+ * V_h = V + F_last/(2m), X += V_h, then membrane forces at the new positions,
+ * the drag xi (V_h - u) with u interpolated there, V = V_h + F/(2m); the total
+ * force F is carried into the next step (zero after switching integrators or
+ * adding objects).  Overlapped stepping supports EULER only (OIF_E_STATE). */
+#define OIF_INTEGRATOR_EULER 0
+#define OIF_INTEGRATOR_VERLET 1
+int oif_set_integrator(oif_ctx* ctx, int integrator);
+
+/* The force carried by the VERLET integrator (total force of the last step,
+ * 3 doubles per mesh node, object oid or -1 for all; zeros under EULER).
+ * Writing it (VERLET only, else OIF_E_STATE; finite values) completes a
+ * checkpoint restore together with oif_write_mesh and oif_write_populations. */
+int oif_read_force(oif_ctx* ctx, int oid, double* F);
+int oif_write_force(oif_ctx* ctx, int oid, const double* F);
 
 /* Overlap (default off): the lattice nodes inside any mesh node's 2x2x2
  * stencil are marked (by the membrane kernel of the previous step); the lattice

@@ -32,6 +32,10 @@ __host__ __device__ constexpr R wt(int i) {
     return i == 0 ? R(1) / R(3) : (i <= 6 ? R(1) / R(18) : R(1) / R(36));
 }
 
+// a * b + c with one rounding
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // storage forms: S = stored type, R = arithmetic type
 template <int P> struct Prec;
 template <> struct Prec<PREC_FP64> { typedef double S; typedef double R; };

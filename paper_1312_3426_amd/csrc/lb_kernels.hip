@@ -47,10 +47,6 @@ __device__ __forceinline__ void take_force(const BoxDev* __restrict__ B, int p, 
     }
 }
 
-// a * b + c with one rounding
-__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
 // e_i . a over the non-zero components of e_i only (i is a compile-time
 // constant once the loops are unrolled)
 template <typename R>

@@ -16,6 +16,11 @@
 //      update, and spreading of the reaction to the 8 nodes (int64 fixed-point
 //      atomics in the FP32 forms, FP64 atomics in the FP64 form) with the
 //      nodes' mask bits set.
+// With velocity Verlet (the integrator of the paper's engine) the staged
+// positions are first advanced by the half-step velocity V + F_last/(2m), the
+// forces and the drag are taken there (drag at the half-step velocity), and
+// the update is the second half kick; the total force is kept for the next
+// step.
 // Meshes whose arrays do not fit in LDS use a per-object global scratch area
 // with the same layout.
 #include <limits.h>
@@ -212,7 +217,14 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     __shared__ int bbox[6];
     __shared__ int ncomp;
 
-    for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x) xs[k] = gld(O.X + k);
+    // half-step velocity of velocity Verlet, V + F_last/(2m), one rounding
+    const R half_im = R(0.5) * O.inv_mass;
+    if (O.F) {
+        for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x)
+            xs[k] = gld(O.X + k) + (double)fmadd(gld(O.F + k), half_im, gld(O.V + k));
+    } else {
+        for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x) xs[k] = gld(O.X + k);
+    }
     if (threadIdx.x == 0) {
         bbox[0] = bbox[1] = bbox[2] = INT_MAX;
         bbox[3] = bbox[4] = bbox[5] = INT_MIN;
@@ -539,6 +551,11 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     for (int v = threadIdx.x; v < nv; v += blockDim.x) {
         const double px = xs[3 * v], py = xs[3 * v + 1], pz = xs[3 * v + 2];
         R vx = gld(O.V + 3 * v), vy = gld(O.V + 3 * v + 1), vz = gld(O.V + 3 * v + 2);
+        if (O.F) {  // the half-step velocity, as staged
+            vx = fmadd(gld(O.F + 3 * v), half_im, vx);
+            vy = fmadd(gld(O.F + 3 * v + 1), half_im, vy);
+            vz = fmadd(gld(O.F + 3 * v + 2), half_im, vz);
+        }
         R dgx = 0, dgy = 0, dgz = 0;
         if (sb[3 * v] != INT_MIN) {
             const double sx = px - 0.5, sy = py - 0.5, sz = pz - 0.5;
@@ -639,14 +656,29 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                 }
             }
         }
-        // eq. newton, symplectic Euler: kick with the total force, then drift
-        vx += (fs[3 * v] - dgx + O.fext[0]) * O.inv_mass;
-        vy += (fs[3 * v + 1] - dgy + O.fext[1]) * O.inv_mass;
-        vz += (fs[3 * v + 2] - dgz + O.fext[2]) * O.inv_mass;
+        // eq. newton.  Symplectic Euler: kick with the total force, then
+        // drift.  Velocity Verlet: the second half kick (the drift came
+        // first), the total force kept for the next step's first half kick.
+        const R ftx = fs[3 * v] - dgx + O.fext[0];
+        const R fty = fs[3 * v + 1] - dgy + O.fext[1];
+        const R ftz = fs[3 * v + 2] - dgz + O.fext[2];
+        if (O.F) {
+            vx += ftx * half_im;
+            vy += fty * half_im;
+            vz += ftz * half_im;
+            gst(O.F + 3 * v, ftx);
+            gst(O.F + 3 * v + 1, fty);
+            gst(O.F + 3 * v + 2, ftz);
+        } else {
+            vx += ftx * O.inv_mass;
+            vy += fty * O.inv_mass;
+            vz += ftz * O.inv_mass;
+        }
         gst(O.V + 3 * v, vx);
         gst(O.V + 3 * v + 1, vy);
         gst(O.V + 3 * v + 2, vz);
-        const double qx = px + (double)vx, qy = py + (double)vy, qz = pz + (double)vz;
+        const double qx = O.F ? px : px + (double)vx, qy = O.F ? py : py + (double)vy,
+                     qz = O.F ? pz : pz + (double)vz;
         gst(O.X + 3 * v, qx);
         gst(O.X + 3 * v + 1, qy);
         gst(O.X + 3 * v + 2, qz);

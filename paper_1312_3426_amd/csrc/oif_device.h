@@ -134,6 +134,9 @@ struct ObjDev {
     double* X;        // [nv][3] object-local positions (FP64 in every form)
     real* V;          // [nv][3]
     double* geo;      // [2]: total area, volume at the start of the last step
+    // velocity Verlet (null: symplectic Euler): the total force of the last
+    // step, [nv][3], carried into the first half kick of the next
+    real* F;
     int anchor[3];
     real inv_mass;
     real fext[3];

@@ -269,12 +269,14 @@ struct oif_ctx {
     std::vector<Object> obj;
     long long M = 0;
     std::vector<double> Xh, Vh; // host mesh state (absolute positions), valid when !host_stale
+    std::vector<double> Fh;     // velocity Verlet: the force carried into the next step
+    int integrator = 0;         // OIF_INTEGRATOR_EULER or OIF_INTEGRATOR_VERLET
     bool host_stale = false;
     bool mesh_dirty = true;     // device mesh arrays must be rebuilt
 
     // device mesh
     std::vector<DevBuf> tbufs;  // per-template arrays
-    DevBuf tmpl_dev, obj_dev, X_dev, V_dev, geo_dev, scratch_dev;
+    DevBuf tmpl_dev, obj_dev, X_dev, V_dev, F_dev, geo_dev, scratch_dev;
     std::vector<unsigned char> obj_host; // ObjDev<real> array as uploaded (sorted)
     int n_lds_obj = 0;          // objects [0, n_lds_obj) use LDS, the rest global scratch
     size_t lds_need = 0;
@@ -353,17 +355,22 @@ int pull_mesh(oif_ctx* c) {
         return OIF_OK;
     }
     const size_t n = 3 * (size_t)c->M;
-    std::vector<double> xl(n), vl(n);
+    const bool verlet = c->integrator == OIF_INTEGRATOR_VERLET && c->F_dev.p;
+    std::vector<double> xl(n), vl(n), fl(verlet ? n : 0);
     HIPCALL(c, hipMemcpyAsync(xl.data(), c->X_dev.p, n * 8, hipMemcpyDeviceToHost, c->stream));
     if (is_fp64(c)) {
         HIPCALL(c, hipMemcpyAsync(vl.data(), c->V_dev.p, n * 8, hipMemcpyDeviceToHost, c->stream));
+        if (verlet) HIPCALL(c, hipMemcpyAsync(fl.data(), c->F_dev.p, n * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCALL(c, hipStreamSynchronize(c->stream));
     } else {
-        std::vector<float> vf(n);
+        std::vector<float> vf(n), ff(verlet ? n : 0);
         HIPCALL(c, hipMemcpyAsync(vf.data(), c->V_dev.p, n * 4, hipMemcpyDeviceToHost, c->stream));
+        if (verlet) HIPCALL(c, hipMemcpyAsync(ff.data(), c->F_dev.p, n * 4, hipMemcpyDeviceToHost, c->stream));
         HIPCALL(c, hipStreamSynchronize(c->stream));
         for (size_t i = 0; i < n; ++i) vl[i] = vf[i];
+        for (size_t i = 0; i < ff.size(); ++i) fl[i] = ff[i];
     }
+    if (verlet) c->Fh = fl;
     for (const Object& o : c->obj)
         for (int v = 0; v < o.nv; ++v)
             for (int k = 0; k < 3; ++k) {
@@ -462,6 +469,14 @@ int upload_mesh_t(oif_ctx* c) {
             }
     if ((rc = dev_alloc(c, c->X_dev, n * sizeof(double)))) return rc;
     if ((rc = dev_alloc(c, c->V_dev, n * sizeof(real)))) return rc;
+    const bool verlet = c->integrator == OIF_INTEGRATOR_VERLET;
+    c->F_dev.release();
+    if (verlet) {
+        std::vector<real> fl(n);
+        for (size_t i = 0; i < n; ++i) fl[i] = (real)c->Fh[i];
+        if ((rc = dev_alloc(c, c->F_dev, n * sizeof(real)))) return rc;
+        if (n) HIPCALL(c, hipMemcpy(c->F_dev.p, fl.data(), n * sizeof(real), hipMemcpyHostToDevice));
+    }
     if ((rc = dev_alloc(c, c->geo_dev, 2 * sizeof(double) * (c->obj.size() + 1)))) return rc;
     HIPCALL(c, hipMemcpy(c->X_dev.p, xl.data(), n * sizeof(double), hipMemcpyHostToDevice));
     HIPCALL(c, hipMemcpy(c->V_dev.p, vl.data(), n * sizeof(real), hipMemcpyHostToDevice));
@@ -505,6 +520,7 @@ int upload_mesh_t(oif_ctx* c) {
         D.box = c->box_dev;
         D.X = (double*)c->X_dev.p + 3 * o.off;
         D.V = (real*)c->V_dev.p + 3 * o.off;
+        D.F = verlet ? (real*)c->F_dev.p + 3 * o.off : nullptr;
         D.geo = (double*)c->geo_dev.p + 2 * order[k];
         for (int a = 0; a < 3; ++a) {
             D.anchor[a] = o.anchor[a];
@@ -842,8 +858,8 @@ int oif_destroy(oif_ctx* c) {
                     (void*)c->status, (void*)c->box_dev, c->bt_dev, c->link_dev, c->wall_dev})
         if (p) (void)hipFree(p);
     for (auto& b : c->tbufs) b.release();
-    for (DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->geo_dev, &c->scratch_dev,
-                      &c->part_dev, &c->diag_out})
+    for (DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->F_dev, &c->geo_dev,
+                      &c->scratch_dev, &c->part_dev, &c->diag_out})
         b->release();
     if (c->own) (void)hipStreamDestroy(c->own);
     if (c->side) (void)hipStreamDestroy(c->side);
@@ -1062,6 +1078,7 @@ int oif_object_add(oif_ctx* c, int oid, int tid, const double origin[3], const d
     const double* R = rot ? rot : I;
     c->Xh.resize(3 * (size_t)(c->M + T.nv));
     c->Vh.resize(3 * (size_t)(c->M + T.nv), 0.0);
+    c->Fh.resize(3 * (size_t)(c->M + T.nv), 0.0);
     for (int v = 0; v < T.nv; ++v) {
         const double* p = &T.x[3 * v];
         for (int a = 0; a < 3; ++a)
@@ -1209,6 +1226,54 @@ int oif_set_graph(oif_ctx* c, int steps_per_graph) {
     return OIF_OK;
 }
 
+int oif_set_integrator(oif_ctx* c, int integrator) {
+    if (!c) return OIF_E_ARG;
+    if (integrator != OIF_INTEGRATOR_EULER && integrator != OIF_INTEGRATOR_VERLET)
+        return fail(c, OIF_E_ARG, "unknown integrator");
+    if (integrator == OIF_INTEGRATOR_VERLET && c->overlap)
+        return fail(c, OIF_E_STATE, "overlapped stepping supports the Euler integrator only");
+    int rc = pull_mesh(c);
+    if (rc) return rc;
+    if (integrator != c->integrator) std::fill(c->Fh.begin(), c->Fh.end(), 0.0);
+    c->integrator = integrator;
+    c->mesh_dirty = true;
+    drop_graph(c);
+    return OIF_OK;
+}
+
+int oif_read_force(oif_ctx* c, int oid, double* F) {
+    if (!c || !F) return OIF_E_ARG;
+    if (oid != -1) {
+        int rc = check_obj(c, oid);
+        if (rc) return rc;
+    }
+    int rc = pull_mesh(c);
+    if (rc) return rc;
+    const size_t off = oid < 0 ? 0 : 3 * (size_t)c->obj[oid].off;
+    const size_t n = oid < 0 ? 3 * (size_t)c->M : 3 * (size_t)c->obj[oid].nv;
+    if (n) std::memcpy(F, &c->Fh[off], n * sizeof(double));
+    return OIF_OK;
+}
+
+int oif_write_force(oif_ctx* c, int oid, const double* F) {
+    if (!c || !F) return OIF_E_ARG;
+    if (c->integrator != OIF_INTEGRATOR_VERLET)
+        return fail(c, OIF_E_STATE, "the carried force exists with the Verlet integrator only");
+    if (oid != -1) {
+        int rc = check_obj(c, oid);
+        if (rc) return rc;
+    }
+    int rc = pull_mesh(c);
+    if (rc) return rc;
+    const size_t off = oid < 0 ? 0 : 3 * (size_t)c->obj[oid].off;
+    const size_t n = oid < 0 ? 3 * (size_t)c->M : 3 * (size_t)c->obj[oid].nv;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(F[i])) return fail(c, OIF_E_ARG, "non-finite force");
+    std::memcpy(&c->Fh[off], F, n * sizeof(double));
+    c->mesh_dirty = true;
+    return OIF_OK;
+}
+
 int oif_set_mrt(oif_ctx* c, const double* gamma) {
     if (!c) return OIF_E_ARG;
     if (gamma)
@@ -1229,6 +1294,8 @@ int oif_set_mrt(oif_ctx* c, const double* gamma) {
 
 int oif_set_overlap(oif_ctx* c, int on) {
     if (!c) return OIF_E_ARG;
+    if (on && c->integrator == OIF_INTEGRATOR_VERLET)
+        return fail(c, OIF_E_STATE, "overlapped stepping supports the Euler integrator only");
     HIPCALL(c, hipStreamSynchronize(c->stream));
     HIPCALL(c, hipStreamSynchronize(c->side));
     c->overlap = on ? 1 : 0;
@@ -1350,7 +1417,8 @@ int oif_info(oif_ctx* c, oif_info_t* info) {
     info->steps_done = c->steps;
     long long bytes = 2 * 19LL * c->N * (long long)c->st_size + 24LL * c->N + 8LL * ((c->N + 63) / 64);
     for (auto& b : c->tbufs) bytes += (long long)b.n;
-    for (const DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->geo_dev, &c->scratch_dev})
+    for (const DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->F_dev, &c->geo_dev,
+                            &c->scratch_dev})
         bytes += (long long)b->n;
     info->device_bytes = bytes;
     info->lb_block = c->lb_block;
@@ -1360,6 +1428,7 @@ int oif_info(oif_ctx* c, oif_info_t* info) {
     info->max_lds = (long long)c->max_lds;
     info->overlap = c->overlap;
     info->lds_objects = c->n_lds_obj;
+    info->integrator = c->integrator;
     return OIF_OK;
 }
 
@@ -1511,7 +1580,7 @@ int time_steps(oif_ctx* c, int n, double* lb_ms, double* mesh_ms) {
 }
 
 struct Snapshot {
-    DevBuf f, x, v;
+    DevBuf f, x, v, F;
 };
 
 int snapshot(oif_ctx* c, Snapshot& s, bool restore) {
@@ -1523,22 +1592,26 @@ int snapshot(oif_ctx* c, Snapshot& s, bool restore) {
         if ((rc = dev_alloc(c, s.f, pb))) return rc;
         if (mb && (rc = dev_alloc(c, s.x, xb))) return rc;
         if (mb && (rc = dev_alloc(c, s.v, mb))) return rc;
+        if (mb && c->F_dev.p && (rc = dev_alloc(c, s.F, mb))) return rc;
         HIPCALL(c, hipMemcpyAsync(s.f.p, c->f[c->parity], pb, hipMemcpyDeviceToDevice, c->stream));
         if (mb) {
             HIPCALL(c, hipMemcpyAsync(s.x.p, c->X_dev.p, xb, hipMemcpyDeviceToDevice, c->stream));
             HIPCALL(c, hipMemcpyAsync(s.v.p, c->V_dev.p, mb, hipMemcpyDeviceToDevice, c->stream));
+            if (s.F.p) HIPCALL(c, hipMemcpyAsync(s.F.p, c->F_dev.p, mb, hipMemcpyDeviceToDevice, c->stream));
         }
     } else {
         HIPCALL(c, hipMemcpyAsync(c->f[c->parity], s.f.p, pb, hipMemcpyDeviceToDevice, c->stream));
         if (mb) {
             HIPCALL(c, hipMemcpyAsync(c->X_dev.p, s.x.p, xb, hipMemcpyDeviceToDevice, c->stream));
             HIPCALL(c, hipMemcpyAsync(c->V_dev.p, s.v.p, mb, hipMemcpyDeviceToDevice, c->stream));
+            if (s.F.p) HIPCALL(c, hipMemcpyAsync(c->F_dev.p, s.F.p, mb, hipMemcpyDeviceToDevice, c->stream));
         }
         HIPCALL(c, hipStreamSynchronize(c->stream));
         c->touch_valid = false;
         s.f.release();
         s.x.release();
         s.v.release();
+        s.F.release();
     }
     return OIF_OK;
 }

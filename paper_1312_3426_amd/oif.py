@@ -55,7 +55,8 @@ class Info(C.Structure):
                 ("walls_z", C.c_int), ("n_nodes", C.c_longlong), ("n_mesh_nodes", C.c_longlong),
                 ("steps_done", C.c_longlong), ("device_bytes", C.c_longlong), ("lb_block", C.c_int),
                 ("mesh_block", C.c_int), ("xcd_remap", C.c_int), ("graph_steps", C.c_int),
-                ("max_lds", C.c_longlong), ("lds_objects", C.c_int), ("overlap", C.c_int)]
+                ("max_lds", C.c_longlong), ("lds_objects", C.c_int), ("overlap", C.c_int),
+                ("integrator", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -92,6 +93,9 @@ SIGNATURES = {
     "oif_set_overlap": (_i, [_vp, _i]),
     "oif_set_launch": (_i, [_vp, _i, _i, _i]),
     "oif_set_mrt": (_i, [_vp, _vp]),
+    "oif_set_integrator": (_i, [_vp, _i]),
+    "oif_read_force": (_i, [_vp, _i, _vp]),
+    "oif_write_force": (_i, [_vp, _i, _vp]),
     "oif_autotune": (_i, [_vp, C.c_char_p]),
     "oif_read_populations": (_i, [_vp, _vp]),
     "oif_write_populations": (_i, [_vp, _vp]),
@@ -261,6 +265,23 @@ class Context:
             g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(4))
             self._chk(lib().oif_set_mrt(self.h, g.ctypes.data))
 
+    def set_integrator(self, name: str):
+        """Mesh integrator: "euler" (default) or "verlet"."""
+        code = {"euler": 0, "verlet": 1}[name]
+        self._chk(lib().oif_set_integrator(self.h, code))
+
+    def read_force(self, oid: int = -1) -> np.ndarray:
+        """Force carried into the next step by velocity Verlet, (n, 3)."""
+        n = self._nv(oid)
+        F = np.empty((n, 3))
+        self._chk(lib().oif_read_force(self.h, int(oid), F.ctypes.data))
+        return F
+
+    def write_force(self, oid: int, F) -> None:
+        n = self._nv(oid)
+        F = np.ascontiguousarray(np.broadcast_to(np.asarray(F, dtype=np.float64), (n, 3)))
+        self._chk(lib().oif_write_force(self.h, int(oid), F.ctypes.data))
+
     def set_overlap(self, on: bool):
         self._chk(lib().oif_set_overlap(self.h, int(bool(on))))
 
@@ -353,6 +374,8 @@ class Context:
                 friction=box.friction, walls_z=box.walls_z, precision=precision, **kw)
         if getattr(box, "mrt", None) is not None:
             c.set_mrt(box.mrt)
+        if getattr(box, "integrator", "euler") != "euler":
+            c.set_integrator(box.integrator)
         for bnd in getattr(box, "boundaries", []) or []:
             if bnd.kind == "rhomboid":
                 c.boundary_rhomboid(bnd.corner, bnd.a, bnd.b, bnd.c, bnd.velocity)

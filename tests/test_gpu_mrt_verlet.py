@@ -172,3 +172,102 @@ def test_mrt_rejects_unstable_factors(oif):
     c.set_mrt((0.1, 0.2, 0.3, 0.4))
     c.set_mrt(None)
     c.close()
+
+
+# ---------------------------------------------------------------------------
+# velocity Verlet
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,mrt", [("fp64", None), ("fp32", None), ("fp64", "ghosts")])
+def test_verlet_coupled_sphere_vs_oracle(oif, orc, prec, mrt):
+    """Velocity Verlet on the 20^3 sphere case from a deformed moving start:
+    fields and the carried force against the oracle (optionally with MRT)."""
+    say(f"[verlet] coupled sphere642 {prec} mrt={mrt}")
+    box = synth.config_sphere_fp64(20)
+    box.integrator = "verlet"
+    box.mrt = RATES[mrt] if mrt else None
+    sysm, X0, V0, n0 = _deformed_sphere(orc, box, seed=22)
+    ctx = oif.Context.from_box(box, precision=prec)
+    assert ctx.info().integrator == 1
+    ctx.write_mesh(-1, X0, V0)
+    ctx.write_populations(n0)
+    done = 0
+    for k in (1, 20):
+        ctx.step(k - done)
+        sysm.run(k - done)
+        done = k
+        g, o = gpu_fields(ctx, box.rho0, X0), oracle_fields(sysm, X0)
+        g["F"], o["F"] = ctx.read_force(-1), sysm.F
+        res = check(g, o, prec, box.rho0, 20)
+        fF = check(dict(V=g["F"]), dict(V=o["F"]), prec, box.rho0, 20, keys=("V",))
+        say(f"   step {k}: {fmt(res)}; F: {fmt(fF)}")
+        assert_ok(res, f"step {k}")
+        assert_ok(fF, f"force, step {k}")
+    ctx.close()
+
+
+def test_verlet_checkpoint_graph_and_batch_bitwise(oif):
+    """Verlet state = populations + positions + velocities + carried force:
+    restoring all four continues bit for bit; graph replay and a batch that
+    mixes Verlet and Euler boxes equal eager single-box stepping."""
+    say("[verlet] checkpoint / graph / batch, fp32 channel")
+    box = synth.config_channel_rbc(20)
+    box.integrator = "verlet"
+    a = oif.Context.from_box(box, precision="fp32")
+    a.step(5)
+    n, (X, V), F = a.read_populations(), a.read_mesh(-1), a.read_force(-1)
+    assert np.abs(F).max() > 0
+    b = oif.Context.from_box(box, precision="fp32")
+    b.write_populations(n)
+    b.write_mesh(-1, X, V)
+    b.write_force(-1, F)
+    a.step(7)
+    b.step(7)
+    assert np.array_equal(a.read_populations(), b.read_populations())
+    assert np.array_equal(a.read_mesh(-1)[0], b.read_mesh(-1)[0])
+    assert np.array_equal(a.read_force(-1), b.read_force(-1))
+    a.close()
+    b.close()
+    # graph replay vs eager
+    out = []
+    for graph in (0, 4):
+        c = oif.Context.from_box(box, precision="fp32")
+        c.set_graph(graph)
+        c.step(12)
+        out.append((c.read_populations(), c.read_mesh(-1)[0], c.read_force(-1)))
+        c.close()
+    assert all(np.array_equal(p, q) for p, q in zip(*out))
+    # batch mixing integrators
+    boxes = synth.config_batch(n_boxes=3, steps=10)
+    boxes[0].integrator = "verlet"
+    boxes[2].integrator = "verlet"
+    singles = []
+    for bx in boxes:
+        c = oif.Context.from_box(bx, precision="fp32")
+        c.step(10)
+        singles.append((c.read_populations(), c.read_mesh(-1)[0]))
+        c.close()
+    ctxs = [oif.Context.from_box(bx, precision="fp32") for bx in boxes]
+    B = oif.Batch(ctxs)
+    B.step(10)
+    for c, (n, X) in zip(ctxs, singles):
+        assert np.array_equal(c.read_populations(), n) and np.array_equal(c.read_mesh(-1)[0], X)
+    B.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_verlet_state_errors(oif):
+    box = synth.config_channel_rbc(1)
+    c = oif.Context.from_box(box, precision="fp32")
+    with pytest.raises(oif.OifError):
+        c.write_force(-1, np.zeros((box.n_mesh_nodes, 3)))  # Euler carries no force
+    c.set_overlap(True)
+    with pytest.raises(oif.OifError):
+        c.set_integrator("verlet")
+    c.set_overlap(False)
+    c.set_integrator("verlet")
+    with pytest.raises(oif.OifError):
+        c.set_overlap(True)
+    with pytest.raises(oif.OifError):
+        c.write_force(-1, np.full((box.n_mesh_nodes, 3), np.nan))
+    c.close()
