@@ -62,7 +62,39 @@ class _Mesh(C.Structure):
                 ("t_tri_off", C.c_void_p), ("tri", C.c_void_p), ("t_k", C.c_void_p),
                 ("t_linear", C.c_void_p), ("n_obj", C.c_int), ("o_tmpl", C.c_void_p),
                 ("o_node_off", C.c_void_p), ("o_mass", C.c_void_p), ("o_fext", C.c_void_p),
-                ("t_model", C.c_void_p), ("integrator", C.c_int)]
+                ("t_model", C.c_void_p), ("integrator", C.c_int), ("o_type", C.c_void_p),
+                ("n_pair", C.c_int), ("pair", C.c_void_p), ("n_wall", C.c_int), ("wall", C.c_void_p),
+                ("n_shape", C.c_int), ("shape", C.c_void_p)]
+
+
+class _SoftSphere(C.Structure):
+    _fields_ = [("type_a", C.c_int), ("type_b", C.c_int), ("a", C.c_double), ("n", C.c_double),
+                ("cutoff", C.c_double), ("offset", C.c_double)]
+
+
+class _Shape(C.Structure):
+    _fields_ = [("kind", C.c_int), ("corner", C.c_double * 3), ("a", C.c_double * 3), ("b", C.c_double * 3),
+                ("c", C.c_double * 3), ("normal", C.c_double * 3), ("dist", C.c_double)]
+
+
+def _shape(b) -> _Shape:
+    sh = _Shape()
+    sh.kind = 0 if b.kind == "rhomboid" else 1
+    for c in range(3):
+        sh.corner[c], sh.a[c], sh.b[c], sh.c[c] = b.corner[c], b.a[c], b.b[c], b.c[c]
+        sh.normal[c] = b.normal[c]
+    sh.dist = float(b.dist)
+    return sh
+
+
+def shape_distance(boundary, x) -> Optional[Tuple[float, np.ndarray]]:
+    """(distance, unit direction from the closest surface point) of a point
+    outside a boundary shape, None inside."""
+    sh = _shape(boundary)
+    d = C.c_double()
+    u = np.zeros(3)
+    ok = lib().orc_shape_distance(C.byref(sh), _p(_f64(x)), C.byref(d), _p(u))
+    return (d.value, u) if ok else None
 
 # force models (orc_membrane_forces)
 MODEL_PAPER = 0
@@ -136,6 +168,10 @@ def lib():
         L.orc_system_forces.argtypes = [vp, dp, dp]
         L.orc_system_touched.restype = C.c_long
         L.orc_system_touched.argtypes = [vp, dp]
+        L.orc_shape_distance.restype = C.c_int
+        L.orc_shape_distance.argtypes = [vp, dp, vp, dp]
+        L.orc_system_repulsion.restype = None
+        L.orc_system_repulsion.argtypes = [vp, dp, dp]
         L.orc_system_get_force.restype = None
         L.orc_system_get_force.argtypes = [vp, dp]
         L.orc_system_set_force.restype = None
@@ -478,6 +514,25 @@ class System:
         m.t_k, m.t_linear, m.t_model = _p(k["t_k"]), _p(k["t_lin"]), _p(k["t_mod"])
         m.n_obj = len(box.objects)
         m.integrator = VERLET if getattr(box, "integrator", "euler") == "verlet" else EULER
+        # soft-sphere repulsion
+        rep = list(getattr(box, "repulsion", []) or [])
+        pairs = [r for r in rep if r.type_b is not None]
+        walls = [r for r in rep if r.type_b is None]
+        PairArr = _SoftSphere * max(len(pairs), 1)
+        WallArr = _SoftSphere * max(len(walls), 1)
+        ShapeArr = _Shape * max(len(bnd), 1)
+        pa, wa, sa = PairArr(), WallArr(), ShapeArr()
+        for arr, lst in ((pa, pairs), (wa, walls)):
+            for i, r in enumerate(lst):
+                arr[i].type_a, arr[i].type_b = int(r.type_a), int(r.type_b if r.type_b is not None else -1)
+                arr[i].a, arr[i].n, arr[i].cutoff, arr[i].offset = float(r.a), float(r.n), float(r.cutoff), float(r.offset)
+        for i, b in enumerate(bnd):
+            sa[i] = _shape(b)
+        self._keep.update(o_type=_i32([getattr(o, "ptype", 0) for o in box.objects] or [0]), pa=pa, wa=wa, sa=sa)
+        m.o_type = _p(self._keep["o_type"])
+        m.n_pair, m.pair = len(pairs), C.addressof(pa)
+        m.n_wall, m.wall = len(walls), C.addressof(wa)
+        m.n_shape, m.shape = len(bnd), C.addressof(sa)
         m.o_tmpl, m.o_node_off, m.o_mass, m.o_fext = _p(k["o_t"]), _p(k["o_off"]), _p(k["o_m"]), _p(k["o_f"])
         self._mesh = m
         h = lib().orc_system_create(C.byref(L), C.byref(m), _p(k["t_off"]), _p(k["t_x"]))
@@ -487,7 +542,7 @@ class System:
         self.X = _f64(np.concatenate(X0)) if X0 else np.zeros((0, 3))
         self.V = np.zeros_like(self.X)
         self.n = equilibrium_populations(box.nx, box.ny, box.nz, box.rho0)
-        self.last_diag = np.zeros(10)
+        self.last_diag = np.zeros(13)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -496,7 +551,7 @@ class System:
             self._h = None
 
     def run(self, n_steps: int) -> None:
-        d = np.zeros(10)
+        d = np.zeros(13)
         Xp = self.X if self.M else np.zeros((1, 3))
         Vp = self.V if self.M else np.zeros((1, 3))
         rc = lib().orc_system_run(self._h, _p(self.n), _p(Xp), _p(Vp), int(n_steps), _p(d))
@@ -523,6 +578,12 @@ class System:
         Vo = np.zeros(max(no, 1))
         lib().orc_system_geometry(self._h, _p(self.X if self.M else np.zeros((1, 3))), _p(Sg), _p(Vo))
         return Sg[:no], Vo[:no]
+
+    def repulsion(self) -> np.ndarray:
+        """Soft-sphere forces on every mesh node at the current positions."""
+        F = np.zeros((max(self.M, 1), 3))
+        lib().orc_system_repulsion(self._h, _p(self.X if self.M else np.zeros((1, 3))), _p(F))
+        return F[:self.M]
 
     def forces(self) -> np.ndarray:
         F = np.zeros((max(self.M, 1), 3))

@@ -37,7 +37,13 @@
  *     inward), one third of it on each vertex; the volume is the
  *     divergence-theorem sum over signed tetrahedra;
  *   - global area: per triangle, along the same centroid-to-vertex unit vector
- *     as the local area force, scaled by the object-global ratio.
+ *     as the local area force, scaled by the object-global ratio;
+ *   - collisions (the repulsion the paper's scripts set between part types
+ *     and with the channel walls by name only): the soft-sphere potential
+ *     a (d - offset)^-n inside offset < d < offset + cutoff, between any two
+ *     distinct mesh nodes of interacting types (minimum-image distance) and
+ *     between a node and each obstacle shape (distance to the shape's
+ *     surface, no force on a node inside a shape).
  */
 #include "oif_oracle.h"
 
@@ -807,6 +813,12 @@ struct orc_system {
     double* Fel; /* [M][3] */
     double* Fprev; /* [M][3] total force of the last step (velocity Verlet) */
     int integrator;
+    double* Frep; /* [M][3] soft-sphere forces of the current step */
+    int* o_type;
+    int n_pair, n_wall, n_shape;
+    orc_soft_sphere* pair;
+    orc_soft_sphere* wall;
+    orc_shape* shape;
     double* G;   /* [3][N] */
     double* u;   /* [3][N] */
     double* rho; /* [N] */
@@ -832,6 +844,11 @@ void orc_system_destroy(orc_system* s) {
     free(s->o_fext);
     free(s->Fel);
     free(s->Fprev);
+    free(s->Frep);
+    free(s->o_type);
+    free(s->pair);
+    free(s->wall);
+    free(s->shape);
     free(s->G);
     free(s->u);
     free(s->rho);
@@ -889,6 +906,18 @@ orc_system* orc_system_create(const orc_lattice* L, const orc_mesh* m, const int
     s->Fel = (double*)calloc((size_t)(3 * s->M + 1), sizeof(double));
     s->Fprev = (double*)calloc((size_t)(3 * s->M + 1), sizeof(double));
     s->integrator = m->integrator;
+    s->Frep = (double*)calloc((size_t)(3 * s->M + 1), sizeof(double));
+    s->o_type = (int*)calloc((size_t)(m->n_obj + 1), sizeof(int));
+    for (int o = 0; o < m->n_obj; ++o) s->o_type[o] = m->o_type ? m->o_type[o] : 0;
+    s->n_pair = m->n_pair;
+    s->n_wall = m->n_wall;
+    s->n_shape = m->n_shape;
+    s->pair = (orc_soft_sphere*)calloc((size_t)(m->n_pair + 1), sizeof(orc_soft_sphere));
+    s->wall = (orc_soft_sphere*)calloc((size_t)(m->n_wall + 1), sizeof(orc_soft_sphere));
+    s->shape = (orc_shape*)calloc((size_t)(m->n_shape + 1), sizeof(orc_shape));
+    if (m->n_pair) memcpy(s->pair, m->pair, sizeof(orc_soft_sphere) * (size_t)m->n_pair);
+    if (m->n_wall) memcpy(s->wall, m->wall, sizeof(orc_soft_sphere) * (size_t)m->n_wall);
+    if (m->n_shape) memcpy(s->shape, m->shape, sizeof(orc_shape) * (size_t)m->n_shape);
     s->G = (double*)calloc((size_t)(3 * N), sizeof(double));
     s->u = (double*)calloc((size_t)(3 * N), sizeof(double));
     s->rho = (double*)calloc((size_t)N, sizeof(double));
@@ -911,6 +940,151 @@ void orc_system_forces(orc_system* s, const double* X, double* F) {
         orc_membrane_forces(T->nv, &X[off], T->nt, T->tri, T->ne, T->edge, T->hinge, T->L0,
                             T->theta0, T->S0, T->Sg0, T->V0, T->k, T->linear, T->model, T->hbar,
                             &F[off]);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Soft-sphere repulsion (the collisions the paper's scripts switch on)       */
+/* ------------------------------------------------------------------------- */
+static void soft_sphere_force(const orc_soft_sphere* ss, double d, const double* dir, double* F) {
+    /* force a n (d - offset)^-(n+1) along dir inside the interaction range */
+    double e = d - ss->offset;
+    if (!(e > 0.0 && e < ss->cutoff)) return;
+    double f = ss->a * ss->n * pow(e, -(ss->n + 1.0));
+    for (int c = 0; c < 3; ++c) F[c] += f * dir[c];
+}
+
+static void consider(const double* x, const double* p, double* best, double* bp) {
+    double r[3];
+    sub3(x, p, r);
+    double d = norm3(r);
+    if (d < *best) {
+        *best = d;
+        for (int c = 0; c < 3; ++c) bp[c] = p[c];
+    }
+}
+
+int orc_shape_distance(const orc_shape* sh, const double* x, double* dist, double* dir) {
+    if (sh->kind == 1) {  /* half-space n.x < dist is solid */
+        double len = norm3(sh->normal);
+        double d = dot3(x, sh->normal) / len - sh->dist;
+        if (!(d > 0.0)) return 0;
+        *dist = d;
+        for (int c = 0; c < 3; ++c) dir[c] = sh->normal[c] / len;
+        return 1;
+    }
+    /* rhomboid: inside when all three Cramer coordinates lie in [0, 1] */
+    const double* E[3] = {sh->a, sh->b, sh->c};
+    double r[3], bc[3], ca[3], ab[3];
+    sub3(x, sh->corner, r);
+    cross3(sh->b, sh->c, bc);
+    cross3(sh->c, sh->a, ca);
+    cross3(sh->a, sh->b, ab);
+    double det = dot3(sh->a, bc);
+    double st[3] = {dot3(r, bc) / det, dot3(r, ca) / det, dot3(r, ab) / det};
+    if (st[0] >= 0.0 && st[0] <= 1.0 && st[1] >= 0.0 && st[1] <= 1.0 && st[2] >= 0.0 && st[2] <= 1.0)
+        return 0;
+    /* closest surface point: the best of the face interiors, the edges and the
+     * corners (the closest point of a convex body is one of them) */
+    double best = INFINITY, bp[3] = {0, 0, 0}, p[3];
+    for (int k = 0; k < 3; ++k) {          /* faces with coordinate k fixed */
+        const double* u = E[(k + 1) % 3];
+        const double* v = E[(k + 2) % 3];
+        for (int side = 0; side < 2; ++side) {
+            double o[3], q[3];
+            for (int c = 0; c < 3; ++c) o[c] = sh->corner[c] + side * E[k][c];
+            sub3(x, o, q);
+            double uu = dot3(u, u), uv = dot3(u, v), vv = dot3(v, v);
+            double qu = dot3(q, u), qv = dot3(q, v);
+            double den = uu * vv - uv * uv;
+            double su = (qu * vv - qv * uv) / den, sv = (qv * uu - qu * uv) / den;
+            if (su >= 0.0 && su <= 1.0 && sv >= 0.0 && sv <= 1.0) {
+                for (int c = 0; c < 3; ++c) p[c] = o[c] + su * u[c] + sv * v[c];
+                consider(x, p, &best, bp);
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k)            /* edges along E[k] */
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                const double* u = E[(k + 1) % 3];
+                const double* v = E[(k + 2) % 3];
+                double o[3], q[3];
+                for (int c = 0; c < 3; ++c) o[c] = sh->corner[c] + i * u[c] + j * v[c];
+                sub3(x, o, q);
+                double t = dot3(q, E[k]) / dot3(E[k], E[k]);
+                t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+                for (int c = 0; c < 3; ++c) p[c] = o[c] + t * E[k][c];
+                consider(x, p, &best, bp);
+            }
+    *dist = best;
+    double rr[3];
+    sub3(x, bp, rr);
+    for (int c = 0; c < 3; ++c) dir[c] = rr[c] / best;
+    return 1;
+}
+
+static const orc_soft_sphere* pair_of(const orc_system* s, int ta, int tb) {
+    for (int k = 0; k < s->n_pair; ++k)
+        if ((s->pair[k].type_a == ta && s->pair[k].type_b == tb) ||
+            (s->pair[k].type_a == tb && s->pair[k].type_b == ta))
+            return &s->pair[k];
+    return NULL;
+}
+
+void orc_system_repulsion(orc_system* s, const double* X, double* F) {
+    const orc_lattice* L = &s->L;
+    double box[3] = {L->nx, L->ny, L->nz};
+    int periodic[3] = {1, 1, !L->walls_z};
+    /* node pairs (each unordered pair once) */
+    for (int o1 = 0; o1 < s->n_obj; ++o1)
+        for (int o2 = o1; o2 < s->n_obj; ++o2) {
+            const orc_soft_sphere* ss = pair_of(s, s->o_type[o1], s->o_type[o2]);
+            if (!ss) continue;
+            int n1 = s->t[s->o_tmpl[o1]].nv, n2 = s->t[s->o_tmpl[o2]].nv;
+            for (int v1 = 0; v1 < n1; ++v1)
+                for (int v2 = (o1 == o2 ? v1 + 1 : 0); v2 < n2; ++v2) {
+                    long j = (long)s->o_off[o1] + v1, k = (long)s->o_off[o2] + v2;
+                    double r[3];
+                    for (int c = 0; c < 3; ++c) {
+                        r[c] = X[3 * j + c] - X[3 * k + c];
+                        if (periodic[c]) r[c] -= box[c] * floor(r[c] / box[c] + 0.5);
+                    }
+                    double d = norm3(r);
+                    if (!(d > ss->offset && d < ss->offset + ss->cutoff)) continue;
+                    double dir[3] = {r[0] / d, r[1] / d, r[2] / d}, f[3] = {0, 0, 0};
+                    soft_sphere_force(ss, d, dir, f);
+                    for (int c = 0; c < 3; ++c) {
+                        F[3 * j + c] += f[c];
+                        F[3 * k + c] -= f[c];
+                    }
+                }
+        }
+    /* walls: every obstacle shape at the node's position in the box, and the
+     * built-in walls z = 0 and z = nz */
+    for (int o = 0; o < s->n_obj; ++o) {
+        const orc_soft_sphere* ss = NULL;
+        for (int k = 0; k < s->n_wall; ++k)
+            if (s->wall[k].type_a == s->o_type[o]) ss = &s->wall[k];
+        if (!ss) continue;
+        int nv = s->t[s->o_tmpl[o]].nv;
+        for (int v = 0; v < nv; ++v) {
+            long j = (long)s->o_off[o] + v;
+            double x[3];
+            for (int c = 0; c < 3; ++c) {
+                x[c] = X[3 * j + c];
+                if (periodic[c]) x[c] -= box[c] * floor(x[c] / box[c]);
+            }
+            for (int k = 0; k < s->n_shape; ++k) {
+                double d, dir[3];
+                if (orc_shape_distance(&s->shape[k], x, &d, dir)) soft_sphere_force(ss, d, dir, &F[3 * j]);
+            }
+            if (L->walls_z) {
+                double up[3] = {0, 0, 1}, down[3] = {0, 0, -1};
+                if (x[2] > 0.0) soft_sphere_force(ss, x[2], up, &F[3 * j]);
+                if (x[2] < L->nz) soft_sphere_force(ss, L->nz - x[2], down, &F[3 * j]);
+            }
+        }
     }
 }
 
@@ -944,8 +1118,9 @@ int orc_system_run(orc_system* s, double* n, double* X, double* V, int n_steps, 
     const orc_lattice* L = &s->L;
     long N = (long)L->nx * L->ny * L->nz;
     int verlet = s->integrator == ORC_VERLET;
+    int repulsion = s->n_pair > 0 || s->n_wall > 0;
     for (int step = 0; step < n_steps; ++step) {
-        double d[10] = {0};
+        double d[13] = {0};
         /* a non-finite mesh state has no stencil: stop instead of indexing */
         for (long j = 0; j < 3 * s->M; ++j)
             if (!isfinite(X[j]) || !isfinite(V[j]) || fabs(X[j]) > 1e9) return -1 - step;
@@ -967,6 +1142,8 @@ int orc_system_run(orc_system* s, double* n, double* X, double* V, int n_steps, 
         /* 1-2: geometry and membrane forces from the current positions (step
          * start; after the drift with velocity Verlet) */
         orc_system_forces(s, X, s->Fel);
+        memset(s->Frep, 0, sizeof(double) * 3 * (size_t)s->M);
+        if (repulsion) orc_system_repulsion(s, X, s->Frep);
         /* 3: coupling.  Node velocity from the populations at step start,
          * with half the body force only. */
         orc_moments(L, n, NULL, s->rho, s->u);
@@ -981,7 +1158,7 @@ int orc_system_run(orc_system* s, double* n, double* X, double* V, int n_steps, 
                 /* 4: mesh update: kick then drift (Euler) or the second half
                  * kick (velocity Verlet) */
                 for (int c = 0; c < 3; ++c) {
-                    double Ft = s->Fel[3 * j + c] - drag[c] + s->o_fext[3 * o + c];
+                    double Ft = s->Fel[3 * j + c] - drag[c] + s->o_fext[3 * o + c] + s->Frep[3 * j + c];
                     if (verlet) {
                         V[3 * j + c] += 0.5 * Ft / m;
                         s->Fprev[3 * j + c] = Ft;
@@ -992,6 +1169,7 @@ int orc_system_run(orc_system* s, double* n, double* X, double* V, int n_steps, 
                     d[1 + c] += s->Fel[3 * j + c];
                     d[4 + c] += -drag[c];
                     d[7 + c] += s->o_fext[3 * o + c];
+                    d[10 + c] += s->Frep[3 * j + c];
                 }
             }
         }

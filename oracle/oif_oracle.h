@@ -162,7 +162,42 @@ typedef struct {
     const double* o_fext;   /* [n_obj][3] */
     const int* t_model;     /* per template ORC_MODEL_*, or NULL for all PAPER */
     int integrator;         /* ORC_EULER or ORC_VERLET (all objects) */
+    /* soft-sphere repulsion (may be empty): part type per object, pair
+     * interactions between mesh nodes of two types, and interactions of the
+     * nodes of a type with every obstacle shape and the built-in z walls */
+    const int* o_type;
+    int n_pair;
+    const struct orc_soft_sphere* pair;
+    int n_wall;
+    const struct orc_soft_sphere* wall;
+    int n_shape;
+    const struct orc_shape* shape;
 } orc_mesh;
+
+/* Soft-sphere interaction (the repulsion of the paper's scripts, "inter
+ * type_a type_b soft-sphere a n cutoff offset"): V(d) = a (d - offset)^-n for
+ * offset < d < offset + cutoff, zero beyond; the force a n (d - offset)^-(n+1)
+ * pushes the two partners apart along the line joining them (for a wall:
+ * along the line from the closest surface point).  Wall entries use type_a
+ * only. */
+typedef struct orc_soft_sphere {
+    int type_a, type_b;
+    double a, n, cutoff, offset;
+} orc_soft_sphere;
+
+/* Obstacle shapes for the wall repulsion: kind 0 = rhomboid {corner + s a +
+ * t b + u c, s, t, u in [0, 1]}, kind 1 = wall, the half-space
+ * normal . x < dist. */
+typedef struct orc_shape {
+    int kind;
+    double corner[3], a[3], b[3], c[3];
+    double normal[3], dist;
+} orc_shape;
+
+/* Distance from x to a shape's surface and the unit vector from the closest
+ * surface point to x; returns 0 if x lies inside (or on) the shape. */
+int orc_shape_distance(const orc_shape* sh, const double* x, double* dist, double* dir);
+
 
 /* Mesh integrators (dt = 1).  EULER: forces from X_t, V_t; V += F/m, then
  * X += V.  VERLET (velocity Verlet, as in the paper's engine): V_h = V_t +
@@ -184,7 +219,8 @@ void orc_system_destroy(orc_system* s);
 /* Advance n_steps coupled steps.  n: populations (19*N) in/out; X, V: mesh
  * positions/velocities (3*M) in/out.  diag (may be NULL) receives, for the LAST
  * step: [0] clamped stencil corners, [1..3] sum of elastic forces,
- * [4..6] sum of coupling forces on the mesh, [7..9] sum of external forces. */
+ * [4..6] sum of coupling forces on the mesh, [7..9] sum of external forces,
+ * [10..12] sum of soft-sphere forces (13 doubles). */
 int orc_system_run(orc_system* s, double* n, double* X, double* V, int n_steps, double* diag);
 
 /* The total force of the last step on every mesh node (3*M): the force the
@@ -198,6 +234,12 @@ void orc_system_geometry(orc_system* s, const double* X, double* Sg, double* Vol
 
 /* Elastic forces of all objects at positions X (overwrites F[3*M]). */
 void orc_system_forces(orc_system* s, const double* X, double* F);
+
+/* Soft-sphere forces on all mesh nodes at positions X (3*M), ADDED to F:
+ * pairs of distinct nodes whose types interact (minimum-image distance in
+ * the periodic directions), and the wall interactions (obstacle shapes at
+ * their positions in the box, the planes z = 0 and z = nz with walls_z). */
+void orc_system_repulsion(orc_system* s, const double* X, double* F);
 
 /* Number of distinct lattice nodes inside any mesh node's 2x2x2 stencil. */
 long orc_system_touched(orc_system* s, const double* X);

@@ -259,6 +259,20 @@ class ObjectSpec:
     rot: Optional[np.ndarray] = None   # (3, 3) or None for identity
     mass: float = 1.0
     fext: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    ptype: int = 0                     # part type (selects repulsion partners)
+
+
+@dataclasses.dataclass
+class SoftSphere:
+    """Soft-sphere repulsion a (d - offset)^-n for offset < d < offset + cutoff
+    between mesh nodes of part types type_a and type_b, or (type_b = None)
+    between nodes of type_a and every obstacle shape / z wall."""
+    type_a: int
+    type_b: Optional[int]
+    a: float
+    n: float
+    cutoff: float
+    offset: float = 0.0
 
 
 @dataclasses.dataclass
@@ -296,6 +310,7 @@ class Box:
     # (gamma_shear, gamma_bulk, gamma_odd, gamma_even)
     mrt: Optional[Tuple[float, float, float, float]] = None
     integrator: str = "euler"  # mesh integrator: "euler" or "verlet"
+    repulsion: List["SoftSphere"] = dataclasses.field(default_factory=list)
 
     @property
     def n_nodes(self) -> int:

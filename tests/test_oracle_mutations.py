@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oif_oracle.c")
 PIN_FILES = ["tests/test_oracle_mesh.py", "tests/test_oracle_lb.py", "tests/test_oracle_coupling.py",
              "tests/test_oracle_conservative.py", "tests/test_oracle_boundaries.py",
-             "tests/test_oracle_mrt_verlet.py"]
+             "tests/test_oracle_mrt_verlet.py", "tests/test_oracle_repulsion.py"]
 
 MUTATIONS = {
     "kappa_exponent": ("(lambda + pow(lambda, -3.0))", "(lambda + pow(lambda, -2.0))"),
@@ -90,6 +90,16 @@ MUTATIONS = {
                                "V[3 * j + c] += s->Fprev[3 * j + c] / m;"),
     "verlet_force_not_carried": ("s->Fprev[3 * j + c] = Ft;", "s->Fprev[3 * j + c] = 0.0;"),
     "verlet_full_second_kick": ("V[3 * j + c] += 0.5 * Ft / m;", "V[3 * j + c] += Ft / m;"),
+    "soft_sphere_exponent": ("pow(e, -(ss->n + 1.0))", "pow(e, -ss->n)"),
+    "soft_sphere_offset_ignored": ("double e = d - ss->offset;", "double e = d;"),
+    "pair_no_minimum_image": ("if (periodic[c]) r[c] -= box[c] * floor(r[c] / box[c] + 0.5);",
+                              "if (0) r[c] -= box[c] * floor(r[c] / box[c] + 0.5);"),
+    "pair_third_law": ("F[3 * k + c] -= f[c];", "F[3 * k + c] += f[c];"),
+    "rhomboid_edges_skipped": ("for (int k = 0; k < 3; ++k)            /* edges along E[k] */",
+                               "for (int k = 0; k < 0; ++k)            /* edges along E[k] */"),
+    "zwall_direction": ("double up[3] = {0, 0, 1}, down[3] = {0, 0, -1};",
+                        "double up[3] = {0, 0, -1}, down[3] = {0, 0, 1};"),
+    "repulsion_not_applied": (" + s->o_fext[3 * o + c] + s->Frep[3 * j + c];", " + s->o_fext[3 * o + c];"),
 }
 
 
