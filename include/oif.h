@@ -237,8 +237,9 @@ int oif_template_create(oif_ctx* ctx, int tid, const double* nodes, int nv, cons
 
 /* Add object oid made from template tid (adding objects of the paper):
  * node positions = origin + R x_template, R = rot (row-major 3x3, NULL =
- * identity).  mass <= 0 means the default 1.  part_type is stored and
- * reported only.  Objects start at rest.  Errors: OIF_E_ARG, OIF_E_ID. */
+ * identity).  mass <= 0 means the default 1.  part_type (0..15, the part-type
+ * of the paper's object command) selects the soft-sphere interactions of the
+ * object's nodes.  Objects start at rest.  Errors: OIF_E_ARG, OIF_E_ID. */
 int oif_object_add(oif_ctx* ctx, int oid, int tid, const double origin[3], const double rot[9],
                    double mass, int part_type);
 
@@ -286,6 +287,28 @@ int oif_set_graph(oif_ctx* ctx, int steps_per_graph);
  * kinematic viscosity is (1 + gamma[0]) / (6 (1 - gamma[0])), and all four
  * equal to 1 - 1/tau give the BGK operator.  gamma = NULL returns to BGK. */
 int oif_set_mrt(oif_ctx* ctx, const double* gamma);
+
+/* Soft-sphere repulsion, the object-object and object-wall collisions of the
+ * paper's channel script ("inter type_a type_b soft-sphere a n cutoff
+ * offset"): V(d) = a (d - offset)^-n for offset < d < offset + cutoff, zero
+ * beyond, the force a n (d - offset)^-(n+1) pushing the partners apart.
+ * oif_set_soft_sphere acts between any two distinct mesh nodes of part types
+ * type_a and type_b (symmetric; the same type also within one object), at
+ * the minimum-image distance in the periodic directions; every periodic box
+ * length must be at least 2 (cutoff + offset).  oif_set_wall_soft_sphere acts
+ * between the nodes of a part type and each obstacle shape (distance from the
+ * node, wrapped into the box, to the shape's surface; no force on a node
+ * inside a shape) and the walls z = 0 and z = nz when they are on.  The
+ * forces are taken where the membrane forces are (step start, or after the
+ * first half kick and drift with velocity Verlet) and added to each node's
+ * total force; found through cell lists of the mesh nodes, summed in FP64 in
+ * a fixed order.  a = 0 removes an interaction.  Types 0..15; a >= 0,
+ * n > 0, cutoff > 0, offset >= 0, finite (OIF_E_ARG otherwise).  The
+ * parameters are in lattice units (the paper's script values are in its own
+ * units with time step 0.1). */
+int oif_set_soft_sphere(oif_ctx* ctx, int type_a, int type_b, double a, double n, double cutoff,
+                        double offset);
+int oif_set_wall_soft_sphere(oif_ctx* ctx, int type, double a, double n, double cutoff, double offset);
 
 /* Mesh integrator (eq. newton, time step 1).  EULER (default): forces and
  * drag from the positions and velocities at the start of the step, V += F/m,

@@ -1024,12 +1024,14 @@ int orc_shape_distance(const orc_shape* sh, const double* x, double* dist, doubl
     return 1;
 }
 
+/* the interaction of two types: the last entry that names them */
 static const orc_soft_sphere* pair_of(const orc_system* s, int ta, int tb) {
+    const orc_soft_sphere* r = NULL;
     for (int k = 0; k < s->n_pair; ++k)
         if ((s->pair[k].type_a == ta && s->pair[k].type_b == tb) ||
             (s->pair[k].type_a == tb && s->pair[k].type_b == ta))
-            return &s->pair[k];
-    return NULL;
+            r = &s->pair[k];
+    return r;
 }
 
 void orc_system_repulsion(orc_system* s, const double* X, double* F) {

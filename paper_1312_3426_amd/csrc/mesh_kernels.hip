@@ -659,9 +659,15 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
         // eq. newton.  Symplectic Euler: kick with the total force, then
         // drift.  Velocity Verlet: the second half kick (the drift came
         // first), the total force kept for the next step's first half kick.
-        const R ftx = fs[3 * v] - dgx + O.fext[0];
-        const R fty = fs[3 * v + 1] - dgy + O.fext[1];
-        const R ftz = fs[3 * v + 2] - dgz + O.fext[2];
+        R rx = 0, ry = 0, rz = 0;  // soft-sphere repulsion of this step
+        if (O.frep) {
+            rx = gld(O.frep + 3 * v);
+            ry = gld(O.frep + 3 * v + 1);
+            rz = gld(O.frep + 3 * v + 2);
+        }
+        const R ftx = fs[3 * v] - dgx + O.fext[0] + rx;
+        const R fty = fs[3 * v + 1] - dgy + O.fext[1] + ry;
+        const R ftz = fs[3 * v + 2] - dgz + O.fext[2] + rz;
         if (O.F) {
             vx += ftx * half_im;
             vy += fty * half_im;

@@ -137,11 +137,53 @@ struct ObjDev {
     // velocity Verlet (null: symplectic Euler): the total force of the last
     // step, [nv][3], carried into the first half kick of the next
     real* F;
+    // soft-sphere repulsion (null: none): this step's force on each node,
+    // [nv][3], computed before the membrane kernel and added to the total
+    const real* frep;
+    int node0;        // index of the object's first node among all mesh nodes
     int anchor[3];
     real inv_mass;
     real fext[3];
     double mass;
     unsigned char* scratch; // global stand-in for LDS when the mesh does not fit
+};
+
+// ---- soft-sphere repulsion ---------------------------------------------------
+// a (d - offset)^-n for offset < d < offset + cutoff; a == 0: no interaction
+struct SoftSphereDev {
+    double a, n, cutoff, offset;
+};
+// Obstacle shape for the wall repulsion.  kind 0: rhomboid corner + s a + t b
+// + u c (s, t, u in [0, 1]); kind 1: half-space n.x < dist (n unit).
+struct ShapeDev {
+    int kind;
+    double corner[3], e[3][3];  // rhomboid corner and edge vectors a, b, c
+    double cof[3][3], det;      // b x c, c x a, a x b and a . (b x c)
+    double n[3], dist;          // half-space
+};
+constexpr int REP_TYPES = 16;   // part types 0 .. 15
+// Cell lists of one box: mesh nodes binned into cells of at least the largest
+// pair range, the cells hashed into H buckets (H a power of two, identity when
+// every cell has its own bucket); per bucket the node ids in ascending order.
+struct RepDev {
+    int M;
+    int H, log2H, direct;
+    int nc[3];
+    double hc[3];               // cell edge per axis (>= the pair range)
+    double L[3];
+    int walls_z, pairs;         // pairs: some pair interaction is set
+    SoftSphereDev pair[REP_TYPES][REP_TYPES];
+    SoftSphereDev wall[REP_TYPES];
+    int n_shape;
+    const ShapeDev* shape;
+    const unsigned char* type;  // [M] part type per node
+    double* pos;                // [M][3] positions the forces are taken at
+    int* cell;                  // [M] cell id
+    int* cnt;                   // [H + 1] nodes per bucket, then bucket starts
+    int* cursor;                // [H]
+    int* bsum;                  // block sums of the scan
+    int* list;                  // [M] node ids by bucket
+    void* frep;                 // [M][3] force, arithmetic type
 };
 
 // ---- launchers (kernels.hip) ----------------------------------------------
@@ -185,6 +227,11 @@ struct MeshLaunch {
     hipStream_t stream;
 };
 hipError_t launch_mesh(const MeshLaunch& L);
+
+// Soft-sphere forces of one box into rep->frep (host copy `h` of the device
+// descriptor `d` gives the sizes): bin, scan, scatter, order, force.
+hipError_t launch_repulsion(const RepDev& h, const RepDev* d, const void* objs, int nobj, int precision,
+                            hipStream_t s);
 
 // Per-template LDS bytes of the mesh kernel.
 size_t mesh_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap, int cons);

@@ -271,6 +271,13 @@ struct oif_ctx {
     std::vector<double> Xh, Vh; // host mesh state (absolute positions), valid when !host_stale
     std::vector<double> Fh;     // velocity Verlet: the force carried into the next step
     int integrator = 0;         // OIF_INTEGRATOR_EULER or OIF_INTEGRATOR_VERLET
+    // soft-sphere repulsion: interaction tables, obstacle shapes, cell lists
+    SoftSphereDev rep_pair[REP_TYPES][REP_TYPES] = {};
+    SoftSphereDev rep_wall[REP_TYPES] = {};
+    std::vector<ShapeDev> shapes;
+    bool rep_on = false;
+    RepDev rep_h{};
+    DevBuf rep_desc, rep_pos, rep_cell, rep_cnt, rep_cursor, rep_bsum, rep_list, rep_frep, rep_type, rep_shape;
     bool host_stale = false;
     bool mesh_dirty = true;     // device mesh arrays must be rebuilt
 
@@ -379,6 +386,83 @@ int pull_mesh(oif_ctx* c) {
                 c->Vh[i] = vl[i];
             }
     c->host_stale = false;
+    return OIF_OK;
+}
+
+// Cell lists and force buffer of the soft-sphere repulsion (when some
+// interaction is set and the box holds mesh nodes): cells of at least the
+// largest pair range per axis, hashed into a power-of-two number of buckets
+// (about two per mesh node; one per cell when the cells are fewer).
+int setup_repulsion(oif_ctx* c, size_t real_bytes) {
+    bool pairs = false, walls = false;
+    double rc = 0.0;
+    for (int a = 0; a < REP_TYPES; ++a) {
+        walls = walls || c->rep_wall[a].a > 0.0;
+        for (int b = 0; b < REP_TYPES; ++b)
+            if (c->rep_pair[a][b].a > 0.0) {
+                pairs = true;
+                rc = std::max(rc, c->rep_pair[a][b].cutoff + c->rep_pair[a][b].offset);
+            }
+    }
+    c->rep_on = (pairs || walls) && c->M > 0;
+    for (DevBuf* b : {&c->rep_desc, &c->rep_pos, &c->rep_cell, &c->rep_cnt, &c->rep_cursor, &c->rep_bsum,
+                      &c->rep_list, &c->rep_frep, &c->rep_type, &c->rep_shape})
+        b->release();
+    if (!c->rep_on) return OIF_OK;
+    RepDev& R = c->rep_h;
+    R = RepDev{};
+    R.M = (int)c->M;
+    R.walls_z = c->d.walls_z ? 1 : 0;
+    R.pairs = pairs ? 1 : 0;
+    const int dims[3] = {c->d.nx, c->d.ny, c->d.nz};
+    long long ncells = 1;
+    for (int a = 0; a < 3; ++a) {
+        R.L[a] = dims[a];
+        R.nc[a] = pairs ? std::max(1, (int)std::floor(dims[a] / rc)) : 1;
+    }
+    // keep the cell count in int range: coarser cells are still correct
+    for (;;) {
+        ncells = (long long)R.nc[0] * R.nc[1] * R.nc[2];
+        if (ncells <= (1LL << 30)) break;
+        int big = 0;
+        for (int a = 1; a < 3; ++a)
+            if (R.nc[a] > R.nc[big]) big = a;
+        R.nc[big] = std::max(1, R.nc[big] / 2);
+    }
+    for (int a = 0; a < 3; ++a) R.hc[a] = R.L[a] / R.nc[a];
+    R.log2H = 10;
+    while ((1LL << R.log2H) < 2LL * c->M) ++R.log2H;
+    R.H = 1 << R.log2H;
+    R.direct = ncells <= R.H ? 1 : 0;
+    std::memcpy(R.pair, c->rep_pair, sizeof(R.pair));
+    std::memcpy(R.wall, c->rep_wall, sizeof(R.wall));
+    const size_t M = c->M;
+    int rc_ = 0;
+    if ((rc_ = dev_alloc(c, c->rep_pos, 3 * M * sizeof(double))) || (rc_ = dev_alloc(c, c->rep_cell, M * 4)) ||
+        (rc_ = dev_alloc(c, c->rep_cnt, ((size_t)R.H + 1) * 4)) || (rc_ = dev_alloc(c, c->rep_cursor, (size_t)R.H * 4)) ||
+        (rc_ = dev_alloc(c, c->rep_bsum, ((size_t)R.H / 1024 + 1) * 4)) || (rc_ = dev_alloc(c, c->rep_list, M * 4)) ||
+        (rc_ = dev_alloc(c, c->rep_frep, 3 * M * real_bytes)) || (rc_ = dev_alloc(c, c->rep_type, M)) ||
+        (rc_ = dev_alloc(c, c->rep_shape, (c->shapes.size() + 1) * sizeof(ShapeDev))) ||
+        (rc_ = dev_alloc(c, c->rep_desc, sizeof(RepDev))))
+        return rc_;
+    std::vector<unsigned char> types(M);
+    for (const Object& o : c->obj)
+        for (int v = 0; v < o.nv; ++v) types[(size_t)o.off + v] = (unsigned char)o.ptype;
+    HIPCALL(c, hipMemcpy(c->rep_type.p, types.data(), M, hipMemcpyHostToDevice));
+    if (!c->shapes.empty())
+        HIPCALL(c, hipMemcpy(c->rep_shape.p, c->shapes.data(), c->shapes.size() * sizeof(ShapeDev),
+                             hipMemcpyHostToDevice));
+    R.n_shape = (int)c->shapes.size();
+    R.shape = (const ShapeDev*)c->rep_shape.p;
+    R.type = (const unsigned char*)c->rep_type.p;
+    R.pos = (double*)c->rep_pos.p;
+    R.cell = (int*)c->rep_cell.p;
+    R.cnt = (int*)c->rep_cnt.p;
+    R.cursor = (int*)c->rep_cursor.p;
+    R.bsum = (int*)c->rep_bsum.p;
+    R.list = (int*)c->rep_list.p;
+    R.frep = c->rep_frep.p;
+    HIPCALL(c, hipMemcpy(c->rep_desc.p, &R, sizeof(RepDev), hipMemcpyHostToDevice));
     return OIF_OK;
 }
 
@@ -511,6 +595,7 @@ int upload_mesh_t(oif_ctx* c) {
         }
     }
     if ((rc = dev_alloc(c, c->scratch_dev, scratch_total))) return rc;
+    if ((rc = setup_repulsion(c, sizeof(real)))) return rc;
     std::vector<ObjDev<real>> od(c->obj.size());
     size_t soff = 0;
     for (size_t k = 0; k < order.size(); ++k) {
@@ -521,6 +606,8 @@ int upload_mesh_t(oif_ctx* c) {
         D.X = (double*)c->X_dev.p + 3 * o.off;
         D.V = (real*)c->V_dev.p + 3 * o.off;
         D.F = verlet ? (real*)c->F_dev.p + 3 * o.off : nullptr;
+        D.frep = c->rep_on ? (const real*)c->rep_frep.p + 3 * o.off : nullptr;
+        D.node0 = o.off;
         D.geo = (double*)c->geo_dev.p + 2 * order[k];
         for (int a = 0; a < 3; ++a) {
             D.anchor[a] = o.anchor[a];
@@ -568,6 +655,9 @@ inline void rec(hipEvent_t e, hipStream_t s) {
 
 int enqueue_mesh(oif_ctx* c, int par, hipStream_t s, int mark_next) {
     const size_t osz = objdev_size(c->d.precision);
+    if (c->rep_on)
+        HIPCALL(c, launch_repulsion(c->rep_h, (const RepDev*)c->rep_desc.p, c->obj_dev.p, (int)c->obj.size(),
+                                    c->d.precision, s));
     MeshLaunch ml{};
     ml.block = c->mesh_block;
     ml.parity = par;
@@ -859,7 +949,9 @@ int oif_destroy(oif_ctx* c) {
         if (p) (void)hipFree(p);
     for (auto& b : c->tbufs) b.release();
     for (DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->F_dev, &c->geo_dev,
-                      &c->scratch_dev, &c->part_dev, &c->diag_out})
+                      &c->scratch_dev, &c->part_dev, &c->diag_out, &c->rep_desc, &c->rep_pos, &c->rep_cell,
+                      &c->rep_cnt, &c->rep_cursor, &c->rep_bsum, &c->rep_list, &c->rep_frep, &c->rep_type,
+                      &c->rep_shape})
         b->release();
     if (c->own) (void)hipStreamDestroy(c->own);
     if (c->side) (void)hipStreamDestroy(c->side);
@@ -1006,6 +1098,19 @@ int oif_boundary_rhomboid(oif_ctx* c, const double corner[3], const double a[3],
     if (!(std::fabs(det) > 0)) return fail(c, OIF_E_ARG, "degenerate rhomboid");
     const double o[3] = {corner[0], corner[1], corner[2]};
     const double BC[3] = {bc[0], bc[1], bc[2]}, CA[3] = {ca[0], ca[1], ca[2]}, AB[3] = {ab[0], ab[1], ab[2]};
+    ShapeDev sh{};
+    sh.kind = 0;
+    for (int k = 0; k < 3; ++k) {
+        sh.corner[k] = corner[k];
+        sh.e[0][k] = a[k];
+        sh.e[1][k] = b[k];
+        sh.e[2][k] = cv[k];
+        sh.cof[0][k] = bc[k];
+        sh.cof[1][k] = ca[k];
+        sh.cof[2][k] = ab[k];
+    }
+    sh.det = det;
+    c->shapes.push_back(sh);
     // the node's coordinates (s, t, u) along a, b, c by Cramer's rule
     return add_boundary(c, velocity, id, [&](double x, double y, double z) {
         const double r[3] = {x - o[0], y - o[1], z - o[2]};
@@ -1019,6 +1124,11 @@ int oif_boundary_wall(oif_ctx* c, const double normal[3], double dist, const dou
     const double len = std::sqrt(vdot(normal, normal));
     if (!std::isfinite(dist) || !std::isfinite(len) || !(len > 0)) return fail(c, OIF_E_ARG, "bad wall");
     const double n[3] = {normal[0], normal[1], normal[2]};
+    ShapeDev sh{};
+    sh.kind = 1;
+    for (int k = 0; k < 3; ++k) sh.n[k] = normal[k] / len;
+    sh.dist = dist;
+    c->shapes.push_back(sh);
     return add_boundary(c, velocity, id, [&](double x, double y, double z) {
         const double r[3] = {x, y, z};
         return vdot(r, n) / len - dist < 0.0;
@@ -1028,6 +1138,7 @@ int oif_boundary_wall(oif_ctx* c, const double normal[3], double dist, const dou
 int oif_boundary_clear(oif_ctx* c) {
     if (!c) return OIF_E_ARG;
     c->n_bnd = 0;
+    c->shapes.clear();
     c->bt_host.clear();
     c->wall_host.clear();
     return upload_boundaries(c);
@@ -1062,6 +1173,7 @@ int oif_object_add(oif_ctx* c, int oid, int tid, const double origin[3], const d
         for (int a = 0; a < 9; ++a)
             if (!std::isfinite(rot[a])) return fail(c, OIF_E_ARG, "non-finite rotation");
     if (!std::isfinite(mass)) return fail(c, OIF_E_ARG, "non-finite mass");
+    if (part_type < 0 || part_type >= REP_TYPES) return fail(c, OIF_E_ARG, "part types must lie in 0..15");
     int rc = pull_mesh(c);
     if (rc) return rc;
     const Template& T = c->tmpl[tid];
@@ -1271,6 +1383,38 @@ int oif_write_force(oif_ctx* c, int oid, const double* F) {
         if (!std::isfinite(F[i])) return fail(c, OIF_E_ARG, "non-finite force");
     std::memcpy(&c->Fh[off], F, n * sizeof(double));
     c->mesh_dirty = true;
+    return OIF_OK;
+}
+
+int oif_set_soft_sphere(oif_ctx* c, int type_a, int type_b, double a, double n, double cutoff, double offset) {
+    if (!c) return OIF_E_ARG;
+    if (type_a < 0 || type_a >= REP_TYPES || type_b < 0 || type_b >= REP_TYPES)
+        return fail(c, OIF_E_ARG, "part types must lie in 0..15");
+    if (!(a >= 0.0) || !std::isfinite(a) || !(n > 0.0) || !std::isfinite(n) || !(cutoff > 0.0) ||
+        !std::isfinite(cutoff) || !(offset >= 0.0) || !std::isfinite(offset))
+        return fail(c, OIF_E_ARG, "soft sphere: a >= 0, n > 0, cutoff > 0, offset >= 0, all finite");
+    const double range = cutoff + offset;
+    const int dims[3] = {c->d.nx, c->d.ny, c->d.nz};
+    for (int k = 0; k < 3; ++k)
+        if ((k < 2 || !c->d.walls_z) && a > 0.0 && dims[k] < 2.0 * range)
+            return fail(c, OIF_E_ARG, "a periodic box length is below twice the interaction range");
+    const SoftSphereDev ss{a, n, cutoff, offset};
+    c->rep_pair[type_a][type_b] = ss;
+    c->rep_pair[type_b][type_a] = ss;
+    c->mesh_dirty = true;
+    drop_graph(c);
+    return OIF_OK;
+}
+
+int oif_set_wall_soft_sphere(oif_ctx* c, int type, double a, double n, double cutoff, double offset) {
+    if (!c) return OIF_E_ARG;
+    if (type < 0 || type >= REP_TYPES) return fail(c, OIF_E_ARG, "part types must lie in 0..15");
+    if (!(a >= 0.0) || !std::isfinite(a) || !(n > 0.0) || !std::isfinite(n) || !(cutoff > 0.0) ||
+        !std::isfinite(cutoff) || !(offset >= 0.0) || !std::isfinite(offset))
+        return fail(c, OIF_E_ARG, "soft sphere: a >= 0, n > 0, cutoff > 0, offset >= 0, all finite");
+    c->rep_wall[type] = SoftSphereDev{a, n, cutoff, offset};
+    c->mesh_dirty = true;
+    drop_graph(c);
     return OIF_OK;
 }
 
@@ -1759,6 +1903,10 @@ int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<h
     const size_t osz = objdev_size(b->precision);
     for (int k = 0; k < n; ++k) {
         if (ev) (void)hipEventRecord((*ev)[3 * k], s);
+        for (oif_ctx* c : b->ctx)
+            if (c->rep_on)
+                BHIP(b, launch_repulsion(c->rep_h, (const RepDev*)c->rep_desc.p, c->obj_dev.p,
+                                         (int)c->obj.size(), c->d.precision, s));
         MeshLaunch ml{};
         ml.block = b->mesh_block;
         ml.parity = par;

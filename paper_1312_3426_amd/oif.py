@@ -94,6 +94,8 @@ SIGNATURES = {
     "oif_set_launch": (_i, [_vp, _i, _i, _i]),
     "oif_set_mrt": (_i, [_vp, _vp]),
     "oif_set_integrator": (_i, [_vp, _i]),
+    "oif_set_soft_sphere": (_i, [_vp, _i, _i, _d, _d, _d, _d]),
+    "oif_set_wall_soft_sphere": (_i, [_vp, _i, _d, _d, _d, _d]),
     "oif_read_force": (_i, [_vp, _i, _vp]),
     "oif_write_force": (_i, [_vp, _i, _vp]),
     "oif_autotune": (_i, [_vp, C.c_char_p]),
@@ -265,6 +267,14 @@ class Context:
             g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(4))
             self._chk(lib().oif_set_mrt(self.h, g.ctypes.data))
 
+    def set_soft_sphere(self, type_a: int, type_b: int, a: float, n: float, cutoff: float, offset: float = 0.0):
+        self._chk(lib().oif_set_soft_sphere(self.h, int(type_a), int(type_b), float(a), float(n), float(cutoff),
+                                            float(offset)))
+
+    def set_wall_soft_sphere(self, ptype: int, a: float, n: float, cutoff: float, offset: float = 0.0):
+        self._chk(lib().oif_set_wall_soft_sphere(self.h, int(ptype), float(a), float(n), float(cutoff),
+                                                 float(offset)))
+
     def set_integrator(self, name: str):
         """Mesh integrator: "euler" (default) or "verlet"."""
         code = {"euler": 0, "verlet": 1}[name]
@@ -384,8 +394,13 @@ class Context:
         for tid, t in enumerate(box.templates):
             c.template_create(tid, t.nodes, t.tris, stretch=t.stretch, ks=t.ks, kb=t.kb, kal=t.kal,
                               kag=t.kag, kv=t.kv, linear=t.linear, model=getattr(t, "model", "paper"))
+        for r in getattr(box, "repulsion", []) or []:
+            if r.type_b is None:
+                c.set_wall_soft_sphere(r.type_a, r.a, r.n, r.cutoff, r.offset)
+            else:
+                c.set_soft_sphere(r.type_a, r.type_b, r.a, r.n, r.cutoff, r.offset)
         for oid, o in enumerate(box.objects):
-            c.object_add(oid, o.tid, o.origin, o.rot, o.mass, 0)
+            c.object_add(oid, o.tid, o.origin, o.rot, o.mass, getattr(o, "ptype", 0))
             if any(o.fext):
                 c.object_set_force(oid, o.fext)
         return c

@@ -271,3 +271,119 @@ def test_verlet_state_errors(oif):
     with pytest.raises(oif.OifError):
         c.write_force(-1, np.full((box.n_mesh_nodes, 3), np.nan))
     c.close()
+
+
+# ---------------------------------------------------------------------------
+# soft-sphere repulsion
+# ---------------------------------------------------------------------------
+def _contact_box(n_box=16, sep=4.18, walls=False, integrator="euler", mrt=None, bnd=(), extra=(), same=False,
+                 cut=0.5):
+    """Two level-2 icospheres (162 nodes, radius 2) whose surfaces nearly touch,
+    types 0 and 1 (or both 0), pair and wall repulsion in range."""
+    x, t = synth.icosphere(2, 2.0)
+    tm = synth.Template(x, t, ks=0.05, kb=0.01, kv=0.5)
+    rng = np.random.default_rng(41)
+    c = n_box / 2
+    objs = [synth.ObjectSpec(0, np.array([c - sep / 2, c, c]), rot=synth.random_rotation(rng), ptype=0),
+            synth.ObjectSpec(0, np.array([c + sep / 2, c + 0.1, c - 0.05]), rot=synth.random_rotation(rng),
+                             ptype=0 if same else 1)]
+    objs += list(extra)
+    rep = [synth.SoftSphere(0, 0 if same else 1, a=2e-6, n=2.0, cutoff=cut, offset=0.02),
+           synth.SoftSphere(0, None, a=1e-6, n=1.5, cutoff=0.8)]
+    if not same:
+        rep.append(synth.SoftSphere(1, None, a=1e-6, n=1.5, cutoff=0.8))
+    return synth.Box(n_box, n_box, n_box, g=(1e-5, 0, 0), friction=0.5, walls_z=walls, templates=[tm],
+                     objects=objs, repulsion=rep, boundaries=list(bnd), integrator=integrator, mrt=mrt)
+
+
+def _run_vs_oracle(oif, orc, box, prec, steps, label):
+    sysm = orc.System(box)
+    X0 = sysm.X.copy()
+    Fr = sysm.repulsion()
+    assert np.abs(Fr).max() > 1e-5, "the configuration must put pairs in range"
+    ctx = oif.Context.from_box(box, precision=prec)
+    done = 0
+    for k in steps:
+        ctx.step(k - done)
+        sysm.run(k - done)
+        done = k
+        res = check(gpu_fields(ctx, box.rho0, X0), oracle_fields(sysm, X0), prec, box.rho0, box.nx)
+        say(f"   {label} step {k}: {fmt(res)}")
+        assert_ok(res, f"{label} step {k}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_repulsion_pairs_vs_oracle(oif, orc, prec):
+    """Two cells in contact in a periodic box (cells hashed into buckets)."""
+    say(f"[repulsion] pair contact {prec}")
+    _run_vs_oracle(oif, orc, _contact_box(), prec, (1, 10), "pairs")
+
+
+def test_repulsion_walls_shapes_and_verlet_vs_oracle(oif, orc):
+    """Cells against the z walls, a sheared block and a half-space wall, with
+    velocity Verlet and MRT, FP64; a second box small enough that every cell
+    has its own bucket."""
+    say("[repulsion] walls, shapes, verlet, mrt fp64")
+    block = synth.Boundary("rhomboid", corner=(1.0, 9.9, 2.0), a=(5.0, 0.0, 0.5), b=(0.5, 3.0, 0.0),
+                           c=(0.0, 0.3, 4.0))
+    wall = synth.Boundary("wall", normal=(0.0, -1.0, 0.0), dist=-13.6)  # solid for y > 13.6
+    box = _contact_box(sep=4.2, walls=True, integrator="verlet", mrt=RATES["ghosts"], bnd=(block, wall))
+    box.objects[0].origin = np.array([5.0, 8.0, 2.6])   # near z = 0 and the block
+    box.objects[1].origin = np.array([9.2, 11.5, 2.7])  # near the half-space wall
+    _run_vs_oracle(oif, orc, box, "fp64", (1, 8), "walls")
+    # pair range 1.62: 9^3 cells of edge 16/9, fewer than the 1024 buckets, one bucket each
+    direct = _contact_box(sep=4.6, cut=1.6)
+    _run_vs_oracle(oif, orc, direct, "fp64", (1, 6), "direct")
+
+
+def test_repulsion_same_type_and_minimum_image(oif, orc):
+    """Both cells of type 0 with a 0-0 interaction (also acting inside each
+    cell), placed across the periodic x boundary."""
+    say("[repulsion] same type across the periodic boundary fp64")
+    box = _contact_box(sep=4.16, same=True)
+    box.objects[0].origin = np.array([1.9, 8.0, 8.0])
+    box.objects[1].origin = np.array([-2.26 + 16.0, 8.1, 7.95])
+    _run_vs_oracle(oif, orc, box, "fp64", (1, 6), "periodic")
+
+
+def test_repulsion_modes_bitwise(oif):
+    """Repulsion is deterministic: rerun, graph replay and a batch with a
+    plain box give the same bits."""
+    say("[repulsion] determinism, graph, batch fp32")
+    box = _contact_box()
+    out = []
+    for graph in (0, 0, 4):
+        c = oif.Context.from_box(box, precision="fp32")
+        c.set_graph(graph)
+        c.step(12)
+        out.append((c.read_populations(), c.read_mesh(-1)[0]))
+        c.close()
+    assert all(np.array_equal(out[0][i], o[i]) for o in out[1:] for i in range(2))
+    other = synth.config_batch(n_boxes=1, steps=12)[0]
+    ref = []
+    for bx in (box, other):
+        c = oif.Context.from_box(bx, precision="fp32")
+        c.step(12)
+        ref.append((c.read_populations(), c.read_mesh(-1)[0]))
+        c.close()
+    ctxs = [oif.Context.from_box(bx, precision="fp32") for bx in (box, other)]
+    B = oif.Batch(ctxs)
+    B.step(12)
+    for c, (n, X) in zip(ctxs, ref):
+        assert np.array_equal(c.read_populations(), n) and np.array_equal(c.read_mesh(-1)[0], X)
+    B.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_repulsion_argument_errors(oif):
+    c = oif.Context(8, 8, 8, precision="fp32")
+    for args in ((16, 0, 1e-6, 2.0, 0.5), (0, -1, 1e-6, 2.0, 0.5), (0, 1, -1.0, 2.0, 0.5),
+                 (0, 1, 1e-6, 0.0, 0.5), (0, 1, 1e-6, 2.0, 0.0), (0, 1, 1e-6, 2.0, 4.5)):
+        with pytest.raises(oif.OifError):
+            c.set_soft_sphere(*args)
+    with pytest.raises(oif.OifError):
+        c.set_wall_soft_sphere(16, 1e-6, 2.0, 0.5)
+    c.set_soft_sphere(0, 1, 1e-6, 2.0, 0.5)
+    c.close()
