@@ -22,6 +22,13 @@ JSON line:
   roofline.traffic  HBM bytes per lattice-kernel launch from the rocprofv3
                  FETCH_SIZE / WRITE_SIZE record in profiles/, reported only while
                  the lattice kernel's sources hash to the recorded value
+  variants       the same workload (FP32 storage) with the multiple-relaxation-
+                 time collision, the velocity Verlet integrator, soft-sphere
+                 repulsion between all cells (cell lists built every step), and
+                 all three together: step time and kernel times
+  obstacles      the S-shaped obstacle channel (384x192x64, 400 cells of 393
+                 nodes, moving inlet): FP32 and FP16 storage, with and without
+                 the obstacles
 """
 from __future__ import annotations
 
@@ -157,6 +164,56 @@ def batching(oif, steps, tune):
                       "one FP64 watchdog"}
 
 
+def variants(oif, box, steps, warmup, tune):
+    """Step and kernel times of the engine variants on the bench workload."""
+    import copy
+
+    from paper_1312_3426_amd import synth
+
+    def run(label, **kw):
+        b = copy.deepcopy(box)
+        for k, v in kw.items():
+            setattr(b, k, v)
+        r = measure(oif, b, "fp32", steps, warmup, tune=tune)
+        ms = r["total_ms"] / steps
+        return label, {"ms_per_step": round(ms, 5), "mlups": round(b.n_nodes / (ms * 1e-3) / 1e6, 2),
+                       "lb_ms": round(r["lb_ms"], 5), "mesh_ms": round(r["mesh_ms"], 5),
+                       "other_ms": round(ms - r["lb_ms"] - r["mesh_ms"], 5)}
+
+    mrt = (0.0, -0.5, 0.3, -0.3)
+    pair = [synth.SoftSphere(0, 0, a=1e-7, n=2.0, cutoff=0.3)]
+    out = dict([run("bgk_euler"), run("mrt", mrt=mrt), run("verlet", integrator="verlet"),
+                run("repulsion", repulsion=pair),
+                run("all_three", mrt=mrt, integrator="verlet", repulsion=pair)])
+    base = out["bgk_euler"]["ms_per_step"]
+    for v in out.values():
+        v["vs_bgk_euler"] = round(v["ms_per_step"] / base, 3)
+    out["note"] = ("FP32 storage, launch shapes of the main run; mrt factors (0, -0.5, 0.3, -0.3); "
+                   "repulsion: soft sphere between all mesh nodes, cutoff 0.3 (cells start apart)")
+    return out
+
+
+def obstacles(oif, steps):
+    """The obstacle channel with and without its obstacles."""
+    from paper_1312_3426_amd import synth
+
+    box = synth.config_obstacle_channel(steps, nx=384, ny=192, nz=64, n_cells=400)
+    shapes = list(box.boundaries)
+    out = {"workload": box.name, "nodes": box.n_nodes, "mesh_nodes": box.n_mesh_nodes}
+    for label, bnd in (("obstacles", shapes), ("none", [])):
+        box.boundaries = bnd
+        for prec in ("fp32", "fp16"):
+            c = oif.Context.from_box(box, precision=prec)
+            c.set_launch(256, 512, 1)
+            c.step(6)
+            t = c.step_timed(steps)
+            c.close()
+            ms = t.total_ms / steps
+            out[f"{label}_{prec}"] = {"ms_per_step": round(ms, 5), "mlups": round(box.n_nodes / (ms * 1e-3) / 1e6, 2),
+                                      "lb_ms": round(t.lb_ms, 5), "mesh_ms": round(t.mesh_ms, 5)}
+    return out
+
+
 def cpu_baseline(box, steps):
     import oracle
 
@@ -181,6 +238,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-storage", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-obstacles", action="store_true")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1312_3426_amd", "autotune.json"))
     ap.add_argument("--workload", default="precision", choices=["precision", "scale"])
     ap.add_argument("--only", default=None, choices=["fp32", "fp16", "bf16"],
@@ -278,6 +337,12 @@ def main():
     if not a.no_batch:
         log("[bench] batching: 32 boxes, batched vs one after another")
         line["batching"] = batching(oif, 200, None if a.no_tune else a.tune_cache)
+    if not a.no_variants and a.workload == "precision":
+        log("[bench] engine variants: MRT, Verlet, repulsion")
+        line["variants"] = variants(oif, box, 100, 10, None if a.no_tune else a.tune_cache)
+    if not a.no_obstacles:
+        log("[bench] obstacle channel")
+        line["obstacles"] = obstacles(oif, 40)
     if not a.no_cpu:
         log(f"[bench] cpu baseline: oracle, {a.cpu_steps} steps")
         line["cpu_baseline"] = cpu_baseline(box, a.cpu_steps)

@@ -162,15 +162,17 @@ struct ShapeDev {
     double n[3], dist;          // half-space
 };
 constexpr int REP_TYPES = 16;   // part types 0 .. 15
-// Cell lists of one box: mesh nodes binned into cells of at least the largest
-// pair range, the cells hashed into H buckets (H a power of two, identity when
-// every cell has its own bucket); per bucket the node ids in ascending order.
+// Cell lists of one box: the mesh nodes sorted by cell (cells of at least the
+// largest pair range, a regular grid over the box, x fastest), inside a cell
+// by node id; positions and types copied into that order, so that a node's
+// partners are read from contiguous runs.
 struct RepDev {
     int M;
-    int H, log2H, direct;
+    int ncell;
     int nc[3];
     double hc[3];               // cell edge per axis (>= the pair range)
     double L[3];
+    double range2;              // square of the largest pair range
     int walls_z, pairs;         // pairs: some pair interaction is set
     SoftSphereDev pair[REP_TYPES][REP_TYPES];
     SoftSphereDev wall[REP_TYPES];
@@ -178,11 +180,13 @@ struct RepDev {
     const ShapeDev* shape;
     const unsigned char* type;  // [M] part type per node
     double* pos;                // [M][3] positions the forces are taken at
-    int* cell;                  // [M] cell id
-    int* cnt;                   // [H + 1] nodes per bucket, then bucket starts
-    int* cursor;                // [H]
+    int* cell;                  // [M] cell of each node
+    int* cnt;                   // [ncell + 1] nodes per cell, then cell starts
+    int* cursor;                // [ncell]
     int* bsum;                  // block sums of the scan
-    int* list;                  // [M] node ids by bucket
+    int* list;                  // [M] node ids in cell order
+    double* spos;               // [M][3] positions in cell order
+    unsigned char* stype;       // [M] types in cell order
     void* frep;                 // [M][3] force, arithmetic type
 };
 

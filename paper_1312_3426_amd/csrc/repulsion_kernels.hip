@@ -8,15 +8,19 @@
 // total force):
 //   rep_bin     the positions the membrane kernel takes its forces at (those
 //               of the step start, or advanced by the half-step velocity with
-//               velocity Verlet), their cells (edge >= the largest pair
-//               range) and the count per bucket (cells hashed into H buckets);
-//   scan        bucket starts (exclusive prefix sum);
-//   scatter     node ids into their buckets;
-//   order       each bucket sorted by node id, so that every node meets its
-//               partners in a fixed order (deterministic sums);
-//   force       per node: the pairs in the 27 surrounding cells (minimum-image
-//               distance in the periodic directions), then every obstacle
-//               shape and the z walls; FP64 arithmetic.
+//               velocity Verlet) and their cells (a regular grid, edge >= the
+//               largest pair range); nodes per cell;
+//   scan        cell starts (exclusive prefix sum);
+//   scatter     node ids into their cells;
+//   order       each cell sorted by node id (deterministic sums);
+//   gather      positions (wrapped into the box along periodic axes) and
+//               types copied into cell order;
+//   force       one thread per node in cell order: the partners in the 27
+//               surrounding cells, read as contiguous runs, a neighbour cell
+//               across a periodic face shifted by the box length (the minimum
+//               image: cells are at least the pair range and the box at least
+//               twice it); then every obstacle shape and the z walls; FP64
+//               arithmetic, fixed order.
 #include <limits.h>
 
 #include "device_common.h"
@@ -25,10 +29,6 @@ namespace oif {
 namespace {
 
 using namespace dev;
-
-__device__ __forceinline__ int bucket_of(const RepDev& D, int cell) {
-    return D.direct ? cell : (int)(((unsigned)cell * 2654435761u) >> (32 - D.log2H));
-}
 
 __device__ __forceinline__ int cell_coord(const RepDev& D, int a, double x, bool periodic) {
     const double w = periodic ? x - D.L[a] * floor(x / D.L[a]) : x;
@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256) rep_bin_kernel(const ObjDev<R>* __restric
         const int cz = cell_coord(D, 2, p[2], !D.walls_z);
         const int cell = (cz * D.nc[1] + cy) * D.nc[0] + cx;
         D.cell[j] = cell;
-        atomicAdd(&D.cnt[bucket_of(D, cell)], 1);
+        atomicAdd(&D.cnt[cell], 1);
     }
 }
 
@@ -84,25 +84,32 @@ __global__ void __launch_bounds__(1024) scan_block_kernel(int* __restrict__ cnt,
     if (threadIdx.x == 1023) bsum[blockIdx.x] = before + incl;
 }
 
+// exclusive scan of the 1024-thread block's values (wave scans, then the
+// wave totals); all threads of the block must call it
+__device__ __forceinline__ int block_exclusive_scan(int v, int* wsum) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    return before + incl - v;
+}
+
 __global__ void __launch_bounds__(1024) scan_top_kernel(int* __restrict__ bsum, int nb) {
-    // one workgroup: every thread scans a contiguous run, then the runs
-    __shared__ int run[1024];
+    // one workgroup: every thread sums a contiguous run, the run sums are
+    // scanned across the block, then every thread writes its run's prefixes
+    __shared__ int wsum[16];
     const int per = (nb + 1023) / 1024;
     const int b0 = threadIdx.x * per;
     int s = 0;
     for (int k = b0; k < b0 + per && k < nb; ++k) s += bsum[k];
-    run[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const int t = run[k];
-            run[k] = acc;
-            acc += t;
-        }
-    }
-    __syncthreads();
-    int acc = run[threadIdx.x];
+    int acc = block_exclusive_scan(s, wsum);
     for (int k = b0; k < b0 + per && k < nb; ++k) {
         const int t = bsum[k];
         bsum[k] = acc;
@@ -125,16 +132,16 @@ __global__ void __launch_bounds__(256) rep_scatter_kernel(const RepDev* __restri
     const RepDev& D = *Dp;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= D.M) return;
-    const int slot = atomicAdd(&D.cursor[bucket_of(D, D.cell[j])], 1);
+    const int slot = atomicAdd(&D.cursor[D.cell[j]], 1);
     D.list[slot] = j;
 }
 
 __global__ void __launch_bounds__(256) rep_order_kernel(const RepDev* __restrict__ Dp) {
     const RepDev& D = *Dp;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= D.H) return;
+    if (b >= D.ncell) return;
     const int s0 = D.cnt[b], s1 = D.cnt[b + 1];
-    for (int s = s0 + 1; s < s1; ++s) {  // insertion sort, buckets are short
+    for (int s = s0 + 1; s < s1; ++s) {  // insertion sort, cells hold few nodes
         const int v = D.list[s];
         int t = s - 1;
         while (t >= s0 && D.list[t] > v) {
@@ -143,6 +150,18 @@ __global__ void __launch_bounds__(256) rep_order_kernel(const RepDev* __restrict
         }
         D.list[t + 1] = v;
     }
+}
+
+__global__ void __launch_bounds__(256) rep_gather_kernel(const RepDev* __restrict__ Dp) {
+    const RepDev& D = *Dp;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= D.M) return;
+    const int j = D.list[s];
+    for (int c = 0; c < 3; ++c) {
+        const double x = D.pos[3 * j + c];
+        D.spos[3 * s + c] = (c < 2 || !D.walls_z) ? x - D.L[c] * floor(x / D.L[c]) : x;
+    }
+    D.stype[s] = D.type[j];
 }
 
 __device__ __forceinline__ double dot3(const double* a, const double* b) {
@@ -235,44 +254,66 @@ __device__ __forceinline__ void offsets(int nc, bool periodic, int& lo, int& hi)
     }
 }
 
+// One thread per node; with pair interactions the threads take the nodes in
+// cell order (slot s holds node list[s]), so a wave's neighbouring cells are
+// shared and each cell's partners are a contiguous run of spos.
 template <typename R>
 __global__ void __launch_bounds__(256) rep_force_kernel(const RepDev* __restrict__ Dp) {
     const RepDev& D = *Dp;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= D.M) return;
-    const double p[3] = {D.pos[3 * j], D.pos[3 * j + 1], D.pos[3 * j + 2]};
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= D.M) return;
+    const int j = D.pairs ? D.list[s] : s;
     const int tj = D.type[j];
     const bool pz = !D.walls_z;
     double f[3] = {0.0, 0.0, 0.0};
     if (D.pairs) {
+        const double p[3] = {D.spos[3 * s], D.spos[3 * s + 1], D.spos[3 * s + 2]};
         const int cell = D.cell[j];
         const int cx = cell % D.nc[0], t = cell / D.nc[0], cy = t % D.nc[1], cz = t / D.nc[1];
         int lx, hx, ly, hy, lz, hz;
         offsets(D.nc[0], true, lx, hx);
         offsets(D.nc[1], true, ly, hy);
         offsets(D.nc[2], pz, lz, hz);
+        // an axis with fewer than 3 cells: each cell once, the image by rounding
+        const bool round_x = D.nc[0] < 3, round_y = D.nc[1] < 3, round_z = pz && D.nc[2] < 3;
         for (int dz = lz; dz <= hz; ++dz) {
             int z = cz + dz;
-            if (pz) z = (z + D.nc[2]) % D.nc[2];
-            else if (z < 0 || z >= D.nc[2]) continue;
+            double sz = 0.0;  // shift of the neighbour cell's nodes (periodic image)
+            if (pz) {
+                if (z < 0) { z += D.nc[2]; sz = -D.L[2]; }
+                else if (z >= D.nc[2]) { z -= D.nc[2]; sz = D.L[2]; }
+            } else if (z < 0 || z >= D.nc[2]) {
+                continue;
+            }
             for (int dy = ly; dy <= hy; ++dy) {
-                const int y = (cy + dy + D.nc[1]) % D.nc[1];
-                for (int dx = lx; dx <= hx; ++dx) {
-                    const int x = (cx + dx + D.nc[0]) % D.nc[0];
-                    const int nb = (z * D.nc[1] + y) * D.nc[0] + x;
-                    const int b = bucket_of(D, nb);
-                    for (int s = D.cnt[b]; s < D.cnt[b + 1]; ++s) {
-                        const int k = D.list[s];
-                        if (k == j || D.cell[k] != nb) continue;
-                        const SoftSphereDev& ss = D.pair[tj][D.type[k]];
+                int y = cy + dy;
+                double sy = 0.0;
+                if (y < 0) { y += D.nc[1]; sy = -D.L[1]; }
+                else if (y >= D.nc[1]) { y -= D.nc[1]; sy = D.L[1]; }
+                const int row = (z * D.nc[1] + y) * D.nc[0];
+                // the cells x - 1 .. x + 1 of a row without a wrap are one
+                // contiguous run of slots
+                const bool run3 = !round_x && cx > 0 && cx + 1 < D.nc[0];
+                for (int dx = run3 ? 0 : lx; dx <= (run3 ? 0 : hx); ++dx) {
+                    int x = cx + dx;
+                    double sx = 0.0;
+                    if (x < 0) { x += D.nc[0]; sx = -D.L[0]; }
+                    else if (x >= D.nc[0]) { x -= D.nc[0]; sx = D.L[0]; }
+                    const int u0 = run3 ? D.cnt[row + cx - 1] : D.cnt[row + x];
+                    const int u1 = run3 ? D.cnt[row + cx + 2] : D.cnt[row + x + 1];
+                    for (int u = u0; u < u1; ++u) {
+                        if (u == s) continue;
+                        double r[3] = {p[0] - (D.spos[3 * u] + sx), p[1] - (D.spos[3 * u + 1] + sy),
+                                       p[2] - (D.spos[3 * u + 2] + sz)};
+                        if (round_x) r[0] -= D.L[0] * rint(r[0] / D.L[0]);
+                        if (round_y) r[1] -= D.L[1] * rint(r[1] / D.L[1]);
+                        if (round_z) r[2] -= D.L[2] * rint(r[2] / D.L[2]);
+                        const double d2 = dot3(r, r);
+                        if (!(d2 < D.range2)) continue;  // beyond every pair range
+                        const SoftSphereDev& ss = D.pair[tj][D.stype[u]];
                         if (ss.a == 0.0) continue;
-                        double r[3];
-                        for (int c = 0; c < 3; ++c) {
-                            r[c] = p[c] - D.pos[3 * k + c];
-                            if (c < 2 || pz) r[c] -= D.L[c] * floor(r[c] / D.L[c] + 0.5);
-                        }
-                        const double d = sqrt(dot3(r, r));
-                        const double dir[3] = {r[0] / d, r[1] / d, r[2] / d};
+                        const double d = sqrt(d2), id = 1.0 / d;
+                        const double dir[3] = {r[0] * id, r[1] * id, r[2] * id};
                         soft_sphere(ss, d, dir, f);
                     }
                 }
@@ -282,7 +323,10 @@ __global__ void __launch_bounds__(256) rep_force_kernel(const RepDev* __restrict
     const SoftSphereDev& ws = D.wall[tj];
     if (ws.a != 0.0) {
         double q[3];
-        for (int c = 0; c < 3; ++c) q[c] = (c < 2 || pz) ? p[c] - D.L[c] * floor(p[c] / D.L[c]) : p[c];
+        for (int c = 0; c < 3; ++c) {
+            const double x = D.pos[3 * j + c];
+            q[c] = (c < 2 || pz) ? x - D.L[c] * floor(x / D.L[c]) : x;
+        }
         for (int k = 0; k < D.n_shape; ++k) {
             double d, dir[3];
             if (shape_distance(D.shape[k], q, d, dir)) soft_sphere(ws, d, dir, f);
@@ -306,18 +350,21 @@ template <typename R>
 hipError_t launch_rep_t(const RepDev& h, const RepDev* d, const void* objs, int nobj, hipStream_t s) {
     const int M = h.M;
     if (M == 0) return hipSuccess;
+    const int gm = (M + 255) / 256;
     if (h.pairs)
-        hipLaunchKernelGGL(fill_int_kernel, dim3((h.H + 1 + 255) / 256), dim3(256), 0, s, h.cnt, h.H + 1, 0);
+        hipLaunchKernelGGL(fill_int_kernel, dim3((h.ncell + 1 + 255) / 256), dim3(256), 0, s, h.cnt, h.ncell + 1, 0);
     hipLaunchKernelGGL((rep_bin_kernel<R>), dim3(nobj), dim3(256), 0, s, (const ObjDev<R>*)objs, d);
     if (h.pairs) {
-        const int nb = (h.H + 1023) / 1024;
-        hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(1024), 0, s, h.cnt, h.bsum, h.H);
+        const int nb = (h.ncell + 1023) / 1024;
+        hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(1024), 0, s, h.cnt, h.bsum, h.ncell);
         hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, h.bsum, nb);
-        hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(1024), 0, s, h.cnt, h.cursor, (const int*)h.bsum, h.H, M);
-        hipLaunchKernelGGL(rep_scatter_kernel, dim3((M + 255) / 256), dim3(256), 0, s, d);
-        hipLaunchKernelGGL(rep_order_kernel, dim3((h.H + 255) / 256), dim3(256), 0, s, d);
+        hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(1024), 0, s, h.cnt, h.cursor, (const int*)h.bsum,
+                           h.ncell, M);
+        hipLaunchKernelGGL(rep_scatter_kernel, dim3(gm), dim3(256), 0, s, d);
+        hipLaunchKernelGGL(rep_order_kernel, dim3((h.ncell + 255) / 256), dim3(256), 0, s, d);
+        hipLaunchKernelGGL(rep_gather_kernel, dim3(gm), dim3(256), 0, s, d);
     }
-    hipLaunchKernelGGL((rep_force_kernel<R>), dim3((M + 255) / 256), dim3(256), 0, s, d);
+    hipLaunchKernelGGL((rep_force_kernel<R>), dim3(gm), dim3(256), 0, s, d);
     return hipGetLastError();
 }
 

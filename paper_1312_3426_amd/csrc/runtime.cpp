@@ -277,7 +277,8 @@ struct oif_ctx {
     std::vector<ShapeDev> shapes;
     bool rep_on = false;
     RepDev rep_h{};
-    DevBuf rep_desc, rep_pos, rep_cell, rep_cnt, rep_cursor, rep_bsum, rep_list, rep_frep, rep_type, rep_shape;
+    DevBuf rep_desc, rep_pos, rep_cell, rep_cnt, rep_cursor, rep_bsum, rep_list, rep_spos, rep_stype, rep_frep,
+        rep_type, rep_shape;
     bool host_stale = false;
     bool mesh_dirty = true;     // device mesh arrays must be rebuilt
 
@@ -390,9 +391,11 @@ int pull_mesh(oif_ctx* c) {
 }
 
 // Cell lists and force buffer of the soft-sphere repulsion (when some
-// interaction is set and the box holds mesh nodes): cells of at least the
-// largest pair range per axis, hashed into a power-of-two number of buckets
-// (about two per mesh node; one per cell when the cells are fewer).
+// interaction is set and the box holds mesh nodes): a regular grid of cells
+// of at least the largest pair range, coarsened until there are at most 16
+// cells per mesh node (at least 4096): cells near the pair range keep the
+// candidate partners few, the cap keeps the per-cell arrays small next to
+// the lattice.
 int setup_repulsion(oif_ctx* c, size_t real_bytes) {
     bool pairs = false, walls = false;
     double rc = 0.0;
@@ -406,7 +409,7 @@ int setup_repulsion(oif_ctx* c, size_t real_bytes) {
     }
     c->rep_on = (pairs || walls) && c->M > 0;
     for (DevBuf* b : {&c->rep_desc, &c->rep_pos, &c->rep_cell, &c->rep_cnt, &c->rep_cursor, &c->rep_bsum,
-                      &c->rep_list, &c->rep_frep, &c->rep_type, &c->rep_shape})
+                      &c->rep_list, &c->rep_spos, &c->rep_stype, &c->rep_frep, &c->rep_type, &c->rep_shape})
         b->release();
     if (!c->rep_on) return OIF_OK;
     RepDev& R = c->rep_h;
@@ -414,33 +417,29 @@ int setup_repulsion(oif_ctx* c, size_t real_bytes) {
     R.M = (int)c->M;
     R.walls_z = c->d.walls_z ? 1 : 0;
     R.pairs = pairs ? 1 : 0;
+    R.range2 = rc * rc;
     const int dims[3] = {c->d.nx, c->d.ny, c->d.nz};
-    long long ncells = 1;
+    const long long target = std::max(4096LL, 16LL * (long long)c->M);
     for (int a = 0; a < 3; ++a) {
         R.L[a] = dims[a];
         R.nc[a] = pairs ? std::max(1, (int)std::floor(dims[a] / rc)) : 1;
     }
-    // keep the cell count in int range: coarser cells are still correct
-    for (;;) {
-        ncells = (long long)R.nc[0] * R.nc[1] * R.nc[2];
-        if (ncells <= (1LL << 30)) break;
+    while ((long long)R.nc[0] * R.nc[1] * R.nc[2] > target) {  // coarser cells are still correct
         int big = 0;
         for (int a = 1; a < 3; ++a)
-            if (R.nc[a] > R.nc[big]) big = a;
-        R.nc[big] = std::max(1, R.nc[big] / 2);
+            if ((double)R.nc[a] / dims[a] > (double)R.nc[big] / dims[big]) big = a;
+        R.nc[big] = std::max(1, R.nc[big] - std::max(1, R.nc[big] / 8));
     }
+    R.ncell = R.nc[0] * R.nc[1] * R.nc[2];
     for (int a = 0; a < 3; ++a) R.hc[a] = R.L[a] / R.nc[a];
-    R.log2H = 10;
-    while ((1LL << R.log2H) < 2LL * c->M) ++R.log2H;
-    R.H = 1 << R.log2H;
-    R.direct = ncells <= R.H ? 1 : 0;
     std::memcpy(R.pair, c->rep_pair, sizeof(R.pair));
     std::memcpy(R.wall, c->rep_wall, sizeof(R.wall));
-    const size_t M = c->M;
+    const size_t M = c->M, NC = (size_t)R.ncell;
     int rc_ = 0;
     if ((rc_ = dev_alloc(c, c->rep_pos, 3 * M * sizeof(double))) || (rc_ = dev_alloc(c, c->rep_cell, M * 4)) ||
-        (rc_ = dev_alloc(c, c->rep_cnt, ((size_t)R.H + 1) * 4)) || (rc_ = dev_alloc(c, c->rep_cursor, (size_t)R.H * 4)) ||
-        (rc_ = dev_alloc(c, c->rep_bsum, ((size_t)R.H / 1024 + 1) * 4)) || (rc_ = dev_alloc(c, c->rep_list, M * 4)) ||
+        (rc_ = dev_alloc(c, c->rep_cnt, (NC + 1) * 4)) || (rc_ = dev_alloc(c, c->rep_cursor, NC * 4)) ||
+        (rc_ = dev_alloc(c, c->rep_bsum, (NC / 1024 + 1) * 4)) || (rc_ = dev_alloc(c, c->rep_list, M * 4)) ||
+        (rc_ = dev_alloc(c, c->rep_spos, 3 * M * sizeof(double))) || (rc_ = dev_alloc(c, c->rep_stype, M)) ||
         (rc_ = dev_alloc(c, c->rep_frep, 3 * M * real_bytes)) || (rc_ = dev_alloc(c, c->rep_type, M)) ||
         (rc_ = dev_alloc(c, c->rep_shape, (c->shapes.size() + 1) * sizeof(ShapeDev))) ||
         (rc_ = dev_alloc(c, c->rep_desc, sizeof(RepDev))))
@@ -461,6 +460,8 @@ int setup_repulsion(oif_ctx* c, size_t real_bytes) {
     R.cursor = (int*)c->rep_cursor.p;
     R.bsum = (int*)c->rep_bsum.p;
     R.list = (int*)c->rep_list.p;
+    R.spos = (double*)c->rep_spos.p;
+    R.stype = (unsigned char*)c->rep_stype.p;
     R.frep = c->rep_frep.p;
     HIPCALL(c, hipMemcpy(c->rep_desc.p, &R, sizeof(RepDev), hipMemcpyHostToDevice));
     return OIF_OK;
@@ -950,8 +951,8 @@ int oif_destroy(oif_ctx* c) {
     for (auto& b : c->tbufs) b.release();
     for (DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->F_dev, &c->geo_dev,
                       &c->scratch_dev, &c->part_dev, &c->diag_out, &c->rep_desc, &c->rep_pos, &c->rep_cell,
-                      &c->rep_cnt, &c->rep_cursor, &c->rep_bsum, &c->rep_list, &c->rep_frep, &c->rep_type,
-                      &c->rep_shape})
+                      &c->rep_cnt, &c->rep_cursor, &c->rep_bsum, &c->rep_list, &c->rep_spos, &c->rep_stype,
+                      &c->rep_frep, &c->rep_type, &c->rep_shape})
         b->release();
     if (c->own) (void)hipStreamDestroy(c->own);
     if (c->side) (void)hipStreamDestroy(c->side);
