@@ -164,8 +164,12 @@ def batching(oif, steps, tune):
                       "one FP64 watchdog"}
 
 
-def variants(oif, box, steps, warmup, tune):
-    """Step and kernel times of the engine variants on the bench workload."""
+VARIANTS = ("bgk_euler", "mrt", "verlet", "repulsion", "all_three")
+
+
+def variants(oif, box, steps, warmup, tune, only=None):
+    """Step and kernel times of the engine variants on the bench workload
+    (all of them, or the one named by `only`)."""
     import copy
 
     from paper_1312_3426_amd import synth
@@ -182,12 +186,14 @@ def variants(oif, box, steps, warmup, tune):
 
     mrt = (0.0, -0.5, 0.3, -0.3)
     pair = [synth.SoftSphere(0, 0, a=1e-7, n=2.0, cutoff=0.3)]
-    out = dict([run("bgk_euler"), run("mrt", mrt=mrt), run("verlet", integrator="verlet"),
-                run("repulsion", repulsion=pair),
-                run("all_three", mrt=mrt, integrator="verlet", repulsion=pair)])
-    base = out["bgk_euler"]["ms_per_step"]
-    for v in out.values():
-        v["vs_bgk_euler"] = round(v["ms_per_step"] / base, 3)
+    settings = {"bgk_euler": {}, "mrt": dict(mrt=mrt), "verlet": dict(integrator="verlet"),
+                "repulsion": dict(repulsion=pair),
+                "all_three": dict(mrt=mrt, integrator="verlet", repulsion=pair)}
+    out = dict(run(k, **v) for k, v in settings.items() if only is None or k == only)
+    if only is None:
+        base = out["bgk_euler"]["ms_per_step"]
+        for v in out.values():
+            v["vs_bgk_euler"] = round(v["ms_per_step"] / base, 3)
     out["note"] = ("FP32 storage, launch shapes of the main run; mrt factors (0, -0.5, 0.3, -0.3); "
                    "repulsion: soft sphere between all mesh nodes, cutoff 0.3 (cells start apart)")
     return out
@@ -240,6 +246,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-obstacles", action="store_true")
+    ap.add_argument("--variant", default=None, choices=VARIANTS,
+                    help="time one engine variant only (FP32 storage; short profiled runs)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1312_3426_amd", "autotune.json"))
     ap.add_argument("--workload", default="precision", choices=["precision", "scale"])
     ap.add_argument("--only", default=None, choices=["fp32", "fp16", "bf16"],
@@ -266,6 +274,10 @@ def main():
         box = synth.config_scale(a.steps)
     N, M = box.n_nodes, box.n_mesh_nodes
     log(f"[bench] workload {box.name}: N={N} M={M} steps={a.steps} warmup={a.warmup}")
+    if a.variant:
+        v = variants(oif, box, a.steps, a.warmup, None if a.no_tune else a.tune_cache, only=a.variant)
+        print(json.dumps({"workload": box.name, "variant": a.variant, **v[a.variant]}), flush=True)
+        return
 
     res = {}
     for prec in ([a.only] if a.only else ["fp32", "fp16", "bf16"]):
