@@ -97,12 +97,52 @@ __device__ __forceinline__ void gstore(T* base, unsigned byte_off, T v) {
     *(gptr<T>)((gptr<char>)base + byte_off) = v;
 }
 template <typename T>
+__device__ __forceinline__ T gload(gptr<const T> base, unsigned byte_off) {
+    return *(gptr<const T>)((gptr<const char>)base + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(gptr<T> base, unsigned byte_off, T v) {
+    *(gptr<T>)((gptr<char>)base + byte_off) = v;
+}
+template <typename T>
 __device__ __forceinline__ T gld(const T* p) {
     return *(gptr<const T>)p;
 }
 template <typename T>
 __device__ __forceinline__ void gst(T* p, T v) {
     *(gptr<T>)p = v;
+}
+// Population buffers: the nodes in tiles of 64 (one wave's nodes), each tile
+// holding its 19 populations one after another, 64 values each, so value
+// (i, p) sits at element ((p / 64) * 19 + i) * 64 + p % 64 and a buffer holds
+// 19 * ceil(N / 64) * 64 values.  A wave then reads, and mostly writes, one
+// contiguous block of 19 x 64 values instead of touching 19 separate arrays.
+// The context keeps the padded buffer below 2^31 elements, so p / 64 < 2^24
+// and the tile product fits the 24-bit multiplier.
+constexpr unsigned POP_TILE = 19u * 64u;
+__device__ __forceinline__ unsigned pop_elem(int p) {
+    return __umul24((unsigned)p >> 6, POP_TILE) + ((unsigned)p & 63u);
+}
+template <typename S>
+__device__ __forceinline__ S pop_load(const S* f, int i, int p) {
+    return ((gptr<const S>)f + 64 * i)[pop_elem(p)];
+}
+template <typename S>
+__device__ __forceinline__ void pop_store(S* f, int i, int p, S v) {
+    ((gptr<S>)f + 64 * i)[pop_elem(p)] = v;
+}
+// A wave of the lattice kernel covers exactly one tile (its blocks are whole
+// multiples of 64 nodes): the tile's base is uniform and kept in SGPRs, and
+// each lane addresses its own value by a 32-bit byte offset from it.
+template <typename S>
+__device__ __forceinline__ gptr<S> wave_tile(S* f, int p) {
+    const unsigned t = __builtin_amdgcn_readfirstlane((unsigned)p >> 6);
+    return (gptr<S>)f + (size_t)t * POP_TILE;
+}
+template <typename S>
+__device__ __forceinline__ gptr<const S> wave_tile(const S* f, int p) {
+    const unsigned t = __builtin_amdgcn_readfirstlane((unsigned)p >> 6);
+    return (gptr<const S>)f + (size_t)t * POP_TILE;
 }
 // HIP's vector types are classes: load their native vector and repack
 __device__ __forceinline__ int2 gld(const int2* p) {

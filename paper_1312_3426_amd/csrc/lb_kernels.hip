@@ -201,9 +201,10 @@ template <int P>
 __device__ __forceinline__ void load_pops(const BoxDev* __restrict__ B, int p, int parity,
                                           typename Prec<P>::S (&raw)[19]) {
     typedef typename Prec<P>::S S;
-    const S* __restrict__ src = (const S*)B->f[parity];
+    const gptr<const S> tile = wave_tile((const S*)B->f[parity], p);
+    const unsigned lane = (unsigned)(p & 63) * (unsigned)sizeof(S);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) raw[i] = gload(src + (size_t)i * B->N, (unsigned)p * (unsigned)sizeof(S));
+    for (int i = 0; i < 19; ++i) raw[i] = gload(tile, lane + 64u * (unsigned)sizeof(S) * i);
 }
 
 template <int P, bool OBST, bool MRT>
@@ -213,8 +214,9 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
                                              unsigned links) {
     typedef typename Prec<P>::S S;
     typedef typename Prec<P>::R R;
-    const int N = B->N;
     S* __restrict__ dst = (S*)B->f[parity ^ 1];
+    const gptr<S> tile = wave_tile(dst, p);
+    const unsigned lane = (unsigned)(p & 63) * (unsigned)sizeof(S);
     const float inv = B->st_inv, scale = B->st_scale;
 
     // an obstacle node is not updated (its link word was loaded beside the
@@ -228,10 +230,10 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
 
     // neighbour offsets with periodic wrap
     const int nx = B->nx, ny = B->ny, nz = B->nz;
-    const int x = p % nx;
-    const int t = p / nx;
-    const int y = t % ny;
-    const int z = t / ny;
+    const int t = B->div_nx ? (int)(__umulhi((unsigned)p, B->div_nx) >> B->sh_nx) : p;
+    const int x = p - t * nx;
+    const int z = B->div_ny ? (int)(__umulhi((unsigned)t, B->div_ny) >> B->sh_ny) : t;
+    const int y = t - z * ny;
     const int plane = nx * ny;
     // wall velocity of the one moving boundary next to this node (if any)
     R wx = R(0), wy = R(0), wz = R(0);
@@ -253,7 +255,7 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
         const S out = enc<P>(ds, scale);
         const bool bounce = (cz(i) > 0 && whi) || (cz(i) < 0 && wlo);
         if (bounce) {
-            gstore(dst + (size_t)opp(i) * N, (unsigned)p * (unsigned)sizeof(S), out);
+            gstore(tile, lane + 64u * (unsigned)sizeof(S) * opp(i), out);
         } else {
             const int off = (cx(i) > 0 ? oxp : (cx(i) < 0 ? oxm : 0)) +
                             (cy(i) > 0 ? oyp : (cy(i) < 0 ? oym : 0)) +
@@ -272,9 +274,9 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
                     }
                     val = enc<P>(ds - R(6) * wt<R>(i) * (R)B->rho0 * euw, scale);
                 }
-                gstore(dst + (size_t)opp(i) * N, (unsigned)p * (unsigned)sizeof(S), val);
+                gstore(tile, lane + 64u * (unsigned)sizeof(S) * opp(i), val);
             } else {
-                gstore(dst + (size_t)i * N, (unsigned)(p + off) * (unsigned)sizeof(S), out);
+                pop_store(dst, i, p + off, out);
             }
         }
     }
@@ -359,7 +361,7 @@ diag_lattice_kernel(const BoxDev* __restrict__ B, int parity, double* __restrict
         double d[19];
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            d[i] = (double)dec<P>(src[(size_t)i * N + p], inv);
+            d[i] = (double)dec<P>(pop_load(src, i, p), inv);
             if (!isfinite(d[i])) bad = 1.0;
         }
 #pragma unroll
@@ -400,9 +402,9 @@ __global__ void pops_to_f64_kernel(const BoxDev* __restrict__ B, int parity, dou
     const int N = B->N;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (size_t)19 * N) return;
-    const int i = (int)(k / N);
+    const int i = (int)(k / N), p = (int)(k - (size_t)i * N);
     const S* src = (const S*)B->f[parity];
-    out[k] = weight_of(i) * B->rho0 + (double)dec<P>(src[k], B->st_inv);
+    out[k] = weight_of(i) * B->rho0 + (double)dec<P>(pop_load(src, i, p), B->st_inv);
 }
 
 template <int P>
@@ -412,9 +414,9 @@ __global__ void f64_to_pops_kernel(const BoxDev* __restrict__ B, int parity, con
     const int N = B->N;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (size_t)19 * N) return;
-    const int i = (int)(k / N);
+    const int i = (int)(k / N), p = (int)(k - (size_t)i * N);
     S* dst = (S*)B->f[parity];
-    dst[k] = enc<P>((R)(in[k] - weight_of(i) * B->rho0), B->st_scale);
+    pop_store(dst, i, p, enc<P>((R)(in[k] - weight_of(i) * B->rho0), B->st_scale));
 }
 
 template <int P>
@@ -437,7 +439,7 @@ __global__ void moments_kernel(const BoxDev* __restrict__ B, int parity, double*
     const S* src = (const S*)B->f[parity];
     double d[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = (double)dec<P>(src[(size_t)i * N + p], B->st_inv);
+    for (int i = 0; i < 19; ++i) d[i] = (double)dec<P>(pop_load(src, i, p), B->st_inv);
     double dr = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < 19; ++i) {

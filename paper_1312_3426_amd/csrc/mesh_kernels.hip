@@ -338,7 +338,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     const R cv = (R)(-T->kv * (Vol - T->V0) / T->V0); // volume coefficient
     const R kal = (R)T->kal;
     const R third = R(1) / R(3);
-    const int nxb = B->nx, nyb = B->ny, nzb = B->nz, Nb = B->N;
+    const int nxb = B->nx, nyb = B->ny, nzb = B->nz;
     const S* __restrict__ pop = (const S*)B->f[parity];
     const float inv = B->st_inv;
     const R gx_ = (R)B->g[0], gy_ = (R)B->g[1], gz_ = (R)B->g[2];
@@ -531,7 +531,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                 R dd[19];
 #pragma unroll
                 for (int i = 0; i < 19; ++i)
-                    dd[i] = dec<P>(gload(pop + (size_t)i * Nb, (unsigned)q * (unsigned)sizeof(S)), inv);
+                    dd[i] = dec<P>(pop_load(pop, i, q), inv);
                 R dr = 0;
 #pragma unroll
                 for (int i = 0; i < 19; ++i) dr += dd[i];
@@ -627,7 +627,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                     }
 #pragma unroll
                     for (int i = 0; i < 19; ++i)
-                        dd[i] = dec<P>(gload(pop + (size_t)i * Nb, (unsigned)qk * (unsigned)sizeof(S)), inv);
+                        dd[i] = dec<P>(pop_load(pop, i, qk), inv);
                     R dr = 0;
 #pragma unroll
                     for (int i = 0; i < 19; ++i) dr += dd[i];

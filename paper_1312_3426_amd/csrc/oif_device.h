@@ -2,9 +2,11 @@
 // and the launchers the host runtime calls.  Internal to liboif.so.
 //
 // HBM layout of one box (context):
-//   f[2]   two population buffers, each [19][N] of the storage type, holding
-//          deviations n_i - w_i rho0 (SoA, x fastest inside a plane); the step
-//          reads f[parity] and writes f[parity ^ 1]
+//   f[2]   two population buffers of the storage type, holding deviations
+//          n_i - w_i rho0, nodes numbered x fastest, then y, then z; tiles of
+//          64 consecutive nodes, each tile [19][64] (value (i, p) at element
+//          ((p / 64) * 19 + i) * 64 + p % 64, N rounded up to whole tiles);
+//          the step reads f[parity] and writes f[parity ^ 1]
 //   G      coupling force density, [3][N]: double (FP64 form) or int64 fixed
 //          point with resolution 2^-e (FP32 forms, order-independent sums)
 //   mask   one bit per node, set where G is non-zero; the lattice kernel reads
@@ -28,6 +30,10 @@ struct BoxDev {
     int nx, ny, nz, walls_z;
     int N;
     int precision;
+    // node index -> coordinates without a hardware divide: for d = nx or ny,
+    // q / d = umulhi(q, div) >> sh for every q < 2^31 (div = 0 marks d = 1)
+    unsigned div_nx, div_ny;
+    int sh_nx, sh_ny;
     void* f[2];
     void* G;
     unsigned long long* mask;

@@ -301,6 +301,24 @@ struct oif_ctx {
     int diag_blocks = 256;
 };
 
+// Multiplier and shift that divide any q < 2^31 by d (1 <= d <= 4096):
+// q / d = (q * m) >> (32 + s) with s = ceil(log2 d) - 1 and m = floor(2^(32+s) / d) + 1.
+// With e = m d - 2^(32+s), 0 < e <= d <= 2^(s+1), the product overshoots q / d
+// by q e / (d 2^(32+s)) < 1 / d, less than the distance from q / d to the next
+// integer; m < 2^32 because d > 2^s unless d is a power of two (then m = 2^31 + 1).
+// d = 1 is marked by m = 0 (the kernel takes the quotient as q).
+static void div_magic(int d, unsigned* m, int* s) {
+    if (d <= 1) { *m = 0; *s = 0; return; }
+    int k = 0;
+    while ((1 << k) < d) ++k;
+    *s = k - 1;
+    *m = (unsigned)(((unsigned long long)1 << (32 + k - 1)) / (unsigned long long)d + 1);
+}
+
+// Bytes of one population buffer: 19 values per node in tiles of 64 nodes,
+// the node count rounded up to whole tiles.
+static size_t pop_bytes(const oif_ctx* c) { return 19 * (((size_t)c->N + 63) & ~(size_t)63) * c->st_size; }
+
 struct oif_batch {
     std::vector<oif_ctx*> ctx;
     std::string err;
@@ -851,7 +869,7 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     const oif_lattice_desc& d = *desc;
     const long long N = (long long)d.nx * d.ny * d.nz;
     bool ok = d.nx >= 1 && d.ny >= 1 && d.nz >= 1 && d.nx <= 4096 && d.ny <= 4096 && d.nz <= 4096 &&
-              N * 19 < (1LL << 31) && std::isfinite(d.tau) && d.tau > 0.5 && std::isfinite(d.rho0) &&
+              (N + 63) / 64 * 64 * 19 < (1LL << 31) && std::isfinite(d.tau) && d.tau > 0.5 && std::isfinite(d.rho0) &&
               d.rho0 > 0 && std::isfinite(d.friction) && d.friction >= 0 && d.precision >= 0 &&
               d.precision <= 3 && d.fp16_scale_exp >= 0 && d.fp16_scale_exp <= 24 &&
               d.fixed_point_exp >= 16 && d.fixed_point_exp <= 56 && (!d.walls_z || d.nz >= 2);
@@ -889,7 +907,7 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
         if (hipMalloc(p, n) != hipSuccess) { *p = nullptr; return OIF_E_NOMEM; }
         return OIF_OK;
     };
-    const size_t popb = 19 * (size_t)N * c->st_size;
+    const size_t popb = pop_bytes(cp);
     const size_t nmask = ((size_t)N + 63) / 64;
     int rc = OIF_OK;
     if ((rc = alloc(&c->f[0], popb)) || (rc = alloc(&c->f[1], popb)) || (rc = alloc(&c->G, 24 * (size_t)N)) ||
@@ -914,6 +932,8 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     b.nx = d.nx; b.ny = d.ny; b.nz = d.nz; b.walls_z = d.walls_z ? 1 : 0;
     b.N = (int)N;
     b.precision = d.precision;
+    div_magic(d.nx, &b.div_nx, &b.sh_nx);
+    div_magic(d.ny, &b.div_ny, &b.sh_ny);
     b.f[0] = c->f[0]; b.f[1] = c->f[1];
     b.G = c->G;
     b.mask = c->mask;
@@ -1055,8 +1075,7 @@ int upload_boundaries(oif_ctx* c) {
         c->box.wall_u = (const double*)c->wall_dev;
     }
     HIPCALL(c, hipMemcpy(c->box_dev, &c->box, sizeof(BoxDev), hipMemcpyHostToDevice));
-    HIPCALL(c, hipMemcpy(c->f[c->parity ^ 1], c->f[c->parity], 19 * (size_t)c->N * c->st_size,
-                         hipMemcpyDeviceToDevice));
+    HIPCALL(c, hipMemcpy(c->f[c->parity ^ 1], c->f[c->parity], pop_bytes(c), hipMemcpyDeviceToDevice));
     // launches and batches hold copies of the box descriptor: rebuild them
     c->mesh_dirty = true;
     drop_graph(c);
@@ -1560,10 +1579,11 @@ int oif_info(oif_ctx* c, oif_info_t* info) {
     info->n_nodes = c->N;
     info->n_mesh_nodes = c->M;
     info->steps_done = c->steps;
-    long long bytes = 2 * 19LL * c->N * (long long)c->st_size + 24LL * c->N + 8LL * ((c->N + 63) / 64);
+    long long bytes = 2 * (long long)pop_bytes(c) + 24LL * c->N + 8LL * ((c->N + 63) / 64);
     for (auto& b : c->tbufs) bytes += (long long)b.n;
     for (const DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->F_dev, &c->geo_dev,
-                            &c->scratch_dev})
+                            &c->scratch_dev, &c->rep_pos, &c->rep_cell, &c->rep_cnt, &c->rep_cursor, &c->rep_bsum,
+                            &c->rep_list, &c->rep_spos, &c->rep_stype, &c->rep_frep, &c->rep_type, &c->rep_shape})
         bytes += (long long)b->n;
     info->device_bytes = bytes;
     info->lb_block = c->lb_block;
@@ -1729,7 +1749,7 @@ struct Snapshot {
 };
 
 int snapshot(oif_ctx* c, Snapshot& s, bool restore) {
-    const size_t pb = 19 * (size_t)c->N * c->st_size;
+    const size_t pb = pop_bytes(c);
     const size_t mb = 3 * (size_t)c->M * real_size(c->d.precision);
     const size_t xb = 3 * (size_t)c->M * sizeof(double);
     if (!restore) {
