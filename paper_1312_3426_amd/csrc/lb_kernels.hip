@@ -203,8 +203,11 @@ __device__ __forceinline__ void load_pops(const BoxDev* __restrict__ B, int p, i
     typedef typename Prec<P>::S S;
     const gptr<const S> tile = wave_tile((const S*)B->f[parity], p);
     const unsigned lane = (unsigned)(p & 63) * (unsigned)sizeof(S);
+    // non-temporal: these values are dead once read, so they should not push
+    // the freshly pushed values (read again by the next step) out of the caches
 #pragma unroll
-    for (int i = 0; i < 19; ++i) raw[i] = gload(tile, lane + 64u * (unsigned)sizeof(S) * i);
+    for (int i = 0; i < 19; ++i)
+        raw[i] = __builtin_nontemporal_load((gptr<const S>)((gptr<const char>)tile + lane + 64u * (unsigned)sizeof(S) * i));
 }
 
 template <int P, bool OBST, bool MRT>

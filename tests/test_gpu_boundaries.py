@@ -50,10 +50,12 @@ def test_boundary_shapes_match_oracle(oif, orc, k):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("walls", [False, True])
-def test_lattice_with_obstacles_vs_oracle(oif, orc, prec, walls):
+@pytest.mark.parametrize("nx", [14, 128])
+def test_lattice_with_obstacles_vs_oracle(oif, orc, prec, walls, nx):
     """Random populations, a resting sheared rhomboid, a sliding wall and a
-    moving slab, body force; 12 steps of the lattice alone."""
-    nx, ny, nz = 14, 11, 9
+    moving slab, body force; 12 steps of the lattice alone (rows of 14 nodes,
+    and rows of two whole 64-node tiles)."""
+    ny, nz = 11, 9
     bnd = [B("rhomboid", corner=(3.2, 2.1, 1.3), a=(4.0, 0.6, 0), b=(0.8, 3.9, 0.4), c=(0.2, 0.3, 4.1)),
            B("wall", normal=(0, 1, 0), dist=1.0, velocity=(0.02, 0, 0.01)),
            B("rhomboid", corner=(11, 0, 0), a=(2, 0, 0), b=(0, ny, 0), c=(0, 0, nz), velocity=(0.015, 0, 0))]
@@ -67,7 +69,7 @@ def test_lattice_with_obstacles_vs_oracle(oif, orc, prec, walls):
     c.step(12)
     s.run(12)
     res = check(gpu_fields(c, box.rho0, None), oracle_fields(s, None), prec, box.rho0, nx)
-    say(f"[obstacles] lattice {prec} walls={walls}: {fmt(res)}")
+    say(f"[obstacles] lattice {prec} walls={walls} nx={nx}: {fmt(res)}")
     c.close()
     assert all(v[3] for v in res.values()), fmt(res)
 

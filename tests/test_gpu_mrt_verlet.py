@@ -41,6 +41,7 @@ LB_CASES = [
     (20, 20, 20, False),   # 8000 nodes: 31.25 blocks of 256
     (9, 7, 11, True),      # ragged, bounce-back walls
     (2, 2, 2, False),      # every neighbour wraps onto the box
+    (128, 2, 3, True),     # rows of two whole tiles: x pushes cross tiles
 ]
 
 

@@ -43,6 +43,7 @@ LB_CASES = [
     (64, 1, 1, False, 1.7),     # single row, exactly one wave
     (2, 2, 2, False, 0.9),      # every neighbour wraps onto the box
     (130, 3, 4, True, 1.1),     # even rows of 65 node pairs: row ends inside a wave
+    (128, 3, 5, True, 0.7),     # rows of two whole tiles: x pushes cross tiles
 ]
 
 
