@@ -91,7 +91,8 @@ def measure(oif, box, prec, steps, warmup, graph_steps=0, tune=None):
     t = ctx.step_timed(steps)
     info = ctx.info()
     out = dict(total_ms=t.total_ms, lb_ms=t.lb_ms, mesh_ms=t.mesh_ms, lb_block=info.lb_block,
-               mesh_block=info.mesh_block, xcd_remap=info.xcd_remap, max_lds=info.max_lds,
+               mesh_block=info.mesh_block, xcd_remap=info.xcd_remap, nt_loads=info.lb_nontemporal,
+               max_lds=info.max_lds,
                lds_objects=info.lds_objects)
     if graph_steps:
         ctx.set_graph(graph_steps)
@@ -316,7 +317,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": box.name, "nx": box.nx, "ny": box.ny, "nz": box.nz, "cells": len(box.objects),
-                   "mesh_nodes": M, "storage": "fp32", "launch": {k: r32[k] for k in ("lb_block", "mesh_block", "xcd_remap")}},
+                   "mesh_nodes": M, "storage": "fp32", "launch": {k: r32[k] for k in ("lb_block", "mesh_block", "xcd_remap", "nt_loads")}},
         "mesh_node_updates_per_s": round(M / (ms_step * 1e-3), 1),
         "kernel_ms": {"lb": round(r32["lb_ms"], 5), "mesh": round(r32["mesh_ms"], 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

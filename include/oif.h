@@ -143,6 +143,7 @@ typedef struct {
     int lds_objects;    /* objects whose mesh is staged in LDS (the rest use global scratch) */
     int overlap;        /* 1 if untouched nodes are updated concurrently with the membrane kernel */
     int integrator;     /* OIF_INTEGRATOR_EULER or OIF_INTEGRATOR_VERLET */
+    int lb_nontemporal; /* population reads of the lattice kernel: 1 non-temporal, 0 ordinary */
 } oif_info_t;
 
 /* FP64 conservation diagnostics and watchdog state. */
@@ -343,6 +344,16 @@ int oif_set_overlap(oif_ctx* ctx, int on);
  * setting. */
 int oif_set_launch(oif_ctx* ctx, int lb_block, int mesh_block, int xcd_remap);
 
+/* Cache policy of the lattice kernel's population reads (the stored
+ * populations of the collide-and-push update, Section "Method"): 1 issues
+ * them as non-temporal loads (a value is dead once read, so these reads do not
+ * displace the values just pushed, which the next step reads: this pays while
+ * the two population buffers are not much larger than the last-level cache),
+ * 0 as ordinary loads.  The results are identical either way.  Default: 1 when
+ * the two buffers together hold at most 1 GiB, else 0; the autotuner measures
+ * both.  OIF_E_ARG for a value other than 0 or 1. */
+int oif_set_lb_loads(oif_ctx* ctx, int nontemporal);
+
 
 /* Measured search of the launch shapes on this context's workload; the
  * choice is applied and, if cache_path is not NULL, stored there as JSON
@@ -409,6 +420,7 @@ int oif_batch_destroy(oif_batch* b);
 int oif_batch_step(oif_batch* b, int n_steps);
 int oif_batch_set_graph(oif_batch* b, int steps_per_graph);
 int oif_batch_set_launch(oif_batch* b, int lb_block, int mesh_block, int xcd_remap);
+int oif_batch_set_lb_loads(oif_batch* b, int nontemporal);
 int oif_batch_autotune(oif_batch* b, const char* cache_path);
 int oif_batch_step_timed(oif_batch* b, int n_steps, oif_timing* t);
 const char* oif_batch_last_error(const oif_batch* b);

@@ -197,17 +197,25 @@ __device__ __forceinline__ void collide_mrt(const BoxDev* __restrict__ B, R (&d)
 // obstacles (OBST), a push into a solid node (bit i of `links`) returns to p in
 // the opposite direction, less 6 w_i rho0 (e_i . u_wall) (bounce-back from a
 // moving obstacle).
-template <int P>
+// NT: non-temporal reads (a value is dead once read, so these reads need not
+// displace the values just pushed, which the next step reads); the values are
+// the same either way.  A template choice: two branches that differ only in
+// the cache hint are merged by the compiler, hint dropped.
+template <int P, bool NT>
 __device__ __forceinline__ void load_pops(const BoxDev* __restrict__ B, int p, int parity,
                                           typename Prec<P>::S (&raw)[19]) {
     typedef typename Prec<P>::S S;
     const gptr<const S> tile = wave_tile((const S*)B->f[parity], p);
     const unsigned lane = (unsigned)(p & 63) * (unsigned)sizeof(S);
-    // non-temporal: these values are dead once read, so they should not push
-    // the freshly pushed values (read again by the next step) out of the caches
+    if (NT) {
 #pragma unroll
-    for (int i = 0; i < 19; ++i)
-        raw[i] = __builtin_nontemporal_load((gptr<const S>)((gptr<const char>)tile + lane + 64u * (unsigned)sizeof(S) * i));
+        for (int i = 0; i < 19; ++i)
+            raw[i] = __builtin_nontemporal_load(
+                (gptr<const S>)((gptr<const char>)tile + lane + 64u * (unsigned)sizeof(S) * i));
+    } else {
+#pragma unroll
+        for (int i = 0; i < 19; ++i) raw[i] = gload(tile, lane + 64u * (unsigned)sizeof(S) * i);
+    }
 }
 
 template <int P, bool OBST, bool MRT>
@@ -289,7 +297,7 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
 // ALL: mode is LB_ALL (every node is updated, so the population loads go out
 // first and are in flight while the mask word and any coupling force are
 // fetched).  MRT: the boxes use the multiple-relaxation-time collision.
-template <int P, bool OBST, bool ALL, bool MRT>
+template <int P, bool OBST, bool ALL, bool MRT, bool NT>
 __global__ void __launch_bounds__(1024)
 lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int nblocks, int parity,
           int remap, int mode) {
@@ -313,7 +321,7 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
     const int p = blk * (int)blockDim.x + (int)threadIdx.x;
     if (p >= N) return;
     S raw[19];
-    if (ALL) load_pops<P>(B, p, parity, raw);
+    if (ALL) load_pops<P, NT>(B, p, parity, raw);
 
     // Force density: body force plus the coupling force G where the node's mask
     // bit is set.  Mask and touch words cover exactly one wave's 64 nodes; all
@@ -346,7 +354,7 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
     // obstacles: which of the node's pushes end in a solid node (and whether
     // the node itself is solid, tested once its populations are loaded)
     const unsigned links = (OBST && B->links) ? gld(B->links + p) : 0u;
-    if (!ALL) load_pops<P>(B, p, parity, raw);
+    if (!ALL) load_pops<P, NT>(B, p, parity, raw);
     if ((m >> (p & 63)) & 1ull) take_force<P>(B, p, fx, fy, fz);
     collide_push<P, OBST, MRT>(B, p, raw, fx, fy, fz, parity, links);
 }
@@ -487,19 +495,22 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
 
 template <int P>
 void launch_lb_p(const LbLaunch& L) {
-#define OIF_LB(O, A, M)                                                                                     \
-    hipLaunchKernelGGL((lb_kernel<P, O, A, M>), dim3(L.nblocks), dim3(L.block), 0, L.stream, L.boxes, L.work, \
+#define OIF_LB(O, A, M, NT)                                                                                     \
+    hipLaunchKernelGGL((lb_kernel<P, O, A, M, NT>), dim3(L.nblocks), dim3(L.block), 0, L.stream, L.boxes, L.work, \
                        L.nblocks, L.parity, L.remap, L.mode)
-#define OIF_LB_M(O, A)         \
-    if (L.mrt) OIF_LB(O, A, true); \
-    else OIF_LB(O, A, false)
+#define OIF_LB_M(O, A, NT)             \
+    if (L.mrt) OIF_LB(O, A, true, NT); \
+    else OIF_LB(O, A, false, NT)
+    // the split step's two launches keep ordinary reads
     const bool all = L.mode == LB_ALL;
     if (L.obstacles) {
-        if (all) OIF_LB_M(true, true);
-        else OIF_LB_M(true, false);
+        if (!all) OIF_LB_M(true, false, false);
+        else if (L.nt) OIF_LB_M(true, true, true);
+        else OIF_LB_M(true, true, false);
     } else {
-        if (all) OIF_LB_M(false, true);
-        else OIF_LB_M(false, false);
+        if (!all) OIF_LB_M(false, false, false);
+        else if (L.nt) OIF_LB_M(false, true, true);
+        else OIF_LB_M(false, true, false);
     }
 #undef OIF_LB_M
 #undef OIF_LB

@@ -216,6 +216,7 @@ struct LbLaunch {
     int mode;              // LB_ALL, LB_FREE or LB_TOUCHED
     int obstacles;         // the boxes of the launch have obstacles
     int mrt;               // the boxes of the launch use the MRT collision
+    int nt;                // population reads are non-temporal (all-node launches)
 };
 hipError_t launch_lb(const LbLaunch& L);
 

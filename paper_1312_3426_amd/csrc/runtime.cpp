@@ -292,6 +292,7 @@ struct oif_ctx {
 
     // launch configuration
     int lb_block = 256, mesh_block = 256, remap = 1;
+    int lb_nt = 0;  // population reads of the lattice kernel non-temporal
     int graph_steps = 0;
     hipGraphExec_t gexec = nullptr;
     int g_len = 0;
@@ -332,6 +333,7 @@ struct oif_batch {
     size_t lds_need = 0;
     int any_conservative = 0;
     int lb_block = 256, mesh_block = 256, remap = 1;
+    int lb_nt = 0;
     int graph_steps = 0;
     hipGraphExec_t gexec = nullptr;
     int g_len = 0;
@@ -712,6 +714,7 @@ int enqueue_lb(oif_ctx* c, int par, hipStream_t s, int mode) {
     ll.mode = mode;
     ll.obstacles = c->n_bnd > 0;
     ll.mrt = c->box.mrt;
+    ll.nt = c->lb_nt;
     HIPCALL(c, launch_lb(ll));
     return OIF_OK;
 }
@@ -886,6 +889,9 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     c->d = d;
     c->N = (int)N;
     c->st_size = d.precision == OIF_PREC_FP64 ? 8 : (d.precision == OIF_PREC_FP32 ? 4 : 2);
+    // non-temporal population reads pay while the two buffers are not much
+    // larger than the last-level cache (the autotuner measures both)
+    c->lb_nt = 2 * pop_bytes(c.get()) <= ((size_t)1 << 30) ? 1 : 0;
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, d.device) == hipSuccess && lds > 0)
         c->max_lds = (size_t)lds;
@@ -1481,6 +1487,14 @@ int oif_set_launch(oif_ctx* c, int lb_block, int mesh_block, int xcd_remap) {
     return OIF_OK;
 }
 
+int oif_set_lb_loads(oif_ctx* c, int nontemporal) {
+    if (!c) return OIF_E_ARG;
+    if (nontemporal != 0 && nontemporal != 1) return fail(c, OIF_E_ARG, "nontemporal must be 0 or 1");
+    c->lb_nt = nontemporal;
+    drop_graph(c);
+    return OIF_OK;
+}
+
 int oif_read_populations(oif_ctx* c, double* out) {
     if (!c || !out) return OIF_E_ARG;
     double* tmp = nullptr;
@@ -1594,6 +1608,7 @@ int oif_info(oif_ctx* c, oif_info_t* info) {
     info->overlap = c->overlap;
     info->lds_objects = c->n_lds_obj;
     info->integrator = c->integrator;
+    info->lb_nontemporal = c->lb_nt;
     return OIF_OK;
 }
 
@@ -1694,7 +1709,7 @@ std::string tune_key(int prec, const std::vector<std::array<int, 3>>& dims, long
     return k.str();
 }
 
-bool cache_lookup(const char* path, const std::string& key, int out[3]) {
+bool cache_lookup(const char* path, const std::string& key, int out[4]) {
     if (!path) return false;
     std::ifstream f(path);
     if (!f) return false;
@@ -1704,29 +1719,35 @@ bool cache_lookup(const char* path, const std::string& key, int out[3]) {
     const std::string pat = "\"" + key + "\": [";
     const size_t p = s.find(pat);
     if (p == std::string::npos) return false;
-    return std::sscanf(s.c_str() + p + pat.size(), "%d, %d, %d", &out[0], &out[1], &out[2]) == 3;
+    int v[4];
+    if (std::sscanf(s.c_str() + p + pat.size(), "%d, %d, %d, %d", &v[0], &v[1], &v[2], &v[3]) != 4) return false;
+    for (int k = 0; k < 4; ++k) out[k] = v[k];
+    return true;
 }
 
-void cache_store(const char* path, const std::string& key, const int v[3]) {
+// Entries are [lb_block, mesh_block, xcd_remap, nontemporal]; entries of
+// another form are dropped (and tuned again when asked for).
+void cache_store(const char* path, const std::string& key, const int v[4]) {
     if (!path) return;
-    std::map<std::string, std::array<int, 3>> entries;
+    std::map<std::string, std::array<int, 4>> entries;
     {
         std::ifstream f(path);
         std::string line;
         while (std::getline(f, line)) {
             const size_t a = line.find('"'), b = line.find("\": [");
             if (a == std::string::npos || b == std::string::npos || b <= a) continue;
-            std::array<int, 3> e{};
-            if (std::sscanf(line.c_str() + b + 4, "%d, %d, %d", &e[0], &e[1], &e[2]) == 3)
+            std::array<int, 4> e{};
+            if (std::sscanf(line.c_str() + b + 4, "%d, %d, %d, %d", &e[0], &e[1], &e[2], &e[3]) == 4)
                 entries[line.substr(a + 1, b - a - 1)] = e;
         }
     }
-    entries[key] = {v[0], v[1], v[2]};
+    entries[key] = {v[0], v[1], v[2], v[3]};
     std::ofstream f(path);
     f << "{\n";
     size_t i = 0;
     for (auto& kv : entries) {
-        f << "  \"" << kv.first << "\": [" << kv.second[0] << ", " << kv.second[1] << ", " << kv.second[2] << "]";
+        f << "  \"" << kv.first << "\": [" << kv.second[0] << ", " << kv.second[1] << ", " << kv.second[2] << ", "
+          << kv.second[3] << "]";
         f << (++i < entries.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -1788,25 +1809,31 @@ extern "C" int oif_autotune(oif_ctx* c, const char* cache_path) {
     int rc = sync_mesh(c);
     if (rc) return rc;
     const std::string key = tune_key(c->d.precision, {{c->d.nx, c->d.ny, c->d.nz}}, (long long)c->obj.size(), c->M);
-    int best[3];
-    if (cache_lookup(cache_path, key, best)) return oif_set_launch(c, best[0], best[1], best[2]);
+    int best[4];
+    if (cache_lookup(cache_path, key, best)) {
+        rc = oif_set_launch(c, best[0], best[1], best[2]);
+        return rc ? rc : oif_set_lb_loads(c, best[3]);
+    }
     Snapshot s;
     if ((rc = snapshot(c, s, false))) return rc;
     const int overlap = c->overlap;
     c->overlap = 0;  // time each kernel alone
     const int reps = 6;  // even: parity is unchanged after each trial
     double best_lb = 1e300, best_mesh = 1e300;
-    best[0] = c->lb_block; best[1] = c->mesh_block; best[2] = c->remap;
-    for (int lb : {128, 256, 512, 1024})
-        for (int rm : {0, 1}) {
-            c->lb_block = lb;
-            c->remap = rm;
-            double tl, tm;
-            if ((rc = time_steps(c, reps, &tl, &tm))) return rc;
-            if (tl < best_lb) { best_lb = tl; best[0] = lb; best[2] = rm; }
-        }
+    best[0] = c->lb_block; best[1] = c->mesh_block; best[2] = c->remap; best[3] = c->lb_nt;
+    for (int nt : {0, 1})
+        for (int lb : {128, 256, 512, 1024})
+            for (int rm : {0, 1}) {
+                c->lb_block = lb;
+                c->remap = rm;
+                c->lb_nt = nt;
+                double tl, tm;
+                if ((rc = time_steps(c, reps, &tl, &tm))) return rc;
+                if (tl < best_lb) { best_lb = tl; best[0] = lb; best[2] = rm; best[3] = nt; }
+            }
     c->lb_block = best[0];
     c->remap = best[2];
+    c->lb_nt = best[3];
     if (!c->obj.empty())
         for (int mb : {128, 256, 384, 512, 640, 768, 1024}) {
             c->mesh_block = mb;
@@ -1950,7 +1977,7 @@ int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<h
         for (int v = 0; v < 4; ++v) {
             LbLaunch ll{(const BoxDev*)b->boxes_dev.p, (const int2*)b->work_dev.p + b->var_off[v],
                         b->var_off[v + 1] - b->var_off[v], b->lb_block, par, b->remap, b->precision, s,
-                        LB_ALL, v & 1, v >> 1};
+                        LB_ALL, v & 1, v >> 1, b->lb_nt};
             if (ll.nblocks > 0) BHIP(b, launch_lb(ll));
         }
         if (ev) (void)hipEventRecord((*ev)[3 * k + 2], s);
@@ -1999,6 +2026,7 @@ int oif_batch_create(oif_ctx* const* boxes, int n, oif_batch** out) {
     b->lb_block = boxes[0]->lb_block;
     b->mesh_block = boxes[0]->mesh_block;
     b->remap = boxes[0]->remap;
+    b->lb_nt = boxes[0]->lb_nt;
     *out = b.release();
     return OIF_OK;
 }
@@ -2032,6 +2060,13 @@ int oif_batch_set_launch(oif_batch* b, int lb_block, int mesh_block, int xcd_rem
     if (mesh_block >= 0) b->mesh_block = mesh_block;
     if (xcd_remap >= 0) b->remap = xcd_remap ? 1 : 0;
     b->built = false;
+    bdrop_graph(b);
+    return OIF_OK;
+}
+
+int oif_batch_set_lb_loads(oif_batch* b, int nontemporal) {
+    if (!b || (nontemporal != 0 && nontemporal != 1)) return OIF_E_ARG;
+    b->lb_nt = nontemporal;
     bdrop_graph(b);
     return OIF_OK;
 }
@@ -2112,8 +2147,11 @@ int oif_batch_autotune(oif_batch* b, const char* cache_path) {
         M += c->M;
     }
     const std::string key = tune_key(b->precision, dims, nobj, M);
-    int best[3] = {b->lb_block, b->mesh_block, b->remap};
-    if (cache_lookup(cache_path, key, best)) return oif_batch_set_launch(b, best[0], best[1], best[2]);
+    int best[4] = {b->lb_block, b->mesh_block, b->remap, b->lb_nt};
+    if (cache_lookup(cache_path, key, best)) {
+        const int rc = oif_batch_set_launch(b, best[0], best[1], best[2]);
+        return rc ? rc : oif_batch_set_lb_loads(b, best[3]);
+    }
     int rc = batch_prepare(b);
     if (rc) return rc;
     std::vector<Snapshot> snaps(b->ctx.size());
@@ -2131,14 +2169,17 @@ int oif_batch_autotune(oif_batch* b, const char* cache_path) {
         *tm = t.mesh_ms;
         return r;
     };
-    for (int lb : {128, 256, 512, 1024})
-        for (int rm : {0, 1}) {
-            oif_batch_set_launch(b, lb, -1, rm);
-            double tl, tm;
-            if ((rc = trial(&tl, &tm))) return rc;
-            if (tl < best_lb) { best_lb = tl; best[0] = lb; best[2] = rm; }
-        }
+    for (int nt : {0, 1})
+        for (int lb : {128, 256, 512, 1024})
+            for (int rm : {0, 1}) {
+                oif_batch_set_launch(b, lb, -1, rm);
+                oif_batch_set_lb_loads(b, nt);
+                double tl, tm;
+                if ((rc = trial(&tl, &tm))) return rc;
+                if (tl < best_lb) { best_lb = tl; best[0] = lb; best[2] = rm; best[3] = nt; }
+            }
     oif_batch_set_launch(b, best[0], -1, best[2]);
+    oif_batch_set_lb_loads(b, best[3]);
     for (int mb : {128, 256, 384, 512, 640, 768, 1024}) {
         oif_batch_set_launch(b, -1, mb, -1);
         double tl, tm;

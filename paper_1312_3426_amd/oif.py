@@ -56,7 +56,7 @@ class Info(C.Structure):
                 ("steps_done", C.c_longlong), ("device_bytes", C.c_longlong), ("lb_block", C.c_int),
                 ("mesh_block", C.c_int), ("xcd_remap", C.c_int), ("graph_steps", C.c_int),
                 ("max_lds", C.c_longlong), ("lds_objects", C.c_int), ("overlap", C.c_int),
-                ("integrator", C.c_int)]
+                ("integrator", C.c_int), ("lb_nontemporal", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -92,6 +92,7 @@ SIGNATURES = {
     "oif_set_graph": (_i, [_vp, _i]),
     "oif_set_overlap": (_i, [_vp, _i]),
     "oif_set_launch": (_i, [_vp, _i, _i, _i]),
+    "oif_set_lb_loads": (_i, [_vp, _i]),
     "oif_set_mrt": (_i, [_vp, _vp]),
     "oif_set_integrator": (_i, [_vp, _i]),
     "oif_set_soft_sphere": (_i, [_vp, _i, _i, _d, _d, _d, _d]),
@@ -119,6 +120,7 @@ SIGNATURES = {
     "oif_batch_step": (_i, [_vp, _i]),
     "oif_batch_set_graph": (_i, [_vp, _i]),
     "oif_batch_set_launch": (_i, [_vp, _i, _i, _i]),
+    "oif_batch_set_lb_loads": (_i, [_vp, _i]),
     "oif_batch_autotune": (_i, [_vp, C.c_char_p]),
     "oif_batch_step_timed": (_i, [_vp, _i, _vp]),
     "oif_batch_last_error": (C.c_char_p, [_vp]),
@@ -257,6 +259,10 @@ class Context:
 
     def set_launch(self, lb_block: int = -1, mesh_block: int = -1, xcd_remap: int = -1):
         self._chk(lib().oif_set_launch(self.h, int(lb_block), int(mesh_block), int(xcd_remap)))
+
+    def set_lb_loads(self, nontemporal: bool):
+        """Population reads of the lattice kernel non-temporal (True) or ordinary."""
+        self._chk(lib().oif_set_lb_loads(self.h, int(bool(nontemporal))))
 
     def set_mrt(self, gamma=None):
         """Multiple-relaxation-time collision with the factors (shear, bulk,
@@ -436,6 +442,9 @@ class Batch:
 
     def set_launch(self, lb_block: int = -1, mesh_block: int = -1, xcd_remap: int = -1):
         self._chk(lib().oif_batch_set_launch(self.h, int(lb_block), int(mesh_block), int(xcd_remap)))
+
+    def set_lb_loads(self, nontemporal: bool):
+        self._chk(lib().oif_batch_set_lb_loads(self.h, int(bool(nontemporal))))
 
     def autotune(self, cache_path: Optional[str] = None):
         self._chk(lib().oif_batch_autotune(self.h, None if cache_path is None else cache_path.encode()))

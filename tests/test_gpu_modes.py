@@ -59,6 +59,31 @@ def test_overlap_matches_sequential_bitwise(oif, prec):
     assert same(*outs)
 
 
+@pytest.mark.parametrize("prec,overlap", [("fp32", False), ("fp16", False), ("fp64", False), ("fp32", True)])
+def test_nontemporal_loads_bitwise(oif, prec, overlap):
+    """The cache policy of the population reads changes no value.  (FP64
+    sums the coupling force of overlapping stencils with FP64 atomics, whose
+    order varies from run to run: there the two runs agree to round-off.)"""
+    say(f"[modes] non-temporal vs ordinary population reads, {prec} channel, overlap={overlap}")
+    box = channel()
+    outs = []
+    for nt in (False, True):
+        c = oif.Context.from_box(box, precision=prec)
+        c.set_overlap(overlap)
+        c.set_lb_loads(nt)
+        assert c.info().lb_nontemporal == int(nt)
+        c.step(40)
+        outs.append(state(c))
+        if nt:
+            assert oif.lib().oif_set_lb_loads(c.h, 2) == -1  # OIF_E_ARG
+        c.close()
+    if prec == "fp64":  # the FP64 parity criterion: 1e-12 relative plus 1e-14 absolute
+        for a, b in zip(*outs):
+            assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a)) + 1e-14
+    else:
+        assert same(*outs)
+
+
 @pytest.mark.parametrize("overlap", [False, True])
 def test_graph_matches_eager_bitwise(oif, overlap):
     say(f"[modes] graph vs eager, overlap={overlap}")
@@ -149,6 +174,7 @@ def test_batch_matches_single_boxes(oif):
     ctxs = [oif.Context.from_box(bx, precision="fp32") for bx in boxes]
     B = oif.Batch(ctxs)
     B.set_graph(4)
+    B.set_lb_loads(not ctxs[0].info().lb_nontemporal)  # the other read policy than the singles
     B.step(1)
     B.step(19)
     for c, ref in zip(ctxs, singles):
