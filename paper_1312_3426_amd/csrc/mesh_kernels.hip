@@ -190,8 +190,11 @@ __device__ void mark_object(const double* pos, int nv, const int* anchor, gptr<c
 
 // CONS: some object of the launch may use the conservative force model (each
 // object's template says whether it does); without it that code is left out.
+// Below FP64, registers are capped for six waves per SIMD: two objects of up
+// to 768 threads then share a compute unit (both meshes fit its LDS), so each
+// phase's loops over triangles, edges and nodes take fewer rounds.
 template <int P, bool USE_LDS, bool CONS>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 1 : 6)))
 mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, int mark_next) {
     typedef typename Prec<P>::S S;
     typedef typename Prec<P>::R R;
