@@ -292,7 +292,17 @@ def main():
     log(f"[bench] plain copy kernel, 1 GiB: {copy_gbs:.1f} GB/s")
 
     r32 = res["fp32"]
-    ms_step = r32["total_ms"] / a.steps
+    # The headline times the stepping call as a user runs it: HIP-graph replays
+    # of 50 steps, wall clock between two device synchronisations, the call's
+    # FP64 watchdog included (below 100 steps that watchdog would weigh more
+    # than 2 %: then the eager launches, timed by HIP events, are used).
+    use_graph = "graph_ms_per_step" in r32 and a.steps >= 100
+
+    def step_ms(r):
+        return r["graph_ms_per_step"] if use_graph else r["total_ms"] / a.steps
+
+    ms_step = step_ms(r32)
+    ms_eager = r32["total_ms"] / a.steps
     mlups = N / (ms_step * 1e-3) / 1e6
     lb_bytes = 2 * 19 * BYTES_POP["fp32"] * N
     achieved = lb_bytes / (r32["lb_ms"] * 1e-3) / 1e9
@@ -318,6 +328,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": box.name, "nx": box.nx, "ny": box.ny, "nz": box.nz, "cells": len(box.objects),
                    "mesh_nodes": M, "storage": "fp32", "launch": {k: r32[k] for k in ("lb_block", "mesh_block", "xcd_remap", "nt_loads")}},
+        "timing": ("hipGraph replays of 50 steps, wall clock between device synchronisations, "
+                   "one FP64 watchdog included" if use_graph else "eager launches, HIP events"),
+        "eager": {"ms_per_step": round(ms_eager, 5), "mlups": round(N / (ms_eager * 1e-3) / 1e6, 2)},
         "mesh_node_updates_per_s": round(M / (ms_step * 1e-3), 1),
         "kernel_ms": {"lb": round(r32["lb_ms"], 5), "mesh": round(r32["mesh_ms"], 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -334,10 +347,12 @@ def main():
     for p in ("fp16", "bf16"):
         if p not in res:
             continue
-        ms_p = res[p]["total_ms"] / a.steps
+        ms_p = step_ms(res[p])
+        ms_pe = res[p]["total_ms"] / a.steps
         lbb = 2 * 19 * BYTES_POP[p] * N
         line["storage"][p] = {"mlups": round(N / (ms_p * 1e-3) / 1e6, 2),
                               "speedup_vs_fp32": round(ms_step / ms_p, 3),
+                              "speedup_vs_fp32_eager": round(ms_eager / ms_pe, 3),
                               "lb_ms": round(res[p]["lb_ms"], 5),
                               "lb_GB/s": round(lbb / (res[p]["lb_ms"] * 1e-3) / 1e9, 1),
                               "mass_rel_drift": res[p]["mass_rel_drift"]}
