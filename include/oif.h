@@ -80,7 +80,8 @@ typedef struct oif_ctx oif_ctx;
 typedef struct oif_batch oif_batch;
 
 /* Fluid box ("Method"; the lbfluid parameters of the paper's example script).
- *   nx, ny, nz      lattice size, each in [1, 4096], nx*ny*nz <= 2^31 / 19
+ *   nx, ny, nz      lattice size, each in [1, 4096], nx*ny*nz rounded up to a
+ *                   multiple of 64 below 2^31 / 19
  *   walls_z         1: halfway bounce-back walls at z = 0 and z = nz (needs nz >= 2)
  *   tau             BGK relaxation time, > 1/2 (kinematic viscosity (tau - 1/2)/3)
  *   rho0            rest density, > 0; the fluid starts at rest at rho0
