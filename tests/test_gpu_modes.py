@@ -2,6 +2,7 @@
 C ABI: overlapped vs sequential steps, graph replay vs eager launches,
 autotuning, checkpoint/restore, the batching form, object analysis,
 conservation diagnostics, the watchdog and input validation."""
+import json
 import os
 
 import numpy as np
@@ -130,6 +131,7 @@ def test_autotune_leaves_state_unchanged(oif, tmp_path):
             c.autotune(cache)
             i = c.info()
             assert i.lb_block in (128, 256, 512, 1024) and i.mesh_block % 64 == 0 and 64 <= i.mesh_block <= 1024
+            chosen = (i.lb_block, i.mesh_block, i.xcd_remap, i.lb_nontemporal)
         c.step(20)
         outs.append(state(c))
         c.close()
@@ -138,9 +140,14 @@ def test_autotune_leaves_state_unchanged(oif, tmp_path):
     for a, b in zip(*outs):
         assert rel(a, b) < 1e-6
     assert os.path.exists(cache) and "gfx950" in open(cache).read()
-    # a second context finds the shapes in the cache
+    # a second context finds the shapes (and the read policy) in the cache
+    entries = json.load(open(cache))
+    assert all(len(v) == 4 for v in entries.values())
     c = oif.Context.from_box(box, precision="fp32")
+    c.set_lb_loads(not chosen[3])
     c.autotune(cache)
+    i = c.info()
+    assert (i.lb_block, i.mesh_block, i.xcd_remap, i.lb_nontemporal) == chosen
     c.close()
 
 
