@@ -81,3 +81,15 @@ def test_scale_case_full_size_fp32(oif, orc, tmp_path):
     res = check(g, o, "fp32", box.rho0, box.nx)
     say(f"   {fmt(res)}")
     assert all(v[3] for v in res.values()), fmt(res)
+
+
+@pytest.mark.timeout(600)
+def test_scale_case_full_size_fp64(oif, orc, tmp_path):
+    """The same box in the FP64 form: each population buffer holds 19 x 33.5 M
+    doubles (5.1 GB), so every population address lies beyond 32-bit byte
+    offsets somewhere; one step against the oracle at the FP64 bar."""
+    box = synth.config_scale(1)
+    g, o = run_case(oif, orc, box, "fp64", 1, 59, str(tmp_path / "t.json"))
+    res = check(g, o, "fp64", box.rho0, box.nx)
+    say(f"   {fmt(res)}")
+    assert all(v[3] for v in res.values()), fmt(res)
