@@ -60,13 +60,15 @@ def test_overlap_matches_sequential_bitwise(oif, prec):
     assert same(*outs)
 
 
-@pytest.mark.parametrize("prec,overlap", [("fp32", False), ("fp16", False), ("fp64", False), ("fp32", True)])
-def test_nontemporal_loads_bitwise(oif, prec, overlap):
+@pytest.mark.parametrize("prec,overlap,obst", [("fp32", False, False), ("fp16", False, False),
+                                               ("fp64", False, False), ("fp32", True, False),
+                                               ("fp32", False, True)])
+def test_nontemporal_loads_bitwise(oif, prec, overlap, obst):
     """The cache policy of the population reads changes no value.  (FP64
     sums the coupling force of overlapping stencils with FP64 atomics, whose
     order varies from run to run: there the two runs agree to round-off.)"""
-    say(f"[modes] non-temporal vs ordinary population reads, {prec} channel, overlap={overlap}")
-    box = channel()
+    say(f"[modes] non-temporal vs ordinary population reads, {prec}, overlap={overlap}, obstacles={obst}")
+    box = synth.config_obstacle_channel(40) if obst else channel()
     outs = []
     for nt in (False, True):
         c = oif.Context.from_box(box, precision=prec)
