@@ -60,15 +60,17 @@ def test_overlap_matches_sequential_bitwise(oif, prec):
     assert same(*outs)
 
 
-@pytest.mark.parametrize("prec,overlap,obst", [("fp32", False, False), ("fp16", False, False),
-                                               ("fp64", False, False), ("fp32", True, False),
-                                               ("fp32", False, True)])
-def test_nontemporal_loads_bitwise(oif, prec, overlap, obst):
+@pytest.mark.parametrize("prec,overlap,case", [("fp32", False, "channel"), ("fp16", False, "channel"),
+                                               ("fp64", False, "channel"), ("fp32", True, "channel"),
+                                               ("fp32", False, "obstacles"), ("fp32", False, "mrt")])
+def test_nontemporal_loads_bitwise(oif, prec, overlap, case):
     """The cache policy of the population reads changes no value.  (FP64
     sums the coupling force of overlapping stencils with FP64 atomics, whose
     order varies from run to run: there the two runs agree to round-off.)"""
-    say(f"[modes] non-temporal vs ordinary population reads, {prec}, overlap={overlap}, obstacles={obst}")
-    box = synth.config_obstacle_channel(40) if obst else channel()
+    say(f"[modes] non-temporal vs ordinary population reads, {prec} {case}, overlap={overlap}")
+    box = synth.config_obstacle_channel(40) if case == "obstacles" else channel()
+    if case == "mrt":
+        box.mrt = (0.25, -0.4, 0.6, -0.7)
     outs = []
     for nt in (False, True):
         c = oif.Context.from_box(box, precision=prec)
