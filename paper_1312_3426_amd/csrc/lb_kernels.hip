@@ -20,30 +20,30 @@ namespace {
 
 using namespace dev;
 
-// Coupling force density at node p, read from G and cleared there.
+// Coupling force density at node p, read from G and cleared there (the
+// node's three components are one 32-byte slot).
 template <int P>
 __device__ __forceinline__ void take_force(const BoxDev* __restrict__ B, int p, typename Prec<P>::R& fx,
                                            typename Prec<P>::R& fy, typename Prec<P>::R& fz) {
     typedef typename Prec<P>::R R;
-    const int N = B->N;
-    const unsigned o = (unsigned)p * 8u;
+    const unsigned o = (unsigned)p * 32u;
     if (P == PREC_FP64) {
         double* G = (double*)B->G;
         fx += (R)gload(G, o);
-        fy += (R)gload(G + N, o);
-        fz += (R)gload(G + 2 * (size_t)N, o);
+        fy += (R)gload(G, o + 8u);
+        fz += (R)gload(G, o + 16u);
         gstore(G, o, 0.0);
-        gstore(G + N, o, 0.0);
-        gstore(G + 2 * (size_t)N, o, 0.0);
+        gstore(G, o + 8u, 0.0);
+        gstore(G, o + 16u, 0.0);
     } else {
         long long* G = (long long*)B->G;
         const double s = B->fp_inv;
         fx += (R)((double)gload(G, o) * s);
-        fy += (R)((double)gload(G + N, o) * s);
-        fz += (R)((double)gload(G + 2 * (size_t)N, o) * s);
+        fy += (R)((double)gload(G, o + 8u) * s);
+        fz += (R)((double)gload(G, o + 16u) * s);
         gstore(G, o, 0ll);
-        gstore(G + N, o, 0ll);
-        gstore(G + 2 * (size_t)N, o, 0ll);
+        gstore(G, o + 8u, 0ll);
+        gstore(G, o + 16u, 0ll);
     }
 }
 

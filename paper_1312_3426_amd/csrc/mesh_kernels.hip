@@ -56,10 +56,10 @@ struct Acc {
     }
     __device__ static unsigned flush(gptr<const BoxDev> B, int q, T x, T y, T z) {
         if ((x | y | z) == 0ull) return 0u;
-        T* G = (T*)B->G;
-        gatomic_add(G + q, x);
-        gatomic_add(G + B->N + q, y);
-        gatomic_add(G + 2 * (size_t)B->N + q, z);
+        T* G = (T*)B->G + 4 * (size_t)q;
+        gatomic_add(G, x);
+        gatomic_add(G + 1, y);
+        gatomic_add(G + 2, z);
         gatomic_or(B->mask + (q >> 6), 1ull << (q & 63));
         return 0u;
     }
@@ -77,10 +77,10 @@ struct Acc<PREC_FP64> {
     }
     __device__ static unsigned flush(gptr<const BoxDev> B, int q, T x, T y, T z) {
         if (x == 0.0 && y == 0.0 && z == 0.0) return 0u;
-        T* G = (T*)B->G;
-        gatomic_add(G + q, x);
-        gatomic_add(G + B->N + q, y);
-        gatomic_add(G + 2 * (size_t)B->N + q, z);
+        T* G = (T*)B->G + 4 * (size_t)q;
+        gatomic_add(G, x);
+        gatomic_add(G + 1, y);
+        gatomic_add(G + 2, z);
         gatomic_or(B->mask + (q >> 6), 1ull << (q & 63));
         return 0u;
     }
@@ -698,9 +698,17 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     if (compact) {
         // one global atomic per touched lattice node and component
         __syncthreads();
-        for (int c = threadIdx.x; c < ncomp; c += blockDim.x) {
-            if (bt && gld(bt + qn[c])) continue;  // an obstacle takes no share
-            flags |= Acc<P>::flush(B, qn[c], gacc[3 * c], gacc[3 * c + 1], gacc[3 * c + 2]);
+        // (one lane per node and component: a wave's atomics cover the
+        // consecutive 32-byte slots of ~21 nodes instead of one component of
+        // 64 nodes spread over three arrays)
+        for (int k = threadIdx.x; k < 3 * ncomp; k += blockDim.x) {
+            const int c = k / 3, comp = k - 3 * c;
+            const int q = qn[c];
+            if (bt && gld(bt + q)) continue;  // an obstacle takes no share
+            const A val = gacc[k];
+            if (val != A(0)) gatomic_add((A*)B->G + 4 * (size_t)q + comp, val);
+            if (comp == 0 && (gacc[3 * c] != A(0) || gacc[3 * c + 1] != A(0) || gacc[3 * c + 2] != A(0)))
+                gatomic_or(B->mask + (q >> 6), 1ull << (q & 63));
         }
     }
     // split stepping: the stencils of the new positions, for the next step

@@ -7,8 +7,9 @@
 //          64 consecutive nodes, each tile [19][64] (value (i, p) at element
 //          ((p / 64) * 19 + i) * 64 + p % 64, N rounded up to whole tiles);
 //          the step reads f[parity] and writes f[parity ^ 1]
-//   G      coupling force density, [3][N]: double (FP64 form) or int64 fixed
-//          point with resolution 2^-e (FP32 forms, order-independent sums)
+//   G      coupling force density, [N][4] (x, y, z, unused: one 32-byte slot
+//          per node): double (FP64 form) or int64 fixed point with resolution
+//          2^-e (FP32 forms, order-independent sums)
 //   mask   one bit per node, set where G is non-zero; the lattice kernel reads
 //          G only where a bit is set and clears both
 //   X, V   mesh node positions (absolute, unwrapped, FP64 in every form, so

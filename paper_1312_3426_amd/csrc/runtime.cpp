@@ -916,7 +916,7 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     const size_t popb = pop_bytes(cp);
     const size_t nmask = ((size_t)N + 63) / 64;
     int rc = OIF_OK;
-    if ((rc = alloc(&c->f[0], popb)) || (rc = alloc(&c->f[1], popb)) || (rc = alloc(&c->G, 24 * (size_t)N)) ||
+    if ((rc = alloc(&c->f[0], popb)) || (rc = alloc(&c->f[1], popb)) || (rc = alloc(&c->G, 32 * (size_t)N)) ||
         (rc = alloc((void**)&c->mask, 8 * nmask)) || (rc = alloc((void**)&c->touch[0], 8 * nmask)) ||
         (rc = alloc((void**)&c->touch[1], 8 * nmask)) ||
         (rc = alloc((void**)&c->status, 256)) ||
@@ -926,7 +926,7 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     }
     if (hipMemsetAsync(c->f[0], 0, popb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->f[1], 0, popb, c->stream) != hipSuccess ||
-        hipMemsetAsync(c->G, 0, 24 * (size_t)N, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->G, 0, 32 * (size_t)N, c->stream) != hipSuccess ||
         hipMemsetAsync(c->mask, 0, 8 * nmask, c->stream) != hipSuccess ||
         hipMemsetAsync(c->touch[0], 0, 8 * nmask, c->stream) != hipSuccess ||
         hipMemsetAsync(c->touch[1], 0, 8 * nmask, c->stream) != hipSuccess ||
@@ -1593,7 +1593,7 @@ int oif_info(oif_ctx* c, oif_info_t* info) {
     info->n_nodes = c->N;
     info->n_mesh_nodes = c->M;
     info->steps_done = c->steps;
-    long long bytes = 2 * (long long)pop_bytes(c) + 24LL * c->N + 8LL * ((c->N + 63) / 64);
+    long long bytes = 2 * (long long)pop_bytes(c) + 32LL * c->N + 8LL * ((c->N + 63) / 64);
     for (auto& b : c->tbufs) bytes += (long long)b.n;
     for (const DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->F_dev, &c->geo_dev,
                             &c->scratch_dev, &c->rep_pos, &c->rep_cell, &c->rep_cnt, &c->rep_cursor, &c->rep_bsum,
