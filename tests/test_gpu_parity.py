@@ -280,3 +280,27 @@ def test_mixed_force_models_in_one_box(oif, orc, prec):
                 for key, (e, r, b, ok) in res.items():
                     assert e <= 1e-12 * r, (k, key, e / r)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("pull", [10.0, 16.0])
+def test_pulled_node_vs_oracle(oif, orc, prec, pull):
+    """One node pulled far from the sphere (radius 4, stencil-box capacity
+    12^3 = 1728 nodes).  By 10 lattice units the box grows to 14 x 10 x 10 and
+    still fits (compact numbering); by 16 it is 20 x 10 x 10 and the coupling
+    takes the per-corner path (interpolation per stencil corner, one global
+    atomic per corner and component).  Both against the oracle for two steps."""
+    say(f"[coupled] sphere642 with node 0 pulled by {pull}, {prec}")
+    box = synth.config_sphere_fp64(2)
+    sysm = orc.System(box)
+    X0 = sysm.X.copy()
+    X0[0, 0] += pull
+    sysm.X[:] = X0
+    ctx = oif.Context.from_box(box, precision=prec)
+    ctx.write_mesh(-1, X0, sysm.V.copy())
+    ctx.step(2)
+    sysm.run(2)
+    res = check(gpu_fields(ctx, box.rho0, X0), oracle_fields(sysm, X0), prec, box.rho0, box.nx)
+    say(f"   {fmt(res)}")
+    ctx.close()
+    assert_ok(res, f"node pulled by {pull}")
