@@ -258,7 +258,7 @@ def main():
                     help="only run the plain copy kernel on BYTES bytes and print its bandwidth")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the sharding design is documented, not built)", file=sys.stderr)
         sys.exit(2)
 

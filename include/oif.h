@@ -51,7 +51,7 @@ extern "C" {
 #define OIF_E_HIP (-6)         /* a HIP runtime call failed */
 #define OIF_E_NONFINITE (-7)   /* watchdog: NaN/Inf in populations or mesh state */
 #define OIF_E_OVERFLOW (-8)    /* watchdog: fixed-point force accumulator out of range */
-#define OIF_E_UNSUPPORTED (-9) /* configuration not supported by this build */
+#define OIF_E_UNSUPPORTED (-9) /* configuration the library does not support */
 
 /* precision forms of the lattice populations */
 #define OIF_PREC_FP64 0          /* FP64 arithmetic and storage */
