@@ -193,7 +193,10 @@ __device__ void mark_object(const double* pos, int nv, const int* anchor, gptr<c
 // Below FP64, registers are capped for six waves per SIMD: two objects of up
 // to 768 threads then share a compute unit (both meshes fit its LDS), so each
 // phase's loops over triangles, edges and nodes take fewer rounds.
-template <int P, bool USE_LDS, bool CONS>
+// CPL (meshes too large for LDS only): the coupling area alone sits in LDS, so
+// that the stencil-bit ORs and the per-node force sums, whose addresses many
+// mesh nodes share, are LDS and not global atomics.
+template <int P, bool USE_LDS, bool CONS, bool CPL = false>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 1 : 6)))
 mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, int mark_next) {
     typedef typename Prec<P>::S S;
@@ -216,7 +219,11 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     R* tr = (R*)(base + lay.tr);      // [nt]: (S - S0)/S
     R* se = (R*)(base + lay.se);      // [ne]: ks kappa strain / L
     R* fh = (R*)(base + lay.fh);      // [ne]: kb (theta - theta0)/theta0
-    unsigned* need = (unsigned*)(base + lay.need);  // coupling phase: stencil-box bits
+    // coupling area: after the mesh arrays, or alone in LDS (CPL)
+    auto carea = [&](size_t off) -> unsigned char* {
+        return (!USE_LDS && CPL) ? smem + (off - lay.need) : base + off;
+    };
+    unsigned* need = (unsigned*)carea(lay.need);  // coupling phase: stencil-box bits
     __shared__ int bbox[6];
     __shared__ int ncomp;
 
@@ -451,10 +458,10 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     const bool grid = bbox[3] >= bbox[0] && exl * eyl * ezl <= (long long)ucap;
     const int ex = (int)exl, exy = (int)(exl * eyl);
     unsigned* pre = need + lay.nwords;             // exclusive popcount prefix per word
-    R* ug = (R*)(base + lay.ug);                   // [ccap][3] velocity at compact nodes
-    int* qn = (int*)(base + lay.qn);               // [ccap] lattice index of compact nodes
+    R* ug = (R*)carea(lay.ug);                   // [ccap][3] velocity at compact nodes
+    int* qn = (int*)carea(lay.qn);               // [ccap] lattice index of compact nodes
     typedef typename Acc<P>::T A;
-    A* gacc = (A*)(base + lay.gacc);               // [ccap][3] summed reaction force
+    A* gacc = (A*)carea(lay.gacc);               // [ccap][3] summed reaction force
     bool compact = false;
     if (grid) {
         const int vol = (int)(exl * eyl * ezl);
@@ -762,6 +769,13 @@ hipError_t launch_mesh_p(const MeshLaunch& L) {
         else
             hipLaunchKernelGGL((mesh_kernel<P, true, false>), g, b, L.lds_bytes, L.stream, objs, L.parity,
                                L.mark_next);
+    } else if (L.cpl_lds_bytes > 0) {
+        if (L.conservative)
+            hipLaunchKernelGGL((mesh_kernel<P, false, true, true>), g, b, L.cpl_lds_bytes, L.stream, objs,
+                               L.parity, L.mark_next);
+        else
+            hipLaunchKernelGGL((mesh_kernel<P, false, false, true>), g, b, L.cpl_lds_bytes, L.stream, objs,
+                               L.parity, L.mark_next);
     } else {
         if (L.conservative)
             hipLaunchKernelGGL((mesh_kernel<P, false, true>), g, b, 0, L.stream, objs, L.parity, L.mark_next);
@@ -778,6 +792,12 @@ size_t mesh_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap,
         .total;
 }
 
+size_t mesh_cpl_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap, int cons) {
+    const MeshLayout L =
+        mesh_layout(precision == PREC_FP64 ? sizeof(double) : sizeof(float), nv, nt, ne, ucap, ccap, cons);
+    return align16(L.gacc + (size_t)ccap * 3 * 8) - L.need;
+}
+
 hipError_t launch_mesh(const MeshLaunch& L) {
     if (L.nobj <= 0) return hipSuccess;
     switch (L.precision) {
@@ -792,14 +812,22 @@ hipError_t launch_mesh(const MeshLaunch& L) {
 // Let the LDS-resident variants use up to `bytes` of dynamic LDS per workgroup.
 hipError_t mesh_set_max_lds(size_t bytes) {
     hipError_t e = hipSuccess;
-    const void* fns[8] = {(const void*)mesh_kernel<PREC_FP64, true, false>,
+    const void* fns[16] = {(const void*)mesh_kernel<PREC_FP64, true, false>,
                           (const void*)mesh_kernel<PREC_FP32, true, false>,
                           (const void*)mesh_kernel<PREC_FP16, true, false>,
                           (const void*)mesh_kernel<PREC_BF16, true, false>,
                           (const void*)mesh_kernel<PREC_FP64, true, true>,
                           (const void*)mesh_kernel<PREC_FP32, true, true>,
                           (const void*)mesh_kernel<PREC_FP16, true, true>,
-                          (const void*)mesh_kernel<PREC_BF16, true, true>};
+                          (const void*)mesh_kernel<PREC_BF16, true, true>,
+                          (const void*)mesh_kernel<PREC_FP64, false, false, true>,
+                          (const void*)mesh_kernel<PREC_FP32, false, false, true>,
+                          (const void*)mesh_kernel<PREC_FP16, false, false, true>,
+                          (const void*)mesh_kernel<PREC_BF16, false, false, true>,
+                          (const void*)mesh_kernel<PREC_FP64, false, true, true>,
+                          (const void*)mesh_kernel<PREC_FP32, false, true, true>,
+                          (const void*)mesh_kernel<PREC_FP16, false, true, true>,
+                          (const void*)mesh_kernel<PREC_BF16, false, true, true>};
     for (const void* f : fns) {
         hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (r != hipSuccess) e = r;

@@ -233,6 +233,9 @@ struct MeshLaunch {
     int parity;
     int precision;
     size_t lds_bytes;      // dynamic LDS per block (0 = each object's global scratch)
+    size_t cpl_lds_bytes;  // scratch launch: dynamic LDS holding the coupling area (stencil
+                           // bits, touched-node velocities and force sums); 0 = that
+                           // area in the scratch too
     int mark_next;         // also mark the stencils of the new positions in
                            // touch[parity ^ 1] (split stepping)
     int conservative;      // some object of the launch uses the conservative force model
@@ -247,6 +250,8 @@ hipError_t launch_repulsion(const RepDev& h, const RepDev* d, const void* objs, 
 
 // Per-template LDS bytes of the mesh kernel.
 size_t mesh_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap, int cons);
+// Bytes of the coupling area alone (the part of the layout from `need` on).
+size_t mesh_cpl_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap, int cons);
 // Allow the LDS-resident mesh kernels to use up to `bytes` of dynamic LDS.
 hipError_t mesh_set_max_lds(size_t bytes);
 

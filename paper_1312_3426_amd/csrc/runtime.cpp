@@ -288,6 +288,7 @@ struct oif_ctx {
     std::vector<unsigned char> obj_host; // ObjDev<real> array as uploaded (sorted)
     int n_lds_obj = 0;          // objects [0, n_lds_obj) use LDS, the rest global scratch
     size_t lds_need = 0;
+    size_t cpl_need = 0;        // LDS for the coupling area of the scratch objects (0: none)
     int any_conservative = 0;   // some template uses the conservative force model
 
     // launch configuration
@@ -331,6 +332,7 @@ struct oif_batch {
     // (obstacles, MRT collision): one launch per group
     int var_off[5] = {0, 0, 0, 0, 0};
     size_t lds_need = 0;
+    size_t cpl_need = 0;
     int any_conservative = 0;
     int lb_block = 256, mesh_block = 256, remap = 1;
     int lb_nt = 0;
@@ -601,6 +603,7 @@ int upload_mesh_t(oif_ctx* c) {
     });
     c->n_lds_obj = 0;
     c->lds_need = 0;
+    c->cpl_need = 0;
     c->any_conservative = 0;
     for (const Template& T : c->tmpl) c->any_conservative |= tmpl_conservative(T);
     c->mark_lds = 16;
@@ -613,8 +616,12 @@ int upload_mesh_t(oif_ctx* c) {
             c->lds_need = std::max(c->lds_need, need(i));
         } else {
             scratch_total += (need(i) + 255) & ~(size_t)255;
+            const Template& T = c->tmpl[c->obj[i].tid];
+            c->cpl_need = std::max(c->cpl_need, mesh_cpl_lds_bytes(c->d.precision, T.nv, T.nt, T.ne, T.ucap,
+                                                                   T.ccap, tmpl_conservative(T)));
         }
     }
+    if (c->cpl_need > budget) c->cpl_need = 0;  // the coupling area stays in the scratch too
     if ((rc = dev_alloc(c, c->scratch_dev, scratch_total))) return rc;
     if ((rc = setup_repulsion(c, sizeof(real)))) return rc;
     std::vector<ObjDev<real>> od(c->obj.size());
@@ -696,6 +703,7 @@ int enqueue_mesh(oif_ctx* c, int par, hipStream_t s, int mark_next) {
         ml.objs = (const unsigned char*)c->obj_dev.p + osz * c->n_lds_obj;
         ml.nobj = (int)c->obj.size() - c->n_lds_obj;
         ml.lds_bytes = 0;
+        ml.cpl_lds_bytes = c->cpl_need;
         HIPCALL(c, launch_mesh(ml));
     }
     return OIF_OK;
@@ -1904,7 +1912,7 @@ int batch_build(oif_batch* b) {
     BHIP(b, hipMemcpy(b->work_dev.p, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice));
     // objects of all boxes: LDS-resident group first, each largest mesh first
     const size_t osz = objdev_size(b->precision);
-    struct Ent { const unsigned char* p; bool lds; int nv; size_t need; };
+    struct Ent { const unsigned char* p; bool lds; int nv; size_t need, cpl; };
     std::vector<Ent> ents;
     for (oif_ctx* c : b->ctx) {
         const size_t n = c->obj.size();
@@ -1918,7 +1926,9 @@ int batch_build(oif_batch* b) {
             const size_t tid = ((const unsigned char*)tptr - (const unsigned char*)c->tmpl_dev.p) / tsz;
             const Template& T = c->tmpl[tid];
             ents.push_back({p, lds, T.nv,
-                            mesh_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T))});
+                            mesh_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T)),
+                            mesh_cpl_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap,
+                                               tmpl_conservative(T))});
         }
     }
     std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& c) {
@@ -1928,6 +1938,7 @@ int batch_build(oif_batch* b) {
     std::vector<unsigned char> host(ents.size() * osz);
     b->n_lds_obj = 0;
     b->lds_need = 0;
+    b->cpl_need = 0;
     b->any_conservative = 0;
     for (oif_ctx* c : b->ctx)
         for (const Template& T : c->tmpl) b->any_conservative |= tmpl_conservative(T);
@@ -1936,8 +1947,11 @@ int batch_build(oif_batch* b) {
         if (ents[k].lds) {
             ++b->n_lds_obj;
             b->lds_need = std::max(b->lds_need, ents[k].need);
+        } else {
+            b->cpl_need = std::max(b->cpl_need, ents[k].cpl);
         }
     }
+    if (b->ctx.empty() || b->cpl_need > b->ctx[0]->max_lds) b->cpl_need = 0;
     b->nobj = (int)ents.size();
     b->obj_dev.release();
     BHIP(b, hipMalloc(&b->obj_dev.p, host.size() + 16));
@@ -1971,6 +1985,7 @@ int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<h
             ml.objs = (const unsigned char*)b->obj_dev.p + osz * b->n_lds_obj;
             ml.nobj = b->nobj - b->n_lds_obj;
             ml.lds_bytes = 0;
+            ml.cpl_lds_bytes = b->cpl_need;
             BHIP(b, launch_mesh(ml));
         }
         if (ev) (void)hipEventRecord((*ev)[3 * k + 1], s);

@@ -216,6 +216,25 @@ def test_batch_box_vs_oracle(oif, orc):
         c.close()
 
 
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_large_meshes_vs_oracle(oif, orc, prec):
+    """A box whose 2562-node spheres do not fit LDS (their mesh arrays in the
+    global scratch, the coupling area alone in LDS) against the oracle."""
+    say(f"[modes] large meshes vs oracle ({prec})")
+    bx = synth.config_batch(n_boxes=1, steps=30)[0]
+    c = oif.Context.from_box(bx, precision=prec)
+    c.step(30)
+    i = c.info()  # objects are placed at the first step
+    assert 0 < i.lds_objects < i.n_objects
+    s = orc.System(bx)
+    X0 = s.X.copy()
+    s.run(30)
+    res = check(gpu_fields(c, bx.rho0, X0), oracle_fields(s, X0), prec, bx.rho0, max(bx.nx, bx.ny, bx.nz))
+    say(f"   {bx.name} ({len(bx.objects)} cells, {i.lds_objects} in LDS): {fmt(res)}")
+    assert all(v[3] for v in res.values())
+    c.close()
+
 def test_object_analysis_vs_oracle(oif, orc):
     say("[aux] object analysis")
     box = synth.config_sphere_fp64(30)
