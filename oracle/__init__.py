@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oif_oracle.c")
 _HDR = os.path.join(_HERE, "oif_oracle.h")
 _LIB = os.path.join(_HERE, "liboif_oracle.so")
+_LIB_OMP = os.path.join(_HERE, "liboif_oracle_omp.so")
 _lock = threading.Lock()
 _lib = None
 
@@ -32,18 +33,22 @@ D3Q19_E = np.array(
 D3Q19_W = np.array([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12)
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (IEEE FP64, no fast-math, no FMA contraction)."""
+def build(force: bool = False, openmp: bool = False) -> str:
+    """Compile the oracle with gcc (IEEE FP64, no fast-math, no FMA contraction).
+    openmp=True builds the variant whose two lattice sweeps run on several host
+    threads (same results bit for bit, see orc_threads); both are built when
+    either is stale."""
     with _lock:
-        stale = (not os.path.exists(_LIB)) or any(
-            os.path.getmtime(p) > os.path.getmtime(_LIB) for p in (_SRC, _HDR))
+        stale = any((not os.path.exists(lib_)) or any(
+            os.path.getmtime(p) > os.path.getmtime(lib_) for p in (_SRC, _HDR)) for lib_ in (_LIB, _LIB_OMP))
         if force or stale:
-            tmp = _LIB + f".tmp{os.getpid()}"
-            cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
-                   "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm"]
-            subprocess.run(cmd, check=True)
-            os.replace(tmp, _LIB)
-    return _LIB
+            for lib_, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+                tmp = lib_ + f".tmp{os.getpid()}"
+                cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
+                       "-ffp-contract=off", "-Wall", "-Wno-unknown-pragmas", *extra, "-o", tmp, _SRC, "-lm"]
+                subprocess.run(cmd, check=True)
+                os.replace(tmp, lib_)
+    return _LIB_OMP if openmp else _LIB
 
 
 class _Lattice(C.Structure):
@@ -111,8 +116,11 @@ def model_code(model) -> int:
 def lib():
     global _lib
     if _lib is None:
-        # OIF_ORACLE_LIB lets the mutation test load a deliberately broken copy
-        path = os.environ.get("OIF_ORACLE_LIB") or build()
+        # OIF_ORACLE_LIB lets the mutation test load a deliberately broken copy;
+        # OIF_ORACLE_OPENMP=1 loads the build whose lattice sweeps use several
+        # host threads (identical results)
+        path = os.environ.get("OIF_ORACLE_LIB") or build(
+            openmp=os.environ.get("OIF_ORACLE_OPENMP") == "1")
         L = C.CDLL(path)
         dp, ip, vp = C.c_void_p, C.c_void_p, C.c_void_p
         L.orc_kappa.restype = C.c_double
@@ -176,8 +184,16 @@ def lib():
         L.orc_system_get_force.argtypes = [vp, dp]
         L.orc_system_set_force.restype = None
         L.orc_system_set_force.argtypes = [vp, dp]
+        L.orc_threads.restype = C.c_int
+        L.orc_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
+
+
+def threads(n: int = 0) -> int:
+    """Host threads of the lattice sweeps (n > 0 sets them; 1 for the serial
+    build); returns the number in use."""
+    return int(lib().orc_threads(int(n)))
 
 
 def _p(a: np.ndarray):

@@ -50,6 +50,25 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Host threads of the two lattice sweeps (orc_moments, orc_lb_step).  Built
+ * without OpenMP everything is serial.  Built with it, those sweeps split
+ * their outer loop over threads: every node reads only the input arrays and
+ * writes outputs no other node writes (its own moments; the populations it
+ * pushes), so the result is bit for bit the serial one.  Everything else
+ * (membrane forces, coupling, spreading) stays serial and ordered. */
+int orc_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------- */
 /* D3Q19 velocity set, weights and opposites                                 */
@@ -499,6 +518,7 @@ static int wrap(int i, int n) {
 void orc_moments(const orc_lattice* L, const double* n, const double* Fx, double* rho,
                  double* u) {
     long N = (long)L->nx * L->ny * L->nz;
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < N; ++p) {
         if (L->solid && L->solid[p]) {
             if (rho) rho[p] = L->rho0;
@@ -641,6 +661,7 @@ static void collide_mrt(const orc_lattice* L, const double* nn, const double* F,
 
 void orc_lb_step(const orc_lattice* L, const double* n, const double* G, double* nout) {
     long N = (long)L->nx * L->ny * L->nz;
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < L->nz; ++z)
         for (int y = 0; y < L->ny; ++y)
             for (int x = 0; x < L->nx; ++x) {

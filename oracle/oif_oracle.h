@@ -244,6 +244,10 @@ void orc_system_repulsion(orc_system* s, const double* X, double* F);
 /* Number of distinct lattice nodes inside any mesh node's 2x2x2 stencil. */
 long orc_system_touched(orc_system* s, const double* X);
 
+/* Host threads for the lattice sweeps (n > 0 sets them); returns the number
+ * in use, 1 when built without OpenMP.  The results do not depend on it. */
+int orc_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

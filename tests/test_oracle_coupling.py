@@ -182,10 +182,84 @@ def test_explicit_coupling_diverges_at_stated_friction(orc):
         assert blew == diverges, xi
 
 
+def _points_system(orc, dims, X, walls_z=False):
+    """Oracle system whose mesh nodes sit at the given points: one
+    tetrahedron object per four points (the touched-node count depends on the
+    positions only)."""
+    X = np.asarray(X, dtype=float).reshape(-1, 3)
+    assert len(X) % 4 == 0
+    n, t = synth.tetrahedron(1.0)
+    b = synth.Box(*dims, walls_z=walls_z, templates=[synth.Template(n, t)],
+                  objects=[synth.ObjectSpec(0, np.zeros(3)) for _ in range(len(X) // 4)])
+    s = orc.System(b)
+    s.X[:] = X
+    return s
+
+
+def _touched_by_hand(dims, X, walls_z=False):
+    """Distinct lattice nodes (i, j, k) with i in {floor(x - 1/2), that + 1}
+    per axis (nodes at cell centres), wrapped periodically, z clamped to the
+    fluid when there are walls: a set of integer triples, nothing shared with
+    the oracle."""
+    seen = set()
+    for x in np.asarray(X, dtype=float).reshape(-1, 3):
+        lo = [int(math.floor(x[a] - 0.5)) for a in range(3)]
+        for dx in (0, 1):
+            for dy in (0, 1):
+                for dz in (0, 1):
+                    i = (lo[0] + dx) % dims[0]
+                    j = (lo[1] + dy) % dims[1]
+                    k = lo[2] + dz
+                    k = min(max(k, 0), dims[2] - 1) if walls_z else k % dims[2]
+                    seen.add((i, j, k))
+    return len(seen)
+
+
+@pytest.mark.parametrize("case,dims,X,walls,expected", [
+    # four points on one node centre: that node's 2x2x2 stencil, 8 nodes
+    ("node_centre", (8, 8, 8), [[3.5, 4.5, 2.5]] * 4, False, 8),
+    # four points in one cell (between the same 8 nodes)
+    ("one_cell", (8, 8, 8), [[3.6, 4.6, 2.6], [4.4, 5.4, 3.4], [3.9, 4.6, 3.0], [4.0, 5.0, 2.9]], False, 8),
+    # two cells side by side in x share a face of 4 nodes: 8 + 4
+    ("adjacent_cells", (8, 8, 8), [[3.6, 4.6, 2.6], [4.6, 4.6, 2.6], [3.7, 4.7, 2.7], [4.7, 4.7, 2.7]], False, 12),
+    # four cells far apart: 4 x 8
+    ("separate", (16, 16, 16), [[1.0, 1.0, 1.0], [5.0, 5.0, 5.0], [9.0, 9.0, 9.0], [13.0, 13.0, 13.0]], False, 32),
+    # a cell straddling the periodic x face (nodes x = 7 and x = 0) reached from
+    # both sides of the face: still the same 8 nodes
+    ("periodic_face", (8, 8, 8), [[7.8, 4.6, 2.6], [0.2, 4.6, 2.6], [7.9, 5.4, 3.4], [0.3, 5.4, 3.4]], False, 8),
+    # a box one node thick in y: both y corners are the same node, 4 per cell
+    ("thin_y", (8, 1, 8), [[3.6, 0.5, 2.6]] * 4, False, 4),
+    # walls in z: below the first node centre both z corners clamp to k = 0
+    # (4 nodes); above the last one both clamp to k = nz - 1 (4 more)
+    ("walls_low_high", (8, 8, 6), [[3.6, 4.6, 0.3], [3.6, 4.6, 0.2], [3.6, 4.6, 5.8], [3.6, 4.6, 5.7]], True, 8),
+    # without walls the same points wrap in z and touch the planes k = 5, 0
+    # from both ends: again the 8 nodes of one wrapped cell
+    ("periodic_z", (8, 8, 6), [[3.6, 4.6, 0.3], [3.6, 4.6, 0.2], [3.6, 4.6, 5.8], [3.6, 4.6, 5.7]], False, 8),
+])
+def test_touched_node_count_by_hand(orc, case, dims, X, walls, expected):
+    """The coupling's byte model counts each lattice node inside some mesh
+    node's 2x2x2 stencil once."""
+    s = _points_system(orc, dims, X, walls)
+    assert _touched_by_hand(dims, X, walls) == expected, case
+    assert s.touched() == expected, case
+
+
+def test_touched_node_count_brute_force(orc):
+    """Random points (also outside the box and across periodic faces) on a
+    small box: the oracle's count equals a set of integer triples built here."""
+    rng = np.random.default_rng(17)
+    for dims, walls in (((7, 5, 6), False), ((9, 4, 8), True)):
+        X = rng.uniform(-3.0, 12.0, size=(40, 3))
+        if walls:
+            X[:, 2] = rng.uniform(-0.4, dims[2] + 0.4, size=40)
+        s = _points_system(orc, dims, X, walls)
+        assert s.touched() == _touched_by_hand(dims, X, walls)
+
+
 def test_touched_node_count_and_rest_start(orc):
     s = orc.System(_c1())
     T = s.touched()
-    assert 0 < T <= 8 * s.M
+    assert T == _touched_by_hand((20, 20, 20), s.X)
     Sg, V = s.geometry()
     x, t = synth.icosphere(3, 4.0)
     _, A, Vt = orc.geometry(x, t)

@@ -99,6 +99,7 @@ MUTATIONS = {
                                "for (int k = 0; k < 0; ++k)            /* edges along E[k] */"),
     "zwall_direction": ("double up[3] = {0, 0, 1}, down[3] = {0, 0, -1};",
                         "double up[3] = {0, 0, -1}, down[3] = {0, 0, 1};"),
+    "touched_double_count": ("            if (!mark[idx[k]]) {", "            if (1) {"),
     "repulsion_not_applied": (" + s->o_fext[3 * o + c] + s->Frep[3 * j + c];", " + s->o_fext[3 * o + c];"),
 }
 
