@@ -65,6 +65,20 @@ __device__ __forceinline__ R edot(int i, R ax, R ay, R az) {
     return s;
 }
 
+// Coefficients 3 w_i of the momentum-carrying (odd) equilibrium parts, for
+// the axis and the diagonal directions.  In exact arithmetic they are 1/6 and
+// 1/12, and sum_i 3 w_i e_i e_i = I makes the collision return the momentum
+// it was given.  Rounded separately to the arithmetic type that identity
+// would fail by one rounding (6 fl(1/6) = 1 + 3e-8 in FP32), and a
+// momentum multiplied by (1 + 3e-8) every step drifts by 3e-8 times the
+// number of steps; so the diagonal coefficient is fl(1/12) and the axis one
+// 1/2 - 4 fl(1/12), which is exact in binary floating point and keeps
+// c_axis + 4 c_diag = 1/2 exactly.
+template <typename R>
+__device__ __forceinline__ R codd(int i) {
+    return i <= 6 ? R(0.5) - R(4) * (R(1) / R(12)) : R(1) / R(12);
+}
+
 // BGK collision with Guo forcing of one node's 19 deviations, in place:
 // d_i <- (1 - omega) d_i + omega deq_i + S_i with the force density f
 // (eq. lbequation with the external force term; density and velocity are the
@@ -72,27 +86,62 @@ __device__ __forceinline__ R edot(int i, R ax, R ay, R az) {
 //   deq_i = w_i [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u^2)]
 //   S_i   = (1 - 1/(2 tau)) w_i [3 (e_i - u) + 9 (e_i . u) e_i] . F
 // Opposite directions share the parts even in e_i and negate the odd ones, so
-// they are formed once per pair.  Every operation is rounded as written (no
+// they are formed once per pair.  The odd part of deq_i is written
+// 3 w_i e_i . (j + F/2), which is rho 3 w_i e_i . u without the division by
+// rho and the multiplication back.  Every operation is rounded as written (no
 // contraction into fused multiply-adds beyond the explicit ones), so that all
 // lattice kernels that inline this function give the same bits node by node.
-template <typename R>
+//
+// ACC (FP32 storage): the odd parts, which carry the momentum, are formed in
+// FP64 from the exact FP64 sum j of the stored FP32 deviations, and each new
+// deviation is rounded to FP32 once.  In FP32 arithmetic the momentum, rebuilt
+// from j + F/2 every step (entirely when tau = 1), picks up rounding residuals
+// that repeat from step to step: the force adds a near-constant increment to a
+// value that sits on the FP32 grid, so the residual of that addition, and of
+// the products after it, does not average out.  Over hundreds of steps of a
+// body-force driven flow that drift reached 1e-5 of the velocity; with the odd
+// parts in FP64 only the final rounding of each stored value remains, whose
+// residuals do average out.  The parts even in e_i (density and the
+// second-order terms) stay in FP32.
+template <typename R, bool ACC>
 __device__ __forceinline__ void collide(const BoxDev* __restrict__ B, R (&d)[19], R fx, R fy, R fz) {
 #pragma clang fp contract(off)
     R drho = 0;
 #pragma unroll
     for (int i = 0; i < 19; ++i) drho += d[i];
-    const R jx = d[1] - d[2] + d[7] - d[8] + d[9] - d[10] + d[11] - d[12] + d[13] - d[14];
-    const R jy = d[3] - d[4] + d[7] - d[8] - d[9] + d[10] + d[15] - d[16] + d[17] - d[18];
-    const R jz = d[5] - d[6] + d[11] - d[12] - d[13] + d[14] + d[15] - d[16] - d[17] + d[18];
     const R rho = (R)B->rho0 + drho;
     const R ir = R(1) / rho;
-    const R ux = (jx + R(0.5) * fx) * ir;
-    const R uy = (jy + R(0.5) * fy) * ir;
-    const R uz = (jz + R(0.5) * fz) * ir;
-    const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
-    const R uF3 = R(3) * (ux * fx + uy * fy + uz * fz);
     const R om = (R)B->omega, gu = (R)B->guo;
     const R keep = R(1) - om;
+    R ax, ay, az;  // j + F/2 (FP32 path)
+    double Ax = 0.0, Ay = 0.0, Az = 0.0;  // j + F/2 in FP64 (ACC)
+    if (ACC) {
+        // pairs of opposite populations first: each difference is exact in
+        // FP64, and few FP64 values are live at a time
+        Ax = 0.5 * (double)fx;
+        Ay = 0.5 * (double)fy;
+        Az = 0.5 * (double)fz;
+#pragma unroll
+        for (int i = 1; i < 19; i += 2) {
+            const double q = (double)d[i] - (double)d[i + 1];
+            if (cx(i)) Ax = cx(i) > 0 ? Ax + q : Ax - q;
+            if (cy(i)) Ay = cy(i) > 0 ? Ay + q : Ay - q;
+            if (cz(i)) Az = cz(i) > 0 ? Az + q : Az - q;
+        }
+        ax = (R)Ax;
+        ay = (R)Ay;
+        az = (R)Az;
+    } else {
+        const R jx = d[1] - d[2] + d[7] - d[8] + d[9] - d[10] + d[11] - d[12] + d[13] - d[14];
+        const R jy = d[3] - d[4] + d[7] - d[8] - d[9] + d[10] + d[15] - d[16] + d[17] - d[18];
+        const R jz = d[5] - d[6] + d[11] - d[12] - d[13] + d[14] + d[15] - d[16] - d[17] + d[18];
+        ax = jx + R(0.5) * fx;
+        ay = jy + R(0.5) * fy;
+        az = jz + R(0.5) * fz;
+    }
+    const R ux = ax * ir, uy = ay * ir, uz = az * ir;
+    const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+    const R uF3 = R(3) * (ux * fx + uy * fy + uz * fz);
     {  // rest population: e = 0
         const R w = wt<R>(0);
         const R deq = w * fmadd(-rho, usq, drho);
@@ -104,12 +153,24 @@ __device__ __forceinline__ void collide(const BoxDev* __restrict__ B, R (&d)[19]
         const R w = wt<R>(i);
         const R eu = edot<R>(i, ux, uy, uz), eF = edot<R>(i, fx, fy, fz);
         const R even = w * fmadd(rho, fmadd(R(4.5) * eu, eu, -usq), drho);
-        const R odd = (R(3) * w) * (rho * eu);
         const R gw = gu * w;
         const R seven = gw * fmadd(R(9) * eu, eF, -uF3);
-        const R sodd = (R(3) * gw) * eF;
-        d[i] = fmadd(keep, d[i], fmadd(om, even + odd, seven + sodd));
-        d[i + 1] = fmadd(keep, d[i + 1], fmadd(om, even - odd, seven - sodd));
+        if (ACC) {
+            // odd part of omega deq_i + S_i in FP64 (the source's odd part, a
+            // constant for a constant force, may keep its FP32 rounding: that
+            // is a fixed relative error of the force, not a drift)
+            const R sodd = (gu * codd<R>(i)) * eF;
+            const double odd = fmadd((double)om * codd<double>(i), edot<double>(i, Ax, Ay, Az), (double)sodd);
+            const double ev = (double)fmadd(om, even, seven);
+            d[i] = fmadd(keep, d[i], (R)(ev + odd));
+            d[i + 1] = fmadd(keep, d[i + 1], (R)(ev - odd));
+        } else {
+            const R c = codd<R>(i);
+            const R odd = c * edot<R>(i, ax, ay, az);
+            const R sodd = (gu * c) * eF;
+            d[i] = fmadd(keep, d[i], fmadd(om, even + odd, seven + sodd));
+            d[i + 1] = fmadd(keep, d[i + 1], fmadd(om, even - odd, seven - sodd));
+        }
     }
 }
 
@@ -124,16 +185,33 @@ __device__ __forceinline__ void collide(const BoxDev* __restrict__ B, R (&d)[19]
 // 4.5 (A : e e - tr A / 3)], A the second moment of the deviations less
 // drho/3 I; what that leaves of the incoming populations (the
 // non-hydrodynamic part) is kept scaled by g_odd and g_even in its parts odd
-// and even under e -> -e.  Rounded as written, like collide().
-template <typename R>
+// and even under e -> -e.  Rounded as written, like collide(), and, with ACC,
+// with the odd (momentum-carrying) parts in FP64 from the exact FP64 momentum
+// for the reason given there.
+template <typename R, bool ACC>
 __device__ __forceinline__ void collide_mrt(const BoxDev* __restrict__ B, R (&d)[19], R fx, R fy, R fz) {
 #pragma clang fp contract(off)
     R drho = 0;
 #pragma unroll
     for (int i = 0; i < 19; ++i) drho += d[i];
-    const R jx = d[1] - d[2] + d[7] - d[8] + d[9] - d[10] + d[11] - d[12] + d[13] - d[14];
-    const R jy = d[3] - d[4] + d[7] - d[8] - d[9] + d[10] + d[15] - d[16] + d[17] - d[18];
-    const R jz = d[5] - d[6] + d[11] - d[12] - d[13] + d[14] + d[15] - d[16] - d[17] + d[18];
+    R jx, jy, jz;
+    double Jx = 0.0, Jy = 0.0, Jz = 0.0;  // the momentum in FP64 (ACC)
+    if (ACC) {
+#pragma unroll
+        for (int i = 1; i < 19; i += 2) {
+            const double q = (double)d[i] - (double)d[i + 1];
+            if (cx(i)) Jx = cx(i) > 0 ? Jx + q : Jx - q;
+            if (cy(i)) Jy = cy(i) > 0 ? Jy + q : Jy - q;
+            if (cz(i)) Jz = cz(i) > 0 ? Jz + q : Jz - q;
+        }
+        jx = (R)Jx;
+        jy = (R)Jy;
+        jz = (R)Jz;
+    } else {
+        jx = d[1] - d[2] + d[7] - d[8] + d[9] - d[10] + d[11] - d[12] + d[13] - d[14];
+        jy = d[3] - d[4] + d[7] - d[8] - d[9] + d[10] + d[15] - d[16] + d[17] - d[18];
+        jz = d[5] - d[6] + d[11] - d[12] - d[13] + d[14] + d[15] - d[16] - d[17] + d[18];
+    }
     // second moment of the deviations
     const R sxy = d[7] + d[8] + d[9] + d[10], sxz = d[11] + d[12] + d[13] + d[14];
     const R syz = d[15] + d[16] + d[17] + d[18];
@@ -183,12 +261,24 @@ __device__ __forceinline__ void collide_mrt(const BoxDev* __restrict__ B, R (&d)
         if (cx(i) && cz(i)) { qa = qa + R(2 * cx(i) * cz(i)) * pxz; qb = qb + R(2 * cx(i) * cz(i)) * bxz; }
         if (cy(i) && cz(i)) { qa = qa + R(2 * cy(i) * cz(i)) * pyz; qb = qb + R(2 * cy(i) * cz(i)) * byz; }
         const R ein = w * (drho + R(4.5) * (qa - tra3)), eout = w * (drho + R(4.5) * (qb - trb3));
-        const R oin = (R(3) * w) * edot<R>(i, jx, jy, jz), oout = (R(3) * w) * edot<R>(i, kx, ky, kz);
         const R geven = R(0.5) * (d[i] + d[i + 1]) - ein;
-        const R godd = R(0.5) * (d[i] - d[i + 1]) - oin;
-        const R even = eout + ge * geven, odd = oout + go * godd;
-        d[i] = even + odd;
-        d[i + 1] = even - odd;
+        const R even = eout + ge * geven;
+        if (ACC) {
+            const double c = codd<double>(i);
+            const double oin = c * edot<double>(i, Jx, Jy, Jz);
+            const double oout = c * edot<double>(i, Jx + (double)fx, Jy + (double)fy, Jz + (double)fz);
+            const double godd = 0.5 * ((double)d[i] - (double)d[i + 1]) - oin;
+            const double odd = oout + (double)go * godd;
+            d[i] = (R)((double)even + odd);
+            d[i + 1] = (R)((double)even - odd);
+        } else {
+            const R c = codd<R>(i);
+            const R oin = c * edot<R>(i, jx, jy, jz), oout = c * edot<R>(i, kx, ky, kz);
+            const R godd = R(0.5) * (d[i] - d[i + 1]) - oin;
+            const R odd = oout + go * godd;
+            d[i] = even + odd;
+            d[i + 1] = even - odd;
+        }
     }
 }
 
@@ -236,8 +326,8 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
     R d[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) d[i] = dec<P>(raw[i], inv);
-    if (MRT) collide_mrt<R>(B, d, fx, fy, fz);
-    else collide<R>(B, d, fx, fy, fz);
+    if (MRT) collide_mrt<R, P == PREC_FP32>(B, d, fx, fy, fz);
+    else collide<R, P == PREC_FP32>(B, d, fx, fy, fz);
 
     // neighbour offsets with periodic wrap
     const int nx = B->nx, ny = B->ny, nz = B->nz;
@@ -298,7 +388,7 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
 // first and are in flight while the mask word and any coupling force are
 // fetched).  MRT: the boxes use the multiple-relaxation-time collision.
 template <int P, bool OBST, bool ALL, bool MRT, bool NT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(1)))
 lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int nblocks, int parity,
           int remap, int mode) {
     typedef typename Prec<P>::S S;
