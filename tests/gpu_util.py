@@ -7,19 +7,28 @@ velocity u, displacement X - X0, mesh velocity V):
     max |gpu - oracle| <= RTOL * max |oracle| + ATOL * scale_f
 
 RTOL is 1e-12 (FP64 form) or 1e-5 (FP32 form).  The absolute term is the
-round-off floor of the oracle's own FP64 representation: it stores full
-populations (~rho0) and absolute positions (~box length), so deviations that
-are tiny next to those carry ~1e-16 * scale of representation error no
-implementation can remove.  scale_f = rho0 for populations, 1 (lattice units)
-for velocities, the box length for positions.
+round-off floor of the FP64 representation both sides share: the oracle stores
+full populations (~rho0, ulp 5.6e-17) and both store absolute positions
+(~box length L, ulp ~2.2e-16 L), so deviations that are tiny next to those
+carry a few ulps of representation error that no implementation can remove.
+scale_f = rho0 for populations, 1 (lattice units) for velocities, the box
+length for positions and mesh velocities (the elastic forces turn the
+positions' round-off into velocity differences of the same size).  ATOL is
+about four times the largest such floor measured over the GPU parity tests
+(|gpu - oracle| / scale_f where the relative bar alone would not hold):
+deviations 2.2e-15, fluid velocity 2.2e-15, displacement 5.3e-16 L, mesh
+velocity 6.2e-16 L.  The FP32 form shares these floors: its positions are
+FP64 as well, and the relative bar covers everything above them.
 """
+import json
+import os
 import sys
 
 import numpy as np
 
 W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
 RTOL = {"fp64": 1e-12, "fp32": 1e-5}
-ATOL = {"fp64": 1e-14, "fp32": 1e-10}
+ATOL = {"delta": 1e-14, "u": 1e-14, "dX": 2.5e-15, "V": 2.5e-15}
 
 
 def say(*a):
@@ -70,8 +79,15 @@ def check(g, o, prec, rho0, box_len, keys=("delta", "u", "dX", "V")):
             continue
         err = float(np.abs(np.asarray(g[k]) - np.asarray(o[k])).max())
         ref = float(np.abs(o[k]).max())
-        bound = RTOL[prec] * ref + ATOL[prec] * scale[k]
+        bound = RTOL[prec] * ref + ATOL[k] * scale[k]
         out[k] = (err, ref, bound, err <= bound)
+    log = os.environ.get("OIF_PARITY_LOG")
+    if log:  # measured errors, for the record of the absolute floors
+        with open(log, "a") as fh:
+            for k, (err, ref, bound, ok) in out.items():
+                fh.write(json.dumps({"test": os.environ.get("PYTEST_CURRENT_TEST", ""), "prec": prec,
+                                     "field": k, "err": err, "ref": ref, "scale": scale[k],
+                                     "ok": ok}) + "\n")
     return out
 
 

@@ -93,3 +93,68 @@ def test_scale_case_full_size_fp64(oif, orc, tmp_path):
     res = check(g, o, "fp64", box.rho0, box.nx)
     say(f"   {fmt(res)}")
     assert all(v[3] for v in res.values()), fmt(res)
+
+
+@pytest.mark.timeout(600)
+def test_scale_case_full_size_fp16(oif, orc, tmp_path):
+    """512x256x256 box, 5000 cells, FP16 storage of the deviations (x 2^12),
+    one step from the random start.  Each stored deviation is rounded once to
+    11 significant bits (unit roundoff 2^-11 = 4.9e-4 of its value, the scale
+    keeps them clear of the subnormal range): deviations and velocity within
+    1e-3 of their maximum, mesh fields at the FP32 bar (the mesh arithmetic is
+    FP32 and reads the velocity only through the interpolation, which uses the
+    step's starting populations written from the same FP64 start)."""
+    box = synth.config_scale(1)
+    g, o = run_case(oif, orc, box, "fp16", 1, 61, str(tmp_path / "t.json"))
+    e = {k: rel(g[k], o[k]) for k in ("delta", "u", "dX", "V")}
+    say("   " + ", ".join(f"{a}={b:.2e}" for a, b in e.items()))
+    assert e["u"] < 1e-3 and e["delta"] < 1e-3
+    res = check(g, o, "fp32", box.rho0, box.nx, keys=("dX", "V"))
+    say(f"   {fmt(res)}")
+
+
+def test_precision_case_full_size_bf16(oif, orc, tmp_path):
+    """256x128x128 box, 500 cells, BF16 storage of the deviations, two steps
+    from the random start.  BF16 keeps 8 significant bits (unit roundoff
+    2^-9 = 2.0e-3 of a value); two roundings of each stored deviation bound
+    the deviations' and the velocity's error by 2 x 2^-9 of their maximum."""
+    box = synth.config_precision(2)
+    g, o = run_case(oif, orc, box, "bf16", 2, 37, str(tmp_path / "t.json"))
+    e = {k: rel(g[k], o[k]) for k in ("delta", "u", "dX", "V")}
+    say("   " + ", ".join(f"{a}={b:.2e}" for a, b in e.items()))
+    assert e["u"] < 2 * 2.0 ** -9 and e["delta"] < 2 * 2.0 ** -9
+
+
+@pytest.mark.timeout(900)
+def test_batch_case_all_boxes_vs_oracle(oif, orc, tmp_path):
+    """The whole batching case (32 boxes, 2.6 M nodes, 1-20 spheres of
+    162/642/2562 nodes each) stepped through one batch in its autotuned launch
+    configuration, from random starts, against the oracle box by box after 3
+    steps, at the FP32 bar."""
+    boxes = synth.config_batch(steps=3)
+    say(f"[fullsize] batching case: {len(boxes)} boxes, {sum(b.n_nodes for b in boxes)} nodes, "
+        f"{sum(b.n_mesh_nodes for b in boxes)} mesh nodes, 3 steps")
+    systems, ctxs = [], []
+    for k, bx in enumerate(boxes):
+        s = seeded_start(bx, orc, 1000 + k)
+        c = oif.Context.from_box(bx, precision="fp32")
+        c.write_populations(s.n)
+        c.write_mesh(-1, s.X, s.V)
+        systems.append((s, s.X.copy()))
+        ctxs.append(c)
+    B = oif.Batch(ctxs)
+    B.autotune(str(tmp_path / "t.json"))
+    B.step(3)
+    worst = {}
+    for k, (bx, c, (s, X0)) in enumerate(zip(boxes, ctxs, systems)):
+        s.run(3)
+        res = check(gpu_fields(c, bx.rho0, X0), oracle_fields(s, X0), "fp32", bx.rho0,
+                    max(bx.nx, bx.ny, bx.nz))
+        for f, v in res.items():
+            r = v[0] / v[1] if v[1] else 0.0
+            worst[f] = max(worst.get(f, 0.0), r)
+        assert all(v[3] for v in res.values()), f"{bx.name}: {fmt(res)}"
+    say("   worst relative error over the 32 boxes: " + ", ".join(f"{f}={v:.2e}" for f, v in worst.items()))
+    B.close()
+    for c in ctxs:
+        c.close()

@@ -227,6 +227,8 @@ def test_large_meshes_vs_oracle(oif, orc, prec):
     c.step(30)
     i = c.info()  # objects are placed at the first step
     assert 0 < i.lds_objects < i.n_objects
+    # the meshes in the scratch keep their coupling area in LDS
+    assert i.lds_objects + i.cpl_objects == i.n_objects and i.cpl_lds_bytes > 0
     s = orc.System(bx)
     X0 = s.X.copy()
     s.run(30)
@@ -234,6 +236,33 @@ def test_large_meshes_vs_oracle(oif, orc, prec):
     say(f"   {bx.name} ({len(bx.objects)} cells, {i.lds_objects} in LDS): {fmt(res)}")
     assert all(v[3] for v in res.values())
     c.close()
+
+@pytest.mark.parametrize("case", ["sphere20", "precision256"])
+def test_touched_nodes_vs_oracle(oif, orc, case):
+    """oif_touched_nodes (the count of distinct lattice nodes inside some mesh
+    node's 2x2x2 stencil, the coupling term of the byte model) equals the
+    oracle's count, at the start and after the meshes have moved."""
+    box = synth.config_sphere_fp64(20) if case == "sphere20" else synth.config_precision(2)
+    prec = "fp64" if case == "sphere20" else "fp32"
+    say(f"[aux] touched nodes vs oracle, {box.name}")
+    c = oif.Context.from_box(box, precision=prec)
+    s = orc.System(box)
+    if case == "sphere20":
+        s.V[:] = 0.05 * np.random.default_rng(3).standard_normal(s.V.shape)
+        c.write_mesh(-1, None, s.V)
+    counts = []
+    for steps in (0, 2):
+        if steps:
+            c.step(steps)
+            s.run(steps)
+            X, _ = c.read_mesh(-1)
+            assert np.abs(X - s.X).max() < 1e-9
+        g, o = c.touched_nodes(), s.touched()
+        counts.append((g, o))
+        assert g == o, (steps, g, o)
+    say(f"   (gpu, oracle) at steps 0 and 2: {counts}")
+    c.close()
+
 
 def test_object_analysis_vs_oracle(oif, orc):
     say("[aux] object analysis")

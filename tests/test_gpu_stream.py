@@ -1,0 +1,104 @@
+"""The stream boundary: a context bound to a PyTorch (HIP) stream with
+oif_bind_stream runs its work there.  Checked in a child process that imports
+torch before loading liboif.so, so that both use one HIP runtime (torch ships
+its own copy of it; the library then resolves to the copy already loaded):
+
+* eager steps and steps replayed from a captured hipGraph on the torch stream
+  give the same bits as a context on its own stream, and so do steps after
+  unbinding;
+* the work is ordered on that stream: with a spin kernel of known length
+  queued on the torch stream first, a bound context's step (which ends by
+  synchronising its stream) returns only after the spin, an unbound one
+  does not wait for it."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+SCRIPT = r"""
+import sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import torch
+torch.cuda.init()
+ts = torch.cuda.Stream()
+from paper_1312_3426_amd import oif, synth
+oif.lib()
+hips = sorted({{ln.split()[-1] for ln in open('/proc/self/maps') if 'libamdhip64' in ln}})
+print('HIP runtimes loaded:', hips, flush=True)
+if len(hips) != 1:
+    sys.exit(3)
+
+def state(c):
+    X, V = c.read_mesh(-1)
+    return [c.read_populations(), X, V]
+
+def same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+box = synth.config_channel_rbc(30, n_cells=4)
+ref = oif.Context.from_box(box, precision='fp32')
+bnd = oif.Context.from_box(box, precision='fp32')
+bnd.bind_stream(ts.cuda_stream)
+for c in (ref, bnd):
+    c.step(10)
+    c.set_graph(4)
+    c.step(10)
+assert same(state(ref), state(bnd)), 'bound eager + graph steps differ'
+print('bound eager + graph: bitwise equal', flush=True)
+
+# spin kernel of a measured length on the torch stream
+def spin(cycles):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(ts):
+        e0.record(ts)
+        torch.cuda._sleep(cycles)
+        e1.record(ts)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+cycles = 1 << 20
+ms = spin(cycles)
+while ms < 200.0 and cycles < (1 << 40):
+    cycles *= 2
+    ms = spin(cycles)
+print(f'spin: {{cycles}} cycles = {{ms:.1f}} ms', flush=True)
+assert 200.0 <= ms < 5000.0
+for c, bound in ((ref, False), (bnd, True)):
+    c.set_graph(0)
+    with torch.cuda.stream(ts):
+        torch.cuda._sleep(cycles)
+    t0 = time.perf_counter()
+    c.step(1)
+    dt = (time.perf_counter() - t0) * 1e3
+    ts.synchronize()
+    print(f'step with the spin queued, bound={{bound}}: {{dt:.1f}} ms', flush=True)
+    if bound:
+        assert dt > 0.8 * ms, 'the bound step did not wait for the torch stream'
+    else:
+        assert dt < 0.5 * ms, 'the unbound step waited for the torch stream'
+bnd.bind_stream(None)
+ref.step(7)
+bnd.step(7)
+assert same(state(ref), state(bnd)), 'steps after unbinding differ'
+print('after unbinding: bitwise equal', flush=True)
+ref.close(); bnd.close()
+print('STREAM-OK', flush=True)
+"""
+
+
+def test_bind_torch_stream_eager_graph_and_order(tmp_path):
+    say("[stream] oif_bind_stream with a torch stream (child process)")
+    env = dict(os.environ, PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-u", "-c", SCRIPT.format(root=ROOT)], env=env, capture_output=True,
+                       text=True, timeout=300)
+    say(r.stdout[-3000:])
+    if r.returncode != 0:
+        say(r.stderr[-3000:])
+    assert r.returncode == 0 and "STREAM-OK" in r.stdout
