@@ -145,6 +145,9 @@ typedef struct {
     int overlap;        /* 1 if untouched nodes are updated concurrently with the membrane kernel */
     int integrator;     /* OIF_INTEGRATOR_EULER or OIF_INTEGRATOR_VERLET */
     int lb_nontemporal; /* population reads of the lattice kernel: 1 non-temporal, 0 ordinary */
+    int cpl_objects;    /* objects in the global scratch whose coupling area (stencil bits,
+                           touched-node velocities, force sums) sits in LDS */
+    long long cpl_lds_bytes; /* LDS bytes per workgroup of that coupling area (0: no such object) */
 } oif_info_t;
 
 /* FP64 conservation diagnostics and watchdog state. */

@@ -287,8 +287,9 @@ struct oif_ctx {
     DevBuf tmpl_dev, obj_dev, X_dev, V_dev, F_dev, geo_dev, scratch_dev;
     std::vector<unsigned char> obj_host; // ObjDev<real> array as uploaded (sorted)
     int n_lds_obj = 0;          // objects [0, n_lds_obj) use LDS, the rest global scratch
+    int n_cpl_obj = 0;          // the next n_cpl_obj keep their coupling area in LDS
     size_t lds_need = 0;
-    size_t cpl_need = 0;        // LDS for the coupling area of the scratch objects (0: none)
+    size_t cpl_need = 0;        // LDS for the coupling area of those objects
     int any_conservative = 0;   // some template uses the conservative force model
 
     // launch configuration
@@ -327,7 +328,7 @@ struct oif_batch {
     int precision = 0;
     DevBuf boxes_dev, work_dev, obj_dev;
     std::vector<unsigned char> obj_host;
-    int nblocks = 0, nobj = 0, n_lds_obj = 0;
+    int nblocks = 0, nobj = 0, n_lds_obj = 0, n_cpl_obj = 0;
     // the work list holds the boxes grouped by lattice-kernel variant
     // (obstacles, MRT collision): one launch per group
     int var_off[5] = {0, 0, 0, 0, 0};
@@ -588,7 +589,9 @@ int upload_mesh_t(oif_ctx* c) {
     HIPCALL(c, hipMemcpy(c->X_dev.p, xl.data(), n * sizeof(double), hipMemcpyHostToDevice));
     HIPCALL(c, hipMemcpy(c->V_dev.p, vl.data(), n * sizeof(real), hipMemcpyHostToDevice));
 
-    // objects sorted: LDS-resident first, each group largest mesh first
+    // objects in three groups, each launched on its own and sorted largest
+    // mesh first: meshes staged in LDS whole; meshes in the global scratch
+    // whose coupling area fits in LDS; meshes entirely in the scratch
     const size_t budget = c->max_lds;
     std::vector<int> order(c->obj.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
@@ -596,12 +599,18 @@ int upload_mesh_t(oif_ctx* c) {
         const Template& T = c->tmpl[c->obj[i].tid];
         return mesh_lds_bytes(c->d.precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T));
     };
+    auto cpl = [&](int i) {
+        const Template& T = c->tmpl[c->obj[i].tid];
+        return mesh_cpl_lds_bytes(c->d.precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T));
+    };
+    auto group = [&](int i) { return need(i) <= budget ? 0 : (cpl(i) <= budget ? 1 : 2); };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const bool la = need(a) <= budget, lb = need(b) <= budget;
-        if (la != lb) return la;
+        const int ga = group(a), gb = group(b);
+        if (ga != gb) return ga < gb;
         return c->obj[a].nv > c->obj[b].nv;
     });
     c->n_lds_obj = 0;
+    c->n_cpl_obj = 0;
     c->lds_need = 0;
     c->cpl_need = 0;
     c->any_conservative = 0;
@@ -611,17 +620,18 @@ int upload_mesh_t(oif_ctx* c) {
     c->mark_lds = std::min<size_t>(c->mark_lds, 49152);  // larger stencil boxes mark corner by corner
     size_t scratch_total = 0;
     for (int i : order) {
-        if (need(i) <= budget) {
+        const int g = group(i);
+        if (g == 0) {
             ++c->n_lds_obj;
             c->lds_need = std::max(c->lds_need, need(i));
         } else {
             scratch_total += (need(i) + 255) & ~(size_t)255;
-            const Template& T = c->tmpl[c->obj[i].tid];
-            c->cpl_need = std::max(c->cpl_need, mesh_cpl_lds_bytes(c->d.precision, T.nv, T.nt, T.ne, T.ucap,
-                                                                   T.ccap, tmpl_conservative(T)));
+            if (g == 1) {
+                ++c->n_cpl_obj;
+                c->cpl_need = std::max(c->cpl_need, cpl(i));
+            }
         }
     }
-    if (c->cpl_need > budget) c->cpl_need = 0;  // the coupling area stays in the scratch too
     if ((rc = dev_alloc(c, c->scratch_dev, scratch_total))) return rc;
     if ((rc = setup_repulsion(c, sizeof(real)))) return rc;
     std::vector<ObjDev<real>> od(c->obj.size());
@@ -699,11 +709,19 @@ int enqueue_mesh(oif_ctx* c, int par, hipStream_t s, int mark_next) {
         ml.lds_bytes = c->lds_need;
         HIPCALL(c, launch_mesh(ml));
     }
-    if ((int)c->obj.size() > c->n_lds_obj) {
+    if (c->n_cpl_obj > 0) {
         ml.objs = (const unsigned char*)c->obj_dev.p + osz * c->n_lds_obj;
-        ml.nobj = (int)c->obj.size() - c->n_lds_obj;
+        ml.nobj = c->n_cpl_obj;
         ml.lds_bytes = 0;
         ml.cpl_lds_bytes = c->cpl_need;
+        HIPCALL(c, launch_mesh(ml));
+    }
+    const int done = c->n_lds_obj + c->n_cpl_obj;
+    if ((int)c->obj.size() > done) {
+        ml.objs = (const unsigned char*)c->obj_dev.p + osz * done;
+        ml.nobj = (int)c->obj.size() - done;
+        ml.lds_bytes = 0;
+        ml.cpl_lds_bytes = 0;
         HIPCALL(c, launch_mesh(ml));
     }
     return OIF_OK;
@@ -787,15 +805,31 @@ int enqueue_steps(oif_ctx* c, int n, int parity0, hipStream_t s) {
     return OIF_OK;
 }
 
-int run_diag(oif_ctx* c, double out[10], unsigned* status) {
-    double* part = (double*)c->part_dev.p;
+// FP64 sums of the current state: per-block and per-object partials in
+// `part` (5 doubles each), the ten totals in `fin`, copied to out[10].
+int run_diag_in(oif_ctx* c, double* part, double* fin, double out[10], unsigned* status) {
     HIPCALL(c, launch_diag_lattice(c->box_dev, c->d.precision, c->parity, part, c->diag_blocks, c->stream));
     HIPCALL(c, launch_diag_mesh(c->obj_dev.p, (int)c->obj.size(), c->d.precision, part + 5 * c->diag_blocks, c->stream));
-    HIPCALL(c, launch_diag_final(part, c->diag_blocks, (int)c->obj.size(), (double*)c->diag_out.p, c->stream));
-    HIPCALL(c, hipMemcpyAsync(out, c->diag_out.p, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCALL(c, launch_diag_final(part, c->diag_blocks, (int)c->obj.size(), fin, c->stream));
+    HIPCALL(c, hipMemcpyAsync(out, fin, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCALL(c, hipMemcpyAsync(status, c->status, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
     HIPCALL(c, hipStreamSynchronize(c->stream));
     return OIF_OK;
+}
+
+int run_diag(oif_ctx* c, double out[10], unsigned* status) {
+    return run_diag_in(c, (double*)c->part_dev.p, (double*)c->diag_out.p, out, status);
+}
+
+void fill_diag(const oif_ctx* c, const double out[10], unsigned st, oif_diag* d) {
+    d->mass = (double)c->N * c->d.rho0 + out[0];
+    for (int k = 0; k < 3; ++k) {
+        d->momentum_fluid[k] = out[1 + k];
+        d->momentum_mesh[k] = out[6 + k];
+    }
+    d->nonfinite = (out[4] != 0 || out[9] != 0 || (st & ST_NONFINITE)) ? 1 : 0;
+    d->clamped = (st & ST_CLAMPED) ? 1 : 0;
+    d->overflow = (st & ST_OVERFLOW) ? 1 : 0;
 }
 
 int watchdog(oif_ctx* c) {
@@ -1615,6 +1649,8 @@ int oif_info(oif_ctx* c, oif_info_t* info) {
     info->max_lds = (long long)c->max_lds;
     info->overlap = c->overlap;
     info->lds_objects = c->n_lds_obj;
+    info->cpl_objects = c->n_cpl_obj;
+    info->cpl_lds_bytes = (long long)c->cpl_need;
     info->integrator = c->integrator;
     info->lb_nontemporal = c->lb_nt;
     return OIF_OK;
@@ -1627,14 +1663,7 @@ int oif_diagnostics(oif_ctx* c, oif_diag* d) {
     double out[10];
     unsigned st = 0;
     if ((rc = run_diag(c, out, &st))) return rc;
-    d->mass = (double)c->N * c->d.rho0 + out[0];
-    for (int k = 0; k < 3; ++k) {
-        d->momentum_fluid[k] = out[1 + k];
-        d->momentum_mesh[k] = out[6 + k];
-    }
-    d->nonfinite = (out[4] != 0 || out[9] != 0 || (st & ST_NONFINITE)) ? 1 : 0;
-    d->clamped = (st & ST_CLAMPED) ? 1 : 0;
-    d->overflow = (st & ST_OVERFLOW) ? 1 : 0;
+    fill_diag(c, out, st, d);
     return OIF_OK;
 }
 
@@ -1912,31 +1941,32 @@ int batch_build(oif_batch* b) {
     BHIP(b, hipMemcpy(b->work_dev.p, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice));
     // objects of all boxes: LDS-resident group first, each largest mesh first
     const size_t osz = objdev_size(b->precision);
-    struct Ent { const unsigned char* p; bool lds; int nv; size_t need, cpl; };
+    struct Ent { const unsigned char* p; int group; int nv; size_t need, cpl; };
     std::vector<Ent> ents;
     for (oif_ctx* c : b->ctx) {
         const size_t n = c->obj.size();
         for (size_t k = 0; k < n; ++k) {
             const unsigned char* p = c->obj_host.data() + k * osz;
-            const bool lds = (int)k < c->n_lds_obj;
+            const int group = (int)k < c->n_lds_obj ? 0 : ((int)k < c->n_lds_obj + c->n_cpl_obj ? 1 : 2);
             // the template pointer of the sorted entry says which mesh it is
             const void* tptr = b->precision == OIF_PREC_FP64 ? (const void*)((const ObjDev<double>*)p)->t
                                                             : (const void*)((const ObjDev<float>*)p)->t;
             const size_t tsz = b->precision == OIF_PREC_FP64 ? sizeof(TmplDev<double>) : sizeof(TmplDev<float>);
             const size_t tid = ((const unsigned char*)tptr - (const unsigned char*)c->tmpl_dev.p) / tsz;
             const Template& T = c->tmpl[tid];
-            ents.push_back({p, lds, T.nv,
+            ents.push_back({p, group, T.nv,
                             mesh_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T)),
                             mesh_cpl_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap,
                                                tmpl_conservative(T))});
         }
     }
     std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& c) {
-        if (a.lds != c.lds) return a.lds;
+        if (a.group != c.group) return a.group < c.group;
         return a.nv > c.nv;
     });
     std::vector<unsigned char> host(ents.size() * osz);
     b->n_lds_obj = 0;
+    b->n_cpl_obj = 0;
     b->lds_need = 0;
     b->cpl_need = 0;
     b->any_conservative = 0;
@@ -1944,14 +1974,14 @@ int batch_build(oif_batch* b) {
         for (const Template& T : c->tmpl) b->any_conservative |= tmpl_conservative(T);
     for (size_t k = 0; k < ents.size(); ++k) {
         std::memcpy(host.data() + k * osz, ents[k].p, osz);
-        if (ents[k].lds) {
+        if (ents[k].group == 0) {
             ++b->n_lds_obj;
             b->lds_need = std::max(b->lds_need, ents[k].need);
-        } else {
+        } else if (ents[k].group == 1) {
+            ++b->n_cpl_obj;
             b->cpl_need = std::max(b->cpl_need, ents[k].cpl);
         }
     }
-    if (b->ctx.empty() || b->cpl_need > b->ctx[0]->max_lds) b->cpl_need = 0;
     b->nobj = (int)ents.size();
     b->obj_dev.release();
     BHIP(b, hipMalloc(&b->obj_dev.p, host.size() + 16));
@@ -1981,11 +2011,19 @@ int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<h
             ml.lds_bytes = b->lds_need;
             BHIP(b, launch_mesh(ml));
         }
-        if (b->nobj > b->n_lds_obj) {
+        if (b->n_cpl_obj > 0) {
             ml.objs = (const unsigned char*)b->obj_dev.p + osz * b->n_lds_obj;
-            ml.nobj = b->nobj - b->n_lds_obj;
+            ml.nobj = b->n_cpl_obj;
             ml.lds_bytes = 0;
             ml.cpl_lds_bytes = b->cpl_need;
+            BHIP(b, launch_mesh(ml));
+        }
+        const int done = b->n_lds_obj + b->n_cpl_obj;
+        if (b->nobj > done) {
+            ml.objs = (const unsigned char*)b->obj_dev.p + osz * done;
+            ml.nobj = b->nobj - done;
+            ml.lds_bytes = 0;
+            ml.cpl_lds_bytes = 0;
             BHIP(b, launch_mesh(ml));
         }
         if (ev) (void)hipEventRecord((*ev)[3 * k + 1], s);
