@@ -11,10 +11,17 @@ JSON line:
                  bytes 2 x 19 x 4 per node per launch / its average duration
                  from HIP events on its own stream during the timed region
   cpu_baseline   the FP64 oracle, single-threaded on the host, on a bounded
-                 sample (a few steps of the same workload)
+                 sample (a few steps of the same workload); beside it the
+                 oracle's OpenMP build (lattice sweeps on all host cores) on
+                 the 64^3 sub-run (31 cells, same number density), 500 steps,
+                 whose velocity field is the reference of `storage`
   storage        FP16/BF16 deviation storage: throughput and velocity error
-                 against the FP64 form after the same number of steps on the
-                 64^3 sub-run (31 cells, same number density)
+                 against the FP64 oracle after 500 steps of that sub-run
+                 (and the FP32 and FP64 forms' errors on the same run)
+  scale          the 512x256x256 box with 5000 cells (the case whose
+                 populations exceed the last-level cache in both storage
+                 forms): FP32 and FP16, kernel times, lattice-only and
+                 full-step fractions of the HBM peak
   batching       32 uneven boxes (1.05-4.7 M nodes in all, 1-20 cells each of
                  162/642/2562 nodes): one launch per kernel over all boxes,
                  eager and as a captured graph, against a loop that steps the
@@ -107,19 +114,15 @@ def measure(oif, box, prec, steps, warmup, graph_steps=0, tune=None):
     return out
 
 
-def storage_error(oif, steps):
-    """Velocity error of FP16/BF16/FP32 storage against the FP64 form after
-    `steps` steps of the 64^3 sub-run."""
+def storage_error(oif, steps, u_ref):
+    """Velocity error of the FP64/FP32/FP16/BF16 forms after `steps` steps of
+    the 64^3 sub-run against the oracle's velocity field u_ref."""
     from paper_1312_3426_amd import synth
 
     box = synth.config_precision_subbox(steps)
-    ref = oif.Context.from_box(box, precision="fp64")
-    ref.step(steps)
-    u_ref = ref.read_velocity()
-    ref.close()
     umax = float(np.abs(u_ref).max())
     out = {}
-    for prec in ("fp32", "fp16", "bf16"):
+    for prec in ("fp64", "fp32", "fp16", "bf16"):
         c = oif.Context.from_box(box, precision=prec)
         c.step(steps)
         du = c.read_velocity() - u_ref
@@ -127,6 +130,56 @@ def storage_error(oif, steps):
         out[prec] = dict(u_err_max=float(np.abs(du).max() / umax),
                          u_err_rms=float(np.sqrt(np.mean(du * du)) / umax))
     return out, umax
+
+
+def host_cpu():
+    """CPU model, logical CPUs of the host and the CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1, len(os.sched_getaffinity(0))
+
+
+def oracle_subrun_child(out, steps, threads):
+    """Child process of the CPU-baseline leg (no GPU): the oracle's OpenMP
+    build on the 64^3 sub-run; writes the velocity field and the timing."""
+    import oracle
+    from paper_1312_3426_amd import synth
+
+    used = oracle.threads(threads)
+    box = synth.config_precision_subbox(steps)
+    t0 = time.perf_counter()
+    s = oracle.System(box)
+    t1 = time.perf_counter()
+    s.run(steps)
+    t2 = time.perf_counter()
+    np.savez(out, u=s.fields()["u"], threads=used, run_s=t2 - t1, setup_s=t1 - t0, nodes=box.n_nodes,
+             mesh_nodes=box.n_mesh_nodes, steps=steps)
+
+
+def oracle_subrun(steps):
+    """Run oracle_subrun_child in a child process with the OpenMP oracle on all
+    CPUs this process may use; returns its record."""
+    import subprocess
+    import tempfile
+
+    import oracle
+
+    oracle.build(openmp=True)
+    _, _, ncpu = host_cpu()
+    with tempfile.TemporaryDirectory() as d:
+        out = os.path.join(d, "sub.npz")
+        env = dict(os.environ, OIF_ORACLE_OPENMP="1")
+        subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-subrun", out, "--steps",
+                        str(steps), "--threads", str(ncpu)], env=env, check=True, timeout=900)
+        r = np.load(out)
+        return {k: r[k] for k in r.files}
 
 
 def batching(oif, steps, tune):
@@ -161,6 +214,8 @@ def batching(oif, steps, tune):
             "steps": steps, "loop_mlups": ml(loop_ms), "batched_mlups": ml(eager_ms),
             "batched_graph_mlups": ml(graph_ms), "speedup_batched": round(loop_ms / eager_ms, 3),
             "speedup_batched_graph": round(loop_ms / graph_ms, 3),
+            "friction": boxes[0].friction,
+            "moduli_2562": "the 2562-node template takes the default moduli x 0.25 (stiffer mesh, same dt)",
             "timing": "loop and batched: HIP events around the launches; graph: wall clock incl. "
                       "one FP64 watchdog"}
 
@@ -221,7 +276,9 @@ def obstacles(oif, steps):
     return out
 
 
-def cpu_baseline(box, steps):
+def cpu_baseline(box, steps, sub=None):
+    """The oracle as it stands (serial) on a few steps of the full workload;
+    with `sub`, the OpenMP run of the 64^3 sub-run beside it."""
     import oracle
 
     oracle.build()
@@ -230,10 +287,49 @@ def cpu_baseline(box, steps):
     t1 = time.perf_counter()
     s.run(steps)
     t2 = time.perf_counter()
-    return dict(value=box.n_nodes * steps / (t2 - t1) / 1e6, unit="MLUPS", cores=1, kind="oracle",
-                sample=f"{steps} coupled steps of the full workload ({box.nx}x{box.ny}x{box.nz}, "
-                       f"{len(box.objects)} cells), single-threaded FP64, {t2 - t1:.1f} s "
-                       f"(+{t1 - t0:.1f} s setup)")
+    model, ncpu, avail = host_cpu()
+    out = dict(value=box.n_nodes * steps / (t2 - t1) / 1e6, unit="MLUPS", cores=1, kind="oracle",
+               sample=f"{steps} coupled steps of the full workload ({box.nx}x{box.ny}x{box.nz}, "
+                      f"{len(box.objects)} cells), single-threaded FP64, {t2 - t1:.1f} s "
+                      f"(+{t1 - t0:.1f} s setup)",
+               cpu_model=model, nproc=ncpu, cpus_available=avail)
+    if sub is not None:
+        n, st, sec = int(sub["nodes"]), int(sub["steps"]), float(sub["run_s"])
+        out["all_cores"] = dict(value=round(n * st / sec / 1e6, 2), unit="MLUPS", cores=int(sub["threads"]),
+                                sample=f"{st} coupled steps of the 64^3 sub-run (31 cells), lattice sweeps "
+                                       f"on {int(sub['threads'])} threads (OpenMP build), coupling and "
+                                       f"membrane serial, {sec:.1f} s")
+    return out
+
+
+def scale_leg(oif, steps, warmup, tune):
+    """The 512x256x256 / 5000-cell case in FP32 and FP16 storage: eager steps
+    timed by HIP events, kernel times, and the lattice-only and full-step byte
+    rates against the HBM peak."""
+    from paper_1312_3426_amd import synth
+
+    box = synth.config_scale(steps)
+    N, M = box.n_nodes, box.n_mesh_nodes
+    out = {"workload": box.name, "nodes": N, "mesh_nodes": M, "steps": steps}
+    for prec in ("fp32", "fp16"):
+        log(f"[bench] scale case, {prec}")
+        r = measure(oif, box, prec, steps, warmup, tune=tune)
+        ms = r["total_ms"] / steps
+        b = BYTES_POP[prec]
+        lb_bytes = 2 * 19 * b * N
+        full = lb_bytes + 48 * M + (19 * b + 24) * r["touched"]
+        out[prec] = {"ms_per_step": round(ms, 5), "mlups": round(N / (ms * 1e-3) / 1e6, 2),
+                     "mesh_node_updates_per_s": round(M / (ms * 1e-3), 1),
+                     "lb_ms": round(r["lb_ms"], 5), "mesh_ms": round(r["mesh_ms"], 5),
+                     "lb_GB/s": round(lb_bytes / (r["lb_ms"] * 1e-3) / 1e9, 1),
+                     "lb_frac": round(lb_bytes / (r["lb_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "touched_nodes": r["touched"], "full_step_bytes": full,
+                     "full_step_frac": round(full / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "launch": {k: r[k] for k in ("lb_block", "mesh_block", "xcd_remap", "nt_loads")}}
+    out["fp16_speedup"] = round(out["fp32"]["ms_per_step"] / out["fp16"]["ms_per_step"], 3)
+    out["bytes_model"] = ("lattice 2 x 19 x b per node; full step adds 48 B per mesh node and "
+                          "19 b + 24 B per touched lattice node (b = 4 FP32, 2 FP16)")
+    return out
 
 
 def main():
@@ -256,7 +352,14 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes, no autotuning")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run the plain copy kernel on BYTES bytes and print its bandwidth")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 512x256x256 / 5000-cell leg")
+    ap.add_argument("--scale-steps", type=int, default=10)
+    ap.add_argument("--oracle-subrun", default=None, metavar="OUT", help=argparse.SUPPRESS)
+    ap.add_argument("--threads", type=int, default=0, help=argparse.SUPPRESS)
     a = ap.parse_args()
+    if a.oracle_subrun:  # child process of the CPU-baseline leg: oracle only, no GPU
+        oracle_subrun_child(a.oracle_subrun, a.steps, a.threads)
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the sharding design is documented, not built)", file=sys.stderr)
@@ -327,7 +430,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": box.name, "nx": box.nx, "ny": box.ny, "nz": box.nz, "cells": len(box.objects),
-                   "mesh_nodes": M, "storage": "fp32", "launch": {k: r32[k] for k in ("lb_block", "mesh_block", "xcd_remap", "nt_loads")}},
+                   "mesh_nodes": M, "storage": "fp32", "tau": box.tau, "body_force": list(box.g),
+                   "friction": box.friction, "moduli": {k: getattr(box.templates[0], k) for k in
+                                                        ("ks", "kb", "kal", "kag", "kv")},
+                   "launch": {k: r32[k] for k in ("lb_block", "mesh_block", "xcd_remap", "nt_loads")}},
         "timing": ("hipGraph replays of 50 steps, wall clock between device synchronisations, "
                    "one FP64 watchdog included" if use_graph else "eager launches, HIP events"),
         "eager": {"ms_per_step": round(ms_eager, 5), "mlups": round(N / (ms_eager * 1e-3) / 1e6, 2)},
@@ -356,12 +462,20 @@ def main():
                               "lb_ms": round(res[p]["lb_ms"], 5),
                               "lb_GB/s": round(lbb / (res[p]["lb_ms"] * 1e-3) / 1e9, 1),
                               "mass_rel_drift": res[p]["mass_rel_drift"]}
-    if not a.no_storage:
+    sub = None
+    if not a.no_cpu:
+        log("[bench] oracle, OpenMP build, 64^3 sub-run, 500 steps (cpu baseline, storage-error reference)")
+        sub = oracle_subrun(500)
+        log(f"[bench]   {float(sub['run_s']):.1f} s on {int(sub['threads'])} threads")
+    if not a.no_storage and sub is not None:
         log("[bench] storage-form velocity error on the 64^3 sub-run")
-        err, umax = storage_error(oif, 500)
+        err, umax = storage_error(oif, 500, sub["u"])
         for p in err:
             line["storage"].setdefault(p, {}).update(err[p])
-        line["storage"]["error_reference"] = f"FP64 form, 64^3 sub-run, 500 steps, max|u| = {umax:.3e}"
+        line["storage"]["error_reference"] = (f"FP64 oracle, 64^3 sub-run (31 cells), 500 steps, "
+                                              f"max|u| = {umax:.3e}")
+    if not a.no_scale and a.workload == "precision":
+        line["scale"] = scale_leg(oif, a.scale_steps, 3, None if a.no_tune else a.tune_cache)
     if not a.no_batch:
         log("[bench] batching: 32 boxes, batched vs one after another")
         line["batching"] = batching(oif, 200, None if a.no_tune else a.tune_cache)
@@ -373,7 +487,7 @@ def main():
         line["obstacles"] = obstacles(oif, 40)
     if not a.no_cpu:
         log(f"[bench] cpu baseline: oracle, {a.cpu_steps} steps")
-        line["cpu_baseline"] = cpu_baseline(box, a.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(box, a.cpu_steps, sub)
     print(json.dumps(line), flush=True)
 
 
