@@ -373,6 +373,15 @@ int oif_read_populations(oif_ctx* ctx, double* out);
  * storage form of the context. */
 int oif_write_populations(oif_ctx* ctx, const double* in);
 
+/* The stored deviations n_i - w_i rho0 (same layout), in FP64, which holds
+ * every storage form exactly (FP16 values unscaled).  Full populations near
+ * w_i rho0 cannot carry the lowest bits of very small deviations (below about
+ * 2^-31 rho0), so checkpoints use this pair: writing back what was read
+ * restores the lattice state bit for bit in every precision form.  Written
+ * values are rounded to the storage form. */
+int oif_read_deviations(oif_ctx* ctx, double* out);
+int oif_write_deviations(oif_ctx* ctx, const double* in);
+
 /* Density rho [nz][ny][nx]. */
 int oif_read_density(oif_ctx* ctx, double* out);
 

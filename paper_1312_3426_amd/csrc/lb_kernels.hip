@@ -497,19 +497,23 @@ __global__ void diag_final_kernel(const double* __restrict__ part, int nlat, int
 
 __device__ inline double weight_of(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
+// full populations n_i = w_i rho0 + d_i (dev = 0), or the stored deviations
+// d_i alone (dev = 1), which FP64 holds exactly in every storage form
 template <int P>
-__global__ void pops_to_f64_kernel(const BoxDev* __restrict__ B, int parity, double* __restrict__ out) {
+__global__ void pops_to_f64_kernel(const BoxDev* __restrict__ B, int parity, double* __restrict__ out, int dev) {
     typedef typename Prec<P>::S S;
     const int N = B->N;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (size_t)19 * N) return;
     const int i = (int)(k / N), p = (int)(k - (size_t)i * N);
     const S* src = (const S*)B->f[parity];
-    out[k] = weight_of(i) * B->rho0 + (double)dec<P>(pop_load(src, i, p), B->st_inv);
+    const double d = (double)dec<P>(pop_load(src, i, p), B->st_inv);
+    out[k] = dev ? d : weight_of(i) * B->rho0 + d;
 }
 
 template <int P>
-__global__ void f64_to_pops_kernel(const BoxDev* __restrict__ B, int parity, const double* __restrict__ in) {
+__global__ void f64_to_pops_kernel(const BoxDev* __restrict__ B, int parity, const double* __restrict__ in,
+                                   int dev) {
     typedef typename Prec<P>::S S;
     typedef typename Prec<P>::R R;
     const int N = B->N;
@@ -517,7 +521,7 @@ __global__ void f64_to_pops_kernel(const BoxDev* __restrict__ B, int parity, con
     if (k >= (size_t)19 * N) return;
     const int i = (int)(k / N), p = (int)(k - (size_t)i * N);
     S* dst = (S*)B->f[parity];
-    pop_store(dst, i, p, enc<P>((R)(in[k] - weight_of(i) * B->rho0), B->st_scale));
+    pop_store(dst, i, p, enc<P>((R)(dev ? in[k] : in[k] - weight_of(i) * B->rho0), B->st_scale));
 }
 
 template <int P>
@@ -629,18 +633,18 @@ hipError_t launch_diag_final(const double* partials, int nlat, int nmesh, double
 }
 
 hipError_t launch_pops_to_f64(const BoxDev* box_dev, int N, int precision, int parity, double* out,
-                              hipStream_t s) {
+                              int deviations, hipStream_t s) {
     const size_t n = (size_t)19 * N;
     OIF_DISPATCH_P(precision, pops_to_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), s, box_dev,
-                   parity, out);
+                   parity, out, deviations);
     return hipGetLastError();
 }
 
 hipError_t launch_f64_to_pops(const BoxDev* box_dev, int N, int precision, int parity,
-                              const double* in, hipStream_t s) {
+                              const double* in, int deviations, hipStream_t s) {
     const size_t n = (size_t)19 * N;
     OIF_DISPATCH_P(precision, f64_to_pops_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), s, box_dev,
-                   parity, in);
+                   parity, in, deviations);
     return hipGetLastError();
 }
 

@@ -267,11 +267,13 @@ hipError_t launch_diag_final(const double* partials, int nlat, int nmesh, double
 // plain device-to-device copy kernel of `bytes` (a multiple of 16)
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
-// conversions between the storage form and canonical FP64 arrays
+// conversions between the storage form and canonical FP64 arrays: full
+// populations, or (deviations = 1) the deviations n_i - w_i rho0 exactly as
+// stored
 hipError_t launch_pops_to_f64(const BoxDev* box_dev, int N, int precision, int parity, double* out,
-                              hipStream_t s);
+                              int deviations, hipStream_t s);
 hipError_t launch_f64_to_pops(const BoxDev* box_dev, int N, int precision, int parity,
-                              const double* in, hipStream_t s);
+                              const double* in, int deviations, hipStream_t s);
 hipError_t launch_moments(const BoxDev* box_dev, int N, int precision, int parity, double* rho,
                           double* u, hipStream_t s);
 

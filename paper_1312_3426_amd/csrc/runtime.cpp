@@ -1537,12 +1537,14 @@ int oif_set_lb_loads(oif_ctx* c, int nontemporal) {
     return OIF_OK;
 }
 
-int oif_read_populations(oif_ctx* c, double* out) {
+namespace {
+
+int read_pops(oif_ctx* c, double* out, int deviations) {
     if (!c || !out) return OIF_E_ARG;
     double* tmp = nullptr;
     const size_t n = 19 * (size_t)c->N;
     HIPCALL(c, hipMalloc(&tmp, n * 8));
-    hipError_t e = launch_pops_to_f64(c->box_dev, c->N, c->d.precision, c->parity, tmp, c->stream);
+    hipError_t e = launch_pops_to_f64(c->box_dev, c->N, c->d.precision, c->parity, tmp, deviations, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, n * 8, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(tmp);
@@ -1550,20 +1552,29 @@ int oif_read_populations(oif_ctx* c, double* out) {
     return OIF_OK;
 }
 
-int oif_write_populations(oif_ctx* c, const double* in) {
+int write_pops(oif_ctx* c, const double* in, int deviations) {
     if (!c || !in) return OIF_E_ARG;
     double* tmp = nullptr;
     const size_t n = 19 * (size_t)c->N;
     HIPCALL(c, hipMalloc(&tmp, n * 8));
     hipError_t e = hipMemcpyAsync(tmp, in, n * 8, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = launch_f64_to_pops(c->box_dev, c->N, c->d.precision, c->parity, tmp, c->stream);
+    if (e == hipSuccess)
+        e = launch_f64_to_pops(c->box_dev, c->N, c->d.precision, c->parity, tmp, deviations, c->stream);
     // both buffers: nothing streams into a solid node, which keeps its values
-    if (e == hipSuccess) e = launch_f64_to_pops(c->box_dev, c->N, c->d.precision, c->parity ^ 1, tmp, c->stream);
+    if (e == hipSuccess)
+        e = launch_f64_to_pops(c->box_dev, c->N, c->d.precision, c->parity ^ 1, tmp, deviations, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(tmp);
     HIPCALL(c, e);
     return OIF_OK;
 }
+
+}  // namespace
+
+int oif_read_populations(oif_ctx* c, double* out) { return read_pops(c, out, 0); }
+int oif_write_populations(oif_ctx* c, const double* in) { return write_pops(c, in, 0); }
+int oif_read_deviations(oif_ctx* c, double* out) { return read_pops(c, out, 1); }
+int oif_write_deviations(oif_ctx* c, const double* in) { return write_pops(c, in, 1); }
 
 static int read_moments(oif_ctx* c, double* rho, double* u) {
     double* tmp = nullptr;

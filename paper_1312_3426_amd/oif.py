@@ -103,6 +103,8 @@ SIGNATURES = {
     "oif_autotune": (_i, [_vp, C.c_char_p]),
     "oif_read_populations": (_i, [_vp, _vp]),
     "oif_write_populations": (_i, [_vp, _vp]),
+    "oif_read_deviations": (_i, [_vp, _vp]),
+    "oif_write_deviations": (_i, [_vp, _vp]),
     "oif_read_density": (_i, [_vp, _vp]),
     "oif_read_velocity": (_i, [_vp, _vp]),
     "oif_read_mesh": (_i, [_vp, _i, _vp, _vp]),
@@ -315,6 +317,18 @@ class Context:
         n = _f64(n)
         assert n.size == 19 * self.N
         self._chk(lib().oif_write_populations(self.h, _p(n)))
+
+    def read_deviations(self) -> np.ndarray:
+        """The stored deviations n_i - w_i rho0, exact in every storage form
+        (the checkpoint form of the lattice state)."""
+        out = np.empty((19,) + self.shape)
+        self._chk(lib().oif_read_deviations(self.h, _p(out)))
+        return out
+
+    def write_deviations(self, d) -> None:
+        d = _f64(d)
+        assert d.size == 19 * self.N
+        self._chk(lib().oif_write_deviations(self.h, _p(d)))
 
     def read_density(self) -> np.ndarray:
         out = np.empty(self.shape)

@@ -207,18 +207,18 @@ def test_verlet_coupled_sphere_vs_oracle(oif, orc, prec, mrt):
 
 
 def test_verlet_checkpoint_graph_and_batch_bitwise(oif):
-    """Verlet state = populations + positions + velocities + carried force:
-    restoring all four continues bit for bit; graph replay and a batch that
+    """Verlet state = populations (as stored deviations) + positions +
+    velocities + carried force: restoring all four continues bit for bit; graph replay and a batch that
     mixes Verlet and Euler boxes equal eager single-box stepping."""
     say("[verlet] checkpoint / graph / batch, fp32 channel")
     box = synth.config_channel_rbc(20)
     box.integrator = "verlet"
     a = oif.Context.from_box(box, precision="fp32")
     a.step(5)
-    n, (X, V), F = a.read_populations(), a.read_mesh(-1), a.read_force(-1)
+    n, (X, V), F = a.read_deviations(), a.read_mesh(-1), a.read_force(-1)
     assert np.abs(F).max() > 0
     b = oif.Context.from_box(box, precision="fp32")
-    b.write_populations(n)
+    b.write_deviations(n)
     b.write_mesh(-1, X, V)
     b.write_force(-1, F)
     a.step(7)
