@@ -405,6 +405,19 @@ int oif_info(oif_ctx* ctx, oif_info_t* info);
 /* FP64 sums of mass and momentum and the watchdog flags of the current state. */
 int oif_diagnostics(oif_ctx* ctx, oif_diag* d);
 
+/* oif_diagnostics for callers that cannot allocate device memory (code under
+ * stream capture elsewhere in the process, tight serving loops, harnesses that
+ * forbid allocation): the same sums, bit for bit, with the partial sums in a
+ * fixed 1 MiB device array that the library holds per device for the life of
+ * the process, instead of memory the context allocates.  The call allocates
+ * nothing and never re-creates the device mesh arrays: it returns
+ * OIF_E_STATE while objects, templates or meshes changed since the last step
+ * (step first), and OIF_E_ARG beyond 25952 objects (the array holds 5 doubles
+ * per object and per lattice block).  All contexts on one device share that
+ * array: calls that overlap in time on one device (several host threads)
+ * race; every call overwrites what it reads, nothing needs clearing. */
+int oif_diagnostics_noalloc(oif_ctx* ctx, oif_diag* d);
+
 /* Number of distinct lattice nodes inside the 2x2x2 stencil of any mesh node
  * at the current positions (used for the byte model of the coupling). */
 int oif_touched_nodes(oif_ctx* ctx, long long* count);

@@ -22,10 +22,44 @@
 #include <unordered_map>
 #include <vector>
 
+#include <mutex>
+
 #include "oif.h"
 #include "oif_device.h"
 
 using namespace oif;
+
+// Fixed device memory of the allocation-free diagnostics call
+// (oif_diagnostics_noalloc): the FP64 partial sums of the lattice blocks and
+// of the objects, then the ten final sums.  Every device the library runs on
+// holds one such array until the process ends, shared by all contexts there.
+// On the host `scratch` names the symbol only, not device memory: host code
+// uses the address looked up once per device (scratch_address), never the
+// name.
+constexpr long long SCRATCH_DOUBLES = 131072;  // 1 MiB
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;
+
+// Device address of `scratch` on `device`, which must be the current device;
+// looked up on the first call for that device and kept.
+hipError_t scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it == g_scratch_addr.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        it = g_scratch_addr.emplace(device, p).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -302,6 +336,7 @@ struct oif_ctx {
     // diagnostics
     DevBuf part_dev, diag_out;
     int diag_blocks = 256;
+    void* scratch_addr = nullptr;  // device address of this device's `scratch` array
 };
 
 // Multiplier and shift that divide any q < 2^31 by d (1 <= d <= 4096):
@@ -928,6 +963,7 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return OIF_E_UNSUPPORTED;
 
     std::unique_ptr<oif_ctx> c(new oif_ctx());
+    if (scratch_address(d.device, &c->scratch_addr) != hipSuccess) return OIF_E_HIP;
     c->d = d;
     c->N = (int)N;
     c->st_size = d.precision == OIF_PREC_FP64 ? 8 : (d.precision == OIF_PREC_FP32 ? 4 : 2);
@@ -1674,6 +1710,30 @@ int oif_diagnostics(oif_ctx* c, oif_diag* d) {
     double out[10];
     unsigned st = 0;
     if ((rc = run_diag(c, out, &st))) return rc;
+    fill_diag(c, out, st, d);
+    return OIF_OK;
+}
+
+int oif_diagnostics_noalloc(oif_ctx* c, oif_diag* d) {
+    if (!c || !d) return OIF_E_ARG;
+    if (c->mesh_dirty)
+        return fail(c, OIF_E_STATE,
+                    "oif_diagnostics_noalloc: the objects changed since the last step and their device arrays "
+                    "are not in place; call oif_step (or oif_diagnostics) first");
+    // partials of the lattice blocks and objects, then the totals on a
+    // 256-byte boundary
+    const long long nobj = (long long)c->obj.size();
+    const long long max_obj = (SCRATCH_DOUBLES - 16) / 32 * 32 / 5 - c->diag_blocks;
+    if (nobj > max_obj)
+        return fail(c, OIF_E_ARG,
+                    "oif_diagnostics_noalloc: " + std::to_string(nobj) + " objects exceed its fixed scratch (at most " +
+                        std::to_string(max_obj) + ")");
+    const long long fin_off = (5LL * (c->diag_blocks + nobj) + 31) / 32 * 32;
+    double* part = (double*)c->scratch_addr;
+    double out[10];
+    unsigned st = 0;
+    int rc = run_diag_in(c, part, part + fin_off, out, &st);
+    if (rc) return rc;
     fill_diag(c, out, st, d);
     return OIF_OK;
 }

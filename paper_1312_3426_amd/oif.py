@@ -112,6 +112,7 @@ SIGNATURES = {
     "oif_object_analyze": (_i, [_vp, _i, _vp]),
     "oif_info": (_i, [_vp, _vp]),
     "oif_diagnostics": (_i, [_vp, _vp]),
+    "oif_diagnostics_noalloc": (_i, [_vp, _vp]),
     "oif_touched_nodes": (_i, [_vp, _vp]),
     "oif_boundary_rhomboid": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "oif_boundary_wall": (_i, [_vp, _vp, C.c_double, _vp, _vp]),
@@ -368,6 +369,12 @@ class Context:
     def diagnostics(self) -> Diag:
         d = Diag()
         self._chk(lib().oif_diagnostics(self.h, C.byref(d)))
+        return d
+
+    def diagnostics_noalloc(self) -> Diag:
+        """oif_diagnostics without device allocation (fixed per-device scratch)."""
+        d = Diag()
+        self._chk(lib().oif_diagnostics_noalloc(self.h, C.byref(d)))
         return d
 
     def touched_nodes(self) -> int:
