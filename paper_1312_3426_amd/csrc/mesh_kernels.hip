@@ -123,6 +123,19 @@ __device__ __forceinline__ int wrap_mod(int a, int n) {
     return r < 0 ? r + n : r;
 }
 
+// Lower corner of the 2x2x2 stencil of a mesh node at (px, py, pz): nodes sit
+// at cell centres, so the stencil starts at floor(x - 1/2) per axis (plus the
+// object's integer anchor).  False for a non-finite or runaway position,
+// which gets no stencil.
+__device__ __forceinline__ bool stencil_corner(double px, double py, double pz, const int* anchor, int (&b)[3]) {
+    const double sx = px - 0.5, sy = py - 0.5, sz = pz - 0.5;
+    if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) return false;
+    b[0] = anchor[0] + (int)floor(sx);
+    b[1] = anchor[1] + (int)floor(sy);
+    b[2] = anchor[2] + (int)floor(sz);
+    return true;
+}
+
 // Stencil marking of one object for split stepping: every lattice node inside
 // the 2x2x2 stencil of a finite node position gets its bit in `touch`.  The
 // object's stencil box is marked in the bitmask `bits` ((ucap + 31)/32 words)
@@ -212,14 +225,14 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     const int cons = CONS ? T->conservative : 0;
     const MeshLayout lay = mesh_layout(sizeof(R), nv, nt, ne, ucap, ccap, cons);
     unsigned char* base = USE_LDS ? smem : O.scratch;
-    double* xs = (double*)base;       // [nv][3]
     R* fs = (R*)(base + lay.fs);      // [nv][3]: elastic force
-    int* sb = (int*)(base + lay.sb);  // [nv][3]: lower stencil corner
+    double* xs = (double*)(base + lay.xs);  // [nv][3]: positions (forces phase)
     R* tn = (R*)(base + lay.tn);      // [nt][4]: unit inward normal, area
     R* tr = (R*)(base + lay.tr);      // [nt]: (S - S0)/S
     R* se = (R*)(base + lay.se);      // [ne]: ks kappa strain / L
     R* fh = (R*)(base + lay.fh);      // [ne]: kb (theta - theta0)/theta0
-    // coupling area: after the mesh arrays, or alone in LDS (CPL)
+    // coupling area: over the positions and the forces-phase arrays, or alone
+    // in LDS (CPL)
     auto carea = [&](size_t off) -> unsigned char* {
         return (!USE_LDS && CPL) ? smem + (off - lay.need) : base + off;
     };
@@ -227,14 +240,16 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     __shared__ int bbox[6];
     __shared__ int ncomp;
 
-    // half-step velocity of velocity Verlet, V + F_last/(2m), one rounding
+    // Position of node k (component-wise index) the forces and the drag are
+    // taken at: X, or with velocity Verlet X + (V + F_last/(2m)), the
+    // half-step velocity rounded once.  Staged in LDS for the forces phase and
+    // formed again from HBM by the coupling phase (the same expression, so the
+    // same bits).
     const R half_im = R(0.5) * O.inv_mass;
-    if (O.F) {
-        for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x)
-            xs[k] = gld(O.X + k) + (double)fmadd(gld(O.F + k), half_im, gld(O.V + k));
-    } else {
-        for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x) xs[k] = gld(O.X + k);
-    }
+    auto stage = [&](int k) -> double {
+        return O.F ? gld(O.X + k) + (double)fmadd(gld(O.F + k), half_im, gld(O.V + k)) : gld(O.X + k);
+    };
+    for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x) xs[k] = stage(k);
     if (threadIdx.x == 0) {
         bbox[0] = bbox[1] = bbox[2] = INT_MAX;
         bbox[3] = bbox[4] = bbox[5] = INT_MIN;
@@ -428,19 +443,12 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
         fs[3 * v + 2] = Fz;
         // lower corner of the node's 2x2x2 stencil (unwrapped lattice index);
         // nodes sit at cell centres, so the stencil starts at floor(x - 1/2)
-        const double sx = px - 0.5, sy = py - 0.5, sz = pz - 0.5;
-        if (fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7) {
-            const int bx = O.anchor[0] + (int)floor(sx);
-            const int by = O.anchor[1] + (int)floor(sy);
-            const int bz = O.anchor[2] + (int)floor(sz);
-            sb[3 * v] = bx;
-            sb[3 * v + 1] = by;
-            sb[3 * v + 2] = bz;
-            blo[0] = min(blo[0], bx); blo[1] = min(blo[1], by); blo[2] = min(blo[2], bz);
-            bhi[0] = max(bhi[0], bx); bhi[1] = max(bhi[1], by); bhi[2] = max(bhi[2], bz);
+        int b[3];
+        if (stencil_corner(px, py, pz, O.anchor, b)) {
+            blo[0] = min(blo[0], b[0]); blo[1] = min(blo[1], b[1]); blo[2] = min(blo[2], b[2]);
+            bhi[0] = max(bhi[0], b[0]); bhi[1] = max(bhi[1], b[1]); bhi[2] = max(bhi[2], b[2]);
         } else {
-            sb[3 * v] = INT_MIN;  // no stencil for a non-finite or runaway node
-            flags |= ST_NONFINITE;
+            flags |= ST_NONFINITE;  // no stencil for a non-finite or runaway node
         }
     }
     wave_bbox_to_block(blo, bhi, bbox);
@@ -469,8 +477,9 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
         for (int k = threadIdx.x; k < nw; k += blockDim.x) need[k] = 0u;
         __syncthreads();
         for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-            if (sb[3 * v] == INT_MIN) continue;
-            const int b0 = (sb[3 * v + 2] - oz) * exy + (sb[3 * v + 1] - oy) * ex + (sb[3 * v] - ox);
+            int b[3];
+            if (!stencil_corner(stage(3 * v), stage(3 * v + 1), stage(3 * v + 2), O.anchor, b)) continue;
+            const int b0 = (b[2] - oz) * exy + (b[1] - oy) * ex + (b[0] - ox);
             // corners in a lane-rotated order: lanes whose nodes share a cell
             // then hit different words in the same instruction
 #pragma unroll
@@ -559,7 +568,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
 
     // per mesh node: interpolate, drag, integrate, spread
     for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-        const double px = xs[3 * v], py = xs[3 * v + 1], pz = xs[3 * v + 2];
+        const double px = stage(3 * v), py = stage(3 * v + 1), pz = stage(3 * v + 2);
         R vx = gld(O.V + 3 * v), vy = gld(O.V + 3 * v + 1), vz = gld(O.V + 3 * v + 2);
         if (O.F) {  // the half-step velocity, as staged
             vx = fmadd(gld(O.F + 3 * v), half_im, vx);
@@ -567,7 +576,8 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
             vz = fmadd(gld(O.F + 3 * v + 2), half_im, vz);
         }
         R dgx = 0, dgy = 0, dgz = 0;
-        if (sb[3 * v] != INT_MIN) {
+        int sb[3];
+        if (stencil_corner(px, py, pz, O.anchor, sb)) {
             const double sx = px - 0.5, sy = py - 0.5, sz = pz - 0.5;
             const R phx = (R)(sx - floor(sx)), phy = (R)(sy - floor(sy)), phz = (R)(sz - floor(sz));
             if (compact) {
@@ -576,7 +586,7 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                 // different LDS accumulators in the same instruction; the
                 // integer sums do not depend on the order
                 const int rot = v & 7;
-                const int b0 = (sb[3 * v + 2] - oz) * exy + (sb[3 * v + 1] - oy) * ex + (sb[3 * v] - ox);
+                const int b0 = (sb[2] - oz) * exy + (sb[1] - oy) * ex + (sb[0] - ox);
                 int cr[8];
                 R wr[8];
                 R ujx = 0, ujy = 0, ujz = 0;
@@ -604,14 +614,14 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
                 }
             } else {
                 // stencil box too large for LDS: per-corner loads and atomics
-                int ix = sb[3 * v] % nxb;
+                int ix = sb[0] % nxb;
                 ix += ix < 0 ? nxb : 0;
-                int iy = sb[3 * v + 1] % nyb;
+                int iy = sb[1] % nyb;
                 iy += iy < 0 ? nyb : 0;
                 const int ix1 = ix + 1 == nxb ? 0 : ix + 1;
                 const int iy1 = iy + 1 == nyb ? 0 : iy + 1;
                 int iz0, iz1;
-                const int izr = sb[3 * v + 2];
+                const int izr = sb[2];
                 if (B->walls_z) {
                     iz0 = izr < 0 ? 0 : (izr >= nzb ? nzb - 1 : izr);
                     iz1 = izr + 1 < 0 ? 0 : (izr + 1 >= nzb ? nzb - 1 : izr + 1);
@@ -698,9 +708,6 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
         gst(O.X + 3 * v, qx);
         gst(O.X + 3 * v + 1, qy);
         gst(O.X + 3 * v + 2, qz);
-        xs[3 * v] = qx;  // only this node's own entry is read in this loop
-        xs[3 * v + 1] = qy;
-        xs[3 * v + 2] = qz;
     }
     if (compact) {
         // one global atomic per touched lattice node and component
@@ -719,8 +726,8 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
         }
     }
     // split stepping: the stencils of the new positions, for the next step
-    if (mark_next)
-        mark_object(xs, nv, O.anchor, B, ucap, need, bbox, B->touch[parity ^ 1]);
+    if (mark_next)  // (mark_object begins with a barrier: every new position is written)
+        mark_object(O.X, nv, O.anchor, B, ucap, need, bbox, B->touch[parity ^ 1]);
     if (flags) gatomic_or(B->status, flags);
 }
 

@@ -95,11 +95,10 @@ struct TmplDev {
 
 // Per-object LDS (or global scratch) layout of the membrane kernel, R = the
 // arithmetic type:
-//   xs  node positions, FP64 [nv][3]
 //   fs  elastic force per node, R [nv][3]
-//   sb  lower stencil corner per node (unwrapped lattice index), int [nv][3]
 //   then a region used twice:
-//     forces phase:  tn  unit inward normal + area per triangle, R [nt][4]
+//     forces phase:  xs  node positions, FP64 [nv][3]
+//                    tn  unit inward normal + area per triangle, R [nt][4]
 //                    tr  (S - S0)/S per triangle, R [nt]
 //                    se  stretching coefficient per edge, R [ne]
 //                    fh  bending coefficients per edge: R [ne] (the paper's
@@ -110,21 +109,23 @@ struct TmplDev {
 //                     ug    fluid velocity at the touched nodes, R [ccap][3]
 //                     qn    their lattice indices, int [ccap]
 //                     gacc  summed reaction force, 8-byte accumulators [ccap][3]
+// (the coupling phase reads the node positions from HBM again, so the
+// positions need not outlive the forces phase)
 struct MeshLayout {
-    size_t fs, sb, tn, tr, se, fh, need, nwords, ug, qn, gacc, total;
+    size_t fs, xs, tn, tr, se, fh, need, nwords, ug, qn, gacc, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 __host__ __device__ inline MeshLayout mesh_layout(size_t r, int nv, int nt, int ne, int ucap, int ccap,
                                                    int cons) {
     MeshLayout L;
-    L.fs = align16((size_t)nv * 3 * sizeof(double));
-    L.sb = align16(L.fs + (size_t)nv * 3 * r);
-    L.tn = align16(L.sb + (size_t)nv * 3 * sizeof(int));
+    L.fs = 0;
+    L.xs = align16((size_t)nv * 3 * r);
+    L.tn = align16(L.xs + (size_t)nv * 3 * sizeof(double));
     L.tr = L.tn + (size_t)nt * 4 * r;
     L.se = align16(L.tr + (size_t)nt * r);
     L.fh = align16(L.se + (size_t)ne * r);
     const size_t end_forces = L.fh + (size_t)ne * r * (cons ? 4 : 1);
-    L.need = L.tn;
+    L.need = L.xs;
     L.nwords = ((size_t)ucap + 31) / 32;
     L.ug = align16(L.need + 2 * L.nwords * 4);
     L.qn = L.ug + (size_t)ccap * 3 * r;

@@ -219,8 +219,49 @@ int build_template(const double* nodes, int nv, const int32_t* tris, int nt, con
         }
         const double side = std::ceil(2.0 * rb) + 4.0;
         T.ucap = side * side * side < 1e6 ? (int)(side * side * side) : 1000000;
-        // touched nodes: a shell about two nodes thick around the surface
-        T.ccap = std::min(T.ucap, (int)std::ceil(4.0 * T.Sg0) + 128);
+        // Touched lattice nodes an object may have in LDS: the most any of 64
+        // rigid placements of the template (rotations and sub-cell shifts
+        // from a fixed sequence) touches, with a quarter more and 64 nodes
+        // for deformation.  An object that touches more takes the slower
+        // per-corner path of the membrane kernel (same results).
+        const int sd = (int)side + 2;
+        std::vector<unsigned char> mark((size_t)sd * sd * sd);
+        int most = 0;
+        unsigned long long st = 0x9e3779b97f4a7c15ull;
+        auto unif = [&]() {  // xorshift64*: uniform in [0, 1)
+            st ^= st >> 12; st ^= st << 25; st ^= st >> 27;
+            return (double)((st * 0x2545f4914f6cdd1dull) >> 11) * (1.0 / 9007199254740992.0);
+        };
+        for (int trial = 0; trial < 64; ++trial) {
+            // uniform random rotation from a unit quaternion
+            const double u1 = unif(), u2 = 2 * M_PI * unif(), u3 = 2 * M_PI * unif();
+            const double qa = std::sqrt(1 - u1) * std::sin(u2), qb = std::sqrt(1 - u1) * std::cos(u2),
+                         qc = std::sqrt(u1) * std::sin(u3), qd = std::sqrt(u1) * std::cos(u3);
+            const double R[9] = {1 - 2 * (qc * qc + qd * qd), 2 * (qb * qc - qa * qd), 2 * (qb * qd + qa * qc),
+                                 2 * (qb * qc + qa * qd), 1 - 2 * (qb * qb + qd * qd), 2 * (qc * qd - qa * qb),
+                                 2 * (qb * qd - qa * qc), 2 * (qc * qd + qa * qb), 1 - 2 * (qb * qb + qc * qc)};
+            const double off[3] = {unif(), unif(), unif()};
+            std::fill(mark.begin(), mark.end(), 0);
+            int cnt = 0;
+            for (int v = 0; v < nv; ++v) {
+                double d[3];
+                vsub(&T.x[3 * v], c, d);
+                int lo[3];
+                for (int a = 0; a < 3; ++a) {
+                    const double y = R[3 * a] * d[0] + R[3 * a + 1] * d[1] + R[3 * a + 2] * d[2];
+                    lo[a] = (int)std::floor(y + off[a] + 0.5 * side - 0.5);  // >= 0 by construction
+                }
+                for (int k = 0; k < 8; ++k) {
+                    const size_t q = ((size_t)(lo[2] + (k >> 2)) * sd + lo[1] + ((k >> 1) & 1)) * sd + lo[0] + (k & 1);
+                    if (q < mark.size() && !mark[q]) {
+                        mark[q] = 1;
+                        ++cnt;
+                    }
+                }
+            }
+            most = std::max(most, cnt);
+        }
+        T.ccap = std::min(T.ucap, most + most / 4 + 64);
     }
     // per-node incidence lists (CSR)
     std::vector<std::vector<std::array<int, 2>>> ei(nv);
