@@ -25,7 +25,8 @@ JSON line:
   batching       32 uneven boxes (1.05-4.7 M nodes in all, 1-20 cells each of
                  162/642/2562 nodes): one launch per kernel over all boxes,
                  eager and as a captured graph, against a loop that steps the
-                 boxes one after another
+                 boxes one after another; and the persistent form (one launch
+                 per step over a device task list), eager and as a graph
   roofline.traffic  HBM bytes per lattice-kernel launch from the rocprofv3
                  FETCH_SIZE / WRITE_SIZE record in profiles/, reported only while
                  the lattice kernel's sources hash to the recorded value
@@ -54,7 +55,8 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 BYTES_POP = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
-LB_SOURCES = ("paper_1312_3426_amd/csrc/lb_kernels.hip", "paper_1312_3426_amd/csrc/device_common.h",
+LB_SOURCES = ("paper_1312_3426_amd/csrc/lb_kernels.hip", "paper_1312_3426_amd/csrc/lb_device.h",
+              "paper_1312_3426_amd/csrc/device_common.h",
               "paper_1312_3426_amd/csrc/oif_device.h")
 TRAFFIC_RECORD = "profiles/lb_kernel_fp32_sphere642x500_256x128x128.md"
 
@@ -206,6 +208,16 @@ def batching(oif, steps, tune):
     t0 = time.perf_counter()
     b.step(steps)
     graph_ms = (time.perf_counter() - t0) * 1e3
+    # the persistent form: one launch per step over a device task list
+    b.set_graph(0)
+    b.set_persistent(True)
+    b.step(2)
+    pers_ms = b.step_timed(steps).total_ms
+    b.set_graph(50)
+    b.step(100)
+    t0 = time.perf_counter()
+    b.step(steps)
+    pers_graph_ms = (time.perf_counter() - t0) * 1e3
     b.close()
     for c in ctxs:
         c.close()
@@ -214,6 +226,9 @@ def batching(oif, steps, tune):
             "steps": steps, "loop_mlups": ml(loop_ms), "batched_mlups": ml(eager_ms),
             "batched_graph_mlups": ml(graph_ms), "speedup_batched": round(loop_ms / eager_ms, 3),
             "speedup_batched_graph": round(loop_ms / graph_ms, 3),
+            "persistent_mlups": ml(pers_ms), "persistent_graph_mlups": ml(pers_graph_ms),
+            "persistent_vs_launch_pairs": round(eager_ms / pers_ms, 3),
+            "persistent_vs_launch_pairs_graph": round(graph_ms / pers_graph_ms, 3),
             "friction": boxes[0].friction,
             "moduli_2562": "the 2562-node template takes the default moduli x 0.25 (stiffer mesh, same dt)",
             "timing": "loop and batched: HIP events around the launches; graph: wall clock incl. "

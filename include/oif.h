@@ -447,6 +447,19 @@ int oif_batch_step(oif_batch* b, int n_steps);
 int oif_batch_set_graph(oif_batch* b, int steps_per_graph);
 int oif_batch_set_launch(oif_batch* b, int lb_block, int mesh_block, int xcd_remap);
 int oif_batch_set_lb_loads(oif_batch* b, int nontemporal);
+
+/* Persistent form (on = 1; default 0): every step is one launch of a kernel
+ * whose workgroups, as many as fit on the device at once, take tasks from a
+ * device list until it is done: the membrane, coupling and update of each
+ * object (largest meshes first), then the lattice update of each block of
+ * nodes of each box; a box's lattice blocks wait only for that box's
+ * membranes, so the lattice update of boxes whose cells are done overlaps the
+ * membranes of the others.  Same results as the launch-per-phase form (bit
+ * for bit below FP64).  Boxes with obstacles or the MRT collision are not
+ * supported in this form: stepping then returns OIF_E_UNSUPPORTED.  The launch
+ * shapes are those of the membrane kernel (oif_batch_set_launch's mesh_block
+ * is the workgroup size of both task kinds). */
+int oif_batch_set_persistent(oif_batch* b, int on);
 int oif_batch_autotune(oif_batch* b, const char* cache_path);
 int oif_batch_step_timed(oif_batch* b, int n_steps, oif_timing* t);
 const char* oif_batch_last_error(const oif_batch* b);

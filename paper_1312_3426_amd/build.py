@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liboif.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("lb_kernels.hip", "mesh_kernels.hip", "repulsion_kernels.hip",
+SOURCES = [os.path.join(CSRC, f) for f in ("lb_kernels.hip", "mesh_kernels.hip", "repulsion_kernels.hip", "batch_kernels.hip",
                                            "runtime.cpp")]
 
 HIPCC_FLAGS = [

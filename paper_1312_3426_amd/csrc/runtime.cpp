@@ -24,6 +24,7 @@
 
 #include <mutex>
 
+#include "batch_sched.h"
 #include "oif.h"
 #include "oif_device.h"
 
@@ -417,6 +418,12 @@ struct oif_batch {
     hipGraphExec_t gexec = nullptr;
     int g_len = 0;
     bool built = false;
+    // persistent form: one launch per step over a device task list
+    int persistent = 0;
+    BatchSched sched{};
+    DevBuf sched_dev, p_objs, p_group, p_objbox, p_lbwork, p_boxnmesh, p_ctr;
+    int p_grid = 0;
+    size_t p_lds = 0;
 };
 
 namespace {
@@ -2053,9 +2060,10 @@ int batch_build(oif_batch* b) {
     BHIP(b, hipMemcpy(b->work_dev.p, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice));
     // objects of all boxes: LDS-resident group first, each largest mesh first
     const size_t osz = objdev_size(b->precision);
-    struct Ent { const unsigned char* p; int group; int nv; size_t need, cpl; };
+    struct Ent { const unsigned char* p; int group; int nv; size_t need, cpl; int box; };
     std::vector<Ent> ents;
-    for (oif_ctx* c : b->ctx) {
+    for (size_t bi = 0; bi < b->ctx.size(); ++bi) {
+        oif_ctx* c = b->ctx[bi];
         const size_t n = c->obj.size();
         for (size_t k = 0; k < n; ++k) {
             const unsigned char* p = c->obj_host.data() + k * osz;
@@ -2069,7 +2077,8 @@ int batch_build(oif_batch* b) {
             ents.push_back({p, group, T.nv,
                             mesh_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T)),
                             mesh_cpl_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap,
-                                               tmpl_conservative(T))});
+                                               tmpl_conservative(T)),
+                            (int)bi});
         }
     }
     std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& c) {
@@ -2098,6 +2107,77 @@ int batch_build(oif_batch* b) {
     b->obj_dev.release();
     BHIP(b, hipMalloc(&b->obj_dev.p, host.size() + 16));
     if (!host.empty()) BHIP(b, hipMemcpy(b->obj_dev.p, host.data(), host.size(), hipMemcpyHostToDevice));
+    if (b->persistent) {
+        // Task list of the persistent form: membrane tasks largest mesh first
+        // (the longest chains start first), then the lattice blocks of the
+        // boxes in the order their membranes should finish (smallest largest
+        // mesh first, then fewest objects).
+        for (oif_ctx* c : b->ctx)
+            if (c->n_bnd > 0 || c->box.mrt)
+                return bfail(b, OIF_E_UNSUPPORTED,
+                             "the persistent batch form runs boxes without obstacles with the BGK collision only");
+        std::vector<int> mo(ents.size());
+        for (size_t k = 0; k < mo.size(); ++k) mo[k] = (int)k;
+        std::stable_sort(mo.begin(), mo.end(), [&](int a, int c) { return ents[a].nv > ents[c].nv; });
+        std::vector<unsigned char> pobj(ents.size() * osz), pgroup(ents.size() + 1, 0);
+        std::vector<int> pbox(ents.size() + 1, 0), bn(b->ctx.size(), 0), bmax(b->ctx.size(), 0);
+        for (size_t k = 0; k < mo.size(); ++k) {
+            const Ent& e = ents[mo[k]];
+            std::memcpy(pobj.data() + k * osz, e.p, osz);
+            pgroup[k] = (unsigned char)e.group;
+            pbox[k] = e.box;
+            ++bn[e.box];
+            bmax[e.box] = std::max(bmax[e.box], e.nv);
+        }
+        std::vector<int> bo(b->ctx.size());
+        for (size_t i = 0; i < bo.size(); ++i) bo[i] = (int)i;
+        std::stable_sort(bo.begin(), bo.end(), [&](int a, int c) {
+            return bmax[a] != bmax[c] ? bmax[a] < bmax[c] : bn[a] < bn[c];
+        });
+        const int block = b->mesh_block;
+        std::vector<int2> lbw;
+        for (int i : bo) {
+            const int nb = (b->ctx[i]->N + block - 1) / block;
+            for (int k = 0; k < nb; ++k) lbw.push_back(make_int2(i, k));
+        }
+        b->p_lds = std::max(b->n_lds_obj ? b->lds_need : 0, b->n_cpl_obj ? b->cpl_need : 0);
+        int per_cu = 0, dev = 0, ncu = 0;
+        BHIP(b, hipGetDevice(&dev));
+        BHIP(b, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        BHIP(b, batch_blocks_per_cu(b->precision, b->lb_nt, block, b->p_lds, &per_cu));
+        if (per_cu < 1) return bfail(b, OIF_E_UNSUPPORTED, "persistent batch: no workgroup fits a compute unit");
+        const int ntasks = (int)(ents.size() + lbw.size());
+        b->p_grid = std::max(1, std::min(per_cu * ncu, ntasks));
+        const size_t nctr = 2 * (3 + b->ctx.size());
+        for (DevBuf* d : {&b->sched_dev, &b->p_objs, &b->p_group, &b->p_objbox, &b->p_lbwork, &b->p_boxnmesh, &b->p_ctr})
+            d->release();
+        BHIP(b, hipMalloc(&b->p_objs.p, pobj.size() + 16));
+        BHIP(b, hipMalloc(&b->p_group.p, pgroup.size()));
+        BHIP(b, hipMalloc(&b->p_objbox.p, pbox.size() * sizeof(int)));
+        BHIP(b, hipMalloc(&b->p_lbwork.p, (lbw.size() + 1) * sizeof(int2)));
+        BHIP(b, hipMalloc(&b->p_boxnmesh.p, bn.size() * sizeof(int)));
+        BHIP(b, hipMalloc(&b->p_ctr.p, nctr * sizeof(unsigned)));
+        BHIP(b, hipMalloc(&b->sched_dev.p, sizeof(BatchSched)));
+        if (!pobj.empty()) BHIP(b, hipMemcpy(b->p_objs.p, pobj.data(), pobj.size(), hipMemcpyHostToDevice));
+        BHIP(b, hipMemcpy(b->p_group.p, pgroup.data(), pgroup.size(), hipMemcpyHostToDevice));
+        BHIP(b, hipMemcpy(b->p_objbox.p, pbox.data(), pbox.size() * sizeof(int), hipMemcpyHostToDevice));
+        if (!lbw.empty()) BHIP(b, hipMemcpy(b->p_lbwork.p, lbw.data(), lbw.size() * sizeof(int2), hipMemcpyHostToDevice));
+        BHIP(b, hipMemcpy(b->p_boxnmesh.p, bn.data(), bn.size() * sizeof(int), hipMemcpyHostToDevice));
+        BHIP(b, hipMemset(b->p_ctr.p, 0, nctr * sizeof(unsigned)));
+        BatchSched& S = b->sched;
+        S.ntasks = ntasks;
+        S.nmesh = (int)ents.size();
+        S.nbox = (int)b->ctx.size();
+        S.objs = b->p_objs.p;
+        S.group = (const unsigned char*)b->p_group.p;
+        S.obj_box = (const int*)b->p_objbox.p;
+        S.lbwork = (const int2*)b->p_lbwork.p;
+        S.boxes = (const BoxDev*)b->boxes_dev.p;
+        S.box_nmesh = (const int*)b->p_boxnmesh.p;
+        S.ctr = (unsigned*)b->p_ctr.p;
+        S.spin_limit = 1ull << 16;  // ~0.1 s of polling; a box's membranes take well under 1 ms
+        BHIP(b, hipMemcpy(b->sched_dev.p, &S, sizeof(BatchSched), hipMemcpyHostToDevice));
+    }
     b->built = true;
     return OIF_OK;
 }
@@ -2111,6 +2191,17 @@ int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<h
             if (c->rep_on)
                 BHIP(b, launch_repulsion(c->rep_h, (const RepDev*)c->rep_desc.p, c->obj_dev.p,
                                          (int)c->obj.size(), c->d.precision, s));
+        if (b->persistent) {  // the membranes and the lattice of every box in one launch
+            BatchLaunch bl{(const BatchSched*)b->sched_dev.p, b->p_grid, b->mesh_block, b->p_lds, par,
+                           b->precision, b->lb_nt, s};
+            BHIP(b, launch_batch(bl));
+            if (ev) {
+                (void)hipEventRecord((*ev)[3 * k + 1], s);
+                (void)hipEventRecord((*ev)[3 * k + 2], s);
+            }
+            par ^= 1;
+            continue;
+        }
         MeshLaunch ml{};
         ml.block = b->mesh_block;
         ml.parity = par;
@@ -2162,6 +2253,20 @@ int batch_prepare(oif_batch* b) {
 }
 
 int batch_finish(oif_batch* b, int n) {
+    if (b->persistent && b->p_ctr.p) {
+        // the wait-limit flags of both step parities
+        const size_t per = 3 + b->ctx.size();
+        unsigned f[2] = {0, 0};
+        hipStream_t s = b->ctx[0]->stream;
+        BHIP(b, hipMemcpyAsync(&f[0], (unsigned*)b->p_ctr.p + 2, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        BHIP(b, hipMemcpyAsync(&f[1], (unsigned*)b->p_ctr.p + per + 2, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        BHIP(b, hipStreamSynchronize(s));
+        if (f[0] | f[1]) {
+            BHIP(b, hipMemset(b->p_ctr.p, 0, 2 * per * sizeof(unsigned)));
+            return bfail(b, OIF_E_HIP, "persistent batch: a lattice task waited past its limit for the membranes "
+                                       "of its box; the step's results are not valid");
+        }
+    }
     for (oif_ctx* c : b->ctx) {
         c->parity ^= (n & 1);
         c->steps += n;
@@ -2203,6 +2308,8 @@ int oif_batch_destroy(oif_batch* b) {
     b->boxes_dev.release();
     b->work_dev.release();
     b->obj_dev.release();
+    for (DevBuf* d : {&b->sched_dev, &b->p_objs, &b->p_group, &b->p_objbox, &b->p_lbwork, &b->p_boxnmesh, &b->p_ctr})
+        d->release();
     delete b;
     return OIF_OK;
 }
@@ -2224,6 +2331,14 @@ int oif_batch_set_launch(oif_batch* b, int lb_block, int mesh_block, int xcd_rem
     if (lb_block >= 0) b->lb_block = lb_block;
     if (mesh_block >= 0) b->mesh_block = mesh_block;
     if (xcd_remap >= 0) b->remap = xcd_remap ? 1 : 0;
+    b->built = false;
+    bdrop_graph(b);
+    return OIF_OK;
+}
+
+int oif_batch_set_persistent(oif_batch* b, int on) {
+    if (!b || (on != 0 && on != 1)) return OIF_E_ARG;
+    b->persistent = on;
     b->built = false;
     bdrop_graph(b);
     return OIF_OK;

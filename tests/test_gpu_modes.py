@@ -419,3 +419,56 @@ def test_membrane_block_sizes_match_oracle(oif, orc, mb):
     c.close()
     say(f"   {fmt(res)}")
     assert all(v[3] for v in res.values()), fmt(res)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_persistent_batch_matches_launch_pairs(oif, prec):
+    """The persistent form of a batch (one launch per step, device task list,
+    per-box waits) gives the launch-per-phase results: bit for bit in FP32
+    (fixed-point spreading), to round-off in FP64 (FP64 atomics); eagerly, under
+    graph capture, and from either step parity.  The boxes mix 162-, 642- and
+    2562-node spheres, so membrane tasks of all three kinds (mesh in LDS, mesh
+    in the scratch with the coupling area in LDS) run."""
+    say(f"[modes] persistent batch vs launch pairs, {prec}")
+    boxes = synth.config_batch(n_boxes=6, steps=12)
+    ref, got = [], []
+    for persistent, out in ((False, ref), (True, got)):
+        ctxs = [oif.Context.from_box(bx, precision=prec) for bx in boxes]
+        ctxs[0].step(1)  # the batch then starts at odd parity in every box
+        for c in ctxs[1:]:
+            c.step(1)
+        B = oif.Batch(ctxs)
+        B.set_persistent(persistent)
+        B.step(3)
+        B.set_graph(4)
+        B.step(8)
+        for c in ctxs:
+            X, V = c.read_mesh(-1)
+            out.append((c.read_deviations(), X, V))
+        B.close()
+        for c in ctxs:
+            c.close()
+    for (d0, X0, V0), (d1, X1, V1) in zip(ref, got):
+        if prec == "fp32":
+            assert np.array_equal(d0, d1) and np.array_equal(X0, X1) and np.array_equal(V0, V1)
+        else:
+            assert np.abs(d0 - d1).max() <= 1e-15 and np.abs(X0 - X1).max() <= 1e-12
+            assert np.abs(V0 - V1).max() <= 1e-14
+
+
+def test_persistent_batch_refuses_obstacles_and_mrt(oif):
+    say("[modes] persistent batch: unsupported boxes")
+    for case in ("obstacles", "mrt"):
+        box = synth.config_obstacle_channel(4) if case == "obstacles" else synth.config_batch(n_boxes=1, steps=4)[0]
+        if case == "mrt":
+            box.mrt = (0.0, -0.5, 0.3, -0.3)
+        c = oif.Context.from_box(box, precision="fp32")
+        B = oif.Batch([c])
+        B.set_persistent(True)
+        with pytest.raises(oif.OifError) as e:
+            B.step(1)
+        assert e.value.code == oif.E_UNSUPPORTED
+        B.set_persistent(False)
+        B.step(1)
+        B.close()
+        c.close()
