@@ -208,11 +208,20 @@ def batching(oif, steps, tune):
     t0 = time.perf_counter()
     b.step(steps)
     graph_ms = (time.perf_counter() - t0) * 1e3
-    # the persistent form: one launch per step over a device task list
+    # the persistent form: one launch per step over a device task list, for
+    # several workgroup sizes and lattice task sizes (0: the library's default)
     b.set_graph(0)
-    b.set_persistent(True)
-    b.step(2)
-    pers_ms = b.step_timed(steps).total_ms
+    pers = {}
+    for mb in (512, 768, 1024):
+        for chunk in (0, 2, 8):
+            b.set_launch(-1, mb, -1)
+            b.set_persistent(True, chunk)
+            b.step(2)
+            pers[(mb, chunk)] = b.step_timed(steps).total_ms
+    best = min(pers, key=pers.get)
+    pers_ms = pers[best]
+    b.set_launch(-1, best[0], -1)
+    b.set_persistent(True, best[1])
     b.set_graph(50)
     b.step(100)
     t0 = time.perf_counter()
@@ -227,6 +236,8 @@ def batching(oif, steps, tune):
             "batched_graph_mlups": ml(graph_ms), "speedup_batched": round(loop_ms / eager_ms, 3),
             "speedup_batched_graph": round(loop_ms / graph_ms, 3),
             "persistent_mlups": ml(pers_ms), "persistent_graph_mlups": ml(pers_graph_ms),
+            "persistent_best": {"workgroup": best[0], "lattice_blocks_per_task": best[1]},
+            "persistent_mlups_by_workgroup_and_blocks_per_task": {f"{k[0]}/{k[1]}": ml(v) for k, v in pers.items()},
             "persistent_vs_launch_pairs": round(eager_ms / pers_ms, 3),
             "persistent_vs_launch_pairs_graph": round(graph_ms / pers_graph_ms, 3),
             "friction": boxes[0].friction,

@@ -458,8 +458,11 @@ int oif_batch_set_lb_loads(oif_batch* b, int nontemporal);
  * for bit below FP64).  Boxes with obstacles or the MRT collision are not
  * supported in this form: stepping then returns OIF_E_UNSUPPORTED.  The launch
  * shapes are those of the membrane kernel (oif_batch_set_launch's mesh_block
- * is the workgroup size of both task kinds). */
-int oif_batch_set_persistent(oif_batch* b, int on);
+ * is the workgroup size of both task kinds).  lattice_blocks_per_task: blocks
+ * of mesh_block nodes that one lattice task updates (0: about three lattice
+ * tasks per resident workgroup).  OIF_E_ARG for on outside {0, 1} or a
+ * negative count. */
+int oif_batch_set_persistent(oif_batch* b, int on, int lattice_blocks_per_task);
 int oif_batch_autotune(oif_batch* b, const char* cache_path);
 int oif_batch_step_timed(oif_batch* b, int n_steps, oif_timing* t);
 const char* oif_batch_last_error(const oif_batch* b);

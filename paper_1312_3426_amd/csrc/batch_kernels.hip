@@ -27,16 +27,60 @@ namespace {
 
 using namespace dev;
 
+// Call arguments arrive in vector registers and as generic pointers.  The
+// task arguments are uniform across the workgroup and the descriptors they
+// point to do not change during a launch, so the callees read them through
+// the constant address space: scalar loads into scalar registers, as the
+// per-phase kernels read theirs from kernel arguments.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> uniform(const T* p) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (cptr<T>)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 // The task bodies as calls rather than inlined: each keeps the register
 // allocation it has in its own kernel (inlined side by side in one loop, the
 // three membrane variants and the lattice update spilled heavily).
+// The object descriptor field by field (a copy through the constant address
+// space; a new field of ObjDev must be added here as well).
+template <typename R>
+__device__ __forceinline__ ObjDev<R> load_obj(cptr<ObjDev<R>> p) {
+    static_assert(sizeof(ObjDev<R>) == (sizeof(R) == 8 ? 120 : 104), "ObjDev changed: update load_obj");
+    ObjDev<R> o;
+    o.t = p->t;
+    o.box = p->box;
+    o.X = p->X;
+    o.V = p->V;
+    o.geo = p->geo;
+    o.F = p->F;
+    o.frep = p->frep;
+    o.node0 = p->node0;
+    for (int k = 0; k < 3; ++k) o.anchor[k] = p->anchor[k];
+    o.inv_mass = p->inv_mass;
+    for (int k = 0; k < 3; ++k) o.fext[k] = p->fext[k];
+    o.mass = p->mass;
+    o.scratch = p->scratch;
+    return o;
+}
+
 template <int P, bool USE_LDS, bool CPL>
 __device__ __noinline__ void mesh_task(const ObjDev<typename Prec<P>::R>* O, unsigned char* smem, int parity) {
-    mesh_object<P, USE_LDS, true, CPL>(*O, smem, parity, 0);
+    const ObjDev<typename Prec<P>::R> o = load_obj(uniform(O));
+    mesh_object<P, USE_LDS, true, CPL>(o, smem, uniform(parity), 0);
 }
 template <int P, bool NT>
-__device__ __noinline__ void lb_task(const BoxDev* B, int blk, int parity) {
-    lb_node<P, false, true, false, NT>(B, blk * (int)blockDim.x + (int)threadIdx.x, parity, LB_ALL);
+__device__ __noinline__ void lb_task(const BoxDev* B, int blk, int nblk, int parity) {
+    const cptr<BoxDev> b = uniform(B);
+    blk = uniform(blk);
+    nblk = uniform(nblk);
+    parity = uniform(parity);
+    for (int k = 0; k < nblk; ++k)
+        lb_node<P, false, true, false, NT>(b, (blk + k) * (int)blockDim.x + (int)threadIdx.x, parity, LB_ALL);
 }
 
 template <int P, bool NT>
@@ -50,12 +94,18 @@ batch_kernel(const BatchSched* __restrict__ S, int parity) {
     // then finished membrane tasks per box (one set per step parity; the set
     // of a launch is cleared by its last workgroup for the launch after next)
     unsigned* ctr = S->ctr + (size_t)(parity & 1) * (3 + nbox);
-    // Thread 0 publishes the membrane task a workgroup has just finished in
-    // the same branch that takes the next ticket, so each pass of the loop has
-    // exactly one single-thread region and it closes at a barrier.  (With a
-    // second such region at the end of the membrane branch the two can be
-    // merged across the back edge, which leaves the ticket barrier reachable
-    // from inside a loop that thread 0 has already left.)
+    // Ordering between the two task kinds, with one device-scope fence per
+    // task, issued by thread 0: a membrane task's threads meet at a barrier
+    // and thread 0 then counts the task with a release increment; a lattice
+    // task's thread 0 polls the count with relaxed loads, then acquires, and
+    // the other threads follow it through a barrier.  (A device-scope fence in
+    // every wave would write back and invalidate the L2 of its XCD once per
+    // wave.)  Thread 0 publishes the finished membrane task in the same branch
+    // that takes the next ticket, so each pass of the loop has one
+    // single-thread region and it closes at a barrier: with a second such
+    // region at the end of the membrane branch the two can be merged across
+    // the back edge, which leaves the ticket barrier inside a loop that
+    // thread 0 has already left.
     int done_box = -1;
     for (;;) {
         if (threadIdx.x == 0) {
@@ -74,28 +124,25 @@ batch_kernel(const BatchSched* __restrict__ S, int parity) {
             if (g == 0) mesh_task<P, true, false>(O, smem, parity);
             else if (g == 1) mesh_task<P, false, true>(O, smem, parity);
             else mesh_task<P, false, false>(O, smem, parity);
-            // every thread's stores and atomics reach device scope before
-            // thread 0 counts the task as finished (next pass of the loop)
-            __threadfence();
-            __syncthreads();
+            __syncthreads();  // all threads' spreading is done before thread 0 counts the task
             done_box = __builtin_amdgcn_readfirstlane(S->obj_box[t]);
         } else {
             done_box = -1;
-            const int2 w = S->lbwork[t - nmesh];  // (box, block of nodes)
+            const int2 w = S->lbwork[t - nmesh];  // (box, first block of nodes)
             if (threadIdx.x == 0) {
                 const unsigned want = (unsigned)S->box_nmesh[w.x];
                 unsigned long long spins = 0;
-                while (__hip_atomic_load(&ctr[3 + w.x], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < want) {
+                while (__hip_atomic_load(&ctr[3 + w.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
                     if (++spins > S->spin_limit) {
                         atomicOr(&ctr[2], 1u);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(4);
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the box's spread forces
             }
             __syncthreads();
-            __threadfence();  // acquire for every wave: the spread forces are read below
-            lb_task<P, NT>(S->boxes + w.x, w.y, parity);
+            lb_task<P, NT>(S->boxes + w.x, w.y, S->lb_chunk, parity);
         }
     }
     // the last workgroup to finish clears this parity's counters (the flag

@@ -14,7 +14,8 @@ struct BatchSched {
     const unsigned char* group;  // [nmesh] 0: mesh in LDS; 1: mesh in the scratch, coupling area in
                                  // LDS; 2: all in the scratch
     const int* obj_box;          // [nmesh] box of each membrane task
-    const int2* lbwork;          // [ntasks - nmesh] (box, block of blockDim nodes)
+    const int2* lbwork;          // [ntasks - nmesh] (box, first block of blockDim nodes)
+    int lb_chunk;                // blocks of nodes per lattice task
     const BoxDev* boxes;         // [nbox]
     const int* box_nmesh;        // [nbox] membrane tasks per box
     unsigned* ctr;               // [2][3 + nbox] per step parity: next ticket, workgroups done,

@@ -11,8 +11,8 @@ namespace dev {
 
 // Coupling force density at node p, read from G and cleared there (the
 // node's three components are one 32-byte slot).
-template <int P>
-__device__ __forceinline__ void take_force(const BoxDev* __restrict__ B, int p, typename Prec<P>::R& fx,
+template <int P, class BP>
+__device__ __forceinline__ void take_force(BP __restrict__ B, int p, typename Prec<P>::R& fx,
                                            typename Prec<P>::R& fy, typename Prec<P>::R& fz) {
     typedef typename Prec<P>::R R;
     const unsigned o = (unsigned)p * 32u;
@@ -92,8 +92,8 @@ __device__ __forceinline__ R codd(int i) {
 // parts in FP64 only the final rounding of each stored value remains, whose
 // residuals do average out.  The parts even in e_i (density and the
 // second-order terms) stay in FP32.
-template <typename R, bool ACC>
-__device__ __forceinline__ void collide(const BoxDev* __restrict__ B, R (&d)[19], R fx, R fy, R fz) {
+template <typename R, bool ACC, class BP>
+__device__ __forceinline__ void collide(BP __restrict__ B, R (&d)[19], R fx, R fy, R fz) {
 #pragma clang fp contract(off)
     R drho = 0;
 #pragma unroll
@@ -177,8 +177,8 @@ __device__ __forceinline__ void collide(const BoxDev* __restrict__ B, R (&d)[19]
 // and even under e -> -e.  Rounded as written, like collide(), and, with ACC,
 // with the odd (momentum-carrying) parts in FP64 from the exact FP64 momentum
 // for the reason given there.
-template <typename R, bool ACC>
-__device__ __forceinline__ void collide_mrt(const BoxDev* __restrict__ B, R (&d)[19], R fx, R fy, R fz) {
+template <typename R, bool ACC, class BP>
+__device__ __forceinline__ void collide_mrt(BP __restrict__ B, R (&d)[19], R fx, R fy, R fz) {
 #pragma clang fp contract(off)
     R drho = 0;
 #pragma unroll
@@ -280,8 +280,8 @@ __device__ __forceinline__ void collide_mrt(const BoxDev* __restrict__ B, R (&d)
 // displace the values just pushed, which the next step reads); the values are
 // the same either way.  A template choice: two branches that differ only in
 // the cache hint are merged by the compiler, hint dropped.
-template <int P, bool NT>
-__device__ __forceinline__ void load_pops(const BoxDev* __restrict__ B, int p, int parity,
+template <int P, bool NT, class BP>
+__device__ __forceinline__ void load_pops(BP __restrict__ B, int p, int parity,
                                           typename Prec<P>::S (&raw)[19]) {
     typedef typename Prec<P>::S S;
     const gptr<const S> tile = wave_tile((const S*)B->f[parity], p);
@@ -297,8 +297,8 @@ __device__ __forceinline__ void load_pops(const BoxDev* __restrict__ B, int p, i
     }
 }
 
-template <int P, bool OBST, bool MRT>
-__device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p,
+template <int P, bool OBST, bool MRT, class BP>
+__device__ __forceinline__ void collide_push(BP __restrict__ B, int p,
                                              const typename Prec<P>::S (&raw)[19], typename Prec<P>::R fx,
                                              typename Prec<P>::R fy, typename Prec<P>::R fz, int parity,
                                              unsigned links) {
@@ -377,9 +377,12 @@ __device__ __forceinline__ void collide_push(const BoxDev* __restrict__ B, int p
 // first and are in flight while the mask word and any coupling force are
 // fetched).  MRT: the boxes use the multiple-relaxation-time collision.
 // The update of lattice node p of box B (nothing for p >= N), called by whole
-// waves whose 64 lanes hold the 64 nodes of one population tile.
-template <int P, bool OBST, bool ALL, bool MRT, bool NT>
-__device__ __forceinline__ void lb_node(const BoxDev* __restrict__ B, int p, int parity, int mode) {
+// waves whose 64 lanes hold the 64 nodes of one population tile.  BP: a plain
+// or a constant-address-space pointer to the box descriptor (the latter keeps
+// the descriptor in scalar registers where the compiler cannot tell that from
+// a kernel argument).
+template <int P, bool OBST, bool ALL, bool MRT, bool NT, class BP>
+__device__ __forceinline__ void lb_node(BP __restrict__ B, int p, int parity, int mode) {
     typedef typename Prec<P>::S S;
     typedef typename Prec<P>::R R;
     const int N = B->N;

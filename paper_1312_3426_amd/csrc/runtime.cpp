@@ -424,6 +424,8 @@ struct oif_batch {
     DevBuf sched_dev, p_objs, p_group, p_objbox, p_lbwork, p_boxnmesh, p_ctr;
     int p_grid = 0;
     size_t p_lds = 0;
+    int p_chunk_req = 0;  // lattice blocks per task as set (0: chosen at build)
+    int p_chunk = 1;
 };
 
 namespace {
@@ -2135,19 +2137,28 @@ int batch_build(oif_batch* b) {
             return bmax[a] != bmax[c] ? bmax[a] < bmax[c] : bn[a] < bn[c];
         });
         const int block = b->mesh_block;
-        std::vector<int2> lbw;
-        for (int i : bo) {
-            const int nb = (b->ctx[i]->N + block - 1) / block;
-            for (int k = 0; k < nb; ++k) lbw.push_back(make_int2(i, k));
-        }
         b->p_lds = std::max(b->n_lds_obj ? b->lds_need : 0, b->n_cpl_obj ? b->cpl_need : 0);
         int per_cu = 0, dev = 0, ncu = 0;
         BHIP(b, hipGetDevice(&dev));
         BHIP(b, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         BHIP(b, batch_blocks_per_cu(b->precision, b->lb_nt, block, b->p_lds, &per_cu));
         if (per_cu < 1) return bfail(b, OIF_E_UNSUPPORTED, "persistent batch: no workgroup fits a compute unit");
+        const int slots = per_cu * ncu;
+        long long nblk_all = 0;
+        for (oif_ctx* c : b->ctx) nblk_all += (c->N + block - 1) / block;
+        // lattice blocks per task: by default about three lattice tasks per
+        // resident workgroup (fewer tickets and waits; enough tasks to even
+        // out the ends of the boxes' membrane phases)
+        b->p_chunk = b->p_chunk_req > 0
+                         ? b->p_chunk_req
+                         : (int)std::max(1LL, std::min(64LL, (nblk_all + 3LL * slots - 1) / (3LL * slots)));
+        std::vector<int2> lbw;
+        for (int i : bo) {
+            const int nb = (b->ctx[i]->N + block - 1) / block;
+            for (int k = 0; k < nb; k += b->p_chunk) lbw.push_back(make_int2(i, k));
+        }
         const int ntasks = (int)(ents.size() + lbw.size());
-        b->p_grid = std::max(1, std::min(per_cu * ncu, ntasks));
+        b->p_grid = std::max(1, std::min(slots, ntasks));
         const size_t nctr = 2 * (3 + b->ctx.size());
         for (DevBuf* d : {&b->sched_dev, &b->p_objs, &b->p_group, &b->p_objbox, &b->p_lbwork, &b->p_boxnmesh, &b->p_ctr})
             d->release();
@@ -2172,6 +2183,7 @@ int batch_build(oif_batch* b) {
         S.group = (const unsigned char*)b->p_group.p;
         S.obj_box = (const int*)b->p_objbox.p;
         S.lbwork = (const int2*)b->p_lbwork.p;
+        S.lb_chunk = b->p_chunk;
         S.boxes = (const BoxDev*)b->boxes_dev.p;
         S.box_nmesh = (const int*)b->p_boxnmesh.p;
         S.ctr = (unsigned*)b->p_ctr.p;
@@ -2336,9 +2348,10 @@ int oif_batch_set_launch(oif_batch* b, int lb_block, int mesh_block, int xcd_rem
     return OIF_OK;
 }
 
-int oif_batch_set_persistent(oif_batch* b, int on) {
-    if (!b || (on != 0 && on != 1)) return OIF_E_ARG;
+int oif_batch_set_persistent(oif_batch* b, int on, int lattice_blocks_per_task) {
+    if (!b || (on != 0 && on != 1) || lattice_blocks_per_task < 0) return OIF_E_ARG;
     b->persistent = on;
+    b->p_chunk_req = lattice_blocks_per_task;
     b->built = false;
     bdrop_graph(b);
     return OIF_OK;

@@ -125,7 +125,7 @@ SIGNATURES = {
     "oif_batch_set_graph": (_i, [_vp, _i]),
     "oif_batch_set_launch": (_i, [_vp, _i, _i, _i]),
     "oif_batch_set_lb_loads": (_i, [_vp, _i]),
-    "oif_batch_set_persistent": (_i, [_vp, _i]),
+    "oif_batch_set_persistent": (_i, [_vp, _i, _i]),
     "oif_batch_autotune": (_i, [_vp, C.c_char_p]),
     "oif_batch_step_timed": (_i, [_vp, _i, _vp]),
     "oif_batch_last_error": (C.c_char_p, [_vp]),
@@ -469,8 +469,8 @@ class Batch:
     def set_lb_loads(self, nontemporal: bool):
         self._chk(lib().oif_batch_set_lb_loads(self.h, int(bool(nontemporal))))
 
-    def set_persistent(self, on: bool):
-        self._chk(lib().oif_batch_set_persistent(self.h, int(bool(on))))
+    def set_persistent(self, on: bool, lattice_blocks_per_task: int = 0):
+        self._chk(lib().oif_batch_set_persistent(self.h, int(bool(on)), int(lattice_blocks_per_task)))
 
     def autotune(self, cache_path: Optional[str] = None):
         self._chk(lib().oif_batch_autotune(self.h, None if cache_path is None else cache_path.encode()))

@@ -421,15 +421,17 @@ def test_membrane_block_sizes_match_oracle(oif, orc, mb):
     assert all(v[3] for v in res.values()), fmt(res)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_persistent_batch_matches_launch_pairs(oif, prec):
+@pytest.mark.parametrize("prec,chunk", [("fp32", 0), ("fp64", 0), ("fp32", 1), ("fp32", 3)])
+def test_persistent_batch_matches_launch_pairs(oif, prec, chunk):
     """The persistent form of a batch (one launch per step, device task list,
     per-box waits) gives the launch-per-phase results: bit for bit in FP32
     (fixed-point spreading), to round-off in FP64 (FP64 atomics); eagerly, under
     graph capture, and from either step parity.  The boxes mix 162-, 642- and
     2562-node spheres, so membrane tasks of all three kinds (mesh in LDS, mesh
-    in the scratch with the coupling area in LDS) run."""
-    say(f"[modes] persistent batch vs launch pairs, {prec}")
+    in the scratch with the coupling area in LDS) run; lattice tasks of one
+    block, of the default count, and of three blocks (a box's last task then
+    runs past its nodes)."""
+    say(f"[modes] persistent batch vs launch pairs, {prec}, lattice blocks per task {chunk}")
     boxes = synth.config_batch(n_boxes=6, steps=12)
     ref, got = [], []
     for persistent, out in ((False, ref), (True, got)):
@@ -438,7 +440,7 @@ def test_persistent_batch_matches_launch_pairs(oif, prec):
         for c in ctxs[1:]:
             c.step(1)
         B = oif.Batch(ctxs)
-        B.set_persistent(persistent)
+        B.set_persistent(persistent, chunk)
         B.step(3)
         B.set_graph(4)
         B.step(8)
