@@ -202,7 +202,8 @@ def batching(oif, steps, tune):
     if tune:
         b.autotune(tune)
     b.step(2)
-    eager_ms = b.step_timed(steps).total_ms
+    tb = b.step_timed(steps)
+    eager_ms = tb.total_ms
     b.set_graph(50)
     b.step(100)
     t0 = time.perf_counter()
@@ -235,6 +236,8 @@ def batching(oif, steps, tune):
             "steps": steps, "loop_mlups": ml(loop_ms), "batched_mlups": ml(eager_ms),
             "batched_graph_mlups": ml(graph_ms), "speedup_batched": round(loop_ms / eager_ms, 3),
             "speedup_batched_graph": round(loop_ms / graph_ms, 3),
+            "membrane_ms_per_step": round(tb.mesh_ms, 4), "lattice_ms_per_step": round(tb.lb_ms, 4),
+            "membrane_share": round(tb.mesh_ms * steps / eager_ms, 3),
             "persistent_mlups": ml(pers_ms), "persistent_graph_mlups": ml(pers_graph_ms),
             "persistent_best": {"workgroup": best[0], "lattice_blocks_per_task": best[1]},
             "persistent_mlups_by_workgroup_and_blocks_per_task": {f"{k[0]}/{k[1]}": ml(v) for k, v in pers.items()},

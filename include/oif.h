@@ -148,6 +148,11 @@ typedef struct {
     int cpl_objects;    /* objects in the global scratch whose coupling area (stencil bits,
                            touched-node velocities, force sums) sits in LDS */
     long long cpl_lds_bytes; /* LDS bytes per workgroup of that coupling area (0: no such object) */
+    int split_objects;  /* objects too large for LDS split over several workgroups each: triangles
+                           and edges in slices, then the nodes in compact patches, with their
+                           positions, the patch's forces and the coupling area in LDS */
+    int split_workgroups; /* workgroups of each of the two split launches */
+    long long split_lds_bytes; /* LDS bytes per workgroup of those launches (0: no such object) */
 } oif_info_t;
 
 /* FP64 conservation diagnostics and watchdog state. */

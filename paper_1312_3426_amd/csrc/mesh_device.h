@@ -124,8 +124,9 @@ __device__ __forceinline__ bool stencil_corner(double px, double py, double pz, 
 // object's stencil box is marked in the bitmask `bits` ((ucap + 31)/32 words)
 // first when it fits, so each touched node costs one global atomic however
 // many stencils contain it; otherwise every corner goes to `touch` directly.
-// Called by the whole workgroup.
-__device__ void mark_object(const double* pos, int nv, const int* anchor, gptr<const BoxDev> B,
+// Called by the whole workgroup.  The nodes marked: 0 .. nv - 1, or
+// order[0 .. nv - 1] when order is not null.
+__device__ void mark_object(const double* pos, const int* order, int nv, const int* anchor, gptr<const BoxDev> B,
                             int ucap, unsigned* bits, int* bbox, unsigned long long* touch) {
     __syncthreads();  // earlier users of bits and bbox are done
     if (threadIdx.x == 0) {
@@ -134,7 +135,8 @@ __device__ void mark_object(const double* pos, int nv, const int* anchor, gptr<c
     }
     __syncthreads();
     int blo[3] = {INT_MAX, INT_MAX, INT_MAX}, bhi[3] = {INT_MIN, INT_MIN, INT_MIN};
-    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        const int v = order ? gld(order + i) : i;
         const double sx = pos[3 * v] - 0.5, sy = pos[3 * v + 1] - 0.5, sz = pos[3 * v + 2] - 0.5;
         if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
         const int bx = anchor[0] + (int)floor(sx), by = anchor[1] + (int)floor(sy),
@@ -152,7 +154,8 @@ __device__ void mark_object(const double* pos, int nv, const int* anchor, gptr<c
         const int ex = (int)exl, exy = (int)(exl * eyl), vol = (int)(exl * eyl * ezl);
         for (int k = threadIdx.x; k < (vol + 31) / 32; k += blockDim.x) bits[k] = 0u;
         __syncthreads();
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+            const int v = order ? gld(order + i) : i;
             const double sx = pos[3 * v] - 0.5, sy = pos[3 * v + 1] - 0.5, sz = pos[3 * v + 2] - 0.5;
             if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
             const int b0 = (anchor[2] + (int)floor(sz) - oz) * exy + (anchor[1] + (int)floor(sy) - oy) * ex +
@@ -171,7 +174,8 @@ __device__ void mark_object(const double* pos, int nv, const int* anchor, gptr<c
             gatomic_or(touch + (q >> 6), 1ull << (q & 63));
         }
     } else {
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+            const int v = order ? gld(order + i) : i;
             const double sx = pos[3 * v] - 0.5, sy = pos[3 * v + 1] - 0.5, sz = pos[3 * v + 2] - 0.5;
             if (!(fabs(sx) < 1e7 && fabs(sy) < 1e7 && fabs(sz) < 1e7)) continue;
             const int bx = anchor[0] + (int)floor(sx), by = anchor[1] + (int)floor(sy),
@@ -189,11 +193,22 @@ __device__ void mark_object(const double* pos, int nv, const int* anchor, gptr<c
 // CPL (meshes too large for LDS only): the coupling area alone sits in LDS, so
 // that the stencil-bit ORs and the per-node force sums, whose addresses many
 // mesh nodes share, are LDS and not global atomics.
+// PH: the whole object in one workgroup (PH_ALL), or one of the two launches
+// that split it over T->nslice workgroups (meshes too large for LDS whose
+// positions fit there): PH_ELEMENTS, slice `slice` of the triangles and of the
+// edges, with the slice's area and volume sums left in the scratch;
+// PH_NODES, the forces, coupling and update of slice `slice` of the nodes (a
+// compact patch of the mesh, T->order), after the area and volume are summed
+// from the slices in a fixed order.  Split launches keep the triangle and edge
+// arrays in the scratch and the positions, the slice's forces and the coupling
+// area in LDS.
 // The membrane forces, coupling and update of object O by the whole
 // workgroup; smem is the workgroup's dynamic LDS.
-template <int P, bool USE_LDS, bool CONS, bool CPL>
+template <int P, bool USE_LDS, bool CONS, bool CPL, int PH = PH_ALL>
 __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O, unsigned char* smem, int parity,
-                                            int mark_next) {
+                                            int mark_next, int slice = 0) {
+    constexpr bool SPLIT = PH != PH_ALL;
+    static_assert(!SPLIT || (!USE_LDS && CPL), "split launches: mesh arrays in the scratch, coupling in LDS");
     typedef typename Prec<P>::S S;
     typedef typename Prec<P>::R R;
     __shared__ double red[16];
@@ -205,17 +220,25 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     const int cons = CONS ? T->conservative : 0;
     const MeshLayout lay = mesh_layout(sizeof(R), nv, nt, ne, ucap, ccap, cons);
     unsigned char* base = USE_LDS ? smem : O.scratch;
-    R* fs = (R*)(base + lay.fs);      // [nv][3]: elastic force
-    double* xs = (double*)(base + lay.xs);  // [nv][3]: positions (forces phase)
+    // split launches: the slice's forces, then the positions in LDS
+    const size_t sxs = SPLIT ? split_xs_offset(sizeof(R), T->smax) : 0;
+    R* fs = SPLIT ? (R*)smem : (R*)(base + lay.fs);  // [nodes of the launch][3]: elastic force
+    double* xs = SPLIT ? (double*)(smem + sxs) : (double*)(base + lay.xs);  // [nv][3]: positions (forces phase)
     R* tn = (R*)(base + lay.tn);      // [nt][4]: unit inward normal, area
     R* tr = (R*)(base + lay.tr);      // [nt]: (S - S0)/S
     R* se = (R*)(base + lay.se);      // [ne]: ks kappa strain / L
     R* fh = (R*)(base + lay.fh);      // [ne]: kb (theta - theta0)/theta0
     // coupling area: over the positions and the forces-phase arrays, or alone
-    // in LDS (CPL)
+    // in LDS (CPL), or over the positions in LDS (split)
     auto carea = [&](size_t off) -> unsigned char* {
-        return (!USE_LDS && CPL) ? smem + (off - lay.need) : base + off;
+        return SPLIT ? smem + sxs + (off - lay.need) : ((!USE_LDS && CPL) ? smem + (off - lay.need) : base + off);
     };
+    // the nodes this launch updates: all, or slice `slice` in T->order
+    const int nsl = SPLIT ? T->nslice : 1;
+    const int n0 = SPLIT ? gld(T->slice_off + slice) : 0;
+    const int nn = SPLIT ? gld(T->slice_off + slice + 1) - n0 : nv;
+    auto node_of = [&](int i) -> int { return SPLIT ? gld(T->order + n0 + i) : i; };
+    double* part = SPLIT ? (double*)(O.scratch + split_part_offset(lay)) : nullptr;  // [nslice][2]
     unsigned* need = (unsigned*)carea(lay.need);  // coupling phase: stencil-box bits
     __shared__ int bbox[6];
     __shared__ int ncomp;
@@ -240,9 +263,11 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     // (S - S0 is formed as (S^2 - S0^2)/(S + S0): the cancelling difference in
     // FP64 multiply-adds, the square root and division in the arithmetic type)
     double sdarea = 0.0, svol = 0.0;
-    {
+    if (PH != PH_NODES) {
         const double r0x = xs[0], r0y = xs[1], r0z = xs[2];
-        for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+        const int t0 = SPLIT ? (int)((long long)nt * slice / nsl) : 0;
+        const int t1 = SPLIT ? (int)((long long)nt * (slice + 1) / nsl) : nt;
+        for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
             const int a = gld(T->tri + 3 * t), b = gld(T->tri + 3 * t + 1), c = gld(T->tri + 3 * t + 2);
             const double ax = xs[3 * a] - r0x, ay = xs[3 * a + 1] - r0y, az = xs[3 * a + 2] - r0z;
             const double bx = xs[3 * b] - r0x, by = xs[3 * b + 1] - r0y, bz = xs[3 * b + 2] - r0z;
@@ -268,18 +293,39 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
             svol -= (ax * cxx + ay * cyy + az * czz) / 6.0;
         }
     }
-    const double dSg = block_sum(sdarea, red);  // Sg - Sg0
-    const double Vol = block_sum(svol, red);
+    double dSg, Vol;  // Sg - Sg0, volume
+    if (PH == PH_ALL) {
+        dSg = block_sum(sdarea, red);
+        Vol = block_sum(svol, red);
+    } else if (PH == PH_ELEMENTS) {
+        dSg = block_sum(sdarea, red);
+        Vol = block_sum(svol, red);
+        if (threadIdx.x == 0) {
+            gst(part + 2 * slice, dSg);
+            gst(part + 2 * slice + 1, Vol);
+        }
+    } else {
+        // the slices' sums, added in slice order (the same bits in every
+        // workgroup of the object)
+        dSg = 0.0;
+        Vol = 0.0;
+        for (int k = 0; k < nsl; ++k) {
+            dSg += gld(part + 2 * k);
+            Vol += gld(part + 2 * k + 1);
+        }
+    }
     const double Sg = T->Sg0 + dSg;
-    if (threadIdx.x == 0 && O.geo) {
+    if (PH != PH_ELEMENTS && threadIdx.x == 0 && slice == 0 && O.geo) {
         gst(O.geo, Sg);
         gst(O.geo + 1, Vol);
     }
 
     // 2. edges: stretching coefficient and bending magnitude of each hinge
     const bool do_s = T->ks != 0.0, do_b = T->kb != 0.0;
-    if (do_s || do_b) {
-        for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    if (PH != PH_NODES && (do_s || do_b)) {
+        const int e0 = SPLIT ? (int)((long long)ne * slice / nsl) : 0;
+        const int e1 = SPLIT ? (int)((long long)ne * (slice + 1) / nsl) : ne;
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
             const int4 h = gld(T->hinge + e);  // (A, B, C, D): the edge is B -> C
             const double dx = xs[3 * h.z] - xs[3 * h.y], dy = xs[3 * h.z + 1] - xs[3 * h.y + 1],
                          dz = xs[3 * h.z + 2] - xs[3 * h.y + 2];
@@ -337,6 +383,7 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
             }
         }
     }
+    if (PH == PH_ELEMENTS) return;  // the node launch reads the slices' results
     __syncthreads();
 
     const R cg = (R)(-T->kag * dSg / Sg);             // global area coefficient
@@ -352,8 +399,9 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     unsigned flags = 0;
     int blo[3] = {INT_MAX, INT_MAX, INT_MAX}, bhi[3] = {INT_MIN, INT_MIN, INT_MIN};
 
-    // 3. nodes
-    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+    // 3. nodes (fs is indexed by the node's place i in the launch's node set)
+    for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+        const int v = node_of(i);
         const double px = xs[3 * v], py = xs[3 * v + 1], pz = xs[3 * v + 2];
         R Fx = 0, Fy = 0, Fz = 0;
         const int4 o0 = gld(T->n_off + v), o1 = gld(T->n_off + v + 1);
@@ -418,9 +466,9 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
             Fz += ct * wz - vf * tn[4 * t + 2];
         }
 
-        fs[3 * v] = Fx;
-        fs[3 * v + 1] = Fy;
-        fs[3 * v + 2] = Fz;
+        fs[3 * i] = Fx;
+        fs[3 * i + 1] = Fy;
+        fs[3 * i + 2] = Fz;
         // lower corner of the node's 2x2x2 stencil (unwrapped lattice index);
         // nodes sit at cell centres, so the stencil starts at floor(x - 1/2)
         int b[3];
@@ -456,7 +504,8 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
         const int nw = (vol + 31) >> 5;
         for (int k = threadIdx.x; k < nw; k += blockDim.x) need[k] = 0u;
         __syncthreads();
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+            const int v = node_of(i);
             int b[3];
             if (!stencil_corner(stage(3 * v), stage(3 * v + 1), stage(3 * v + 2), O.anchor, b)) continue;
             const int b0 = (b[2] - oz) * exy + (b[1] - oy) * ex + (b[0] - ox);
@@ -547,7 +596,8 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     }
 
     // per mesh node: interpolate, drag, integrate, spread
-    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+    for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+        const int v = node_of(i);
         const double px = stage(3 * v), py = stage(3 * v + 1), pz = stage(3 * v + 2);
         R vx = gld(O.V + 3 * v), vy = gld(O.V + 3 * v + 1), vz = gld(O.V + 3 * v + 2);
         if (O.F) {  // the half-step velocity, as staged
@@ -665,9 +715,9 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
             ry = gld(O.frep + 3 * v + 1);
             rz = gld(O.frep + 3 * v + 2);
         }
-        const R ftx = fs[3 * v] - dgx + O.fext[0] + rx;
-        const R fty = fs[3 * v + 1] - dgy + O.fext[1] + ry;
-        const R ftz = fs[3 * v + 2] - dgz + O.fext[2] + rz;
+        const R ftx = fs[3 * i] - dgx + O.fext[0] + rx;
+        const R fty = fs[3 * i + 1] - dgy + O.fext[1] + ry;
+        const R ftz = fs[3 * i + 2] - dgz + O.fext[2] + rz;
         if (O.F) {
             vx += ftx * half_im;
             vy += fty * half_im;
@@ -707,7 +757,8 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     }
     // split stepping: the stencils of the new positions, for the next step
     if (mark_next)  // (mark_object begins with a barrier: every new position is written)
-        mark_object(O.X, nv, O.anchor, B, ucap, need, bbox, B->touch[parity ^ 1]);
+        mark_object(O.X, SPLIT ? T->order + n0 : nullptr, nn, O.anchor, B, ucap, need, bbox,
+                    B->touch[parity ^ 1]);
     if (flags) gatomic_or(B->status, flags);
 }
 

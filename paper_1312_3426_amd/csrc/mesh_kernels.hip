@@ -22,7 +22,10 @@
 // the update is the second half kick; the total force is kept for the next
 // step.
 // Meshes whose arrays do not fit in LDS use a per-object global scratch area
-// with the same layout.
+// with the same layout; when their positions fit in LDS, they are split over
+// several workgroups per object (triangles and edges in slices, then the
+// nodes in compact patches, with the area and volume summed over the slices
+// in a fixed order).
 #include "mesh_device.h"
 
 namespace oif {
@@ -43,6 +46,18 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     mesh_object<P, USE_LDS, CONS, CPL>(objs[bid], smem, parity, mark_next);
 }
 
+// Meshes too large for LDS whose positions fit there, split over several
+// workgroups per object: the elements launch (PH_ELEMENTS) and then the nodes
+// launch (PH_NODES), one workgroup per (object, slice) in `work`.
+template <int P, bool CONS, int PH>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 1 : 6)))
+mesh_split_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, const int2* __restrict__ work, int parity,
+                  int mark_next) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 w = work[blockIdx.x];
+    mesh_object<P, false, CONS, true, PH>(objs[w.x], smem, parity, mark_next, w.y);
+}
+
 // Touch bits of a step of parity `parity` from the current positions (split
 // stepping, when the membrane kernel of the previous step did not mark them).
 // One workgroup per object.
@@ -52,7 +67,7 @@ __global__ void __launch_bounds__(256) mark_kernel(const ObjDev<R>* __restrict__
     __shared__ int bbox[6];
     const ObjDev<R>& O = objs[blockIdx.x];
     const gptr<const BoxDev> B = (gptr<const BoxDev>)O.box;
-    mark_object(O.X, O.t->nv, O.anchor, B, min(O.t->ucap, cap), bits, bbox, B->touch[parity]);
+    mark_object(O.X, nullptr, O.t->nv, O.anchor, B, min(O.t->ucap, cap), bits, bbox, B->touch[parity]);
 }
 
 template <typename R>
@@ -81,7 +96,20 @@ hipError_t launch_mesh_p(const MeshLaunch& L) {
     typedef typename Prec<P>::R R;
     const ObjDev<R>* objs = (const ObjDev<R>*)L.objs;
     const dim3 g(L.nobj), b(L.block);
-    if (L.lds_bytes > 0) {
+    if (L.work) {
+        const dim3 gw(L.nwork);
+        if (L.conservative) {
+            hipLaunchKernelGGL((mesh_split_kernel<P, true, PH_ELEMENTS>), gw, b, L.split_lds, L.stream, objs, L.work,
+                               L.parity, L.mark_next);
+            hipLaunchKernelGGL((mesh_split_kernel<P, true, PH_NODES>), gw, b, L.split_lds, L.stream, objs, L.work,
+                               L.parity, L.mark_next);
+        } else {
+            hipLaunchKernelGGL((mesh_split_kernel<P, false, PH_ELEMENTS>), gw, b, L.split_lds, L.stream, objs,
+                               L.work, L.parity, L.mark_next);
+            hipLaunchKernelGGL((mesh_split_kernel<P, false, PH_NODES>), gw, b, L.split_lds, L.stream, objs, L.work,
+                               L.parity, L.mark_next);
+        }
+    } else if (L.lds_bytes > 0) {
         if (L.conservative)
             hipLaunchKernelGGL((mesh_kernel<P, true, true>), g, b, L.lds_bytes, L.stream, objs, L.parity,
                                L.mark_next);
@@ -118,7 +146,7 @@ size_t mesh_cpl_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int c
 }
 
 hipError_t launch_mesh(const MeshLaunch& L) {
-    if (L.nobj <= 0) return hipSuccess;
+    if (L.work ? L.nwork <= 0 : L.nobj <= 0) return hipSuccess;
     switch (L.precision) {
         case PREC_FP64: return launch_mesh_p<PREC_FP64>(L);
         case PREC_FP32: return launch_mesh_p<PREC_FP32>(L);
@@ -147,7 +175,27 @@ hipError_t mesh_set_max_lds(size_t bytes) {
                           (const void*)mesh_kernel<PREC_FP32, false, true, true>,
                           (const void*)mesh_kernel<PREC_FP16, false, true, true>,
                           (const void*)mesh_kernel<PREC_BF16, false, true, true>};
+    const void* split[16] = {(const void*)mesh_split_kernel<PREC_FP64, false, PH_ELEMENTS>,
+                             (const void*)mesh_split_kernel<PREC_FP32, false, PH_ELEMENTS>,
+                             (const void*)mesh_split_kernel<PREC_FP16, false, PH_ELEMENTS>,
+                             (const void*)mesh_split_kernel<PREC_BF16, false, PH_ELEMENTS>,
+                             (const void*)mesh_split_kernel<PREC_FP64, true, PH_ELEMENTS>,
+                             (const void*)mesh_split_kernel<PREC_FP32, true, PH_ELEMENTS>,
+                             (const void*)mesh_split_kernel<PREC_FP16, true, PH_ELEMENTS>,
+                             (const void*)mesh_split_kernel<PREC_BF16, true, PH_ELEMENTS>,
+                             (const void*)mesh_split_kernel<PREC_FP64, false, PH_NODES>,
+                             (const void*)mesh_split_kernel<PREC_FP32, false, PH_NODES>,
+                             (const void*)mesh_split_kernel<PREC_FP16, false, PH_NODES>,
+                             (const void*)mesh_split_kernel<PREC_BF16, false, PH_NODES>,
+                             (const void*)mesh_split_kernel<PREC_FP64, true, PH_NODES>,
+                             (const void*)mesh_split_kernel<PREC_FP32, true, PH_NODES>,
+                             (const void*)mesh_split_kernel<PREC_FP16, true, PH_NODES>,
+                             (const void*)mesh_split_kernel<PREC_BF16, true, PH_NODES>};
     for (const void* f : fns) {
+        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (r != hipSuccess) e = r;
+    }
+    for (const void* f : split) {
         hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (r != hipSuccess) e = r;
     }

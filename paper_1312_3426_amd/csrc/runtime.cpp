@@ -67,6 +67,10 @@ namespace {
 // ---------------------------------------------------------------------------
 // templates (paper: template creation; relaxed values)
 // ---------------------------------------------------------------------------
+// Nodes per workgroup of the split membrane launches (at most; the slices
+// halve a mesh until they are this small).
+constexpr int SLICE_NODES = 768;
+
 struct Template {
     int nv = 0, nt = 0, ne = 0;
     std::vector<double> x;              // stretched coordinates [nv][3]
@@ -80,6 +84,10 @@ struct Template {
     oif_moduli k{};
     int ucap = 0; // lattice nodes of the largest stencil box an object can span
     int ccap = 0; // touched lattice nodes an object may have (LDS capacity)
+    // node slices of the split membrane launches: compact patches of the
+    // reference shape (recursive halving along the longest extent)
+    int nslice = 1, smax = 0;
+    std::vector<int> order, slice_off;
     std::vector<int> e_off, h_off, t_off;
     std::vector<std::array<int, 2>> e_inc;
     std::vector<int> h_inc, t_inc;
@@ -264,6 +272,42 @@ int build_template(const double* nodes, int nv, const int32_t* tris, int nt, con
         }
         T.ccap = std::min(T.ucap, most + most / 4 + 64);
     }
+    // node slices for the split launches: about 768 nodes each (a power of two
+    // of them), each half of its parent's nodes along the parent's longest
+    // extent, ties broken by node index
+    {
+        int K = 1;
+        while ((long long)K * SLICE_NODES < nv) K *= 2;
+        T.nslice = K;
+        T.order.resize(nv);
+        for (int v = 0; v < nv; ++v) T.order[v] = v;
+        T.slice_off.assign(1, 0);
+        std::function<void(int, int, int)> halve = [&](int lo, int hi, int k) {
+            if (k == 1) {
+                T.slice_off.push_back(hi);
+                return;
+            }
+            double mn[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, mx[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+            for (int i = lo; i < hi; ++i)
+                for (int a = 0; a < 3; ++a) {
+                    mn[a] = std::min(mn[a], T.x[3 * T.order[i] + a]);
+                    mx[a] = std::max(mx[a], T.x[3 * T.order[i] + a]);
+                }
+            int ax = 0;
+            for (int a = 1; a < 3; ++a)
+                if (mx[a] - mn[a] > mx[ax] - mn[ax]) ax = a;
+            std::sort(T.order.begin() + lo, T.order.begin() + hi, [&](int a, int b) {
+                const double xa = T.x[3 * a + ax], xb = T.x[3 * b + ax];
+                return xa != xb ? xa < xb : a < b;
+            });
+            const int mid = lo + (hi - lo) / 2;
+            halve(lo, mid, k / 2);
+            halve(mid, hi, k / 2);
+        };
+        halve(0, nv, K);
+        T.smax = 0;
+        for (int k = 0; k < K; ++k) T.smax = std::max(T.smax, T.slice_off[k + 1] - T.slice_off[k]);
+    }
     // per-node incidence lists (CSR)
     std::vector<std::vector<std::array<int, 2>>> ei(nv);
     std::vector<std::vector<int>> hi(nv), ti(nv);
@@ -363,9 +407,13 @@ struct oif_ctx {
     DevBuf tmpl_dev, obj_dev, X_dev, V_dev, F_dev, geo_dev, scratch_dev;
     std::vector<unsigned char> obj_host; // ObjDev<real> array as uploaded (sorted)
     int n_lds_obj = 0;          // objects [0, n_lds_obj) use LDS, the rest global scratch
+    int n_split_obj = 0;        // the next n_split_obj run split over several workgroups each
     int n_cpl_obj = 0;          // the next n_cpl_obj keep their coupling area in LDS
     size_t lds_need = 0;
-    size_t cpl_need = 0;        // LDS for the coupling area of those objects
+    size_t split_need = 0;      // LDS per workgroup of the split launches
+    size_t cpl_need = 0;        // LDS for the coupling area of the CPL objects
+    DevBuf split_work;          // (object, slice) per workgroup of the split launches
+    int n_split_work = 0;
     int any_conservative = 0;   // some template uses the conservative force model
 
     // launch configuration
@@ -405,7 +453,11 @@ struct oif_batch {
     int precision = 0;
     DevBuf boxes_dev, work_dev, obj_dev;
     std::vector<unsigned char> obj_host;
-    int nblocks = 0, nobj = 0, n_lds_obj = 0, n_cpl_obj = 0;
+    int nblocks = 0, nobj = 0, n_lds_obj = 0, n_split_obj = 0, n_cpl_obj = 0;
+    size_t split_need = 0;
+    DevBuf split_work;  // (object index within the split group, slice)
+    int n_split_work = 0;
+    size_t p_cpl_need = 0;  // persistent form: coupling area of split and CPL objects
     // the work list holds the boxes grouped by lattice-kernel variant
     // (obstacles, MRT collision): one launch per group
     int var_off[5] = {0, 0, 0, 0, 0};
@@ -612,7 +664,8 @@ int upload_mesh_t(oif_ctx* c) {
                  {tinc.data(), tinc.size() * 16},         {L0.data(), L0.size() * sizeof(double)},
                  {hv.data(), hv.size() * 16},             {th.data(), th.size() * sizeof(double)},
                  {cs0.data(), cs0.size() * sizeof(double)}, {S0.data(), S0.size() * sizeof(double)},
-                 {T.hbar.data(), T.hbar.size() * sizeof(double)}};
+                 {T.hbar.data(), T.hbar.size() * sizeof(double)}, {T.order.data(), T.order.size() * 4},
+                 {T.slice_off.data(), T.slice_off.size() * 4}};
         std::vector<size_t> offs;
         size_t total = 0;
         for (auto& p : parts) {
@@ -644,6 +697,10 @@ int upload_mesh_t(oif_ctx* c) {
         D.ks = T.k.ks; D.kb = T.k.kb; D.kal = T.k.kal; D.kag = T.k.kag; D.kv = T.k.kv;
         D.ucap = T.ucap;
         D.ccap = T.ccap;
+        D.nslice = T.nslice;
+        D.smax = T.smax;
+        D.order = (const int*)(b + offs[11]);
+        D.slice_off = (const int*)(b + offs[12]);
     }
     int rc = dev_alloc(c, c->tmpl_dev, td.size() * sizeof(TmplDev<real>));
     if (rc) return rc;
@@ -674,9 +731,11 @@ int upload_mesh_t(oif_ctx* c) {
     HIPCALL(c, hipMemcpy(c->X_dev.p, xl.data(), n * sizeof(double), hipMemcpyHostToDevice));
     HIPCALL(c, hipMemcpy(c->V_dev.p, vl.data(), n * sizeof(real), hipMemcpyHostToDevice));
 
-    // objects in three groups, each launched on its own and sorted largest
-    // mesh first: meshes staged in LDS whole; meshes in the global scratch
-    // whose coupling area fits in LDS; meshes entirely in the scratch
+    // objects in four groups, each launched on its own and sorted largest
+    // mesh first: meshes staged in LDS whole; meshes split over several
+    // workgroups (positions, slice forces and coupling area in LDS, element
+    // arrays in the scratch); meshes in the global scratch whose coupling area
+    // fits in LDS; meshes entirely in the scratch
     const size_t budget = c->max_lds;
     std::vector<int> order(c->obj.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
@@ -688,15 +747,29 @@ int upload_mesh_t(oif_ctx* c) {
         const Template& T = c->tmpl[c->obj[i].tid];
         return mesh_cpl_lds_bytes(c->d.precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T));
     };
-    auto group = [&](int i) { return need(i) <= budget ? 0 : (cpl(i) <= budget ? 1 : 2); };
+    auto split = [&](int i) {
+        const Template& T = c->tmpl[c->obj[i].tid];
+        return split_lds_bytes(c->d.precision == OIF_PREC_FP64 ? sizeof(double) : sizeof(float), T.nv, T.nt, T.ne,
+                               T.ucap, T.ccap, tmpl_conservative(T), T.smax);
+    };
+    auto group = [&](int i) {
+        return need(i) <= budget ? 0 : (split(i) <= budget ? 1 : (cpl(i) <= budget ? 2 : 3));
+    };
+    // scratch of an object outside LDS: the mesh layout, then the slices' sums
+    auto scratch_bytes = [&](int i) {
+        const Template& T = c->tmpl[c->obj[i].tid];
+        return (need(i) + 16 * (size_t)T.nslice + 16 + 255) & ~(size_t)255;
+    };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         const int ga = group(a), gb = group(b);
         if (ga != gb) return ga < gb;
         return c->obj[a].nv > c->obj[b].nv;
     });
     c->n_lds_obj = 0;
+    c->n_split_obj = 0;
     c->n_cpl_obj = 0;
     c->lds_need = 0;
+    c->split_need = 0;
     c->cpl_need = 0;
     c->any_conservative = 0;
     for (const Template& T : c->tmpl) c->any_conservative |= tmpl_conservative(T);
@@ -710,14 +783,30 @@ int upload_mesh_t(oif_ctx* c) {
             ++c->n_lds_obj;
             c->lds_need = std::max(c->lds_need, need(i));
         } else {
-            scratch_total += (need(i) + 255) & ~(size_t)255;
+            scratch_total += scratch_bytes(i);
             if (g == 1) {
+                ++c->n_split_obj;
+                c->split_need = std::max(c->split_need, split(i));
+            } else if (g == 2) {
                 ++c->n_cpl_obj;
                 c->cpl_need = std::max(c->cpl_need, cpl(i));
             }
         }
     }
     if ((rc = dev_alloc(c, c->scratch_dev, scratch_total))) return rc;
+    {  // the split launches' workgroups: (object index within the group, slice)
+        std::vector<int2> w;
+        for (int k = 0; k < c->n_split_obj; ++k) {
+            const Template& T = c->tmpl[c->obj[order[c->n_lds_obj + k]].tid];
+            for (int sl = 0; sl < T.nslice; ++sl) w.push_back(make_int2(k, sl));
+        }
+        c->n_split_work = (int)w.size();
+        c->split_work.release();
+        if (!w.empty()) {
+            if ((rc = dev_alloc(c, c->split_work, w.size() * sizeof(int2)))) return rc;
+            HIPCALL(c, hipMemcpy(c->split_work.p, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice));
+        }
+    }
     if ((rc = setup_repulsion(c, sizeof(real)))) return rc;
     std::vector<ObjDev<real>> od(c->obj.size());
     size_t soff = 0;
@@ -741,7 +830,7 @@ int upload_mesh_t(oif_ctx* c) {
         D.scratch = nullptr;
         if ((int)k >= c->n_lds_obj) {
             D.scratch = (unsigned char*)c->scratch_dev.p + soff;
-            soff += (need(order[k]) + 255) & ~(size_t)255;
+            soff += scratch_bytes(order[k]);
         }
     }
     c->obj_host.assign((unsigned char*)od.data(), (unsigned char*)(od.data() + od.size()));
@@ -794,14 +883,24 @@ int enqueue_mesh(oif_ctx* c, int par, hipStream_t s, int mark_next) {
         ml.lds_bytes = c->lds_need;
         HIPCALL(c, launch_mesh(ml));
     }
+    if (c->n_split_obj > 0) {
+        MeshLaunch sl = ml;
+        sl.objs = (const unsigned char*)c->obj_dev.p + osz * c->n_lds_obj;
+        sl.nobj = c->n_split_obj;
+        sl.lds_bytes = 0;
+        sl.work = (const int2*)c->split_work.p;
+        sl.nwork = c->n_split_work;
+        sl.split_lds = c->split_need;
+        HIPCALL(c, launch_mesh(sl));
+    }
     if (c->n_cpl_obj > 0) {
-        ml.objs = (const unsigned char*)c->obj_dev.p + osz * c->n_lds_obj;
+        ml.objs = (const unsigned char*)c->obj_dev.p + osz * (c->n_lds_obj + c->n_split_obj);
         ml.nobj = c->n_cpl_obj;
         ml.lds_bytes = 0;
         ml.cpl_lds_bytes = c->cpl_need;
         HIPCALL(c, launch_mesh(ml));
     }
-    const int done = c->n_lds_obj + c->n_cpl_obj;
+    const int done = c->n_lds_obj + c->n_split_obj + c->n_cpl_obj;
     if ((int)c->obj.size() > done) {
         ml.objs = (const unsigned char*)c->obj_dev.p + osz * done;
         ml.nobj = (int)c->obj.size() - done;
@@ -1104,7 +1203,8 @@ int oif_destroy(oif_ctx* c) {
         if (p) (void)hipFree(p);
     for (auto& b : c->tbufs) b.release();
     for (DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->F_dev, &c->geo_dev,
-                      &c->scratch_dev, &c->part_dev, &c->diag_out, &c->rep_desc, &c->rep_pos, &c->rep_cell,
+                      &c->scratch_dev, &c->split_work, &c->part_dev, &c->diag_out, &c->rep_desc, &c->rep_pos,
+                      &c->rep_cell,
                       &c->rep_cnt, &c->rep_cursor, &c->rep_bsum, &c->rep_list, &c->rep_spos, &c->rep_stype,
                       &c->rep_frep, &c->rep_type, &c->rep_shape})
         b->release();
@@ -1748,6 +1848,9 @@ int oif_info(oif_ctx* c, oif_info_t* info) {
     info->lds_objects = c->n_lds_obj;
     info->cpl_objects = c->n_cpl_obj;
     info->cpl_lds_bytes = (long long)c->cpl_need;
+    info->split_objects = c->n_split_obj;
+    info->split_workgroups = c->n_split_work;
+    info->split_lds_bytes = (long long)c->split_need;
     info->integrator = c->integrator;
     info->lb_nontemporal = c->lb_nt;
     return OIF_OK;
@@ -2062,14 +2165,17 @@ int batch_build(oif_batch* b) {
     BHIP(b, hipMemcpy(b->work_dev.p, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice));
     // objects of all boxes: LDS-resident group first, each largest mesh first
     const size_t osz = objdev_size(b->precision);
-    struct Ent { const unsigned char* p; int group; int nv; size_t need, cpl; int box; };
+    struct Ent { const unsigned char* p; int group; int nv; size_t need, cpl, split; int box; int nslice; };
     std::vector<Ent> ents;
     for (size_t bi = 0; bi < b->ctx.size(); ++bi) {
         oif_ctx* c = b->ctx[bi];
         const size_t n = c->obj.size();
         for (size_t k = 0; k < n; ++k) {
             const unsigned char* p = c->obj_host.data() + k * osz;
-            const int group = (int)k < c->n_lds_obj ? 0 : ((int)k < c->n_lds_obj + c->n_cpl_obj ? 1 : 2);
+            const int kk = (int)k;
+            const int group = kk < c->n_lds_obj ? 0
+                              : kk < c->n_lds_obj + c->n_split_obj ? 1
+                              : kk < c->n_lds_obj + c->n_split_obj + c->n_cpl_obj ? 2 : 3;
             // the template pointer of the sorted entry says which mesh it is
             const void* tptr = b->precision == OIF_PREC_FP64 ? (const void*)((const ObjDev<double>*)p)->t
                                                             : (const void*)((const ObjDev<float>*)p)->t;
@@ -2080,7 +2186,9 @@ int batch_build(oif_batch* b) {
                             mesh_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T)),
                             mesh_cpl_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap,
                                                tmpl_conservative(T)),
-                            (int)bi});
+                            split_lds_bytes(b->precision == OIF_PREC_FP64 ? sizeof(double) : sizeof(float), T.nv,
+                                            T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T), T.smax),
+                            (int)bi, T.nslice});
         }
     }
     std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& c) {
@@ -2089,10 +2197,14 @@ int batch_build(oif_batch* b) {
     });
     std::vector<unsigned char> host(ents.size() * osz);
     b->n_lds_obj = 0;
+    b->n_split_obj = 0;
     b->n_cpl_obj = 0;
     b->lds_need = 0;
+    b->split_need = 0;
     b->cpl_need = 0;
+    b->p_cpl_need = 0;
     b->any_conservative = 0;
+    std::vector<int2> sw;  // split launches' workgroups
     for (oif_ctx* c : b->ctx)
         for (const Template& T : c->tmpl) b->any_conservative |= tmpl_conservative(T);
     for (size_t k = 0; k < ents.size(); ++k) {
@@ -2101,9 +2213,21 @@ int batch_build(oif_batch* b) {
             ++b->n_lds_obj;
             b->lds_need = std::max(b->lds_need, ents[k].need);
         } else if (ents[k].group == 1) {
+            for (int sl = 0; sl < ents[k].nslice; ++sl) sw.push_back(make_int2(b->n_split_obj, sl));
+            ++b->n_split_obj;
+            b->split_need = std::max(b->split_need, ents[k].split);
+            b->p_cpl_need = std::max(b->p_cpl_need, ents[k].cpl);
+        } else if (ents[k].group == 2) {
             ++b->n_cpl_obj;
             b->cpl_need = std::max(b->cpl_need, ents[k].cpl);
+            b->p_cpl_need = std::max(b->p_cpl_need, ents[k].cpl);
         }
+    }
+    b->n_split_work = (int)sw.size();
+    b->split_work.release();
+    if (!sw.empty()) {
+        BHIP(b, hipMalloc(&b->split_work.p, sw.size() * sizeof(int2)));
+        BHIP(b, hipMemcpy(b->split_work.p, sw.data(), sw.size() * sizeof(int2), hipMemcpyHostToDevice));
     }
     b->nobj = (int)ents.size();
     b->obj_dev.release();
@@ -2126,7 +2250,9 @@ int batch_build(oif_batch* b) {
         for (size_t k = 0; k < mo.size(); ++k) {
             const Ent& e = ents[mo[k]];
             std::memcpy(pobj.data() + k * osz, e.p, osz);
-            pgroup[k] = (unsigned char)e.group;
+            // the persistent kernel runs split objects whole, with the coupling
+            // area in LDS
+            pgroup[k] = (unsigned char)(e.group == 0 ? 0 : (e.group <= 2 ? 1 : 2));
             pbox[k] = e.box;
             ++bn[e.box];
             bmax[e.box] = std::max(bmax[e.box], e.nv);
@@ -2137,7 +2263,7 @@ int batch_build(oif_batch* b) {
             return bmax[a] != bmax[c] ? bmax[a] < bmax[c] : bn[a] < bn[c];
         });
         const int block = b->mesh_block;
-        b->p_lds = std::max(b->n_lds_obj ? b->lds_need : 0, b->n_cpl_obj ? b->cpl_need : 0);
+        b->p_lds = std::max(b->n_lds_obj ? b->lds_need : 0, b->p_cpl_need);
         int per_cu = 0, dev = 0, ncu = 0;
         BHIP(b, hipGetDevice(&dev));
         BHIP(b, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -2226,14 +2352,24 @@ int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<h
             ml.lds_bytes = b->lds_need;
             BHIP(b, launch_mesh(ml));
         }
+        if (b->n_split_obj > 0) {
+            MeshLaunch sl = ml;
+            sl.objs = (const unsigned char*)b->obj_dev.p + osz * b->n_lds_obj;
+            sl.nobj = b->n_split_obj;
+            sl.lds_bytes = 0;
+            sl.work = (const int2*)b->split_work.p;
+            sl.nwork = b->n_split_work;
+            sl.split_lds = b->split_need;
+            BHIP(b, launch_mesh(sl));
+        }
         if (b->n_cpl_obj > 0) {
-            ml.objs = (const unsigned char*)b->obj_dev.p + osz * b->n_lds_obj;
+            ml.objs = (const unsigned char*)b->obj_dev.p + osz * (b->n_lds_obj + b->n_split_obj);
             ml.nobj = b->n_cpl_obj;
             ml.lds_bytes = 0;
             ml.cpl_lds_bytes = b->cpl_need;
             BHIP(b, launch_mesh(ml));
         }
-        const int done = b->n_lds_obj + b->n_cpl_obj;
+        const int done = b->n_lds_obj + b->n_split_obj + b->n_cpl_obj;
         if (b->nobj > done) {
             ml.objs = (const unsigned char*)b->obj_dev.p + osz * done;
             ml.nobj = b->nobj - done;
@@ -2320,6 +2456,7 @@ int oif_batch_destroy(oif_batch* b) {
     b->boxes_dev.release();
     b->work_dev.release();
     b->obj_dev.release();
+    b->split_work.release();
     for (DevBuf* d : {&b->sched_dev, &b->p_objs, &b->p_group, &b->p_objbox, &b->p_lbwork, &b->p_boxnmesh, &b->p_ctr})
         d->release();
     delete b;

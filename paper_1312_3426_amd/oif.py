@@ -57,7 +57,8 @@ class Info(C.Structure):
                 ("mesh_block", C.c_int), ("xcd_remap", C.c_int), ("graph_steps", C.c_int),
                 ("max_lds", C.c_longlong), ("lds_objects", C.c_int), ("overlap", C.c_int),
                 ("integrator", C.c_int), ("lb_nontemporal", C.c_int), ("cpl_objects", C.c_int),
-                ("cpl_lds_bytes", C.c_longlong)]
+                ("cpl_lds_bytes", C.c_longlong), ("split_objects", C.c_int), ("split_workgroups", C.c_int),
+                ("split_lds_bytes", C.c_longlong)]
 
 
 class Diag(C.Structure):
