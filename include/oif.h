@@ -153,6 +153,7 @@ typedef struct {
                            positions, the patch's forces and the coupling area in LDS */
     int split_workgroups; /* workgroups of each of the two split launches */
     long long split_lds_bytes; /* LDS bytes per workgroup of those launches (0: no such object) */
+    int force_clear_by_membrane; /* see oif_set_force_clear */
 } oif_info_t;
 
 /* FP64 conservation diagnostics and watchdog state. */
@@ -362,6 +363,18 @@ int oif_set_launch(oif_ctx* ctx, int lb_block, int mesh_block, int xcd_remap);
  * the two buffers together hold at most 1 GiB, else 0; the autotuner measures
  * both.  OIF_E_ARG for a value other than 0 or 1. */
 int oif_set_lb_loads(oif_ctx* ctx, int nontemporal);
+
+/* Who clears the coupling force density G (the reaction of eq. dragforce
+ * spread to the lattice, Section "Method").  G is kept per step parity.
+ * 0 (default): the lattice kernel clears each node's G where it reads it.
+ * 1: each membrane workgroup keeps the list of lattice nodes it added to and
+ * zeroes them one step later, when the lattice kernel is done with them, so
+ * the lattice kernel only reads G (its write traffic is the pushes alone);
+ * the membrane kernel then writes what the lattice kernel no longer does.
+ * Which is faster depends on the workload; the autotuner measures both.  The
+ * results are identical either way, and the choice may change between any
+ * two steps.  OIF_E_ARG for a value other than 0 or 1. */
+int oif_set_force_clear(oif_ctx* ctx, int by_membrane);
 
 
 /* Measured search of the launch shapes on this context's workload; the

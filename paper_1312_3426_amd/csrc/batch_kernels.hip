@@ -50,7 +50,7 @@ __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirs
 // space; a new field of ObjDev must be added here as well).
 template <typename R>
 __device__ __forceinline__ ObjDev<R> load_obj(cptr<ObjDev<R>> p) {
-    static_assert(sizeof(ObjDev<R>) == (sizeof(R) == 8 ? 120 : 104), "ObjDev changed: update load_obj");
+    static_assert(sizeof(ObjDev<R>) == (sizeof(R) == 8 ? 128 : 112), "ObjDev changed: update load_obj");
     ObjDev<R> o;
     o.t = p->t;
     o.box = p->box;
@@ -65,6 +65,7 @@ __device__ __forceinline__ ObjDev<R> load_obj(cptr<ObjDev<R>> p) {
     for (int k = 0; k < 3; ++k) o.fext[k] = p->fext[k];
     o.mass = p->mass;
     o.scratch = p->scratch;
+    o.qsave = p->qsave;
     return o;
 }
 

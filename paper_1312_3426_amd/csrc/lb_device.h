@@ -9,30 +9,37 @@
 namespace oif {
 namespace dev {
 
-// Coupling force density at node p, read from G and cleared there (the
-// node's three components are one 32-byte slot).
+// Coupling force density at node p, read from the step's G (the node's three
+// components are one 32-byte slot).  The membrane workgroups zero their slots
+// in the next step; only where one of them spread corner by corner (no list
+// of its slots) is the slot cleared here.
 template <int P, class BP>
-__device__ __forceinline__ void take_force(BP __restrict__ B, int p, typename Prec<P>::R& fx,
-                                           typename Prec<P>::R& fy, typename Prec<P>::R& fz) {
+__device__ __forceinline__ void take_force(BP __restrict__ B, int p, int parity, bool clear,
+                                           typename Prec<P>::R& fx, typename Prec<P>::R& fy,
+                                           typename Prec<P>::R& fz) {
     typedef typename Prec<P>::R R;
     const unsigned o = (unsigned)p * 32u;
     if (P == PREC_FP64) {
-        double* G = (double*)B->G;
+        double* G = (double*)B->G[parity];
         fx += (R)gload(G, o);
         fy += (R)gload(G, o + 8u);
         fz += (R)gload(G, o + 16u);
-        gstore(G, o, 0.0);
-        gstore(G, o + 8u, 0.0);
-        gstore(G, o + 16u, 0.0);
+        if (clear) {
+            gstore(G, o, 0.0);
+            gstore(G, o + 8u, 0.0);
+            gstore(G, o + 16u, 0.0);
+        }
     } else {
-        long long* G = (long long*)B->G;
+        long long* G = (long long*)B->G[parity];
         const double s = B->fp_inv;
         fx += (R)((double)gload(G, o) * s);
         fy += (R)((double)gload(G, o + 8u) * s);
         fz += (R)((double)gload(G, o + 16u) * s);
-        gstore(G, o, 0ll);
-        gstore(G, o + 8u, 0ll);
-        gstore(G, o + 16u, 0ll);
+        if (clear) {
+            gstore(G, o, 0ll);
+            gstore(G, o + 8u, 0ll);
+            gstore(G, o + 16u, 0ll);
+        }
     }
 }
 
@@ -394,6 +401,10 @@ __device__ __forceinline__ void lb_node(BP __restrict__ B, int p, int parity, in
     // bit is set.  Mask and touch words cover exactly one wave's 64 nodes; all
     // lanes load a word before the wave's first lane clears it.
     R fx = (R)B->g[0], fy = (R)B->g[1], fz = (R)B->g[2];
+    // whether this step's G is cleared here: always when the membrane kernel
+    // does not clear it, else where a workgroup spread corner by corner
+    // (uniform; loaded beside the mask word, not after it)
+    const unsigned gclear = B->g_by_mesh ? gld(B->gclear + parity) : 1u;
     unsigned long long* mk = B->mask + (p >> 6);
     unsigned long long m = 0ull;
     if (ALL) {
@@ -422,7 +433,7 @@ __device__ __forceinline__ void lb_node(BP __restrict__ B, int p, int parity, in
     // the node itself is solid, tested once its populations are loaded)
     const unsigned links = (OBST && B->links) ? gld(B->links + p) : 0u;
     if (!ALL) load_pops<P, NT>(B, p, parity, raw);
-    if ((m >> (p & 63)) & 1ull) take_force<P>(B, p, fx, fy, fz);
+    if ((m >> (p & 63)) & 1ull) take_force<P>(B, p, parity, gclear != 0u, fx, fy, fz);
     collide_push<P, OBST, MRT>(B, p, raw, fx, fy, fz, parity, links);
 }
 

@@ -3,8 +3,9 @@
 // term, eq. lbequation, and the moment definitions of density and velocity).
 //
 //   lb_kernel   one lattice node per thread: decode the 19 stored deviations,
-//               BGK collision with Guo forcing (force density g + G, G read
-//               only where the node's mask bit is set, then cleared), push the
+//               BGK collision with Guo forcing (force density g + G, the
+//               step's G read only where the node's mask bit is set, the bit
+//               cleared; the membrane kernel zeroes G in the next step), push the
 //               19 post-collision values to the neighbours (halfway
 //               bounce-back at z walls), encode.  HBM bound: every node reads
 //               and writes 19 stored values once, 2 x 19 x sizeof(storage)

@@ -37,9 +37,9 @@ struct Acc {
         atomicAdd(acc + 2, c);
         return fl;
     }
-    __device__ static unsigned flush(gptr<const BoxDev> B, int q, T x, T y, T z) {
+    __device__ static unsigned flush(gptr<const BoxDev> B, int parity, int q, T x, T y, T z) {
         if ((x | y | z) == 0ull) return 0u;
-        T* G = (T*)B->G + 4 * (size_t)q;
+        T* G = (T*)B->G[parity] + 4 * (size_t)q;
         gatomic_add(G, x);
         gatomic_add(G + 1, y);
         gatomic_add(G + 2, z);
@@ -58,9 +58,9 @@ struct Acc<PREC_FP64> {
         atomicAdd(acc + 2, z);
         return 0u;
     }
-    __device__ static unsigned flush(gptr<const BoxDev> B, int q, T x, T y, T z) {
+    __device__ static unsigned flush(gptr<const BoxDev> B, int parity, int q, T x, T y, T z) {
         if (x == 0.0 && y == 0.0 && z == 0.0) return 0u;
-        T* G = (T*)B->G + 4 * (size_t)q;
+        T* G = (T*)B->G[parity] + 4 * (size_t)q;
         gatomic_add(G, x);
         gatomic_add(G + 1, y);
         gatomic_add(G + 2, z);
@@ -202,9 +202,11 @@ __device__ void mark_object(const double* pos, const int* order, int nv, const i
 // from the slices in a fixed order.  Split launches keep the triangle and edge
 // arrays in the scratch and the positions, the slice's forces and the coupling
 // area in LDS.
+// LISTS: some box of the launch has the membrane kernel clear its coupling
+// force (BoxDev::g_by_mesh); without it the list code is left out.
 // The membrane forces, coupling and update of object O by the whole
 // workgroup; smem is the workgroup's dynamic LDS.
-template <int P, bool USE_LDS, bool CONS, bool CPL, int PH = PH_ALL>
+template <int P, bool USE_LDS, bool CONS, bool CPL, int PH = PH_ALL, bool LISTS = true>
 __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O, unsigned char* smem, int parity,
                                             int mark_next, int slice = 0) {
     constexpr bool SPLIT = PH != PH_ALL;
@@ -239,6 +241,34 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     const int nn = SPLIT ? gld(T->slice_off + slice + 1) - n0 : nv;
     auto node_of = [&](int i) -> int { return SPLIT ? gld(T->order + n0 + i) : i; };
     double* part = SPLIT ? (double*)(O.scratch + split_part_offset(lay)) : nullptr;  // [nslice][2]
+
+    // When the membrane kernel clears G (B->g_by_mesh): the G slots this object
+    // added to in the previous step (G[parity ^ 1], which the lattice kernel
+    // has read by now) are zeroed for the step after this one, from the lists
+    // the previous step kept (per slice; a whole-object workgroup takes all of
+    // them, since the previous step may have run split), and the previous
+    // step's flag is reset.  This step's lists start empty.  (Otherwise the
+    // lattice kernel clears G and no lists are kept.)
+    const bool lists = LISTS && B->g_by_mesh != 0;
+    const int kq = T->nslice;
+    const size_t qstride = (size_t)ccap + 1;
+    if (PH != PH_ELEMENTS && lists) {
+        const int np = parity ^ 1;
+        unsigned char* Gp = (unsigned char*)B->G[np];
+        for (int sl = SPLIT ? slice : 0; sl < (SPLIT ? slice + 1 : kq); ++sl) {
+            const int* qo = O.qsave + ((size_t)np * kq + sl) * qstride;
+            const int cnt = min(gld(qo), ccap);
+            for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+                unsigned long long* g = (unsigned long long*)(Gp + 32 * (size_t)gld(qo + 1 + k));
+                gst(g, 0ull);
+                gst(g + 1, 0ull);
+                gst(g + 2, 0ull);
+            }
+        }
+        if (threadIdx.x == 0) gst(B->gclear + np, 0u);
+        if ((int)threadIdx.x < (SPLIT ? 1 : kq))
+            gst(O.qsave + ((size_t)parity * kq + (SPLIT ? slice : (int)threadIdx.x)) * qstride, 0);
+    }
     unsigned* need = (unsigned*)carea(lay.need);  // coupling phase: stencil-box bits
     __shared__ int bbox[6];
     __shared__ int ncomp;
@@ -566,6 +596,11 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
                 qn[c] = (gz * nyb + gy) * nxb + gx;
             }
             __syncthreads();
+            if (lists) {  // the slots this workgroup adds to, zeroed by it in the next step
+                int* qs = O.qsave + ((size_t)parity * kq + (SPLIT ? slice : 0)) * qstride;
+                for (int k = threadIdx.x; k < ncomp; k += blockDim.x) gst(qs + 1 + k, qn[k]);
+                if (threadIdx.x == 0) gst(qs, ncomp);
+            }
             // fluid velocity there: one dense pass, all population loads in flight
             for (int c = threadIdx.x; c < ncomp; c += blockDim.x) {
                 const int q = qn[c];
@@ -594,6 +629,9 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
         }
         __syncthreads();
     }
+    // corner by corner with lists kept: the lattice kernel clears G[parity]
+    // where it reads it in this step
+    if (lists && !compact && threadIdx.x == 0) gst(B->gclear + parity, 1u);
 
     // per mesh node: interpolate, drag, integrate, spread
     for (int i = threadIdx.x; i < nn; i += blockDim.x) {
@@ -702,7 +740,7 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
                     const typename Acc<P>::T az = Acc<P>::convert(wk * dgz, B->fp_scale, flags);
                     const int qk = ((dz ? iz1 : iz0) * nyb + (dy ? iy1 : iy)) * nxb + (dx ? ix1 : ix);
                     if (bt && gld(bt + qk)) continue;  // an obstacle takes no share
-                    flags |= Acc<P>::flush(B, qk, ax, ay, az);
+                    flags |= Acc<P>::flush(B, parity, qk, ax, ay, az);
                 }
             }
         }
@@ -750,7 +788,7 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
             const int q = qn[c];
             if (bt && gld(bt + q)) continue;  // an obstacle takes no share
             const A val = gacc[k];
-            if (val != A(0)) gatomic_add((A*)B->G + 4 * (size_t)q + comp, val);
+            if (val != A(0)) gatomic_add((A*)B->G[parity] + 4 * (size_t)q + comp, val);
             if (comp == 0 && (gacc[3 * c] != A(0) || gacc[3 * c + 1] != A(0) || gacc[3 * c + 2] != A(0)))
                 gatomic_or(B->mask + (q >> 6), 1ull << (q & 63));
         }

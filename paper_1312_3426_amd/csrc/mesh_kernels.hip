@@ -26,6 +26,8 @@
 // several workgroups per object (triangles and edges in slices, then the
 // nodes in compact patches, with the area and volume summed over the slices
 // in a fixed order).
+#include <vector>
+
 #include "mesh_device.h"
 
 namespace oif {
@@ -38,24 +40,24 @@ using namespace dev;
 // Below FP64, registers are capped for six waves per SIMD: two objects of up
 // to 768 threads then share a compute unit (both meshes fit its LDS), so each
 // phase's loops over triangles, edges and nodes take fewer rounds.
-template <int P, bool USE_LDS, bool CONS, bool CPL = false>
+template <int P, bool USE_LDS, bool CONS, bool CPL, bool LISTS>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 1 : 6)))
 mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, int mark_next) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int bid = blockIdx.x;
-    mesh_object<P, USE_LDS, CONS, CPL>(objs[bid], smem, parity, mark_next);
+    mesh_object<P, USE_LDS, CONS, CPL, PH_ALL, LISTS>(objs[bid], smem, parity, mark_next);
 }
 
 // Meshes too large for LDS whose positions fit there, split over several
 // workgroups per object: the elements launch (PH_ELEMENTS) and then the nodes
 // launch (PH_NODES), one workgroup per (object, slice) in `work`.
-template <int P, bool CONS, int PH>
+template <int P, bool CONS, int PH, bool LISTS>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 1 : 6)))
 mesh_split_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, const int2* __restrict__ work, int parity,
                   int mark_next) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 w = work[blockIdx.x];
-    mesh_object<P, false, CONS, true, PH>(objs[w.x], smem, parity, mark_next, w.y);
+    mesh_object<P, false, CONS, true, PH, LISTS>(objs[w.x], smem, parity, mark_next, w.y);
 }
 
 // Touch bits of a step of parity `parity` from the current positions (split
@@ -91,45 +93,66 @@ diag_mesh_kernel(const ObjDev<R>* __restrict__ objs, double* __restrict__ part) 
     }
 }
 
-template <int P>
-hipError_t launch_mesh_p(const MeshLaunch& L) {
+template <int P, bool LISTS>
+hipError_t launch_mesh_pl(const MeshLaunch& L) {
     typedef typename Prec<P>::R R;
     const ObjDev<R>* objs = (const ObjDev<R>*)L.objs;
     const dim3 g(L.nobj), b(L.block);
     if (L.work) {
         const dim3 gw(L.nwork);
         if (L.conservative) {
-            hipLaunchKernelGGL((mesh_split_kernel<P, true, PH_ELEMENTS>), gw, b, L.split_lds, L.stream, objs, L.work,
-                               L.parity, L.mark_next);
-            hipLaunchKernelGGL((mesh_split_kernel<P, true, PH_NODES>), gw, b, L.split_lds, L.stream, objs, L.work,
-                               L.parity, L.mark_next);
-        } else {
-            hipLaunchKernelGGL((mesh_split_kernel<P, false, PH_ELEMENTS>), gw, b, L.split_lds, L.stream, objs,
+            hipLaunchKernelGGL((mesh_split_kernel<P, true, PH_ELEMENTS, LISTS>), gw, b, L.split_lds, L.stream, objs,
                                L.work, L.parity, L.mark_next);
-            hipLaunchKernelGGL((mesh_split_kernel<P, false, PH_NODES>), gw, b, L.split_lds, L.stream, objs, L.work,
-                               L.parity, L.mark_next);
+            hipLaunchKernelGGL((mesh_split_kernel<P, true, PH_NODES, LISTS>), gw, b, L.split_lds, L.stream, objs,
+                               L.work, L.parity, L.mark_next);
+        } else {
+            hipLaunchKernelGGL((mesh_split_kernel<P, false, PH_ELEMENTS, LISTS>), gw, b, L.split_lds, L.stream, objs,
+                               L.work, L.parity, L.mark_next);
+            hipLaunchKernelGGL((mesh_split_kernel<P, false, PH_NODES, LISTS>), gw, b, L.split_lds, L.stream, objs,
+                               L.work, L.parity, L.mark_next);
         }
     } else if (L.lds_bytes > 0) {
         if (L.conservative)
-            hipLaunchKernelGGL((mesh_kernel<P, true, true>), g, b, L.lds_bytes, L.stream, objs, L.parity,
+            hipLaunchKernelGGL((mesh_kernel<P, true, true, false, LISTS>), g, b, L.lds_bytes, L.stream, objs, L.parity,
                                L.mark_next);
         else
-            hipLaunchKernelGGL((mesh_kernel<P, true, false>), g, b, L.lds_bytes, L.stream, objs, L.parity,
+            hipLaunchKernelGGL((mesh_kernel<P, true, false, false, LISTS>), g, b, L.lds_bytes, L.stream, objs, L.parity,
                                L.mark_next);
     } else if (L.cpl_lds_bytes > 0) {
         if (L.conservative)
-            hipLaunchKernelGGL((mesh_kernel<P, false, true, true>), g, b, L.cpl_lds_bytes, L.stream, objs,
+            hipLaunchKernelGGL((mesh_kernel<P, false, true, true, LISTS>), g, b, L.cpl_lds_bytes, L.stream, objs,
                                L.parity, L.mark_next);
         else
-            hipLaunchKernelGGL((mesh_kernel<P, false, false, true>), g, b, L.cpl_lds_bytes, L.stream, objs,
+            hipLaunchKernelGGL((mesh_kernel<P, false, false, true, LISTS>), g, b, L.cpl_lds_bytes, L.stream, objs,
                                L.parity, L.mark_next);
     } else {
         if (L.conservative)
-            hipLaunchKernelGGL((mesh_kernel<P, false, true>), g, b, 0, L.stream, objs, L.parity, L.mark_next);
+            hipLaunchKernelGGL((mesh_kernel<P, false, true, false, LISTS>), g, b, 0, L.stream, objs, L.parity,
+                               L.mark_next);
         else
-            hipLaunchKernelGGL((mesh_kernel<P, false, false>), g, b, 0, L.stream, objs, L.parity, L.mark_next);
+            hipLaunchKernelGGL((mesh_kernel<P, false, false, false, LISTS>), g, b, 0, L.stream, objs, L.parity,
+                               L.mark_next);
     }
     return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_mesh_p(const MeshLaunch& L) {
+    return L.lists ? launch_mesh_pl<P, true>(L) : launch_mesh_pl<P, false>(L);
+}
+
+// every membrane kernel variant that may take more than the default dynamic
+// LDS, for one precision
+template <int P, bool LISTS>
+void dynlds_kernels(std::vector<const void*>& v) {
+    v.push_back((const void*)mesh_kernel<P, true, false, false, LISTS>);
+    v.push_back((const void*)mesh_kernel<P, true, true, false, LISTS>);
+    v.push_back((const void*)mesh_kernel<P, false, false, true, LISTS>);
+    v.push_back((const void*)mesh_kernel<P, false, true, true, LISTS>);
+    v.push_back((const void*)mesh_split_kernel<P, false, PH_ELEMENTS, LISTS>);
+    v.push_back((const void*)mesh_split_kernel<P, true, PH_ELEMENTS, LISTS>);
+    v.push_back((const void*)mesh_split_kernel<P, false, PH_NODES, LISTS>);
+    v.push_back((const void*)mesh_split_kernel<P, true, PH_NODES, LISTS>);
 }
 
 }  // namespace
@@ -159,43 +182,16 @@ hipError_t launch_mesh(const MeshLaunch& L) {
 // Let the LDS-resident variants use up to `bytes` of dynamic LDS per workgroup.
 hipError_t mesh_set_max_lds(size_t bytes) {
     hipError_t e = hipSuccess;
-    const void* fns[16] = {(const void*)mesh_kernel<PREC_FP64, true, false>,
-                          (const void*)mesh_kernel<PREC_FP32, true, false>,
-                          (const void*)mesh_kernel<PREC_FP16, true, false>,
-                          (const void*)mesh_kernel<PREC_BF16, true, false>,
-                          (const void*)mesh_kernel<PREC_FP64, true, true>,
-                          (const void*)mesh_kernel<PREC_FP32, true, true>,
-                          (const void*)mesh_kernel<PREC_FP16, true, true>,
-                          (const void*)mesh_kernel<PREC_BF16, true, true>,
-                          (const void*)mesh_kernel<PREC_FP64, false, false, true>,
-                          (const void*)mesh_kernel<PREC_FP32, false, false, true>,
-                          (const void*)mesh_kernel<PREC_FP16, false, false, true>,
-                          (const void*)mesh_kernel<PREC_BF16, false, false, true>,
-                          (const void*)mesh_kernel<PREC_FP64, false, true, true>,
-                          (const void*)mesh_kernel<PREC_FP32, false, true, true>,
-                          (const void*)mesh_kernel<PREC_FP16, false, true, true>,
-                          (const void*)mesh_kernel<PREC_BF16, false, true, true>};
-    const void* split[16] = {(const void*)mesh_split_kernel<PREC_FP64, false, PH_ELEMENTS>,
-                             (const void*)mesh_split_kernel<PREC_FP32, false, PH_ELEMENTS>,
-                             (const void*)mesh_split_kernel<PREC_FP16, false, PH_ELEMENTS>,
-                             (const void*)mesh_split_kernel<PREC_BF16, false, PH_ELEMENTS>,
-                             (const void*)mesh_split_kernel<PREC_FP64, true, PH_ELEMENTS>,
-                             (const void*)mesh_split_kernel<PREC_FP32, true, PH_ELEMENTS>,
-                             (const void*)mesh_split_kernel<PREC_FP16, true, PH_ELEMENTS>,
-                             (const void*)mesh_split_kernel<PREC_BF16, true, PH_ELEMENTS>,
-                             (const void*)mesh_split_kernel<PREC_FP64, false, PH_NODES>,
-                             (const void*)mesh_split_kernel<PREC_FP32, false, PH_NODES>,
-                             (const void*)mesh_split_kernel<PREC_FP16, false, PH_NODES>,
-                             (const void*)mesh_split_kernel<PREC_BF16, false, PH_NODES>,
-                             (const void*)mesh_split_kernel<PREC_FP64, true, PH_NODES>,
-                             (const void*)mesh_split_kernel<PREC_FP32, true, PH_NODES>,
-                             (const void*)mesh_split_kernel<PREC_FP16, true, PH_NODES>,
-                             (const void*)mesh_split_kernel<PREC_BF16, true, PH_NODES>};
+    std::vector<const void*> fns;
+    dynlds_kernels<PREC_FP64, false>(fns);
+    dynlds_kernels<PREC_FP32, false>(fns);
+    dynlds_kernels<PREC_FP16, false>(fns);
+    dynlds_kernels<PREC_BF16, false>(fns);
+    dynlds_kernels<PREC_FP64, true>(fns);
+    dynlds_kernels<PREC_FP32, true>(fns);
+    dynlds_kernels<PREC_FP16, true>(fns);
+    dynlds_kernels<PREC_BF16, true>(fns);
     for (const void* f : fns) {
-        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (r != hipSuccess) e = r;
-    }
-    for (const void* f : split) {
         hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (r != hipSuccess) e = r;
     }

@@ -7,11 +7,15 @@
 //          64 consecutive nodes, each tile [19][64] (value (i, p) at element
 //          ((p / 64) * 19 + i) * 64 + p % 64, N rounded up to whole tiles);
 //          the step reads f[parity] and writes f[parity ^ 1]
-//   G      coupling force density, [N][4] (x, y, z, unused: one 32-byte slot
-//          per node): double (FP64 form) or int64 fixed point with resolution
-//          2^-e (FP32 forms, order-independent sums)
+//   G[2]   coupling force density per step parity (a step of parity k spreads
+//          into G[k]), [N][4] (x, y, z, unused: one 32-byte slot per node):
+//          double (FP64 form) or int64 fixed point with resolution 2^-e (FP32
+//          forms, order-independent sums).  The lattice kernel only reads it:
+//          each membrane workgroup keeps the list of slots it added to and
+//          zeroes them in the next step, when the lattice kernel is done with
+//          them (gclear covers a workgroup that spread corner by corner)
 //   mask   one bit per node, set where G is non-zero; the lattice kernel reads
-//          G only where a bit is set and clears both
+//          G only where a bit is set and clears the bit
 //   X, V   mesh node positions (absolute, unwrapped, FP64 in every form, so
 //          that edge lengths and areas near their relaxed values do not lose
 //          their digits to position round-off; an integer per-object anchor is
@@ -36,7 +40,16 @@ struct BoxDev {
     unsigned div_nx, div_ny;
     int sh_nx, sh_ny;
     void* f[2];
-    void* G;
+    void* G[2];
+    // [2] per step parity, used when the membrane kernel clears G: set when a
+    // workgroup of that step spread without a list of its slots (corner by
+    // corner); the lattice kernel then clears G[parity] where it reads it.
+    // Reset by the membrane launch of the next step.
+    unsigned* gclear;
+    // 1: the membrane workgroups keep lists of the slots they add to and zero
+    // them one step later (G[0] and G[1] distinct); 0: they keep none and the
+    // lattice kernel clears G where it reads it (G[0] == G[1])
+    int g_by_mesh;
     unsigned long long* mask;
     // Split (overlapped) stepping, double-buffered by population parity:
     // touch[k] has one bit per node inside some mesh node's 2x2x2 stencil at
@@ -177,6 +190,9 @@ struct ObjDev {
     real fext[3];
     double mass;
     unsigned char* scratch; // global stand-in for LDS when the mesh does not fit
+    // slots of G this object's workgroups added to, per step parity and slice:
+    // [2][nslice][1 + ccap] ints (a count, then lattice node indices)
+    int* qsave;
 };
 
 // ---- soft-sphere repulsion ---------------------------------------------------
@@ -226,7 +242,7 @@ struct RepDev {
 enum : int {
     LB_ALL = 0,      // every node (coupling force read where the mask says so)
     LB_FREE = 1,     // only nodes whose touch bit (touch[parity]) is clear
-    LB_TOUCHED = 2,  // only nodes whose touch bit is set; clears touch[parity], mask and G
+    LB_TOUCHED = 2,  // only nodes whose touch bit is set; clears touch[parity] and the mask
 };
 
 struct LbLaunch {
@@ -270,6 +286,7 @@ struct MeshLaunch {
     const int2* work;
     int nwork;
     size_t split_lds;
+    int lists;             // some box of the launch has the membrane kernel clear G
 };
 hipError_t launch_mesh(const MeshLaunch& L);
 

@@ -363,7 +363,9 @@ struct oif_ctx {
     int N = 0;
     size_t st_size = 0;
     void* f[2] = {nullptr, nullptr};
-    void* G = nullptr;
+    void* G = nullptr;          // coupling force: [N][4] 8-byte words, [2][N][4] once the membrane kernel clears it
+    size_t G_bytes = 0;
+    unsigned* gclear = nullptr; // [2] corner-by-corner flags (BoxDev::gclear)
     unsigned long long* mask = nullptr;
     unsigned long long* touch[2] = {nullptr, nullptr};
     unsigned* status = nullptr;
@@ -405,6 +407,7 @@ struct oif_ctx {
     // device mesh
     std::vector<DevBuf> tbufs;  // per-template arrays
     DevBuf tmpl_dev, obj_dev, X_dev, V_dev, F_dev, geo_dev, scratch_dev;
+    DevBuf qsave_dev;           // per object: the G slots its workgroups added to (ObjDev::qsave)
     std::vector<unsigned char> obj_host; // ObjDev<real> array as uploaded (sorted)
     int n_lds_obj = 0;          // objects [0, n_lds_obj) use LDS, the rest global scratch
     int n_split_obj = 0;        // the next n_split_obj run split over several workgroups each
@@ -458,6 +461,7 @@ struct oif_batch {
     DevBuf split_work;  // (object index within the split group, slice)
     int n_split_work = 0;
     size_t p_cpl_need = 0;  // persistent form: coupling area of split and CPL objects
+    int any_lists = 0;      // some box has the membrane kernel clear its coupling force
     // the work list holds the boxes grouped by lattice-kernel variant
     // (obstacles, MRT collision): one launch per group
     int var_off[5] = {0, 0, 0, 0, 0};
@@ -794,6 +798,19 @@ int upload_mesh_t(oif_ctx* c) {
         }
     }
     if ((rc = dev_alloc(c, c->scratch_dev, scratch_total))) return rc;
+    // slot lists of G (two step parities, one per slice) and clean force
+    // buffers: the lists of the objects as they were are gone
+    size_t qtotal = 0;
+    for (int i : order) {
+        const Template& T = c->tmpl[c->obj[i].tid];
+        qtotal += 2 * (size_t)T.nslice * ((size_t)T.ccap + 1);
+    }
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    HIPCALL(c, hipStreamSynchronize(c->side));
+    if ((rc = dev_alloc(c, c->qsave_dev, 4 * qtotal + 16))) return rc;
+    HIPCALL(c, hipMemset(c->qsave_dev.p, 0, 4 * qtotal + 16));
+    HIPCALL(c, hipMemset(c->G, 0, c->G_bytes));
+    HIPCALL(c, hipMemset(c->gclear, 0, 2 * sizeof(unsigned)));
     {  // the split launches' workgroups: (object index within the group, slice)
         std::vector<int2> w;
         for (int k = 0; k < c->n_split_obj; ++k) {
@@ -809,7 +826,7 @@ int upload_mesh_t(oif_ctx* c) {
     }
     if ((rc = setup_repulsion(c, sizeof(real)))) return rc;
     std::vector<ObjDev<real>> od(c->obj.size());
-    size_t soff = 0;
+    size_t soff = 0, qoff = 0;
     for (size_t k = 0; k < order.size(); ++k) {
         const Object& o = c->obj[order[k]];
         ObjDev<real>& D = od[k];
@@ -828,6 +845,11 @@ int upload_mesh_t(oif_ctx* c) {
         D.inv_mass = (real)(1.0 / o.mass);
         D.mass = o.mass;
         D.scratch = nullptr;
+        D.qsave = (int*)c->qsave_dev.p + qoff;
+        {
+            const Template& T = c->tmpl[o.tid];
+            qoff += 2 * (size_t)T.nslice * ((size_t)T.ccap + 1);
+        }
         if ((int)k >= c->n_lds_obj) {
             D.scratch = (unsigned char*)c->scratch_dev.p + soff;
             soff += scratch_bytes(order[k]);
@@ -877,6 +899,7 @@ int enqueue_mesh(oif_ctx* c, int par, hipStream_t s, int mark_next) {
     ml.conservative = c->any_conservative;
     ml.precision = c->d.precision;
     ml.stream = s;
+    ml.lists = c->box.g_by_mesh;
     if (c->n_lds_obj > 0) {
         ml.objs = c->obj_dev.p;
         ml.nobj = c->n_lds_obj;
@@ -1143,7 +1166,9 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     const size_t popb = pop_bytes(cp);
     const size_t nmask = ((size_t)N + 63) / 64;
     int rc = OIF_OK;
-    if ((rc = alloc(&c->f[0], popb)) || (rc = alloc(&c->f[1], popb)) || (rc = alloc(&c->G, 32 * (size_t)N)) ||
+    c->G_bytes = 32 * (size_t)N;
+    if ((rc = alloc(&c->f[0], popb)) || (rc = alloc(&c->f[1], popb)) || (rc = alloc(&c->G, c->G_bytes)) ||
+        (rc = alloc((void**)&c->gclear, 2 * sizeof(unsigned))) ||
         (rc = alloc((void**)&c->mask, 8 * nmask)) || (rc = alloc((void**)&c->touch[0], 8 * nmask)) ||
         (rc = alloc((void**)&c->touch[1], 8 * nmask)) ||
         (rc = alloc((void**)&c->status, 256)) ||
@@ -1153,7 +1178,8 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     }
     if (hipMemsetAsync(c->f[0], 0, popb, c->stream) != hipSuccess ||
         hipMemsetAsync(c->f[1], 0, popb, c->stream) != hipSuccess ||
-        hipMemsetAsync(c->G, 0, 32 * (size_t)N, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->G, 0, c->G_bytes, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->gclear, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess ||
         hipMemsetAsync(c->mask, 0, 8 * nmask, c->stream) != hipSuccess ||
         hipMemsetAsync(c->touch[0], 0, 8 * nmask, c->stream) != hipSuccess ||
         hipMemsetAsync(c->touch[1], 0, 8 * nmask, c->stream) != hipSuccess ||
@@ -1168,7 +1194,11 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     div_magic(d.nx, &b.div_nx, &b.sh_nx);
     div_magic(d.ny, &b.div_ny, &b.sh_ny);
     b.f[0] = c->f[0]; b.f[1] = c->f[1];
-    b.G = c->G;
+    // the lattice kernel clears G (the default): one buffer for both parities
+    b.G[0] = c->G;
+    b.G[1] = c->G;
+    b.gclear = c->gclear;
+    b.g_by_mesh = 0;
     b.mask = c->mask;
     b.touch[0] = c->touch[0];
     b.touch[1] = c->touch[1];
@@ -1198,12 +1228,13 @@ int oif_destroy(oif_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
     if (c->side) (void)hipStreamSynchronize(c->side);
-    for (void* p : {c->f[0], c->f[1], c->G, (void*)c->mask, (void*)c->touch[0], (void*)c->touch[1],
+    for (void* p : {c->f[0], c->f[1], c->G, (void*)c->gclear, (void*)c->mask, (void*)c->touch[0], (void*)c->touch[1],
                     (void*)c->status, (void*)c->box_dev, c->bt_dev, c->link_dev, c->wall_dev})
         if (p) (void)hipFree(p);
     for (auto& b : c->tbufs) b.release();
     for (DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->F_dev, &c->geo_dev,
-                      &c->scratch_dev, &c->split_work, &c->part_dev, &c->diag_out, &c->rep_desc, &c->rep_pos,
+                      &c->scratch_dev, &c->split_work, &c->qsave_dev, &c->part_dev, &c->diag_out, &c->rep_desc,
+                      &c->rep_pos,
                       &c->rep_cell,
                       &c->rep_cnt, &c->rep_cursor, &c->rep_bsum, &c->rep_list, &c->rep_spos, &c->rep_stype,
                       &c->rep_frep, &c->rep_type, &c->rep_shape})
@@ -1725,6 +1756,47 @@ int oif_set_lb_loads(oif_ctx* c, int nontemporal) {
 
 namespace {
 
+// Who clears G.  The lattice kernel (0): one buffer serves both step parities
+// (the slots a step spreads to are the ones it reads and clears, and they stay
+// in cache from step to step).  The membrane kernel (1): a buffer per parity,
+// so that the slots a step spread to can be zeroed while the next step
+// spreads into the other one.  The switch zeroes G and the slot lists (they
+// are laid out per mode).
+int set_g_mode(oif_ctx* c, int by_membrane) {
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    HIPCALL(c, hipStreamSynchronize(c->side));
+    if (by_membrane && c->G_bytes < 64 * (size_t)c->N) {  // the second parity's buffer
+        void* g = nullptr;
+        if (hipMalloc(&g, 64 * (size_t)c->N) != hipSuccess) return fail(c, OIF_E_NOMEM, "hipMalloc of G failed");
+        (void)hipFree(c->G);
+        c->G = g;
+        c->G_bytes = 64 * (size_t)c->N;
+        c->box.G[0] = c->G;
+    }
+    c->box.g_by_mesh = by_membrane;
+    c->box.G[1] = by_membrane ? (void*)((unsigned char*)c->G + 32 * (size_t)c->N) : c->G;
+    HIPCALL(c, hipMemset(c->G, 0, c->G_bytes));
+    HIPCALL(c, hipMemset(c->gclear, 0, 2 * sizeof(unsigned)));
+    if (c->qsave_dev.p) HIPCALL(c, hipMemset(c->qsave_dev.p, 0, c->qsave_dev.n));
+    HIPCALL(c, hipMemcpy(c->box_dev, &c->box, sizeof(BoxDev), hipMemcpyHostToDevice));
+    return OIF_OK;
+}
+
+}  // namespace
+
+int oif_set_force_clear(oif_ctx* c, int by_membrane) {
+    if (!c) return OIF_E_ARG;
+    if (by_membrane != 0 && by_membrane != 1) return fail(c, OIF_E_ARG, "by_membrane must be 0 or 1");
+    if (c->box.g_by_mesh == by_membrane) return OIF_OK;
+    const int rc = set_g_mode(c, by_membrane);
+    if (rc) return rc;
+    c->mesh_dirty = true;  // batches holding this box copy it again
+    drop_graph(c);
+    return OIF_OK;
+}
+
+namespace {
+
 int read_pops(oif_ctx* c, double* out, int deviations) {
     if (!c || !out) return OIF_E_ARG;
     double* tmp = nullptr;
@@ -1832,10 +1904,11 @@ int oif_info(oif_ctx* c, oif_info_t* info) {
     info->n_nodes = c->N;
     info->n_mesh_nodes = c->M;
     info->steps_done = c->steps;
-    long long bytes = 2 * (long long)pop_bytes(c) + 32LL * c->N + 8LL * ((c->N + 63) / 64);
+    long long bytes = 2 * (long long)pop_bytes(c) + (long long)c->G_bytes + 8LL * ((c->N + 63) / 64);
     for (auto& b : c->tbufs) bytes += (long long)b.n;
     for (const DevBuf* b : {&c->tmpl_dev, &c->obj_dev, &c->X_dev, &c->V_dev, &c->F_dev, &c->geo_dev,
-                            &c->scratch_dev, &c->rep_pos, &c->rep_cell, &c->rep_cnt, &c->rep_cursor, &c->rep_bsum,
+                            &c->scratch_dev, &c->qsave_dev, &c->rep_pos, &c->rep_cell, &c->rep_cnt, &c->rep_cursor,
+                            &c->rep_bsum,
                             &c->rep_list, &c->rep_spos, &c->rep_stype, &c->rep_frep, &c->rep_type, &c->rep_shape})
         bytes += (long long)b->n;
     info->device_bytes = bytes;
@@ -1848,6 +1921,7 @@ int oif_info(oif_ctx* c, oif_info_t* info) {
     info->lds_objects = c->n_lds_obj;
     info->cpl_objects = c->n_cpl_obj;
     info->cpl_lds_bytes = (long long)c->cpl_need;
+    info->force_clear_by_membrane = c->box.g_by_mesh;
     info->split_objects = c->n_split_obj;
     info->split_workgroups = c->n_split_work;
     info->split_lds_bytes = (long long)c->split_need;
@@ -1970,7 +2044,7 @@ std::string tune_key(int prec, const std::vector<std::array<int, 3>>& dims, long
     return k.str();
 }
 
-bool cache_lookup(const char* path, const std::string& key, int out[4]) {
+bool cache_lookup(const char* path, const std::string& key, int out[5]) {
     if (!path) return false;
     std::ifstream f(path);
     if (!f) return false;
@@ -1980,35 +2054,37 @@ bool cache_lookup(const char* path, const std::string& key, int out[4]) {
     const std::string pat = "\"" + key + "\": [";
     const size_t p = s.find(pat);
     if (p == std::string::npos) return false;
-    int v[4];
-    if (std::sscanf(s.c_str() + p + pat.size(), "%d, %d, %d, %d", &v[0], &v[1], &v[2], &v[3]) != 4) return false;
-    for (int k = 0; k < 4; ++k) out[k] = v[k];
+    int v[5];
+    if (std::sscanf(s.c_str() + p + pat.size(), "%d, %d, %d, %d, %d", &v[0], &v[1], &v[2], &v[3], &v[4]) != 5)
+        return false;
+    for (int k = 0; k < 5; ++k) out[k] = v[k];
     return true;
 }
 
-// Entries are [lb_block, mesh_block, xcd_remap, nontemporal]; entries of
-// another form are dropped (and tuned again when asked for).
-void cache_store(const char* path, const std::string& key, const int v[4]) {
+// Entries are [lb_block, mesh_block, xcd_remap, nontemporal, force clear by
+// the membrane kernel]; entries of another form are dropped (and tuned again
+// when asked for).
+void cache_store(const char* path, const std::string& key, const int v[5]) {
     if (!path) return;
-    std::map<std::string, std::array<int, 4>> entries;
+    std::map<std::string, std::array<int, 5>> entries;
     {
         std::ifstream f(path);
         std::string line;
         while (std::getline(f, line)) {
             const size_t a = line.find('"'), b = line.find("\": [");
             if (a == std::string::npos || b == std::string::npos || b <= a) continue;
-            std::array<int, 4> e{};
-            if (std::sscanf(line.c_str() + b + 4, "%d, %d, %d, %d", &e[0], &e[1], &e[2], &e[3]) == 4)
+            std::array<int, 5> e{};
+            if (std::sscanf(line.c_str() + b + 4, "%d, %d, %d, %d, %d", &e[0], &e[1], &e[2], &e[3], &e[4]) == 5)
                 entries[line.substr(a + 1, b - a - 1)] = e;
         }
     }
-    entries[key] = {v[0], v[1], v[2], v[3]};
+    entries[key] = {v[0], v[1], v[2], v[3], v[4]};
     std::ofstream f(path);
     f << "{\n";
     size_t i = 0;
     for (auto& kv : entries) {
         f << "  \"" << kv.first << "\": [" << kv.second[0] << ", " << kv.second[1] << ", " << kv.second[2] << ", "
-          << kv.second[3] << "]";
+          << kv.second[3] << ", " << kv.second[4] << "]";
         f << (++i < entries.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -2070,10 +2146,11 @@ extern "C" int oif_autotune(oif_ctx* c, const char* cache_path) {
     int rc = sync_mesh(c);
     if (rc) return rc;
     const std::string key = tune_key(c->d.precision, {{c->d.nx, c->d.ny, c->d.nz}}, (long long)c->obj.size(), c->M);
-    int best[4];
+    int best[5];
     if (cache_lookup(cache_path, key, best)) {
         rc = oif_set_launch(c, best[0], best[1], best[2]);
-        return rc ? rc : oif_set_lb_loads(c, best[3]);
+        if (!rc) rc = oif_set_lb_loads(c, best[3]);
+        return rc ? rc : oif_set_force_clear(c, best[4]);
     }
     Snapshot s;
     if ((rc = snapshot(c, s, false))) return rc;
@@ -2082,6 +2159,7 @@ extern "C" int oif_autotune(oif_ctx* c, const char* cache_path) {
     const int reps = 6;  // even: parity is unchanged after each trial
     double best_lb = 1e300, best_mesh = 1e300;
     best[0] = c->lb_block; best[1] = c->mesh_block; best[2] = c->remap; best[3] = c->lb_nt;
+    best[4] = c->box.g_by_mesh;
     for (int nt : {0, 1})
         for (int lb : {128, 256, 512, 1024})
             for (int rm : {0, 1}) {
@@ -2103,6 +2181,20 @@ extern "C" int oif_autotune(oif_ctx* c, const char* cache_path) {
             if (tm < best_mesh) { best_mesh = tm; best[1] = mb; }
         }
     c->mesh_block = best[1];
+    if (!c->obj.empty()) {
+        // who clears G: the lattice kernel where it reads it, or the membrane
+        // kernel from its slot lists one step later (the step time decides)
+        double best_step = 1e300;
+        const int g0 = c->box.g_by_mesh;
+        for (int g : {0, 1}) {
+            if ((rc = set_g_mode(c, g))) return rc;
+            double tl, tm;
+            if ((rc = time_steps(c, reps, &tl, &tm))) return rc;
+            if (tl + tm < best_step) { best_step = tl + tm; best[4] = g; }
+        }
+        if ((rc = set_g_mode(c, best[4]))) return rc;
+        if (best[4] != g0) c->mesh_dirty = true;  // batches copy the box again
+    }
     c->overlap = overlap;
     if ((rc = snapshot(c, s, true))) return rc;
     c->host_stale = c->M > 0;
@@ -2204,6 +2296,8 @@ int batch_build(oif_batch* b) {
     b->cpl_need = 0;
     b->p_cpl_need = 0;
     b->any_conservative = 0;
+    b->any_lists = 0;
+    for (oif_ctx* c : b->ctx) b->any_lists |= c->box.g_by_mesh;
     std::vector<int2> sw;  // split launches' workgroups
     for (oif_ctx* c : b->ctx)
         for (const Template& T : c->tmpl) b->any_conservative |= tmpl_conservative(T);
@@ -2346,6 +2440,7 @@ int batch_enqueue(oif_batch* b, int n, int parity0, hipStream_t s, std::vector<h
         ml.precision = b->precision;
         ml.conservative = b->any_conservative;
         ml.stream = s;
+        ml.lists = b->any_lists;
         if (b->n_lds_obj > 0) {
             ml.objs = b->obj_dev.p;
             ml.nobj = b->n_lds_obj;
@@ -2577,7 +2672,7 @@ int oif_batch_autotune(oif_batch* b, const char* cache_path) {
         M += c->M;
     }
     const std::string key = tune_key(b->precision, dims, nobj, M);
-    int best[4] = {b->lb_block, b->mesh_block, b->remap, b->lb_nt};
+    int best[5] = {b->lb_block, b->mesh_block, b->remap, b->lb_nt, 0};
     if (cache_lookup(cache_path, key, best)) {
         const int rc = oif_batch_set_launch(b, best[0], best[1], best[2]);
         return rc ? rc : oif_batch_set_lb_loads(b, best[3]);

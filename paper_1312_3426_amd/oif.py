@@ -58,7 +58,7 @@ class Info(C.Structure):
                 ("max_lds", C.c_longlong), ("lds_objects", C.c_int), ("overlap", C.c_int),
                 ("integrator", C.c_int), ("lb_nontemporal", C.c_int), ("cpl_objects", C.c_int),
                 ("cpl_lds_bytes", C.c_longlong), ("split_objects", C.c_int), ("split_workgroups", C.c_int),
-                ("split_lds_bytes", C.c_longlong)]
+                ("split_lds_bytes", C.c_longlong), ("force_clear_by_membrane", C.c_int)]
 
 
 class Diag(C.Structure):
@@ -95,6 +95,7 @@ SIGNATURES = {
     "oif_set_overlap": (_i, [_vp, _i]),
     "oif_set_launch": (_i, [_vp, _i, _i, _i]),
     "oif_set_lb_loads": (_i, [_vp, _i]),
+    "oif_set_force_clear": (_i, [_vp, _i]),
     "oif_set_mrt": (_i, [_vp, _vp]),
     "oif_set_integrator": (_i, [_vp, _i]),
     "oif_set_soft_sphere": (_i, [_vp, _i, _i, _d, _d, _d, _d]),
@@ -269,6 +270,11 @@ class Context:
     def set_lb_loads(self, nontemporal: bool):
         """Population reads of the lattice kernel non-temporal (True) or ordinary."""
         self._chk(lib().oif_set_lb_loads(self.h, int(bool(nontemporal))))
+
+    def set_force_clear(self, by_membrane: bool):
+        """Coupling force cleared by the membrane kernel from its slot lists
+        (True) or by the lattice kernel where it reads it (False)."""
+        self._chk(lib().oif_set_force_clear(self.h, int(bool(by_membrane))))
 
     def set_mrt(self, gamma=None):
         """Multiple-relaxation-time collision with the factors (shear, bulk,

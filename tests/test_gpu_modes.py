@@ -136,7 +136,7 @@ def test_autotune_leaves_state_unchanged(oif, tmp_path):
             c.autotune(cache)
             i = c.info()
             assert i.lb_block in (128, 256, 512, 1024) and i.mesh_block % 64 == 0 and 64 <= i.mesh_block <= 1024
-            chosen = (i.lb_block, i.mesh_block, i.xcd_remap, i.lb_nontemporal)
+            chosen = (i.lb_block, i.mesh_block, i.xcd_remap, i.lb_nontemporal, i.force_clear_by_membrane)
         c.step(20)
         outs.append(state(c))
         c.close()
@@ -145,14 +145,16 @@ def test_autotune_leaves_state_unchanged(oif, tmp_path):
     for a, b in zip(*outs):
         assert rel(a, b) < 1e-6
     assert os.path.exists(cache) and "gfx950" in open(cache).read()
-    # a second context finds the shapes (and the read policy) in the cache
+    # a second context finds the shapes, the read policy and who clears the
+    # coupling force in the cache
     entries = json.load(open(cache))
-    assert all(len(v) == 4 for v in entries.values())
+    assert all(len(v) == 5 for v in entries.values())
     c = oif.Context.from_box(box, precision="fp32")
     c.set_lb_loads(not chosen[3])
+    c.set_force_clear(not chosen[4])
     c.autotune(cache)
     i = c.info()
-    assert (i.lb_block, i.mesh_block, i.xcd_remap, i.lb_nontemporal) == chosen
+    assert (i.lb_block, i.mesh_block, i.xcd_remap, i.lb_nontemporal, i.force_clear_by_membrane) == chosen
     c.close()
 
 
@@ -270,6 +272,62 @@ def test_large_meshes_vs_oracle(oif, orc, prec):
     say(f"   {bx.name} ({len(bx.objects)} cells, {i.lds_objects} in LDS): {fmt(res)}")
     assert all(v[3] for v in res.values())
     c.close()
+
+@pytest.mark.parametrize("case", ["batchbox", "pulled"])
+def test_force_clear_modes_bitwise(oif, case):
+    """The coupling force cleared by the lattice kernel (the default), by the
+    membrane kernel from its lists of slots one step later, or by one and then
+    the other, switching every two steps: the same bits (FP32), eagerly, under
+    graph capture and in a batch.  The batching box has 2562-node spheres split
+    over several workgroups (a list per slice) beside spheres in LDS; in the
+    pulled case one node 16 units out sends the sphere's coupling corner by
+    corner (no list: the lattice kernel clears G in that step)."""
+    say(f"[modes] force clear by lattice / membrane kernel, {case}")
+    box = synth.config_batch(n_boxes=1, steps=12)[0] if case == "batchbox" else synth.config_sphere_fp64(12)
+
+    def make(by_membrane=False):
+        c = oif.Context.from_box(box, precision="fp32")
+        if case == "pulled":
+            X, V = c.read_mesh(-1)
+            X[0, 0] += 16.0
+            c.write_mesh(-1, X, V)
+        c.set_force_clear(by_membrane)
+        assert c.info().force_clear_by_membrane == int(by_membrane)
+        return c
+
+    def state(c):
+        X, V = c.read_mesh(-1)
+        return c.read_deviations(), X, V
+
+    def same(a, b):
+        return all(np.array_equal(p, q) for p, q in zip(a, b))
+
+    ref = make()
+    ref.step(12)
+    want = state(ref)
+    ref.close()
+    a = make(True)
+    a.step(12)
+    assert same(want, state(a)), "membrane-side clearing differs"
+    a.close()
+    b = make()
+    for mode in (1, 0, 1, 1, 0, 0):
+        b.set_force_clear(bool(mode))
+        b.step(2)
+    assert same(want, state(b)), "switching between the two differs"
+    b.close()
+    g = make(True)
+    g.set_graph(4)
+    g.step(12)
+    assert same(want, state(g)), "membrane-side clearing under graph capture differs"
+    g.close()
+    c = make(True)
+    B = oif.Batch([c])
+    B.step(12)
+    B.close()
+    assert same(want, state(c)), "membrane-side clearing in a batch differs"
+    c.close()
+
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_oversize_meshes_vs_oracle(oif, orc, prec):
