@@ -101,6 +101,7 @@ def measure(oif, box, prec, steps, warmup, graph_steps=0, tune=None):
     info = ctx.info()
     out = dict(total_ms=t.total_ms, lb_ms=t.lb_ms, mesh_ms=t.mesh_ms, lb_block=info.lb_block,
                mesh_block=info.mesh_block, xcd_remap=info.xcd_remap, nt_loads=info.lb_nontemporal,
+               force_clear_by_membrane=info.force_clear_by_membrane,
                max_lds=info.max_lds,
                lds_objects=info.lds_objects)
     if graph_steps:
@@ -354,7 +355,8 @@ def scale_leg(oif, steps, warmup, tune):
                      "lb_frac": round(lb_bytes / (r["lb_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "touched_nodes": r["touched"], "full_step_bytes": full,
                      "full_step_frac": round(full / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "launch": {k: r[k] for k in ("lb_block", "mesh_block", "xcd_remap", "nt_loads")}}
+                     "launch": {k: r[k] for k in ("lb_block", "mesh_block", "xcd_remap", "nt_loads",
+                                                                      "force_clear_by_membrane")}}
     out["fp16_speedup"] = round(out["fp32"]["ms_per_step"] / out["fp16"]["ms_per_step"], 3)
     out["bytes_model"] = ("lattice 2 x 19 x b per node; full step adds 48 B per mesh node and "
                           "19 b + 24 B per touched lattice node (b = 4 FP32, 2 FP16)")
@@ -462,7 +464,8 @@ def main():
                    "mesh_nodes": M, "storage": "fp32", "tau": box.tau, "body_force": list(box.g),
                    "friction": box.friction, "moduli": {k: getattr(box.templates[0], k) for k in
                                                         ("ks", "kb", "kal", "kag", "kv")},
-                   "launch": {k: r32[k] for k in ("lb_block", "mesh_block", "xcd_remap", "nt_loads")}},
+                   "launch": {k: r32[k] for k in ("lb_block", "mesh_block", "xcd_remap", "nt_loads",
+                                                                      "force_clear_by_membrane")}},
         "timing": ("hipGraph replays of 50 steps, wall clock between device synchronisations, "
                    "one FP64 watchdog included" if use_graph else "eager launches, HIP events"),
         "eager": {"ms_per_step": round(ms_eager, 5), "mlups": round(N / (ms_eager * 1e-3) / 1e6, 2)},

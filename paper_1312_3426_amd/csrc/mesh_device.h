@@ -195,13 +195,13 @@ __device__ void mark_object(const double* pos, const int* order, int nv, const i
 // mesh nodes share, are LDS and not global atomics.
 // PH: the whole object in one workgroup (PH_ALL), or one of the two launches
 // that split it over T->nslice workgroups (meshes too large for LDS whose
-// positions fit there): PH_ELEMENTS, slice `slice` of the triangles and of the
-// edges, with the slice's area and volume sums left in the scratch;
-// PH_NODES, the forces, coupling and update of slice `slice` of the nodes (a
-// compact patch of the mesh, T->order), after the area and volume are summed
-// from the slices in a fixed order.  Split launches keep the triangle and edge
-// arrays in the scratch and the positions, the slice's forces and the coupling
-// area in LDS.
+// patches fit there): PH_SUMS, the area and volume sums of slice `slice` of
+// the triangles, left in the object's scratch; PH_PATCH, the forces, coupling
+// and update of patch `slice` of the nodes, run as an LDS-resident object on
+// the patch's sub-template (T->subs[slice]: the patch's nodes first, then the
+// other nodes its triangles and hinges reach, with the triangles and hinges
+// its nodes' gathers read and incidence lists in local numbering), after the
+// area and volume are summed from the slices in a fixed order.
 // LISTS: some box of the launch has the membrane kernel clear its coupling
 // force (BoxDev::g_by_mesh); without it the list code is left out.
 // The membrane forces, coupling and update of object O by the whole
@@ -210,37 +210,42 @@ template <int P, bool USE_LDS, bool CONS, bool CPL, int PH = PH_ALL, bool LISTS 
 __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O, unsigned char* smem, int parity,
                                             int mark_next, int slice = 0) {
     constexpr bool SPLIT = PH != PH_ALL;
-    static_assert(!SPLIT || (!USE_LDS && CPL), "split launches: mesh arrays in the scratch, coupling in LDS");
+    static_assert(PH != PH_SUMS || (!USE_LDS && CPL), "sums launch: positions alone in LDS");
+    static_assert(PH != PH_PATCH || (USE_LDS && !CPL), "patch launch: the patch's sub-template in LDS");
     typedef typename Prec<P>::S S;
     typedef typename Prec<P>::R R;
     __shared__ double red[16];
 
-    const gptr<const TmplDev<R>> T = (gptr<const TmplDev<R>>)O.t;
+    const gptr<const TmplDev<R>> Tp = (gptr<const TmplDev<R>>)O.t;  // the object's template
+    const gptr<const TmplDev<R>> T = PH == PH_PATCH ? (gptr<const TmplDev<R>>)(Tp->subs + slice) : Tp;
     const gptr<const BoxDev> B = (gptr<const BoxDev>)O.box;
     const int nv = T->nv, nt = T->nt, ne = T->ne;
     const int ucap = T->ucap, ccap = T->ccap;
     const int cons = CONS ? T->conservative : 0;
     const MeshLayout lay = mesh_layout(sizeof(R), nv, nt, ne, ucap, ccap, cons);
     unsigned char* base = USE_LDS ? smem : O.scratch;
-    // split launches: the slice's forces, then the positions in LDS
-    const size_t sxs = SPLIT ? split_xs_offset(sizeof(R), T->smax) : 0;
-    R* fs = SPLIT ? (R*)smem : (R*)(base + lay.fs);  // [nodes of the launch][3]: elastic force
-    double* xs = SPLIT ? (double*)(smem + sxs) : (double*)(base + lay.xs);  // [nv][3]: positions (forces phase)
+    R* fs = (R*)(base + lay.fs);      // [nodes of the launch][3]: elastic force
+    // [nv][3]: positions (forces phase); the sums launch keeps them alone in LDS
+    double* xs = PH == PH_SUMS ? (double*)smem : (double*)(base + lay.xs);
     R* tn = (R*)(base + lay.tn);      // [nt][4]: unit inward normal, area
     R* tr = (R*)(base + lay.tr);      // [nt]: (S - S0)/S
     R* se = (R*)(base + lay.se);      // [ne]: ks kappa strain / L
     R* fh = (R*)(base + lay.fh);      // [ne]: kb (theta - theta0)/theta0
     // coupling area: over the positions and the forces-phase arrays, or alone
-    // in LDS (CPL), or over the positions in LDS (split)
+    // in LDS (CPL)
     auto carea = [&](size_t off) -> unsigned char* {
-        return SPLIT ? smem + sxs + (off - lay.need) : ((!USE_LDS && CPL) ? smem + (off - lay.need) : base + off);
+        return (!USE_LDS && CPL) ? smem + (off - lay.need) : base + off;
     };
-    // the nodes this launch updates: all, or slice `slice` in T->order
+    // the nodes this launch updates: all, or the patch (its sub-template's
+    // first nodes; T->order maps them to the object's node numbers)
     const int nsl = SPLIT ? T->nslice : 1;
-    const int n0 = SPLIT ? gld(T->slice_off + slice) : 0;
-    const int nn = SPLIT ? gld(T->slice_off + slice + 1) - n0 : nv;
-    auto node_of = [&](int i) -> int { return SPLIT ? gld(T->order + n0 + i) : i; };
-    double* part = SPLIT ? (double*)(O.scratch + split_part_offset(lay)) : nullptr;  // [nslice][2]
+    const int n0 = 0;
+    const int nn = PH == PH_PATCH ? gld(T->slice_off + 1) : nv;
+    auto node_of = [&](int i) -> int { return PH == PH_PATCH ? gld(T->order + i) : i; };
+    // the slices' area and volume sums, after the object's mesh layout in its scratch
+    double* part = SPLIT ? (double*)(O.scratch + split_part_offset(mesh_layout(sizeof(R), Tp->nv, Tp->nt, Tp->ne,
+                                                                                ucap, ccap, cons)))
+                         : nullptr;  // [nslice][2]
 
     // When the membrane kernel clears G (B->g_by_mesh): the G slots this object
     // added to in the previous step (G[parity ^ 1], which the lattice kernel
@@ -252,7 +257,7 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     const bool lists = LISTS && B->g_by_mesh != 0;
     const int kq = T->nslice;
     const size_t qstride = (size_t)ccap + 1;
-    if (PH != PH_ELEMENTS && lists) {
+    if (PH != PH_SUMS && lists) {
         const int np = parity ^ 1;
         unsigned char* Gp = (unsigned char*)B->G[np];
         for (int sl = SPLIT ? slice : 0; sl < (SPLIT ? slice + 1 : kq); ++sl) {
@@ -282,7 +287,8 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     auto stage = [&](int k) -> double {
         return O.F ? gld(O.X + k) + (double)fmadd(gld(O.F + k), half_im, gld(O.V + k)) : gld(O.X + k);
     };
-    for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x) xs[k] = stage(k);
+    for (int k = threadIdx.x; k < 3 * nv; k += blockDim.x)
+        xs[k] = PH == PH_PATCH ? stage(3 * gld(T->order + k / 3) + k % 3) : stage(k);
     if (threadIdx.x == 0) {
         bbox[0] = bbox[1] = bbox[2] = INT_MAX;
         bbox[3] = bbox[4] = bbox[5] = INT_MIN;
@@ -293,10 +299,13 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     // (S - S0 is formed as (S^2 - S0^2)/(S + S0): the cancelling difference in
     // FP64 multiply-adds, the square root and division in the arithmetic type)
     double sdarea = 0.0, svol = 0.0;
-    if (PH != PH_NODES) {
-        const double r0x = xs[0], r0y = xs[1], r0z = xs[2];
-        const int t0 = SPLIT ? (int)((long long)nt * slice / nsl) : 0;
-        const int t1 = SPLIT ? (int)((long long)nt * (slice + 1) / nsl) : nt;
+    {
+        // node 0 of the object: the apex of the signed tetrahedra, and the
+        // origin the triangles' edge vectors are taken from in every launch
+        const double r0x = PH == PH_PATCH ? stage(0) : xs[0], r0y = PH == PH_PATCH ? stage(1) : xs[1],
+                     r0z = PH == PH_PATCH ? stage(2) : xs[2];
+        const int t0 = PH == PH_SUMS ? (int)((long long)nt * slice / nsl) : 0;
+        const int t1 = PH == PH_SUMS ? (int)((long long)nt * (slice + 1) / nsl) : nt;
         for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
             const int a = gld(T->tri + 3 * t), b = gld(T->tri + 3 * t + 1), c = gld(T->tri + 3 * t + 2);
             const double ax = xs[3 * a] - r0x, ay = xs[3 * a + 1] - r0y, az = xs[3 * a + 2] - r0z;
@@ -312,11 +321,13 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
             const R S = R(0.5) * len;
             const double S0 = gld(T->S0 + t);
             const R dS = (R)(0.25 * n2 - S0 * S0) / (S + (R)S0);
-            tn[4 * t + 0] = (R)nx_ / len;
-            tn[4 * t + 1] = (R)ny_ / len;
-            tn[4 * t + 2] = (R)nz_ / len;
-            tn[4 * t + 3] = S;
-            tr[t] = dS / S;
+            if (PH != PH_SUMS) {  // the sums launch keeps the sums only
+                tn[4 * t + 0] = (R)nx_ / len;
+                tn[4 * t + 1] = (R)ny_ / len;
+                tn[4 * t + 2] = (R)nz_ / len;
+                tn[4 * t + 3] = S;
+                tr[t] = dS / S;
+            }
             sdarea += (double)dS;
             // signed tetrahedron (node 0, a, b, c): inward orientation gives -6 V
             const double cxx = by * qz - bz * qy, cyy = bz * qx - bx * qz, czz = bx * qy - by * qx;
@@ -327,13 +338,14 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     if (PH == PH_ALL) {
         dSg = block_sum(sdarea, red);
         Vol = block_sum(svol, red);
-    } else if (PH == PH_ELEMENTS) {
+    } else if (PH == PH_SUMS) {
         dSg = block_sum(sdarea, red);
         Vol = block_sum(svol, red);
         if (threadIdx.x == 0) {
             gst(part + 2 * slice, dSg);
             gst(part + 2 * slice + 1, Vol);
         }
+        return;  // the patch launch reads the slices' sums
     } else {
         // the slices' sums, added in slice order (the same bits in every
         // workgroup of the object)
@@ -345,17 +357,15 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
         }
     }
     const double Sg = T->Sg0 + dSg;
-    if (PH != PH_ELEMENTS && threadIdx.x == 0 && slice == 0 && O.geo) {
+    if (threadIdx.x == 0 && slice == 0 && O.geo) {
         gst(O.geo, Sg);
         gst(O.geo + 1, Vol);
     }
 
     // 2. edges: stretching coefficient and bending magnitude of each hinge
     const bool do_s = T->ks != 0.0, do_b = T->kb != 0.0;
-    if (PH != PH_NODES && (do_s || do_b)) {
-        const int e0 = SPLIT ? (int)((long long)ne * slice / nsl) : 0;
-        const int e1 = SPLIT ? (int)((long long)ne * (slice + 1) / nsl) : ne;
-        for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
+    if (do_s || do_b) {
+        for (int e = threadIdx.x; e < ne; e += blockDim.x) {
             const int4 h = gld(T->hinge + e);  // (A, B, C, D): the edge is B -> C
             const double dx = xs[3 * h.z] - xs[3 * h.y], dy = xs[3 * h.z + 1] - xs[3 * h.y + 1],
                          dz = xs[3 * h.z + 2] - xs[3 * h.y + 2];
@@ -413,7 +423,6 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
             }
         }
     }
-    if (PH == PH_ELEMENTS) return;  // the node launch reads the slices' results
     __syncthreads();
 
     const R cg = (R)(-T->kag * dSg / Sg);             // global area coefficient
@@ -429,9 +438,10 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     unsigned flags = 0;
     int blo[3] = {INT_MAX, INT_MAX, INT_MAX}, bhi[3] = {INT_MIN, INT_MIN, INT_MIN};
 
-    // 3. nodes (fs is indexed by the node's place i in the launch's node set)
+    // 3. nodes (in the patch launch the patch's nodes are the sub-template's
+    // first nn nodes, so xs, the incidence lists and fs take the same index)
     for (int i = threadIdx.x; i < nn; i += blockDim.x) {
-        const int v = node_of(i);
+        const int v = i;
         const double px = xs[3 * v], py = xs[3 * v + 1], pz = xs[3 * v + 2];
         R Fx = 0, Fy = 0, Fz = 0;
         const int4 o0 = gld(T->n_off + v), o1 = gld(T->n_off + v + 1);

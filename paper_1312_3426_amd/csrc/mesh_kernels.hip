@@ -22,10 +22,10 @@
 // the update is the second half kick; the total force is kept for the next
 // step.
 // Meshes whose arrays do not fit in LDS use a per-object global scratch area
-// with the same layout; when their positions fit in LDS, they are split over
-// several workgroups per object (triangles and edges in slices, then the
-// nodes in compact patches, with the area and volume summed over the slices
-// in a fixed order).
+// with the same layout; when their patches fit in LDS, they are split over
+// several workgroups per object (the area and volume summed over slices of
+// the triangles, then each compact patch of nodes run as an LDS-resident
+// object on its own sub-template, the slices' sums added in a fixed order).
 #include <vector>
 
 #include "mesh_device.h"
@@ -48,16 +48,16 @@ mesh_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, int parity, in
     mesh_object<P, USE_LDS, CONS, CPL, PH_ALL, LISTS>(objs[bid], smem, parity, mark_next);
 }
 
-// Meshes too large for LDS whose positions fit there, split over several
-// workgroups per object: the elements launch (PH_ELEMENTS) and then the nodes
-// launch (PH_NODES), one workgroup per (object, slice) in `work`.
+// Meshes too large for LDS whose patches fit there, split over several
+// workgroups per object: the sums launch (PH_SUMS) and then the patch launch
+// (PH_PATCH), one workgroup per (object, slice) in `work`.
 template <int P, bool CONS, int PH, bool LISTS>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(P == PREC_FP64 ? 1 : 6)))
 mesh_split_kernel(const ObjDev<typename Prec<P>::R>* __restrict__ objs, const int2* __restrict__ work, int parity,
                   int mark_next) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 w = work[blockIdx.x];
-    mesh_object<P, false, CONS, true, PH, LISTS>(objs[w.x], smem, parity, mark_next, w.y);
+    mesh_object<P, PH == PH_PATCH, CONS, PH != PH_PATCH, PH, LISTS>(objs[w.x], smem, parity, mark_next, w.y);
 }
 
 // Touch bits of a step of parity `parity` from the current positions (split
@@ -101,14 +101,14 @@ hipError_t launch_mesh_pl(const MeshLaunch& L) {
     if (L.work) {
         const dim3 gw(L.nwork);
         if (L.conservative) {
-            hipLaunchKernelGGL((mesh_split_kernel<P, true, PH_ELEMENTS, LISTS>), gw, b, L.split_lds, L.stream, objs,
+            hipLaunchKernelGGL((mesh_split_kernel<P, true, PH_SUMS, LISTS>), gw, b, L.split_lds, L.stream, objs,
                                L.work, L.parity, L.mark_next);
-            hipLaunchKernelGGL((mesh_split_kernel<P, true, PH_NODES, LISTS>), gw, b, L.split_lds, L.stream, objs,
+            hipLaunchKernelGGL((mesh_split_kernel<P, true, PH_PATCH, LISTS>), gw, b, L.split_lds, L.stream, objs,
                                L.work, L.parity, L.mark_next);
         } else {
-            hipLaunchKernelGGL((mesh_split_kernel<P, false, PH_ELEMENTS, LISTS>), gw, b, L.split_lds, L.stream, objs,
+            hipLaunchKernelGGL((mesh_split_kernel<P, false, PH_SUMS, LISTS>), gw, b, L.split_lds, L.stream, objs,
                                L.work, L.parity, L.mark_next);
-            hipLaunchKernelGGL((mesh_split_kernel<P, false, PH_NODES, LISTS>), gw, b, L.split_lds, L.stream, objs,
+            hipLaunchKernelGGL((mesh_split_kernel<P, false, PH_PATCH, LISTS>), gw, b, L.split_lds, L.stream, objs,
                                L.work, L.parity, L.mark_next);
         }
     } else if (L.lds_bytes > 0) {
@@ -149,10 +149,10 @@ void dynlds_kernels(std::vector<const void*>& v) {
     v.push_back((const void*)mesh_kernel<P, true, true, false, LISTS>);
     v.push_back((const void*)mesh_kernel<P, false, false, true, LISTS>);
     v.push_back((const void*)mesh_kernel<P, false, true, true, LISTS>);
-    v.push_back((const void*)mesh_split_kernel<P, false, PH_ELEMENTS, LISTS>);
-    v.push_back((const void*)mesh_split_kernel<P, true, PH_ELEMENTS, LISTS>);
-    v.push_back((const void*)mesh_split_kernel<P, false, PH_NODES, LISTS>);
-    v.push_back((const void*)mesh_split_kernel<P, true, PH_NODES, LISTS>);
+    v.push_back((const void*)mesh_split_kernel<P, false, PH_SUMS, LISTS>);
+    v.push_back((const void*)mesh_split_kernel<P, true, PH_SUMS, LISTS>);
+    v.push_back((const void*)mesh_split_kernel<P, false, PH_PATCH, LISTS>);
+    v.push_back((const void*)mesh_split_kernel<P, true, PH_PATCH, LISTS>);
 }
 
 }  // namespace

@@ -106,10 +106,16 @@ struct TmplDev {
     int ccap;              // touched lattice nodes an object may have in LDS
     // Split launches (meshes too large for LDS): nslice workgroups per object;
     // slice k updates the nodes order[slice_off[k] .. slice_off[k + 1]), a
-    // compact patch of the reference shape, of at most smax nodes.
+    // compact patch of the reference shape, of at most smax nodes, through its
+    // sub-template subs[k]: the patch's nodes (numbered 0 .. slice_off[1] - 1
+    // there) and the other nodes its triangles and hinges reach, those
+    // triangles and hinges, and the incidence lists of the patch's nodes, all
+    // in local numbering; its order maps local node numbers to the object's.
+    // A sub-template keeps the template's nslice, smax, capacities and moduli.
     int nslice, smax;
     const int* order;      // [nv]
     const int* slice_off;  // [nslice + 1]
+    const TmplDev* subs;   // [nslice], null when nslice == 1
 };
 
 // Per-object LDS (or global scratch) layout of the membrane kernel, R = the
@@ -156,20 +162,12 @@ __host__ __device__ inline MeshLayout mesh_layout(size_t r, int nv, int nt, int 
 
 // Split launches (meshes too large for LDS whose positions fit there): the
 // phase a membrane launch runs (all of it, or one of the two split launches)
-enum { PH_ALL = 0, PH_ELEMENTS = 1, PH_NODES = 2 };
-// Their LDS: the forces of the largest node slice (R [smax][3]), then the
-// positions (FP64 [nv][3]) with the coupling area over them.  Their scratch:
-// the mesh layout (triangle and edge arrays at its offsets), then the area and
+enum { PH_ALL = 0, PH_SUMS = 1, PH_PATCH = 2 };
+// LDS of the split launches: the sums launch holds the object's positions
+// (FP64 [nv][3]); the patch launch the mesh layout of the patch's
+// sub-template.  The object's scratch: its mesh layout, then the area and
 // volume sums of each slice (double [nslice][2]).
-__host__ __device__ inline size_t split_xs_offset(size_t r, int smax) { return align16((size_t)smax * 3 * r); }
 __host__ __device__ inline size_t split_part_offset(const MeshLayout& L) { return align16(L.total); }
-__host__ __device__ inline size_t split_lds_bytes(size_t r, int nv, int nt, int ne, int ucap, int ccap, int cons,
-                                                  int smax) {
-    const MeshLayout L = mesh_layout(r, nv, nt, ne, ucap, ccap, cons);
-    const size_t coupling = align16(L.gacc + (size_t)ccap * 3 * 8) - L.need;
-    const size_t pos = (size_t)nv * 3 * sizeof(double);
-    return split_xs_offset(r, smax) + align16(pos > coupling ? pos : coupling);
-}
 
 template <typename real>
 struct ObjDev {
@@ -280,7 +278,7 @@ struct MeshLaunch {
                            // touch[parity ^ 1] (split stepping)
     int conservative;      // some object of the launch uses the conservative force model
     hipStream_t stream;
-    // split launches (work != null): split_lds_bytes of LDS, one workgroup per
+    // split launches (work != null): split_lds of LDS, one workgroup per
     // (object, slice) in work (object index into objs, slice); the elements
     // launch, then the nodes launch
     const int2* work;

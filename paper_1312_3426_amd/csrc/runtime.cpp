@@ -88,6 +88,9 @@ struct Template {
     // reference shape (recursive halving along the longest extent)
     int nslice = 1, smax = 0;
     std::vector<int> order, slice_off;
+    // nodes, triangles and hinges of each patch's sub-template (set when the
+    // template is uploaded)
+    std::vector<int> pnv, pnt, pne;
     std::vector<int> e_off, h_off, t_off;
     std::vector<std::array<int, 2>> e_inc;
     std::vector<int> h_inc, t_inc;
@@ -631,6 +634,213 @@ int setup_repulsion(oif_ctx* c, size_t real_bytes) {
     return OIF_OK;
 }
 
+// Device-format arrays of a template, or of one patch's sub-template (split
+// membrane launches); hinge and incidence entries hold everything the gather
+// needs, so a node's entries are independent loads.
+struct TArr {
+    int nv = 0, nt = 0, ne = 0;
+    std::vector<int> tri;           // [nt][3]
+    std::vector<int4> noff;         // [nv + 1] (edge, hinge, triangle) list offsets
+    std::vector<int2> einc;         // (neighbour, edge)
+    std::vector<int4> hinc;         // (hinge << 2 | role, T1, T2, 0)
+    std::vector<int4> tinc;         // (triangle, next vertex, vertex after that, 0)
+    std::vector<double> L0;         // [ne]
+    std::vector<int4> hv;           // [ne] (A, B, C, D)
+    std::vector<double> th, cs0;    // [ne], [ne][2]: theta0; cos, sin of theta0 - pi
+    std::vector<double> S0;         // [nt]
+    std::vector<double> hbar;       // [ne]
+    std::vector<int> order, slice_off;
+};
+
+TArr template_arrays(const Template& T) {
+    TArr A;
+    A.nv = T.nv;
+    A.nt = T.nt;
+    A.ne = T.ne;
+    A.tri = T.tri;
+    A.L0 = T.L0;
+    A.th = T.theta0;
+    A.S0 = T.S0;
+    A.hbar = T.hbar;
+    A.cs0.resize(2 * (size_t)T.ne);
+    for (int e = 0; e < T.ne; ++e) {
+        A.cs0[2 * e] = std::cos(T.theta0[e] - M_PI);
+        A.cs0[2 * e + 1] = std::sin(T.theta0[e] - M_PI);
+    }
+    A.hv.resize(T.ne);
+    for (int e = 0; e < T.ne; ++e) A.hv[e] = make_int4(T.hinge[e][0], T.hinge[e][1], T.hinge[e][2], T.hinge[e][3]);
+    A.noff.resize((size_t)T.nv + 1);
+    for (int v = 0; v <= T.nv; ++v) A.noff[v] = make_int4(T.e_off[v], T.h_off[v], T.t_off[v], 0);
+    A.einc.resize(T.e_inc.size());
+    for (size_t k = 0; k < T.e_inc.size(); ++k) A.einc[k] = make_int2(T.e_inc[k][0], T.e_inc[k][1]);
+    A.hinc.resize(T.h_inc.size());
+    for (size_t k = 0; k < T.h_inc.size(); ++k) {
+        const int e = T.h_inc[k] >> 2;
+        A.hinc[k] = make_int4(T.h_inc[k], T.hinge_tri[e][0], T.hinge_tri[e][1], 0);
+    }
+    A.tinc.resize(T.t_inc.size());
+    for (size_t k = 0; k < T.t_inc.size(); ++k) {
+        const int t = T.t_inc[k] >> 2, s3 = T.t_inc[k] & 3;
+        A.tinc[k] = make_int4(t, T.tri[3 * t + (s3 + 1) % 3], T.tri[3 * t + (s3 + 2) % 3], 0);
+    }
+    A.order = T.order;
+    A.slice_off = T.slice_off;
+    return A;
+}
+
+// Sub-template of patch k: the patch's nodes first (in slice order), then the
+// other nodes its triangles and hinges reach; the triangles and hinges the
+// patch nodes' gathers read; incidence lists of the patch nodes only, entry
+// for entry those of the template, renumbered (so a node's forces are summed
+// in the same order as in the whole template).
+TArr patch_arrays(const Template& T, const TArr& A, int k) {
+    TArr P;
+    std::vector<int> nl(T.nv, -1), tl(T.nt, -1), el(T.ne, -1), tris, edges;
+    auto addn = [&](int v) {
+        if (nl[v] < 0) {
+            nl[v] = (int)P.order.size();
+            P.order.push_back(v);
+        }
+    };
+    auto addt = [&](int t) {
+        if (tl[t] < 0) {
+            tl[t] = (int)tris.size();
+            tris.push_back(t);
+        }
+    };
+    auto adde = [&](int e) {
+        if (el[e] < 0) {
+            el[e] = (int)edges.size();
+            edges.push_back(e);
+        }
+    };
+    const int s0 = T.slice_off[k], s1 = T.slice_off[k + 1], np = s1 - s0;
+    for (int i = s0; i < s1; ++i) addn(T.order[i]);
+    for (int i = 0; i < np; ++i) {
+        const int v = P.order[i];
+        const int4 o0 = A.noff[v], o1 = A.noff[v + 1];
+        for (int q = o0.x; q < o1.x; ++q) adde(A.einc[q].y);
+        for (int q = o0.y; q < o1.y; ++q) {
+            adde(A.hinc[q].x >> 2);
+            addt(A.hinc[q].y);
+            addt(A.hinc[q].z);
+        }
+        for (int q = o0.z; q < o1.z; ++q) addt(A.tinc[q].x);
+    }
+    for (int t : tris)
+        for (int a = 0; a < 3; ++a) addn(A.tri[3 * t + a]);
+    for (int e : edges) {
+        addn(A.hv[e].x);
+        addn(A.hv[e].y);
+        addn(A.hv[e].z);
+        addn(A.hv[e].w);
+    }
+    P.nv = (int)P.order.size();
+    P.nt = (int)tris.size();
+    P.ne = (int)edges.size();
+    for (int t : tris) {
+        for (int a = 0; a < 3; ++a) P.tri.push_back(nl[A.tri[3 * t + a]]);
+        P.S0.push_back(A.S0[t]);
+    }
+    for (int e : edges) {
+        const int4 h = A.hv[e];
+        P.hv.push_back(make_int4(nl[h.x], nl[h.y], nl[h.z], nl[h.w]));
+        P.L0.push_back(A.L0[e]);
+        P.th.push_back(A.th[e]);
+        P.cs0.push_back(A.cs0[2 * e]);
+        P.cs0.push_back(A.cs0[2 * e + 1]);
+        P.hbar.push_back(A.hbar[e]);
+    }
+    P.noff.resize((size_t)P.nv + 1);
+    for (int i = 0; i < P.nv; ++i) {
+        P.noff[i] = make_int4((int)P.einc.size(), (int)P.hinc.size(), (int)P.tinc.size(), 0);
+        if (i >= np) continue;
+        const int v = P.order[i];
+        const int4 o0 = A.noff[v], o1 = A.noff[v + 1];
+        for (int q = o0.x; q < o1.x; ++q) P.einc.push_back(make_int2(nl[A.einc[q].x], el[A.einc[q].y]));
+        for (int q = o0.y; q < o1.y; ++q) {
+            const int4 h = A.hinc[q];
+            P.hinc.push_back(make_int4((el[h.x >> 2] << 2) | (h.x & 3), tl[h.y], tl[h.z], 0));
+        }
+        for (int q = o0.z; q < o1.z; ++q) {
+            const int4 r = A.tinc[q];
+            P.tinc.push_back(make_int4(tl[r.x], nl[r.y], nl[r.z], 0));
+        }
+    }
+    P.noff[P.nv] = make_int4((int)P.einc.size(), (int)P.hinc.size(), (int)P.tinc.size(), 0);
+    P.slice_off = {0, np};
+    return P;
+}
+
+template <typename V>
+size_t vbytes(const std::vector<V>& v) {
+    return (v.size() * sizeof(V) + 15) & ~(size_t)15;
+}
+
+size_t tarr_bytes(const TArr& A) {
+    return vbytes(A.tri) + vbytes(A.noff) + vbytes(A.einc) + vbytes(A.hinc) + vbytes(A.tinc) + vbytes(A.L0) +
+           vbytes(A.hv) + vbytes(A.th) + vbytes(A.cs0) + vbytes(A.S0) + vbytes(A.hbar) + vbytes(A.order) +
+           vbytes(A.slice_off);
+}
+
+// Copies A's arrays to host[..] and points D's arrays at dev[..] (the same
+// offsets in the device buffer the host image is copied to).
+template <typename real>
+void tarr_place(const TArr& A, unsigned char* host, unsigned char* dev, TmplDev<real>& D) {
+    size_t off = 0;
+    auto put = [&](const auto& v) -> const void* {
+        if (!v.empty()) std::memcpy(host + off, v.data(), v.size() * sizeof(v[0]));
+        const void* p = dev + off;
+        off += vbytes(v);
+        return p;
+    };
+    D.nv = A.nv;
+    D.nt = A.nt;
+    D.ne = A.ne;
+    D.tri = (const int*)put(A.tri);
+    D.n_off = (const int4*)put(A.noff);
+    D.e_inc = (const int2*)put(A.einc);
+    D.h_inc = (const int4*)put(A.hinc);
+    D.t_inc = (const int4*)put(A.tinc);
+    D.L0 = (const double*)put(A.L0);
+    D.hinge = (const int4*)put(A.hv);
+    D.theta0 = (const double*)put(A.th);
+    D.cs0 = (const double2*)put(A.cs0);
+    D.S0 = (const double*)put(A.S0);
+    D.hbar = (const double*)put(A.hbar);
+    D.order = (const int*)put(A.order);
+    D.slice_off = (const int*)put(A.slice_off);
+}
+
+template <typename real>
+void tmpl_scalars(const Template& T, TmplDev<real>& D) {
+    D.linear = T.k.stretch_law == OIF_STRETCH_LINEAR;
+    D.conservative = tmpl_conservative(T);
+    D.Sg0 = T.Sg0;
+    D.V0 = T.V0;
+    D.ks = T.k.ks;
+    D.kb = T.k.kb;
+    D.kal = T.k.kal;
+    D.kag = T.k.kag;
+    D.kv = T.k.kv;
+    D.ucap = T.ucap;
+    D.ccap = T.ccap;
+    D.nslice = T.nslice;
+    D.smax = T.smax;
+}
+
+// LDS per workgroup of the split launches of template T (the larger of the
+// sums launch's positions and the largest patch's layout); none when the
+// template has a single slice.
+size_t split_need_bytes(int precision, const Template& T) {
+    if (T.nslice <= 1 || T.pnv.empty()) return SIZE_MAX;
+    size_t need = align16((size_t)T.nv * 3 * sizeof(double));
+    for (int k = 0; k < T.nslice; ++k)
+        need = std::max(need, mesh_lds_bytes(precision, T.pnv[k], T.pnt[k], T.pne[k], T.ucap, T.ccap,
+                                             tmpl_conservative(T)));
+    return need;
+}
+
 template <typename real>
 int upload_mesh_t(oif_ctx* c) {
     // per-template arrays
@@ -638,73 +848,47 @@ int upload_mesh_t(oif_ctx* c) {
     c->tbufs.assign(c->tmpl.size(), DevBuf());
     std::vector<TmplDev<real>> td(c->tmpl.size());
     for (size_t t = 0; t < c->tmpl.size(); ++t) {
-        const Template& T = c->tmpl[t];
-        // one allocation, sub-arrays 16-byte aligned
-        std::vector<std::pair<const void*, size_t>> parts;
-        const std::vector<double>& L0 = T.L0;
-        const std::vector<double>& S0 = T.S0;
-        const std::vector<double>& th = T.theta0;
-        std::vector<double> cs0(2 * (size_t)T.ne);  // cos, sin of theta0 - pi
-        for (int e = 0; e < T.ne; ++e) {
-            cs0[2 * e] = std::cos(T.theta0[e] - M_PI);
-            cs0[2 * e + 1] = std::sin(T.theta0[e] - M_PI);
+        Template& T = c->tmpl[t];
+        const TArr A = template_arrays(T);
+        std::vector<TArr> pa;
+        if (T.nslice > 1)
+            for (int k = 0; k < T.nslice; ++k) pa.push_back(patch_arrays(T, A, k));
+        T.pnv.clear();
+        T.pnt.clear();
+        T.pne.clear();
+        for (const TArr& P : pa) {
+            T.pnv.push_back(P.nv);
+            T.pnt.push_back(P.nt);
+            T.pne.push_back(P.ne);
         }
-        std::vector<int4> hv(T.ne), noff((size_t)T.nv + 1), hinc(T.h_inc.size()), tinc(T.t_inc.size());
-        std::vector<int2> einc(T.e_inc.size());
-        for (int e = 0; e < T.ne; ++e)
-            hv[e] = make_int4(T.hinge[e][0], T.hinge[e][1], T.hinge[e][2], T.hinge[e][3]);
-        for (int v = 0; v <= T.nv; ++v) noff[v] = make_int4(T.e_off[v], T.h_off[v], T.t_off[v], 0);
-        for (size_t k = 0; k < T.e_inc.size(); ++k) einc[k] = make_int2(T.e_inc[k][0], T.e_inc[k][1]);
-        for (size_t k = 0; k < T.h_inc.size(); ++k) {
-            const int e = T.h_inc[k] >> 2;
-            hinc[k] = make_int4(T.h_inc[k], T.hinge_tri[e][0], T.hinge_tri[e][1], 0);
-        }
-        for (size_t k = 0; k < T.t_inc.size(); ++k) {
-            const int t = T.t_inc[k] >> 2, s3 = T.t_inc[k] & 3;
-            tinc[k] = make_int4(t, T.tri[3 * t + (s3 + 1) % 3], T.tri[3 * t + (s3 + 2) % 3], 0);
-        }
-        parts = {{T.tri.data(), T.tri.size() * 4},        {noff.data(), noff.size() * 16},
-                 {einc.data(), einc.size() * 8},          {hinc.data(), hinc.size() * 16},
-                 {tinc.data(), tinc.size() * 16},         {L0.data(), L0.size() * sizeof(double)},
-                 {hv.data(), hv.size() * 16},             {th.data(), th.size() * sizeof(double)},
-                 {cs0.data(), cs0.size() * sizeof(double)}, {S0.data(), S0.size() * sizeof(double)},
-                 {T.hbar.data(), T.hbar.size() * sizeof(double)}, {T.order.data(), T.order.size() * 4},
-                 {T.slice_off.data(), T.slice_off.size() * 4}};
-        std::vector<size_t> offs;
+        // one allocation: the template's arrays, each patch's arrays, then the
+        // patches' descriptors; sub-arrays 16-byte aligned
         size_t total = 0;
-        for (auto& p : parts) {
-            offs.push_back(total);
-            total += (p.second + 15) & ~(size_t)15;
+        const size_t off_main = total;
+        total += tarr_bytes(A);
+        std::vector<size_t> off_p;
+        for (const TArr& P : pa) {
+            off_p.push_back(total);
+            total += tarr_bytes(P);
         }
-        std::vector<unsigned char> host(total, 0);
-        for (size_t k = 0; k < parts.size(); ++k) std::memcpy(host.data() + offs[k], parts[k].first, parts[k].second);
+        const size_t off_subs = total;
+        total += pa.size() * sizeof(TmplDev<real>);
         int rc = dev_alloc(c, c->tbufs[t], total);
         if (rc) return rc;
-        HIPCALL(c, hipMemcpy(c->tbufs[t].p, host.data(), total, hipMemcpyHostToDevice));
         unsigned char* b = (unsigned char*)c->tbufs[t].p;
+        std::vector<unsigned char> host(total, 0);
         TmplDev<real>& D = td[t];
-        D.nv = T.nv; D.nt = T.nt; D.ne = T.ne;
-        D.linear = T.k.stretch_law == OIF_STRETCH_LINEAR;
-        D.tri = (const int*)(b + offs[0]);
-        D.n_off = (const int4*)(b + offs[1]);
-        D.e_inc = (const int2*)(b + offs[2]);
-        D.h_inc = (const int4*)(b + offs[3]);
-        D.t_inc = (const int4*)(b + offs[4]);
-        D.L0 = (const double*)(b + offs[5]);
-        D.hinge = (const int4*)(b + offs[6]);
-        D.theta0 = (const double*)(b + offs[7]);
-        D.cs0 = (const double2*)(b + offs[8]);
-        D.S0 = (const double*)(b + offs[9]);
-        D.hbar = (const double*)(b + offs[10]);
-        D.conservative = tmpl_conservative(T);
-        D.Sg0 = T.Sg0; D.V0 = T.V0;
-        D.ks = T.k.ks; D.kb = T.k.kb; D.kal = T.k.kal; D.kag = T.k.kag; D.kv = T.k.kv;
-        D.ucap = T.ucap;
-        D.ccap = T.ccap;
-        D.nslice = T.nslice;
-        D.smax = T.smax;
-        D.order = (const int*)(b + offs[11]);
-        D.slice_off = (const int*)(b + offs[12]);
+        tarr_place(A, host.data() + off_main, b + off_main, D);
+        tmpl_scalars(T, D);
+        D.subs = pa.empty() ? nullptr : (const TmplDev<real>*)(b + off_subs);
+        for (size_t k = 0; k < pa.size(); ++k) {
+            TmplDev<real> S{};
+            tarr_place(pa[k], host.data() + off_p[k], b + off_p[k], S);
+            tmpl_scalars(T, S);
+            S.subs = nullptr;
+            std::memcpy(host.data() + off_subs + k * sizeof(TmplDev<real>), &S, sizeof(S));
+        }
+        HIPCALL(c, hipMemcpy(c->tbufs[t].p, host.data(), total, hipMemcpyHostToDevice));
     }
     int rc = dev_alloc(c, c->tmpl_dev, td.size() * sizeof(TmplDev<real>));
     if (rc) return rc;
@@ -751,11 +935,7 @@ int upload_mesh_t(oif_ctx* c) {
         const Template& T = c->tmpl[c->obj[i].tid];
         return mesh_cpl_lds_bytes(c->d.precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T));
     };
-    auto split = [&](int i) {
-        const Template& T = c->tmpl[c->obj[i].tid];
-        return split_lds_bytes(c->d.precision == OIF_PREC_FP64 ? sizeof(double) : sizeof(float), T.nv, T.nt, T.ne,
-                               T.ucap, T.ccap, tmpl_conservative(T), T.smax);
-    };
+    auto split = [&](int i) { return split_need_bytes(c->d.precision, c->tmpl[c->obj[i].tid]); };
     auto group = [&](int i) {
         return need(i) <= budget ? 0 : (split(i) <= budget ? 1 : (cpl(i) <= budget ? 2 : 3));
     };
@@ -2278,8 +2458,7 @@ int batch_build(oif_batch* b) {
                             mesh_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T)),
                             mesh_cpl_lds_bytes(b->precision, T.nv, T.nt, T.ne, T.ucap, T.ccap,
                                                tmpl_conservative(T)),
-                            split_lds_bytes(b->precision == OIF_PREC_FP64 ? sizeof(double) : sizeof(float), T.nv,
-                                            T.nt, T.ne, T.ucap, T.ccap, tmpl_conservative(T), T.smax),
+                            split_need_bytes(b->precision, T),
                             (int)bi, T.nslice});
         }
     }
