@@ -329,6 +329,45 @@ def test_force_clear_modes_bitwise(oif, case):
     c.close()
 
 
+def test_split_meshes_overlap_bitwise(oif):
+    """Split stepping (the lattice update of the nodes outside every stencil
+    concurrent with the membrane launches) with 2562-node spheres split into
+    patches: each patch workgroup marks its own nodes' stencils for the next
+    step, and the result is the sequential step's, bit for bit (FP32)."""
+    say("[modes] overlap vs sequential, batching box with split meshes")
+    box = synth.config_batch(n_boxes=1, steps=20)[0]
+    outs = []
+    for ov in (False, True):
+        c = oif.Context.from_box(box, precision="fp32")
+        c.set_overlap(ov)
+        c.step(20)
+        assert c.info().split_objects > 0 and c.info().overlap == int(ov)
+        outs.append(state(c))
+        c.close()
+    assert same(*outs)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_split_meshes_verlet_vs_oracle(oif, orc, prec):
+    """Velocity Verlet with 2562-node spheres split into patches (the staged
+    half-step positions, the carried force written per patch) against the
+    oracle."""
+    say(f"[modes] split meshes with velocity Verlet vs oracle ({prec})")
+    bx = synth.config_batch(n_boxes=1, steps=20)[0]
+    bx.integrator = "verlet"
+    c = oif.Context.from_box(bx, precision=prec)
+    c.step(20)
+    i = c.info()
+    assert i.split_objects > 0 and i.integrator == 1
+    s = orc.System(bx)
+    X0 = s.X.copy()
+    s.run(20)
+    res = check(gpu_fields(c, bx.rho0, X0), oracle_fields(s, X0), prec, bx.rho0, max(bx.nx, bx.ny, bx.nz))
+    say(f"   {bx.name}: {fmt(res)}")
+    assert all(v[3] for v in res.values())
+    c.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_oversize_meshes_vs_oracle(oif, orc, prec):
     """A 10242-node sphere, whose positions alone exceed LDS, runs in one
