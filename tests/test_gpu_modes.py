@@ -327,6 +327,14 @@ def test_force_clear_modes_bitwise(oif, case):
     B.close()
     assert same(want, state(c)), "membrane-side clearing in a batch differs"
     c.close()
+    if case == "pulled":  # the persistent form runs meshes whole, as the single box does here
+        c = make(True)
+        B = oif.Batch([c])
+        B.set_persistent(True)
+        B.step(12)
+        B.close()
+        assert same(want, state(c)), "membrane-side clearing in the persistent form differs"
+        c.close()
 
 
 def test_split_meshes_overlap_bitwise(oif):
