@@ -35,6 +35,7 @@
 #ifndef OIF_H
 #define OIF_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -202,6 +203,23 @@ const char* oif_last_error(const oif_ctx* ctx);
  * instead of its own stream; NULL restores the own stream.  The caller keeps
  * the stream alive while it is bound. */
 int oif_bind_stream(oif_ctx* ctx, void* hip_stream);
+
+/* Bytes of each of the context's two population buffers (*bytes). */
+int oif_population_bytes(const oif_ctx* ctx, size_t* bytes);
+
+/* Keep the context's two population buffers (the stored deviations of the
+ * current and the next step, in the library's own tiled layout: opaque to the
+ * caller) in caller-owned device memory, e.g. two tensors allocated by
+ * PyTorch: f0 and f1 each of `bytes` >= oif_population_bytes, 256-byte
+ * aligned, disjoint, device memory of the context's device, with no work
+ * pending on them.  The current state is copied into them and the context's
+ * own buffers are freed; both NULL copies the state back into buffers of the
+ * context's own (bytes ignored).  While bound, the caller keeps the memory
+ * alive and leaves it alone; the context never frees it.  Captured graphs are
+ * dropped and batches holding the box take the new buffers at their next
+ * step.  Errors: OIF_E_ARG (one NULL, too small, misaligned, overlapping or
+ * not device memory of the device; nothing changes), OIF_E_NOMEM, OIF_E_HIP. */
+int oif_bind_device_buffers(oif_ctx* ctx, void* f0, void* f1, size_t bytes);
 
 /* ---- obstacles ---------------------------------------------------------------- */
 

@@ -366,6 +366,7 @@ struct oif_ctx {
     int N = 0;
     size_t st_size = 0;
     void* f[2] = {nullptr, nullptr};
+    bool f_bound = false;  // f[] is caller memory (oif_bind_device_buffers)
     void* G = nullptr;          // coupling force: [N][4] 8-byte words, [2][N][4] once the membrane kernel clears it
     size_t G_bytes = 0;
     unsigned* gclear = nullptr; // [2] corner-by-corner flags (BoxDev::gclear)
@@ -1408,7 +1409,10 @@ int oif_destroy(oif_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
     if (c->side) (void)hipStreamSynchronize(c->side);
-    for (void* p : {c->f[0], c->f[1], c->G, (void*)c->gclear, (void*)c->mask, (void*)c->touch[0], (void*)c->touch[1],
+    if (!c->f_bound)
+        for (void* p : {c->f[0], c->f[1]})
+            if (p) (void)hipFree(p);
+    for (void* p : {c->G, (void*)c->gclear, (void*)c->mask, (void*)c->touch[0], (void*)c->touch[1],
                     (void*)c->status, (void*)c->box_dev, c->bt_dev, c->link_dev, c->wall_dev})
         if (p) (void)hipFree(p);
     for (auto& b : c->tbufs) b.release();
@@ -1432,6 +1436,68 @@ int oif_bind_stream(oif_ctx* c, void* s) {
     HIPCALL(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
     c->stream = s ? (hipStream_t)s : c->own;
+    return OIF_OK;
+}
+
+int oif_population_bytes(const oif_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return OIF_E_ARG;
+    *bytes = pop_bytes(c);
+    return OIF_OK;
+}
+
+int oif_bind_device_buffers(oif_ctx* c, void* f0, void* f1, size_t bytes) {
+    if (!c) return OIF_E_ARG;
+    if ((f0 == nullptr) != (f1 == nullptr)) return fail(c, OIF_E_ARG, "bind both population buffers or neither");
+    const size_t pb = pop_bytes(c);
+    if (f0) {
+        const uintptr_t a = (uintptr_t)f0, b = (uintptr_t)f1;
+        if (bytes < pb) return fail(c, OIF_E_ARG, "population buffers smaller than oif_population_bytes");
+        if ((a | b) & 255) return fail(c, OIF_E_ARG, "population buffers must be 256-byte aligned");
+        if (a < b + pb && b < a + pb) return fail(c, OIF_E_ARG, "population buffers overlap");
+        for (void* p : {f0, f1}) {
+            hipPointerAttribute_t at{};
+            if (hipPointerGetAttributes(&at, p) != hipSuccess || at.type != hipMemoryTypeDevice ||
+                at.device != c->d.device) {
+                (void)hipGetLastError();
+                return fail(c, OIF_E_ARG, "population buffers must be device memory of the context's device");
+            }
+        }
+    } else if (!c->f_bound) {
+        return OIF_OK;  // the context's own buffers already
+    }
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    HIPCALL(c, hipStreamSynchronize(c->side));
+    void* nf[2] = {f0, f1};
+    if (!f0)  // back to buffers of the context's own
+        for (int k = 0; k < 2; ++k)
+            if (hipMalloc(&nf[k], pb) != hipSuccess) {
+                if (k) (void)hipFree(nf[0]);
+                return fail(c, OIF_E_NOMEM, "hipMalloc of the population buffers failed");
+            }
+    // both buffers carry state (solid nodes keep their values in both)
+    for (int k = 0; k < 2; ++k) {
+        if (nf[k] == c->f[k]) continue;
+        const hipError_t e = hipMemcpy(nf[k], c->f[k], pb, hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) {
+            if (!f0) {
+                (void)hipFree(nf[0]);
+                (void)hipFree(nf[1]);
+            }
+            return fail(c, OIF_E_HIP, std::string("copying the populations: ") + hipGetErrorString(e));
+        }
+    }
+    if (!c->f_bound) {
+        (void)hipFree(c->f[0]);
+        (void)hipFree(c->f[1]);
+    }
+    c->f[0] = nf[0];
+    c->f[1] = nf[1];
+    c->f_bound = f0 != nullptr;
+    c->box.f[0] = c->f[0];
+    c->box.f[1] = c->f[1];
+    HIPCALL(c, hipMemcpy(c->box_dev, &c->box, sizeof(BoxDev), hipMemcpyHostToDevice));
+    c->mesh_dirty = true;  // batches hold copies of the box descriptor
+    drop_graph(c);
     return OIF_OK;
 }
 

@@ -83,6 +83,8 @@ SIGNATURES = {
     "oif_destroy": (_i, [_vp]),
     "oif_last_error": (C.c_char_p, [_vp]),
     "oif_bind_stream": (_i, [_vp, _vp]),
+    "oif_population_bytes": (_i, [_vp, _vp]),
+    "oif_bind_device_buffers": (_i, [_vp, _vp, _vp, C.c_size_t]),
     "oif_template_create": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp]),
     "oif_object_add": (_i, [_vp, _i, _i, _vp, _vp, _d, _i]),
     "oif_euler_to_rot": (_i, [_d, _d, _d, _vp]),
@@ -224,6 +226,30 @@ class Context:
 
     def bind_stream(self, stream_ptr: Optional[int]):
         self._chk(lib().oif_bind_stream(self.h, stream_ptr))
+
+    def population_bytes(self) -> int:
+        """Bytes of each of the two population buffers."""
+        n = C.c_size_t()
+        self._chk(lib().oif_population_bytes(self.h, C.byref(n)))
+        return n.value
+
+    def bind_device_buffers(self, f0, f1, nbytes: Optional[int] = None):
+        """Keep the population buffers in caller-owned device memory: two
+        objects with ``data_ptr()`` and ``nbytes`` (e.g. PyTorch tensors on
+        the context's device), or two addresses with ``nbytes`` given; both
+        None returns them to the context.  The caller keeps the memory alive
+        while it is bound."""
+        if f0 is None and f1 is None:
+            self._chk(lib().oif_bind_device_buffers(self.h, None, None, 0))
+            self._bound = None
+            return
+        if (f0 is None) != (f1 is None):  # the library refuses it too
+            raise ValueError("bind both population buffers or neither")
+        ptrs = [t if isinstance(t, int) else t.data_ptr() for t in (f0, f1)]
+        if nbytes is None:
+            nbytes = min(int(t.nbytes) for t in (f0, f1))
+        self._chk(lib().oif_bind_device_buffers(self.h, ptrs[0], ptrs[1], int(nbytes)))
+        self._bound = (f0, f1)  # keeps Python-owned buffers alive while bound
 
     # -- templates and objects --
     def template_create(self, tid: int, nodes, tris, stretch=None, ks=0.0, kb=0.0, kal=0.0, kag=0.0,
