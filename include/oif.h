@@ -29,7 +29,8 @@
  *     the last error of a context is returned by oif_last_error.
  *   - Ownership: input arrays are copied during the call and stay the
  *     caller's; output arrays are caller-allocated host memory of the stated
- *     size.  Device memory is owned by the context.
+ *     size.  Device memory is owned by the context, except population
+ *     buffers the caller binds with oif_bind_device_buffers.
  *   - A context is not thread-safe; use one context per host thread.
  */
 #ifndef OIF_H
