@@ -353,6 +353,8 @@ def scale_leg(oif, steps, warmup, tune):
                      "lb_ms": round(r["lb_ms"], 5), "mesh_ms": round(r["mesh_ms"], 5),
                      "lb_GB/s": round(lb_bytes / (r["lb_ms"] * 1e-3) / 1e9, 1),
                      "lb_frac": round(lb_bytes / (r["lb_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "mesh_frac": round((48 * M + (19 * b + 24) * r["touched"]) / (r["mesh_ms"] * 1e-3) / 1e9
+                                        / HBM_PEAK_GBS, 4),
                      "touched_nodes": r["touched"], "full_step_bytes": full,
                      "full_step_frac": round(full / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "launch": {k: r[k] for k in ("lb_block", "mesh_block", "xcd_remap", "nt_loads",
@@ -478,6 +480,10 @@ def main():
                      "copy_kernel_GB/s": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "full_step": {"bytes": full_bytes, "touched_nodes": T, "GB/s": round(full_gbs, 1),
                       "frac": round(full_gbs / HBM_PEAK_GBS, 4)},
+        "membrane_kernel": {"bytes": 48 * M + 100 * T, "ms": round(r32["mesh_ms"], 5),
+                            "GB/s": round((48 * M + 100 * T) / (r32["mesh_ms"] * 1e-3) / 1e9, 1),
+                            "frac": round((48 * M + 100 * T) / (r32["mesh_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "bound": "latency of each object's dependent LDS and memory round trips"},
         "graph": {p: (round(N / (res[p]["graph_ms_per_step"] * 1e-3) / 1e6, 2) if "graph_ms_per_step" in res[p] else None)
                   for p in res},
         "storage": {},
