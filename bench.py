@@ -360,6 +360,19 @@ def scale_leg(oif, steps, warmup, tune):
                      "launch": {k: r[k] for k in ("lb_block", "mesh_block", "xcd_remap", "nt_loads",
                                                                       "force_clear_by_membrane")}}
     out["fp16_speedup"] = round(out["fp32"]["ms_per_step"] / out["fp16"]["ms_per_step"], 3)
+    # one GPU's share if the case were split over 8 GPUs along x: the slab with
+    # the most cells (the one that sets a sharded step's time) at real shape, FP32
+    share = max((synth.config_scale_share(8, k, steps) for k in range(8)), key=lambda b: len(b.objects))
+    log(f"[bench] scale case, one GPU's slab of 8 ({share.name})")
+    r = measure(oif, share, "fp32", steps, warmup, tune=tune)
+    ms = r["total_ms"] / steps
+    lbb = 2 * 19 * 4 * share.n_nodes
+    out["slab_1of8"] = {"workload": share.name, "nodes": share.n_nodes, "cells": len(share.objects),
+                        "ms_per_step": round(ms, 5), "mlups": round(share.n_nodes / (ms * 1e-3) / 1e6, 2),
+                        "lb_ms": round(r["lb_ms"], 5), "mesh_ms": round(r["mesh_ms"], 5),
+                        "lb_frac": round(lbb / (r["lb_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "halo_bytes_per_face_and_direction": share.ny * share.nz * 5 * 4,
+                        "note": "periodic in x in place of the exchange with the neighbouring slabs"}
     out["bytes_model"] = ("lattice 2 x 19 x b per node; full step adds 48 B per mesh node and "
                           "19 b + 24 B per touched lattice node (b = 4 FP32, 2 FP16)")
     return out

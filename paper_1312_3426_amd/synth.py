@@ -467,6 +467,23 @@ def config_scale(steps: int = 200, seed: int = 5, nx: int = 512, ny: int = 256, 
                name=f"rbc642x{n_cells}_{nx}x{ny}x{nz}")
 
 
+def config_scale_share(ranks: int = 8, rank: int = 0, steps: int = 200, seed: int = 5) -> Box:
+    """One GPU's share of the scale case split into `ranks` slabs along x: the
+    (512 / ranks) x 256 x 256 slab of rank `rank` with the cells whose centres
+    lie in it, shifted to the slab's origin.  The slab is periodic in x as
+    well, standing in for the populations and forces its faces would exchange
+    with the neighbouring ranks (the per-rank work is the same)."""
+    full = config_scale(steps=steps, seed=seed)
+    if full.nx % ranks or not 0 <= rank < ranks:
+        raise ValueError("ranks must divide nx and 0 <= rank < ranks")
+    w = full.nx // ranks
+    x0 = rank * w
+    objs = [dataclasses.replace(o, origin=o.origin - np.array([x0, 0.0, 0.0]))
+            for o in full.objects if x0 <= o.origin[0] < x0 + w]
+    return Box(w, full.ny, full.nz, templates=full.templates, objects=objs, steps=steps,
+               name=f"rbc642x{len(objs)}_{w}x{full.ny}x{full.nz}_slab{rank + 1}of{ranks}")
+
+
 def random_populations(rng: np.random.Generator, box: Box, amp: float = 1e-3) -> np.ndarray:
     """Full D3Q19 populations (19, nz, ny, nx) close to rest: weights times rho0
     plus uniform noise of the given amplitude.  Used to start parity runs from a
