@@ -218,8 +218,11 @@ int oif_population_bytes(const oif_ctx* ctx, size_t* bytes);
  * context's own (bytes ignored).  While bound, the caller keeps the memory
  * alive and leaves it alone; the context never frees it.  Captured graphs are
  * dropped and batches holding the box take the new buffers at their next
- * step.  Errors: OIF_E_ARG (one NULL, too small, misaligned, overlapping or
- * not device memory of the device; nothing changes), OIF_E_NOMEM, OIF_E_HIP. */
+ * step.  Binding again while bound moves the state into the new buffers; each
+ * new buffer may be the one it replaces but must not otherwise overlap the
+ * bound ones.  Errors: OIF_E_ARG (one NULL, too small, misaligned,
+ * overlapping, or not device memory of the device; nothing changes),
+ * OIF_E_NOMEM, OIF_E_HIP. */
 int oif_bind_device_buffers(oif_ctx* ctx, void* f0, void* f1, size_t bytes);
 
 /* ---- obstacles ---------------------------------------------------------------- */

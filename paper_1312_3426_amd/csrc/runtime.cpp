@@ -1462,6 +1462,15 @@ int oif_bind_device_buffers(oif_ctx* c, void* f0, void* f1, size_t bytes) {
                 return fail(c, OIF_E_ARG, "population buffers must be device memory of the context's device");
             }
         }
+        // rebinding: a new buffer may be the one it replaces, but no other
+        // overlap with the bound ones (the copies would overwrite state)
+        if (c->f_bound)
+            for (int k = 0; k < 2; ++k)
+                for (int j = 0; j < 2; ++j) {
+                    const uintptr_t n = k ? b : a, o = (uintptr_t)c->f[j];
+                    if (n < o + pb && o < n + pb && !(k == j && n == o))
+                        return fail(c, OIF_E_ARG, "population buffers overlap the bound ones other than in place");
+                }
     } else if (!c->f_bound) {
         return OIF_OK;  // the context's own buffers already
     }

@@ -17,8 +17,9 @@ Device buffers:
 * the state is copied into the tensors when they are bound, and eager,
   graph-replayed and batched steps on them give the same bits as a context
   on buffers of its own; the steps write the tensors;
-* calls with one buffer, too little memory, misaligned, overlapping or host
-  memory are refused and change nothing;
+* calls with one buffer, too little memory, misaligned, overlapping, host
+  memory or the bound buffers swapped are refused and change nothing;
+  binding two new tensors moves the state into them;
 * unbinding copies the state back and the tensors are no longer written."""
 import os
 import subprocess
@@ -171,9 +172,25 @@ for args, what in (((p0, None, nb), 'one buffer'), ((p0, p1, nb - 1), 'too small
     rc = L.oif_bind_device_buffers(c.h, args[0], args[1], args[2])
     assert rc == -1, (what, rc)  # OIF_E_ARG
     print('refused:', what, '-', L.oif_last_error(c.h).decode(), flush=True)
+rc = L.oif_bind_device_buffers(c.h, p1, p0, nb)  # swapped while bound
+assert rc == -1, ('swapped', rc)
+print('refused: the bound buffers swapped -', L.oif_last_error(c.h).decode(), flush=True)
 for x in (ref, c):
     x.step(3)
 assert same(state(ref), state(c)), 'a refused call changed the state'
+# rebinding moves the state into new buffers; the old ones are left alone
+u0 = torch.zeros(nb, dtype=torch.uint8, device='cuda')
+u1 = torch.zeros(nb, dtype=torch.uint8, device='cuda')
+torch.cuda.synchronize()
+c.bind_device_buffers(u0, u1)
+o0, o1 = t0.clone(), t1.clone()
+torch.cuda.synchronize()
+for x in (ref, c):
+    x.step(2)
+torch.cuda.synchronize()
+assert same(state(ref), state(c)), 'steps after rebinding differ'
+assert torch.equal(o0, t0) and torch.equal(o1, t1), 'the replaced tensors were written'
+print('rebound: bitwise equal, the replaced tensors untouched', flush=True)
 
 bt = oif.Batch([c])
 bt.step(4)
@@ -184,12 +201,12 @@ print('bound: batched steps bitwise equal', flush=True)
 
 c.bind_device_buffers(None, None)
 assert same(state(ref), state(c)), 'unbinding changed the state'
-b0, b1 = t0.clone(), t1.clone()
+b0, b1 = u0.clone(), u1.clone()
 torch.cuda.synchronize()
 for x in (ref, c):
     x.step(5)
 torch.cuda.synchronize()
-assert torch.equal(b0, t0) and torch.equal(b1, t1), 'the tensors were written after unbinding'
+assert torch.equal(b0, u0) and torch.equal(b1, u1), 'the tensors were written after unbinding'
 assert same(state(ref), state(c)), 'steps after unbinding differ'
 print('after unbinding: bitwise equal, tensors untouched', flush=True)
 ref.close(); c.close()
