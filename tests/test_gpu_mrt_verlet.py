@@ -2,6 +2,8 @@
 multiple-relaxation-time collision (the LB operator of the paper's
 references) and the velocity Verlet mesh integrator (the paper's engine),
 against the FP64 oracle on the same seeded inputs."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -376,6 +378,25 @@ def test_repulsion_modes_bitwise(oif):
     B.close()
     for c in ctxs:
         c.close()
+
+
+def test_repulsion_duplicate_settings_last_one_holds(oif):
+    """A pair and a wall interaction set twice (the pair the second time with
+    its types swapped): the same bits as the later settings alone."""
+    say("[repulsion] duplicate settings fp32")
+    box = _contact_box(walls=True)
+    dup = synth.Box(**{f.name: getattr(box, f.name) for f in dataclasses.fields(box)})
+    dup.repulsion = [synth.SoftSphere(1, 0, a=7e-6, n=3.0, cutoff=0.45, offset=0.0),
+                     synth.SoftSphere(0, None, a=5e-6, n=2.0, cutoff=0.7),
+                     synth.SoftSphere(0, 1, a=2e-6, n=2.0, cutoff=0.5, offset=0.02)] + box.repulsion[1:]
+    out = []
+    for b in (box, dup):
+        c = oif.Context.from_box(b, precision="fp32")
+        c.step(6)
+        X, V = c.read_mesh(-1)
+        out.append((c.read_populations(), X, V))
+        c.close()
+    assert all(np.array_equal(p, q) for p, q in zip(*out))
 
 
 def test_repulsion_argument_errors(oif):

@@ -76,6 +76,40 @@ def test_single_pair_closed_form(orc):
     assert np.abs(s2.repulsion()).max() == 0.0
 
 
+def test_duplicate_settings_last_one_holds(orc):
+    """A pair of types set twice (the second time with the types swapped) and
+    a type's wall interaction set twice: the later setting replaces the
+    earlier one, pinned by the closed form of the later one."""
+    tm, objs = _tetra_objects([(5.0, 5.0, 1.0), (5.0, 5.0, 1.0)], [0, 1])
+    last = synth.SoftSphere(1, 0, a=2e-4, n=1.5, cutoff=0.4, offset=0.05)
+    first = synth.SoftSphere(0, 1, a=9e-4, n=3.0, cutoff=0.45, offset=0.0)
+    s = orc.System(_box(objs, tm, [first, last]))
+    X = s.X.copy()
+    X[4:] += np.array([4.0, 0.0, 3.0])  # object 1 away from object 0 and from the z walls
+    sep = np.array([0.12, -0.2, 0.1])
+    X[4] = X[2] + sep
+    s.X[:] = X
+    d = np.linalg.norm(sep)
+    f = 2e-4 * 1.5 * (d - 0.05) ** -2.5
+    want = np.zeros_like(X)
+    want[4] = f * sep / d
+    want[2] = -f * sep / d
+    dist = np.linalg.norm(X[:4, None, :] - X[None, 4:, :], axis=2)
+    assert (dist < 0.46).sum() == 1
+    assert np.abs(s.repulsion() - want).max() < 1e-14 * f
+    # walls: node 0 of object 0 near z = 0 (the wall at z = 0 sits half a
+    # lattice spacing below the first node layer); type 0 set twice
+    wfirst = synth.SoftSphere(0, None, a=5e-4, n=2.0, cutoff=1.5)
+    wlast = synth.SoftSphere(0, None, a=1e-4, n=1.5, cutoff=1.5)
+    sw = orc.System(_box(objs, tm, [wfirst, wlast], walls=True))
+    so = orc.System(_box(objs, tm, [wlast], walls=True))
+    sw.X[:] = X
+    so.X[:] = X
+    Fw, Fo = sw.repulsion(), so.repulsion()
+    assert np.abs(Fo).max() > 0.0
+    assert np.array_equal(Fw, Fo)
+
+
 def test_pair_forces_are_minus_gradient_and_conserve(orc):
     """Random close packing of three objects (types 0, 1, 0; pairs 0-1 and
     0-0, the latter also inside an object): forces = -grad of the brute-force
