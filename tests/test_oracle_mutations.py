@@ -18,6 +18,12 @@ PIN_FILES = ["tests/test_oracle_mesh.py", "tests/test_oracle_lb.py", "tests/test
              "tests/test_oracle_mrt_verlet.py", "tests/test_oracle_repulsion.py"]
 
 MUTATIONS = {
+    "pair_first_setting": ("            r = &s->pair[k];\n    return r;",
+                           "            if (!r) r = &s->pair[k];\n    return r;"),
+    "wall_first_setting": ("if (s->wall[k].type_a == s->o_type[o]) ss = &s->wall[k];",
+                           "if (s->wall[k].type_a == s->o_type[o] && !ss) ss = &s->wall[k];"),
+    "pair_order_matters": ("(s->pair[k].type_a == ta && s->pair[k].type_b == tb) ||\n            (s->pair[k].type_a == tb && s->pair[k].type_b == ta)",
+                           "(s->pair[k].type_a == ta && s->pair[k].type_b == tb)"),
     "kappa_exponent": ("(lambda + pow(lambda, -3.0))", "(lambda + pow(lambda, -2.0))"),
     "stretch_sign": ("double f = ks * kap * (L - L0[e]) / L0[e];",
                      "double f = ks * kap * (L0[e] - L) / L0[e];"),
