@@ -9,27 +9,28 @@
 namespace oif {
 namespace dev {
 
-// Coupling force density at node p, read from the step's G (the node's three
-// components are one 32-byte slot).  The membrane workgroups zero their slots
-// in the next step; only where one of them spread corner by corner (no list
-// of its slots) is the slot cleared here.
+// Coupling force density at node p, read from the step's G (the node's
+// slot: three int64 words at 2^-fixed_point_exp in the FP32 forms, 32 bytes;
+// three pairs of int64 words at 2^-30 and 2^-80 in the FP64 form, 64 bytes).
+// The membrane workgroups zero their slots in the next step; only where one
+// of them spread corner by corner (no list of its slots) is the slot cleared
+// here.
 template <int P, class BP>
 __device__ __forceinline__ void take_force(BP __restrict__ B, int p, int parity, bool clear,
                                            typename Prec<P>::R& fx, typename Prec<P>::R& fy,
                                            typename Prec<P>::R& fz) {
     typedef typename Prec<P>::R R;
-    const unsigned o = (unsigned)p * 32u;
     if (P == PREC_FP64) {
-        double* G = (double*)B->G[parity];
-        fx += (R)gload(G, o);
-        fy += (R)gload(G, o + 8u);
-        fz += (R)gload(G, o + 16u);
-        if (clear) {
-            gstore(G, o, 0.0);
-            gstore(G, o + 8u, 0.0);
-            gstore(G, o + 16u, 0.0);
-        }
+        long long* G = (long long*)B->G[parity] + 8 * (size_t)p;
+        const long long w0 = gld(G), w1 = gld(G + 1), w2 = gld(G + 2), w3 = gld(G + 3), w4 = gld(G + 4),
+                        w5 = gld(G + 5);
+        fx += (R)((double)w0 * 0x1p-30 + (double)w1 * 0x1p-80);
+        fy += (R)((double)w2 * 0x1p-30 + (double)w3 * 0x1p-80);
+        fz += (R)((double)w4 * 0x1p-30 + (double)w5 * 0x1p-80);
+        if (clear)
+            for (int w = 0; w < 6; ++w) gst(G + w, 0ll);
     } else {
+        const unsigned o = (unsigned)p * 32u;
         long long* G = (long long*)B->G[parity];
         const double s = B->fp_inv;
         fx += (R)((double)gload(G, o) * s);

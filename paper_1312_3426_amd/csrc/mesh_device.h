@@ -20,54 +20,75 @@ namespace dev {
 // order in which mesh nodes add (bitwise reproducible); FP64 form: FP64.
 template <int P>
 struct Acc {
+    // FP32 forms: one int64 word per component, the value times 2^fixed_point_exp
     typedef unsigned long long T;
-    __device__ static T convert(float v, double scale, unsigned& fl) {
+    static constexpr int WC = 1;    // words per component
+    static constexpr int SLOT = 4;  // words per node of G (x, y, z, unused)
+    __device__ static void convert(float v, double scale, T* out, unsigned& fl) {
         const double a = (double)v * scale;
         if (!(fabs(a) < 4.0e18)) {  // out of range or not finite
             fl |= ST_OVERFLOW;
-            return 0ull;
+            out[0] = 0ull;
+            return;
         }
-        return (T)__double2ll_rn(a);
-    }
-    __device__ static unsigned add(T* acc, float x, float y, float z, double scale) {
-        unsigned fl = 0;
-        const T a = convert(x, scale, fl), b = convert(y, scale, fl), c = convert(z, scale, fl);
-        atomicAdd(acc, a);
-        atomicAdd(acc + 1, b);
-        atomicAdd(acc + 2, c);
-        return fl;
-    }
-    __device__ static unsigned flush(gptr<const BoxDev> B, int parity, int q, T x, T y, T z) {
-        if ((x | y | z) == 0ull) return 0u;
-        T* G = (T*)B->G[parity] + 4 * (size_t)q;
-        gatomic_add(G, x);
-        gatomic_add(G + 1, y);
-        gatomic_add(G + 2, z);
-        gatomic_or(B->mask + (q >> 6), 1ull << (q & 63));
-        return 0u;
+        out[0] = (T)__double2ll_rn(a);
     }
 };
 
 template <>
 struct Acc<PREC_FP64> {
-    typedef double T;
-    __device__ static T convert(double v, double, unsigned&) { return v; }
-    __device__ static unsigned add(T* acc, double x, double y, double z, double) {
-        atomicAdd(acc, x);
-        atomicAdd(acc + 1, y);
-        atomicAdd(acc + 2, z);
-        return 0u;
-    }
-    __device__ static unsigned flush(gptr<const BoxDev> B, int parity, int q, T x, T y, T z) {
-        if (x == 0.0 && y == 0.0 && z == 0.0) return 0u;
-        T* G = (T*)B->G[parity] + 4 * (size_t)q;
-        gatomic_add(G, x);
-        gatomic_add(G + 1, y);
-        gatomic_add(G + 2, z);
-        gatomic_or(B->mask + (q >> 6), 1ull << (q & 63));
-        return 0u;
+    // FP64 form: two int64 words per component, the value split into a
+    // multiple of 2^-30 and the remainder in units of 2^-80.  Both integer
+    // sums are exact, so the spread force does not depend on the order of the
+    // additions (as in the FP32 forms); a value is rounded only below 2^-80,
+    // and |value| < 2^33 (else the overflow flag).
+    typedef unsigned long long T;
+    static constexpr int WC = 2;
+    static constexpr int SLOT = 8;  // x hi, x lo, y hi, y lo, z hi, z lo, two unused
+    __device__ static void convert(double v, double, T* out, unsigned& fl) {
+        if (!(fabs(v) < 8.0e9)) {
+            fl |= ST_OVERFLOW;
+            out[0] = out[1] = 0ull;
+            return;
+        }
+        const double h = rint(v * 0x1p30);
+        const double r = v - h * 0x1p-30;  // exact: h 2^-30 is within a factor 2 of v, or 0
+        out[0] = (T)(long long)h;
+        out[1] = (T)__double2ll_rn(r * 0x1p80);
     }
 };
+
+// Add a reaction force to a node's LDS accumulator (3 * WC words).
+template <int P>
+__device__ __forceinline__ unsigned acc_add(typename Acc<P>::T* acc, typename Prec<P>::R x, typename Prec<P>::R y,
+                                            typename Prec<P>::R z, double scale) {
+    constexpr int WC = Acc<P>::WC;
+    unsigned fl = 0;
+    typename Acc<P>::T v[3 * WC];
+    Acc<P>::convert(x, scale, v, fl);
+    Acc<P>::convert(y, scale, v + WC, fl);
+    Acc<P>::convert(z, scale, v + 2 * WC, fl);
+#pragma unroll
+    for (int w = 0; w < 3 * WC; ++w) atomicAdd(acc + w, v[w]);
+    return fl;
+}
+
+// Add a node's summed reaction (3 * WC words) to G at lattice node q and set
+// its mask bit.
+template <int P>
+__device__ __forceinline__ void acc_flush(gptr<const BoxDev> B, int parity, int q, const typename Acc<P>::T* v) {
+    constexpr int WC = Acc<P>::WC;
+    typedef typename Acc<P>::T T;
+    T any = 0ull;
+#pragma unroll
+    for (int w = 0; w < 3 * WC; ++w) any |= v[w];
+    if (any == 0ull) return;
+    T* G = (T*)B->G[parity] + Acc<P>::SLOT * (size_t)q;
+#pragma unroll
+    for (int w = 0; w < 3 * WC; ++w)
+        if (v[w]) gatomic_add(G + w, v[w]);
+    gatomic_or(B->mask + (q >> 6), 1ull << (q & 63));
+}
 
 // Lattice index of the (unwrapped) node (gx, gy, gz): periodic in x and y,
 // periodic or clamped to the walls in z.
@@ -264,10 +285,9 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
             const int* qo = O.qsave + ((size_t)np * kq + sl) * qstride;
             const int cnt = min(gld(qo), ccap);
             for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-                unsigned long long* g = (unsigned long long*)(Gp + 32 * (size_t)gld(qo + 1 + k));
-                gst(g, 0ull);
-                gst(g + 1, 0ull);
-                gst(g + 2, 0ull);
+                unsigned long long* g = (unsigned long long*)Gp + Acc<P>::SLOT * (size_t)gld(qo + 1 + k);
+#pragma unroll
+                for (int w = 0; w < 3 * Acc<P>::WC; ++w) gst(g + w, 0ull);
             }
         }
         if (threadIdx.x == 0) gst(B->gclear + np, 0u);
@@ -537,7 +557,8 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
     R* ug = (R*)carea(lay.ug);                   // [ccap][3] velocity at compact nodes
     int* qn = (int*)carea(lay.qn);               // [ccap] lattice index of compact nodes
     typedef typename Acc<P>::T A;
-    A* gacc = (A*)carea(lay.gacc);               // [ccap][3] summed reaction force
+    constexpr int AW = 3 * Acc<P>::WC;           // accumulator words per node
+    A* gacc = (A*)carea(lay.gacc);               // [ccap][AW] summed reaction force
     bool compact = false;
     if (grid) {
         const int vol = (int)(exl * eyl * ezl);
@@ -580,7 +601,7 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
         __syncthreads();
         compact = ncomp <= ccap;  // block-uniform
         if (compact) {
-            for (int k = threadIdx.x; k < 3 * ncomp; k += blockDim.x) gacc[k] = A(0);
+            for (int k = threadIdx.x; k < AW * ncomp; k += blockDim.x) gacc[k] = A(0);
             // lattice index of every touched node, in compact numbering (the
             // box origin wrapped once, box offsets without integer division)
             const int oxw = wrap_mod(ox, nxb), oyw = wrap_mod(oy, nyb);
@@ -687,7 +708,7 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
 #pragma unroll
                 for (int kk = 0; kk < 8; ++kk) {
                     if (wr[kk] == R(0)) continue;
-                    flags |= Acc<P>::add(&gacc[3 * cr[kk]], wr[kk] * dgx, wr[kk] * dgy, wr[kk] * dgz,
+                    flags |= acc_add<P>(&gacc[AW * cr[kk]], wr[kk] * dgx, wr[kk] * dgy, wr[kk] * dgz,
                                          B->fp_scale);
                 }
             } else {
@@ -745,12 +766,13 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
                     const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
                     const R wk = (dx ? phx : R(1) - phx) * (dy ? phy : R(1) - phy) * (dz ? phz : R(1) - phz);
                     if (wk == R(0)) continue;
-                    const typename Acc<P>::T ax = Acc<P>::convert(wk * dgx, B->fp_scale, flags);
-                    const typename Acc<P>::T ay = Acc<P>::convert(wk * dgy, B->fp_scale, flags);
-                    const typename Acc<P>::T az = Acc<P>::convert(wk * dgz, B->fp_scale, flags);
+                    A av[AW];
+                    Acc<P>::convert(wk * dgx, B->fp_scale, av, flags);
+                    Acc<P>::convert(wk * dgy, B->fp_scale, av + AW / 3, flags);
+                    Acc<P>::convert(wk * dgz, B->fp_scale, av + 2 * AW / 3, flags);
                     const int qk = ((dz ? iz1 : iz0) * nyb + (dy ? iy1 : iy)) * nxb + (dx ? ix1 : ix);
                     if (bt && gld(bt + qk)) continue;  // an obstacle takes no share
-                    flags |= Acc<P>::flush(B, parity, qk, ax, ay, az);
+                    acc_flush<P>(B, parity, qk, av);
                 }
             }
         }
@@ -788,19 +810,23 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
         gst(O.X + 3 * v + 2, qz);
     }
     if (compact) {
-        // one global atomic per touched lattice node and component
+        // one global atomic per touched lattice node and accumulator word
         __syncthreads();
-        // (one lane per node and component: a wave's atomics cover the
-        // consecutive 32-byte slots of ~21 nodes instead of one component of
-        // 64 nodes spread over three arrays)
-        for (int k = threadIdx.x; k < 3 * ncomp; k += blockDim.x) {
-            const int c = k / 3, comp = k - 3 * c;
+        // (one lane per node and word: a wave's atomics cover the consecutive
+        // slots of ~21 nodes (FP32 forms) instead of one component of 64 nodes
+        // spread over three arrays)
+        for (int k = threadIdx.x; k < AW * ncomp; k += blockDim.x) {
+            const int c = k / AW, w = k - AW * c;
             const int q = qn[c];
             if (bt && gld(bt + q)) continue;  // an obstacle takes no share
             const A val = gacc[k];
-            if (val != A(0)) gatomic_add((A*)B->G[parity] + 4 * (size_t)q + comp, val);
-            if (comp == 0 && (gacc[3 * c] != A(0) || gacc[3 * c + 1] != A(0) || gacc[3 * c + 2] != A(0)))
-                gatomic_or(B->mask + (q >> 6), 1ull << (q & 63));
+            if (val != A(0)) gatomic_add((A*)B->G[parity] + Acc<P>::SLOT * (size_t)q + w, val);
+            if (w == 0) {
+                A any = A(0);
+#pragma unroll
+                for (int u = 0; u < AW; ++u) any |= gacc[AW * c + u];
+                if (any != A(0)) gatomic_or(B->mask + (q >> 6), 1ull << (q & 63));
+            }
         }
     }
     // split stepping: the stencils of the new positions, for the next step

@@ -14,7 +14,8 @@
 //      fixed order (deterministic, no atomics), trilinear interpolation of the
 //      fluid velocity from the 8 surrounding nodes, drag, symplectic Euler
 //      update, and spreading of the reaction to the 8 nodes (int64 fixed-point
-//      atomics in the FP32 forms, FP64 atomics in the FP64 form) with the
+//      atomics: one word per component in the FP32 forms, a 2^-30 / 2^-80
+//      pair of words in the FP64 form; exact, so order-independent) with the
 //      nodes' mask bits set.
 // With velocity Verlet (the integrator of the paper's engine) the staged
 // positions are first advanced by the half-step velocity V + F_last/(2m), the
@@ -165,7 +166,7 @@ size_t mesh_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap,
 size_t mesh_cpl_lds_bytes(int precision, int nv, int nt, int ne, int ucap, int ccap, int cons) {
     const MeshLayout L =
         mesh_layout(precision == PREC_FP64 ? sizeof(double) : sizeof(float), nv, nt, ne, ucap, ccap, cons);
-    return align16(L.gacc + (size_t)ccap * 3 * 8) - L.need;
+    return align16(L.gacc + (size_t)ccap * (precision == PREC_FP64 ? 6 : 3) * 8) - L.need;
 }
 
 hipError_t launch_mesh(const MeshLaunch& L) {

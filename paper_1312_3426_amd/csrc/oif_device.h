@@ -155,7 +155,8 @@ __host__ __device__ inline MeshLayout mesh_layout(size_t r, int nv, int nt, int 
     L.ug = align16(L.need + 2 * L.nwords * 4);
     L.qn = L.ug + (size_t)ccap * 3 * r;
     L.gacc = align16(L.qn + (size_t)ccap * 4);
-    const size_t end_coupling = L.gacc + (size_t)ccap * 3 * 8;
+    // summed reaction force: 3 int64 words per node (FP32 forms), 6 (FP64)
+    const size_t end_coupling = L.gacc + (size_t)ccap * (r == 8 ? 6 : 3) * 8;
     L.total = align16(end_forces > end_coupling ? end_forces : end_coupling);
     return L;
 }

@@ -453,6 +453,9 @@ static void div_magic(int d, unsigned* m, int* s) {
 // Bytes of one population buffer: 19 values per node in tiles of 64 nodes,
 // the node count rounded up to whole tiles.
 static size_t pop_bytes(const oif_ctx* c) { return 19 * (((size_t)c->N + 63) & ~(size_t)63) * c->st_size; }
+// bytes per lattice node of the coupling force G: three int64 words (FP32
+// forms) or three pairs of them (FP64 form), padded to 32 / 64
+static size_t g_slot(const oif_ctx* c) { return c->d.precision == OIF_PREC_FP64 ? 64 : 32; }
 
 struct oif_batch {
     std::vector<oif_ctx*> ctx;
@@ -1347,7 +1350,7 @@ int oif_create(const oif_lattice_desc* desc, oif_ctx** out) {
     const size_t popb = pop_bytes(cp);
     const size_t nmask = ((size_t)N + 63) / 64;
     int rc = OIF_OK;
-    c->G_bytes = 32 * (size_t)N;
+    c->G_bytes = g_slot(cp) * (size_t)N;
     if ((rc = alloc(&c->f[0], popb)) || (rc = alloc(&c->f[1], popb)) || (rc = alloc(&c->G, c->G_bytes)) ||
         (rc = alloc((void**)&c->gclear, 2 * sizeof(unsigned))) ||
         (rc = alloc((void**)&c->mask, 8 * nmask)) || (rc = alloc((void**)&c->touch[0], 8 * nmask)) ||
@@ -2020,16 +2023,17 @@ namespace {
 int set_g_mode(oif_ctx* c, int by_membrane) {
     HIPCALL(c, hipStreamSynchronize(c->stream));
     HIPCALL(c, hipStreamSynchronize(c->side));
-    if (by_membrane && c->G_bytes < 64 * (size_t)c->N) {  // the second parity's buffer
+    const size_t gb = g_slot(c) * (size_t)c->N;
+    if (by_membrane && c->G_bytes < 2 * gb) {  // the second parity's buffer
         void* g = nullptr;
-        if (hipMalloc(&g, 64 * (size_t)c->N) != hipSuccess) return fail(c, OIF_E_NOMEM, "hipMalloc of G failed");
+        if (hipMalloc(&g, 2 * gb) != hipSuccess) return fail(c, OIF_E_NOMEM, "hipMalloc of G failed");
         (void)hipFree(c->G);
         c->G = g;
-        c->G_bytes = 64 * (size_t)c->N;
+        c->G_bytes = 2 * gb;
         c->box.G[0] = c->G;
     }
     c->box.g_by_mesh = by_membrane;
-    c->box.G[1] = by_membrane ? (void*)((unsigned char*)c->G + 32 * (size_t)c->N) : c->G;
+    c->box.G[1] = by_membrane ? (void*)((unsigned char*)c->G + gb) : c->G;
     HIPCALL(c, hipMemset(c->G, 0, c->G_bytes));
     HIPCALL(c, hipMemset(c->gclear, 0, 2 * sizeof(unsigned)));
     if (c->qsave_dev.p) HIPCALL(c, hipMemset(c->qsave_dev.p, 0, c->qsave_dev.n));

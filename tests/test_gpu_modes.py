@@ -65,9 +65,8 @@ def test_overlap_matches_sequential_bitwise(oif, prec):
                                                ("fp64", False, "channel"), ("fp32", True, "channel"),
                                                ("fp32", False, "obstacles"), ("fp32", False, "mrt")])
 def test_nontemporal_loads_bitwise(oif, prec, overlap, case):
-    """The cache policy of the population reads changes no value.  (FP64
-    sums the coupling force of overlapping stencils with FP64 atomics, whose
-    order varies from run to run: there the two runs agree to round-off.)"""
+    """The cache policy of the population reads changes no value, in either
+    form (the spreading is exact fixed point in both)."""
     say(f"[modes] non-temporal vs ordinary population reads, {prec} {case}, overlap={overlap}")
     box = synth.config_obstacle_channel(40) if case == "obstacles" else channel()
     if case == "mrt":
@@ -83,11 +82,7 @@ def test_nontemporal_loads_bitwise(oif, prec, overlap, case):
         if nt:
             assert oif.lib().oif_set_lb_loads(c.h, 2) == -1  # OIF_E_ARG
         c.close()
-    if prec == "fp64":  # the FP64 parity criterion: 1e-12 relative plus 1e-14 absolute
-        for a, b in zip(*outs):
-            assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a)) + 1e-14
-    else:
-        assert same(*outs)
+    assert same(*outs)
 
 
 @pytest.mark.parametrize("overlap", [False, True])
@@ -163,9 +158,7 @@ def test_checkpoint_restore_bitwise(oif, prec):
     """Checkpoint = stored deviations + mesh positions and velocities:
     restoring them into a new context continues bit for bit in every form,
     also early in a run, when many deviations are too small for full FP64
-    populations near w_i rho0 to carry all their bits.  (FP64 sums overlapping
-    stencils' coupling forces with FP64 atomics in a varying order: there the
-    continuation agrees to round-off.)"""
+    populations near w_i rho0 to carry all their bits."""
     say(f"[modes] checkpoint / restore, {prec}")
     box = channel()
     for first in (3, 30):
@@ -182,10 +175,7 @@ def test_checkpoint_restore_bitwise(oif, prec):
         b.write_mesh(-1, X, V)
         b.step(20)
         got = state(b)
-        if prec == "fp64":
-            assert all(np.allclose(p, q, rtol=0, atol=1e-14 * max(1.0, np.abs(q).max())) for p, q in zip(got, ref))
-        else:
-            assert same(ref, got)
+        assert same(ref, got)
         b.close()
 
 
@@ -564,8 +554,8 @@ def test_persistent_batch_matches_launch_pairs(oif, prec, chunk, meshes):
     capture, and from either step parity; lattice tasks of one block, of the
     default count, and of three blocks (a box's last task then runs past its
     nodes).  With the 162- and 642-node spheres of the batching case only (all
-    meshes in LDS) the results agree bit for bit in FP32 (fixed-point
-    spreading) and to round-off in FP64 (FP64 atomics).  With its 2562-node
+    meshes in LDS) the results agree bit for bit (fixed-point spreading in
+    every form).  With its 2562-node
     spheres as well, which the launch-per-phase form splits over several
     workgroups and the persistent form runs whole (coupling area in LDS), the
     area and volume sums are rounded in another order, so the two agree to the
@@ -603,11 +593,8 @@ def test_persistent_batch_matches_launch_pairs(oif, prec, chunk, meshes):
                                 (V0, V1, ATOL["V"] * L)):
                 if a.size:
                     assert np.abs(a - b).max() <= rtol * np.abs(a).max() + floor
-        elif prec == "fp32":
-            assert np.array_equal(d0, d1) and np.array_equal(X0, X1) and np.array_equal(V0, V1)
         else:
-            assert np.abs(d0 - d1).max() <= 1e-15 and np.abs(X0 - X1).max() <= 1e-12
-            assert np.abs(V0 - V1).max() <= 1e-14
+            assert np.array_equal(d0, d1) and np.array_equal(X0, X1) and np.array_equal(V0, V1)
 
 
 def test_persistent_batch_refuses_obstacles_and_mrt(oif):

@@ -155,13 +155,16 @@ def test_storage_forms_velocity_error(oif, orc, prec, bound):
     assert e["u"] <= bound
 
 
-def test_fp32_deterministic(oif):
-    """Fixed-point spreading makes the FP32 form bitwise reproducible."""
-    say("[determinism] rbc393x10 fp32 x2")
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_fp32_deterministic(oif, prec):
+    """Fixed-point spreading (one int64 word per component in the FP32 forms,
+    a 2^-30 / 2^-80 pair of them in the FP64 form) makes both forms bitwise
+    reproducible."""
+    say(f"[determinism] rbc393x10 {prec} x2")
     box = synth.config_channel_rbc(50)
     outs = []
     for _ in range(2):
-        ctx = oif.Context.from_box(box, precision="fp32")
+        ctx = oif.Context.from_box(box, precision=prec)
         ctx.step(50)
         outs.append((ctx.read_populations(), *ctx.read_mesh(-1)))
         ctx.close()

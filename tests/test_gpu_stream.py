@@ -21,8 +21,7 @@ Device buffers:
   memory or the bound buffers swapped are refused and change nothing;
   binding two new tensors moves the state into them;
 * the FP64, FP16 and BF16 forms take buffers of their own size and give the
-  same bits bound and unbound (FP64, whose spreading adds FP64 atomics in a
-  varying order, to 1e-12);
+  same bits bound and unbound;
 * unbinding copies the state back and the tensors are no longer written."""
 import os
 import subprocess
@@ -215,10 +214,6 @@ print('after unbinding: bitwise equal, tensors untouched', flush=True)
 ref.close(); c.close()
 
 # every storage form: the buffer size and a bound run against an unbound one
-# (FP64 spreads with FP64 atomics, whose order varies: close, not bitwise)
-def close(a, b):
-    return all(np.abs(x - y).max() <= 1e-12 * np.abs(y).max() + 1e-15 for x, y in zip(a, b))
-
 small = synth.config_sphere_fp64(10)
 for prec, size in (('fp64', 8), ('fp16', 2), ('bf16', 2)):
     r2 = oif.Context.from_box(small, precision=prec)
@@ -233,13 +228,12 @@ for prec, size in (('fp64', 8), ('fp16', 2), ('bf16', 2)):
     c2.bind_device_buffers(v0, v1)
     for x in (r2, c2):
         x.step(4)
-    eq = close if prec == 'fp64' else same
-    assert eq(state(r2), state(c2)), prec
+    assert same(state(r2), state(c2)), prec
     c2.bind_device_buffers(None, None)
     for x in (r2, c2):
         x.step(2)
-    assert eq(state(r2), state(c2)), prec
-    print(prec, 'bound and unbound:', 'equal to 1e-12' if prec == 'fp64' else 'bitwise equal', flush=True)
+    assert same(state(r2), state(c2)), prec
+    print(prec, 'bound and unbound: bitwise equal', flush=True)
     r2.close(); c2.close()
 print('BUFFERS-OK', flush=True)
 """
