@@ -263,20 +263,21 @@ def test_large_meshes_vs_oracle(oif, orc, prec):
     assert all(v[3] for v in res.values())
     c.close()
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("case", ["batchbox", "pulled"])
-def test_force_clear_modes_bitwise(oif, case):
+def test_force_clear_modes_bitwise(oif, case, prec):
     """The coupling force cleared by the lattice kernel (the default), by the
     membrane kernel from its lists of slots one step later, or by one and then
-    the other, switching every two steps: the same bits (FP32), eagerly, under
-    graph capture and in a batch.  The batching box has 2562-node spheres split
+    the other, switching every two steps: the same bits (FP32, and FP64 with
+    its 64-byte slots), eagerly, under graph capture and in a batch.  The batching box has 2562-node spheres split
     over several workgroups (a list per slice) beside spheres in LDS; in the
     pulled case one node 16 units out sends the sphere's coupling corner by
     corner (no list: the lattice kernel clears G in that step)."""
-    say(f"[modes] force clear by lattice / membrane kernel, {case}")
+    say(f"[modes] force clear by lattice / membrane kernel, {case} {prec}")
     box = synth.config_batch(n_boxes=1, steps=12)[0] if case == "batchbox" else synth.config_sphere_fp64(12)
 
     def make(by_membrane=False):
-        c = oif.Context.from_box(box, precision="fp32")
+        c = oif.Context.from_box(box, precision=prec)
         if case == "pulled":
             X, V = c.read_mesh(-1)
             X[0, 0] += 16.0
