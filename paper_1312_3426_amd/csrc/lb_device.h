@@ -5,6 +5,7 @@
 #pragma once
 
 #include "device_common.h"
+#include "fixed_point.h"
 
 namespace oif {
 namespace dev {
@@ -24,9 +25,9 @@ __device__ __forceinline__ void take_force(BP __restrict__ B, int p, int parity,
         long long* G = (long long*)B->G[parity] + 8 * (size_t)p;
         const long long w0 = gld(G), w1 = gld(G + 1), w2 = gld(G + 2), w3 = gld(G + 3), w4 = gld(G + 4),
                         w5 = gld(G + 5);
-        fx += (R)((double)w0 * 0x1p-30 + (double)w1 * 0x1p-80);
-        fy += (R)((double)w2 * 0x1p-30 + (double)w3 * 0x1p-80);
-        fz += (R)((double)w4 * 0x1p-30 + (double)w5 * 0x1p-80);
+        fx += (R)fx_value(w0, w1);
+        fy += (R)fx_value(w2, w3);
+        fz += (R)fx_value(w4, w5);
         if (clear)
             for (int w = 0; w < 6; ++w) gst(G + w, 0ll);
     } else {

@@ -11,6 +11,7 @@
 #include <limits.h>
 
 #include "device_common.h"
+#include "fixed_point.h"
 
 namespace oif {
 namespace dev {
@@ -46,15 +47,10 @@ struct Acc<PREC_FP64> {
     static constexpr int WC = 2;
     static constexpr int SLOT = 8;  // x hi, x lo, y hi, y lo, z hi, z lo, two unused
     __device__ static void convert(double v, double, T* out, unsigned& fl) {
-        if (!(fabs(v) < 8.0e9)) {
-            fl |= ST_OVERFLOW;
-            out[0] = out[1] = 0ull;
-            return;
-        }
-        const double h = rint(v * 0x1p30);
-        const double r = v - h * 0x1p-30;  // exact: h 2^-30 is within a factor 2 of v, or 0
-        out[0] = (T)(long long)h;
-        out[1] = (T)__double2ll_rn(r * 0x1p80);
+        long long hi, lo;
+        if (!fx_split(v, hi, lo)) fl |= ST_OVERFLOW;
+        out[0] = (T)hi;
+        out[1] = (T)lo;
     }
 };
 

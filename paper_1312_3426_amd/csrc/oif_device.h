@@ -234,6 +234,7 @@ struct RepDev {
     double* spos;               // [M][3] positions in cell order
     unsigned char* stype;       // [M] types in cell order
     void* frep;                 // [M][3] force, arithmetic type
+    unsigned* status;           // the box's watchdog word (ST_OVERFLOW: a force out of range)
 };
 
 // ---- launchers (kernels.hip) ----------------------------------------------

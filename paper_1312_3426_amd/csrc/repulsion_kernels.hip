@@ -11,8 +11,8 @@
 //               velocity Verlet) and their cells (a regular grid, edge >= the
 //               largest pair range); nodes per cell;
 //   scan        cell starts (exclusive prefix sum);
-//   scatter     node ids into their cells;
-//   order       each cell sorted by node id (deterministic sums);
+//   scatter     node ids into their cells (in whatever order the atomics
+//               hand out the slots);
 //   gather      positions (wrapped into the box along periodic axes) and
 //               types copied into cell order;
 //   force       one thread per node in cell order: the partners in the 27
@@ -20,10 +20,13 @@
 //               across a periodic face shifted by the box length (the minimum
 //               image: cells are at least the pair range and the box at least
 //               twice it); then every obstacle shape and the z walls; FP64
-//               arithmetic, fixed order.
+//               arithmetic, each node's terms summed exactly (fixed_point.h),
+//               so the result does not depend on the order of the cells'
+//               slots.
 #include <limits.h>
 
 #include "device_common.h"
+#include "fixed_point.h"
 
 namespace oif {
 namespace {
@@ -64,26 +67,6 @@ __global__ void __launch_bounds__(256) rep_bin_kernel(const ObjDev<R>* __restric
     }
 }
 
-// exclusive prefix sum of cnt[0, n) in place; cnt[n] = total; cursor = starts
-__global__ void __launch_bounds__(1024) scan_block_kernel(int* __restrict__ cnt, int* __restrict__ bsum, int n) {
-    __shared__ int wsum[16];
-    const int i = blockIdx.x * 1024 + threadIdx.x;
-    const int v = i < n ? cnt[i] : 0;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
-    if (lane == 63) wsum[w] = incl;
-    __syncthreads();
-    int before = 0;
-    for (int k = 0; k < w; ++k) before += wsum[k];
-    if (i < n) cnt[i] = before + incl - v;
-    if (threadIdx.x == 1023) bsum[blockIdx.x] = before + incl;
-}
-
 // exclusive scan of the 1024-thread block's values (wave scans, then the
 // wave totals); all threads of the block must call it
 __device__ __forceinline__ int block_exclusive_scan(int v, int* wsum) {
@@ -99,6 +82,44 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wsum) {
     int before = 0;
     for (int k = 0; k < w; ++k) before += wsum[k];
     return before + incl - v;
+}
+
+// The four counts of thread t of a block: cnt[4 (1024 b + t) ...], one 16-byte
+// access where all four lie below n (cnt is 16-byte aligned).
+__device__ __forceinline__ void load4(const int* cnt, int i, int n, int (&v)[4]) {
+    if (i + 3 < n) {
+        const int4 q = *(const int4*)(cnt + i);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+        for (int k = 0; k < 4; ++k) v[k] = i + k < n ? cnt[i + k] : 0;
+    }
+}
+__device__ __forceinline__ void store4(int* a, int i, int n, const int (&v)[4]) {
+    if (i + 3 < n) {
+        *(int4*)(a + i) = make_int4(v[0], v[1], v[2], v[3]);
+    } else {
+        for (int k = 0; k < 4; ++k)
+            if (i + k < n) a[i + k] = v[k];
+    }
+}
+
+// exclusive prefix sum of cnt[0, n) in place, per block of 4096 counts (four
+// per thread); the block totals go to bsum
+__global__ void __launch_bounds__(1024) scan_block_kernel(int* __restrict__ cnt, int* __restrict__ bsum, int n) {
+    __shared__ int wsum[16];
+    const int i = 4 * (blockIdx.x * 1024 + threadIdx.x);
+    int v[4];
+    load4(cnt, i, n, v);
+    const int t = v[0] + v[1] + v[2] + v[3];
+    int acc = block_exclusive_scan(t, wsum);
+    int e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        e[k] = acc;
+        acc += v[k];
+    }
+    store4(cnt, i, n, e);
+    if (threadIdx.x == 1023) bsum[blockIdx.x] = acc;
 }
 
 __global__ void __launch_bounds__(1024) scan_top_kernel(int* __restrict__ bsum, int nb) {
@@ -117,13 +138,19 @@ __global__ void __launch_bounds__(1024) scan_top_kernel(int* __restrict__ bsum, 
     }
 }
 
+// add the block offsets: cnt = cell starts, cursor = a copy for the scatter;
+// cnt[n] = total
 __global__ void __launch_bounds__(1024) scan_add_kernel(int* __restrict__ cnt, int* __restrict__ cursor,
                                                         const int* __restrict__ bsum, int n, int total) {
-    const int i = blockIdx.x * 1024 + threadIdx.x;
+    const int i = 4 * (blockIdx.x * 1024 + threadIdx.x);
     if (i < n) {
-        const int v = cnt[i] + bsum[blockIdx.x];
-        cnt[i] = v;
-        cursor[i] = v;
+        int v[4];
+        load4(cnt, i, n, v);
+        const int b = bsum[blockIdx.x];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += b;
+        store4(cnt, i, n, v);
+        store4(cursor, i, n, v);
     }
     if (i == 0) cnt[n] = total;
 }
@@ -134,22 +161,6 @@ __global__ void __launch_bounds__(256) rep_scatter_kernel(const RepDev* __restri
     if (j >= D.M) return;
     const int slot = atomicAdd(&D.cursor[D.cell[j]], 1);
     D.list[slot] = j;
-}
-
-__global__ void __launch_bounds__(256) rep_order_kernel(const RepDev* __restrict__ Dp) {
-    const RepDev& D = *Dp;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= D.ncell) return;
-    const int s0 = D.cnt[b], s1 = D.cnt[b + 1];
-    for (int s = s0 + 1; s < s1; ++s) {  // insertion sort, cells hold few nodes
-        const int v = D.list[s];
-        int t = s - 1;
-        while (t >= s0 && D.list[t] > v) {
-            D.list[t + 1] = D.list[t];
-            --t;
-        }
-        D.list[t + 1] = v;
-    }
 }
 
 __global__ void __launch_bounds__(256) rep_gather_kernel(const RepDev* __restrict__ Dp) {
@@ -235,11 +246,27 @@ __device__ bool shape_distance(const ShapeDev& S, const double x[3], double& dis
     return true;
 }
 
-__device__ __forceinline__ void soft_sphere(const SoftSphereDev& ss, double d, const double dir[3], double f[3]) {
+// Exact sum of a node's force terms (three components).
+struct ForceSum {
+    long long hi[3] = {0, 0, 0}, lo[3] = {0, 0, 0};
+    bool ok = true;
+    __device__ void add(double fx, double fy, double fz) {
+        const double g[3] = {fx, fy, fz};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            long long h, l;
+            ok = fx_split(g[c], h, l) && ok;
+            hi[c] += h;
+            lo[c] += l;
+        }
+    }
+};
+
+__device__ __forceinline__ void soft_sphere(const SoftSphereDev& ss, double d, const double dir[3], ForceSum& f) {
     const double e = d - ss.offset;
     if (!(e > 0.0 && e < ss.cutoff)) return;
     const double m = ss.a * ss.n * pow(e, -(ss.n + 1.0));
-    for (int c = 0; c < 3; ++c) f[c] += m * dir[c];
+    f.add(m * dir[0], m * dir[1], m * dir[2]);
 }
 
 // neighbour cell offsets along one axis: -1..1, each cell once when the
@@ -265,7 +292,7 @@ __global__ void __launch_bounds__(256) rep_force_kernel(const RepDev* __restrict
     const int j = D.pairs ? D.list[s] : s;
     const int tj = D.type[j];
     const bool pz = !D.walls_z;
-    double f[3] = {0.0, 0.0, 0.0};
+    ForceSum f;
     if (D.pairs) {
         const double p[3] = {D.spos[3 * s], D.spos[3 * s + 1], D.spos[3 * s + 2]};
         const int cell = D.cell[j];
@@ -338,12 +365,15 @@ __global__ void __launch_bounds__(256) rep_force_kernel(const RepDev* __restrict
         }
     }
     R* out = (R*)D.frep;
-    for (int c = 0; c < 3; ++c) out[3 * j + c] = (R)f[c];
+    for (int c = 0; c < 3; ++c) out[3 * j + c] = (R)fx_value(f.hi[c], f.lo[c]);
+    if (!f.ok) atomicOr(D.status, ST_OVERFLOW);
 }
 
+// a[0, n) = v, four per thread (a 16-byte aligned)
 __global__ void __launch_bounds__(256) fill_int_kernel(int* __restrict__ a, int n, int v) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = v;
+    const int i = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+    const int f[4] = {v, v, v, v};
+    if (i < n) store4(a, i, n, f);
 }
 
 template <typename R>
@@ -352,16 +382,15 @@ hipError_t launch_rep_t(const RepDev& h, const RepDev* d, const void* objs, int 
     if (M == 0) return hipSuccess;
     const int gm = (M + 255) / 256;
     if (h.pairs)
-        hipLaunchKernelGGL(fill_int_kernel, dim3((h.ncell + 1 + 255) / 256), dim3(256), 0, s, h.cnt, h.ncell + 1, 0);
+        hipLaunchKernelGGL(fill_int_kernel, dim3((h.ncell + 1 + 1023) / 1024), dim3(256), 0, s, h.cnt, h.ncell + 1, 0);
     hipLaunchKernelGGL((rep_bin_kernel<R>), dim3(nobj), dim3(256), 0, s, (const ObjDev<R>*)objs, d);
     if (h.pairs) {
-        const int nb = (h.ncell + 1023) / 1024;
+        const int nb = (h.ncell + 4095) / 4096;
         hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(1024), 0, s, h.cnt, h.bsum, h.ncell);
         hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, h.bsum, nb);
         hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(1024), 0, s, h.cnt, h.cursor, (const int*)h.bsum,
                            h.ncell, M);
         hipLaunchKernelGGL(rep_scatter_kernel, dim3(gm), dim3(256), 0, s, d);
-        hipLaunchKernelGGL(rep_order_kernel, dim3((h.ncell + 255) / 256), dim3(256), 0, s, d);
         hipLaunchKernelGGL(rep_gather_kernel, dim3(gm), dim3(256), 0, s, d);
     }
     hipLaunchKernelGGL((rep_force_kernel<R>), dim3(gm), dim3(256), 0, s, d);

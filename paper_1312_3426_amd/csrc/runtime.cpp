@@ -634,6 +634,7 @@ int setup_repulsion(oif_ctx* c, size_t real_bytes) {
     R.spos = (double*)c->rep_spos.p;
     R.stype = (unsigned char*)c->rep_stype.p;
     R.frep = c->rep_frep.p;
+    R.status = c->status;
     HIPCALL(c, hipMemcpy(c->rep_desc.p, &R, sizeof(RepDev), hipMemcpyHostToDevice));
     return OIF_OK;
 }
