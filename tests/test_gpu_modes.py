@@ -474,11 +474,21 @@ def test_watchdog_nonfinite_population(oif):
     c.close()
 
 
-def test_watchdog_fixed_point_overflow(oif):
-    say("[aux] watchdog: fixed-point range")
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_watchdog_fixed_point_overflow(oif, prec):
+    """A spread force beyond the fixed-point range: 2^63 units of
+    2^-fixed_point_exp in the FP32 forms, 2^33 in the FP64 form (a huge
+    external force gives the mesh a huge velocity in step 1; the drag of step
+    2 overflows)."""
+    say(f"[aux] watchdog: fixed-point range, {prec}")
     box = synth.config_sphere_fp64(2)
-    box.objects[0].fext = (1e6, 0.0, 0.0)
-    c = oif.Context.from_box(box, precision="fp32", fixed_point_exp=56)
+    if prec == "fp32":
+        box.objects[0].fext = (1e6, 0.0, 0.0)
+        c = oif.Context.from_box(box, precision="fp32", fixed_point_exp=56)
+    else:
+        box.objects[0].fext = (2e6, 0.0, 0.0)
+        box.friction = 1e5
+        c = oif.Context.from_box(box, precision="fp64")
     c.step(1)
     with pytest.raises(oif.OifError) as ei:
         c.step(1)
