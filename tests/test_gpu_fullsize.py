@@ -84,6 +84,17 @@ def test_scale_case_full_size_fp32(oif, orc, tmp_path):
 
 
 @pytest.mark.timeout(600)
+def test_scale_slab_full_size_fp32(oif, orc, tmp_path):
+    """One GPU's share of the scale case split into eight x-slabs: the slab
+    with the most cells (64x256x256, periodic in x), as timed, two steps."""
+    share = max((synth.config_scale_share(8, k, 2) for k in range(8)), key=lambda b: len(b.objects))
+    g, o = run_case(oif, orc, share, "fp32", 2, 67, str(tmp_path / "t.json"))
+    res = check(g, o, "fp32", share.rho0, max(share.nx, share.ny, share.nz))
+    say(f"   {fmt(res)}")
+    assert all(v[3] for v in res.values()), fmt(res)
+
+
+@pytest.mark.timeout(600)
 def test_scale_case_full_size_fp64(oif, orc, tmp_path):
     """The same box in the FP64 form: each population buffer holds 19 x 33.5 M
     doubles (5.1 GB), so every population address lies beyond 32-bit byte
