@@ -17,7 +17,8 @@ positions' round-off into velocity differences of the same size).  ATOL is
 about four times the largest such floor measured over the GPU parity tests
 (|gpu - oracle| / scale_f where the relative bar alone would not hold):
 deviations 2.2e-15, fluid velocity 2.2e-15, displacement 5.3e-16 L, mesh
-velocity 6.2e-16 L.  The FP32 form shares these floors: its positions are
+velocity 6.2e-16 L; the density's deviation rho - rho0 (a sum of 19
+deviations) takes the deviations' floor.  The FP32 form shares these floors: its positions are
 FP64 as well, and the relative bar covers everything above them.
 """
 import json
@@ -28,7 +29,7 @@ import numpy as np
 
 W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
 RTOL = {"fp64": 1e-12, "fp32": 1e-5}
-ATOL = {"delta": 1e-14, "u": 1e-14, "dX": 2.5e-15, "V": 2.5e-15}
+ATOL = {"delta": 1e-14, "u": 1e-14, "dX": 2.5e-15, "V": 2.5e-15, "drho": 1e-14}
 
 
 def say(*a):
@@ -72,7 +73,7 @@ def check(g, o, prec, rho0, box_len, keys=("delta", "u", "dX", "V")):
     """Apply the parity criterion; returns {field: (abs_err, ref_max, bound, ok)}."""
     # mesh velocities inherit the positions' representation floor (~1e-16 of
     # the box length) through the elastic forces, so both take the box length
-    scale = {"delta": rho0, "u": 1.0, "dX": box_len, "V": box_len}
+    scale = {"delta": rho0, "drho": rho0, "u": 1.0, "dX": box_len, "V": box_len}
     out = {}
     for k in keys:
         if k not in g or k not in o or not o[k].size:

@@ -539,6 +539,40 @@ def test_input_validation(oif):
     c.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_set_nodes_and_density_vs_oracle(oif, orc, prec):
+    """oif_object_set_nodes (absolute positions of one object's nodes; here the
+    third of four cells, so the node offset of an object counts) and
+    oif_read_density, against the oracle: FP64 channel from random populations
+    with that cell's nodes displaced, 5 steps; the density compared as a field
+    of its own (rho - rho0, at the deviations' bar)."""
+    say(f"[aux] object_set_nodes + read_density vs oracle ({prec})")
+    box = synth.config_channel_rbc(5, n_cells=4)
+    s = orc.System(box)
+    rng = np.random.default_rng(71)
+    s.n[:] = synth.random_populations(rng, box, amp=1e-3)
+    nvs = [len(box.templates[o.tid].nodes) for o in box.objects]
+    a = sum(nvs[:2])
+    Xn = s.X[a:a + nvs[2]] + 0.05 * rng.standard_normal((nvs[2], 3))
+    s.X[a:a + nvs[2]] = Xn
+    c = oif.Context.from_box(box, precision=prec)
+    c.write_populations(s.n)
+    c.object_set_nodes(2, Xn)
+    X2, _ = c.read_mesh(2)
+    assert np.abs(X2 - Xn).max() <= 4 * np.finfo(float).eps * box.nx
+    X0 = s.X.copy()
+    c.step(5)
+    s.run(5)
+    g, o = gpu_fields(c, box.rho0, X0), oracle_fields(s, X0)
+    g["drho"] = c.read_density() - box.rho0
+    o["drho"] = s.fields()["rho"] - box.rho0
+    c.close()
+    res = check(g, o, prec, box.rho0, box.nx, keys=("delta", "u", "dX", "V", "drho"))
+    say(f"   {fmt(res)}")
+    assert set(res) == {"delta", "u", "dX", "V", "drho"}
+    assert all(v[3] for v in res.values()), fmt(res)
+
+
 @pytest.mark.parametrize("mb", [192, 640, 768])
 def test_membrane_block_sizes_match_oracle(oif, orc, mb):
     """Membrane workgroups of any multiple of 64 (not only powers of two) give
