@@ -573,6 +573,39 @@ def test_set_nodes_and_density_vs_oracle(oif, orc, prec):
     assert all(v[3] for v in res.values()), fmt(res)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zero_friction_decouples(oif, orc, prec):
+    """xi = 0 switches the coupling off (eq. dragforce with a zero
+    coefficient): the fluid evolves bit for bit as the same box without
+    objects, while the deformed, moving cells follow their elastic forces
+    alone, as in the oracle.  Channel, random start, 10 steps."""
+    say(f"[aux] zero friction decouples fluid and cells ({prec})")
+    box = dataclasses.replace(synth.config_channel_rbc(10, n_cells=4), friction=0.0)
+    rng = np.random.default_rng(73)
+    s = orc.System(box)
+    n0 = synth.random_populations(rng, box, amp=1e-3)
+    s.n[:] = n0
+    s.X += 0.02 * rng.standard_normal(s.X.shape)
+    s.V[:] = 1e-4 * rng.standard_normal(s.X.shape)
+    X0 = s.X.copy()
+    c = oif.Context.from_box(box, precision=prec)
+    c.write_populations(n0)
+    c.write_mesh(-1, s.X, s.V)
+    bare = oif.Context.from_box(dataclasses.replace(box, objects=[]), precision=prec)
+    bare.write_populations(n0)
+    c.step(10)
+    bare.step(10)
+    s.run(10)
+    assert np.array_equal(c.read_deviations(), bare.read_deviations()), "the cells moved the fluid"
+    g, o = gpu_fields(c, box.rho0, X0), oracle_fields(s, X0)
+    c.close()
+    bare.close()
+    res = check(g, o, prec, box.rho0, box.nx)
+    say(f"   {fmt(res)}")
+    assert all(v[3] for v in res.values()), fmt(res)
+    assert np.abs(o["dX"]).max() > 1e-3  # the cells did move
+
+
 @pytest.mark.parametrize("mb", [192, 640, 768])
 def test_membrane_block_sizes_match_oracle(oif, orc, mb):
     """Membrane workgroups of any multiple of 64 (not only powers of two) give
