@@ -606,6 +606,42 @@ def test_zero_friction_decouples(oif, orc, prec):
     assert np.abs(o["dX"]).max() > 1e-3  # the cells did move
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_template_options_vs_oracle(oif, orc, prec):
+    """Template and object options against the oracle, one cell each: the
+    linear stretching law alone; bending and local area without stretching,
+    on a template stretched by (1.2, 1, 0.8) (relaxed values taken after the
+    stretch); global area and volume alone (no edge forces at all); no moduli
+    (a passive cell, drag only).  Masses 1, 2, 0.5, 3, rotated placements,
+    deformed moving start, random populations, 20 steps."""
+    say(f"[aux] template options vs oracle ({prec})")
+    x, t = synth.icosphere(2, 3.0)
+    tms = [synth.Template(x, t, ks=0.1, linear=True),
+           synth.Template(x, t, kb=0.03, kal=0.1, stretch=(1.2, 1.0, 0.8)),
+           synth.Template(x, t, kag=0.4, kv=1.0),
+           synth.Template(x, t)]
+    centres = [(8.0, 8.0, 8.0), (24.0, 8.5, 8.0), (8.5, 24.0, 24.0), (24.0, 24.0, 15.5)]
+    masses = [1.0, 2.0, 0.5, 3.0]
+    rng = np.random.default_rng(79)
+    objs = [synth.ObjectSpec(k, np.array(c), synth.random_rotation(rng), m)
+            for k, (c, m) in enumerate(zip(centres, masses))]
+    box = synth.Box(32, 32, 32, templates=tms, objects=objs, steps=20, name="template_options")
+    s = orc.System(box)
+    s.n[:] = synth.random_populations(rng, box, amp=1e-3)
+    s.X += 0.02 * rng.standard_normal(s.X.shape)
+    s.V[:] = 1e-4 * rng.standard_normal(s.X.shape)
+    X0 = s.X.copy()
+    c = oif.Context.from_box(box, precision=prec)
+    c.write_populations(s.n)
+    c.write_mesh(-1, s.X, s.V)
+    c.step(20)
+    s.run(20)
+    res = check(gpu_fields(c, box.rho0, X0), oracle_fields(s, X0), prec, box.rho0, box.nx)
+    c.close()
+    say(f"   {fmt(res)}")
+    assert all(v[3] for v in res.values()), fmt(res)
+
+
 @pytest.mark.parametrize("mb", [192, 640, 768])
 def test_membrane_block_sizes_match_oracle(oif, orc, mb):
     """Membrane workgroups of any multiple of 64 (not only powers of two) give
