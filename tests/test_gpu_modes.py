@@ -612,8 +612,9 @@ def test_template_options_vs_oracle(oif, orc, prec):
     linear stretching law alone; bending and local area without stretching,
     on a template stretched by (1.2, 1, 0.8) (relaxed values taken after the
     stretch); global area and volume alone (no edge forces at all); no moduli
-    (a passive cell, drag only).  Masses 1, 2, 0.5, 3, rotated placements,
-    deformed moving start, random populations, 20 steps."""
+    (a passive cell, drag only).  Masses 1, 2, 0.5, 3, an external force on
+    the second and fourth cell, rotated placements, deformed moving start,
+    random populations, 20 steps."""
     say(f"[aux] template options vs oracle ({prec})")
     x, t = synth.icosphere(2, 3.0)
     tms = [synth.Template(x, t, ks=0.1, linear=True),
@@ -623,8 +624,9 @@ def test_template_options_vs_oracle(oif, orc, prec):
     centres = [(8.0, 8.0, 8.0), (24.0, 8.5, 8.0), (8.5, 24.0, 24.0), (24.0, 24.0, 15.5)]
     masses = [1.0, 2.0, 0.5, 3.0]
     rng = np.random.default_rng(79)
-    objs = [synth.ObjectSpec(k, np.array(c), synth.random_rotation(rng), m)
-            for k, (c, m) in enumerate(zip(centres, masses))]
+    fext = [(0.0, 0.0, 0.0), (2e-5, -1e-5, 5e-6), (0.0, 0.0, 0.0), (-1e-5, 0.0, 3e-5)]
+    objs = [synth.ObjectSpec(k, np.array(c), synth.random_rotation(rng), m, f)
+            for k, (c, m, f) in enumerate(zip(centres, masses, fext))]
     box = synth.Box(32, 32, 32, templates=tms, objects=objs, steps=20, name="template_options")
     s = orc.System(box)
     s.n[:] = synth.random_populations(rng, box, amp=1e-3)
