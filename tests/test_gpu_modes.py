@@ -644,6 +644,42 @@ def test_template_options_vs_oracle(oif, orc, prec):
     assert all(v[3] for v in res.values()), fmt(res)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("path", ["compact", "per-corner"])
+def test_stencils_clamped_at_walls_vs_oracle(oif, orc, prec, path):
+    """A cell whose lowest nodes lie below the first node centre of a z wall
+    (z < 1/2): their stencils reach past the wall and are clamped to the
+    first fluid layer, on both sides the same way (both z corners then take
+    the layer k = 0), and the diagnostics report it.  Compact numbering of the
+    stencil box, and the per-corner path (one node pulled far out of the cell
+    makes the box too large; two steps, as that node snaps back fast).
+    Channel 32x24x16, 5 steps."""
+    say(f"[aux] stencils clamped at a z wall vs oracle ({prec}, {path})")
+    x, t = synth.icosphere(2, 3.0)
+    tm = synth.Template(x, t, **synth.MODULI_DEFAULT)
+    box = synth.Box(32, 24, 16, walls_z=True, templates=[tm],
+                    objects=[synth.ObjectSpec(0, np.array([12.0, 12.0, 3.2]))], steps=5, name="wall_contact")
+    s = orc.System(box)
+    rng = np.random.default_rng(83)
+    s.n[:] = synth.random_populations(rng, box, amp=1e-3)
+    if path == "per-corner":
+        s.X[int(np.argmax(s.X[:, 2])), 0] += 16.0
+    assert s.X[:, 2].min() < 0.5
+    X0 = s.X.copy()
+    c = oif.Context.from_box(box, precision=prec)
+    c.write_populations(s.n)
+    c.write_mesh(-1, s.X, s.V)
+    steps = 5 if path == "compact" else 2
+    c.step(steps)
+    s.run(steps)
+    d = c.diagnostics()
+    res = check(gpu_fields(c, box.rho0, X0), oracle_fields(s, X0), prec, box.rho0, box.nx)
+    c.close()
+    say(f"   clamped={d.clamped}; {fmt(res)}")
+    assert d.clamped == 1 and d.nonfinite == 0 and d.overflow == 0
+    assert all(v[3] for v in res.values()), fmt(res)
+
+
 @pytest.mark.parametrize("mb", [192, 640, 768])
 def test_membrane_block_sizes_match_oracle(oif, orc, mb):
     """Membrane workgroups of any multiple of 64 (not only powers of two) give
