@@ -680,6 +680,39 @@ def test_stencils_clamped_at_walls_vs_oracle(oif, orc, prec, path):
     assert all(v[3] for v in res.values()), fmt(res)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("path", ["compact", "per-corner"])
+def test_cell_across_periodic_corner_vs_oracle(oif, orc, prec, path):
+    """A cell centred on a corner of the periodic box, so that its stencils
+    wrap in x, y and z at once (unwrapped positions on both sides of a
+    periodic face on every axis); compact stencil box and per-corner path (one node
+    pulled out of the cell).  24x20x16, random start, 5 / 2 steps."""
+    say(f"[aux] cell across the periodic corner vs oracle ({prec}, {path})")
+    x, t = synth.icosphere(2, 3.0)
+    tm = synth.Template(x, t, **synth.MODULI_DEFAULT)
+    box = synth.Box(24, 20, 16, templates=[tm], objects=[synth.ObjectSpec(0, np.array([0.3, 19.8, 0.1]))],
+                    steps=5, name="periodic_corner")
+    s = orc.System(box)
+    rng = np.random.default_rng(89)
+    s.n[:] = synth.random_populations(rng, box, amp=1e-3)
+    s.V[:] = 1e-4 * rng.standard_normal(s.X.shape)
+    if path == "per-corner":
+        s.X[int(np.argmax(s.X[:, 0])), 0] += 16.0
+    lo, hi = s.X.min(axis=0), s.X.max(axis=0)
+    assert lo[0] < 0 < hi[0] and lo[1] < box.ny < hi[1] and lo[2] < 0 < hi[2]
+    X0 = s.X.copy()
+    c = oif.Context.from_box(box, precision=prec)
+    c.write_populations(s.n)
+    c.write_mesh(-1, s.X, s.V)
+    steps = 5 if path == "compact" else 2
+    c.step(steps)
+    s.run(steps)
+    res = check(gpu_fields(c, box.rho0, X0), oracle_fields(s, X0), prec, box.rho0, box.nx)
+    c.close()
+    say(f"   {fmt(res)}")
+    assert all(v[3] for v in res.values()), fmt(res)
+
+
 @pytest.mark.parametrize("mb", [192, 640, 768])
 def test_membrane_block_sizes_match_oracle(oif, orc, mb):
     """Membrane workgroups of any multiple of 64 (not only powers of two) give
