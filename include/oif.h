@@ -42,6 +42,9 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+/* The library is built with hidden symbol visibility; the calls declared
+ * here are its only exports. */
+#pragma GCC visibility push(default)
 
 /* error codes */
 #define OIF_OK 0
@@ -511,6 +514,7 @@ int oif_batch_autotune(oif_batch* b, const char* cache_path);
 int oif_batch_step_timed(oif_batch* b, int n_steps, oif_timing* t);
 const char* oif_batch_last_error(const oif_batch* b);
 
+#pragma GCC visibility pop
 #ifdef __cplusplus
 }
 #endif

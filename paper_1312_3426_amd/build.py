@@ -25,6 +25,8 @@ HIPCC_FLAGS = [
     # no packed-FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
+    # host symbols hidden: the C calls of include/oif.h are the only exports
+    "-Xarch_host", "-fvisibility=hidden", "-Xarch_host", "-fvisibility-inlines-hidden",
     "-I" + os.path.join(ROOT, "include"),
 ]
 
@@ -49,7 +51,8 @@ def build(verbose: bool = False) -> str:
         if verbose and lines:
             print("\n".join(lines))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
+           "-Wl,--version-script=" + os.path.join(CSRC, "liboif.map"), "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

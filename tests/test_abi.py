@@ -33,6 +33,20 @@ def test_library_exports_every_declared_symbol(oiflib):
     assert set(names) == set(oiflib.SIGNATURES)
 
 
+def test_library_exports_nothing_else(oiflib):
+    """The dynamic symbol table holds the declared calls and no internal
+    symbol (hidden visibility, version script)."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--defined-only", oiflib.lib()._name], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    assert exported == set(declared_symbols()), sorted(exported ^ set(declared_symbols()))[:10]
+
+
 def test_desc_defaults(oiflib):
     d = oiflib.LatticeDesc()
     assert oiflib.lib().oif_lattice_desc_init(C.byref(d)) == 0
