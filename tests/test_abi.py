@@ -47,6 +47,18 @@ def test_library_exports_nothing_else(oiflib):
     assert exported == set(declared_symbols()), sorted(exported ^ set(declared_symbols()))[:10]
 
 
+def test_readme_c_example_compiles_and_links(oiflib, tmp_path):
+    """The C example of README.md builds against oif.h and links liboif.so
+    (it runs in the GPU tests)."""
+    from example_util import build_readme_example
+    oiflib.lib()
+    try:
+        exe = build_readme_example(tmp_path)
+    except FileNotFoundError:
+        pytest.skip("gcc not available")
+    assert os.path.exists(exe)
+
+
 def test_desc_defaults(oiflib):
     d = oiflib.LatticeDesc()
     assert oiflib.lib().oif_lattice_desc_init(C.byref(d)) == 0

@@ -5,6 +5,7 @@ conservation diagnostics, the watchdog and input validation."""
 import dataclasses
 import json
 import os
+import re
 
 import numpy as np
 import pytest
@@ -711,6 +712,23 @@ def test_cell_across_periodic_corner_vs_oracle(oif, orc, prec, path):
     c.close()
     say(f"   {fmt(res)}")
     assert all(v[3] for v in res.values()), fmt(res)
+
+
+def test_readme_c_example_runs(oif, tmp_path):
+    """The C example of README.md, built with gcc against the C ABI alone:
+    100 steps of one octahedral cell in a fluid driven along x; it exits 0 and
+    the cell has been carried along +x."""
+    import subprocess
+    from example_util import build_readme_example
+    say("[aux] README C example")
+    exe = build_readme_example(tmp_path)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    say("   " + r.stdout.strip() + r.stderr.strip())
+    assert r.returncode == 0, r.stderr
+    m = re.search(r"node 0 at \(([-0-9.]+), ([-0-9.]+), ([-0-9.]+)\), moving at ([-0-9.e+]+) along x", r.stdout)
+    assert m, r.stdout
+    x0, v0 = float(m.group(1)), float(m.group(4))
+    assert 19.0 < x0 < 19.5 and v0 > 0.0
 
 
 @pytest.mark.parametrize("mb", [192, 640, 768])
