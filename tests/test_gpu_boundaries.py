@@ -95,6 +95,31 @@ def test_obstacle_channel_vs_oracle(oif, orc, prec, steps):
     c.close()
 
 
+@pytest.mark.parametrize("prec,bound", [("fp16", 5e-3), ("bf16", 5e-2)])
+@pytest.mark.parametrize("mrt", [False, True])
+def test_obstacle_channel_storage_forms_vs_oracle(oif, orc, prec, bound, mrt):
+    """The obstacle channel (bounce-back from solid nodes, the moving inlet's
+    wall term, ten cells) with FP16 / BF16 storage of the deviations, BGK and
+    MRT collision: velocity error after 100 steps (MRT: 10, the oracle's
+    mode-space collision is slow) against the FP64 oracle, relative to max |u|,
+    within the bounds the plain channel meets in these forms."""
+    steps = 10 if mrt else 100
+    box = synth.config_obstacle_channel(steps)
+    if mrt:
+        box.mrt = (0.25, -0.4, 0.0, 0.0)
+    say(f"[obstacles] {box.name} {prec}{' mrt' if mrt else ''}")
+    s = orc.System(box)
+    X0 = s.X.copy()
+    c = oif.Context.from_box(box, precision=prec)
+    c.step(steps)
+    s.run(steps)
+    g, o = gpu_fields(c, box.rho0, X0), oracle_fields(s, X0)
+    c.close()
+    e = {k: rel(g[k], o[k]) for k in ("u", "delta", "dX", "V")}
+    say(f"   step {steps}: " + ", ".join(f"{a}={b:.2e}" for a, b in e.items()))
+    assert e["u"] <= bound
+
+
 def test_obstacle_batch_matches_single_boxes(oif):
     boxes = [synth.config_obstacle_channel(10, seed=6), synth.config_channel_rbc(10)]
     singles = []
