@@ -107,6 +107,34 @@ def test_scale_case_full_size_fp64(oif, orc, tmp_path):
 
 
 @pytest.mark.timeout(600)
+def test_scale_case_fp64_momentum_budget_and_mass(oif):
+    """512x256x256, 5000 cells, FP64 form, with the stretching and volume
+    moduli only (forces that sum to zero over each closed mesh): after three
+    steps from rest the fluid's and the meshes' momentum together grew by
+    3 N g and the mass is unchanged, in the FP64 sums of the diagnostics over
+    33.5 M lattice nodes and 3.2 M mesh nodes."""
+    box = synth.config_scale(3)
+    t = box.templates[0]
+    t.kb = t.kal = t.kag = 0.0
+    say(f"[fullsize] {box.name} fp64: momentum budget and mass, 3 steps")
+    c = oif.Context.from_box(box, precision="fp64")
+    d0 = c.diagnostics()
+    c.step(3)
+    d1 = c.diagnostics()
+    c.close()
+    P0 = np.array(d0.momentum_fluid) + np.array(d0.momentum_mesh)
+    P1 = np.array(d1.momentum_fluid) + np.array(d1.momentum_mesh)
+    want = 3 * box.n_nodes * np.array(box.g)
+    err = np.abs((P1 - P0) - want).max()
+    say(f"   momentum change {P1 - P0} against {want}: error {err:.2e}; mesh momentum {np.array(d1.momentum_mesh)}; "
+        f"mass {d1.mass!r} against {box.n_nodes * box.rho0!r}")
+    assert np.abs(np.array(d1.momentum_mesh)).max() > 0.0  # the fluid has dragged the cells
+    assert err <= 1e-12 * np.abs(want).max()
+    assert d1.mass == pytest.approx(box.n_nodes * box.rho0, rel=1e-14)
+    assert d1.nonfinite == 0 and d1.clamped == 0 and d1.overflow == 0
+
+
+@pytest.mark.timeout(600)
 def test_scale_case_full_size_fp16(oif, orc, tmp_path):
     """512x256x256 box, 5000 cells, FP16 storage of the deviations (x 2^12),
     one step from the random start.  Each stored deviation is rounded once to
