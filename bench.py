@@ -56,6 +56,7 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 BYTES_POP = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
 LB_SOURCES = ("paper_1312_3426_amd/csrc/lb_kernels.hip", "paper_1312_3426_amd/csrc/lb_device.h",
+              "paper_1312_3426_amd/csrc/fixed_point.h",
               "paper_1312_3426_amd/csrc/device_common.h",
               "paper_1312_3426_amd/csrc/oif_device.h")
 TRAFFIC_RECORD = "profiles/lb_kernel_fp32_sphere642x500_256x128x128.md"

@@ -96,11 +96,15 @@ typedef struct oif_batch oif_batch;
  *   fp16_scale_exp  FP16 storage: deviations n_i - w_i rho0 are stored times
  *                   2^fp16_scale_exp, in [0, 24]
  *   fixed_point_exp FP32 modes: the coupling force density is accumulated in
- *                   int64 with resolution 2^-fixed_point_exp, in [16, 56]
+ *                   int64 with resolution 2^-fixed_point_exp, in [16, 56];
+ *                   each value added must lie below 2^(55 - fixed_point_exp)
+ *                   (else OIF_E_OVERFLOW), so up to 256 of them can meet in
+ *                   one lattice node without leaving the int64 range
  *                   (the FP64 mode accumulates each component as two int64
  *                   sums, of its multiples of 2^-30 and of the remainders in
  *                   units of 2^-80: exact and order-independent sums too, a
- *                   value rounded only below 2^-80, |value| < 2^33)
+ *                   value rounded only below 2^-80, |value| < 2^25 with the
+ *                   same room for 256 values)
  *   device          HIP device ordinal
  * Fill with oif_lattice_desc_init first; it sets tau 1, rho0 1, friction 0,
  * FP32, fp16_scale_exp 12, fixed_point_exp 40, device 0, sizes 0. */

@@ -12,10 +12,12 @@ namespace oif {
 namespace dev {
 
 // v = hi 2^-30 + lo 2^-80 + (a rounding below 2^-81); false (and zeros) for
-// |v| >= 2^33 or a non-finite v.  v - hi 2^-30 is exact: hi 2^-30 is v
-// rounded to a multiple of 2^-30, so it is 0 or within a factor 2 of v.
+// |v| >= 2^25 or a non-finite v.  The bound keeps |hi| below 2^55, so a sum
+// of up to 256 values cannot leave the int64 range (|lo| stays below 2^49).
+// v - hi 2^-30 is exact: hi 2^-30 is v rounded to a multiple of 2^-30, so it
+// is 0 or within a factor 2 of v.
 __device__ __forceinline__ bool fx_split(double v, long long& hi, long long& lo) {
-    if (!(fabs(v) < 0x1p33)) {
+    if (!(fabs(v) < 0x1p25)) {
         hi = lo = 0;
         return false;
     }

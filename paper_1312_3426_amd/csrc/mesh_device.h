@@ -27,7 +27,8 @@ struct Acc {
     static constexpr int SLOT = 4;  // words per node of G (x, y, z, unused)
     __device__ static void convert(float v, double scale, T* out, unsigned& fl) {
         const double a = (double)v * scale;
-        if (!(fabs(a) < 4.0e18)) {  // out of range or not finite
+        // below 2^55 units, so a sum of up to 256 values stays in the int64 range
+        if (!(fabs(a) < 0x1p55)) {  // out of range or not finite
             fl |= ST_OVERFLOW;
             out[0] = 0ull;
             return;
@@ -42,7 +43,8 @@ struct Acc<PREC_FP64> {
     // multiple of 2^-30 and the remainder in units of 2^-80.  Both integer
     // sums are exact, so the spread force does not depend on the order of the
     // additions (as in the FP32 forms); a value is rounded only below 2^-80,
-    // and |value| < 2^33 (else the overflow flag).
+    // and |value| < 2^25 (else the overflow flag), which leaves room for
+    // sums of 256 values.
     typedef unsigned long long T;
     static constexpr int WC = 2;
     static constexpr int SLOT = 8;  // x hi, x lo, y hi, y lo, z hi, z lo, two unused

@@ -477,10 +477,10 @@ def test_watchdog_nonfinite_population(oif):
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_watchdog_fixed_point_overflow(oif, prec):
-    """A spread force beyond the fixed-point range: 2^63 units of
-    2^-fixed_point_exp in the FP32 forms, 2^33 in the FP64 form (a huge
-    external force gives the mesh a huge velocity in step 1; the drag of step
-    2 overflows)."""
+    """A spread force beyond the fixed-point range: 2^55 units of
+    2^-fixed_point_exp in the FP32 forms, 2^25 in the FP64 form (room for sums
+    of 256 such values; a huge external force gives the mesh a huge velocity
+    in step 1, the drag of step 2 overflows)."""
     say(f"[aux] watchdog: fixed-point range, {prec}")
     box = synth.config_sphere_fp64(2)
     if prec == "fp32":
