@@ -296,7 +296,8 @@ int oif_euler_to_rot(double rx, double ry, double rz, double R[9]);
 int oif_object_set_force(oif_ctx* ctx, int oid, const double f[3]);
 
 /* Translate object oid so that the mean of its nodes is at o (object
- * customisation: origin). */
+ * customisation: origin).  Errors: OIF_E_ARG for a non-finite o or
+ * |o| > 1e6 (as in oif_object_add), or an unknown oid. */
 int oif_object_set_origin(oif_ctx* ctx, int oid, const double o[3]);
 
 /* Replace the node positions of object oid (object customisation:

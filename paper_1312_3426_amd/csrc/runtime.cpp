@@ -1759,6 +1759,8 @@ int oif_object_set_origin(oif_ctx* c, int oid, const double o[3]) {
     int rc = check_obj(c, oid);
     if (rc) return rc;
     if (!o) return OIF_E_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(o[a]) || std::fabs(o[a]) > 1e6) return fail(c, OIF_E_ARG, "origin must be finite, |o| <= 1e6");
     if ((rc = pull_mesh(c))) return rc;
     const Object& ob = c->obj[oid];
     double mean[3] = {0, 0, 0};

@@ -529,6 +529,30 @@ def test_input_validation(oif):
     assert np.allclose(a.origin, 8.0, atol=1e-12)
     c.object_set_origin(0, (5.0, 6.0, 7.0))
     assert np.allclose(c.object_analyze(0).origin, (5, 6, 7), atol=1e-12)
+    # refused arguments leave the state as it was
+    for bad in ((np.nan, 0.0, 0.0), (0.0, 2e6, 0.0)):
+        with pytest.raises(oif.OifError) as ei:
+            c.object_set_origin(0, bad)
+        assert ei.value.code == oif.E_ARG
+    with pytest.raises(oif.OifError) as ei:
+        c.object_set_origin(1, (5.0, 6.0, 7.0))
+    assert ei.value.code == oif.E_ARG
+    Xb = c.read_mesh(0)[0]
+    Xbad = Xb.copy()
+    Xbad[3, 1] = np.inf
+    with pytest.raises(oif.OifError) as ei:
+        c.object_set_nodes(0, Xbad)
+    assert ei.value.code == oif.E_ARG
+    assert np.array_equal(c.read_mesh(0)[0], Xb)
+    assert np.allclose(c.object_analyze(0).origin, (5, 6, 7), atol=1e-12)
+    with pytest.raises(oif.OifError) as ei:
+        c.object_set_force(0, (0.0, np.inf, 0.0))
+    assert ei.value.code == oif.E_ARG
+    with pytest.raises(oif.OifError) as ei:
+        c.step(-1)
+    assert ei.value.code == oif.E_ARG
+    c.step(0)
+    assert c.info().steps_done == 0
     # launch shapes: lattice blocks are powers of two, membrane blocks multiples of 64
     for lb, mb in ((100, -1), (2048, -1), (-1, 100), (-1, 1088), (-1, 32)):
         with pytest.raises(oif.OifError) as ei:
