@@ -1654,13 +1654,14 @@ int oif_boundary_rhomboid(oif_ctx* c, const double corner[3], const double a[3],
         sh.cof[2][k] = ab[k];
     }
     sh.det = det;
-    c->shapes.push_back(sh);
     // the node's coordinates (s, t, u) along a, b, c by Cramer's rule
-    return add_boundary(c, velocity, id, [&](double x, double y, double z) {
+    const int rc = add_boundary(c, velocity, id, [&](double x, double y, double z) {
         const double r[3] = {x - o[0], y - o[1], z - o[2]};
         const double s = vdot(r, BC) / det, t = vdot(r, CA) / det, u = vdot(r, AB) / det;
         return s >= 0.0 && s <= 1.0 && t >= 0.0 && t <= 1.0 && u >= 0.0 && u <= 1.0;
     });
+    if (rc == OIF_OK) c->shapes.push_back(sh);  // a refused boundary leaves no shape behind
+    return rc;
 }
 
 int oif_boundary_wall(oif_ctx* c, const double normal[3], double dist, const double velocity[3], int* id) {
@@ -1672,11 +1673,12 @@ int oif_boundary_wall(oif_ctx* c, const double normal[3], double dist, const dou
     sh.kind = 1;
     for (int k = 0; k < 3; ++k) sh.n[k] = normal[k] / len;
     sh.dist = dist;
-    c->shapes.push_back(sh);
-    return add_boundary(c, velocity, id, [&](double x, double y, double z) {
+    const int rc = add_boundary(c, velocity, id, [&](double x, double y, double z) {
         const double r[3] = {x, y, z};
         return vdot(r, n) / len - dist < 0.0;
     });
+    if (rc == OIF_OK) c->shapes.push_back(sh);
+    return rc;
 }
 
 int oif_boundary_clear(oif_ctx* c) {

@@ -340,6 +340,29 @@ def test_repulsion_walls_shapes_and_verlet_vs_oracle(oif, orc):
     _run_vs_oracle(oif, orc, direct, "fp64", (1, 6), "direct")
 
 
+def test_refused_boundary_leaves_no_shape(oif):
+    """A boundary call refused for its velocity leaves the obstacle shapes
+    that the wall repulsion acts against as they were: steps afterwards give
+    the bits of a context that never made the call (the refused half-space
+    and block would lie next to the cells)."""
+    say("[repulsion] refused boundaries leave no shape")
+    box = _contact_box(walls=True)
+    ref = oif.Context.from_box(box, precision="fp32")
+    c = oif.Context.from_box(box, precision="fp32")
+    with pytest.raises(oif.OifError) as ei:
+        c.boundary_wall((1.0, 0.0, 0.0), 7.5, (np.nan, 0.0, 0.0))
+    assert ei.value.code == oif.E_ARG
+    with pytest.raises(oif.OifError) as ei:
+        c.boundary_rhomboid((7.0, 9.8, 7.0), (2.0, 0.0, 0.0), (0.0, 2.0, 0.0), (0.0, 0.0, 2.0), (0.0, np.inf, 0.0))
+    assert ei.value.code == oif.E_ARG
+    ref.step(5)
+    c.step(5)
+    (X1, V1), (X2, V2) = ref.read_mesh(-1), c.read_mesh(-1)
+    ref.close()
+    c.close()
+    assert np.array_equal(X1, X2) and np.array_equal(V1, V2)
+
+
 def test_repulsion_same_type_and_minimum_image(oif, orc):
     """Both cells of type 0 with a 0-0 interaction (also acting inside each
     cell), placed across the periodic x boundary."""
