@@ -75,17 +75,31 @@ diag_lattice_kernel(const BoxDev* __restrict__ B, int parity, double* __restrict
     }
 }
 
-__global__ void diag_final_kernel(const double* __restrict__ part, int nlat, int nmesh,
-                                  double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double a[5] = {0, 0, 0, 0, 0}, b[5] = {0, 0, 0, 0, 0};
-    for (int k = 0; k < nlat; ++k)
-        for (int c = 0; c < 5; ++c) a[c] += part[5 * k + c];
-    for (int k = 0; k < nmesh; ++k)
-        for (int c = 0; c < 5; ++c) b[c] += part[5 * (nlat + k) + c];
-    for (int c = 0; c < 5; ++c) {
-        out[c] = a[c];
-        out[5 + c] = b[c];
+// The five sums of the lattice blocks' partials and of the objects' partials
+// in a fixed order (thread t adds partials t, t + 256, ... in turn, then a fixed
+// tree over the 256 threads): the same bits on every run.
+__global__ void __launch_bounds__(256) diag_final_kernel(const double* __restrict__ part, int nlat, int nmesh,
+                                                         double* __restrict__ out) {
+    __shared__ double red[5][256];
+    const int t = threadIdx.x;
+    for (int g = 0; g < 2; ++g) {
+        const double* p = part + (g ? 5 * (size_t)nlat : 0);
+        const int n = g ? nmesh : nlat;
+        double s[5] = {0, 0, 0, 0, 0};
+        for (int k = t; k < n; k += 256)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) s[c] += p[5 * (size_t)k + c];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) red[c][t] = s[c];
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (t < w)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) red[c][t] += red[c][t + w];
+            __syncthreads();
+        }
+        if (t < 5) out[5 * g + t] = red[t][0];
+        __syncthreads();
     }
 }
 
@@ -222,7 +236,7 @@ hipError_t launch_diag_lattice(const BoxDev* box_dev, int precision, int parity,
 }
 
 hipError_t launch_diag_final(const double* partials, int nlat, int nmesh, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partials, nlat, nmesh, out);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, partials, nlat, nmesh, out);
     return hipGetLastError();
 }
 
