@@ -9,7 +9,7 @@ import pytest
 
 from paper_1312_3426_amd import synth
 
-from gpu_util import W, check, fmt, gpu_fields, oracle_fields, say
+from gpu_util import W, check, fmt, gpu_fields, oracle_fields, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -361,6 +361,37 @@ def test_refused_boundary_leaves_no_shape(oif):
     ref.close()
     c.close()
     assert np.array_equal(X1, X2) and np.array_equal(V1, V2)
+
+
+@pytest.mark.parametrize("prec,bound", [("fp16", 5e-3), ("bf16", 5e-2)])
+def test_mixed_feature_batch_storage_forms_vs_oracle(oif, orc, prec, bound):
+    """One batch in FP16 / BF16 storage whose boxes each switch on other
+    options: velocity Verlet (channel), soft-sphere repulsion with MRT (two
+    cells in contact), the conservative force model (sphere).  Each box
+    against the FP64 oracle after 20 steps: velocity error relative to max |u|
+    within the storage form's bound for the plain channel, and the mesh
+    fields close to the oracle's."""
+    say(f"[batch] mixed options, {prec} storage")
+    chan = synth.config_channel_rbc(20, n_cells=4)
+    chan.integrator = "verlet"
+    contact = _contact_box(mrt=RATES["ghosts"])
+    contact.name = "contact_repulsion_mrt"
+    sph = synth.config_sphere_fp64(20)
+    sph.templates[0].model = "conservative"
+    boxes = [chan, contact, sph]
+    systems = [orc.System(b) for b in boxes]
+    X0s = [s.X.copy() for s in systems]
+    ctxs = [oif.Context.from_box(b, precision=prec) for b in boxes]
+    B = oif.Batch(ctxs)
+    B.step(20)
+    B.close()
+    for b, s, X0, c in zip(boxes, systems, X0s, ctxs):
+        s.run(20)
+        g, o = gpu_fields(c, b.rho0, X0), oracle_fields(s, X0)
+        c.close()
+        e = {k: rel(g[k], o[k]) for k in ("u", "delta", "dX", "V")}
+        say(f"   {b.name}: " + ", ".join(f"{a}={v:.2e}" for a, v in e.items()))
+        assert e["u"] <= bound and e["dX"] <= bound and e["V"] <= bound, (b.name, e)
 
 
 def test_repulsion_same_type_and_minimum_image(oif, orc):
