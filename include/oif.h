@@ -252,8 +252,10 @@ int oif_bind_device_buffers(oif_ctx* ctx, void* f0, void* f1, size_t bytes);
  * (walls_z) are separate and act first.
  * Rhomboid: {corner + s a + t b + u c : s, t, u in [0, 1]}, the edge vectors
  * linearly independent.  Wall: the half-space n . x < dist with n = normal /
- * |normal|.  Errors: OIF_E_ARG (non-finite or degenerate shape, 255 boundaries
- * already), OIF_E_NOMEM, OIF_E_HIP. */
+ * |normal|.  Each shape also bounds the soft-sphere wall interactions
+ * (oif_set_wall_soft_sphere).  Errors: OIF_E_ARG (non-finite or degenerate
+ * shape, non-finite velocity, 255 boundaries already; such a call changes
+ * nothing), OIF_E_NOMEM, OIF_E_HIP. */
 int oif_boundary_rhomboid(oif_ctx* ctx, const double corner[3], const double a[3], const double b[3],
                           const double c[3], const double velocity[3], int* id);
 int oif_boundary_wall(oif_ctx* ctx, const double normal[3], double dist, const double velocity[3], int* id);
