@@ -102,3 +102,14 @@ def test_product_does_not_import_oracle():
             txt = open(os.path.join(ROOT, "oracle", f)).read()
             assert "import paper_1312_3426_amd" not in txt and "from paper_1312_3426_amd" not in txt, f
             assert "oif_device" not in txt and "kernels.hip" not in txt, f
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message and
+    status 2 before touching any device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
