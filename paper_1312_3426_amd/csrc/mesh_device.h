@@ -743,11 +743,11 @@ __device__ __forceinline__ void mesh_object(const ObjDev<typename Prec<P>::R>& O
                         continue;
                     }
 #pragma unroll
-                    for (int i = 0; i < 19; ++i)
-                        dd[i] = dec<P>(pop_load(pop, i, qk), inv);
+                    for (int j = 0; j < 19; ++j)
+                        dd[j] = dec<P>(pop_load(pop, j, qk), inv);
                     R dr = 0;
 #pragma unroll
-                    for (int i = 0; i < 19; ++i) dr += dd[i];
+                    for (int j = 0; j < 19; ++j) dr += dd[j];
                     const R jx = dd[1] - dd[2] + dd[7] - dd[8] + dd[9] - dd[10] + dd[11] - dd[12] + dd[13] - dd[14];
                     const R jy = dd[3] - dd[4] + dd[7] - dd[8] - dd[9] + dd[10] + dd[15] - dd[16] + dd[17] - dd[18];
                     const R jz = dd[5] - dd[6] + dd[11] - dd[12] - dd[13] + dd[14] + dd[15] - dd[16] - dd[17] + dd[18];

@@ -263,8 +263,8 @@ int build_template(const double* nodes, int nv, const int32_t* tris, int nt, con
                     const double y = R[3 * a] * d[0] + R[3 * a + 1] * d[1] + R[3 * a + 2] * d[2];
                     lo[a] = (int)std::floor(y + off[a] + 0.5 * side - 0.5);  // >= 0 by construction
                 }
-                for (int k = 0; k < 8; ++k) {
-                    const size_t q = ((size_t)(lo[2] + (k >> 2)) * sd + lo[1] + ((k >> 1) & 1)) * sd + lo[0] + (k & 1);
+                for (int cr = 0; cr < 8; ++cr) {
+                    const size_t q = ((size_t)(lo[2] + (cr >> 2)) * sd + lo[1] + ((cr >> 1) & 1)) * sd + lo[0] + (cr & 1);
                     if (q < mark.size() && !mark[q]) {
                         mark[q] = 1;
                         ++cnt;
@@ -309,7 +309,7 @@ int build_template(const double* nodes, int nv, const int32_t* tris, int nt, con
         };
         halve(0, nv, K);
         T.smax = 0;
-        for (int k = 0; k < K; ++k) T.smax = std::max(T.smax, T.slice_off[k + 1] - T.slice_off[k]);
+        for (int sl = 0; sl < K; ++sl) T.smax = std::max(T.smax, T.slice_off[sl + 1] - T.slice_off[sl]);
     }
     // per-node incidence lists (CSR)
     std::vector<std::vector<std::array<int, 2>>> ei(nv);
