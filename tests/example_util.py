@@ -1,4 +1,5 @@
-"""Builds the C example of README.md against include/oif.h and liboif.so."""
+"""The examples of README.md: the C program built against include/oif.h and
+liboif.so, the Python program's source."""
 import os
 import re
 import shutil
@@ -25,3 +26,11 @@ def build_readme_example(out_dir) -> str:
                     "-L" + lib_dir, "-loif", "-Wl,-rpath," + lib_dir, "-o", exe], check=True,
                    capture_output=True, text=True)
     return exe
+
+
+def readme_python_example() -> str:
+    """The Python program that follows the `example.py` marker in README.md."""
+    text = open(os.path.join(ROOT, "README.md")).read()
+    m = re.search(r"<!-- example.py -->\n```python\n(.*?)```", text, re.S)
+    assert m, "README.md holds no Python example"
+    return m.group(1)

@@ -755,6 +755,20 @@ def test_readme_c_example_runs(oif, tmp_path):
     assert 19.0 < x0 < 19.5 and v0 > 0.0
 
 
+def test_readme_python_example_runs(oif):
+    """The Python example of README.md runs in a child process and prints a
+    rate, the kernel times and finite fields."""
+    import subprocess
+    import sys
+    from example_util import ROOT, readme_python_example
+    say("[aux] README Python example")
+    r = subprocess.run([sys.executable, "-c", readme_python_example()], capture_output=True, text=True,
+                       timeout=300, cwd=ROOT, env=dict(os.environ, PYTHONPATH=ROOT))
+    say("   " + r.stdout.strip().replace("\n", " | ") + r.stderr[-2000:])
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert re.search(r"^\d+ MLUPS$", r.stdout, re.M) and "lattice kernel" in r.stdout and "max |u|" in r.stdout
+
+
 @pytest.mark.parametrize("mb", [192, 640, 768])
 def test_membrane_block_sizes_match_oracle(oif, orc, mb):
     """Membrane workgroups of any multiple of 64 (not only powers of two) give
