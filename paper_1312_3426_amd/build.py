@@ -24,7 +24,7 @@ HIPCC_FLAGS = [
     "-munsafe-fp-atomics",
     # no packed-FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-result",
+    "-Wall", "-Wextra", "-Wshadow", "-Wno-unused-result",
     # host symbols hidden: the C calls of include/oif.h are the only exports
     "-Xarch_host", "-fvisibility=hidden", "-Xarch_host", "-fvisibility-inlines-hidden",
     "-I" + os.path.join(ROOT, "include"),
