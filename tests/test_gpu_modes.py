@@ -221,18 +221,20 @@ def test_batch_matches_single_boxes(oif):
         c.close()
 
 
-def test_batch_box_vs_oracle(oif, orc):
-    """A batched box with 162/642/2562-node spheres against the oracle."""
-    say("[modes] batch box 0 vs oracle (fp32)")
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_box_vs_oracle(oif, orc, prec):
+    """Two batched boxes with 162/642/2562-node spheres (the largest split over
+    several workgroups) against the oracle, 30 steps."""
+    say(f"[modes] batch boxes 0-1 vs oracle ({prec})")
     boxes = synth.config_batch(n_boxes=2, steps=30)
-    ctxs = [oif.Context.from_box(bx, precision="fp32") for bx in boxes]
+    ctxs = [oif.Context.from_box(bx, precision=prec) for bx in boxes]
     B = oif.Batch(ctxs)
     B.step(30)
     for bx, c in zip(boxes, ctxs):
         s = orc.System(bx)
         X0 = s.X.copy()
         s.run(30)
-        res = check(gpu_fields(c, bx.rho0, X0), oracle_fields(s, X0), "fp32", bx.rho0, max(bx.nx, bx.ny, bx.nz))
+        res = check(gpu_fields(c, bx.rho0, X0), oracle_fields(s, X0), prec, bx.rho0, max(bx.nx, bx.ny, bx.nz))
         say(f"   {bx.name} ({len(bx.objects)} cells): {fmt(res)}")
         assert all(v[3] for v in res.values())
     B.close()
