@@ -155,6 +155,33 @@ def test_storage_forms_velocity_error(oif, orc, prec, bound):
     assert e["u"] <= bound
 
 
+def test_fp16_scale_exponent_vs_oracle(oif, orc):
+    """FP16 storage keeps the deviations times 2^s.  On the channel case from
+    rest the velocity error against the oracle stays within the FP16 bound
+    for s = 8, 12 and 20 after 5 and after 100 steps.  Unscaled (s = 0) the
+    early deviations (1e-7 to 1e-5, below FP16's smallest normal 6.1e-5) are
+    stored as subnormals with an absolute step of 6e-8, and the error after
+    5 steps is several times that of s = 12: the reason the form scales."""
+    box = synth.config_channel_rbc(100)
+    s = orc.System(box)
+    ref = {}
+    for k, n in ((5, 5), (100, 95)):
+        s.run(n)
+        ref[k] = s.fields()["u"]
+    err = {}
+    for sexp in (0, 8, 12, 20):
+        c = oif.Context.from_box(box, precision="fp16", fp16_scale_exp=sexp)
+        c.step(5)
+        e5 = rel(c.read_velocity(), ref[5])
+        c.step(95)
+        err[sexp] = (e5, rel(c.read_velocity(), ref[100]))
+        c.close()
+    say("[coupled] channel fp16, velocity error after 5 / 100 steps by scale exponent: "
+        + ", ".join(f"s={k}: {a:.2e} / {b:.2e}" for k, (a, b) in err.items()))
+    assert all(max(err[k]) <= 5e-3 for k in (8, 12, 20))
+    assert err[0][0] > 2 * err[12][0]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_fp32_deterministic(oif, prec):
     """Fixed-point spreading (one int64 word per component in the FP32 forms,
