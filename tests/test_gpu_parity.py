@@ -182,6 +182,34 @@ def test_fp16_scale_exponent_vs_oracle(oif, orc):
     assert err[0][0] > 2 * err[12][0]
 
 
+def test_fixed_point_exponent_vs_oracle(oif, orc):
+    """The FP32 forms sum the spread coupling force in int64 units of
+    2^-e.  On the channel case (deformed, moving start so the drag is strong
+    from step 1), e = 40 (the default), 48 and 56 meet the FP32 parity bar
+    against the oracle after 20 steps; a coarse e = 24 quantises each spread
+    value to 6e-8 and the error grows well past the default's."""
+    box = synth.config_channel_rbc(20)
+    rng = np.random.default_rng(97)
+    sysm = orc.System(box)
+    X0 = sysm.X + 0.01 * rng.standard_normal(sysm.X.shape)
+    V0 = 1e-4 * rng.standard_normal(sysm.X.shape)
+    sysm.X[:] = X0
+    sysm.V[:] = V0
+    sysm.run(20)
+    o = oracle_fields(sysm, X0)
+    res = {}
+    for e in (24, 40, 48, 56):
+        c = oif.Context.from_box(box, precision="fp32", fixed_point_exp=e)
+        c.write_mesh(-1, X0, V0)
+        c.step(20)
+        res[e] = check(gpu_fields(c, box.rho0, X0), o, "fp32", box.rho0, box.nx)
+        c.close()
+        say(f"[coupled] channel fp32, fixed point 2^-{e}: {fmt(res[e])}")
+    for e in (40, 48, 56):
+        assert all(v[3] for v in res[e].values()), (e, fmt(res[e]))
+    assert res[24]["V"][0] > 10 * res[40]["V"][0]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_fp32_deterministic(oif, prec):
     """Fixed-point spreading (one int64 word per component in the FP32 forms,
