@@ -2,6 +2,8 @@
 same seeded inputs.  Criterion (see gpu_util): max|gpu - oracle| <=
 RTOL * max|oracle| + ATOL * scale, RTOL = 1e-12 (FP64 form) or 1e-5 (FP32
 form); the FP16/BF16 storage forms against the bounds stated in their tests."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -208,6 +210,37 @@ def test_fixed_point_exponent_vs_oracle(oif, orc):
     for e in (40, 48, 56):
         assert all(v[3] for v in res[e].values()), (e, fmt(res[e]))
     assert res[24]["V"][0] > 10 * res[40]["V"][0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["sphere", "obstacles"])
+def test_rest_density_and_tau_vs_oracle(oif, orc, prec, case):
+    """A rest density other than 1 and relaxation times other than 1 in the
+    coupled step: the deviations are stored about w_i rho0, the interpolated
+    velocity divides by rho0 + sum of deviations, the moving inlet's wall term
+    carries rho0.  Sphere (rho0 0.8, tau 1.3, deformed moving start) and the
+    obstacle channel with its moving inlet (rho0 1.7, tau 0.7), 10 steps."""
+    if case == "sphere":
+        box = dataclasses.replace(synth.config_sphere_fp64(10), rho0=0.8, tau=1.3)
+    else:
+        box = dataclasses.replace(synth.config_obstacle_channel(10), rho0=1.7, tau=0.7)
+    say(f"[coupled] {box.name}: rho0 {box.rho0}, tau {box.tau}, {prec}")
+    rng = np.random.default_rng(101)
+    sysm = orc.System(box)
+    X0 = sysm.X + (0.01 * rng.standard_normal(sysm.X.shape) if case == "sphere" else 0.0)
+    V0 = 1e-4 * rng.standard_normal(sysm.X.shape)
+    sysm.X[:] = X0
+    sysm.V[:] = V0
+    ctx = oif.Context.from_box(box, precision=prec)
+    ctx.write_mesh(-1, X0, V0)
+    ctx.step(10)
+    sysm.run(10)
+    res = check(gpu_fields(ctx, box.rho0, X0), oracle_fields(sysm, X0), prec, box.rho0, max(box.nx, box.ny, box.nz))
+    d = ctx.diagnostics()
+    ctx.close()
+    say(f"   {fmt(res)}")
+    assert_ok(res, case)
+    assert d.mass == pytest.approx(float(sysm.fields()["rho"].sum()), rel=1e-12 if prec == "fp64" else 1e-6)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
