@@ -218,10 +218,11 @@ def test_rest_density_and_tau_vs_oracle(oif, orc, prec, case):
     """A rest density other than 1 and relaxation times other than 1 in the
     coupled step: the deviations are stored about w_i rho0, the interpolated
     velocity divides by rho0 + sum of deviations, the moving inlet's wall term
-    carries rho0.  Sphere (rho0 0.8, tau 1.3, deformed moving start) and the
-    obstacle channel with its moving inlet (rho0 1.7, tau 0.7), 10 steps."""
+    carries rho0.  Sphere (rho0 0.8, tau 1.3, a body force along all three
+    axes, deformed moving start) and the obstacle channel with its moving
+    inlet (rho0 1.7, tau 0.7), 10 steps."""
     if case == "sphere":
-        box = dataclasses.replace(synth.config_sphere_fp64(10), rho0=0.8, tau=1.3)
+        box = dataclasses.replace(synth.config_sphere_fp64(10), rho0=0.8, tau=1.3, g=(1e-5, -2e-5, 3e-5))
     else:
         box = dataclasses.replace(synth.config_obstacle_channel(10), rho0=1.7, tau=0.7)
     say(f"[coupled] {box.name}: rho0 {box.rho0}, tau {box.tau}, {prec}")
