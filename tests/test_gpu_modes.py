@@ -371,6 +371,39 @@ def test_split_meshes_verlet_vs_oracle(oif, orc, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_split_meshes_conservative_vs_oracle(oif, orc, prec):
+    """The conservative force model (gradient bending, balanced area forces)
+    on every template of a batching box whose 2562-node spheres do not fit
+    LDS: split into patches in the FP32 form (the model's per-hinge wing
+    factors and feet gathered per patch), whole in global scratch in the FP64
+    form (whose patches, with four FP64 words per edge, would not fit LDS);
+    from a deformed moving
+    start, against the oracle after 10 steps."""
+    say(f"[modes] split meshes with the conservative model vs oracle ({prec})")
+    bx = synth.config_batch(n_boxes=1, steps=10)[0]
+    for t in bx.templates:
+        t.model = "conservative"
+    rng = np.random.default_rng(103)
+    s = orc.System(bx)
+    X0 = s.X + 0.01 * rng.standard_normal(s.X.shape)
+    V0 = 1e-4 * rng.standard_normal(s.X.shape)
+    s.X[:] = X0
+    s.V[:] = V0
+    c = oif.Context.from_box(bx, precision=prec)
+    c.write_mesh(-1, X0, V0)
+    c.step(10)
+    i = c.info()
+    s.run(10)
+    res = check(gpu_fields(c, bx.rho0, X0), oracle_fields(s, X0), prec, bx.rho0, max(bx.nx, bx.ny, bx.nz))
+    c.close()
+    say(f"   {bx.name}: objects {i.n_objects}, in LDS {i.lds_objects}, split {i.split_objects}; {fmt(res)}")
+    assert all(v[3] for v in res.values()), fmt(res)
+    assert i.lds_objects < i.n_objects
+    if prec == "fp32":
+        assert i.split_objects > 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_oversize_meshes_vs_oracle(oif, orc, prec):
     """A 10242-node sphere, whose positions alone exceed LDS, runs in one
     workgroup with its mesh arrays in the global scratch and its coupling area
