@@ -86,13 +86,14 @@ def test_nontemporal_loads_bitwise(oif, prec, overlap, case):
     assert same(*outs)
 
 
-@pytest.mark.parametrize("overlap", [False, True])
-def test_graph_matches_eager_bitwise(oif, overlap):
-    say(f"[modes] graph vs eager, overlap={overlap}")
+@pytest.mark.parametrize("prec,overlap", [("fp32", False), ("fp32", True), ("fp64", False), ("fp16", False),
+                                          ("bf16", True)])
+def test_graph_matches_eager_bitwise(oif, prec, overlap):
+    say(f"[modes] graph vs eager, {prec}, overlap={overlap}")
     box = channel()
     outs = []
     for g in (0, 8):
-        c = oif.Context.from_box(box, precision="fp32")
+        c = oif.Context.from_box(box, precision=prec)
         c.set_overlap(overlap)
         c.set_graph(g)
         c.step(3)    # odd: the graph path must first realign to parity 0
