@@ -44,7 +44,7 @@ lb_kernel(const BoxDev* __restrict__ boxes, const int2* __restrict__ work, int n
 }
 
 template <int P>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 diag_lattice_kernel(const BoxDev* __restrict__ B, int parity, double* __restrict__ part) {
     typedef typename Prec<P>::S S;
     __shared__ double red[16];
@@ -231,7 +231,9 @@ hipError_t launch_lb(const LbLaunch& L) {
 
 hipError_t launch_diag_lattice(const BoxDev* box_dev, int precision, int parity, double* partials,
                                int nblocks, hipStream_t s) {
-    OIF_DISPATCH_P(precision, diag_lattice_kernel, dim3(nblocks), dim3(256), s, box_dev, parity, partials);
+    // 1024 threads per block: sixteen waves per compute unit keep enough
+    // population loads in flight over the grid-stride loop
+    OIF_DISPATCH_P(precision, diag_lattice_kernel, dim3(nblocks), dim3(1024), s, box_dev, parity, partials);
     return hipGetLastError();
 }
 
